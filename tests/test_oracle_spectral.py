@@ -1,0 +1,171 @@
+"""Pins of the oracle's spectral Poisson solve (Section III-D/E, Eqs.
+(8)-(12)) against closed forms, the PDE itself, Parseval, symmetry and a
+library DCT."""
+import math
+
+import numpy as np
+import pytest
+import scipy.fft
+
+import oracle
+
+
+def _cw(n):
+    c = np.full(n, 2.0)
+    c[0] = 1.0
+    return c
+
+
+@pytest.mark.parametrize("n", [4, 8])
+def test_literal_quadruple_sum_equals_separable(n):
+    rho = np.random.default_rng(n).random((n, n))
+    a1 = oracle.dct_coefficients_literal(rho)
+    a2 = oracle.dct_coefficients(rho)
+    assert np.max(np.abs(a1 - a2)) < 1e-13
+
+
+@pytest.mark.parametrize("n", [8, 64, 256])
+def test_coefficients_are_scaled_library_dct2(n):
+    # scipy's unnormalised DCT-II is 2 * sum x_i cos(pi k (2i+1) / 2n)
+    rho = np.random.default_rng(n + 1).random((n, n))
+    a = oracle.dct_coefficients(rho)
+    ref = np.outer(_cw(n), _cw(n)) / (4.0 * n * n) * scipy.fft.dctn(rho, type=2)
+    assert np.max(np.abs(a - ref)) < 1e-13
+
+
+@pytest.mark.parametrize("n", [8, 32])
+def test_coefficients_reconstruct_density(n):
+    # Eq. (9) with these coefficients gives rho back at the bin centres
+    rng = np.random.default_rng(2 * n)
+    rho = rng.random((n, n))
+    a = oracle.dct_coefficients(rho)
+    x = np.arange(n) + 0.5
+    w = np.pi * np.arange(n) / n
+    rec = np.cos(np.outer(x, w)) @ a @ np.cos(np.outer(w, x))   # [iy, v] a[v, u] [u, ix]
+    assert np.max(np.abs(rec - rho)) < 1e-12
+
+
+@pytest.mark.parametrize("n,u,v", [(16, 3, 5), (16, 1, 0), (16, 0, 7), (64, 17, 40)])
+def test_single_mode_closed_form(n, u, v):
+    x = np.arange(n) + 0.5
+    wu, wv = np.pi * u / n, np.pi * v / n
+    rho = np.outer(np.cos(wv * x), np.cos(wu * x))          # [iy, ix]
+    psi, ex, ey, a = oracle.poisson_solve(rho)
+    d = wu * wu + wv * wv
+    assert np.max(np.abs(psi - rho / d)) < 1e-12 * max(1.0, 1.0 / d)
+    ex_ref = wu / d * np.outer(np.cos(wv * x), np.sin(wu * x))
+    ey_ref = wv / d * np.outer(np.sin(wv * x), np.cos(wu * x))
+    assert np.max(np.abs(ex - ex_ref)) < 1e-12 * max(1.0, 1.0 / d)
+    assert np.max(np.abs(ey - ey_ref)) < 1e-12 * max(1.0, 1.0 / d)
+
+
+def test_constant_density_gives_nothing():
+    rho = np.full((16, 16), 0.9)
+    psi, ex, ey, a = oracle.poisson_solve(rho)
+    assert np.max(np.abs(psi)) < 1e-14 and np.max(np.abs(ex)) < 1e-14
+    assert np.max(np.abs(ey)) < 1e-14
+    assert abs(oracle.energy(rho, psi)) < 1e-12
+
+
+def test_dc_removed_and_psi_zero_mean():
+    rho = np.random.default_rng(1).random((32, 32)) + 5.0
+    psi, ex, ey, a = oracle.poisson_solve(rho)
+    assert a[0, 0] == 0.0
+    assert abs(psi.sum()) < 1e-10 * np.abs(psi).sum()      # zero integral, Eq. (8)
+    rho2 = rho + 3.0                                        # shifting rho changes nothing
+    psi2, ex2, ey2, _ = oracle.poisson_solve(rho2)
+    assert np.max(np.abs(psi2 - psi)) < 1e-11
+
+
+@pytest.mark.parametrize("n", [16, 64])
+def test_parseval_energy(n):
+    rho = np.random.default_rng(n).random((n, n))
+    psi, ex, ey, a = oracle.poisson_solve(rho)
+    w = np.pi * np.arange(n) / n
+    d = w[:, None] ** 2 + w[None, :] ** 2
+    d[0, 0] = 1.0
+    c = _cw(n)
+    N_spec = n * n * np.sum(a * a / (np.outer(c, c) * d))
+    N = oracle.energy(rho, psi)
+    assert N > 0
+    assert abs(N - N_spec) < 1e-12 * N
+
+
+def _series(G, Gx, Gy, xs, ys):
+    # continuous Fourier series of Eqs. (11)/(12) at arbitrary points
+    n = G.shape[0]
+    w = np.pi * np.arange(n) / n
+    cy, sy = np.cos(np.outer(ys, w)), np.sin(np.outer(ys, w))
+    cx, sx = np.cos(np.outer(w, xs)), np.sin(np.outer(w, xs))
+    return cy @ G @ cx, cy @ Gx @ sx, sy @ Gy @ cx
+
+
+def test_poisson_pde_neumann_and_field_is_minus_gradient():
+    n = 16
+    rng = np.random.default_rng(11)
+    rho = rng.random((n, n))
+    psi, ex, ey, a = oracle.poisson_solve(rho)
+    G, Gx, Gy = oracle.spectral_potential(a)
+    xc = np.arange(n) + 0.5
+    h = 1e-3
+    P = lambda xs, ys: _series(G, Gx, Gy, xs, ys)[0]
+    # series at the bin centres is what the oracle returned
+    assert np.max(np.abs(P(xc, xc) - psi)) < 1e-12
+    # -Laplacian(psi) = rho - mean(rho) at the bin centres (Eq. (8))
+    lap = (P(xc + h, xc) + P(xc - h, xc) + P(xc, xc + h) + P(xc, xc - h)
+           - 4 * P(xc, xc)) / (h * h)
+    assert np.max(np.abs(-lap - (rho - rho.mean()))) < 2e-5
+    # E = -grad psi (Eq. (12) from Eq. (11)), by central differences
+    dpx = (P(xc + h, xc) - P(xc - h, xc)) / (2 * h)
+    dpy = (P(xc, xc + h) - P(xc, xc - h)) / (2 * h)
+    assert np.max(np.abs(ex + dpx)) < 1e-6 * np.max(np.abs(ex))
+    assert np.max(np.abs(ey + dpy)) < 1e-6 * np.max(np.abs(ey))
+    # Neumann: zero normal derivative on the region boundary x = 0, n
+    ys = np.linspace(0, n, 7)
+    for xb in (0.0, float(n)):
+        _, exb, _ = _series(G, Gx, Gy, np.array([xb]), ys)
+        assert np.max(np.abs(exb)) < 1e-12
+        _, _, eyb = _series(G, Gx, Gy, ys, np.array([xb]))
+        assert np.max(np.abs(eyb)) < 1e-12
+
+
+def test_mirror_and_transpose_symmetry():
+    n = 32
+    rho = np.random.default_rng(5).random((n, n))
+    psi, ex, ey, _ = oracle.poisson_solve(rho)
+    psf, exf, eyf, _ = oracle.poisson_solve(rho[:, ::-1])        # flip in x
+    assert np.max(np.abs(psf - psi[:, ::-1])) < 1e-12
+    assert np.max(np.abs(exf + ex[:, ::-1])) < 1e-12
+    assert np.max(np.abs(eyf - ey[:, ::-1])) < 1e-12
+    pst, ext, eyt, _ = oracle.poisson_solve(rho.T)               # transpose
+    assert np.max(np.abs(pst - psi.T)) < 1e-12
+    assert np.max(np.abs(ext - ey.T)) < 1e-12
+    assert np.max(np.abs(eyt - ex.T)) < 1e-12
+
+
+def test_dst_as_reversed_cosine_identity():
+    # sum_{u>=1} b_u sin(w_u (i+1/2)) = (-1)^i sum_{k>=1} b_{n-k} cos(w_k (i+1/2))
+    n = 32
+    b = np.random.default_rng(3).random(n)
+    b[0] = 0.0
+    i = np.arange(n)
+    S = oracle.sin_table(n)
+    K = oracle.cos_table(n)
+    lhs = b @ S
+    br = np.zeros(n)
+    br[1:] = b[n - np.arange(1, n)]
+    rhs = ((-1.0) ** i) * (br @ K)
+    assert np.max(np.abs(lhs - rhs)) < 1e-13
+
+
+def test_tables_against_direct_trig():
+    n = 1024
+    u = np.array([0, 1, 511, 512, 1023])
+    i = np.array([0, 5, 1023])
+    K = oracle.cos_table(n)
+    S = oracle.sin_table(n)
+    for uu in u:
+        for ii in i:
+            ang = math.pi * uu * (2 * ii + 1) / (2 * n)
+            assert abs(K[uu, ii] - math.cos(ang)) < 1e-12
+            assert abs(S[uu, ii] - math.sin(ang)) < 1e-12
