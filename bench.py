@@ -1,0 +1,213 @@
+"""Benchmark of one FFTPL evaluation (density -> spectral solve -> gradients).
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload large_2m]
+                [--dct fft|gemm_f32|gemm_bf16x3] [--no-cpu-baseline]
+
+A step is one full fftpl_eval over the workload's positions, inputs resident
+in HBM: scatter, the FFT Poisson solve, field gather, WA wirelength, and the
+FP64 energy / wirelength / HPWL / overflow reductions.  Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("cell-gradient evals/s at 2M cells n=1024 (plain vs split-BF16); "
+          "served p50/p99")
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+BF16_PEAK_TFLOPS = 2500.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="large_2m")
+    ap.add_argument("--dct", default="fft")
+    ap.add_argument("--variants", default="fft,gemm_f32,gemm_bf16x3",
+                    help="spectral variants to time besides --dct")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-evals", type=int, default=2)
+    return ap.parse_args()
+
+
+def algorithmic_bytes(inst):
+    """Compulsory HBM bytes of each HBM-bound stage (float32 SoA layout)."""
+    m, E, P, n2 = inst.num_cells, inst.num_nets, inst.num_pins, inst.n ** 2
+    return {
+        # x, y, w, h read; base read; rho written (the atomics stay in cache)
+        "density": 16 * m + 4 * n2 + 4 * n2,
+        # x, y, w, h read; interleaved (Ex, Ey) map read; gx, gy written
+        "gather": 16 * m + 8 * n2 + 8 * m,
+        # pin_cell, pin_dx, pin_dy; net_ptr; x, y read; gx, gy read+written
+        "wa": 12 * P + 4 * (E + 1) + 8 * m + 16 * m,
+        # rho in; psi, Ex, Ey out (compulsory maps of the solve)
+        "spectral": 4 * n2 * 4,
+    }
+
+
+def time_loop(fn, steps, stream):
+    import torch
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for _ in range(steps):
+        fn()
+    stop.record(stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / steps
+
+
+def per_step_times(fn, steps, stream):
+    import torch
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    evs[0].record(stream)
+    for i in range(steps):
+        fn()
+        evs[i + 1].record(stream)
+    torch.cuda.synchronize()
+    return [evs[i].elapsed_time(evs[i + 1]) for i in range(steps)]
+
+
+def cpu_baseline(inst, evals):
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    except Exception:  # pragma: no cover
+        cores = 1
+    t0 = time.perf_counter()
+    for _ in range(evals):
+        oracle.evaluate(inst, lam=1.0, grad_mode="field")
+    dt = (time.perf_counter() - t0) / evals
+    return {"value": inst.num_cells / dt, "unit": "cell-gradient evals/s",
+            "cores": int(cores), "kind": "oracle",
+            "sample": (f"{evals} full FP64 oracle evaluation(s) of the same "
+                       f"{inst.num_cells}-cell n={inst.n} workload, {dt:.2f} s each; "
+                       "numpy, BLAS threads for the dense cosine sums, the rest "
+                       "single-threaded")}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): this build has "
+              "no multi-GPU path; see the sharding notes in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import gen
+    from paper_1312_4587_amd import _lib, fftpl
+
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1312_4587_amd import build
+        build.build()
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    inst = gen.make_config(args.workload)
+    prob = fftpl.Problem.from_instance(inst)
+    x = torch.as_tensor(inst.x).cuda()
+    y = torch.as_tensor(inst.y).cuda()
+    m = inst.num_cells
+    gx = torch.empty(m, device="cuda")
+    gy = torch.empty(m, device="cuda")
+    out4 = torch.empty(4, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+
+    plans = {}
+
+    def plan_for(mode):
+        if mode not in plans:
+            plans[mode] = fftpl.Plan(inst.n, mode)
+        return plans[mode]
+
+    def eval_fn(mode):
+        plan = plan_for(mode)
+        return lambda: fftpl.eval(plan, prob, x, y, 1.0, inst.gamma, "field", gx, gy, out4)
+
+    # ---- headline: whole evaluation
+    f = eval_fn(args.dct)
+    for _ in range(args.warmup):
+        f()
+    ms = time_loop(f, args.steps, stream)
+    steps_ms = per_step_times(f, min(args.steps, 200), stream)
+    value = m / (ms / 1e3)
+
+    variants = {}
+    for mode in [v for v in args.variants.split(",") if v and v != args.dct]:
+        try:
+            fv = eval_fn(mode)
+            for _ in range(3):
+                fv()
+            msv = time_loop(fv, max(10, args.steps // 2), stream)
+            variants[mode] = {"ms_per_eval": msv, "value": m / (msv / 1e3)}
+        except fftpl.FFTPLError as e:
+            variants[mode] = {"unavailable": str(e)}
+    variants[args.dct] = {"ms_per_eval": ms, "value": value}
+
+    # ---- per-stage timing with the individual entry points (same kernels and
+    # launch shapes as inside fftpl_eval), HIP events on this stream
+    grid = prob.grid
+    A = prob.arrays
+    n2 = inst.n ** 2
+    rho = torch.empty(n2, device="cuda")
+    psi = torch.empty(n2, device="cuda")
+    ex = torch.empty(n2, device="cuda")
+    ey = torch.empty(n2, device="cuda")
+    plan = plan_for(args.dct)
+    fftpl.density_map(grid, x, y, A["w"], A["h"], A["base"], rho)
+    fftpl.poisson_solve(plan, grid, rho, psi, ex, ey)
+    stage_fns = {
+        "density": lambda: fftpl.density_map(grid, x, y, A["w"], A["h"], A["base"], rho),
+        "spectral": lambda: fftpl.poisson_solve(plan, grid, rho, psi, ex, ey),
+        "gather": lambda: fftpl.field_gather(grid, x, y, A["w"], A["h"], ex, ey, None,
+                                             "field", 1.0, 0, gx, gy),
+        "wa": lambda: fftpl.wa_grad(A["net_ptr"], A["pin_cell"], A["pin_dx"], A["pin_dy"],
+                                    x, y, inst.gamma, 1, gx, gy),
+    }
+    nbytes = algorithmic_bytes(inst)
+    stages = {}
+    for name, fn in stage_fns.items():
+        for _ in range(3):
+            fn()
+        t = time_loop(fn, args.steps, stream)
+        stages[name] = {"ms": t, "algorithmic_bytes": nbytes[name],
+                        "GBps": nbytes[name] / (t / 1e3) / 1e9}
+    hbm = {k: v for k, v in stages.items() if k != "spectral"}
+    dom = max(hbm, key=lambda k: hbm[k]["ms"])
+    ach = stages[dom]["GBps"]
+    roofline = {"bound": "hbm", "kernel": {"wa": "k_wa", "density": "k_fill+k_scatter",
+                                           "gather": "k_gather"}[dom],
+                "stage": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": ach / HBM_PEAK_GBS, "traffic": None}
+
+    res = {
+        "metric": METRIC, "value": value, "unit": "cell-gradient evals/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": args.workload, "cells": m, "nets": inst.num_nets,
+                   "pins": inst.num_pins, "grid_n": inst.n, "macros": inst.num_fixed,
+                   "dct": args.dct, "grad_mode": "field", "seed": inst.meta["seed"]},
+        "p50_ms": float(np.percentile(steps_ms, 50)),
+        "p90_ms": float(np.percentile(steps_ms, 90)),
+        "variants": variants, "stages": stages, "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(inst, args.cpu_evals)
+    for p in plans.values():
+        p.close()
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,217 @@
+/*
+ * fftpl.h -- C ABI of the MI355X (gfx950) hot path of FFTPL, the FFT-based
+ * electrostatic global placer of J. Lu et al., "FFTPL: An Analytic Placement
+ * Algorithm Using Fast Fourier Transform for Density Equalization".
+ *
+ * One evaluation of the placement objective f = W~ + lambda*N (Eq. (7)) and
+ * its gradient: cells are rasterised into an n x n bin density map (Eq. (2)),
+ * the Neumann Poisson equation (Eq. (8)) is solved spectrally (Eqs. (9)-(12)),
+ * the field is gathered back to the cells (Section III-C), and the weighted-
+ * average wirelength gradient (Eq. (3)) is added.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every array pointer is a DEVICE pointer owned by the caller.  The library
+ *   never frees, retains or copies caller memory beyond the call.
+ * - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Every
+ *   compute call only enqueues work on `stream` and returns; no call
+ *   synchronises the host, and no compute call allocates device memory
+ *   (workspace lives in the plan).
+ * - Every call returns an int status (enum fftpl_status) and never throws.
+ *   Argument errors are detected on the host before anything is enqueued and
+ *   return FFTPL_E_INVAL.  A failed kernel launch returns FFTPL_E_DEVICE;
+ *   because launches are asynchronous, a fault of earlier work may also be
+ *   reported as FFTPL_E_DEVICE by a later call.
+ * - Units: positions, sizes, bin sizes and gamma are physical; maps are in
+ *   bin-area units (a full bin has density 1).  Maps are float32 row-major
+ *   [iy][ix] with ix (the x direction) fastest, n*n entries.
+ * - Cell rectangles: each cell's edges in bin units are computed in float32,
+ *   one rounding per operation and no contraction:
+ *       c = (x - (float)xl) * (float)(1/bin_w);  half = 0.5f * (w * (float)(1/bin_w));
+ *       lo = c - half;  hi = c + half
+ *   Bins are half-open [j, j+1); a cell touches bins floor(lo) .. ceil(hi)-1,
+ *   clipped to [0, n-1]; its overlap with bin j is min(hi, j+1) - max(lo, j)
+ *   with the edges clipped to [0, n].  Cells outside the region contribute
+ *   only their in-region part.
+ * - A plan is not thread-safe; use one plan per stream.
+ * - Setting the environment variable FFTPL_VALIDATE=1 adds O(pins) content
+ *   checks (CSR monotone, pin cells in range, positive sizes) that copy the
+ *   arrays to the host and synchronise; they are off by default.
+ */
+#ifndef FFTPL_H
+#define FFTPL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FFTPL_VERSION 10000 /* major*10000 + minor*100 + patch */
+
+enum fftpl_status {
+  FFTPL_OK = 0,
+  FFTPL_E_INVAL = -1,       /* bad argument (NULL, size, mode, n)           */
+  FFTPL_E_NOMEM = -2,       /* device allocation failed (plan creation)     */
+  FFTPL_E_DEVICE = -3,      /* a HIP runtime call or kernel launch failed   */
+  FFTPL_E_UNSUPPORTED = -4, /* valid but not supported (e.g. n for a mode)  */
+  FFTPL_E_STATE = -5        /* plan used with a grid of another size        */
+};
+
+/* How the DCT/DST stages of the spectral solve are computed. */
+enum fftpl_dct_mode {
+  FFTPL_DCT_FFT = 0,         /* hand-written radix-4 FFTs in LDS, float32     */
+  FFTPL_DCT_GEMM_F32 = 1,    /* cosine/sine-matrix GEMMs on MFMA, float32     */
+  FFTPL_DCT_GEMM_BF16X3 = 2  /* the same GEMMs with each float32 operand split
+                                into bf16 hi + lo, three MFMA products
+                                (hi*hi + hi*lo + lo*hi), float32 accumulate   */
+};
+
+/* Which density gradient is produced. */
+enum fftpl_grad_mode {
+  FFTPL_GRAD_FIELD = 0, /* Section III-C: dN/dx_i ~ -q_i E_i, with the cell's
+                           field the overlap-weighted sum of E over its bins */
+  FFTPL_GRAD_EXACT = 1  /* exact derivative of N = sum_b rho_b psi_b (Eq. (6))
+                           with respect to the cell centre (includes the
+                           factor 2 of the quadratic form)                   */
+};
+
+/* The bin grid over the placement region R (Section II): n x n bins of
+ * bin_w x bin_h starting at (xl, yl).  target_density is rho_t, the scale of
+ * fixed-node charge (Section III-B). */
+typedef struct fftpl_grid {
+  int32_t n;
+  int32_t reserved; /* must be 0 */
+  double xl, yl;
+  double bin_w, bin_h;
+  double target_density;
+} fftpl_grid;
+
+/* Opaque: twiddle/trigonometric tables and map workspace for one n and one
+ * dct_mode.  About 36*n*n bytes of device memory at n = 1024. */
+typedef struct fftpl_plan fftpl_plan;
+
+/* A static netlist and fixed charge; references caller-owned device arrays,
+ * the library copies nothing.  w, h: movable cell sizes [num_cells].
+ * base: fixed charge map [n*n] (see fftpl_fixed_map) or NULL for none.
+ * cap: movable capacity map [n*n] for the overflow ratio, or NULL to use
+ * max(0, rho_t - min(rho_t, base)).  Nets: CSR net_ptr [num_nets+1]
+ * (net_ptr[0] = 0, nondecreasing, net_ptr[num_nets] = num_pins), pin_cell
+ * [num_pins] in [0, num_cells), pin offsets from the cell centre
+ * pin_dx, pin_dy [num_pins]. */
+typedef struct fftpl_problem {
+  fftpl_grid grid;
+  int32_t num_cells;
+  int32_t num_nets;
+  int32_t num_pins;
+  int32_t reserved; /* must be 0 */
+  const float* w;
+  const float* h;
+  const float* base;
+  const float* cap;
+  const int32_t* net_ptr;
+  const int32_t* pin_cell;
+  const float* pin_dx;
+  const float* pin_dy;
+} fftpl_problem;
+
+/* Library version (FFTPL_VERSION of the build). */
+int fftpl_version(void);
+
+/* Static, NUL-terminated description of a status code. */
+const char* fftpl_status_string(int status);
+
+/* Create a plan for grid side n and a dct_mode.  FFTPL_DCT_FFT needs n a
+ * power of two with 8 <= n <= 1024 (the paper's grids are powers of two up to
+ * 1024, Section IV-A); the GEMM modes need n a multiple of 64 with
+ * 64 <= n <= 4096.  Tables are uploaded on `stream`.  On success *out owns
+ * device memory until fftpl_plan_destroy.  Errors: FFTPL_E_INVAL (NULL out,
+ * bad mode), FFTPL_E_UNSUPPORTED (n), FFTPL_E_NOMEM, FFTPL_E_DEVICE. */
+int fftpl_plan_create(fftpl_plan** out, int32_t n, int32_t dct_mode, void* stream);
+
+/* Destroy a plan (synchronises the device first).  NULL is accepted. */
+int fftpl_plan_destroy(fftpl_plan* plan);
+
+/* Side n and dct_mode of a plan. */
+int fftpl_plan_info(const fftpl_plan* plan, int32_t* n, int32_t* dct_mode);
+
+/* Device pointers of the maps the last fftpl_eval on this plan produced, for
+ * inspection: rho [n*n], psi [n*n] (written in FFTPL_GRAD_EXACT mode and by
+ * fftpl_eval_maps), exy [2*n*n] with (Ex, Ey) interleaved per bin.  Owned by
+ * the plan.  Any pointer argument may be NULL. */
+int fftpl_plan_maps(const fftpl_plan* plan, const float** rho, const float** psi,
+                    const float** exy);
+
+/* Fixed charge (Section III-B: fixed and dark node areas scaled by rho_t):
+ *   base[b] = rho_t * f_b,  cap[b] = rho_t * max(0, 1 - min(1, f_b)),
+ * f_b = sum over fixed rectangles of their overlap with bin b.  Rectangles
+ * are given by centre (fx, fy) and size (fw, fh) [num_fixed].  base is
+ * overwritten; cap may be NULL.  num_fixed may be 0 (maps become 0 and rho_t). */
+int fftpl_fixed_map(const fftpl_grid* grid, int32_t num_fixed, const float* fx,
+                    const float* fy, const float* fw, const float* fh, float* base,
+                    float* cap, void* stream);
+
+/* Density map (Eq. (2), Section III-B): rho = base + sum over movable cells of
+ * their overlap area with each bin.  base may be NULL (treated as 0).  rho is
+ * overwritten; accumulation uses float atomics, so the rounding order (not
+ * the value beyond float32 rounding) varies between runs. */
+int fftpl_density_map(const fftpl_grid* grid, int32_t num_cells, const float* x,
+                      const float* y, const float* w, const float* h,
+                      const float* base, float* rho, void* stream);
+
+/* Spectral Neumann Poisson solve (Eqs. (8)-(12)) on the plan's grid:
+ *   a_uv = (c_u c_v / n^2) sum rho cos(w_u (ix+1/2)) cos(w_v (iy+1/2)),
+ *   c_0 = 1, c_{k>0} = 2, w_u = pi u / n, a_00 := 0 (DC removed, Section III-A),
+ *   psi = sum a/(w_u^2+w_v^2) cos cos, Ex = sum a w_u/(..) sin(w_u x) cos(w_v y),
+ *   Ey = sum a w_v/(..) cos(w_u x) sin(w_v y), at bin centres, bin units.
+ * rho is read; psi, ex, ey [n*n] are written (ex and ey may both be NULL);
+ * energy, if not NULL, is a device double set to N = sum_b rho_b psi_b
+ * (Eq. (6)).  grid->n must equal the plan's n (else FFTPL_E_STATE). */
+int fftpl_poisson_solve(fftpl_plan* plan, const fftpl_grid* grid, const float* rho,
+                        float* psi, float* ex, float* ey, double* energy,
+                        void* stream);
+
+/* Density gradient per movable cell (Section III-C), times `scale` (lambda):
+ *   FIELD: gx_i = -scale/bin_w * sum_b ov(i,b) Ex_b  (gy with Ey, bin_h); reads ex, ey.
+ *   EXACT: gx_i = 2*scale/bin_w * sum_iy oy(i,iy) [psi(iy, floor(hi)) [0<hi<n]
+ *                                              - psi(iy, floor(lo)) [0<lo<n]]
+ *          (gy symmetric); reads psi.
+ * accumulate = 0 overwrites gx, gy; 1 adds to them. */
+int fftpl_field_gather(const fftpl_grid* grid, int32_t num_cells, const float* x,
+                       const float* y, const float* w, const float* h,
+                       const float* ex, const float* ey, const float* psi,
+                       int32_t grad_mode, float scale, int32_t accumulate,
+                       float* gx, float* gy, void* stream);
+
+/* Weighted-average wirelength (Eq. (3)) and HPWL (Eq. (1)) over the pin-net
+ * CSR, pins at cell centre + offset.  Adds (accumulate = 1) or writes
+ * (accumulate = 0) dW~/dx, dW~/dy summed over each cell's pins into gx, gy
+ * [num_cells] (float atomics).  wa and hpwl, if not NULL, are device doubles
+ * set to the totals over all nets and both axes.  gamma > 0, physical units. */
+int fftpl_wa_grad(int32_t num_nets, const int32_t* net_ptr, int32_t num_pins,
+                  const int32_t* pin_cell, const float* pin_dx, const float* pin_dy,
+                  int32_t num_cells, const float* x, const float* y, float gamma,
+                  int32_t accumulate, float* gx, float* gy, double* wa,
+                  double* hpwl, void* stream);
+
+/* One full evaluation (Algorithm 1, the density / FFT solve / gradient steps):
+ *   rho = base + cells; Poisson solve; g = dW~/dv + lambda * g_N (grad_mode);
+ *   out4 (device double[4]) = [N, W~, HPWL, tau] with tau the overflow ratio
+ *   sum_b max(0, rho_b - base_b - cap_b) / sum_b (rho_b - base_b).
+ * gx, gy [num_cells] are overwritten.  prob->grid.n must equal the plan's n. */
+int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
+               const float* y, float lambda, float gamma, int32_t grad_mode,
+               float* gx, float* gy, double* out4, void* stream);
+
+/* Test export: the integer bin range of every cell under the rectangle rule
+ * above, ranges[4*i + {0,1,2,3}] = {ix0, ix1, iy0, iy1} (empty when first >
+ * last).  ranges is a device int32 array [4*num_cells]. */
+int fftpl_debug_cell_bins(const fftpl_grid* grid, int32_t num_cells, const float* x,
+                          const float* y, const float* w, const float* h,
+                          int32_t* ranges, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FFTPL_H */

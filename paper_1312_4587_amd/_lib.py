@@ -1,0 +1,80 @@
+"""ctypes loader for libfftpl.so.  Loading fails loudly when the HIP library
+has not been built; there is no fallback implementation."""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfftpl.so")
+
+c_int = ctypes.c_int32
+c_float = ctypes.c_float
+c_double = ctypes.c_double
+c_void_p = ctypes.c_void_p
+c_char_p = ctypes.c_char_p
+
+
+class fftpl_grid(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("xl", c_double), ("yl", c_double),
+                ("bin_w", c_double), ("bin_h", c_double),
+                ("target_density", c_double)]
+
+
+class fftpl_problem(ctypes.Structure):
+    _fields_ = [("grid", fftpl_grid),
+                ("num_cells", ctypes.c_int32), ("num_nets", ctypes.c_int32),
+                ("num_pins", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("w", c_void_p), ("h", c_void_p), ("base", c_void_p),
+                ("cap", c_void_p), ("net_ptr", c_void_p), ("pin_cell", c_void_p),
+                ("pin_dx", c_void_p), ("pin_dy", c_void_p)]
+
+
+_G = ctypes.POINTER(fftpl_grid)
+_P = ctypes.POINTER(fftpl_problem)
+
+# name -> (restype, argtypes); mirrors include/fftpl.h
+SIGNATURES = {
+    "fftpl_version": (c_int, []),
+    "fftpl_status_string": (c_char_p, [c_int]),
+    "fftpl_plan_create": (c_int, [ctypes.POINTER(c_void_p), c_int, c_int, c_void_p]),
+    "fftpl_plan_destroy": (c_int, [c_void_p]),
+    "fftpl_plan_info": (c_int, [c_void_p, ctypes.POINTER(c_int), ctypes.POINTER(c_int)]),
+    "fftpl_plan_maps": (c_int, [c_void_p, ctypes.POINTER(c_void_p),
+                                ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p)]),
+    "fftpl_fixed_map": (c_int, [_G, c_int, c_void_p, c_void_p, c_void_p, c_void_p,
+                                c_void_p, c_void_p, c_void_p]),
+    "fftpl_density_map": (c_int, [_G, c_int, c_void_p, c_void_p, c_void_p, c_void_p,
+                                  c_void_p, c_void_p, c_void_p]),
+    "fftpl_poisson_solve": (c_int, [c_void_p, _G, c_void_p, c_void_p, c_void_p,
+                                    c_void_p, c_void_p, c_void_p]),
+    "fftpl_field_gather": (c_int, [_G, c_int, c_void_p, c_void_p, c_void_p, c_void_p,
+                                   c_void_p, c_void_p, c_void_p, c_int, c_float, c_int,
+                                   c_void_p, c_void_p, c_void_p]),
+    "fftpl_wa_grad": (c_int, [c_int, c_void_p, c_int, c_void_p, c_void_p, c_void_p,
+                              c_int, c_void_p, c_void_p, c_float, c_int, c_void_p,
+                              c_void_p, c_void_p, c_void_p, c_void_p]),
+    "fftpl_eval": (c_int, [c_void_p, _P, c_void_p, c_void_p, c_float, c_float, c_int,
+                           c_void_p, c_void_p, c_void_p, c_void_p]),
+    "fftpl_debug_cell_bins": (c_int, [_G, c_int, c_void_p, c_void_p, c_void_p,
+                                      c_void_p, c_void_p, c_void_p]),
+}
+
+_lib = None
+
+
+def load():
+    """Load libfftpl.so (once) and declare every entry point's signature."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"{LIB_PATH} is not built; run `python -m paper_1312_4587_amd.build` "
+            "(hipcc, gfx950).  There is no CPU fallback.")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib

@@ -1,0 +1,342 @@
+// extern "C" entry points of libfftpl: host-side argument validation, plan
+// lifecycle and the launch sequences of the hot path.  Argument meaning,
+// layout, ownership and error behaviour are specified in include/fftpl.h.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "fftpl_internal.hpp"
+
+using namespace fftpl;
+
+struct fftpl_plan {
+  Plan p;
+};
+
+namespace {
+
+inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+inline int dev_status(hipError_t e) { return e == hipSuccess ? FFTPL_OK : FFTPL_E_DEVICE; }
+
+bool validate_env() {
+  const char* v = getenv("FFTPL_VALIDATE");
+  return v && v[0] == '1';
+}
+
+bool grid_ok(const fftpl_grid* g) {
+  return g && g->n >= 1 && g->n <= 65536 && g->reserved == 0 && isfinite(g->xl) &&
+         isfinite(g->yl) && isfinite(g->bin_w) && isfinite(g->bin_h) && g->bin_w > 0 &&
+         g->bin_h > 0 && isfinite(g->target_density) && g->target_density >= 0;
+}
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+template <typename T>
+std::vector<T> to_host(const T* d, size_t count) {
+  std::vector<T> h(count);
+  if (count) hipMemcpy(h.data(), d, count * sizeof(T), hipMemcpyDeviceToHost);
+  return h;
+}
+
+// O(pins) content checks, only under FFTPL_VALIDATE=1 (synchronous).
+int validate_netlist(int num_nets, const int32_t* net_ptr, int num_pins,
+                     const int32_t* pin_cell, int num_cells) {
+  if (hipDeviceSynchronize() != hipSuccess) return FFTPL_E_DEVICE;
+  auto ptr = to_host(net_ptr, (size_t)num_nets + 1);
+  if (ptr[0] != 0 || ptr[num_nets] != num_pins) return FFTPL_E_INVAL;
+  for (int e = 0; e < num_nets; ++e)
+    if (ptr[e + 1] < ptr[e]) return FFTPL_E_INVAL;
+  auto pc = to_host(pin_cell, (size_t)num_pins);
+  for (int p = 0; p < num_pins; ++p)
+    if (pc[p] < 0 || pc[p] >= num_cells) return FFTPL_E_INVAL;
+  return FFTPL_OK;
+}
+
+int validate_cells(int m, const float* x, const float* y, const float* w, const float* h) {
+  if (hipDeviceSynchronize() != hipSuccess) return FFTPL_E_DEVICE;
+  auto hx = to_host(x, m), hy = to_host(y, m), hw = to_host(w, m), hh = to_host(h, m);
+  for (int i = 0; i < m; ++i)
+    if (!isfinite(hx[i]) || !isfinite(hy[i]) || !(hw[i] > 0) || !(hh[i] > 0) ||
+        !isfinite(hw[i]) || !isfinite(hh[i]))
+      return FFTPL_E_INVAL;
+  return FFTPL_OK;
+}
+
+void free_plan(Plan& p) {
+  hipFree(p.fft_tw);
+  hipFree(p.dct_cs);
+  hipFree(p.wfreq);
+  hipFree(p.rho);
+  hipFree(p.tmp0);
+  hipFree(p.tmp1);
+  hipFree(p.tmp2);
+  hipFree(p.psi);
+  hipFree(p.exy);
+  hipFree(p.rowsum);
+  hipFree(p.scal);
+  gemm_plan_free(p);
+}
+
+}  // namespace
+
+extern "C" {
+
+int fftpl_version(void) { return FFTPL_VERSION; }
+
+const char* fftpl_status_string(int status) {
+  switch (status) {
+    case FFTPL_OK: return "FFTPL_OK: success";
+    case FFTPL_E_INVAL: return "FFTPL_E_INVAL: invalid argument";
+    case FFTPL_E_NOMEM: return "FFTPL_E_NOMEM: device allocation failed";
+    case FFTPL_E_DEVICE: return "FFTPL_E_DEVICE: HIP runtime or kernel launch error";
+    case FFTPL_E_UNSUPPORTED: return "FFTPL_E_UNSUPPORTED: unsupported size or mode";
+    case FFTPL_E_STATE: return "FFTPL_E_STATE: plan does not match the grid";
+    default: return "unknown fftpl status";
+  }
+}
+
+int fftpl_plan_create(fftpl_plan** out, int32_t n, int32_t dct_mode, void* stream) {
+  if (!out) return FFTPL_E_INVAL;
+  *out = nullptr;
+  if (dct_mode < FFTPL_DCT_FFT || dct_mode > FFTPL_DCT_GEMM_BF16X3) return FFTPL_E_INVAL;
+  if (dct_mode == FFTPL_DCT_FFT) {
+    if (!is_pow2(n) || n < 8 || n > 1024) return FFTPL_E_UNSUPPORTED;
+  } else {
+    if (n < 64 || n > 4096 || n % 64) return FFTPL_E_UNSUPPORTED;
+  }
+  fftpl_plan* pl = new (std::nothrow) fftpl_plan();
+  if (!pl) return FFTPL_E_NOMEM;
+  Plan& p = pl->p;
+  p.n = n;
+  p.mode = dct_mode;
+  hipGetDevice(&p.device);
+  const size_t nn = (size_t)n * n;
+  bool ok = hipMalloc(&p.fft_tw, sizeof(float2) * n) == hipSuccess &&
+            hipMalloc(&p.dct_cs, sizeof(float2) * (n / 2 + 1)) == hipSuccess &&
+            hipMalloc(&p.wfreq, sizeof(float) * n) == hipSuccess &&
+            hipMalloc(&p.rho, sizeof(float) * nn) == hipSuccess &&
+            hipMalloc(&p.tmp0, sizeof(float) * nn) == hipSuccess &&
+            hipMalloc(&p.tmp1, sizeof(float) * nn) == hipSuccess &&
+            hipMalloc(&p.tmp2, sizeof(float) * nn) == hipSuccess &&
+            hipMalloc(&p.psi, sizeof(float) * nn) == hipSuccess &&
+            hipMalloc(&p.exy, sizeof(float) * 2 * nn) == hipSuccess &&
+            hipMalloc(&p.rowsum, sizeof(double) * n) == hipSuccess &&
+            hipMalloc(&p.scal, sizeof(double) * 8) == hipSuccess;
+  if (!ok) {
+    hipGetLastError();
+    free_plan(p);
+    delete pl;
+    return FFTPL_E_NOMEM;
+  }
+  std::vector<float2> tw(n), cs(n / 2 + 1);
+  std::vector<float> wf(n);
+  const double pi = 3.14159265358979323846;
+  for (int t = 0; t < n; ++t) {
+    tw[t] = make_float2((float)cos(2.0 * pi * t / n), (float)(-sin(2.0 * pi * t / n)));
+    wf[t] = (float)(pi * t / n);
+  }
+  for (int k = 0; k <= n / 2; ++k)
+    cs[k] = make_float2((float)cos(pi * k / (2.0 * n)), (float)sin(pi * k / (2.0 * n)));
+  hipStream_t s = as_stream(stream);
+  hipError_t e = hipMemcpyAsync(p.fft_tw, tw.data(), sizeof(float2) * n,
+                                hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(p.dct_cs, cs.data(), sizeof(float2) * (n / 2 + 1),
+                       hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(p.wfreq, wf.data(), sizeof(float) * n, hipMemcpyHostToDevice, s);
+  int st = FFTPL_OK;
+  if (e == hipSuccess && dct_mode != FFTPL_DCT_FFT) st = gemm_plan_init(p, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess || st != FFTPL_OK) {
+    free_plan(p);
+    delete pl;
+    return st != FFTPL_OK ? st : FFTPL_E_DEVICE;
+  }
+  *out = pl;
+  return FFTPL_OK;
+}
+
+int fftpl_plan_destroy(fftpl_plan* plan) {
+  if (!plan) return FFTPL_OK;
+  hipError_t e = hipDeviceSynchronize();
+  free_plan(plan->p);
+  delete plan;
+  return dev_status(e);
+}
+
+int fftpl_plan_info(const fftpl_plan* plan, int32_t* n, int32_t* dct_mode) {
+  if (!plan) return FFTPL_E_INVAL;
+  if (n) *n = plan->p.n;
+  if (dct_mode) *dct_mode = plan->p.mode;
+  return FFTPL_OK;
+}
+
+int fftpl_plan_maps(const fftpl_plan* plan, const float** rho, const float** psi,
+                    const float** exy) {
+  if (!plan) return FFTPL_E_INVAL;
+  if (rho) *rho = plan->p.rho;
+  if (psi) *psi = plan->p.psi;
+  if (exy) *exy = plan->p.exy;
+  return FFTPL_OK;
+}
+
+int fftpl_fixed_map(const fftpl_grid* grid, int32_t num_fixed, const float* fx,
+                    const float* fy, const float* fw, const float* fh, float* base,
+                    float* cap, void* stream) {
+  if (!grid_ok(grid) || num_fixed < 0 || !base) return FFTPL_E_INVAL;
+  if (num_fixed > 0 && (!fx || !fy || !fw || !fh)) return FFTPL_E_INVAL;
+  return dev_status(launch_fixed_map(make_gridf(*grid), num_fixed, fx, fy, fw, fh, base,
+                                     cap, as_stream(stream)));
+}
+
+int fftpl_density_map(const fftpl_grid* grid, int32_t num_cells, const float* x,
+                      const float* y, const float* w, const float* h,
+                      const float* base, float* rho, void* stream) {
+  if (!grid_ok(grid) || num_cells < 0 || !rho) return FFTPL_E_INVAL;
+  if (num_cells > 0 && (!x || !y || !w || !h)) return FFTPL_E_INVAL;
+  if (validate_env() && num_cells > 0) {
+    int v = validate_cells(num_cells, x, y, w, h);
+    if (v != FFTPL_OK) return v;
+  }
+  const GridF g = make_gridf(*grid);
+  hipStream_t s = as_stream(stream);
+  hipError_t e = launch_fill(rho, base, 0.0f, (int64_t)grid->n * grid->n, s);
+  if (e == hipSuccess) e = launch_scatter(g, num_cells, x, y, w, h, rho, s);
+  return dev_status(e);
+}
+
+int fftpl_poisson_solve(fftpl_plan* plan, const fftpl_grid* grid, const float* rho,
+                        float* psi, float* ex, float* ey, double* energy,
+                        void* stream) {
+  if (!plan || !grid_ok(grid) || !rho || !psi) return FFTPL_E_INVAL;
+  if ((ex == nullptr) != (ey == nullptr)) return FFTPL_E_INVAL;
+  if (grid->n != plan->p.n) return FFTPL_E_STATE;
+  hipStream_t s = as_stream(stream);
+  SpectralArgs a;
+  a.rho = rho;
+  a.psi = psi;
+  a.ex = ex;
+  a.ey = ey;
+  a.energy = energy;
+  hipError_t e = hipSuccess;
+  if (energy) e = launch_fill_f64(energy, 0.0, 1, s);
+  if (e == hipSuccess)
+    e = plan->p.mode == FFTPL_DCT_FFT ? spectral_fft(plan->p, a, s)
+                                      : spectral_gemm(plan->p, a, s);
+  return dev_status(e);
+}
+
+int fftpl_field_gather(const fftpl_grid* grid, int32_t num_cells, const float* x,
+                       const float* y, const float* w, const float* h,
+                       const float* ex, const float* ey, const float* psi,
+                       int32_t grad_mode, float scale, int32_t accumulate,
+                       float* gx, float* gy, void* stream) {
+  if (!grid_ok(grid) || num_cells < 0 || !isfinite(scale)) return FFTPL_E_INVAL;
+  if (grad_mode != FFTPL_GRAD_FIELD && grad_mode != FFTPL_GRAD_EXACT) return FFTPL_E_INVAL;
+  if (accumulate != 0 && accumulate != 1) return FFTPL_E_INVAL;
+  if (num_cells == 0) return FFTPL_OK;
+  if (!x || !y || !w || !h || !gx || !gy) return FFTPL_E_INVAL;
+  if (grad_mode == FFTPL_GRAD_FIELD && (!ex || !ey)) return FFTPL_E_INVAL;
+  if (grad_mode == FFTPL_GRAD_EXACT && !psi) return FFTPL_E_INVAL;
+  return dev_status(launch_gather(make_gridf(*grid), num_cells, x, y, w, h, ex, ey,
+                                  nullptr, psi, grad_mode, scale, accumulate, gx, gy,
+                                  as_stream(stream)));
+}
+
+int fftpl_wa_grad(int32_t num_nets, const int32_t* net_ptr, int32_t num_pins,
+                  const int32_t* pin_cell, const float* pin_dx, const float* pin_dy,
+                  int32_t num_cells, const float* x, const float* y, float gamma,
+                  int32_t accumulate, float* gx, float* gy, double* wa, double* hpwl,
+                  void* stream) {
+  if (num_nets < 0 || num_pins < 0 || num_cells < 0) return FFTPL_E_INVAL;
+  if (!(gamma > 0) || !isfinite(gamma)) return FFTPL_E_INVAL;
+  if (accumulate != 0 && accumulate != 1) return FFTPL_E_INVAL;
+  if (!net_ptr || (num_pins > 0 && (!pin_cell || !pin_dx || !pin_dy))) return FFTPL_E_INVAL;
+  if (num_cells > 0 && (!x || !y || !gx || !gy)) return FFTPL_E_INVAL;
+  if (num_pins > 0 && num_cells == 0) return FFTPL_E_INVAL;
+  if (validate_env()) {
+    int v = validate_netlist(num_nets, net_ptr, num_pins, pin_cell, num_cells);
+    if (v != FFTPL_OK) return v;
+  }
+  hipStream_t s = as_stream(stream);
+  hipError_t e = hipSuccess;
+  if (!accumulate && num_cells > 0) {
+    e = launch_fill(gx, nullptr, 0.0f, num_cells, s);
+    if (e == hipSuccess) e = launch_fill(gy, nullptr, 0.0f, num_cells, s);
+  }
+  if (e == hipSuccess && wa) e = launch_fill_f64(wa, 0.0, 1, s);
+  if (e == hipSuccess && hpwl) e = launch_fill_f64(hpwl, 0.0, 1, s);
+  if (e == hipSuccess)
+    e = launch_wa(num_nets, net_ptr, pin_cell, pin_dx, pin_dy, x, y, gamma, gx, gy, wa,
+                  hpwl, s);
+  return dev_status(e);
+}
+
+int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
+               const float* y, float lambda, float gamma, int32_t grad_mode, float* gx,
+               float* gy, double* out4, void* stream) {
+  if (!plan || !prob || !out4 || !grid_ok(&prob->grid)) return FFTPL_E_INVAL;
+  if (prob->reserved != 0) return FFTPL_E_INVAL;
+  if (prob->grid.n != plan->p.n) return FFTPL_E_STATE;
+  const int m = prob->num_cells;
+  if (m < 0 || prob->num_nets < 0 || prob->num_pins < 0) return FFTPL_E_INVAL;
+  if (grad_mode != FFTPL_GRAD_FIELD && grad_mode != FFTPL_GRAD_EXACT) return FFTPL_E_INVAL;
+  if (!isfinite(lambda) || !(gamma > 0) || !isfinite(gamma)) return FFTPL_E_INVAL;
+  if (m > 0 && (!x || !y || !prob->w || !prob->h || !gx || !gy)) return FFTPL_E_INVAL;
+  if (!prob->net_ptr) return FFTPL_E_INVAL;
+  if (prob->num_pins > 0 && (!prob->pin_cell || !prob->pin_dx || !prob->pin_dy || m == 0))
+    return FFTPL_E_INVAL;
+  if (validate_env()) {
+    int v = validate_netlist(prob->num_nets, prob->net_ptr, prob->num_pins, prob->pin_cell, m);
+    if (v == FFTPL_OK && m > 0) v = validate_cells(m, x, y, prob->w, prob->h);
+    if (v != FFTPL_OK) return v;
+  }
+  Plan& p = plan->p;
+  const GridF g = make_gridf(prob->grid);
+  hipStream_t s = as_stream(stream);
+  const int64_t nn = (int64_t)p.n * p.n;
+  // 1. reset: rho = base, scalar accumulators = 0
+  hipError_t e = launch_fill(p.rho, prob->base, 0.0f, nn, s);
+  if (e == hipSuccess) e = launch_fill_f64(out4, 0.0, 4, s);
+  if (e == hipSuccess) e = launch_fill_f64(p.scal, 0.0, 2, s);
+  // 2. density scatter
+  if (e == hipSuccess) e = launch_scatter(g, m, x, y, prob->w, prob->h, p.rho, s);
+  // 3. spectral solve; overflow sums in the first pass, energy in the last
+  if (e == hipSuccess) {
+    SpectralArgs a;
+    a.rho = p.rho;
+    a.psi = grad_mode == FFTPL_GRAD_EXACT ? p.psi : nullptr;
+    a.exy = grad_mode == FFTPL_GRAD_FIELD ? p.exy : nullptr;
+    a.energy = &out4[0];
+    a.base = prob->base;
+    a.cap = prob->cap;
+    a.rho_t = g.rho_t;
+    a.tau2 = p.scal;
+    e = p.mode == FFTPL_DCT_FFT ? spectral_fft(p, a, s) : spectral_gemm(p, a, s);
+  }
+  // 4. density gradient (overwrites g), 5. WA gradient (accumulates)
+  if (e == hipSuccess)
+    e = launch_gather(g, m, x, y, prob->w, prob->h, nullptr, nullptr, p.exy, p.psi,
+                      grad_mode, lambda, 0, gx, gy, s);
+  if (e == hipSuccess)
+    e = launch_wa(prob->num_nets, prob->net_ptr, prob->pin_cell, prob->pin_dx,
+                  prob->pin_dy, x, y, gamma, gx, gy, &out4[1], &out4[2], s);
+  if (e == hipSuccess) e = launch_overflow_finalize(out4, p.scal, s);
+  return dev_status(e);
+}
+
+int fftpl_debug_cell_bins(const fftpl_grid* grid, int32_t num_cells, const float* x,
+                          const float* y, const float* w, const float* h,
+                          int32_t* ranges, void* stream) {
+  if (!grid_ok(grid) || num_cells < 0) return FFTPL_E_INVAL;
+  if (num_cells > 0 && (!x || !y || !w || !h || !ranges)) return FFTPL_E_INVAL;
+  return dev_status(
+      launch_cell_bins(make_gridf(*grid), num_cells, x, y, w, h, ranges, as_stream(stream)));
+}
+
+}  // extern "C"

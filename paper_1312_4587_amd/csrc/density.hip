@@ -1,0 +1,248 @@
+// Bin-grid kernels: map fill, fixed-charge rasterisation, the movable-cell
+// density scatter (Eq. (2), Section III-B) and the field gather that turns
+// E or psi back into per-cell density gradients (Section III-C).
+#include "fftpl_internal.hpp"
+
+namespace fftpl {
+
+GridF make_gridf(const fftpl_grid& g) {
+  GridF f;
+  f.n = g.n;
+  f.xl = (float)g.xl;
+  f.yl = (float)g.yl;
+  f.inv_bw = (float)(1.0 / g.bin_w);
+  f.inv_bh = (float)(1.0 / g.bin_h);
+  f.bin_w = (float)g.bin_w;
+  f.bin_h = (float)g.bin_h;
+  f.rho_t = (float)g.target_density;
+  return f;
+}
+
+// dst[i] = src ? src[i] : value
+__global__ void k_fill(float* __restrict__ dst, const float* __restrict__ src,
+                       float value, int64_t count) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < count; i += stride) dst[i] = src ? src[i] : value;
+}
+
+__global__ void k_fill_f64(double* __restrict__ dst, double value, int count) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) dst[i] = value;
+}
+
+hipError_t launch_fill(float* dst, const float* src, float value, int64_t count,
+                       hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  int64_t blocks = (count + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(256), 0, s, dst, src, value,
+                     count);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_f64(double* dst, double value, int count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_f64, dim3((count + 63) / 64), dim3(64), 0, s, dst, value,
+                     count);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Fixed charge: one block per rectangle accumulates its overlap f_b, then a
+// pointwise pass scales by rho_t and derives the movable capacity.
+// ---------------------------------------------------------------------------
+__global__ void k_fixed_cover(GridF g, const float* __restrict__ fx,
+                              const float* __restrict__ fy, const float* __restrict__ fw,
+                              const float* __restrict__ fh, float* __restrict__ cover) {
+  const int i = blockIdx.x;
+  const Span sx = cell_span(fx[i], fw[i], g.xl, g.inv_bw, g.n);
+  const Span sy = cell_span(fy[i], fh[i], g.yl, g.inv_bh, g.n);
+  if (sx.i0 > sx.i1 || sy.i0 > sy.i1) return;
+  const int nx = sx.i1 - sx.i0 + 1;
+  const int ny = sy.i1 - sy.i0 + 1;
+  const int64_t total = (int64_t)nx * ny;
+  for (int64_t t = threadIdx.x; t < total; t += blockDim.x) {
+    const int ix = sx.i0 + (int)(t % nx);
+    const int iy = sy.i0 + (int)(t / nx);
+    const float ov = span_overlap(sx, ix) * span_overlap(sy, iy);
+    atomicAdd(&cover[(int64_t)iy * g.n + ix], ov);
+  }
+}
+
+__global__ void k_fixed_finalize(float* __restrict__ base, float* __restrict__ cap,
+                                 float rho_t, int64_t count) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const float f = base[i];
+  base[i] = rho_t * f;
+  if (cap) cap[i] = rho_t * fmaxf(0.0f, 1.0f - fminf(1.0f, f));
+}
+
+hipError_t launch_fixed_map(const GridF& g, int num_fixed, const float* fx,
+                            const float* fy, const float* fw, const float* fh,
+                            float* base, float* cap, hipStream_t s) {
+  const int64_t nn = (int64_t)g.n * g.n;
+  hipError_t e = launch_fill(base, nullptr, 0.0f, nn, s);
+  if (e != hipSuccess) return e;
+  if (num_fixed > 0) {
+    hipLaunchKernelGGL(k_fixed_cover, dim3(num_fixed), dim3(256), 0, s, g, fx, fy, fw,
+                       fh, base);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_fixed_finalize, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0,
+                     s, base, cap, g.rho_t, nn);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Movable-cell scatter: one thread per cell adds ox*oy into every bin of its
+// span with float atomics on the n*n map (4 MB at n = 1024, cache resident).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_scatter(GridF g, int m, const float* __restrict__ x,
+                                                 const float* __restrict__ y,
+                                                 const float* __restrict__ w,
+                                                 const float* __restrict__ h,
+                                                 float* __restrict__ rho) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const Span sx = cell_span(x[i], w[i], g.xl, g.inv_bw, g.n);
+  const Span sy = cell_span(y[i], h[i], g.yl, g.inv_bh, g.n);
+  for (int iy = sy.i0; iy <= sy.i1; ++iy) {
+    const float oy = span_overlap(sy, iy);
+    float* row = rho + (int64_t)iy * g.n;
+    for (int ix = sx.i0; ix <= sx.i1; ++ix) {
+      unsafeAtomicAdd(&row[ix], span_overlap(sx, ix) * oy);
+    }
+  }
+}
+
+hipError_t launch_scatter(const GridF& g, int m, const float* x, const float* y,
+                          const float* w, const float* h, float* rho, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scatter, dim3((m + 255) / 256), dim3(256), 0, s, g, m, x, y, w, h,
+                     rho);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Field gather.  FIELD: g = -scale/bin * sum ov * E (E separate or
+// interleaved).  EXACT: g = 2*scale/bin * sum_other-axis ov *
+// [psi at right edge - psi at left edge] for edges strictly inside (0, n).
+// ---------------------------------------------------------------------------
+template <int MODE, bool INTERLEAVED>
+__global__ void __launch_bounds__(256) k_gather(GridF g, int m, const float* __restrict__ x,
+                                                const float* __restrict__ y,
+                                                const float* __restrict__ w,
+                                                const float* __restrict__ h,
+                                                const float* __restrict__ ex,
+                                                const float* __restrict__ ey,
+                                                const float2* __restrict__ exy,
+                                                const float* __restrict__ psi, float scale,
+                                                int accumulate, float* __restrict__ gx,
+                                                float* __restrict__ gy) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const int n = g.n;
+  const Span sx = cell_span(x[i], w[i], g.xl, g.inv_bw, n);
+  const Span sy = cell_span(y[i], h[i], g.yl, g.inv_bh, n);
+  float ax = 0.0f, ay = 0.0f;
+  if (MODE == FFTPL_GRAD_FIELD) {
+    for (int iy = sy.i0; iy <= sy.i1; ++iy) {
+      const float oy = span_overlap(sy, iy);
+      for (int ix = sx.i0; ix <= sx.i1; ++ix) {
+        const float ov = span_overlap(sx, ix) * oy;
+        const int64_t b = (int64_t)iy * n + ix;
+        if (INTERLEAVED) {
+          const float2 e = exy[b];
+          ax += ov * e.x;
+          ay += ov * e.y;
+        } else {
+          ax += ov * ex[b];
+          ay += ov * ey[b];
+        }
+      }
+    }
+    ax *= -scale * g.inv_bw;
+    ay *= -scale * g.inv_bh;
+  } else {
+    const float fn = (float)n;
+    const bool xr = sx.hi > 0.0f && sx.hi < fn, xl = sx.lo > 0.0f && sx.lo < fn;
+    const bool yr = sy.hi > 0.0f && sy.hi < fn, yl = sy.lo > 0.0f && sy.lo < fn;
+    const int cxr = xr ? (int)floorf(sx.hi) : 0, cxl = xl ? (int)floorf(sx.lo) : 0;
+    const int cyr = yr ? (int)floorf(sy.hi) : 0, cyl = yl ? (int)floorf(sy.lo) : 0;
+    for (int iy = sy.i0; iy <= sy.i1; ++iy) {
+      const float oy = span_overlap(sy, iy);
+      const float* row = psi + (int64_t)iy * n;
+      float d = 0.0f;
+      if (xr) d += row[cxr];
+      if (xl) d -= row[cxl];
+      ax += oy * d;
+    }
+    for (int ix = sx.i0; ix <= sx.i1; ++ix) {
+      const float ox = span_overlap(sx, ix);
+      float d = 0.0f;
+      if (yr) d += psi[(int64_t)cyr * n + ix];
+      if (yl) d -= psi[(int64_t)cyl * n + ix];
+      ay += ox * d;
+    }
+    ax *= 2.0f * scale * g.inv_bw;
+    ay *= 2.0f * scale * g.inv_bh;
+  }
+  if (accumulate) {
+    gx[i] += ax;
+    gy[i] += ay;
+  } else {
+    gx[i] = ax;
+    gy[i] = ay;
+  }
+}
+
+hipError_t launch_gather(const GridF& g, int m, const float* x, const float* y,
+                         const float* w, const float* h, const float* ex,
+                         const float* ey, const float* exy, const float* psi,
+                         int grad_mode, float scale, int accumulate, float* gx,
+                         float* gy, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  dim3 grid((m + 255) / 256), block(256);
+  const float2* e2 = reinterpret_cast<const float2*>(exy);
+  if (grad_mode == FFTPL_GRAD_EXACT) {
+    hipLaunchKernelGGL((k_gather<FFTPL_GRAD_EXACT, false>), grid, block, 0, s, g, m, x, y,
+                       w, h, ex, ey, e2, psi, scale, accumulate, gx, gy);
+  } else if (exy) {
+    hipLaunchKernelGGL((k_gather<FFTPL_GRAD_FIELD, true>), grid, block, 0, s, g, m, x, y,
+                       w, h, ex, ey, e2, psi, scale, accumulate, gx, gy);
+  } else {
+    hipLaunchKernelGGL((k_gather<FFTPL_GRAD_FIELD, false>), grid, block, 0, s, g, m, x, y,
+                       w, h, ex, ey, e2, psi, scale, accumulate, gx, gy);
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Test export: the integer span of every cell.
+// ---------------------------------------------------------------------------
+__global__ void k_cell_bins(GridF g, int m, const float* __restrict__ x,
+                            const float* __restrict__ y, const float* __restrict__ w,
+                            const float* __restrict__ h, int32_t* __restrict__ ranges) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const Span sx = cell_span(x[i], w[i], g.xl, g.inv_bw, g.n);
+  const Span sy = cell_span(y[i], h[i], g.yl, g.inv_bh, g.n);
+  int32_t* r = ranges + 4 * (int64_t)i;
+  r[0] = sx.i0;
+  r[1] = sx.i1;
+  r[2] = sy.i0;
+  r[3] = sy.i1;
+}
+
+hipError_t launch_cell_bins(const GridF& g, int m, const float* x, const float* y,
+                            const float* w, const float* h, int32_t* ranges,
+                            hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cell_bins, dim3((m + 255) / 256), dim3(256), 0, s, g, m, x, y, w, h,
+                     ranges);
+  return hipGetLastError();
+}
+
+}  // namespace fftpl

@@ -1,0 +1,183 @@
+// Internal declarations shared by the HIP translation units of libfftpl.
+// Device helpers: the float32 cell-rectangle rule, wave reductions and the
+// XCD-aware block remap.  Host side: the plan layout and the launchers each
+// translation unit exports to the C ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/fftpl.h"
+
+namespace fftpl {
+
+constexpr int kWave = 64;
+constexpr int kNumXcd = 8;   // MI355X: 256 CUs in 8 XCDs, blocks dealt round-robin
+
+// ---------------------------------------------------------------------------
+// Device helpers
+// ---------------------------------------------------------------------------
+
+// Float32 grid parameters as the kernels use them (origin, 1/bin size).
+struct GridF {
+  int n;
+  float xl, yl;
+  float inv_bw, inv_bh;   // fl32(1 / bin size), computed in double on the host
+  float bin_w, bin_h;
+  float rho_t;
+};
+
+// One axis of the cell-rectangle rule: edges in bin units (rounded once per
+// operation, no contraction), the clipped edges, and the first/last bin.
+struct Span {
+  float lo, hi;     // unclipped edges in bin units
+  float clo, chi;   // edges clipped to [0, n]
+  int i0, i1;       // bins touched, empty when i0 > i1
+};
+
+__device__ __forceinline__ Span cell_span(float centre, float size, float origin,
+                                          float inv, int n) {
+#pragma clang fp contract(off)
+  Span s;
+  const float c = (centre - origin) * inv;
+  const float half = 0.5f * (size * inv);
+  s.lo = c - half;
+  s.hi = c + half;
+  const float fn = (float)n;
+  s.clo = fminf(fmaxf(s.lo, 0.0f), fn);
+  s.chi = fminf(fmaxf(s.hi, 0.0f), fn);
+  s.i0 = (int)floorf(s.clo);
+  s.i1 = (int)ceilf(fminf(fmaxf(s.hi, -1.0f), fn)) - 1;
+  return s;
+}
+
+// Overlap of the clipped edges [clo, chi) with bin j.
+__device__ __forceinline__ float span_overlap(const Span& s, int j) {
+  return fminf(s.chi, (float)(j + 1)) - fmaxf(s.clo, (float)j);
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, kWave));
+  return v;
+}
+
+__device__ __forceinline__ float wave_min(float v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = fminf(v, __shfl_xor(v, off, kWave));
+  return v;
+}
+
+// Order LDS accesses of one wavefront (all lanes) without a block barrier.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Blocks are dealt to the 8 XCDs round-robin.  Remap so that XCD k runs a
+// contiguous range of logical blocks (its writes then fill whole cache lines
+// in its own L2).  Identity when the grid is not a multiple of 8.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  if (nb % kNumXcd) return b;
+  return (b % kNumXcd) * (nb / kNumXcd) + b / kNumXcd;
+}
+
+// Block-wide double sum to one atomicAdd (blockDim a multiple of 64, <= 1024).
+__device__ __forceinline__ void block_atomic_add(double v, double* dst) {
+  __shared__ double red[16];
+  v = wave_sum(v);
+  const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  if (w == 0) {
+    const int nw = blockDim.x / kWave;
+    double t = lane < nw ? red[lane] : 0.0;
+    t = wave_sum(t);
+    if (lane == 0) atomicAdd(dst, t);
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+
+GridF make_gridf(const fftpl_grid& g);
+
+struct Plan {
+  int n = 0;
+  int mode = 0;
+  int device = 0;
+  // FFT-mode tables (float2): fft twiddles exp(-2 pi i t / n), t < n, and
+  // (cos, sin)(pi k / (2n)), k <= n/2; frequency table w_u = pi u / n.
+  float2* fft_tw = nullptr;
+  float2* dct_cs = nullptr;
+  float* wfreq = nullptr;
+  // GEMM-mode tables: cosine and frequency-weighted sine matrices.
+  void* gemm_tables = nullptr;
+  size_t gemm_tables_bytes = 0;
+  // Workspace maps.
+  float* rho = nullptr;     // n*n
+  float* tmp0 = nullptr;    // n*n  (bT / GEMM intermediate)
+  float* tmp1 = nullptr;    // n*n  (P)
+  float* tmp2 = nullptr;    // n*n  (Q)
+  float* psi = nullptr;     // n*n
+  float* exy = nullptr;     // 2*n*n interleaved (Ex, Ey)
+  void* gemm_ws = nullptr;  // extra GEMM-mode workspace
+  size_t gemm_ws_bytes = 0;
+  double* rowsum = nullptr; // n doubles
+  double* scal = nullptr;   // 8 doubles of scalar accumulators
+};
+
+// Launchers (return a hipError_t of the launch).
+hipError_t launch_fill(float* dst, const float* src, float value, int64_t count,
+                       hipStream_t s);
+hipError_t launch_fill_f64(double* dst, double value, int count, hipStream_t s);
+hipError_t launch_fixed_map(const GridF& g, int num_fixed, const float* fx,
+                            const float* fy, const float* fw, const float* fh,
+                            float* base, float* cap, hipStream_t s);
+hipError_t launch_scatter(const GridF& g, int m, const float* x, const float* y,
+                          const float* w, const float* h, float* rho, hipStream_t s);
+hipError_t launch_gather(const GridF& g, int m, const float* x, const float* y,
+                         const float* w, const float* h, const float* ex,
+                         const float* ey, const float* exy, const float* psi,
+                         int grad_mode, float scale, int accumulate, float* gx,
+                         float* gy, hipStream_t s);
+hipError_t launch_cell_bins(const GridF& g, int m, const float* x, const float* y,
+                            const float* w, const float* h, int32_t* ranges,
+                            hipStream_t s);
+hipError_t launch_wa(int num_nets, const int32_t* net_ptr, const int32_t* pin_cell,
+                     const float* pin_dx, const float* pin_dy, const float* x,
+                     const float* y, float gamma, float* gx, float* gy,
+                     double* wa_out, double* hp_out, hipStream_t s);
+hipError_t launch_overflow_finalize(double* out4, const double* scal, hipStream_t s);
+
+// Spectral solve.  psi/ex/ey/exy may be null individually; energy may be null.
+// If base/cap_or_null and tau2 are given, pass A also accumulates the two
+// overflow sums into tau2[0], tau2[1] (tau2 must be zeroed by the caller).
+struct SpectralArgs {
+  const float* rho = nullptr;
+  float* psi = nullptr;
+  float* ex = nullptr;
+  float* ey = nullptr;
+  float* exy = nullptr;
+  double* energy = nullptr;     // accumulated into (caller zeroes)
+  const float* base = nullptr;
+  const float* cap = nullptr;
+  float rho_t = 1.0f;
+  double* tau2 = nullptr;
+};
+hipError_t spectral_fft(Plan& p, const SpectralArgs& a, hipStream_t s);
+hipError_t spectral_gemm(Plan& p, const SpectralArgs& a, hipStream_t s);
+int gemm_plan_init(Plan& p, hipStream_t s);   // returns fftpl_status
+void gemm_plan_free(Plan& p);
+
+}  // namespace fftpl

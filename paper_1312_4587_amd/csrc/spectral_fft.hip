@@ -1,0 +1,405 @@
+// Spectral Neumann Poisson solve (Eqs. (8)-(12)) with hand-written FFTs.
+//
+// The 2-D transforms are separable; the solve is three passes over the map,
+// each one wavefront per pair of rows (or columns), the 1-D transforms done
+// in LDS:
+//   A  rows:    DCT-II along x of rho           -> bT[u][iy] (written transposed)
+//   B  columns: DCT-II along y, scale by c_u c_v / n^2 / (w_u^2 + w_v^2)
+//               (zero at (0,0): the DC is removed), then DCT-III along y
+//               (-> P) and the sine transform along y weighted by w_v (-> Q)
+//                                               -> P[iy][u], Q[iy][u]
+//   C  rows:    DCT-III along x of P (-> psi) and of Q (-> Ey), sine
+//               transform along x of w_u P (-> Ex); energy sum rho*psi.
+// A length-n DCT-II is an n-point complex FFT of the even/odd reordered
+// sequence followed by a quarter-sample twiddle (Makhoul's algorithm); two
+// real sequences share one complex FFT as its real and imaginary parts.  A
+// DCT-III runs the same steps backwards.  The sine transform is a DCT-III of
+// the reversed coefficients with alternating output signs:
+//   sum_{k>=1} b_k sin(pi k (2i+1)/2n) = (-1)^i sum_{k>=1} b_{n-k} cos(pi k (2i+1)/2n).
+// The 1-D FFT is a Stockham autosort radix-4 (one radix-2 stage first when
+// log2 n is odd), in place in one LDS buffer per wave, every stage reading
+// all its inputs into registers before writing.
+#include "fftpl_internal.hpp"
+
+namespace fftpl {
+
+namespace {
+
+constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// Position of sample i in the even/odd reordered sequence.
+template <int N>
+__device__ __forceinline__ int mk_pos(int i) {
+  return (i & 1) ? N - ((i + 1) >> 1) : (i >> 1);
+}
+
+// Unnormalised in-place DFT of buf[N] by one wavefront; INV selects exp(+).
+// tw[t] = exp(-2 pi i t / N).
+template <int N, bool INV>
+__device__ __forceinline__ void wave_fft(float2* buf, const float2* __restrict__ tw,
+                                         int lane) {
+  constexpr int LOG = ilog2c(N);
+  int ns = 1;
+  if constexpr (LOG & 1) {
+    constexpr int B = N / 2;
+    constexpr int PER = (B + kWave - 1) / kWave;
+    float2 v0[PER], v1[PER];
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+      const int j = lane + kWave * t;
+      if (B % kWave == 0 || j < B) {
+        v0[t] = buf[j];
+        v1[t] = buf[j + B];
+      }
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+      const int j = lane + kWave * t;
+      if (B % kWave == 0 || j < B) {
+        buf[2 * j] = make_float2(v0[t].x + v1[t].x, v0[t].y + v1[t].y);
+        buf[2 * j + 1] = make_float2(v0[t].x - v1[t].x, v0[t].y - v1[t].y);
+      }
+    }
+    wave_lds_sync();
+    ns = 2;
+  }
+  constexpr int B = N / 4;
+  constexpr int PER = (B + kWave - 1) / kWave;
+#pragma unroll
+  for (int st = 0; st < LOG / 2; ++st) {
+    float2 v[PER][4];
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+      const int j = lane + kWave * t;
+      if (B % kWave == 0 || j < B) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[t][r] = buf[j + r * B];
+      }
+    }
+    wave_lds_sync();
+    const int stride = N / (4 * ns);
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+      const int j = lane + kWave * t;
+      if (B % kWave == 0 || j < B) {
+        const int k = j & (ns - 1);
+        if (ns > 1) {
+#pragma unroll
+          for (int r = 1; r < 4; ++r) {
+            float2 w = tw[k * r * stride];
+            if (INV) w.y = -w.y;
+            v[t][r] = cmul(v[t][r], w);
+          }
+        }
+        const float2 t0 = make_float2(v[t][0].x + v[t][2].x, v[t][0].y + v[t][2].y);
+        const float2 t1 = make_float2(v[t][0].x - v[t][2].x, v[t][0].y - v[t][2].y);
+        const float2 t2 = make_float2(v[t][1].x + v[t][3].x, v[t][1].y + v[t][3].y);
+        const float2 d = make_float2(v[t][1].x - v[t][3].x, v[t][1].y - v[t][3].y);
+        // forward: t3 = -i * d ; inverse: t3 = +i * d
+        const float2 t3 = INV ? make_float2(-d.y, d.x) : make_float2(d.y, -d.x);
+        const int o = (j - k) * 4 + k;
+        buf[o] = make_float2(t0.x + t2.x, t0.y + t2.y);
+        buf[o + ns] = make_float2(t1.x + t3.x, t1.y + t3.y);
+        buf[o + 2 * ns] = make_float2(t0.x - t2.x, t0.y - t2.y);
+        buf[o + 3 * ns] = make_float2(t1.x - t3.x, t1.y - t3.y);
+      }
+    }
+    wave_lds_sync();
+    ns *= 4;
+  }
+}
+
+// Forward post-processing for the pair (k, n-k) of a two-real-sequence FFT
+// V = FFT(v1 + i v2): returns the DCT-II outputs X1, X2 at k and n-k.
+// cs = (cos, sin)(pi k / 2n).
+__device__ __forceinline__ void dct2_pair(float2 A, float2 B, float2 cs, float& x1k,
+                                          float& x2k, float& x1kp, float& x2kp) {
+  const float v1x = 0.5f * (A.x + B.x), v1y = 0.5f * (A.y - B.y);
+  const float v2x = 0.5f * (A.y + B.y), v2y = -0.5f * (A.x - B.x);
+  x1k = cs.x * v1x + cs.y * v1y;
+  x2k = cs.x * v2x + cs.y * v2y;
+  x1kp = cs.y * v1x - cs.x * v1y;
+  x2kp = cs.y * v2x - cs.x * v2y;
+}
+
+// Hermitian input of a DCT-III of real coefficients Y at the pair (k, n-k):
+// H_k = exp(i pi k / 2n) (Y_k - i Y_{n-k}) / 2, H_{n-k} = conj(H_k), H_0 = Y_0.
+__device__ __forceinline__ void dct3_herm(float yk, float ykp, float2 cs, bool k0,
+                                          float2& hk, float2& hkp) {
+  if (k0) {
+    hk = make_float2(yk, 0.0f);
+    hkp = hk;
+    return;
+  }
+  hk = make_float2(0.5f * (cs.x * yk + cs.y * ykp), 0.5f * (cs.y * yk - cs.x * ykp));
+  hkp = make_float2(hk.x, -hk.y);
+}
+
+// z = ha + i hb
+__device__ __forceinline__ float2 pack2(float2 ha, float2 hb) {
+  return make_float2(ha.x - hb.y, ha.y + hb.x);
+}
+
+// ---------------------------------------------------------------------------
+// Pass A: rows -> bT (transposed), row sums in double; optional overflow sums.
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ void __launch_bounds__(64)
+    k_rows_dct2(const float* __restrict__ rho, float* __restrict__ bT,
+                double* __restrict__ rowsum, const float2* __restrict__ tw,
+                const float2* __restrict__ cs, const float* __restrict__ base,
+                const float* __restrict__ cap, float rho_t, double* __restrict__ tau2) {
+  __shared__ float2 buf[N];
+  constexpr int PER = (N + kWave - 1) / kWave;
+  const int lane = threadIdx.x;
+  const int pair = xcd_block(blockIdx.x, gridDim.x);
+  const int r1 = 2 * pair, r2 = r1 + 1;
+  float a1[PER], a2[PER];
+  double s1 = 0.0, s2 = 0.0, ovf = 0.0, mov = 0.0;
+#pragma unroll
+  for (int t = 0; t < PER; ++t) {
+    const int i = lane + kWave * t;
+    if (N % kWave == 0 || i < N) {
+      a1[t] = rho[(int64_t)r1 * N + i];
+      a2[t] = rho[(int64_t)r2 * N + i];
+      s1 += a1[t];
+      s2 += a2[t];
+      if (tau2) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int64_t b = (int64_t)(q ? r2 : r1) * N + i;
+          const float bb = base ? base[b] : 0.0f;
+          const float cc = cap ? cap[b] : fmaxf(0.0f, rho_t - fminf(rho_t, bb));
+          const float mv = (q ? a2[t] : a1[t]) - bb;
+          ovf += fmaxf(0.0f, mv - cc);
+          mov += mv;
+        }
+      }
+    }
+  }
+  s1 = wave_sum(s1);
+  s2 = wave_sum(s2);
+  if (tau2) {
+    ovf = wave_sum(ovf);
+    mov = wave_sum(mov);
+    if (lane == 0) {
+      atomicAdd(&tau2[0], ovf);
+      atomicAdd(&tau2[1], mov);
+    }
+  }
+  const float m1 = (float)(s1 / N), m2 = (float)(s2 / N);
+#pragma unroll
+  for (int t = 0; t < PER; ++t) {
+    const int i = lane + kWave * t;
+    if (N % kWave == 0 || i < N) buf[mk_pos<N>(i)] = make_float2(a1[t] - m1, a2[t] - m2);
+  }
+  wave_lds_sync();
+  wave_fft<N, false>(buf, tw, lane);
+  for (int k = lane; k <= N / 2; k += kWave) {
+    const int kp = (N - k) & (N - 1);
+    float x1k, x2k, x1kp, x2kp;
+    dct2_pair(buf[k], buf[kp], cs[k], x1k, x2k, x1kp, x2kp);
+    if (k == 0) {
+      x1k = (float)s1;
+      x2k = (float)s2;
+    }
+    *reinterpret_cast<float2*>(&bT[(int64_t)k * N + r1]) = make_float2(x1k, x2k);
+    if (k != 0 && k != N / 2)
+      *reinterpret_cast<float2*>(&bT[(int64_t)kp * N + r1]) = make_float2(x1kp, x2kp);
+  }
+  if (lane == 0) {
+    rowsum[r1] = s1;
+    rowsum[r2] = s2;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pass B: columns u1 = 2q, u2 = 2q+1 (rows of bT).  Column 0 is rebuilt from
+// the double row sums minus their mean so that the DC never enters float32.
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ void __launch_bounds__(64)
+    k_cols_solve(const float* __restrict__ bT, const double* __restrict__ rowsum,
+                 float* __restrict__ P, float* __restrict__ Q,
+                 const float2* __restrict__ tw, const float2* __restrict__ cs,
+                 const float* __restrict__ wf) {
+  __shared__ float2 buf0[N];
+  __shared__ float2 buf1[N];
+  constexpr int PER = (N + kWave - 1) / kWave;
+  const int lane = threadIdx.x;
+  const int q = xcd_block(blockIdx.x, gridDim.x);
+  const int u1 = 2 * q, u2 = u1 + 1;
+  double mean0 = 0.0;
+  if (u1 == 0) {
+    double s = 0.0;
+    for (int i = lane; i < N; i += kWave) s += rowsum[i];
+    mean0 = wave_sum(s) / N;
+  }
+#pragma unroll
+  for (int t = 0; t < PER; ++t) {
+    const int i = lane + kWave * t;
+    if (N % kWave == 0 || i < N) {
+      const float c1 = (u1 == 0) ? (float)(rowsum[i] - mean0) : bT[(int64_t)u1 * N + i];
+      const float c2 = bT[(int64_t)u2 * N + i];
+      buf0[mk_pos<N>(i)] = make_float2(c1, c2);
+    }
+  }
+  wave_lds_sync();
+  wave_fft<N, false>(buf0, tw, lane);
+  const float inv_n2 = 1.0f / ((float)N * (float)N);
+  const float wu1 = wf[u1], wu2 = wf[u2];
+  const float f1 = (u1 == 0 ? 1.0f : 2.0f) * inv_n2, f2 = 2.0f * inv_n2;
+  for (int k = lane; k <= N / 2; k += kWave) {
+    const int kp = (N - k) & (N - 1);
+    const float2 c = cs[k];
+    float x1k, x2k, x1kp, x2kp;
+    dct2_pair(buf0[k], buf0[kp], c, x1k, x2k, x1kp, x2kp);
+    const float wk = wf[k], wkp = wf[kp];
+    const float ck = (k == 0 ? 1.0f : 2.0f), ckp = (kp == 0 ? 1.0f : 2.0f);
+    float g1k = x1k * (f1 * ck) / (wu1 * wu1 + wk * wk);
+    float g1kp = x1kp * (f1 * ckp) / (wu1 * wu1 + wkp * wkp);
+    const float g2k = x2k * (f2 * ck) / (wu2 * wu2 + wk * wk);
+    const float g2kp = x2kp * (f2 * ckp) / (wu2 * wu2 + wkp * wkp);
+    if (u1 == 0 && k == 0) g1k = 0.0f;   // a_00 := 0
+    // P: DCT-III of G.  Q: DCT-III of Yb with Yb_k = w_{n-k} G_{n-k} (k >= 1),
+    // Yb_0 = 0.  The two columns' P share one complex FFT and their Q another:
+    // sequences packed together must have similar magnitudes (P ~ 1/w^2 is far
+    // larger than Q ~ 1/w), or the rounding of one swamps the other.
+    const bool k0 = (k == 0);
+    float2 h1, h1p, h2, h2p;
+    dct3_herm(g1k, g1kp, c, k0, h1, h1p);
+    dct3_herm(g2k, g2kp, c, k0, h2, h2p);
+    buf0[k] = pack2(h1, h2);
+    if (!k0 && k != N / 2) buf0[kp] = pack2(h1p, h2p);
+    dct3_herm(k0 ? 0.0f : wkp * g1kp, k0 ? 0.0f : wk * g1k, c, k0, h1, h1p);
+    dct3_herm(k0 ? 0.0f : wkp * g2kp, k0 ? 0.0f : wk * g2k, c, k0, h2, h2p);
+    buf1[k] = pack2(h1, h2);
+    if (!k0 && k != N / 2) buf1[kp] = pack2(h1p, h2p);
+  }
+  wave_lds_sync();
+  wave_fft<N, true>(buf0, tw, lane);
+  wave_fft<N, true>(buf1, tw, lane);
+  for (int iy = lane; iy < N; iy += kWave) {
+    const int mpos = mk_pos<N>(iy);
+    const float2 zp = buf0[mpos], zq = buf1[mpos];
+    const float sg = (iy & 1) ? -1.0f : 1.0f;
+    *reinterpret_cast<float2*>(&P[(int64_t)iy * N + u1]) = zp;
+    *reinterpret_cast<float2*>(&Q[(int64_t)iy * N + u1]) = make_float2(sg * zq.x, sg * zq.y);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pass C: rows r1 = 2p, r2 = 2p+1 of P and Q -> psi, Ex, Ey; energy.
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ void __launch_bounds__(64)
+    k_rows_inverse(const float* __restrict__ P, const float* __restrict__ Q,
+                   const float* __restrict__ rho, float* __restrict__ psi,
+                   float* __restrict__ ex, float* __restrict__ ey,
+                   float2* __restrict__ exy, double* __restrict__ energy,
+                   const float2* __restrict__ tw, const float2* __restrict__ cs,
+                   const float* __restrict__ wf) {
+  __shared__ float2 bufa[N];
+  __shared__ float2 bufb[N];
+  __shared__ float2 bufc[N];
+  const int lane = threadIdx.x;
+  const int pr = xcd_block(blockIdx.x, gridDim.x);
+  const int r1 = 2 * pr, r2 = r1 + 1;
+  const float* P1 = P + (int64_t)r1 * N;
+  const float* P2 = P + (int64_t)r2 * N;
+  const float* Q1 = Q + (int64_t)r1 * N;
+  const float* Q2 = Q + (int64_t)r2 * N;
+  for (int k = lane; k <= N / 2; k += kWave) {
+    const int kp = (N - k) & (N - 1);
+    const bool k0 = (k == 0), self = k0 || k == N / 2;
+    const float2 c = cs[k];
+    const float wk = wf[k], wkp = wf[kp];
+    const float p1k = P1[k], p1kp = P1[kp], p2k = P2[k], p2kp = P2[kp];
+    // like-magnitude pairs share a complex FFT: (psi r1, psi r2), (Ey r1, Ey r2),
+    // (Ex r1, Ex r2)
+    float2 ha, hap, hb, hbp;
+    dct3_herm(p1k, p1kp, c, k0, ha, hap);
+    dct3_herm(p2k, p2kp, c, k0, hb, hbp);
+    bufa[k] = pack2(ha, hb);
+    if (!self) bufa[kp] = pack2(hap, hbp);
+    dct3_herm(Q1[k], Q1[kp], c, k0, ha, hap);
+    dct3_herm(Q2[k], Q2[kp], c, k0, hb, hbp);
+    bufb[k] = pack2(ha, hb);
+    if (!self) bufb[kp] = pack2(hap, hbp);
+    dct3_herm(k0 ? 0.0f : wkp * p1kp, k0 ? 0.0f : wk * p1k, c, k0, ha, hap);
+    dct3_herm(k0 ? 0.0f : wkp * p2kp, k0 ? 0.0f : wk * p2k, c, k0, hb, hbp);
+    bufc[k] = pack2(ha, hb);
+    if (!self) bufc[kp] = pack2(hap, hbp);
+  }
+  wave_lds_sync();
+  wave_fft<N, true>(bufa, tw, lane);
+  wave_fft<N, true>(bufb, tw, lane);
+  wave_fft<N, true>(bufc, tw, lane);
+  double en = 0.0;
+  for (int ix = lane; ix < N; ix += kWave) {
+    const int mpos = mk_pos<N>(ix);
+    const float2 za = bufa[mpos], zb = bufb[mpos], zc = bufc[mpos];
+    const float sg = (ix & 1) ? -1.0f : 1.0f;
+    const int64_t o1 = (int64_t)r1 * N + ix, o2 = (int64_t)r2 * N + ix;
+    if (psi) {
+      psi[o1] = za.x;
+      psi[o2] = za.y;
+    }
+    if (ex) {
+      ex[o1] = sg * zc.x;
+      ex[o2] = sg * zc.y;
+    }
+    if (ey) {
+      ey[o1] = zb.x;
+      ey[o2] = zb.y;
+    }
+    if (exy) {
+      exy[o1] = make_float2(sg * zc.x, zb.x);
+      exy[o2] = make_float2(sg * zc.y, zb.y);
+    }
+    if (energy) en += (double)rho[o1] * za.x + (double)rho[o2] * za.y;
+  }
+  if (energy) {
+    en = wave_sum(en);
+    if (lane == 0) atomicAdd(energy, en);
+  }
+}
+
+template <int N>
+hipError_t run_fft(Plan& p, const SpectralArgs& a, hipStream_t s) {
+  const dim3 grid(N / 2), block(kWave);
+  hipLaunchKernelGGL(k_rows_dct2<N>, grid, block, 0, s, a.rho, p.tmp0, p.rowsum, p.fft_tw,
+                     p.dct_cs, a.base, a.cap, a.rho_t, a.tau2);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_cols_solve<N>, grid, block, 0, s, p.tmp0, p.rowsum, p.tmp1, p.tmp2,
+                     p.fft_tw, p.dct_cs, p.wfreq);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_rows_inverse<N>, grid, block, 0, s, p.tmp1, p.tmp2, a.rho, a.psi,
+                     a.ex, a.ey, reinterpret_cast<float2*>(a.exy), a.energy, p.fft_tw,
+                     p.dct_cs, p.wfreq);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t spectral_fft(Plan& p, const SpectralArgs& a, hipStream_t s) {
+  switch (p.n) {
+    case 8: return run_fft<8>(p, a, s);
+    case 16: return run_fft<16>(p, a, s);
+    case 32: return run_fft<32>(p, a, s);
+    case 64: return run_fft<64>(p, a, s);
+    case 128: return run_fft<128>(p, a, s);
+    case 256: return run_fft<256>(p, a, s);
+    case 512: return run_fft<512>(p, a, s);
+    case 1024: return run_fft<1024>(p, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace fftpl

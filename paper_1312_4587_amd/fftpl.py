@@ -1,0 +1,262 @@
+"""Thin Python binding of the libfftpl C ABI.
+
+Same names as the C entry points (without the ``fftpl_`` prefix); arguments
+are torch tensors on the GPU (device memory only) and an optional
+``torch.cuda.Stream`` (default: the current stream).  Every step of the
+computation runs in the HIP kernels of libfftpl; this module only marshals
+pointers and sizes, and raises ``FFTPLError`` on a non-zero status.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+from typing import Optional
+
+import torch
+
+from . import _lib
+
+OK, E_INVAL, E_NOMEM, E_DEVICE, E_UNSUPPORTED, E_STATE = 0, -1, -2, -3, -4, -5
+DCT_MODES = {"fft": 0, "gemm_f32": 1, "gemm_bf16x3": 2}
+GRAD_MODES = {"field": 0, "exact": 1}
+
+
+class FFTPLError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        lib = _lib.load()
+        msg = lib.fftpl_status_string(status).decode()
+        super().__init__(f"{where}: {msg}")
+        self.status = status
+
+
+def _check(status: int, where: str) -> None:
+    if status != OK:
+        raise FFTPLError(status, where)
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _ptr(t, dtype=None, numel=None, name="tensor"):
+    """Device pointer of a contiguous CUDA tensor (None passes NULL)."""
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a GPU tensor (got {t.device})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype} (got {t.dtype})")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"{name} needs at least {numel} elements (got {t.numel()})")
+    return t.data_ptr()
+
+
+@dataclasses.dataclass
+class Grid:
+    n: int
+    xl: float
+    yl: float
+    bin_w: float
+    bin_h: float
+    target_density: float = 1.0
+
+    @classmethod
+    def of(cls, inst) -> "Grid":
+        return cls(int(inst.n), float(inst.xl), float(inst.yl), float(inst.bin_w),
+                   float(inst.bin_h), float(inst.target_density))
+
+    def c(self) -> _lib.fftpl_grid:
+        return _lib.fftpl_grid(self.n, 0, self.xl, self.yl, self.bin_w, self.bin_h,
+                               self.target_density)
+
+
+def version() -> int:
+    return _lib.load().fftpl_version()
+
+
+def status_string(status: int) -> str:
+    return _lib.load().fftpl_status_string(status).decode()
+
+
+class Plan:
+    """fftpl_plan_create / fftpl_plan_destroy."""
+
+    def __init__(self, n: int, dct_mode: str = "fft", stream=None):
+        lib = _lib.load()
+        h = ctypes.c_void_p()
+        _check(lib.fftpl_plan_create(ctypes.byref(h), int(n), DCT_MODES[dct_mode],
+                                     _stream(stream)), "fftpl_plan_create")
+        self._h = h
+        self.n = int(n)
+        self.dct_mode = dct_mode
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("plan is destroyed")
+        return self._h
+
+    def info(self):
+        n, mode = ctypes.c_int32(), ctypes.c_int32()
+        _check(_lib.load().fftpl_plan_info(self.handle, ctypes.byref(n), ctypes.byref(mode)),
+               "fftpl_plan_info")
+        return n.value, mode.value
+
+    def maps(self):
+        """Views (no copy) of the plan's rho [n,n], psi [n,n] and exy [n,n,2]."""
+        r, p, e = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+        _check(_lib.load().fftpl_plan_maps(self.handle, ctypes.byref(r), ctypes.byref(p),
+                                           ctypes.byref(e)), "fftpl_plan_maps")
+        n = self.n
+        return (_wrap(r.value, (n, n)), _wrap(p.value, (n, n)), _wrap(e.value, (n, n, 2)))
+
+    def close(self):
+        if self._h is not None:
+            _check(_lib.load().fftpl_plan_destroy(self._h), "fftpl_plan_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class _DevArray:
+    """Minimal __cuda_array_interface__ holder to view plan-owned memory."""
+
+    def __init__(self, ptr, shape):
+        self.__cuda_array_interface__ = {
+            "shape": tuple(shape), "typestr": "<f4", "data": (ptr, False),
+            "version": 2, "strides": None}
+
+
+def _wrap(ptr, shape):
+    return torch.as_tensor(_DevArray(ptr, shape), device="cuda")
+
+
+def fixed_map(grid: Grid, fx, fy, fw, fh, base, cap=None, stream=None):
+    n2 = grid.n * grid.n
+    nf = 0 if fx is None else int(fx.numel())
+    _check(_lib.load().fftpl_fixed_map(
+        ctypes.byref(grid.c()), nf, _ptr(fx, torch.float32, nf, "fx"),
+        _ptr(fy, torch.float32, nf, "fy"), _ptr(fw, torch.float32, nf, "fw"),
+        _ptr(fh, torch.float32, nf, "fh"), _ptr(base, torch.float32, n2, "base"),
+        _ptr(cap, torch.float32, n2, "cap"), _stream(stream)), "fftpl_fixed_map")
+
+
+def density_map(grid: Grid, x, y, w, h, base, rho, stream=None):
+    m = int(x.numel())
+    n2 = grid.n * grid.n
+    _check(_lib.load().fftpl_density_map(
+        ctypes.byref(grid.c()), m, _ptr(x, torch.float32, m, "x"),
+        _ptr(y, torch.float32, m, "y"), _ptr(w, torch.float32, m, "w"),
+        _ptr(h, torch.float32, m, "h"), _ptr(base, torch.float32, n2, "base"),
+        _ptr(rho, torch.float32, n2, "rho"), _stream(stream)), "fftpl_density_map")
+
+
+def poisson_solve(plan: Plan, grid: Grid, rho, psi, ex=None, ey=None, energy=None,
+                  stream=None):
+    n2 = grid.n * grid.n
+    _check(_lib.load().fftpl_poisson_solve(
+        plan.handle, ctypes.byref(grid.c()), _ptr(rho, torch.float32, n2, "rho"),
+        _ptr(psi, torch.float32, n2, "psi"), _ptr(ex, torch.float32, n2, "ex"),
+        _ptr(ey, torch.float32, n2, "ey"), _ptr(energy, torch.float64, 1, "energy"),
+        _stream(stream)), "fftpl_poisson_solve")
+
+
+def field_gather(grid: Grid, x, y, w, h, ex, ey, psi, grad_mode, scale, accumulate,
+                 gx, gy, stream=None):
+    m = int(x.numel())
+    n2 = grid.n * grid.n
+    _check(_lib.load().fftpl_field_gather(
+        ctypes.byref(grid.c()), m, _ptr(x, torch.float32, m, "x"),
+        _ptr(y, torch.float32, m, "y"), _ptr(w, torch.float32, m, "w"),
+        _ptr(h, torch.float32, m, "h"), _ptr(ex, torch.float32, n2, "ex"),
+        _ptr(ey, torch.float32, n2, "ey"), _ptr(psi, torch.float32, n2, "psi"),
+        GRAD_MODES.get(grad_mode, grad_mode), float(scale), int(accumulate),
+        _ptr(gx, torch.float32, m, "gx"), _ptr(gy, torch.float32, m, "gy"),
+        _stream(stream)), "fftpl_field_gather")
+
+
+def wa_grad(net_ptr, pin_cell, pin_dx, pin_dy, x, y, gamma, accumulate, gx, gy,
+            wa=None, hpwl=None, stream=None):
+    E = int(net_ptr.numel()) - 1
+    P = int(pin_cell.numel())
+    m = int(x.numel())
+    _check(_lib.load().fftpl_wa_grad(
+        E, _ptr(net_ptr, torch.int32, E + 1, "net_ptr"), P,
+        _ptr(pin_cell, torch.int32, P, "pin_cell"), _ptr(pin_dx, torch.float32, P, "pin_dx"),
+        _ptr(pin_dy, torch.float32, P, "pin_dy"), m, _ptr(x, torch.float32, m, "x"),
+        _ptr(y, torch.float32, m, "y"), float(gamma), int(accumulate),
+        _ptr(gx, torch.float32, m, "gx"), _ptr(gy, torch.float32, m, "gy"),
+        _ptr(wa, torch.float64, 1, "wa"), _ptr(hpwl, torch.float64, 1, "hpwl"),
+        _stream(stream)), "fftpl_wa_grad")
+
+
+class Problem:
+    """Device-resident static instance (sizes, netlist, fixed maps) and its
+    fftpl_problem struct.  ``arrays`` holds the tensors the struct points to."""
+
+    def __init__(self, grid: Grid, w, h, net_ptr, pin_cell, pin_dx, pin_dy,
+                 base=None, cap=None):
+        self.grid = grid
+        self.arrays = dict(w=w, h=h, net_ptr=net_ptr, pin_cell=pin_cell,
+                           pin_dx=pin_dx, pin_dy=pin_dy, base=base, cap=cap)
+        m = int(w.numel())
+        E = int(net_ptr.numel()) - 1
+        P = int(pin_cell.numel())
+        n2 = grid.n * grid.n
+        self.num_cells, self.num_nets, self.num_pins = m, E, P
+        self.c = _lib.fftpl_problem(
+            grid.c(), m, E, P, 0,
+            _ptr(w, torch.float32, m, "w"), _ptr(h, torch.float32, m, "h"),
+            _ptr(base, torch.float32, n2, "base"), _ptr(cap, torch.float32, n2, "cap"),
+            _ptr(net_ptr, torch.int32, E + 1, "net_ptr"),
+            _ptr(pin_cell, torch.int32, P, "pin_cell"),
+            _ptr(pin_dx, torch.float32, P, "pin_dx"), _ptr(pin_dy, torch.float32, P, "pin_dy"))
+
+    @classmethod
+    def from_instance(cls, inst, device="cuda", stream=None) -> "Problem":
+        """Upload an instance's static arrays and rasterise its fixed maps."""
+        def t(a, dt):
+            return torch.as_tensor(a, dtype=dt).to(device).contiguous()
+        grid = Grid.of(inst)
+        n2 = grid.n * grid.n
+        base = torch.empty(n2, dtype=torch.float32, device=device)
+        cap = torch.empty(n2, dtype=torch.float32, device=device)
+        fx = t(inst.fx, torch.float32) if inst.fx.size else None
+        fixed_map(grid, fx, t(inst.fy, torch.float32) if fx is not None else None,
+                  t(inst.fw, torch.float32) if fx is not None else None,
+                  t(inst.fh, torch.float32) if fx is not None else None,
+                  base, cap, stream=stream)
+        return cls(grid, t(inst.w, torch.float32), t(inst.h, torch.float32),
+                   t(inst.net_ptr, torch.int32), t(inst.pin_cell, torch.int32),
+                   t(inst.pin_dx, torch.float32), t(inst.pin_dy, torch.float32),
+                   base=base, cap=cap)
+
+
+def eval(plan: Plan, prob: Problem, x, y, lam, gamma, grad_mode, gx, gy, out4,
+         stream=None):  # noqa: A001 - the C name
+    m = prob.num_cells
+    _check(_lib.load().fftpl_eval(
+        plan.handle, ctypes.byref(prob.c), _ptr(x, torch.float32, m, "x"),
+        _ptr(y, torch.float32, m, "y"), float(lam), float(gamma),
+        GRAD_MODES.get(grad_mode, grad_mode), _ptr(gx, torch.float32, m, "gx"),
+        _ptr(gy, torch.float32, m, "gy"), _ptr(out4, torch.float64, 4, "out4"),
+        _stream(stream)), "fftpl_eval")
+
+
+def debug_cell_bins(grid: Grid, x, y, w, h, ranges, stream=None):
+    m = int(x.numel())
+    _check(_lib.load().fftpl_debug_cell_bins(
+        ctypes.byref(grid.c()), m, _ptr(x, torch.float32, m, "x"),
+        _ptr(y, torch.float32, m, "y"), _ptr(w, torch.float32, m, "w"),
+        _ptr(h, torch.float32, m, "h"), _ptr(ranges, torch.int32, 4 * m, "ranges"),
+        _stream(stream)), "fftpl_debug_cell_bins")
