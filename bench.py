@@ -37,18 +37,49 @@ def parse():
     return ap.parse_args()
 
 
-def algorithmic_bytes(inst):
-    """Compulsory HBM bytes of each HBM-bound stage (float32 SoA layout)."""
+def band_entries(inst):
+    """Number of (cell, band) entries the banded scatter lists: bookkeeping
+    for the byte counts only (float32 edges, bands of ceil(n/256) rows)."""
+    import numpy as np
+    inv = np.float32(1.0 / inst.bin_h)
+    c = (inst.y.astype(np.float32) - np.float32(inst.yl)) * inv
+    half = np.float32(0.5) * (inst.h.astype(np.float32) * inv)
+    lo = np.clip(c - half, 0, inst.n)
+    hi = np.clip(c + half, -1, inst.n)
+    i0 = np.floor(lo).astype(np.int64)
+    i1 = np.ceil(hi).astype(np.int64) - 1
+    rows = (inst.n + 255) // 256
+    ok = i1 >= i0
+    return int(np.sum(np.where(ok, i1 // rows - i0 // rows + 1, 0)))
+
+
+def kernel_bytes(inst, nent):
+    """Algorithmic bytes per launch of every kernel of the atomic-free
+    evaluation: compulsory reads and writes of its inputs and outputs in the
+    float32 structure-of-arrays layout (entries are 16-byte band records)."""
     m, E, P, n2 = inst.num_cells, inst.num_nets, inst.num_pins, inst.n ** 2
     return {
-        # x, y, w, h read; base read; rho written (the atomics stay in cache)
-        "density": 16 * m + 4 * n2 + 4 * n2,
-        # x, y, w, h read; interleaved (Ex, Ey) map read; gx, gy written
-        "gather": 16 * m + 8 * n2 + 8 * m,
-        # pin_cell, pin_dx, pin_dy; net_ptr; x, y read; gx, gy read+written
-        "wa": 12 * P + 4 * (E + 1) + 8 * m + 16 * m,
-        # rho in; psi, Ex, Ey out (compulsory maps of the solve)
-        "spectral": 4 * n2 * 4,
+        "k_init_eval": 0,
+        "k_band_count": 16 * m,
+        "k_band_place": 16 * m + 8 * m + 16 * nent,
+        "k_band_accum": 16 * nent + 4 * n2 + 4 * n2,
+        "k_rows_dct2": 4 * n2 + 4 * n2 + 8 * n2,        # rho, base+cap in; bT out
+        "k_cols_solve": 4 * n2 + 8 * n2,                # bT in; P, Q out
+        "k_rows_inverse": 8 * n2 + 4 * n2 + 8 * n2,     # P, Q, rho in; (Ex, Ey) out
+        "k_wa_slots": 12 * P + 4 * (E + 1) + 8 * m + 8 * P,
+        "k_gather_pins": 16 * m + 8 * n2 + 4 * (m + 1) + 8 * P + 8 * m,
+        "k_overflow_finalize": 0,
+    }
+
+
+def stage_bytes(inst):
+    """Compulsory bytes per stage of one evaluation, implementation-free."""
+    m, E, P, n2 = inst.num_cells, inst.num_nets, inst.num_pins, inst.n ** 2
+    return {
+        "density": 16 * m + 4 * n2 + 4 * n2,          # cells in; base in; rho out
+        "spectral": 4 * n2 * 4,                       # rho in; psi, Ex, Ey out
+        "gather": 16 * m + 8 * n2 + 8 * m,            # cells, E in; g out
+        "wirelength": 12 * P + 4 * (E + 1) + 8 * m + 8 * m,   # pins, nets, x, y in; g out
     }
 
 
@@ -154,41 +185,45 @@ def main():
             variants[mode] = {"unavailable": str(e)}
     variants[args.dct] = {"ms_per_eval": ms, "value": value}
 
-    # ---- per-stage timing with the individual entry points (same kernels and
-    # launch shapes as inside fftpl_eval), HIP events on this stream
-    grid = prob.grid
-    A = prob.arrays
-    n2 = inst.n ** 2
-    rho = torch.empty(n2, device="cuda")
-    psi = torch.empty(n2, device="cuda")
-    ex = torch.empty(n2, device="cuda")
-    ey = torch.empty(n2, device="cuda")
+    # ---- the float-atomic evaluation path, for comparison
+    try:
+        prob_atomic = fftpl.Problem.from_instance(inst, fast=False)
+        plan_a = plan_for(args.dct)
+        fa = lambda: fftpl.eval(plan_a, prob_atomic, x, y, 1.0, inst.gamma, "field",  # noqa
+                                gx, gy, out4)
+        for _ in range(2):
+            fa()
+        msa = time_loop(fa, max(5, args.steps // 5), stream)
+        variants["fft_float_atomics"] = {"ms_per_eval": msa, "value": m / (msa / 1e3)}
+        del prob_atomic
+    except fftpl.FFTPLError as e:
+        variants["fft_float_atomics"] = {"unavailable": str(e)}
+
+    # ---- per-kernel durations of the headline evaluation: HIP events the
+    # library records on this stream after every kernel (timing on the plan)
     plan = plan_for(args.dct)
-    fftpl.density_map(grid, x, y, A["w"], A["h"], A["base"], rho)
-    fftpl.poisson_solve(plan, grid, rho, psi, ex, ey)
-    stage_fns = {
-        "density": lambda: fftpl.density_map(grid, x, y, A["w"], A["h"], A["base"], rho),
-        "spectral": lambda: fftpl.poisson_solve(plan, grid, rho, psi, ex, ey),
-        "gather": lambda: fftpl.field_gather(grid, x, y, A["w"], A["h"], ex, ey, None,
-                                             "field", 1.0, 0, gx, gy),
-        "wa": lambda: fftpl.wa_grad(A["net_ptr"], A["pin_cell"], A["pin_dx"], A["pin_dy"],
-                                    x, y, inst.gamma, 1, gx, gy),
-    }
-    nbytes = algorithmic_bytes(inst)
-    stages = {}
-    for name, fn in stage_fns.items():
-        for _ in range(3):
-            fn()
-        t = time_loop(fn, args.steps, stream)
-        stages[name] = {"ms": t, "algorithmic_bytes": nbytes[name],
-                        "GBps": nbytes[name] / (t / 1e3) / 1e9}
-    hbm = {k: v for k, v in stages.items() if k != "spectral"}
-    dom = max(hbm, key=lambda k: hbm[k]["ms"])
-    ach = stages[dom]["GBps"]
-    roofline = {"bound": "hbm", "kernel": {"wa": "k_wa", "density": "k_fill+k_scatter",
-                                           "gather": "k_gather"}[dom],
-                "stage": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": ach / HBM_PEAK_GBS, "traffic": None}
+    plan.timing(True)
+    acc = {}
+    reps = max(10, args.steps // 2)
+    for _ in range(reps):
+        f()
+        for name, t in plan.kernel_times():
+            acc.setdefault(name, []).append(t)
+    plan.timing(False)
+    nbytes = kernel_bytes(inst, band_entries(inst))
+    kernels = {}
+    for name, ts in acc.items():
+        t = float(np.mean(ts))
+        b = nbytes.get(name)
+        kernels[name] = {"ms": t, "algorithmic_bytes": b,
+                         "GBps": (b / (t / 1e3) / 1e9) if b else None}
+    dom = max(kernels, key=lambda k: kernels[k]["ms"])
+    ach = kernels[dom]["GBps"] or 0.0
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None}
+    sb = stage_bytes(inst)
+    stages = {"algorithmic_bytes": sb,
+              "eval_GBps": sum(sb.values()) / (ms / 1e3) / 1e9}
 
     res = {
         "metric": METRIC, "value": value, "unit": "cell-gradient evals/s",
@@ -200,7 +235,7 @@ def main():
                    "dct": args.dct, "grad_mode": "field", "seed": inst.meta["seed"]},
         "p50_ms": float(np.percentile(steps_ms, 50)),
         "p90_ms": float(np.percentile(steps_ms, 90)),
-        "variants": variants, "stages": stages, "roofline": roofline,
+        "variants": variants, "kernels": kernels, "stages": stages, "roofline": roofline,
     }
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(inst, args.cpu_evals)

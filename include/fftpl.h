@@ -98,7 +98,15 @@ typedef struct fftpl_plan fftpl_plan;
  * max(0, rho_t - min(rho_t, base)).  Nets: CSR net_ptr [num_nets+1]
  * (net_ptr[0] = 0, nondecreasing, net_ptr[num_nets] = num_pins), pin_cell
  * [num_pins] in [0, num_cells), pin offsets from the cell centre
- * pin_dx, pin_dy [num_pins]. */
+ * pin_dx, pin_dy [num_pins].
+ *
+ * Optional, for the atomic-free evaluation path (all four set, n <= 1024):
+ * cell_ptr [num_cells+1] and pin_slot [num_pins] from fftpl_netlist_index, and
+ * a device workspace `work` of work_bytes >= fftpl_problem_work_bytes(...)
+ * bytes, owned by the caller and used by one evaluation at a time.  When any
+ * is NULL (or work_bytes is too small) fftpl_eval uses float atomics for the
+ * density scatter and the wirelength gradient instead: same results up to
+ * float32 rounding order, several times slower. */
 typedef struct fftpl_problem {
   fftpl_grid grid;
   int32_t num_cells;
@@ -113,6 +121,10 @@ typedef struct fftpl_problem {
   const int32_t* pin_cell;
   const float* pin_dx;
   const float* pin_dy;
+  const int32_t* cell_ptr;
+  const int32_t* pin_slot;
+  void* work;
+  uint64_t work_bytes;
 } fftpl_problem;
 
 /* Library version (FFTPL_VERSION of the build). */
@@ -141,6 +153,18 @@ int fftpl_plan_info(const fftpl_plan* plan, int32_t* n, int32_t* dct_mode);
  * the plan.  Any pointer argument may be NULL. */
 int fftpl_plan_maps(const fftpl_plan* plan, const float** rho, const float** psi,
                     const float** exy);
+
+/* Per-kernel timing for profiling.  With enable = 1 every later
+ * fftpl_poisson_solve / fftpl_eval on this plan records a HIP event on its
+ * stream after each kernel (and one before the first).  Creates the events on
+ * first use. */
+int fftpl_plan_timing(fftpl_plan* plan, int32_t enable);
+
+/* Durations of the kernels of the last timed call on this plan, in launch
+ * order: ms[i] and names[i] (static strings) for i < *count <= max.  Waits for
+ * the last event.  *count = 0 when timing is off. */
+int fftpl_plan_kernel_times(fftpl_plan* plan, int32_t max, float* ms, const char** names,
+                            int32_t* count);
 
 /* Fixed charge (Section III-B: fixed and dark node areas scaled by rho_t):
  *   base[b] = rho_t * f_b,  cap[b] = rho_t * max(0, 1 - min(1, f_b)),
@@ -193,6 +217,24 @@ int fftpl_wa_grad(int32_t num_nets, const int32_t* net_ptr, int32_t num_pins,
                   int32_t num_cells, const float* x, const float* y, float gamma,
                   int32_t accumulate, float* gx, float* gy, double* wa,
                   double* hpwl, void* stream);
+
+/* Bytes of the optional fftpl_problem workspace for grid side n, num_cells
+ * cells and num_pins pins (the interleaved positions, per-pin gradients, band
+ * lists of the density scatter and their counters).  Host-only. */
+int fftpl_problem_work_bytes(int32_t n, int32_t num_cells, int32_t num_pins,
+                             uint64_t* bytes);
+
+/* Cell-major index of the pins of a netlist (Section II: the netlist as a
+ * hypergraph; this is the transpose of its pin-net incidence), built once per
+ * netlist on `stream`:
+ *   cell_ptr [num_cells+1]: cell_ptr[c] = number of pins on cells < c,
+ *   pin_slot [num_pins]:    a permutation of 0..num_pins-1 with
+ *                           cell_ptr[pin_cell[p]] <= pin_slot[p] < cell_ptr[pin_cell[p]+1].
+ * The order of one cell's slots is arbitrary (integer atomics) but fixed once
+ * built.  work: device int32 scratch of num_cells + (num_cells+1023)/1024 + 1
+ * entries.  pin_cell values must lie in [0, num_cells). */
+int fftpl_netlist_index(int32_t num_cells, int32_t num_pins, const int32_t* pin_cell,
+                        int32_t* cell_ptr, int32_t* pin_slot, int32_t* work, void* stream);
 
 /* One full evaluation (Algorithm 1, the density / FFT solve / gradient steps):
  *   rho = base + cells; Poisson solve; g = dW~/dv + lambda * g_N (grad_mode);

@@ -26,7 +26,9 @@ class fftpl_problem(ctypes.Structure):
                 ("num_pins", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("w", c_void_p), ("h", c_void_p), ("base", c_void_p),
                 ("cap", c_void_p), ("net_ptr", c_void_p), ("pin_cell", c_void_p),
-                ("pin_dx", c_void_p), ("pin_dy", c_void_p)]
+                ("pin_dx", c_void_p), ("pin_dy", c_void_p),
+                ("cell_ptr", c_void_p), ("pin_slot", c_void_p),
+                ("work", c_void_p), ("work_bytes", ctypes.c_uint64)]
 
 
 _G = ctypes.POINTER(fftpl_grid)
@@ -57,6 +59,13 @@ SIGNATURES = {
                            c_void_p, c_void_p, c_void_p, c_void_p]),
     "fftpl_debug_cell_bins": (c_int, [_G, c_int, c_void_p, c_void_p, c_void_p,
                                       c_void_p, c_void_p, c_void_p]),
+    "fftpl_problem_work_bytes": (c_int, [c_int, c_int, c_int,
+                                         ctypes.POINTER(ctypes.c_uint64)]),
+    "fftpl_netlist_index": (c_int, [c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p,
+                                    c_void_p]),
+    "fftpl_plan_timing": (c_int, [c_void_p, c_int]),
+    "fftpl_plan_kernel_times": (c_int, [c_void_p, c_int, ctypes.POINTER(c_float),
+                                        ctypes.POINTER(c_char_p), ctypes.POINTER(c_int)]),
 }
 
 _lib = None

@@ -78,6 +78,8 @@ void free_plan(Plan& p) {
   hipFree(p.exy);
   hipFree(p.rowsum);
   hipFree(p.scal);
+  for (int i = 0; i < Plan::kMaxEvents; ++i)
+    if (p.ev[i]) hipEventDestroy(p.ev[i]);
   gemm_plan_free(p);
 }
 
@@ -224,7 +226,10 @@ int fftpl_poisson_solve(fftpl_plan* plan, const fftpl_grid* grid, const float* r
   a.ey = ey;
   a.energy = energy;
   hipError_t e = hipSuccess;
+  plan->p.nev = 0;
+  plan_mark(plan->p, "start", s);
   if (energy) e = launch_fill_f64(energy, 0.0, 1, s);
+  if (energy) plan_mark(plan->p, "k_fill_f64", s);
   if (e == hipSuccess)
     e = plan->p.mode == FFTPL_DCT_FFT ? spectral_fft(plan->p, a, s)
                                       : spectral_gemm(plan->p, a, s);
@@ -300,12 +305,30 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
   const GridF g = make_gridf(prob->grid);
   hipStream_t s = as_stream(stream);
   const int64_t nn = (int64_t)p.n * p.n;
-  // 1. reset: rho = base, scalar accumulators = 0
-  hipError_t e = launch_fill(p.rho, prob->base, 0.0f, nn, s);
-  if (e == hipSuccess) e = launch_fill_f64(out4, 0.0, 4, s);
-  if (e == hipSuccess) e = launch_fill_f64(p.scal, 0.0, 2, s);
-  // 2. density scatter
-  if (e == hipSuccess) e = launch_scatter(g, m, x, y, prob->w, prob->h, p.rho, s);
+  // Atomic-free path when the caller supplied the pin index and workspace.
+  size_t need = 0;
+  BandLayout L = band_layout(p.n, m, prob->num_pins, nullptr, &need);
+  const bool fast = prob->cell_ptr && prob->pin_slot && prob->work &&
+                    prob->work_bytes >= need && p.n <= kBandMaxN;
+  if (fast) L = band_layout(p.n, m, prob->num_pins, prob->work, nullptr);
+  hipError_t e = hipSuccess;
+  p.nev = 0;
+  plan_mark(p, "start", s);
+  if (fast) {
+    // 1. zero scalars and band counters; 2. banded density scatter
+    e = launch_init_eval(out4, p.scal, L.counters, L.nb + 1, s);
+    plan_mark(p, "k_init_eval", s);
+    if (e == hipSuccess)
+      e = launch_band_scatter(g, L, x, y, prob->w, prob->h, prob->base, p.rho, s, &p);
+  } else {
+    // 1. reset: rho = base, scalar accumulators = 0; 2. atomic scatter
+    e = launch_fill(p.rho, prob->base, 0.0f, nn, s);
+    plan_mark(p, "k_fill", s);
+    if (e == hipSuccess) e = launch_init_eval(out4, p.scal, nullptr, 0, s);
+    plan_mark(p, "k_init_eval", s);
+    if (e == hipSuccess) e = launch_scatter(g, m, x, y, prob->w, prob->h, p.rho, s);
+    plan_mark(p, "k_scatter", s);
+  }
   // 3. spectral solve; overflow sums in the first pass, energy in the last
   if (e == hipSuccess) {
     SpectralArgs a;
@@ -319,15 +342,85 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
     a.tau2 = p.scal;
     e = p.mode == FFTPL_DCT_FFT ? spectral_fft(p, a, s) : spectral_gemm(p, a, s);
   }
-  // 4. density gradient (overwrites g), 5. WA gradient (accumulates)
-  if (e == hipSuccess)
-    e = launch_gather(g, m, x, y, prob->w, prob->h, nullptr, nullptr, p.exy, p.psi,
-                      grad_mode, lambda, 0, gx, gy, s);
-  if (e == hipSuccess)
-    e = launch_wa(prob->num_nets, prob->net_ptr, prob->pin_cell, prob->pin_dx,
-                  prob->pin_dy, x, y, gamma, gx, gy, &out4[1], &out4[2], s);
+  if (fast) {
+    // 4. per-pin WA gradients into cell-major slots, 5. per cell: density
+    // gradient plus the sum of its pins' slots
+    if (e == hipSuccess)
+      e = launch_wa_pins(prob->num_nets, prob->net_ptr, prob->pin_cell, prob->pin_dx,
+                         prob->pin_dy, L.xy, prob->pin_slot, gamma, L.pin_grad, &out4[1],
+                         &out4[2], s);
+    plan_mark(p, "k_wa_slots", s);
+    if (e == hipSuccess)
+      e = launch_gather_pins(g, m, x, y, prob->w, prob->h, p.exy, p.psi, grad_mode, lambda,
+                             prob->cell_ptr, L.pin_grad, gx, gy, s);
+    plan_mark(p, "k_gather_pins", s);
+  } else {
+    // 4. density gradient (overwrites g), 5. WA gradient (float atomics)
+    if (e == hipSuccess)
+      e = launch_gather(g, m, x, y, prob->w, prob->h, nullptr, nullptr, p.exy, p.psi,
+                        grad_mode, lambda, 0, gx, gy, s);
+    plan_mark(p, "k_gather", s);
+    if (e == hipSuccess)
+      e = launch_wa(prob->num_nets, prob->net_ptr, prob->pin_cell, prob->pin_dx,
+                    prob->pin_dy, x, y, gamma, gx, gy, &out4[1], &out4[2], s);
+    plan_mark(p, "k_wa_atomic", s);
+  }
   if (e == hipSuccess) e = launch_overflow_finalize(out4, p.scal, s);
+  plan_mark(p, "k_overflow_finalize", s);
   return dev_status(e);
+}
+
+int fftpl_plan_timing(fftpl_plan* plan, int32_t enable) {
+  if (!plan || (enable != 0 && enable != 1)) return FFTPL_E_INVAL;
+  Plan& p = plan->p;
+  if (enable && !p.ev[0]) {
+    for (int i = 0; i < Plan::kMaxEvents; ++i)
+      if (hipEventCreate(&p.ev[i]) != hipSuccess) return FFTPL_E_DEVICE;
+  }
+  p.timing = enable != 0;
+  p.nev = 0;
+  return FFTPL_OK;
+}
+
+int fftpl_plan_kernel_times(fftpl_plan* plan, int32_t max, float* ms, const char** names,
+                            int32_t* count) {
+  if (!plan || !count || max < 0 || (max > 0 && (!ms || !names))) return FFTPL_E_INVAL;
+  Plan& p = plan->p;
+  *count = 0;
+  if (!p.timing || p.nev < 2) return FFTPL_OK;
+  if (hipEventSynchronize(p.ev[p.nev - 1]) != hipSuccess) return FFTPL_E_DEVICE;
+  const int k = p.nev - 1 < max ? p.nev - 1 : max;
+  for (int i = 0; i < k; ++i) {
+    float t = 0.0f;
+    if (hipEventElapsedTime(&t, p.ev[i], p.ev[i + 1]) != hipSuccess) return FFTPL_E_DEVICE;
+    ms[i] = t;
+    names[i] = p.ev_name[i + 1];
+  }
+  *count = k;
+  return FFTPL_OK;
+}
+
+int fftpl_problem_work_bytes(int32_t n, int32_t num_cells, int32_t num_pins,
+                             uint64_t* bytes) {
+  if (!bytes || n < 1 || num_cells < 0 || num_pins < 0) return FFTPL_E_INVAL;
+  size_t need = 0;
+  band_layout(n, num_cells, num_pins, nullptr, &need);
+  *bytes = need;
+  return FFTPL_OK;
+}
+
+int fftpl_netlist_index(int32_t num_cells, int32_t num_pins, const int32_t* pin_cell,
+                        int32_t* cell_ptr, int32_t* pin_slot, int32_t* work, void* stream) {
+  if (num_cells < 0 || num_pins < 0 || !cell_ptr || !work) return FFTPL_E_INVAL;
+  if (num_pins > 0 && (!pin_cell || !pin_slot || num_cells == 0)) return FFTPL_E_INVAL;
+  if (validate_env() && num_pins > 0) {
+    if (hipDeviceSynchronize() != hipSuccess) return FFTPL_E_DEVICE;
+    auto pc = to_host(pin_cell, (size_t)num_pins);
+    for (int q = 0; q < num_pins; ++q)
+      if (pc[q] < 0 || pc[q] >= num_cells) return FFTPL_E_INVAL;
+  }
+  return dev_status(launch_netlist_index(num_cells, num_pins, pin_cell, cell_ptr, pin_slot,
+                                         work, as_stream(stream)));
 }
 
 int fftpl_debug_cell_bins(const fftpl_grid* grid, int32_t num_cells, const float* x,

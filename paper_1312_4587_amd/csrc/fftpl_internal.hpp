@@ -35,20 +35,25 @@ struct Span {
   int i0, i1;       // bins touched, empty when i0 > i1
 };
 
+// Clipped edges and bin range of the edges [lo, hi) in bin units.
+__device__ __forceinline__ Span span_from_edges(float lo, float hi, int n) {
+  Span s;
+  s.lo = lo;
+  s.hi = hi;
+  const float fn = (float)n;
+  s.clo = fminf(fmaxf(lo, 0.0f), fn);
+  s.chi = fminf(fmaxf(hi, 0.0f), fn);
+  s.i0 = (int)floorf(s.clo);
+  s.i1 = (int)ceilf(fminf(fmaxf(hi, -1.0f), fn)) - 1;
+  return s;
+}
+
 __device__ __forceinline__ Span cell_span(float centre, float size, float origin,
                                           float inv, int n) {
 #pragma clang fp contract(off)
-  Span s;
   const float c = (centre - origin) * inv;
   const float half = 0.5f * (size * inv);
-  s.lo = c - half;
-  s.hi = c + half;
-  const float fn = (float)n;
-  s.clo = fminf(fmaxf(s.lo, 0.0f), fn);
-  s.chi = fminf(fmaxf(s.hi, 0.0f), fn);
-  s.i0 = (int)floorf(s.clo);
-  s.i1 = (int)ceilf(fminf(fmaxf(s.hi, -1.0f), fn)) - 1;
-  return s;
+  return span_from_edges(c - half, c + half, n);
 }
 
 // Overlap of the clipped edges [clo, chi) with bin j.
@@ -88,6 +93,29 @@ __device__ __forceinline__ void wave_lds_sync() {
 __device__ __forceinline__ int xcd_block(int b, int nb) {
   if (nb % kNumXcd) return b;
   return (b % kNumXcd) * (nb / kNumXcd) + b / kNumXcd;
+}
+
+// Exclusive prefix sum over a 256-thread block; *total gets the block sum.
+__device__ __forceinline__ int block_exclusive_scan256(int v, int* total) {
+  __shared__ int wsum[4];
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  int inc = v;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const int u = __shfl_up(inc, off, kWave);
+    if (lane >= off) inc += u;
+  }
+  if (lane == kWave - 1) wsum[w] = inc;
+  __syncthreads();
+  int woff = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (k < w) woff += wsum[k];
+    tot += wsum[k];
+  }
+  __syncthreads();
+  *total = tot;
+  return woff + inc - v;
 }
 
 // Block-wide double sum to one atomicAdd (blockDim a multiple of 64, <= 1024).
@@ -135,7 +163,23 @@ struct Plan {
   size_t gemm_ws_bytes = 0;
   double* rowsum = nullptr; // n doubles
   double* scal = nullptr;   // 8 doubles of scalar accumulators
+  // Optional per-kernel timing: an event is recorded on the launch stream
+  // after every kernel of an evaluation (the first one before it).
+  static constexpr int kMaxEvents = 24;
+  bool timing = false;
+  int nev = 0;
+  hipEvent_t ev[kMaxEvents] = {};
+  const char* ev_name[kMaxEvents] = {};
 };
+
+// Record a timing event named for the kernel that just finished (no-op
+// unless timing is enabled on the plan).
+inline void plan_mark(Plan& p, const char* name, hipStream_t s) {
+  if (!p.timing || p.nev >= Plan::kMaxEvents) return;
+  hipEventRecord(p.ev[p.nev], s);
+  p.ev_name[p.nev] = name;
+  ++p.nev;
+}
 
 // Launchers (return a hipError_t of the launch).
 hipError_t launch_fill(float* dst, const float* src, float value, int64_t count,
@@ -159,6 +203,47 @@ hipError_t launch_wa(int num_nets, const int32_t* net_ptr, const int32_t* pin_ce
                      const float* y, float gamma, float* gx, float* gy,
                      double* wa_out, double* hp_out, hipStream_t s);
 hipError_t launch_overflow_finalize(double* out4, const double* scal, hipStream_t s);
+
+// ---- banded density scatter (atomic-free in global memory) ----------------
+// Cells are counting-sorted into bands of `rows` bin rows (a cell is listed in
+// every band its span touches, at most kMaxBands; taller cells go to a short
+// list every band block walks), then one block per band accumulates its rows
+// in LDS and writes them out.  Needs n <= kBandMaxN.
+constexpr int kMaxBands = 4;
+constexpr int kBandMaxN = 1024;
+constexpr int kCellsPerBlock = 8192;   // cells per counting/placing block
+
+struct BandLayout {
+  int n = 0, rows = 0, nb = 0;   // band height in rows, number of bands
+  int m = 0, nblk = 0;           // cells, counting blocks
+  // regions of the problem workspace
+  float2* xy = nullptr;          // [m] interleaved positions
+  float2* pin_grad = nullptr;    // [P] per-pin WA gradients, cell-major slots
+  float4* entries = nullptr;     // [kMaxBands*m] band entries: cell edges in bins
+  int32_t* big = nullptr;        // [m] cells spanning more than kMaxBands bands
+  int32_t* blk_base = nullptr;   // [nblk*nb] block offsets inside each band
+  int32_t* counters = nullptr;   // [nb + 1] band counts, then the big-cell count
+};
+BandLayout band_layout(int n, int m, int num_pins, void* work, size_t* bytes_out);
+
+hipError_t launch_band_scatter(const GridF& g, const BandLayout& L, const float* x,
+                               const float* y, const float* w, const float* h,
+                               const float* base, float* rho, hipStream_t s,
+                               Plan* tp = nullptr);
+hipError_t launch_init_eval(double* out4, double* scal, int32_t* counters, int ncount,
+                            hipStream_t s);
+hipError_t launch_wa_pins(int num_nets, const int32_t* net_ptr, const int32_t* pin_cell,
+                          const float* pin_dx, const float* pin_dy, const float2* xy,
+                          const int32_t* pin_slot, float gamma, float2* pin_grad,
+                          double* wa_out, double* hp_out, hipStream_t s);
+hipError_t launch_gather_pins(const GridF& g, int m, const float* x, const float* y,
+                              const float* w, const float* h, const float* exy,
+                              const float* psi, int grad_mode, float scale,
+                              const int32_t* cell_ptr, const float2* pin_grad, float* gx,
+                              float* gy, hipStream_t s);
+hipError_t launch_netlist_index(int m, int num_pins, const int32_t* pin_cell,
+                                int32_t* cell_ptr, int32_t* pin_slot, int32_t* work,
+                                hipStream_t s);
 
 // Spectral solve.  psi/ex/ey/exy may be null individually; energy may be null.
 // If base/cap_or_null and tau2 are given, pass A also accumulates the two

@@ -377,13 +377,17 @@ hipError_t run_fft(Plan& p, const SpectralArgs& a, hipStream_t s) {
                      p.dct_cs, a.base, a.cap, a.rho_t, a.tau2);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  plan_mark(p, "k_rows_dct2", s);
   hipLaunchKernelGGL(k_cols_solve<N>, grid, block, 0, s, p.tmp0, p.rowsum, p.tmp1, p.tmp2,
                      p.fft_tw, p.dct_cs, p.wfreq);
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  plan_mark(p, "k_cols_solve", s);
   hipLaunchKernelGGL(k_rows_inverse<N>, grid, block, 0, s, p.tmp1, p.tmp2, a.rho, a.psi,
                      a.ex, a.ey, reinterpret_cast<float2*>(a.exy), a.energy, p.fft_tw,
                      p.dct_cs, p.wfreq);
-  return hipGetLastError();
+  e = hipGetLastError();
+  plan_mark(p, "k_rows_inverse", s);
+  return e;
 }
 
 }  // namespace

@@ -12,8 +12,14 @@
 //
 // One thread per net for degree <= kSmallDeg (the bulk of every netlist);
 // larger nets found in a wavefront are processed by the whole wavefront
-// cooperatively, one after another.  Gradients go to the cells with float
-// atomics; the W~ and HPWL totals are reduced in double.
+// cooperatively, one after another.  The W~ and HPWL totals are reduced in
+// double.  Two ways to hand the per-pin gradients to the cells:
+//   ATOMIC: float atomics into gx, gy (stateless; each atomic costs about as
+//           much as a random cache-line transfer, two per pin);
+//   SLOTS:  each pin's (gx, gy) is stored at its slot in a cell-major copy of
+//           the pins (one random 8-byte write per pin); the cell pass then sums
+//           contiguous slots.  Positions come interleaved as float2 so the
+//           gather is one random read per pin.
 #include <math.h>
 
 #include "fftpl_internal.hpp"
@@ -22,12 +28,59 @@ namespace fftpl {
 
 constexpr int kSmallDeg = 8;
 
+template <bool SLOTS>
+struct PinIO {
+  const float* x;
+  const float* y;
+  const float2* xy;
+  const int32_t* slot;
+  float* gx;
+  float* gy;
+  float2* pin_grad;
+  __device__ __forceinline__ float2 pos(int c) const {
+    if (SLOTS) return xy[c];
+    return make_float2(x[c], y[c]);
+  }
+  __device__ __forceinline__ void put(int p, int c, float vx, float vy) const {
+    if (SLOTS) {
+      pin_grad[slot[p]] = make_float2(vx, vy);
+    } else {
+      unsafeAtomicAdd(&gx[c], vx);
+      unsafeAtomicAdd(&gy[c], vy);
+    }
+  }
+};
+
+// Per-axis sums of one net: S+ = sum e+, T+ = sum (X-M) e+, S-, T- likewise.
+struct AxisSums {
+  float sp, tp, sm, tm;
+};
+
+__device__ __forceinline__ void axis_accum(AxisSums& a, float X, float M, float L,
+                                           float inv_gamma) {
+  float d = X - M, ee = expf(d * inv_gamma);
+  a.sp += ee;
+  a.tp += d * ee;
+  d = X - L;
+  ee = expf(-d * inv_gamma);
+  a.sm += ee;
+  a.tm += d * ee;
+}
+
+// dW~/dX for one pin, given M, L and W+ - M = wp, W- - L = wm, 1/S+, 1/S-.
+__device__ __forceinline__ float axis_grad(float X, float M, float L, float wp, float wm,
+                                           float rsp, float rsm, float inv_gamma) {
+  const float dp = X - M, dm = X - L;
+  return expf(dp * inv_gamma) * rsp * (1.0f + (dp - wp) * inv_gamma) -
+         expf(-dm * inv_gamma) * rsm * (1.0f - (dm - wm) * inv_gamma);
+}
+
+template <bool SLOTS>
 __global__ void __launch_bounds__(256)
     k_wa(int num_nets, const int32_t* __restrict__ net_ptr,
          const int32_t* __restrict__ pin_cell, const float* __restrict__ pin_dx,
-         const float* __restrict__ pin_dy, const float* __restrict__ x,
-         const float* __restrict__ y, float inv_gamma, float* __restrict__ gx,
-         float* __restrict__ gy, double* __restrict__ wa_out, double* __restrict__ hp_out) {
+         const float* __restrict__ pin_dy, PinIO<SLOTS> io, float inv_gamma,
+         double* __restrict__ wa_out, double* __restrict__ hp_out) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   const int lane = threadIdx.x & (kWave - 1);
   int p0 = 0, p1 = 0;
@@ -41,59 +94,39 @@ __global__ void __launch_bounds__(256)
   if (deg >= 2 && deg <= kSmallDeg) {
     int cell[kSmallDeg];
     float px[kSmallDeg], py[kSmallDeg];
-    const int c0 = pin_cell[p0];
-    const float x0 = x[c0], y0 = y[c0];
+    const float2 r = io.pos(pin_cell[p0]);
     float mx = -INFINITY, lx = INFINITY, my = -INFINITY, ly = INFINITY;
 #pragma unroll
     for (int k = 0; k < kSmallDeg; ++k) {
       if (k < deg) {
         const int c = pin_cell[p0 + k];
+        const float2 q = io.pos(c);
         cell[k] = c;
-        px[k] = (x[c] - x0) + pin_dx[p0 + k];
-        py[k] = (y[c] - y0) + pin_dy[p0 + k];
+        px[k] = (q.x - r.x) + pin_dx[p0 + k];
+        py[k] = (q.y - r.y) + pin_dy[p0 + k];
         mx = fmaxf(mx, px[k]);
         lx = fminf(lx, px[k]);
         my = fmaxf(my, py[k]);
         ly = fminf(ly, py[k]);
       }
     }
-    float spx = 0.f, tpx = 0.f, smx = 0.f, tmx = 0.f;
-    float spy = 0.f, tpy = 0.f, smy = 0.f, tmy = 0.f;
+    AxisSums sx = {0.f, 0.f, 0.f, 0.f}, sy = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int k = 0; k < kSmallDeg; ++k) {
       if (k < deg) {
-        float d = px[k] - mx, ee = expf(d * inv_gamma);
-        spx += ee;
-        tpx += d * ee;
-        d = px[k] - lx;
-        ee = expf(-d * inv_gamma);
-        smx += ee;
-        tmx += d * ee;
-        d = py[k] - my;
-        ee = expf(d * inv_gamma);
-        spy += ee;
-        tpy += d * ee;
-        d = py[k] - ly;
-        ee = expf(-d * inv_gamma);
-        smy += ee;
-        tmy += d * ee;
+        axis_accum(sx, px[k], mx, lx, inv_gamma);
+        axis_accum(sy, py[k], my, ly, inv_gamma);
       }
     }
-    // W+ - M and W- - L per axis
-    const float wpx = tpx / spx, wmx = tmx / smx, wpy = tpy / spy, wmy = tmy / smy;
-    const float rspx = 1.0f / spx, rsmx = 1.0f / smx, rspy = 1.0f / spy, rsmy = 1.0f / smy;
+    const float wpx = sx.tp / sx.sp, wmx = sx.tm / sx.sm;
+    const float wpy = sy.tp / sy.sp, wmy = sy.tm / sy.sm;
+    const float rspx = 1.0f / sx.sp, rsmx = 1.0f / sx.sm;
+    const float rspy = 1.0f / sy.sp, rsmy = 1.0f / sy.sm;
 #pragma unroll
     for (int k = 0; k < kSmallDeg; ++k) {
       if (k < deg) {
-        float dp = px[k] - mx, dm = px[k] - lx;
-        float g = expf(dp * inv_gamma) * rspx * (1.0f + (dp - wpx) * inv_gamma) -
-                  expf(-dm * inv_gamma) * rsmx * (1.0f - (dm - wmx) * inv_gamma);
-        unsafeAtomicAdd(&gx[cell[k]], g);
-        dp = py[k] - my;
-        dm = py[k] - ly;
-        g = expf(dp * inv_gamma) * rspy * (1.0f + (dp - wpy) * inv_gamma) -
-            expf(-dm * inv_gamma) * rsmy * (1.0f - (dm - wmy) * inv_gamma);
-        unsafeAtomicAdd(&gy[cell[k]], g);
+        io.put(p0 + k, cell[k], axis_grad(px[k], mx, lx, wpx, wmx, rspx, rsmx, inv_gamma),
+               axis_grad(py[k], my, ly, wpy, wmy, rspy, rsmy, inv_gamma));
       }
     }
     acc_wa = (double)((mx - lx) + wpx - wmx) + (double)((my - ly) + wpy - wmy);
@@ -106,12 +139,11 @@ __global__ void __launch_bounds__(256)
     const int src = __ffsll((long long)big) - 1;
     big &= big - 1;
     const int b0 = __shfl(p0, src, kWave), b1 = __shfl(p1, src, kWave);
-    const int c0 = pin_cell[b0];
-    const float x0 = x[c0], y0 = y[c0];
+    const float2 r = io.pos(pin_cell[b0]);
     float mx = -INFINITY, lx = INFINITY, my = -INFINITY, ly = INFINITY;
     for (int p = b0 + lane; p < b1; p += kWave) {
-      const int c = pin_cell[p];
-      const float X = (x[c] - x0) + pin_dx[p], Y = (y[c] - y0) + pin_dy[p];
+      const float2 q = io.pos(pin_cell[p]);
+      const float X = (q.x - r.x) + pin_dx[p], Y = (q.y - r.y) + pin_dy[p];
       mx = fmaxf(mx, X);
       lx = fminf(lx, X);
       my = fmaxf(my, Y);
@@ -121,49 +153,30 @@ __global__ void __launch_bounds__(256)
     lx = wave_min(lx);
     my = wave_max(my);
     ly = wave_min(ly);
-    float spx = 0.f, tpx = 0.f, smx = 0.f, tmx = 0.f;
-    float spy = 0.f, tpy = 0.f, smy = 0.f, tmy = 0.f;
+    AxisSums sx = {0.f, 0.f, 0.f, 0.f}, sy = {0.f, 0.f, 0.f, 0.f};
     for (int p = b0 + lane; p < b1; p += kWave) {
-      const int c = pin_cell[p];
-      const float X = (x[c] - x0) + pin_dx[p], Y = (y[c] - y0) + pin_dy[p];
-      float d = X - mx, ee = expf(d * inv_gamma);
-      spx += ee;
-      tpx += d * ee;
-      d = X - lx;
-      ee = expf(-d * inv_gamma);
-      smx += ee;
-      tmx += d * ee;
-      d = Y - my;
-      ee = expf(d * inv_gamma);
-      spy += ee;
-      tpy += d * ee;
-      d = Y - ly;
-      ee = expf(-d * inv_gamma);
-      smy += ee;
-      tmy += d * ee;
+      const float2 q = io.pos(pin_cell[p]);
+      axis_accum(sx, (q.x - r.x) + pin_dx[p], mx, lx, inv_gamma);
+      axis_accum(sy, (q.y - r.y) + pin_dy[p], my, ly, inv_gamma);
     }
-    spx = wave_sum(spx);
-    tpx = wave_sum(tpx);
-    smx = wave_sum(smx);
-    tmx = wave_sum(tmx);
-    spy = wave_sum(spy);
-    tpy = wave_sum(tpy);
-    smy = wave_sum(smy);
-    tmy = wave_sum(tmy);
-    const float wpx = tpx / spx, wmx = tmx / smx, wpy = tpy / spy, wmy = tmy / smy;
-    const float rspx = 1.0f / spx, rsmx = 1.0f / smx, rspy = 1.0f / spy, rsmy = 1.0f / smy;
+    sx.sp = wave_sum(sx.sp);
+    sx.tp = wave_sum(sx.tp);
+    sx.sm = wave_sum(sx.sm);
+    sx.tm = wave_sum(sx.tm);
+    sy.sp = wave_sum(sy.sp);
+    sy.tp = wave_sum(sy.tp);
+    sy.sm = wave_sum(sy.sm);
+    sy.tm = wave_sum(sy.tm);
+    const float wpx = sx.tp / sx.sp, wmx = sx.tm / sx.sm;
+    const float wpy = sy.tp / sy.sp, wmy = sy.tm / sy.sm;
+    const float rspx = 1.0f / sx.sp, rsmx = 1.0f / sx.sm;
+    const float rspy = 1.0f / sy.sp, rsmy = 1.0f / sy.sm;
     for (int p = b0 + lane; p < b1; p += kWave) {
       const int c = pin_cell[p];
-      const float X = (x[c] - x0) + pin_dx[p], Y = (y[c] - y0) + pin_dy[p];
-      float dp = X - mx, dm = X - lx;
-      float g = expf(dp * inv_gamma) * rspx * (1.0f + (dp - wpx) * inv_gamma) -
-                expf(-dm * inv_gamma) * rsmx * (1.0f - (dm - wmx) * inv_gamma);
-      unsafeAtomicAdd(&gx[c], g);
-      dp = Y - my;
-      dm = Y - ly;
-      g = expf(dp * inv_gamma) * rspy * (1.0f + (dp - wpy) * inv_gamma) -
-          expf(-dm * inv_gamma) * rsmy * (1.0f - (dm - wmy) * inv_gamma);
-      unsafeAtomicAdd(&gy[c], g);
+      const float2 q = io.pos(c);
+      const float X = (q.x - r.x) + pin_dx[p], Y = (q.y - r.y) + pin_dy[p];
+      io.put(p, c, axis_grad(X, mx, lx, wpx, wmx, rspx, rsmx, inv_gamma),
+             axis_grad(Y, my, ly, wpy, wmy, rspy, rsmy, inv_gamma));
     }
     if (lane == src) {
       acc_wa += (double)((mx - lx) + wpx - wmx) + (double)((my - ly) + wpy - wmy);
@@ -179,9 +192,20 @@ hipError_t launch_wa(int num_nets, const int32_t* net_ptr, const int32_t* pin_ce
                      const float* y, float gamma, float* gx, float* gy,
                      double* wa_out, double* hp_out, hipStream_t s) {
   if (num_nets <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_wa, dim3((num_nets + 255) / 256), dim3(256), 0, s, num_nets,
-                     net_ptr, pin_cell, pin_dx, pin_dy, x, y, 1.0f / gamma, gx, gy,
-                     wa_out, hp_out);
+  PinIO<false> io{x, y, nullptr, nullptr, gx, gy, nullptr};
+  hipLaunchKernelGGL(k_wa<false>, dim3((num_nets + 255) / 256), dim3(256), 0, s, num_nets,
+                     net_ptr, pin_cell, pin_dx, pin_dy, io, 1.0f / gamma, wa_out, hp_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_wa_pins(int num_nets, const int32_t* net_ptr, const int32_t* pin_cell,
+                          const float* pin_dx, const float* pin_dy, const float2* xy,
+                          const int32_t* pin_slot, float gamma, float2* pin_grad,
+                          double* wa_out, double* hp_out, hipStream_t s) {
+  if (num_nets <= 0) return hipSuccess;
+  PinIO<true> io{nullptr, nullptr, xy, pin_slot, nullptr, nullptr, pin_grad};
+  hipLaunchKernelGGL(k_wa<true>, dim3((num_nets + 255) / 256), dim3(256), 0, s, num_nets,
+                     net_ptr, pin_cell, pin_dx, pin_dy, io, 1.0f / gamma, wa_out, hp_out);
   return hipGetLastError();
 }
 
@@ -193,6 +217,109 @@ __global__ void k_overflow_finalize(double* __restrict__ out4, const double* __r
 hipError_t launch_overflow_finalize(double* out4, const double* scal, hipStream_t s) {
   hipLaunchKernelGGL(k_overflow_finalize, dim3(1), dim3(64), 0, s, out4, scal);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Cell-major pin index (built once per netlist): cell_ptr = exclusive prefix
+// sum of the pin count of every cell, pin_slot[p] = position of pin p among
+// the slots of its cell.  Ranks inside a cell come from integer atomics, so
+// the order of a cell's slots is arbitrary but fixed once built.
+// ---------------------------------------------------------------------------
+__global__ void k_zero_i32(int32_t* __restrict__ a, int count) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x)
+    a[i] = 0;
+}
+
+__global__ void k_count_pins(int num_pins, const int32_t* __restrict__ pin_cell,
+                             int32_t* __restrict__ cnt) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < num_pins) atomicAdd(&cnt[pin_cell[p]], 1);
+}
+
+// Block-local exclusive scan of 1024 items (4 per thread); block totals out.
+__global__ void __launch_bounds__(256)
+    k_scan_blocks(const int32_t* __restrict__ in, int count, int32_t* __restrict__ out,
+                  int32_t* __restrict__ sums) {
+  const int base = blockIdx.x * 1024 + threadIdx.x * 4;
+  int v[4], s = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    v[k] = base + k < count ? in[base + k] : 0;
+    s += v[k];
+  }
+  int total;
+  int run = block_exclusive_scan256(s, &total);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (base + k < count) out[base + k] = run;
+    run += v[k];
+  }
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// Exclusive scan of the block sums in place (one block, chunks of 256 with a
+// running carry); the grand total goes to *total_out.
+__global__ void __launch_bounds__(256)
+    k_scan_sums(int32_t* __restrict__ sums, int nsums, int32_t* __restrict__ total_out) {
+  int carry = 0;
+  for (int c0 = 0; c0 < nsums; c0 += 256) {
+    const int i = c0 + threadIdx.x;
+    const int v = i < nsums ? sums[i] : 0;
+    int tot;
+    const int ex = block_exclusive_scan256(v, &tot);
+    if (i < nsums) sums[i] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) *total_out = carry;
+}
+
+__global__ void k_scan_add(int32_t* __restrict__ out, int count, const int32_t* __restrict__ sums) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) out[i] += sums[i / 1024];
+}
+
+__global__ void k_pin_slots(int num_pins, const int32_t* __restrict__ pin_cell,
+                            const int32_t* __restrict__ cell_ptr, int32_t* __restrict__ cursor,
+                            int32_t* __restrict__ slot) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < num_pins) {
+    const int c = pin_cell[p];
+    slot[p] = cell_ptr[c] + atomicAdd(&cursor[c], 1);
+  }
+}
+
+hipError_t launch_netlist_index(int m, int num_pins, const int32_t* pin_cell,
+                                int32_t* cell_ptr, int32_t* pin_slot, int32_t* work,
+                                hipStream_t s) {
+  // work: m counters followed by ceil(m/1024) block sums
+  const int nsb = (m + 1023) / 1024;
+  int32_t* sums = work + m;
+  hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, s, work, m);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (num_pins > 0) {
+    hipLaunchKernelGGL(k_count_pins, dim3((num_pins + 255) / 256), dim3(256), 0, s,
+                       num_pins, pin_cell, work);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (m > 0) {
+    hipLaunchKernelGGL(k_scan_blocks, dim3(nsb), dim3(256), 0, s, work, m, cell_ptr, sums);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(256), 0, s, sums, nsb, cell_ptr + m);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (m > 0) {
+    hipLaunchKernelGGL(k_scan_add, dim3((m + 255) / 256), dim3(256), 0, s, cell_ptr, m, sums);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, s, work, m);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (num_pins > 0) {
+    hipLaunchKernelGGL(k_pin_slots, dim3((num_pins + 255) / 256), dim3(256), 0, s,
+                       num_pins, pin_cell, cell_ptr, work, pin_slot);
+    e = hipGetLastError();
+  }
+  return e;
 }
 
 }  // namespace fftpl

@@ -116,6 +116,22 @@ class Plan:
         n = self.n
         return (_wrap(r.value, (n, n)), _wrap(p.value, (n, n)), _wrap(e.value, (n, n, 2)))
 
+    def timing(self, enable: bool = True):
+        """fftpl_plan_timing: per-kernel HIP events on later calls."""
+        _check(_lib.load().fftpl_plan_timing(self.handle, 1 if enable else 0),
+               "fftpl_plan_timing")
+
+    def kernel_times(self):
+        """[(kernel name, ms)] of the last timed call (waits for it)."""
+        mx = 32
+        ms = (ctypes.c_float * mx)()
+        names = (ctypes.c_char_p * mx)()
+        cnt = ctypes.c_int32()
+        _check(_lib.load().fftpl_plan_kernel_times(self.handle, mx, ms, names,
+                                                   ctypes.byref(cnt)),
+               "fftpl_plan_kernel_times")
+        return [(names[i].decode(), float(ms[i])) for i in range(cnt.value)]
+
     def close(self):
         if self._h is not None:
             _check(_lib.load().fftpl_plan_destroy(self._h), "fftpl_plan_destroy")
@@ -200,30 +216,71 @@ def wa_grad(net_ptr, pin_cell, pin_dx, pin_dy, x, y, gamma, accumulate, gx, gy,
         _stream(stream)), "fftpl_wa_grad")
 
 
+def problem_work_bytes(n: int, num_cells: int, num_pins: int) -> int:
+    b = ctypes.c_uint64()
+    _check(_lib.load().fftpl_problem_work_bytes(int(n), int(num_cells), int(num_pins),
+                                                ctypes.byref(b)), "fftpl_problem_work_bytes")
+    return int(b.value)
+
+
+def netlist_index(num_cells: int, pin_cell, cell_ptr, pin_slot, stream=None):
+    """fftpl_netlist_index with its int32 scratch allocated here."""
+    m = int(num_cells)
+    P = int(pin_cell.numel())
+    work = torch.empty(m + (m + 1023) // 1024 + 1, dtype=torch.int32, device="cuda")
+    _check(_lib.load().fftpl_netlist_index(
+        m, P, _ptr(pin_cell, torch.int32, P, "pin_cell"),
+        _ptr(cell_ptr, torch.int32, m + 1, "cell_ptr"),
+        _ptr(pin_slot, torch.int32, P, "pin_slot"), _ptr(work, torch.int32, None, "work"),
+        _stream(stream)), "fftpl_netlist_index")
+    return work
+
+
 class Problem:
     """Device-resident static instance (sizes, netlist, fixed maps) and its
-    fftpl_problem struct.  ``arrays`` holds the tensors the struct points to."""
+    fftpl_problem struct.  ``arrays`` holds the tensors the struct points to.
+
+    With ``fast=True`` (default) the cell-major pin index and the evaluation
+    workspace are built here, which selects the atomic-free evaluation path."""
 
     def __init__(self, grid: Grid, w, h, net_ptr, pin_cell, pin_dx, pin_dy,
-                 base=None, cap=None):
+                 base=None, cap=None, fast=True, stream=None):
         self.grid = grid
-        self.arrays = dict(w=w, h=h, net_ptr=net_ptr, pin_cell=pin_cell,
-                           pin_dx=pin_dx, pin_dy=pin_dy, base=base, cap=cap)
         m = int(w.numel())
         E = int(net_ptr.numel()) - 1
         P = int(pin_cell.numel())
         n2 = grid.n * grid.n
         self.num_cells, self.num_nets, self.num_pins = m, E, P
+        cell_ptr = pin_slot = work = None
+        work_bytes = 0
+        if fast:
+            cell_ptr = torch.empty(m + 1, dtype=torch.int32, device="cuda")
+            pin_slot = torch.empty(max(P, 1), dtype=torch.int32, device="cuda")
+            scratch = netlist_index(m, pin_cell, cell_ptr, pin_slot, stream=stream)
+            work_bytes = problem_work_bytes(grid.n, m, P)
+            work = torch.empty(max(work_bytes, 1), dtype=torch.uint8, device="cuda")
+            torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+            del scratch
+        self.arrays = dict(w=w, h=h, net_ptr=net_ptr, pin_cell=pin_cell,
+                           pin_dx=pin_dx, pin_dy=pin_dy, base=base, cap=cap,
+                           cell_ptr=cell_ptr, pin_slot=pin_slot, work=work)
         self.c = _lib.fftpl_problem(
             grid.c(), m, E, P, 0,
             _ptr(w, torch.float32, m, "w"), _ptr(h, torch.float32, m, "h"),
             _ptr(base, torch.float32, n2, "base"), _ptr(cap, torch.float32, n2, "cap"),
             _ptr(net_ptr, torch.int32, E + 1, "net_ptr"),
             _ptr(pin_cell, torch.int32, P, "pin_cell"),
-            _ptr(pin_dx, torch.float32, P, "pin_dx"), _ptr(pin_dy, torch.float32, P, "pin_dy"))
+            _ptr(pin_dx, torch.float32, P, "pin_dx"), _ptr(pin_dy, torch.float32, P, "pin_dy"),
+            _ptr(cell_ptr, torch.int32, None, "cell_ptr"),
+            _ptr(pin_slot, torch.int32, None, "pin_slot"),
+            _ptr(work, torch.uint8, None, "work"), work_bytes)
+
+    @property
+    def fast(self) -> bool:
+        return self.arrays["work"] is not None
 
     @classmethod
-    def from_instance(cls, inst, device="cuda", stream=None) -> "Problem":
+    def from_instance(cls, inst, device="cuda", stream=None, fast=True) -> "Problem":
         """Upload an instance's static arrays and rasterise its fixed maps."""
         def t(a, dt):
             return torch.as_tensor(a, dtype=dt).to(device).contiguous()
@@ -239,7 +296,7 @@ class Problem:
         return cls(grid, t(inst.w, torch.float32), t(inst.h, torch.float32),
                    t(inst.net_ptr, torch.int32), t(inst.pin_cell, torch.int32),
                    t(inst.pin_dx, torch.float32), t(inst.pin_dy, torch.float32),
-                   base=base, cap=cap)
+                   base=base, cap=cap, fast=fast, stream=stream)
 
 
 def eval(plan: Plan, prob: Problem, x, y, lam, gamma, grad_mode, gx, gy, out4,

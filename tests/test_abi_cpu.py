@@ -47,7 +47,8 @@ def test_struct_layouts_match_header():
     from paper_1312_4587_amd import _lib as L
     assert ctypes.sizeof(L.fftpl_grid) == 48
     assert L.fftpl_problem.w.offset == 64
-    assert ctypes.sizeof(L.fftpl_problem) == 64 + 8 * 8
+    assert ctypes.sizeof(L.fftpl_problem) == 64 + 8 * 8 + 4 * 8
+    assert L.fftpl_problem.work_bytes.offset == 152
 
 
 def test_argument_errors_are_reported_before_any_device_work():

@@ -281,9 +281,10 @@ def test_wa_grad(F, which):
 # full evaluation
 # ---------------------------------------------------------------------------
 
-def _run_eval(F, inst, lam, mode, dct="fft", plan=None):
+def _run_eval(F, inst, lam, mode, dct="fft", plan=None, fast=True):
     import torch
-    prob = F.Problem.from_instance(inst)
+    prob = F.Problem.from_instance(inst, fast=fast)
+    assert prob.fast == fast
     own = plan is None
     plan = plan or F.Plan(inst.n, dct)
     c = DeviceCells(inst)
@@ -318,13 +319,14 @@ def _check_eval(inst, got, ref, lam, mode):
     assert rel_l2(got["gx"], ref["gx"]) < RTOL and rel_l2(got["gy"], ref["gy"]) < RTOL
 
 
+@pytest.mark.parametrize("fast", [True, False])
 @pytest.mark.parametrize("mode", ["field", "exact"])
-def test_eval_small(F, mode):
+def test_eval_small(F, mode, fast):
     inst = gen.make_config("small_2k")
     inst = with_macros(inst, [[30.0, 30.0, 10.0, 8.0], [60.0, 20.0, 5.0, 12.0]])
     lam = 3.0
-    say("eval small", mode)
-    got = _run_eval(F, inst, lam, mode)
+    say("eval small", mode, "fast" if fast else "atomic")
+    got = _run_eval(F, inst, lam, mode, fast=fast)
     ref = oracle.evaluate(inst, lam=lam, grad_mode=mode)
     _check_eval(inst, got, ref, lam, mode)
 
@@ -343,16 +345,18 @@ def test_eval_edge_cases(F):
     import torch
     # no cells and no nets at the smallest grid
     inst = hand_instance(np.zeros((0, 4)), n=8)
-    got = _run_eval(F, inst, 1.0, "field")
-    assert np.all(got["out"] == 0.0) and np.all(got["rho"] == 0.0)
+    for fast in (True, False):
+        got = _run_eval(F, inst, 1.0, "field", fast=fast)
+        assert np.all(got["out"] == 0.0) and np.all(got["rho"] == 0.0)
     # cells partly and fully outside the region, exact mode, n = 8
     inst = hand_instance([[0.25, 2.0, 1.5, 1.0], [7.9, 7.9, 1.0, 3.0], [-5, -5, 1, 1],
                           [4, 4, 0.25, 0.25], [3.3, 5.1, 2.0, 1.0]], n=8,
                          nets=[[(0, 0, 0), (1, 0.1, 0)], [(2, 0, 0), (3, 0, 0), (4, 0, 0)]])
     for mode in ("field", "exact"):
-        got = _run_eval(F, inst, 2.0, mode)
-        ref = oracle.evaluate(inst, lam=2.0, grad_mode=mode)
-        _check_eval(inst, got, ref, 2.0, mode)
+        for fast in (True, False):
+            got = _run_eval(F, inst, 2.0, mode, fast=fast)
+            ref = oracle.evaluate(inst, lam=2.0, grad_mode=mode)
+            _check_eval(inst, got, ref, 2.0, mode)
     # a plan of another size is refused
     plan = F.Plan(16)
     with pytest.raises(F.FFTPLError) as ei:
@@ -367,3 +371,44 @@ def test_eval_repeatable(F):
     b = _run_eval(F, inst, 1.0, "field")
     assert rel_l2(a["gx"], b["gx"]) < 1e-6 and rel_l2(a["rho"], b["rho"]) < 1e-6
     assert abs(a["out"][0] - b["out"][0]) <= 1e-6 * abs(a["out"][0])
+
+
+def test_netlist_index_is_a_cell_major_permutation(F):
+    import torch
+    inst = gen.make_instance(41, num_cells=50_000, util=0.8, n=256, num_nets=60_000,
+                             hi_frac=0.01, hi_range=(20, 300))
+    m, P = inst.num_cells, inst.num_pins
+    say("netlist index", m, P)
+    cp = torch.empty(m + 1, dtype=torch.int32, device="cuda")
+    ps = torch.empty(P, dtype=torch.int32, device="cuda")
+    F.netlist_index(m, dev(inst.pin_cell), cp, ps)
+    cp, ps = host(cp), host(ps)
+    cnt = np.bincount(inst.pin_cell, minlength=m)
+    assert np.array_equal(cp, np.concatenate([[0], np.cumsum(cnt)]))
+    assert np.array_equal(np.sort(ps), np.arange(P))
+    c = inst.pin_cell
+    assert np.all(ps >= cp[c]) and np.all(ps < cp[c + 1])
+
+
+@pytest.mark.parametrize("n", [16, 64, 512, 1024])
+def test_banded_scatter_with_tall_and_outside_cells(F, n):
+    # cells spanning many bands take the short list every band block walks;
+    # cells outside the region and ragged sizes mixed in
+    rng = np.random.default_rng(n)
+    m = 3000
+    side = 100.0
+    x = rng.random(m) * 110 - 5
+    y = rng.random(m) * 110 - 5
+    w = rng.integers(1, 5, m).astype(float)
+    h = np.ones(m)
+    tall = rng.random(m) < 0.02
+    h[tall] = rng.random(tall.sum()) * 60 + 5
+    w[rng.random(m) < 0.01] = 40.0
+    cells = np.stack([x, y, w, h], axis=1)
+    nets = [[(int(a), 0.0, 0.0), (int(b), 0.1, -0.1)] for a, b in rng.integers(0, m, (500, 2)) if a != b]
+    inst = hand_instance(cells, n=n, bin_size=side / n, nets=nets)
+    inst = with_macros(inst, [[50.0, 50.0, 10.0, 30.0]])
+    say("band scatter", n)
+    got = _run_eval(F, inst, 1.0, "field", fast=True)
+    ref = oracle.evaluate(inst, lam=1.0, grad_mode="field")
+    _check_eval(inst, got, ref, 1.0, "field")
