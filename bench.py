@@ -57,18 +57,24 @@ def kernel_bytes(inst, nent):
     """Algorithmic bytes per launch of every kernel of the atomic-free
     evaluation: compulsory reads and writes of its inputs and outputs in the
     float32 structure-of-arrays layout (entries are 16-byte band records)."""
+    import numpy as np
     m, E, P, n2 = inst.num_cells, inst.num_nets, inst.num_pins, inst.n ** 2
+    deg = np.diff(inst.net_ptr.astype(np.int64))
+    p_big = int(deg[deg > 8].sum())
+    p_small = P - p_big
     return {
         "k_init_eval": 0,
+        # pins (cell, dx, dy) in, per-pin gradient out, net_ptr; positions once
+        "k_wa_slots_small": 12 * p_small + 8 * p_small + 4 * (E + 1) + 8 * m,
+        "k_wa_slots_big": 12 * p_big + 8 * p_big + 4 * (E + 1),
         "k_band_count": 16 * m,
         "k_band_place": 16 * m + 8 * m + 16 * nent,
         "k_band_accum": 16 * nent + 4 * n2 + 4 * n2,
         "k_rows_dct2": 4 * n2 + 4 * n2 + 8 * n2,        # rho, base+cap in; bT out
         "k_cols_solve": 4 * n2 + 8 * n2,                # bT in; P, Q out
         "k_rows_inverse": 8 * n2 + 4 * n2 + 8 * n2,     # P, Q, rho in; (Ex, Ey) out
-        "k_wa_slots": 12 * P + 4 * (E + 1) + 8 * m + 8 * P,
         "k_gather_pins": 16 * m + 8 * n2 + 4 * (m + 1) + 8 * P + 8 * m,
-        "k_overflow_finalize": 0,
+        "k_eval_finalize": 0,
     }
 
 

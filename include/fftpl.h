@@ -219,10 +219,11 @@ int fftpl_wa_grad(int32_t num_nets, const int32_t* net_ptr, int32_t num_pins,
                   double* hpwl, void* stream);
 
 /* Bytes of the optional fftpl_problem workspace for grid side n, num_cells
- * cells and num_pins pins (the interleaved positions, per-pin gradients, band
- * lists of the density scatter and their counters).  Host-only. */
-int fftpl_problem_work_bytes(int32_t n, int32_t num_cells, int32_t num_pins,
-                             uint64_t* bytes);
+ * cells, num_nets nets and num_pins pins (the interleaved positions, per-pin
+ * gradients, band lists of the density scatter, their counters, and per-block
+ * partial sums of the wirelength).  Host-only. */
+int fftpl_problem_work_bytes(int32_t n, int32_t num_cells, int32_t num_nets,
+                             int32_t num_pins, uint64_t* bytes);
 
 /* Cell-major index of the pins of a netlist (Section II: the netlist as a
  * hypergraph; this is the transpose of its pin-net incidence), built once per

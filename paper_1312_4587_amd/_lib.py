@@ -59,7 +59,7 @@ SIGNATURES = {
                            c_void_p, c_void_p, c_void_p, c_void_p]),
     "fftpl_debug_cell_bins": (c_int, [_G, c_int, c_void_p, c_void_p, c_void_p,
                                       c_void_p, c_void_p, c_void_p]),
-    "fftpl_problem_work_bytes": (c_int, [c_int, c_int, c_int,
+    "fftpl_problem_work_bytes": (c_int, [c_int, c_int, c_int, c_int,
                                          ctypes.POINTER(ctypes.c_uint64)]),
     "fftpl_netlist_index": (c_int, [c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p,
                                     c_void_p]),

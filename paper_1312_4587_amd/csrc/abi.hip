@@ -77,7 +77,7 @@ void free_plan(Plan& p) {
   hipFree(p.psi);
   hipFree(p.exy);
   hipFree(p.rowsum);
-  hipFree(p.scal);
+  hipFree(p.partials);
   for (int i = 0; i < Plan::kMaxEvents; ++i)
     if (p.ev[i]) hipEventDestroy(p.ev[i]);
   gemm_plan_free(p);
@@ -127,7 +127,7 @@ int fftpl_plan_create(fftpl_plan** out, int32_t n, int32_t dct_mode, void* strea
             hipMalloc(&p.psi, sizeof(float) * nn) == hipSuccess &&
             hipMalloc(&p.exy, sizeof(float) * 2 * nn) == hipSuccess &&
             hipMalloc(&p.rowsum, sizeof(double) * n) == hipSuccess &&
-            hipMalloc(&p.scal, sizeof(double) * 8) == hipSuccess;
+            hipMalloc(&p.partials, sizeof(double) * (3 * (size_t)n / 2 + 2)) == hipSuccess;
   if (!ok) {
     hipGetLastError();
     free_plan(p);
@@ -224,15 +224,17 @@ int fftpl_poisson_solve(fftpl_plan* plan, const fftpl_grid* grid, const float* r
   a.psi = psi;
   a.ex = ex;
   a.ey = ey;
-  a.energy = energy;
+  a.en_part = energy ? plan->p.partials : nullptr;
   hipError_t e = hipSuccess;
   plan->p.nev = 0;
   plan_mark(plan->p, "start", s);
-  if (energy) e = launch_fill_f64(energy, 0.0, 1, s);
-  if (energy) plan_mark(plan->p, "k_fill_f64", s);
-  if (e == hipSuccess)
-    e = plan->p.mode == FFTPL_DCT_FFT ? spectral_fft(plan->p, a, s)
-                                      : spectral_gemm(plan->p, a, s);
+  e = plan->p.mode == FFTPL_DCT_FFT ? spectral_fft(plan->p, a, s)
+                                    : spectral_gemm(plan->p, a, s);
+  if (e == hipSuccess && energy) {
+    e = launch_eval_finalize(plan->p.partials, plan->p.n / 2, nullptr, 0, nullptr, 0, energy,
+                             nullptr, nullptr, nullptr, s);
+    plan_mark(plan->p, "k_eval_finalize", s);
+  }
   return dev_status(e);
 }
 
@@ -307,16 +309,16 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
   const int64_t nn = (int64_t)p.n * p.n;
   // Atomic-free path when the caller supplied the pin index and workspace.
   size_t need = 0;
-  BandLayout L = band_layout(p.n, m, prob->num_pins, nullptr, &need);
+  BandLayout L = band_layout(p.n, m, prob->num_nets, prob->num_pins, nullptr, &need);
   const bool fast = prob->cell_ptr && prob->pin_slot && prob->work &&
                     prob->work_bytes >= need && p.n <= kBandMaxN;
-  if (fast) L = band_layout(p.n, m, prob->num_pins, prob->work, nullptr);
+  if (fast) L = band_layout(p.n, m, prob->num_nets, prob->num_pins, prob->work, nullptr);
   hipError_t e = hipSuccess;
   p.nev = 0;
   plan_mark(p, "start", s);
   if (fast) {
     // 1. zero scalars and band counters; 2. banded density scatter
-    e = launch_init_eval(out4, p.scal, L.counters, L.nb + 1, s);
+    e = launch_init_eval(out4, L.counters, L.nb + 1, s);
     plan_mark(p, "k_init_eval", s);
     if (e == hipSuccess)
       e = launch_band_scatter(g, L, x, y, prob->w, prob->h, prob->base, p.rho, s, &p);
@@ -324,7 +326,7 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
     // 1. reset: rho = base, scalar accumulators = 0; 2. atomic scatter
     e = launch_fill(p.rho, prob->base, 0.0f, nn, s);
     plan_mark(p, "k_fill", s);
-    if (e == hipSuccess) e = launch_init_eval(out4, p.scal, nullptr, 0, s);
+    if (e == hipSuccess) e = launch_init_eval(out4, nullptr, 0, s);
     plan_mark(p, "k_init_eval", s);
     if (e == hipSuccess) e = launch_scatter(g, m, x, y, prob->w, prob->h, p.rho, s);
     plan_mark(p, "k_scatter", s);
@@ -335,11 +337,11 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
     a.rho = p.rho;
     a.psi = grad_mode == FFTPL_GRAD_EXACT ? p.psi : nullptr;
     a.exy = grad_mode == FFTPL_GRAD_FIELD ? p.exy : nullptr;
-    a.energy = &out4[0];
+    a.en_part = p.partials;
     a.base = prob->base;
     a.cap = prob->cap;
     a.rho_t = g.rho_t;
-    a.tau2 = p.scal;
+    a.tau_part = p.partials + p.n / 2;
     e = p.mode == FFTPL_DCT_FFT ? spectral_fft(p, a, s) : spectral_gemm(p, a, s);
   }
   if (fast) {
@@ -347,9 +349,8 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
     // gradient plus the sum of its pins' slots
     if (e == hipSuccess)
       e = launch_wa_pins(prob->num_nets, prob->net_ptr, prob->pin_cell, prob->pin_dx,
-                         prob->pin_dy, L.xy, prob->pin_slot, gamma, L.pin_grad, &out4[1],
-                         &out4[2], s);
-    plan_mark(p, "k_wa_slots", s);
+                         prob->pin_dy, L.xy, prob->pin_slot, gamma, L.pin_grad, L.wa_part,
+                         s, &p);
     if (e == hipSuccess)
       e = launch_gather_pins(g, m, x, y, prob->w, prob->h, p.exy, p.psi, grad_mode, lambda,
                              prob->cell_ptr, L.pin_grad, gx, gy, s);
@@ -365,8 +366,13 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
                     prob->pin_dy, x, y, gamma, gx, gy, &out4[1], &out4[2], s);
     plan_mark(p, "k_wa_atomic", s);
   }
-  if (e == hipSuccess) e = launch_overflow_finalize(out4, p.scal, s);
-  plan_mark(p, "k_overflow_finalize", s);
+  // 6. N, W~, HPWL, tau from the per-block partials (the atomic path added
+  // W~ and HPWL into out4 directly)
+  if (e == hipSuccess)
+    e = launch_eval_finalize(p.partials, p.n / 2, p.partials + p.n / 2, p.n / 2,
+                             fast ? L.wa_part : nullptr, L.nwa, &out4[0], &out4[1], &out4[2],
+                             &out4[3], s);
+  plan_mark(p, "k_eval_finalize", s);
   return dev_status(e);
 }
 
@@ -400,11 +406,12 @@ int fftpl_plan_kernel_times(fftpl_plan* plan, int32_t max, float* ms, const char
   return FFTPL_OK;
 }
 
-int fftpl_problem_work_bytes(int32_t n, int32_t num_cells, int32_t num_pins,
-                             uint64_t* bytes) {
-  if (!bytes || n < 1 || num_cells < 0 || num_pins < 0) return FFTPL_E_INVAL;
+int fftpl_problem_work_bytes(int32_t n, int32_t num_cells, int32_t num_nets,
+                             int32_t num_pins, uint64_t* bytes) {
+  if (!bytes || n < 1 || num_cells < 0 || num_nets < 0 || num_pins < 0)
+    return FFTPL_E_INVAL;
   size_t need = 0;
-  band_layout(n, num_cells, num_pins, nullptr, &need);
+  band_layout(n, num_cells, num_nets, num_pins, nullptr, &need);
   *bytes = need;
   return FFTPL_OK;
 }

@@ -125,181 +125,17 @@ hipError_t launch_scatter(const GridF& g, int m, const float* x, const float* y,
   return hipGetLastError();
 }
 
-// ---------------------------------------------------------------------------
-// Banded scatter.  Float atomics in global memory retire at roughly 20 G/s
-// on the whole chip whatever their scope, so the map is built without them:
-//   count: each block of kCellsPerBlock cells histograms the bands its
-//          cells touch in LDS and reserves its slice of every band with one
-//          integer atomic per (block, band);
-//   place: the same blocks write each cell's edges (bin units) into every
-//          band it touches, at LDS-atomic ranks inside the reserved slice,
-//          and the interleaved (x, y) the wirelength pass gathers;
-//   accum: one block per band adds its entries into an LDS copy of its rows
-//          (LDS float atomics) and writes rho = base + rows once.
-// ---------------------------------------------------------------------------
-static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
-
-BandLayout band_layout(int n, int m, int num_pins, void* work, size_t* bytes_out) {
-  BandLayout L;
-  L.n = n;
-  L.rows = (n + 255) / 256;              // <= 4 rows for n <= 1024: rows*n <= 4096
-  L.nb = (n + L.rows - 1) / L.rows;      // <= 256 bands; the last may be short
-  L.m = m;
-  L.nblk = m > 0 ? (m + kCellsPerBlock - 1) / kCellsPerBlock : 1;
-  size_t off = 0;
-  const size_t o_xy = off;
-  off = align256(off + sizeof(float2) * (size_t)m);
-  const size_t o_pg = off;
-  off = align256(off + sizeof(float2) * (size_t)num_pins);
-  const size_t o_en = off;
-  off = align256(off + sizeof(float4) * (size_t)kMaxBands * m);
-  const size_t o_big = off;
-  off = align256(off + sizeof(int32_t) * (size_t)m);
-  const size_t o_bb = off;
-  off = align256(off + sizeof(int32_t) * (size_t)L.nblk * L.nb);
-  const size_t o_ct = off;
-  off = align256(off + sizeof(int32_t) * (size_t)(L.nb + 1));
-  if (bytes_out) *bytes_out = off;
-  if (work) {
-    char* b = static_cast<char*>(work);
-    L.xy = reinterpret_cast<float2*>(b + o_xy);
-    L.pin_grad = reinterpret_cast<float2*>(b + o_pg);
-    L.entries = reinterpret_cast<float4*>(b + o_en);
-    L.big = reinterpret_cast<int32_t*>(b + o_big);
-    L.blk_base = reinterpret_cast<int32_t*>(b + o_bb);
-    L.counters = reinterpret_cast<int32_t*>(b + o_ct);
-  }
-  return L;
-}
-
-__global__ void __launch_bounds__(256)
-    k_band_count(GridF g, BandLayout L, const float* __restrict__ x,
-                 const float* __restrict__ y, const float* __restrict__ w,
-                 const float* __restrict__ h) {
-  __shared__ int hist[256];
-  for (int b = threadIdx.x; b < L.nb; b += blockDim.x) hist[b] = 0;
-  __syncthreads();
-  const int c0 = blockIdx.x * kCellsPerBlock;
-  const int c1 = min(L.m, c0 + kCellsPerBlock);
-  for (int i = c0 + (int)threadIdx.x; i < c1; i += blockDim.x) {
-    const Span sx = cell_span(x[i], w[i], g.xl, g.inv_bw, g.n);
-    const Span sy = cell_span(y[i], h[i], g.yl, g.inv_bh, g.n);
-    if (sx.i0 > sx.i1 || sy.i0 > sy.i1) continue;
-    const int b0 = sy.i0 / L.rows, b1 = sy.i1 / L.rows;
-    if (b1 - b0 >= kMaxBands) {
-      L.big[atomicAdd(&L.counters[L.nb], 1)] = i;
-      continue;
-    }
-    for (int b = b0; b <= b1; ++b) atomicAdd(&hist[b], 1);
-  }
-  __syncthreads();
-  for (int b = threadIdx.x; b < L.nb; b += blockDim.x) {
-    const int c = hist[b];
-    L.blk_base[(size_t)blockIdx.x * L.nb + b] = c ? atomicAdd(&L.counters[b], c) : 0;
-  }
-}
-
-__global__ void __launch_bounds__(256)
-    k_band_place(GridF g, BandLayout L, const float* __restrict__ x,
-                 const float* __restrict__ y, const float* __restrict__ w,
-                 const float* __restrict__ h) {
-  __shared__ int cursor[256];
-  const int t = threadIdx.x;
-  int total;
-  const int ex = block_exclusive_scan256(t < L.nb ? L.counters[t] : 0, &total);
-  if (t < L.nb) cursor[t] = ex + L.blk_base[(size_t)blockIdx.x * L.nb + t];
-  __syncthreads();
-  const int c0 = blockIdx.x * kCellsPerBlock;
-  const int c1 = min(L.m, c0 + kCellsPerBlock);
-  for (int i = c0 + t; i < c1; i += blockDim.x) {
-    const float xv = x[i], yv = y[i];
-    L.xy[i] = make_float2(xv, yv);
-    const Span sx = cell_span(xv, w[i], g.xl, g.inv_bw, g.n);
-    const Span sy = cell_span(yv, h[i], g.yl, g.inv_bh, g.n);
-    if (sx.i0 > sx.i1 || sy.i0 > sy.i1) continue;
-    const int b0 = sy.i0 / L.rows, b1 = sy.i1 / L.rows;
-    if (b1 - b0 >= kMaxBands) continue;
-    const float4 e = make_float4(sx.lo, sx.hi, sy.lo, sy.hi);
-    for (int b = b0; b <= b1; ++b) L.entries[atomicAdd(&cursor[b], 1)] = e;
-  }
-}
-
-__global__ void __launch_bounds__(256)
-    k_band_accum(GridF g, BandLayout L, const float* __restrict__ x,
-                 const float* __restrict__ y, const float* __restrict__ w,
-                 const float* __restrict__ h, const float* __restrict__ base,
-                 float* __restrict__ rho) {
-  __shared__ float acc[kBandMaxN * 4];   // rows * n <= 4096 floats
-  const int t = threadIdx.x;
-  const int n = g.n, R = L.rows, band = blockIdx.x, r0 = band * R;
-  const int cells = min(R, n - r0) * n;
-  for (int k = t; k < cells; k += blockDim.x) acc[k] = 0.0f;
-  int start;
-  block_exclusive_scan256(t < band ? L.counters[t] : 0, &start);   // sum of earlier bands
-  const int count = L.counters[band];
-  __syncthreads();
-  for (int e = start + t; e < start + count; e += blockDim.x) {
-    const float4 q = L.entries[e];
-    const Span sx = span_from_edges(q.x, q.y, n);
-    const Span sy = span_from_edges(q.z, q.w, n);
-    const int ya = max(sy.i0, r0), yb = min(sy.i1, r0 + R - 1);
-    for (int iy = ya; iy <= yb; ++iy) {
-      const float oy = span_overlap(sy, iy);
-      float* row = acc + (iy - r0) * n;
-      for (int ix = sx.i0; ix <= sx.i1; ++ix) atomicAdd(&row[ix], span_overlap(sx, ix) * oy);
-    }
-  }
-  // cells too tall to be listed per band: every band block adds its rows of them
-  const int nbig = L.counters[L.nb];
-  for (int j = 0; j < nbig; ++j) {
-    const int i = L.big[j];
-    const Span sx = cell_span(x[i], w[i], g.xl, g.inv_bw, n);
-    const Span sy = cell_span(y[i], h[i], g.yl, g.inv_bh, n);
-    const int ya = max(sy.i0, r0), yb = min(sy.i1, r0 + R - 1);
-    if (ya > yb) continue;
-    const int nx = sx.i1 - sx.i0 + 1;
-    const int tot = nx * (yb - ya + 1);
-    for (int k = t; k < tot; k += blockDim.x) {
-      const int ix = sx.i0 + k % nx, iy = ya + k / nx;
-      atomicAdd(&acc[(iy - r0) * n + ix], span_overlap(sx, ix) * span_overlap(sy, iy));
-    }
-  }
-  __syncthreads();
-  const size_t o = (size_t)r0 * n;
-  for (int k = t; k < cells; k += blockDim.x) rho[o + k] = (base ? base[o + k] : 0.0f) + acc[k];
-}
-
-hipError_t launch_band_scatter(const GridF& g, const BandLayout& L, const float* x,
-                               const float* y, const float* w, const float* h,
-                               const float* base, float* rho, hipStream_t s, Plan* tp) {
-  if (L.m > 0) {
-    hipLaunchKernelGGL(k_band_count, dim3(L.nblk), dim3(256), 0, s, g, L, x, y, w, h);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    if (tp) plan_mark(*tp, "k_band_count", s);
-    hipLaunchKernelGGL(k_band_place, dim3(L.nblk), dim3(256), 0, s, g, L, x, y, w, h);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (tp) plan_mark(*tp, "k_band_place", s);
-  }
-  hipLaunchKernelGGL(k_band_accum, dim3(L.nb), dim3(256), 0, s, g, L, x, y, w, h, base, rho);
-  hipError_t e = hipGetLastError();
-  if (tp) plan_mark(*tp, "k_band_accum", s);
-  return e;
-}
-
 // Zero the per-evaluation scalars and the band counters in one launch.
-__global__ void k_init_eval(double* __restrict__ out4, double* __restrict__ scal,
-                            int32_t* __restrict__ counters, int ncount) {
+__global__ void k_init_eval(double* __restrict__ out4, int32_t* __restrict__ counters,
+                            int ncount) {
   const int t = threadIdx.x;
   if (t < 4) out4[t] = 0.0;
-  if (t < 2) scal[t] = 0.0;
   if (counters)
     for (int k = t; k < ncount; k += blockDim.x) counters[k] = 0;
 }
 
-hipError_t launch_init_eval(double* out4, double* scal, int32_t* counters, int ncount,
-                            hipStream_t s) {
-  hipLaunchKernelGGL(k_init_eval, dim3(1), dim3(256), 0, s, out4, scal, counters, ncount);
+hipError_t launch_init_eval(double* out4, int32_t* counters, int ncount, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_eval, dim3(1), dim3(256), 0, s, out4, counters, ncount);
   return hipGetLastError();
 }
 

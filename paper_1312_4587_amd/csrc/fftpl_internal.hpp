@@ -95,9 +95,11 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
   return (b % kNumXcd) * (nb / kNumXcd) + b / kNumXcd;
 }
 
-// Exclusive prefix sum over a 256-thread block; *total gets the block sum.
-__device__ __forceinline__ int block_exclusive_scan256(int v, int* total) {
-  __shared__ int wsum[4];
+// Exclusive prefix sum over a block of NT threads; *total gets the block sum.
+template <int NT>
+__device__ __forceinline__ int block_exclusive_scan(int v, int* total) {
+  constexpr int NW = NT / kWave;
+  __shared__ int wsum[NW];
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
   int inc = v;
 #pragma unroll
@@ -109,7 +111,7 @@ __device__ __forceinline__ int block_exclusive_scan256(int v, int* total) {
   __syncthreads();
   int woff = 0, tot = 0;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < NW; ++k) {
     if (k < w) woff += wsum[k];
     tot += wsum[k];
   }
@@ -118,8 +120,16 @@ __device__ __forceinline__ int block_exclusive_scan256(int v, int* total) {
   return woff + inc - v;
 }
 
-// Block-wide double sum to one atomicAdd (blockDim a multiple of 64, <= 1024).
-__device__ __forceinline__ void block_atomic_add(double v, double* dst) {
+__device__ __forceinline__ int block_exclusive_scan256(int v, int* total) {
+  return block_exclusive_scan<256>(v, total);
+}
+
+// Block-wide double sum (blockDim a multiple of 64, <= 1024), either added to
+// *dst with one atomic or stored to *dst.  Many blocks adding to one address
+// serialise on it, so the hot paths store per-block partials instead and
+// reduce them in a final kernel.
+template <bool ATOMIC>
+__device__ __forceinline__ void block_sum_to(double v, double* dst) {
   __shared__ double red[16];
   v = wave_sum(v);
   const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
@@ -129,9 +139,18 @@ __device__ __forceinline__ void block_atomic_add(double v, double* dst) {
     const int nw = blockDim.x / kWave;
     double t = lane < nw ? red[lane] : 0.0;
     t = wave_sum(t);
-    if (lane == 0) atomicAdd(dst, t);
+    if (lane == 0) {
+      if (ATOMIC)
+        atomicAdd(dst, t);
+      else
+        *dst = t;
+    }
   }
   __syncthreads();
+}
+
+__device__ __forceinline__ void block_atomic_add(double v, double* dst) {
+  block_sum_to<true>(v, dst);
 }
 
 // ---------------------------------------------------------------------------
@@ -162,7 +181,7 @@ struct Plan {
   void* gemm_ws = nullptr;  // extra GEMM-mode workspace
   size_t gemm_ws_bytes = 0;
   double* rowsum = nullptr; // n doubles
-  double* scal = nullptr;   // 8 doubles of scalar accumulators
+  double* partials = nullptr;  // n/2 energy partials, then n overflow partials
   // Optional per-kernel timing: an event is recorded on the launch stream
   // after every kernel of an evaluation (the first one before it).
   static constexpr int kMaxEvents = 24;
@@ -202,7 +221,9 @@ hipError_t launch_wa(int num_nets, const int32_t* net_ptr, const int32_t* pin_ce
                      const float* pin_dx, const float* pin_dy, const float* x,
                      const float* y, float gamma, float* gx, float* gy,
                      double* wa_out, double* hp_out, hipStream_t s);
-hipError_t launch_overflow_finalize(double* out4, const double* scal, hipStream_t s);
+hipError_t launch_eval_finalize(const double* en, int n_en, const double* tau, int n_tau,
+                                const double* wa, int n_wa, double* o_en, double* o_wa,
+                                double* o_hp, double* o_tau, hipStream_t s);
 
 // ---- banded density scatter (atomic-free in global memory) ----------------
 // Cells are counting-sorted into bands of `rows` bin rows (a cell is listed in
@@ -211,7 +232,9 @@ hipError_t launch_overflow_finalize(double* out4, const double* scal, hipStream_
 // in LDS and writes them out.  Needs n <= kBandMaxN.
 constexpr int kMaxBands = 4;
 constexpr int kBandMaxN = 1024;
-constexpr int kCellsPerBlock = 8192;   // cells per counting/placing block
+constexpr int kBandThreads = 1024;     // threads of every band-sort block
+constexpr int kCellBatch = 8;          // cells whose loads a thread issues together
+constexpr int kCellsPerBlock = kBandThreads * 2 * kCellBatch;   // 16384
 
 struct BandLayout {
   int n = 0, rows = 0, nb = 0;   // band height in rows, number of bands
@@ -223,19 +246,21 @@ struct BandLayout {
   int32_t* big = nullptr;        // [m] cells spanning more than kMaxBands bands
   int32_t* blk_base = nullptr;   // [nblk*nb] block offsets inside each band
   int32_t* counters = nullptr;   // [nb + 1] band counts, then the big-cell count
+  double* wa_part = nullptr;     // [4*nwa] per-block W~ / HPWL partials
+  int nwa = 0;                   // blocks of each wirelength kernel
 };
-BandLayout band_layout(int n, int m, int num_pins, void* work, size_t* bytes_out);
+BandLayout band_layout(int n, int m, int num_nets, int num_pins, void* work,
+                       size_t* bytes_out);
 
 hipError_t launch_band_scatter(const GridF& g, const BandLayout& L, const float* x,
                                const float* y, const float* w, const float* h,
                                const float* base, float* rho, hipStream_t s,
                                Plan* tp = nullptr);
-hipError_t launch_init_eval(double* out4, double* scal, int32_t* counters, int ncount,
-                            hipStream_t s);
+hipError_t launch_init_eval(double* out4, int32_t* counters, int ncount, hipStream_t s);
 hipError_t launch_wa_pins(int num_nets, const int32_t* net_ptr, const int32_t* pin_cell,
                           const float* pin_dx, const float* pin_dy, const float2* xy,
                           const int32_t* pin_slot, float gamma, float2* pin_grad,
-                          double* wa_out, double* hp_out, hipStream_t s);
+                          double* wa_part, hipStream_t s, Plan* tp = nullptr);
 hipError_t launch_gather_pins(const GridF& g, int m, const float* x, const float* y,
                               const float* w, const float* h, const float* exy,
                               const float* psi, int grad_mode, float scale,
@@ -245,20 +270,21 @@ hipError_t launch_netlist_index(int m, int num_pins, const int32_t* pin_cell,
                                 int32_t* cell_ptr, int32_t* pin_slot, int32_t* work,
                                 hipStream_t s);
 
-// Spectral solve.  psi/ex/ey/exy may be null individually; energy may be null.
-// If base/cap_or_null and tau2 are given, pass A also accumulates the two
-// overflow sums into tau2[0], tau2[1] (tau2 must be zeroed by the caller).
+// Spectral solve.  psi/ex/ey/exy may be null individually.  en_part, if set,
+// receives n/2 per-block partials of the energy sum rho*psi; tau_part, if
+// set, n values: per-block pairs (overflow, movable area) of the first pass,
+// read against base (or 0) and cap (or rho_t - min(rho_t, base)).
 struct SpectralArgs {
   const float* rho = nullptr;
   float* psi = nullptr;
   float* ex = nullptr;
   float* ey = nullptr;
   float* exy = nullptr;
-  double* energy = nullptr;     // accumulated into (caller zeroes)
+  double* en_part = nullptr;
   const float* base = nullptr;
   const float* cap = nullptr;
   float rho_t = 1.0f;
-  double* tau2 = nullptr;
+  double* tau_part = nullptr;
 };
 hipError_t spectral_fft(Plan& p, const SpectralArgs& a, hipStream_t s);
 hipError_t spectral_gemm(Plan& p, const SpectralArgs& a, hipStream_t s);

@@ -114,6 +114,15 @@ __device__ __forceinline__ void wave_fft(float2* buf, const float2* __restrict__
   }
 }
 
+// Copy the twiddle table into LDS (one coalesced read per block; the FFT
+// stages then never wait on global memory for a twiddle).
+template <int N>
+__device__ __forceinline__ void stage_twiddles(float2* tw, const float2* __restrict__ tw_g,
+                                               int lane) {
+  for (int t = lane; t < N; t += kWave) tw[t] = tw_g[t];
+  wave_lds_sync();
+}
+
 // Forward post-processing for the pair (k, n-k) of a two-real-sequence FFT
 // V = FFT(v1 + i v2): returns the DCT-II outputs X1, X2 at k and n-k.
 // cs = (cos, sin)(pi k / 2n).
@@ -151,12 +160,14 @@ __device__ __forceinline__ float2 pack2(float2 ha, float2 hb) {
 template <int N>
 __global__ void __launch_bounds__(64)
     k_rows_dct2(const float* __restrict__ rho, float* __restrict__ bT,
-                double* __restrict__ rowsum, const float2* __restrict__ tw,
+                double* __restrict__ rowsum, const float2* __restrict__ tw_g,
                 const float2* __restrict__ cs, const float* __restrict__ base,
-                const float* __restrict__ cap, float rho_t, double* __restrict__ tau2) {
+                const float* __restrict__ cap, float rho_t, double* __restrict__ tau_part) {
   __shared__ float2 buf[N];
+  __shared__ float2 tw[N];
   constexpr int PER = (N + kWave - 1) / kWave;
   const int lane = threadIdx.x;
+  stage_twiddles<N>(tw, tw_g, lane);
   const int pair = xcd_block(blockIdx.x, gridDim.x);
   const int r1 = 2 * pair, r2 = r1 + 1;
   float a1[PER], a2[PER];
@@ -169,7 +180,7 @@ __global__ void __launch_bounds__(64)
       a2[t] = rho[(int64_t)r2 * N + i];
       s1 += a1[t];
       s2 += a2[t];
-      if (tau2) {
+      if (tau_part) {
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
           const int64_t b = (int64_t)(q ? r2 : r1) * N + i;
@@ -184,12 +195,12 @@ __global__ void __launch_bounds__(64)
   }
   s1 = wave_sum(s1);
   s2 = wave_sum(s2);
-  if (tau2) {
+  if (tau_part) {
     ovf = wave_sum(ovf);
     mov = wave_sum(mov);
     if (lane == 0) {
-      atomicAdd(&tau2[0], ovf);
-      atomicAdd(&tau2[1], mov);
+      tau_part[2 * pair] = ovf;
+      tau_part[2 * pair + 1] = mov;
     }
   }
   const float m1 = (float)(s1 / N), m2 = (float)(s2 / N);
@@ -226,12 +237,14 @@ template <int N>
 __global__ void __launch_bounds__(64)
     k_cols_solve(const float* __restrict__ bT, const double* __restrict__ rowsum,
                  float* __restrict__ P, float* __restrict__ Q,
-                 const float2* __restrict__ tw, const float2* __restrict__ cs,
+                 const float2* __restrict__ tw_g, const float2* __restrict__ cs,
                  const float* __restrict__ wf) {
   __shared__ float2 buf0[N];
   __shared__ float2 buf1[N];
+  __shared__ float2 tw[N];
   constexpr int PER = (N + kWave - 1) / kWave;
   const int lane = threadIdx.x;
+  stage_twiddles<N>(tw, tw_g, lane);
   const int q = xcd_block(blockIdx.x, gridDim.x);
   const int u1 = 2 * q, u2 = u1 + 1;
   double mean0 = 0.0;
@@ -302,12 +315,14 @@ __global__ void __launch_bounds__(64)
                    const float* __restrict__ rho, float* __restrict__ psi,
                    float* __restrict__ ex, float* __restrict__ ey,
                    float2* __restrict__ exy, double* __restrict__ energy,
-                   const float2* __restrict__ tw, const float2* __restrict__ cs,
+                   const float2* __restrict__ tw_g, const float2* __restrict__ cs,
                    const float* __restrict__ wf) {
   __shared__ float2 bufa[N];
   __shared__ float2 bufb[N];
   __shared__ float2 bufc[N];
+  __shared__ float2 tw[N];
   const int lane = threadIdx.x;
+  stage_twiddles<N>(tw, tw_g, lane);
   const int pr = xcd_block(blockIdx.x, gridDim.x);
   const int r1 = 2 * pr, r2 = r1 + 1;
   const float* P1 = P + (int64_t)r1 * N;
@@ -366,7 +381,7 @@ __global__ void __launch_bounds__(64)
   }
   if (energy) {
     en = wave_sum(en);
-    if (lane == 0) atomicAdd(energy, en);
+    if (lane == 0) energy[pr] = en;   // per-block partial
   }
 }
 
@@ -374,7 +389,7 @@ template <int N>
 hipError_t run_fft(Plan& p, const SpectralArgs& a, hipStream_t s) {
   const dim3 grid(N / 2), block(kWave);
   hipLaunchKernelGGL(k_rows_dct2<N>, grid, block, 0, s, a.rho, p.tmp0, p.rowsum, p.fft_tw,
-                     p.dct_cs, a.base, a.cap, a.rho_t, a.tau2);
+                     p.dct_cs, a.base, a.cap, a.rho_t, a.tau_part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   plan_mark(p, "k_rows_dct2", s);
@@ -383,7 +398,7 @@ hipError_t run_fft(Plan& p, const SpectralArgs& a, hipStream_t s) {
   if ((e = hipGetLastError()) != hipSuccess) return e;
   plan_mark(p, "k_cols_solve", s);
   hipLaunchKernelGGL(k_rows_inverse<N>, grid, block, 0, s, p.tmp1, p.tmp2, a.rho, a.psi,
-                     a.ex, a.ey, reinterpret_cast<float2*>(a.exy), a.energy, p.fft_tw,
+                     a.ex, a.ey, reinterpret_cast<float2*>(a.exy), a.en_part, p.fft_tw,
                      p.dct_cs, p.wfreq);
   e = hipGetLastError();
   plan_mark(p, "k_rows_inverse", s);

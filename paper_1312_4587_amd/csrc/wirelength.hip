@@ -27,6 +27,7 @@
 namespace fftpl {
 
 constexpr int kSmallDeg = 8;
+constexpr int kBigRegs = 16;   // pins per lane kept in registers for one wave's net
 
 template <bool SLOTS>
 struct PinIO {
@@ -75,12 +76,13 @@ __device__ __forceinline__ float axis_grad(float X, float M, float L, float wp, 
          expf(-dm * inv_gamma) * rsm * (1.0f - (dm - wm) * inv_gamma);
 }
 
-template <bool SLOTS>
+template <bool SLOTS, int PART>   // PART 0: nets of degree <= kSmallDeg; 1: larger nets
 __global__ void __launch_bounds__(256)
     k_wa(int num_nets, const int32_t* __restrict__ net_ptr,
          const int32_t* __restrict__ pin_cell, const float* __restrict__ pin_dx,
          const float* __restrict__ pin_dy, PinIO<SLOTS> io, float inv_gamma,
-         double* __restrict__ wa_out, double* __restrict__ hp_out) {
+         double* __restrict__ wa_out, double* __restrict__ hp_out,
+         double* __restrict__ part) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   const int lane = threadIdx.x & (kWave - 1);
   int p0 = 0, p1 = 0;
@@ -91,19 +93,23 @@ __global__ void __launch_bounds__(256)
   const int deg = p1 - p0;
   double acc_wa = 0.0, acc_hp = 0.0;
 
-  if (deg >= 2 && deg <= kSmallDeg) {
+  if (PART == 0 && deg >= 2 && deg <= kSmallDeg) {
     int cell[kSmallDeg];
     float px[kSmallDeg], py[kSmallDeg];
-    const float2 r = io.pos(pin_cell[p0]);
+    // all loads first (independent), positions relative to the first pin's cell
+#pragma unroll
+    for (int k = 0; k < kSmallDeg; ++k)
+      if (k < deg) cell[k] = pin_cell[p0 + k];
+    float2 q[kSmallDeg];
+#pragma unroll
+    for (int k = 0; k < kSmallDeg; ++k)
+      if (k < deg) q[k] = io.pos(cell[k]);
     float mx = -INFINITY, lx = INFINITY, my = -INFINITY, ly = INFINITY;
 #pragma unroll
     for (int k = 0; k < kSmallDeg; ++k) {
       if (k < deg) {
-        const int c = pin_cell[p0 + k];
-        const float2 q = io.pos(c);
-        cell[k] = c;
-        px[k] = (q.x - r.x) + pin_dx[p0 + k];
-        py[k] = (q.y - r.y) + pin_dy[p0 + k];
+        px[k] = (q[k].x - q[0].x) + pin_dx[p0 + k];
+        py[k] = (q[k].y - q[0].y) + pin_dy[p0 + k];
         mx = fmaxf(mx, px[k]);
         lx = fminf(lx, px[k]);
         my = fmaxf(my, py[k]);
@@ -134,11 +140,77 @@ __global__ void __launch_bounds__(256)
   }
 
   // Larger nets: the whole wavefront cooperates on each in turn.
-  unsigned long long big = __ballot(deg > kSmallDeg);
+  unsigned long long big = PART == 1 ? __ballot(deg > kSmallDeg) : 0ull;
   while (big) {
     const int src = __ffsll((long long)big) - 1;
     big &= big - 1;
     const int b0 = __shfl(p0, src, kWave), b1 = __shfl(p1, src, kWave);
+    if (b1 - b0 <= kWave * kBigRegs) {
+      // up to kBigRegs pins per lane held in registers: one pass over memory
+      int cj[kBigRegs];
+      float2 q[kBigRegs];
+#pragma unroll
+      for (int j = 0; j < kBigRegs; ++j) {
+        const int p = b0 + lane + kWave * j;
+        if (p < b1) cj[j] = pin_cell[p];
+      }
+#pragma unroll
+      for (int j = 0; j < kBigRegs; ++j) {
+        const int p = b0 + lane + kWave * j;
+        if (p < b1) q[j] = io.pos(cj[j]);
+      }
+      const float rx = __shfl(q[0].x, 0, kWave), ry = __shfl(q[0].y, 0, kWave);
+      float mx = -INFINITY, lx = INFINITY, my = -INFINITY, ly = INFINITY;
+#pragma unroll
+      for (int j = 0; j < kBigRegs; ++j) {
+        const int p = b0 + lane + kWave * j;
+        if (p < b1) {
+          q[j].x = (q[j].x - rx) + pin_dx[p];
+          q[j].y = (q[j].y - ry) + pin_dy[p];
+          mx = fmaxf(mx, q[j].x);
+          lx = fminf(lx, q[j].x);
+          my = fmaxf(my, q[j].y);
+          ly = fminf(ly, q[j].y);
+        }
+      }
+      mx = wave_max(mx);
+      lx = wave_min(lx);
+      my = wave_max(my);
+      ly = wave_min(ly);
+      AxisSums sx = {0.f, 0.f, 0.f, 0.f}, sy = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int j = 0; j < kBigRegs; ++j) {
+        if (b0 + lane + kWave * j < b1) {
+          axis_accum(sx, q[j].x, mx, lx, inv_gamma);
+          axis_accum(sy, q[j].y, my, ly, inv_gamma);
+        }
+      }
+      sx.sp = wave_sum(sx.sp);
+      sx.tp = wave_sum(sx.tp);
+      sx.sm = wave_sum(sx.sm);
+      sx.tm = wave_sum(sx.tm);
+      sy.sp = wave_sum(sy.sp);
+      sy.tp = wave_sum(sy.tp);
+      sy.sm = wave_sum(sy.sm);
+      sy.tm = wave_sum(sy.tm);
+      const float wpx = sx.tp / sx.sp, wmx = sx.tm / sx.sm;
+      const float wpy = sy.tp / sy.sp, wmy = sy.tm / sy.sm;
+      const float rspx = 1.0f / sx.sp, rsmx = 1.0f / sx.sm;
+      const float rspy = 1.0f / sy.sp, rsmy = 1.0f / sy.sm;
+#pragma unroll
+      for (int j = 0; j < kBigRegs; ++j) {
+        const int p = b0 + lane + kWave * j;
+        if (p < b1)
+          io.put(p, cj[j], axis_grad(q[j].x, mx, lx, wpx, wmx, rspx, rsmx, inv_gamma),
+                 axis_grad(q[j].y, my, ly, wpy, wmy, rspy, rsmy, inv_gamma));
+      }
+      if (lane == src) {
+        acc_wa += (double)((mx - lx) + wpx - wmx) + (double)((my - ly) + wpy - wmy);
+        acc_hp += (double)(mx - lx) + (double)(my - ly);
+      }
+      continue;
+    }
+    // nets beyond the register capacity: three passes over the pins
     const float2 r = io.pos(pin_cell[b0]);
     float mx = -INFINITY, lx = INFINITY, my = -INFINITY, ly = INFINITY;
     for (int p = b0 + lane; p < b1; p += kWave) {
@@ -183,8 +255,14 @@ __global__ void __launch_bounds__(256)
       acc_hp += (double)(mx - lx) + (double)(my - ly);
     }
   }
-  if (wa_out) block_atomic_add(acc_wa, wa_out);
-  if (hp_out) block_atomic_add(acc_hp, hp_out);
+  if (part) {
+    // per-block partials: part[b] = W~, part[gridDim.x + b] = HPWL
+    block_sum_to<false>(acc_wa, &part[blockIdx.x]);
+    block_sum_to<false>(acc_hp, &part[gridDim.x + blockIdx.x]);
+  } else {
+    if (wa_out) block_atomic_add(acc_wa, wa_out);
+    if (hp_out) block_atomic_add(acc_hp, hp_out);
+  }
 }
 
 hipError_t launch_wa(int num_nets, const int32_t* net_ptr, const int32_t* pin_cell,
@@ -193,29 +271,94 @@ hipError_t launch_wa(int num_nets, const int32_t* net_ptr, const int32_t* pin_ce
                      double* wa_out, double* hp_out, hipStream_t s) {
   if (num_nets <= 0) return hipSuccess;
   PinIO<false> io{x, y, nullptr, nullptr, gx, gy, nullptr};
-  hipLaunchKernelGGL(k_wa<false>, dim3((num_nets + 255) / 256), dim3(256), 0, s, num_nets,
-                     net_ptr, pin_cell, pin_dx, pin_dy, io, 1.0f / gamma, wa_out, hp_out);
+  const dim3 grid((num_nets + 255) / 256);
+  hipLaunchKernelGGL((k_wa<false, 0>), grid, dim3(256), 0, s, num_nets, net_ptr, pin_cell,
+                     pin_dx, pin_dy, io, 1.0f / gamma, wa_out, hp_out, nullptr);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_wa<false, 1>), grid, dim3(256), 0, s, num_nets, net_ptr, pin_cell,
+                     pin_dx, pin_dy, io, 1.0f / gamma, wa_out, hp_out, nullptr);
   return hipGetLastError();
 }
 
 hipError_t launch_wa_pins(int num_nets, const int32_t* net_ptr, const int32_t* pin_cell,
                           const float* pin_dx, const float* pin_dy, const float2* xy,
                           const int32_t* pin_slot, float gamma, float2* pin_grad,
-                          double* wa_out, double* hp_out, hipStream_t s) {
+                          double* wa_part, hipStream_t s, Plan* tp) {
   if (num_nets <= 0) return hipSuccess;
   PinIO<true> io{nullptr, nullptr, xy, pin_slot, nullptr, nullptr, pin_grad};
-  hipLaunchKernelGGL(k_wa<true>, dim3((num_nets + 255) / 256), dim3(256), 0, s, num_nets,
-                     net_ptr, pin_cell, pin_dx, pin_dy, io, 1.0f / gamma, wa_out, hp_out);
-  return hipGetLastError();
+  const int nblk = (num_nets + 255) / 256;
+  const dim3 grid(nblk);
+  hipLaunchKernelGGL((k_wa<true, 0>), grid, dim3(256), 0, s, num_nets, net_ptr, pin_cell,
+                     pin_dx, pin_dy, io, 1.0f / gamma, nullptr, nullptr, wa_part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (tp) plan_mark(*tp, "k_wa_slots_small", s);
+  hipLaunchKernelGGL((k_wa<true, 1>), grid, dim3(256), 0, s, num_nets, net_ptr, pin_cell,
+                     pin_dx, pin_dy, io, 1.0f / gamma, nullptr, nullptr,
+                     wa_part + 2 * (size_t)nblk);
+  e = hipGetLastError();
+  if (tp) plan_mark(*tp, "k_wa_slots_big", s);
+  return e;
 }
 
-// out4[3] = tau = scal[0] / scal[1] (0 when there is no movable area).
-__global__ void k_overflow_finalize(double* __restrict__ out4, const double* __restrict__ scal) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) out4[3] = scal[1] > 0.0 ? scal[0] / scal[1] : 0.0;
+// Sum of v over a block, in a fixed order; valid in thread 0.
+__device__ __forceinline__ double block_total(double v) {
+  __shared__ double red[16];
+  v = wave_sum(v);
+  const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int k = 0; k < (int)(blockDim.x / kWave); ++k) t += red[k];
+  __syncthreads();
+  return t;
 }
 
-hipError_t launch_overflow_finalize(double* out4, const double* scal, hipStream_t s) {
-  hipLaunchKernelGGL(k_overflow_finalize, dim3(1), dim3(64), 0, s, out4, scal);
+// The evaluation's scalars from per-block partials, summed in double in a
+// fixed order (so repeated evaluations give identical scalars):
+//   energy N   = sum en[0..n_en)
+//   tau        = sum tau[2i] / sum tau[2i+1]   (overflow / movable area)
+//   W~, HPWL   = sums of the two wirelength kernels' per-block partials,
+//                wa = [W_small, H_small, W_big, H_big], n_wa each.
+__global__ void __launch_bounds__(1024)
+    k_eval_finalize(const double* __restrict__ en, int n_en, const double* __restrict__ tau,
+                    int n_tau, const double* __restrict__ wa, int n_wa,
+                    double* __restrict__ o_en, double* __restrict__ o_wa,
+                    double* __restrict__ o_hp, double* __restrict__ o_tau) {
+  const int t = threadIdx.x;
+  double se = 0.0, so = 0.0, sm = 0.0, sw = 0.0, sh = 0.0;
+  if (en)
+    for (int i = t; i < n_en; i += blockDim.x) se += en[i];
+  if (tau)
+    for (int i = t; i < n_tau; i += blockDim.x) {
+      so += tau[2 * i];
+      sm += tau[2 * i + 1];
+    }
+  if (wa)
+    for (int i = t; i < n_wa; i += blockDim.x) {
+      sw += wa[i] + wa[2 * n_wa + i];
+      sh += wa[n_wa + i] + wa[3 * n_wa + i];
+    }
+  se = block_total(se);
+  so = block_total(so);
+  sm = block_total(sm);
+  sw = block_total(sw);
+  sh = block_total(sh);
+  if (t == 0) {
+    if (o_en) *o_en = se;
+    if (o_tau) *o_tau = sm > 0.0 ? so / sm : 0.0;
+    if (wa && o_wa) *o_wa = sw;
+    if (wa && o_hp) *o_hp = sh;
+  }
+}
+
+hipError_t launch_eval_finalize(const double* en, int n_en, const double* tau, int n_tau,
+                                const double* wa, int n_wa, double* o_en, double* o_wa,
+                                double* o_hp, double* o_tau, hipStream_t s) {
+  hipLaunchKernelGGL(k_eval_finalize, dim3(1), dim3(1024), 0, s, en, n_en, tau, n_tau, wa,
+                     n_wa, o_en, o_wa, o_hp, o_tau);
   return hipGetLastError();
 }
 

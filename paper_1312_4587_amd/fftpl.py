@@ -216,10 +216,11 @@ def wa_grad(net_ptr, pin_cell, pin_dx, pin_dy, x, y, gamma, accumulate, gx, gy,
         _stream(stream)), "fftpl_wa_grad")
 
 
-def problem_work_bytes(n: int, num_cells: int, num_pins: int) -> int:
+def problem_work_bytes(n: int, num_cells: int, num_nets: int, num_pins: int) -> int:
     b = ctypes.c_uint64()
-    _check(_lib.load().fftpl_problem_work_bytes(int(n), int(num_cells), int(num_pins),
-                                                ctypes.byref(b)), "fftpl_problem_work_bytes")
+    _check(_lib.load().fftpl_problem_work_bytes(int(n), int(num_cells), int(num_nets),
+                                                int(num_pins), ctypes.byref(b)),
+           "fftpl_problem_work_bytes")
     return int(b.value)
 
 
@@ -257,7 +258,7 @@ class Problem:
             cell_ptr = torch.empty(m + 1, dtype=torch.int32, device="cuda")
             pin_slot = torch.empty(max(P, 1), dtype=torch.int32, device="cuda")
             scratch = netlist_index(m, pin_cell, cell_ptr, pin_slot, stream=stream)
-            work_bytes = problem_work_bytes(grid.n, m, P)
+            work_bytes = problem_work_bytes(grid.n, m, E, P)
             work = torch.empty(max(work_bytes, 1), dtype=torch.uint8, device="cuda")
             torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
             del scratch
