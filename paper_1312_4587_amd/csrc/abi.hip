@@ -370,7 +370,7 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
   // W~ and HPWL into out4 directly)
   if (e == hipSuccess)
     e = launch_eval_finalize(p.partials, p.n / 2, p.partials + p.n / 2, p.n / 2,
-                             fast ? L.wa_part : nullptr, L.nwa, &out4[0], &out4[1], &out4[2],
+                             fast ? L.wa_part : nullptr, prob->num_nets, &out4[0], &out4[1], &out4[2],
                              &out4[3], s);
   plan_mark(p, "k_eval_finalize", s);
   return dev_status(e);

@@ -221,9 +221,18 @@ hipError_t launch_wa(int num_nets, const int32_t* net_ptr, const int32_t* pin_ce
                      const float* pin_dx, const float* pin_dy, const float* x,
                      const float* y, float gamma, float* gx, float* gy,
                      double* wa_out, double* hp_out, hipStream_t s);
+// wa: the wirelength partials of fftpl_eval's atomic-free path for num_nets
+// nets (or null: W~ and HPWL are left as they are).
 hipError_t launch_eval_finalize(const double* en, int n_en, const double* tau, int n_tau,
-                                const double* wa, int n_wa, double* o_en, double* o_wa,
+                                const double* wa, int num_nets, double* o_en, double* o_wa,
                                 double* o_hp, double* o_tau, hipStream_t s);
+
+// Blocks of the persistent big-net wirelength kernel (4 waves each; 512
+// blocks keep every SIMD busy at its 2-wave occupancy).
+inline int wa_big_grid(int num_nets) {
+  const int nb = (num_nets + 255) / 256;
+  return nb < 512 ? (nb > 0 ? nb : 1) : 512;
+}
 
 // ---- banded density scatter (atomic-free in global memory) ----------------
 // Cells are counting-sorted into bands of `rows` bin rows (a cell is listed in

@@ -123,6 +123,18 @@ __device__ __forceinline__ void stage_twiddles(float2* tw, const float2* __restr
   wave_lds_sync();
 }
 
+// Same for the quarter-sample table cs and the frequency table wf, which the
+// pair loops read once per pair.
+template <int N>
+__device__ __forceinline__ void stage_tables(float2* cs, const float2* __restrict__ cs_g,
+                                             float* wf, const float* __restrict__ wf_g,
+                                             int lane) {
+  for (int t = lane; t <= N / 2; t += kWave) cs[t] = cs_g[t];
+  if (wf)
+    for (int t = lane; t < N; t += kWave) wf[t] = wf_g[t];
+  wave_lds_sync();
+}
+
 // Forward post-processing for the pair (k, n-k) of a two-real-sequence FFT
 // V = FFT(v1 + i v2): returns the DCT-II outputs X1, X2 at k and n-k.
 // cs = (cos, sin)(pi k / 2n).
@@ -161,13 +173,15 @@ template <int N>
 __global__ void __launch_bounds__(64)
     k_rows_dct2(const float* __restrict__ rho, float* __restrict__ bT,
                 double* __restrict__ rowsum, const float2* __restrict__ tw_g,
-                const float2* __restrict__ cs, const float* __restrict__ base,
+                const float2* __restrict__ cs_g, const float* __restrict__ base,
                 const float* __restrict__ cap, float rho_t, double* __restrict__ tau_part) {
   __shared__ float2 buf[N];
   __shared__ float2 tw[N];
+  __shared__ float2 cs[N / 2 + 1];
   constexpr int PER = (N + kWave - 1) / kWave;
   const int lane = threadIdx.x;
   stage_twiddles<N>(tw, tw_g, lane);
+  stage_tables<N>(cs, cs_g, nullptr, nullptr, lane);
   const int pair = xcd_block(blockIdx.x, gridDim.x);
   const int r1 = 2 * pair, r2 = r1 + 1;
   float a1[PER], a2[PER];
@@ -237,14 +251,17 @@ template <int N>
 __global__ void __launch_bounds__(64)
     k_cols_solve(const float* __restrict__ bT, const double* __restrict__ rowsum,
                  float* __restrict__ P, float* __restrict__ Q,
-                 const float2* __restrict__ tw_g, const float2* __restrict__ cs,
-                 const float* __restrict__ wf) {
+                 const float2* __restrict__ tw_g, const float2* __restrict__ cs_g,
+                 const float* __restrict__ wf_g) {
   __shared__ float2 buf0[N];
   __shared__ float2 buf1[N];
   __shared__ float2 tw[N];
+  __shared__ float2 cs[N / 2 + 1];
+  __shared__ float wf[N];
   constexpr int PER = (N + kWave - 1) / kWave;
   const int lane = threadIdx.x;
   stage_twiddles<N>(tw, tw_g, lane);
+  stage_tables<N>(cs, cs_g, wf, wf_g, lane);
   const int q = xcd_block(blockIdx.x, gridDim.x);
   const int u1 = 2 * q, u2 = u1 + 1;
   double mean0 = 0.0;
@@ -315,20 +332,31 @@ __global__ void __launch_bounds__(64)
                    const float* __restrict__ rho, float* __restrict__ psi,
                    float* __restrict__ ex, float* __restrict__ ey,
                    float2* __restrict__ exy, double* __restrict__ energy,
-                   const float2* __restrict__ tw_g, const float2* __restrict__ cs,
-                   const float* __restrict__ wf) {
+                   const float2* __restrict__ tw_g, const float2* __restrict__ cs_g,
+                   const float* __restrict__ wf_g) {
   __shared__ float2 bufa[N];
   __shared__ float2 bufb[N];
   __shared__ float2 bufc[N];
   __shared__ float2 tw[N];
+  __shared__ float2 cs[N / 2 + 1];
+  __shared__ float wf[N];
+  __shared__ float rows[4 * N];
   const int lane = threadIdx.x;
-  stage_twiddles<N>(tw, tw_g, lane);
   const int pr = xcd_block(blockIdx.x, gridDim.x);
   const int r1 = 2 * pr, r2 = r1 + 1;
-  const float* P1 = P + (int64_t)r1 * N;
-  const float* P2 = P + (int64_t)r2 * N;
-  const float* Q1 = Q + (int64_t)r1 * N;
-  const float* Q2 = Q + (int64_t)r2 * N;
+  // rows P[r1], P[r2], Q[r1], Q[r2] staged in LDS with all loads up front
+  for (int t = lane; t < N; t += kWave) {
+    rows[t] = P[(int64_t)r1 * N + t];
+    rows[N + t] = P[(int64_t)r2 * N + t];
+    rows[2 * N + t] = Q[(int64_t)r1 * N + t];
+    rows[3 * N + t] = Q[(int64_t)r2 * N + t];
+  }
+  stage_twiddles<N>(tw, tw_g, lane);
+  stage_tables<N>(cs, cs_g, wf, wf_g, lane);
+  const float* P1 = rows;
+  const float* P2 = rows + N;
+  const float* Q1 = rows + 2 * N;
+  const float* Q2 = rows + 3 * N;
   for (int k = lane; k <= N / 2; k += kWave) {
     const int kp = (N - k) & (N - 1);
     const bool k0 = (k == 0), self = k0 || k == N / 2;
@@ -356,7 +384,11 @@ __global__ void __launch_bounds__(64)
   wave_fft<N, true>(bufb, tw, lane);
   wave_fft<N, true>(bufc, tw, lane);
   double en = 0.0;
-  for (int ix = lane; ix < N; ix += kWave) {
+  constexpr int PERX = (N + kWave - 1) / kWave;
+#pragma unroll
+  for (int t = 0; t < PERX; ++t) {
+    const int ix = lane + kWave * t;
+    if (N % kWave != 0 && ix >= N) continue;
     const int mpos = mk_pos<N>(ix);
     const float2 za = bufa[mpos], zb = bufb[mpos], zc = bufc[mpos];
     const float sg = (ix & 1) ? -1.0f : 1.0f;

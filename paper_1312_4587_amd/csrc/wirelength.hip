@@ -86,7 +86,7 @@ __global__ void __launch_bounds__(256)
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   const int lane = threadIdx.x & (kWave - 1);
   int p0 = 0, p1 = 0;
-  if (e < num_nets) {
+  if (PART == 0 && e < num_nets) {
     p0 = net_ptr[e];
     p1 = net_ptr[e + 1];
   }
@@ -139,12 +139,24 @@ __global__ void __launch_bounds__(256)
     acc_hp = (double)(mx - lx) + (double)(my - ly);
   }
 
-  // Larger nets: the whole wavefront cooperates on each in turn.
-  unsigned long long big = PART == 1 ? __ballot(deg > kSmallDeg) : 0ull;
+  // Larger nets: the whole wavefront cooperates on each in turn.  This part
+  // runs on a persistent grid (every wavefront walks chunks of kWave nets), so
+  // a few slow nets do not hold back the dispatch of thousands of blocks.
+  const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int nwaves = gridDim.x * blockDim.x / kWave;
+  const int nchunks = PART == 1 ? (num_nets + kWave - 1) / kWave : 0;
+  for (int ch = wid; ch < nchunks; ch += nwaves) {
+  const int ec = ch * kWave + lane;
+  int c0 = 0, c1 = 0;
+  if (ec < num_nets) {
+    c0 = net_ptr[ec];
+    c1 = net_ptr[ec + 1];
+  }
+  unsigned long long big = __ballot(c1 - c0 > kSmallDeg);
   while (big) {
     const int src = __ffsll((long long)big) - 1;
     big &= big - 1;
-    const int b0 = __shfl(p0, src, kWave), b1 = __shfl(p1, src, kWave);
+    const int b0 = __shfl(c0, src, kWave), b1 = __shfl(c1, src, kWave);
     if (b1 - b0 <= kWave * kBigRegs) {
       // up to kBigRegs pins per lane held in registers: one pass over memory
       int cj[kBigRegs];
@@ -255,6 +267,7 @@ __global__ void __launch_bounds__(256)
       acc_hp += (double)(mx - lx) + (double)(my - ly);
     }
   }
+  }
   if (part) {
     // per-block partials: part[b] = W~, part[gridDim.x + b] = HPWL
     block_sum_to<false>(acc_wa, &part[blockIdx.x]);
@@ -276,7 +289,7 @@ hipError_t launch_wa(int num_nets, const int32_t* net_ptr, const int32_t* pin_ce
                      pin_dx, pin_dy, io, 1.0f / gamma, wa_out, hp_out, nullptr);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_wa<false, 1>), grid, dim3(256), 0, s, num_nets, net_ptr, pin_cell,
+  hipLaunchKernelGGL((k_wa<false, 1>), dim3(wa_big_grid(num_nets)), dim3(256), 0, s, num_nets, net_ptr, pin_cell,
                      pin_dx, pin_dy, io, 1.0f / gamma, wa_out, hp_out, nullptr);
   return hipGetLastError();
 }
@@ -294,7 +307,7 @@ hipError_t launch_wa_pins(int num_nets, const int32_t* net_ptr, const int32_t* p
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (tp) plan_mark(*tp, "k_wa_slots_small", s);
-  hipLaunchKernelGGL((k_wa<true, 1>), grid, dim3(256), 0, s, num_nets, net_ptr, pin_cell,
+  hipLaunchKernelGGL((k_wa<true, 1>), dim3(wa_big_grid(num_nets)), dim3(256), 0, s, num_nets, net_ptr, pin_cell,
                      pin_dx, pin_dy, io, 1.0f / gamma, nullptr, nullptr,
                      wa_part + 2 * (size_t)nblk);
   e = hipGetLastError();
@@ -321,10 +334,10 @@ __device__ __forceinline__ double block_total(double v) {
 //   energy N   = sum en[0..n_en)
 //   tau        = sum tau[2i] / sum tau[2i+1]   (overflow / movable area)
 //   W~, HPWL   = sums of the two wirelength kernels' per-block partials,
-//                wa = [W_small, H_small, W_big, H_big], n_wa each.
+//                wa = [W_small(n_s), H_small(n_s), W_big(n_b), H_big(n_b)].
 __global__ void __launch_bounds__(1024)
     k_eval_finalize(const double* __restrict__ en, int n_en, const double* __restrict__ tau,
-                    int n_tau, const double* __restrict__ wa, int n_wa,
+                    int n_tau, const double* __restrict__ wa, int n_s, int n_b,
                     double* __restrict__ o_en, double* __restrict__ o_wa,
                     double* __restrict__ o_hp, double* __restrict__ o_tau) {
   const int t = threadIdx.x;
@@ -336,11 +349,16 @@ __global__ void __launch_bounds__(1024)
       so += tau[2 * i];
       sm += tau[2 * i + 1];
     }
-  if (wa)
-    for (int i = t; i < n_wa; i += blockDim.x) {
-      sw += wa[i] + wa[2 * n_wa + i];
-      sh += wa[n_wa + i] + wa[3 * n_wa + i];
+  if (wa) {
+    for (int i = t; i < n_s; i += blockDim.x) {
+      sw += wa[i];
+      sh += wa[n_s + i];
     }
+    for (int i = t; i < n_b; i += blockDim.x) {
+      sw += wa[2 * n_s + i];
+      sh += wa[2 * n_s + n_b + i];
+    }
+  }
   se = block_total(se);
   so = block_total(so);
   sm = block_total(sm);
@@ -355,10 +373,11 @@ __global__ void __launch_bounds__(1024)
 }
 
 hipError_t launch_eval_finalize(const double* en, int n_en, const double* tau, int n_tau,
-                                const double* wa, int n_wa, double* o_en, double* o_wa,
+                                const double* wa, int num_nets, double* o_en, double* o_wa,
                                 double* o_hp, double* o_tau, hipStream_t s) {
+  const int n_s = (num_nets + 255) / 256, n_b = wa ? wa_big_grid(num_nets) : 0;
   hipLaunchKernelGGL(k_eval_finalize, dim3(1), dim3(1024), 0, s, en, n_en, tau, n_tau, wa,
-                     n_wa, o_en, o_wa, o_hp, o_tau);
+                     n_s, n_b, o_en, o_wa, o_hp, o_tau);
   return hipGetLastError();
 }
 
