@@ -68,7 +68,8 @@ def kernel_bytes(inst, nent):
         "k_wa_slots_small": 12 * p_small + 8 * p_small + 4 * (E + 1) + 8 * m,
         "k_wa_slots_big": 12 * p_big + 8 * p_big + 4 * (E + 1),
         "k_band_count": 16 * m,
-        "k_band_place": 16 * m + 8 * m + 16 * nent,
+        "k_interleave": 8 * m + 8 * m,
+        "k_band_place": 16 * m + 16 * nent,
         "k_band_accum": 16 * nent + 4 * n2 + 4 * n2,
         "k_rows_dct2": 4 * n2 + 4 * n2 + 8 * n2,        # rho, base+cap in; bT out
         "k_cols_solve": 4 * n2 + 8 * n2,                # bT in; P, Q out

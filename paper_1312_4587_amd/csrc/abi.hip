@@ -80,6 +80,9 @@ void free_plan(Plan& p) {
   hipFree(p.partials);
   for (int i = 0; i < Plan::kMaxEvents; ++i)
     if (p.ev[i]) hipEventDestroy(p.ev[i]);
+  if (p.fork) hipEventDestroy(p.fork);
+  if (p.join) hipEventDestroy(p.join);
+  if (p.side) hipStreamDestroy(p.side);
   gemm_plan_free(p);
 }
 
@@ -128,6 +131,9 @@ int fftpl_plan_create(fftpl_plan** out, int32_t n, int32_t dct_mode, void* strea
             hipMalloc(&p.exy, sizeof(float) * 2 * nn) == hipSuccess &&
             hipMalloc(&p.rowsum, sizeof(double) * n) == hipSuccess &&
             hipMalloc(&p.partials, sizeof(double) * (3 * (size_t)n / 2 + 2)) == hipSuccess;
+  ok = ok && hipStreamCreateWithFlags(&p.side, hipStreamNonBlocking) == hipSuccess &&
+       hipEventCreateWithFlags(&p.fork, hipEventDisableTiming) == hipSuccess &&
+       hipEventCreateWithFlags(&p.join, hipEventDisableTiming) == hipSuccess;
   if (!ok) {
     hipGetLastError();
     free_plan(p);
@@ -316,10 +322,29 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
   hipError_t e = hipSuccess;
   p.nev = 0;
   plan_mark(p, "start", s);
+  // With per-kernel timing on, everything runs on `s` so that consecutive
+  // events bracket single kernels; otherwise the wirelength kernels overlap
+  // the density and the solve on the plan's side stream.
+  const bool overlap = fast && !p.timing;
+  hipStream_t ws = overlap ? p.side : s;
   if (fast) {
-    // 1. zero scalars and band counters; 2. banded density scatter
+    // 1. zero scalars and band counters
     e = launch_init_eval(out4, L.counters, L.nb + 1, s);
     plan_mark(p, "k_init_eval", s);
+    // wirelength branch: interleave positions, per-pin WA gradients into
+    // cell-major slots
+    if (e == hipSuccess && overlap) {
+      e = hipEventRecord(p.fork, s);
+      if (e == hipSuccess) e = hipStreamWaitEvent(ws, p.fork, 0);
+    }
+    if (e == hipSuccess) e = launch_interleave(m, x, y, L.xy, ws);
+    plan_mark(p, "k_interleave", ws);
+    if (e == hipSuccess)
+      e = launch_wa_pins(prob->num_nets, prob->net_ptr, prob->pin_cell, prob->pin_dx,
+                         prob->pin_dy, L.xy, prob->pin_slot, gamma, L.pin_grad, L.wa_part,
+                         ws, &p);
+    if (e == hipSuccess && overlap) e = hipEventRecord(p.join, ws);
+    // 2. banded density scatter
     if (e == hipSuccess)
       e = launch_band_scatter(g, L, x, y, prob->w, prob->h, prob->base, p.rho, s, &p);
   } else {
@@ -345,12 +370,9 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
     e = p.mode == FFTPL_DCT_FFT ? spectral_fft(p, a, s) : spectral_gemm(p, a, s);
   }
   if (fast) {
-    // 4. per-pin WA gradients into cell-major slots, 5. per cell: density
-    // gradient plus the sum of its pins' slots
-    if (e == hipSuccess)
-      e = launch_wa_pins(prob->num_nets, prob->net_ptr, prob->pin_cell, prob->pin_dx,
-                         prob->pin_dy, L.xy, prob->pin_slot, gamma, L.pin_grad, L.wa_part,
-                         s, &p);
+    // join the wirelength branch; 5. per cell: density gradient plus the sum
+    // of its pins' slots
+    if (e == hipSuccess && overlap) e = hipStreamWaitEvent(s, p.join, 0);
     if (e == hipSuccess)
       e = launch_gather_pins(g, m, x, y, prob->w, prob->h, p.exy, p.psi, grad_mode, lambda,
                              prob->cell_ptr, L.pin_grad, gx, gy, s);

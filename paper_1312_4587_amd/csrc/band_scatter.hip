@@ -135,7 +135,6 @@ __global__ void __launch_bounds__(kBandThreads)
     for (int j = 0; j < B; ++j) {
       const int i = base + j * NT + t;
       if (i >= L.m) continue;
-      L.xy[i] = make_float2(c.x[j], c.y[j]);
       const Span sx = cell_span(c.x[j], c.w[j], g.xl, g.inv_bw, g.n);
       const Span sy = cell_span(c.y[j], c.h[j], g.yl, g.inv_bh, g.n);
       if (sx.i0 > sx.i1 || sy.i0 > sy.i1) continue;
@@ -199,6 +198,23 @@ __global__ void __launch_bounds__(kBandThreads)
   __syncthreads();
   const size_t o = (size_t)r0 * n;
   for (int k = t; k < cells; k += NT) rho[o + k] = (base ? base[o + k] : 0.0f) + acc[k];
+}
+
+// xy[i] = (x[i], y[i]): the wirelength pass then gathers one float2 per pin.
+__global__ void __launch_bounds__(256)
+    k_interleave(int m, const float* __restrict__ x, const float* __restrict__ y,
+                 float2* __restrict__ xy) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x)
+    xy[i] = make_float2(x[i], y[i]);
+}
+
+hipError_t launch_interleave(int m, const float* x, const float* y, float2* xy,
+                             hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  int blocks = (m + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_interleave, dim3(blocks), dim3(256), 0, s, m, x, y, xy);
+  return hipGetLastError();
 }
 
 hipError_t launch_band_scatter(const GridF& g, const BandLayout& L, const float* x,

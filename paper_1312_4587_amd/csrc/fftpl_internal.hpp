@@ -185,6 +185,11 @@ struct Plan {
   // Optional per-kernel timing: an event is recorded on the launch stream
   // after every kernel of an evaluation (the first one before it).
   static constexpr int kMaxEvents = 24;
+  // The wirelength kernels do not depend on the density or the solve: they
+  // run on a second stream forked from and joined back into the caller's
+  // stream with events (default priority; created with the plan).
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
   bool timing = false;
   int nev = 0;
   hipEvent_t ev[kMaxEvents] = {};
@@ -266,6 +271,8 @@ hipError_t launch_band_scatter(const GridF& g, const BandLayout& L, const float*
                                const float* base, float* rho, hipStream_t s,
                                Plan* tp = nullptr);
 hipError_t launch_init_eval(double* out4, int32_t* counters, int ncount, hipStream_t s);
+hipError_t launch_interleave(int m, const float* x, const float* y, float2* xy,
+                             hipStream_t s);
 hipError_t launch_wa_pins(int num_nets, const int32_t* net_ptr, const int32_t* pin_cell,
                           const float* pin_dx, const float* pin_dy, const float2* xy,
                           const int32_t* pin_slot, float gamma, float2* pin_grad,
