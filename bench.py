@@ -34,6 +34,9 @@ def parse():
                     help="spectral variants to time besides --dct")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-evals", type=int, default=2)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 256 MiB device copy (reference for the "
+                         "FETCH_SIZE / WRITE_SIZE counters)")
     return ap.parse_args()
 
 
@@ -151,6 +154,13 @@ def main():
         build.build()
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if args.calibrate_copy:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")   # 256 MiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     inst = gen.make_config(args.workload)
     prob = fftpl.Problem.from_instance(inst)
     x = torch.as_tensor(inst.x).cuda()

@@ -66,6 +66,20 @@ int validate_cells(int m, const float* x, const float* y, const float* w, const 
   return FFTPL_OK;
 }
 
+// Sizes the per-block partial sums of the solve (see Plan::partials) and
+// returns the number of doubles to allocate.
+size_t plan_partials(Plan& p, int n, int mode) {
+  if (mode == FFTPL_DCT_FFT) {
+    p.n_en = n / 2;
+    p.n_tau = n / 2;
+  } else {
+    p.n_en = 2 * (n / 64) * (n / 64);
+    p.n_tau = n;
+  }
+  p.en_max = p.n_en;
+  return (size_t)p.en_max + 2 * (size_t)p.n_tau + 2;
+}
+
 void free_plan(Plan& p) {
   hipFree(p.fft_tw);
   hipFree(p.dct_cs);
@@ -130,7 +144,7 @@ int fftpl_plan_create(fftpl_plan** out, int32_t n, int32_t dct_mode, void* strea
             hipMalloc(&p.psi, sizeof(float) * nn) == hipSuccess &&
             hipMalloc(&p.exy, sizeof(float) * 2 * nn) == hipSuccess &&
             hipMalloc(&p.rowsum, sizeof(double) * n) == hipSuccess &&
-            hipMalloc(&p.partials, sizeof(double) * (3 * (size_t)n / 2 + 2)) == hipSuccess;
+            hipMalloc(&p.partials, sizeof(double) * plan_partials(p, n, dct_mode)) == hipSuccess;
   ok = ok && hipStreamCreateWithFlags(&p.side, hipStreamNonBlocking) == hipSuccess &&
        hipEventCreateWithFlags(&p.fork, hipEventDisableTiming) == hipSuccess &&
        hipEventCreateWithFlags(&p.join, hipEventDisableTiming) == hipSuccess;
@@ -237,7 +251,7 @@ int fftpl_poisson_solve(fftpl_plan* plan, const fftpl_grid* grid, const float* r
   e = plan->p.mode == FFTPL_DCT_FFT ? spectral_fft(plan->p, a, s)
                                     : spectral_gemm(plan->p, a, s);
   if (e == hipSuccess && energy) {
-    e = launch_eval_finalize(plan->p.partials, plan->p.n / 2, nullptr, 0, nullptr, 0, energy,
+    e = launch_eval_finalize(plan->p.partials, plan->p.n_en, nullptr, 0, nullptr, 0, energy,
                              nullptr, nullptr, nullptr, s);
     plan_mark(plan->p, "k_eval_finalize", s);
   }
@@ -366,7 +380,7 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
     a.base = prob->base;
     a.cap = prob->cap;
     a.rho_t = g.rho_t;
-    a.tau_part = p.partials + p.n / 2;
+    a.tau_part = p.partials + p.en_max;
     e = p.mode == FFTPL_DCT_FFT ? spectral_fft(p, a, s) : spectral_gemm(p, a, s);
   }
   if (fast) {
@@ -391,7 +405,7 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
   // 6. N, W~, HPWL, tau from the per-block partials (the atomic path added
   // W~ and HPWL into out4 directly)
   if (e == hipSuccess)
-    e = launch_eval_finalize(p.partials, p.n / 2, p.partials + p.n / 2, p.n / 2,
+    e = launch_eval_finalize(p.partials, p.n_en, p.partials + p.en_max, p.n_tau,
                              fast ? L.wa_part : nullptr, prob->num_nets, &out4[0], &out4[1], &out4[2],
                              &out4[3], s);
   plan_mark(p, "k_eval_finalize", s);

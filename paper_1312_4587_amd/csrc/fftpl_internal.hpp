@@ -181,7 +181,12 @@ struct Plan {
   void* gemm_ws = nullptr;  // extra GEMM-mode workspace
   size_t gemm_ws_bytes = 0;
   double* rowsum = nullptr; // n doubles
-  double* partials = nullptr;  // n/2 energy partials, then n overflow partials
+  // Per-block partial sums of the solve: en_max energy slots, then overflow
+  // pairs.  FFT: n/2 energy partials and n/2 pairs (one per row pair);
+  // GEMM: 2 (n/64)^2 energy partials (one per output tile) and n pairs.
+  double* partials = nullptr;
+  int en_max = 0;
+  int n_en = 0, n_tau = 0;
   // Optional per-kernel timing: an event is recorded on the launch stream
   // after every kernel of an evaluation (the first one before it).
   static constexpr int kMaxEvents = 24;

@@ -1,10 +1,523 @@
-// Spectral solve as dense cosine/sine-matrix GEMMs on MFMA (placeholder until
-// the GEMM kernels land: plans in the GEMM modes report unsupported).
+// Spectral solve (Eqs. (9)-(12)) as dense cosine/sine-matrix products on the
+// matrix cores: the same transforms as the FFT path, written as five GEMMs.
+// With K[u][i] = cos(w_u (i+1/2)), S[u][i] = sin(w_u (i+1/2)), w_u = pi u / n,
+// Sw = diag(w) S and R = rho - mean(rho) (mean in double, so the large DC
+// never enters the float32 sums):
+//   W  = R K^T                         (along x)
+//   G  = scale(K W)                    (along y; c_u c_v / n^2 / (w_u^2+w_v^2),
+//                                       zero at (0,0): the DC is removed)
+//   [U | V]     = G [K | Sw]           (inverse along x: cos for psi and Ey,
+//                                       frequency-weighted sine for Ex)
+//   [psi ; Ey]  = [K^T ; Sw^T] U       (inverse along y)
+//   Ex          = K^T V
+// 7 n^3 multiply-adds in all.  Two precisions:
+//   FP32:   v_mfma_f32_16x16x4_f32 on float32 operands;
+//   BF16X3: every float32 operand X is split into bf16 hi = bf16(X) and
+//           lo = bf16(X - hi); each product is Ah Bh + Ah Bl + Al Bh on
+//           v_mfma_f32_16x16x32_bf16 with float32 accumulation.
+// Block tile 64 x 64, four waves of 32 x 32 (2 x 2 MFMA tiles of 16 x 16),
+// K step 32 staged in LDS.  The constant matrices are built once per plan in
+// double and rounded (and split) once.
+#include <math.h>
+#include <string.h>
+
+#include <vector>
+
 #include "fftpl_internal.hpp"
 
 namespace fftpl {
 
-int gemm_plan_init(Plan&, hipStream_t) { return FFTPL_E_UNSUPPORTED; }
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+constexpr int TM = 64, TN = 64, TK = 32;
+
+enum EpiMode { EPI_F32 = 0, EPI_SPLIT = 1, EPI_SPLIT_T = 2, EPI_PSI_EY = 3, EPI_EX = 4 };
+
+struct GemmArgs {
+  const void* a_hi;   // A [M][K] row-major (float32, or bf16 hi)
+  const void* a_lo;   // bf16 lo of A
+  int lda;
+  const void* b_hi;   // float32: B [K][N] row-major; bf16: B^T [N][K] row-major
+  const void* b_lo;
+  int ldb;
+  int M, N, K;
+};
+
+struct Epi {
+  int mode = EPI_F32;
+  int spectral = 0;   // scale element (row v, col u) by c_u c_v / (n^2 (w_u^2 + w_v^2))
+  int n = 0;
+  const float* wf = nullptr;
+  float* out = nullptr;
+  int ldo = 0;
+  __bf16* hi = nullptr;
+  __bf16* lo = nullptr;
+  float* psi = nullptr;
+  float* ex = nullptr;
+  float* ey = nullptr;
+  float* exy = nullptr;
+  const float* rho = nullptr;
+  double* en_part = nullptr;
+};
+
+__device__ __forceinline__ void split_bf16(float v, __bf16& hi, __bf16& lo) {
+  hi = (__bf16)v;
+  lo = (__bf16)(v - (float)hi);
+}
+
+template <bool BF16>
+__global__ void __launch_bounds__(256) k_gemm(GemmArgs g, Epi ep) {
+  const int tiles_n = g.N / TN;
+  const int tile = xcd_block(blockIdx.x, gridDim.x);
+  const int m0 = (tile / tiles_n) * TM, n0 = (tile % tiles_n) * TN;
+  const int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
+  const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+  const int l16 = lane & 15, lg = lane >> 4;
+  f4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+
+  if constexpr (!BF16) {
+    __shared__ float As[TK][TM + 4];   // A^T tile: As[k][m]
+    __shared__ float Bs[TK][TN + 4];   // B tile:   Bs[k][n]
+    const float* A = static_cast<const float*>(g.a_hi);
+    const float* B = static_cast<const float*>(g.b_hi);
+    const int ar = t >> 2, ak = (t & 3) * 8;     // A: row, first k of 8
+    const int bk = t >> 3, bn = (t & 7) * 8;     // B: k, first n of 8
+    for (int k0 = 0; k0 < g.K; k0 += TK) {
+      const float4* sa = reinterpret_cast<const float4*>(A + (size_t)(m0 + ar) * g.lda + k0 + ak);
+      const float4* sb = reinterpret_cast<const float4*>(B + (size_t)(k0 + bk) * g.ldb + n0 + bn);
+      const float4 a0 = sa[0], a1 = sa[1], b0 = sb[0], b1 = sb[1];
+      As[ak + 0][ar] = a0.x;
+      As[ak + 1][ar] = a0.y;
+      As[ak + 2][ar] = a0.z;
+      As[ak + 3][ar] = a0.w;
+      As[ak + 4][ar] = a1.x;
+      As[ak + 5][ar] = a1.y;
+      As[ak + 6][ar] = a1.z;
+      As[ak + 7][ar] = a1.w;
+      *reinterpret_cast<float4*>(&Bs[bk][bn]) = b0;
+      *reinterpret_cast<float4*>(&Bs[bk][bn + 4]) = b1;
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < TK; kk += 4) {
+        const int kq = kk + lg;
+        const float x0 = As[kq][wm + l16], x1 = As[kq][wm + 16 + l16];
+        const float y0 = Bs[kq][wn + l16], y1 = Bs[kq][wn + 16 + l16];
+        acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(x0, y0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(x0, y1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(x1, y0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(x1, y1, acc[1][1], 0, 0, 0);
+      }
+      __syncthreads();
+    }
+  } else {
+    // tiles keep 8 consecutive k of one row (A) or one column (B^T) together,
+    // which is what one lane feeds to the 16x16x32 bf16 MFMA
+    __shared__ bf8 Ah[TM][TK / 8], Al[TM][TK / 8];
+    __shared__ bf8 Bh[TN][TK / 8], Bl[TN][TK / 8];
+    const __bf16* gah = static_cast<const __bf16*>(g.a_hi);
+    const __bf16* gal = static_cast<const __bf16*>(g.a_lo);
+    const __bf16* gbh = static_cast<const __bf16*>(g.b_hi);
+    const __bf16* gbl = static_cast<const __bf16*>(g.b_lo);
+    const int r = t >> 2, kc = t & 3;
+    for (int k0 = 0; k0 < g.K; k0 += TK) {
+      const size_t oa = (size_t)(m0 + r) * g.lda + k0 + kc * 8;
+      const size_t ob = (size_t)(n0 + r) * g.ldb + k0 + kc * 8;
+      Ah[r][kc] = *reinterpret_cast<const bf8*>(gah + oa);
+      Al[r][kc] = *reinterpret_cast<const bf8*>(gal + oa);
+      Bh[r][kc] = *reinterpret_cast<const bf8*>(gbh + ob);
+      Bl[r][kc] = *reinterpret_cast<const bf8*>(gbl + ob);
+      __syncthreads();
+      const bf8 xh0 = Ah[wm + l16][lg], xl0 = Al[wm + l16][lg];
+      const bf8 xh1 = Ah[wm + 16 + l16][lg], xl1 = Al[wm + 16 + l16][lg];
+      const bf8 yh0 = Bh[wn + l16][lg], yl0 = Bl[wn + l16][lg];
+      const bf8 yh1 = Bh[wn + 16 + l16][lg], yl1 = Bl[wn + 16 + l16][lg];
+#define FFTPL_MFMA3(ACC, XH, XL, YH, YL)                                      \
+  ACC = __builtin_amdgcn_mfma_f32_16x16x32_bf16(XH, YH, ACC, 0, 0, 0);        \
+  ACC = __builtin_amdgcn_mfma_f32_16x16x32_bf16(XH, YL, ACC, 0, 0, 0);        \
+  ACC = __builtin_amdgcn_mfma_f32_16x16x32_bf16(XL, YH, ACC, 0, 0, 0);
+      FFTPL_MFMA3(acc[0][0], xh0, xl0, yh0, yl0)
+      FFTPL_MFMA3(acc[0][1], xh0, xl0, yh1, yl1)
+      FFTPL_MFMA3(acc[1][0], xh1, xl1, yh0, yl0)
+      FFTPL_MFMA3(acc[1][1], xh1, xl1, yh1, yl1)
+#undef FFTPL_MFMA3
+      __syncthreads();
+    }
+  }
+
+  // Epilogue.  Lane l of a 16x16 tile holds column l%16, rows 4*(l/16)+r.
+  const int n = ep.n;
+  const float inv_n2 = 1.0f / ((float)n * (float)n);
+  double en = 0.0;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = n0 + wn + 16 * j + l16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm + 16 * i + 4 * lg + r;
+        float v = acc[i][j][r];
+        if (ep.spectral) {
+          const float wu = ep.wf[col], wv = ep.wf[row];
+          const float cu = col ? 2.0f : 1.0f, cv = row ? 2.0f : 1.0f;
+          v = (row == 0 && col == 0) ? 0.0f : v * (cu * cv * inv_n2) / (wu * wu + wv * wv);
+        }
+        if (ep.mode == EPI_F32) {
+          ep.out[(size_t)row * ep.ldo + col] = v;
+        } else if (ep.mode == EPI_SPLIT || ep.mode == EPI_SPLIT_T) {
+          __bf16 h, l;
+          split_bf16(v, h, l);
+          const size_t o = ep.mode == EPI_SPLIT ? (size_t)row * ep.ldo + col
+                                                : (size_t)col * ep.ldo + row;
+          ep.hi[o] = h;
+          ep.lo[o] = l;
+        } else if (ep.mode == EPI_PSI_EY) {
+          if (row < n) {
+            const size_t o = (size_t)row * n + col;
+            if (ep.psi) ep.psi[o] = v;
+            if (ep.rho) en += (double)ep.rho[o] * v;
+          } else {
+            const size_t o = (size_t)(row - n) * n + col;
+            if (ep.ey) ep.ey[o] = v;
+            if (ep.exy) ep.exy[2 * o + 1] = v;
+          }
+        } else {   // EPI_EX
+          const size_t o = (size_t)row * n + col;
+          if (ep.ex) ep.ex[o] = v;
+          if (ep.exy) ep.exy[2 * o] = v;
+        }
+      }
+    }
+  }
+  if (ep.mode == EPI_PSI_EY && ep.en_part) block_sum_to<false>(en, &ep.en_part[tile]);
+}
+
+// Row sums of rho in double, and the per-row overflow pairs (overflow,
+// movable area) against base and cap (cap or rho_t - min(rho_t, base)).
+__global__ void __launch_bounds__(256)
+    k_gemm_rowsum(const float* __restrict__ rho, int n, double* __restrict__ rowsum,
+                  const float* __restrict__ base, const float* __restrict__ cap, float rho_t,
+                  double* __restrict__ tau_part) {
+  const int row = blockIdx.x;
+  double s = 0.0, ovf = 0.0, mov = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const size_t o = (size_t)row * n + i;
+    const float v = rho[o];
+    s += v;
+    if (tau_part) {
+      const float bb = base ? base[o] : 0.0f;
+      const float cc = cap ? cap[o] : fmaxf(0.0f, rho_t - fminf(rho_t, bb));
+      const float mv = v - bb;
+      ovf += fmaxf(0.0f, mv - cc);
+      mov += mv;
+    }
+  }
+  block_sum_to<false>(s, &rowsum[row]);
+  if (tau_part) {
+    block_sum_to<false>(ovf, &tau_part[2 * row]);
+    block_sum_to<false>(mov, &tau_part[2 * row + 1]);
+  }
+}
+
+// R = rho - mean(rho), mean from the double row sums; float32 or bf16 hi/lo.
+template <bool BF16>
+__global__ void __launch_bounds__(256)
+    k_gemm_prep(const float* __restrict__ rho, int n, const double* __restrict__ rowsum,
+                float* __restrict__ out, __bf16* __restrict__ hi, __bf16* __restrict__ lo) {
+  __shared__ double red[4];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) s += rowsum[i];
+  s = wave_sum(s);
+  if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = s;
+  __syncthreads();
+  const float mean = (float)((red[0] + red[1] + red[2] + red[3]) / ((double)n * n));
+  const size_t total = (size_t)n * n;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const float v = rho[i] - mean;
+    if (BF16) {
+      __bf16 h, l;
+      split_bf16(v, h, l);
+      hi[i] = h;
+      lo[i] = l;
+    } else {
+      out[i] = v;
+    }
+  }
+}
+
+// ---- host-side tables ------------------------------------------------------
+
+uint16_t f32_to_bf16_rne(float f) {
+  uint32_t u;
+  memcpy(&u, &f, 4);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+float bf16_to_f32(uint16_t h) {
+  const uint32_t u = (uint32_t)h << 16;
+  float f;
+  memcpy(&f, &u, 4);
+  return f;
+}
+
+// Region offsets (in bytes) inside the plan's table and workspace blocks.
+struct GemmLayout {
+  size_t nn;
+  // float32 tables: K [n][n], KSw [n][2n], KTSwT [2n][n]
+  size_t t_k, t_ksw, t_ktswt;
+  // bf16 tables (hi, lo): K [n][n], KSwT [2n][n], KTSwT [2n][n]
+  size_t b_kh, b_kl, b_kswth, b_kswtl, b_ktswth, b_ktswtl;
+  size_t tables_bytes;
+  // workspace float32: R [n][n], W [n][n], G [n][n], UV [n][2n]
+  size_t w_r, w_w, w_g, w_uv;
+  // workspace bf16 (hi, lo): R, W^T, G [n][n], UV^T [2n][n]
+  size_t v_rh, v_rl, v_wth, v_wtl, v_gh, v_gl, v_uvth, v_uvtl;
+  size_t ws_bytes;
+};
+
+GemmLayout gemm_layout(int n) {
+  GemmLayout L;
+  const size_t nn = (size_t)n * n;
+  L.nn = nn;
+  L.t_k = 0;
+  L.t_ksw = L.t_k + 4 * nn;
+  L.t_ktswt = L.t_ksw + 8 * nn;
+  const size_t f32_end = L.t_ktswt + 8 * nn;
+  L.b_kh = 0;
+  L.b_kl = L.b_kh + 2 * nn;
+  L.b_kswth = L.b_kl + 2 * nn;
+  L.b_kswtl = L.b_kswth + 4 * nn;
+  L.b_ktswth = L.b_kswtl + 4 * nn;
+  L.b_ktswtl = L.b_ktswth + 4 * nn;
+  const size_t bf_end = L.b_ktswtl + 4 * nn;
+  L.tables_bytes = f32_end > bf_end ? f32_end : bf_end;
+  L.w_r = 0;
+  L.w_w = 4 * nn;
+  L.w_g = 8 * nn;
+  L.w_uv = 12 * nn;
+  const size_t wf_end = 20 * nn;
+  L.v_rh = 0;
+  L.v_rl = 2 * nn;
+  L.v_wth = 4 * nn;
+  L.v_wtl = 6 * nn;
+  L.v_gh = 8 * nn;
+  L.v_gl = 10 * nn;
+  L.v_uvth = 12 * nn;
+  L.v_uvtl = 16 * nn;
+  const size_t wb_end = 20 * nn;
+  L.ws_bytes = wf_end > wb_end ? wf_end : wb_end;
+  return L;
+}
+
+template <bool BF16>
+hipError_t launch_gemm(const GemmArgs& g, const Epi& ep, hipStream_t s) {
+  const int blocks = (g.M / TM) * (g.N / TN);
+  hipLaunchKernelGGL(k_gemm<BF16>, dim3(blocks), dim3(256), 0, s, g, ep);
+  return hipGetLastError();
+}
+
+template <bool BF16>
+hipError_t run_gemm_path(Plan& p, const SpectralArgs& a, hipStream_t s) {
+  const int n = p.n;
+  const GemmLayout L = gemm_layout(n);
+  char* tb = static_cast<char*>(p.gemm_tables);
+  char* wb = static_cast<char*>(p.gemm_ws);
+  double* tau_part = a.tau_part;
+  hipLaunchKernelGGL(k_gemm_rowsum, dim3(n), dim3(256), 0, s, a.rho, n, p.rowsum, a.base,
+                     a.cap, a.rho_t, tau_part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  plan_mark(p, "k_gemm_rowsum", s);
+  int pblocks = (int)((L.nn + 1023) / 1024);
+  if (pblocks > 4096) pblocks = 4096;
+  if (BF16) {
+    hipLaunchKernelGGL(k_gemm_prep<true>, dim3(pblocks), dim3(256), 0, s, a.rho, n, p.rowsum,
+                       nullptr, reinterpret_cast<__bf16*>(wb + L.v_rh),
+                       reinterpret_cast<__bf16*>(wb + L.v_rl));
+  } else {
+    hipLaunchKernelGGL(k_gemm_prep<false>, dim3(pblocks), dim3(256), 0, s, a.rho, n,
+                       p.rowsum, reinterpret_cast<float*>(wb + L.w_r), nullptr, nullptr);
+  }
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  plan_mark(p, "k_gemm_prep", s);
+
+  GemmArgs g;
+  Epi ep;
+  ep.n = n;
+  ep.wf = p.wfreq;
+  // 1. W = R K^T            (fp32: B = K^T [ix][u];   bf16: B^T = K [u][ix])
+  g.M = n; g.N = n; g.K = n;
+  if (BF16) {
+    g.a_hi = wb + L.v_rh; g.a_lo = wb + L.v_rl; g.lda = n;
+    g.b_hi = tb + L.b_kh; g.b_lo = tb + L.b_kl; g.ldb = n;
+    ep.mode = EPI_SPLIT_T;   // stored as W^T [u][iy]: the B^T of the next product
+    ep.hi = reinterpret_cast<__bf16*>(wb + L.v_wth);
+    ep.lo = reinterpret_cast<__bf16*>(wb + L.v_wtl);
+    ep.ldo = n;
+  } else {
+    g.a_hi = wb + L.w_r; g.lda = n;
+    g.b_hi = tb + L.t_ktswt; g.ldb = n;   // K^T = first n rows of [K^T ; Sw^T]
+    ep.mode = EPI_F32;
+    ep.out = reinterpret_cast<float*>(wb + L.w_w);
+    ep.ldo = n;
+  }
+  if ((e = launch_gemm<BF16>(g, ep, s)) != hipSuccess) return e;
+  plan_mark(p, "k_gemm_w", s);
+  // 2. G = scale(K W)
+  ep = Epi();
+  ep.n = n;
+  ep.wf = p.wfreq;
+  ep.spectral = 1;
+  if (BF16) {
+    g.a_hi = tb + L.b_kh; g.a_lo = tb + L.b_kl; g.lda = n;
+    g.b_hi = wb + L.v_wth; g.b_lo = wb + L.v_wtl; g.ldb = n;
+    ep.mode = EPI_SPLIT;
+    ep.hi = reinterpret_cast<__bf16*>(wb + L.v_gh);
+    ep.lo = reinterpret_cast<__bf16*>(wb + L.v_gl);
+    ep.ldo = n;
+  } else {
+    g.a_hi = tb + L.t_k; g.lda = n;
+    g.b_hi = wb + L.w_w; g.ldb = n;
+    ep.mode = EPI_F32;
+    ep.out = reinterpret_cast<float*>(wb + L.w_g);
+    ep.ldo = n;
+  }
+  if ((e = launch_gemm<BF16>(g, ep, s)) != hipSuccess) return e;
+  plan_mark(p, "k_gemm_g", s);
+  // 3. [U | V] = G [K | Sw]   (bf16: stored transposed, [2n][n])
+  ep = Epi();
+  ep.n = n;
+  g.M = n; g.N = 2 * n; g.K = n;
+  if (BF16) {
+    g.a_hi = wb + L.v_gh; g.a_lo = wb + L.v_gl; g.lda = n;
+    g.b_hi = tb + L.b_kswth; g.b_lo = tb + L.b_kswtl; g.ldb = n;
+    ep.mode = EPI_SPLIT_T;
+    ep.hi = reinterpret_cast<__bf16*>(wb + L.v_uvth);
+    ep.lo = reinterpret_cast<__bf16*>(wb + L.v_uvtl);
+    ep.ldo = n;
+  } else {
+    g.a_hi = wb + L.w_g; g.lda = n;
+    g.b_hi = tb + L.t_ksw; g.ldb = 2 * n;
+    ep.mode = EPI_F32;
+    ep.out = reinterpret_cast<float*>(wb + L.w_uv);
+    ep.ldo = 2 * n;
+  }
+  if ((e = launch_gemm<BF16>(g, ep, s)) != hipSuccess) return e;
+  plan_mark(p, "k_gemm_uv", s);
+  // 4. [psi ; Ey] = [K^T ; Sw^T] U   (+ energy partials)
+  ep = Epi();
+  ep.n = n;
+  ep.mode = EPI_PSI_EY;
+  ep.psi = a.psi;
+  ep.ey = a.ey;
+  ep.exy = a.exy;
+  ep.rho = a.en_part ? a.rho : nullptr;
+  ep.en_part = a.en_part;
+  g.M = 2 * n; g.N = n; g.K = n;
+  if (BF16) {
+    g.a_hi = tb + L.b_ktswth; g.a_lo = tb + L.b_ktswtl; g.lda = n;
+    g.b_hi = wb + L.v_uvth; g.b_lo = wb + L.v_uvtl; g.ldb = n;
+  } else {
+    g.a_hi = tb + L.t_ktswt; g.lda = n;
+    g.b_hi = wb + L.w_uv; g.ldb = 2 * n;
+  }
+  if ((e = launch_gemm<BF16>(g, ep, s)) != hipSuccess) return e;
+  plan_mark(p, "k_gemm_psi_ey", s);
+  // 5. Ex = K^T V
+  ep = Epi();
+  ep.n = n;
+  ep.mode = EPI_EX;
+  ep.ex = a.ex;
+  ep.exy = a.exy;
+  g.M = n; g.N = n; g.K = n;
+  if (BF16) {
+    g.a_hi = tb + L.b_ktswth; g.a_lo = tb + L.b_ktswtl; g.lda = n;
+    g.b_hi = wb + L.v_uvth + 2 * L.nn; g.b_lo = wb + L.v_uvtl + 2 * L.nn; g.ldb = n;
+  } else {
+    g.a_hi = tb + L.t_ktswt; g.lda = n;
+    g.b_hi = wb + L.w_uv + 4 * (size_t)n; g.ldb = 2 * n;
+  }
+  if ((e = launch_gemm<BF16>(g, ep, s)) != hipSuccess) return e;
+  plan_mark(p, "k_gemm_ex", s);
+  return hipSuccess;
+}
+
+}  // namespace
+
+int gemm_plan_init(Plan& p, hipStream_t s) {
+  const int n = p.n;
+  const GemmLayout L = gemm_layout(n);
+  if (hipMalloc(&p.gemm_tables, L.tables_bytes) != hipSuccess ||
+      hipMalloc(&p.gemm_ws, L.ws_bytes) != hipSuccess) {
+    hipGetLastError();
+    return FFTPL_E_NOMEM;
+  }
+  p.gemm_tables_bytes = L.tables_bytes;
+  p.gemm_ws_bytes = L.ws_bytes;
+  const double pi = 3.14159265358979323846;
+  const size_t nn = L.nn;
+  // K[u][i] and Sw[u][i] = w_u S[u][i], argument reduced as pi*((u(2i+1)) mod 4n)/(2n)
+  std::vector<double> K(nn), Sw(nn);
+  for (int u = 0; u < n; ++u) {
+    const double wu = pi * u / n;
+    for (int i = 0; i < n; ++i) {
+      const long long r = ((long long)u * (2 * i + 1)) % (4LL * n);
+      const double ang = pi * (double)r / (2.0 * n);
+      K[(size_t)u * n + i] = cos(ang);
+      Sw[(size_t)u * n + i] = wu * sin(ang);
+    }
+  }
+  std::vector<char> host(L.tables_bytes);
+  if (p.mode == FFTPL_DCT_GEMM_F32) {
+    float* tk = reinterpret_cast<float*>(host.data() + L.t_k);
+    float* tksw = reinterpret_cast<float*>(host.data() + L.t_ksw);
+    float* tkt = reinterpret_cast<float*>(host.data() + L.t_ktswt);
+    for (int a = 0; a < n; ++a)
+      for (int b = 0; b < n; ++b) {
+        tk[(size_t)a * n + b] = (float)K[(size_t)a * n + b];
+        tksw[(size_t)a * 2 * n + b] = (float)K[(size_t)a * n + b];          // [u][ix]
+        tksw[(size_t)a * 2 * n + n + b] = (float)Sw[(size_t)a * n + b];
+        tkt[(size_t)a * n + b] = (float)K[(size_t)b * n + a];               // [iy][v]
+        tkt[(size_t)(n + a) * n + b] = (float)Sw[(size_t)b * n + a];
+      }
+  } else {
+    uint16_t* kh = reinterpret_cast<uint16_t*>(host.data() + L.b_kh);
+    uint16_t* kl = reinterpret_cast<uint16_t*>(host.data() + L.b_kl);
+    uint16_t* sh = reinterpret_cast<uint16_t*>(host.data() + L.b_kswth);
+    uint16_t* sl = reinterpret_cast<uint16_t*>(host.data() + L.b_kswtl);
+    uint16_t* th = reinterpret_cast<uint16_t*>(host.data() + L.b_ktswth);
+    uint16_t* tl = reinterpret_cast<uint16_t*>(host.data() + L.b_ktswtl);
+    auto split = [](double v, uint16_t& h, uint16_t& l) {
+      const float f = (float)v;
+      h = f32_to_bf16_rne(f);
+      l = f32_to_bf16_rne(f - bf16_to_f32(h));
+    };
+    for (int a = 0; a < n; ++a)
+      for (int b = 0; b < n; ++b) {
+        split(K[(size_t)a * n + b], kh[(size_t)a * n + b], kl[(size_t)a * n + b]);
+        // [K | Sw]^T: row ix' (n + ix for the sine half), column u
+        split(K[(size_t)b * n + a], sh[(size_t)a * n + b], sl[(size_t)a * n + b]);
+        split(Sw[(size_t)b * n + a], sh[(size_t)(n + a) * n + b], sl[(size_t)(n + a) * n + b]);
+        // [K^T ; Sw^T]: row iy (n + iy), column v
+        split(K[(size_t)b * n + a], th[(size_t)a * n + b], tl[(size_t)a * n + b]);
+        split(Sw[(size_t)b * n + a], th[(size_t)(n + a) * n + b], tl[(size_t)(n + a) * n + b]);
+      }
+  }
+  if (hipMemcpyAsync(p.gemm_tables, host.data(), L.tables_bytes, hipMemcpyHostToDevice, s) !=
+          hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return FFTPL_E_DEVICE;
+  return FFTPL_OK;
+}
 
 void gemm_plan_free(Plan& p) {
   hipFree(p.gemm_tables);
@@ -13,8 +526,9 @@ void gemm_plan_free(Plan& p) {
   p.gemm_ws = nullptr;
 }
 
-hipError_t spectral_gemm(Plan&, const SpectralArgs&, hipStream_t) {
-  return hipErrorNotSupported;
+hipError_t spectral_gemm(Plan& p, const SpectralArgs& a, hipStream_t s) {
+  return p.mode == FFTPL_DCT_GEMM_BF16X3 ? run_gemm_path<true>(p, a, s)
+                                         : run_gemm_path<false>(p, a, s);
 }
 
 }  // namespace fftpl

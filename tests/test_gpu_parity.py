@@ -412,3 +412,54 @@ def test_banded_scatter_with_tall_and_outside_cells(F, n):
     got = _run_eval(F, inst, 1.0, "field", fast=True)
     ref = oracle.evaluate(inst, lam=1.0, grad_mode="field")
     _check_eval(inst, got, ref, 1.0, "field")
+
+
+# ---------------------------------------------------------------------------
+# GEMM (matrix-core) variants of the spectral solve
+# ---------------------------------------------------------------------------
+
+# split-bf16 errors are reported, not gated at 1e-5; this bound only catches
+# a broken product (a wrong operand layout gives errors of order 1)
+BF16X3_SANITY = 1e-4
+
+
+@pytest.mark.parametrize("mode", ["gemm_f32", "gemm_bf16x3"])
+@pytest.mark.parametrize("n", [64, 128, 256, 1024])
+def test_poisson_solve_gemm_random_density(F, mode, n):
+    rng = np.random.default_rng(200 + n)
+    rho = (0.9 + 0.4 * rng.standard_normal((n, n))).astype(np.float32)
+    psi, ex, ey, en = _solve(F, n, rho, mode)
+    psi0, ex0, ey0, _ = oracle.poisson_solve(rho.astype(np.float64))
+    e0 = oracle.energy(rho.astype(np.float64), psi0)
+    errs = (rel_l2(psi, psi0), rel_l2(ex, ex0), rel_l2(ey, ey0), abs(en - e0) / abs(e0))
+    say("gemm", mode, n, "errors psi/ex/ey/N", *errs)
+    tol = RTOL if mode == "gemm_f32" else BF16X3_SANITY
+    assert max(errs) < tol
+
+
+@pytest.mark.parametrize("mode", ["gemm_f32", "gemm_bf16x3"])
+def test_poisson_single_mode_gemm(F, mode):
+    n, u, v = 256, 3, 5
+    x = np.arange(n) + 0.5
+    wu, wv = np.pi * u / n, np.pi * v / n
+    rho = np.outer(np.cos(wv * x), np.cos(wu * x))
+    psi, ex, ey, _ = _solve(F, n, rho.astype(np.float32) + np.float32(0.75), mode)
+    d = wu * wu + wv * wv
+    err = rel_l2(psi, rho.astype(np.float32).astype(np.float64) / d)
+    say("gemm single mode", mode, err)
+    assert err < (RTOL if mode == "gemm_f32" else BF16X3_SANITY)
+
+
+@pytest.mark.parametrize("mode", ["gemm_f32", "gemm_bf16x3"])
+@pytest.mark.parametrize("grad", ["field", "exact"])
+def test_eval_small_gemm(F, mode, grad):
+    inst = gen.make_config("small_2k")
+    inst = with_macros(inst, [[30.0, 30.0, 10.0, 8.0]])
+    got = _run_eval(F, inst, 2.0, grad, dct=mode)
+    ref = oracle.evaluate(inst, lam=2.0, grad_mode=grad)
+    if mode == "gemm_f32":
+        _check_eval(inst, got, ref, 2.0, grad)
+    else:
+        e = rel_l2(got["gx"], ref["gx"])
+        say("bf16x3 eval small", grad, "grad err", e)
+        assert e < BF16X3_SANITY
