@@ -34,6 +34,8 @@ def parse():
                     help="spectral variants to time besides --dct")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-evals", type=int, default=2)
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the per-variant error report against the FP64 oracle")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for the "
                          "FETCH_SIZE / WRITE_SIZE counters)")
@@ -82,6 +84,12 @@ def kernel_bytes(inst, nent):
     }
 
 
+def gemm_flops(n):
+    """Multiply-add flops (2 per MAC) of each GEMM of the matrix-core solve."""
+    return {"k_gemm_w": 2 * n ** 3, "k_gemm_g": 2 * n ** 3, "k_gemm_uv": 4 * n ** 3,
+            "k_gemm_psi_ey": 4 * n ** 3, "k_gemm_ex": 2 * n ** 3}
+
+
 def stage_bytes(inst):
     """Compulsory bytes per stage of one evaluation, implementation-free."""
     m, E, P, n2 = inst.num_cells, inst.num_nets, inst.num_pins, inst.n ** 2
@@ -127,14 +135,14 @@ def cpu_baseline(inst, evals):
         cores = 1
     t0 = time.perf_counter()
     for _ in range(evals):
-        oracle.evaluate(inst, lam=1.0, grad_mode="field")
+        ref = oracle.evaluate(inst, lam=1.0, grad_mode="field")
     dt = (time.perf_counter() - t0) / evals
     return {"value": inst.num_cells / dt, "unit": "cell-gradient evals/s",
             "cores": int(cores), "kind": "oracle",
             "sample": (f"{evals} full FP64 oracle evaluation(s) of the same "
                        f"{inst.num_cells}-cell n={inst.n} workload, {dt:.2f} s each; "
                        "numpy, BLAS threads for the dense cosine sums, the rest "
-                       "single-threaded")}
+                       "single-threaded")}, ref
 
 
 def main():
@@ -216,26 +224,45 @@ def main():
     except fftpl.FFTPLError as e:
         variants["fft_float_atomics"] = {"unavailable": str(e)}
 
-    # ---- per-kernel durations of the headline evaluation: HIP events the
-    # library records on this stream after every kernel (timing on the plan)
-    plan = plan_for(args.dct)
-    plan.timing(True)
-    acc = {}
-    reps = max(10, args.steps // 2)
-    for _ in range(reps):
-        f()
-        for name, t in plan.kernel_times():
-            acc.setdefault(name, []).append(t)
-    plan.timing(False)
+    # ---- per-kernel durations: HIP events the library records on this
+    # stream after every kernel (timing on the plan; no stream overlap then)
     nbytes = kernel_bytes(inst, band_entries(inst))
-    kernels = {}
-    for name, ts in acc.items():
-        t = float(np.mean(ts))
-        b = nbytes.get(name)
-        kernels[name] = {"ms": t, "algorithmic_bytes": b,
-                         "GBps": (b / (t / 1e3) / 1e9) if b else None}
-    dom = max(kernels, key=lambda k: kernels[k]["ms"])
-    ach = kernels[dom]["GBps"] or 0.0
+    gflop = gemm_flops(inst.n)
+
+    def kernel_table(mode):
+        plan = plan_for(mode)
+        fk = eval_fn(mode)
+        plan.timing(True)
+        acc = {}
+        for _ in range(max(10, args.steps // 4)):
+            fk()
+            for name, t in plan.kernel_times():
+                acc.setdefault(name, []).append(t)
+        plan.timing(False)
+        table = {}
+        for name, ts in acc.items():
+            t = float(np.mean(ts))
+            row = {"ms": t}
+            b = nbytes.get(name)
+            if b:
+                row.update(algorithmic_bytes=b, GBps=b / (t / 1e3) / 1e9)
+            if name in gflop:
+                mult = 3 if mode == "gemm_bf16x3" else 1
+                peak = BF16_PEAK_TFLOPS if mode == "gemm_bf16x3" else FP32_PEAK_TFLOPS
+                tf = mult * gflop[name] / (t / 1e3) / 1e12
+                row.update(mfma_flops=mult * gflop[name], TFLOPs=tf, mfma_util=tf / peak)
+            table[name] = row
+        return table
+
+    kernels = kernel_table(args.dct)
+    variant_kernels = {}
+    for mode in variants:
+        if mode != args.dct and "ms_per_eval" in variants[mode] and mode in ("gemm_f32",
+                                                                            "gemm_bf16x3"):
+            variant_kernels[mode] = kernel_table(mode)
+    hbm = {k: v for k, v in kernels.items() if v.get("GBps")}
+    dom = max(hbm, key=lambda k: hbm[k]["ms"])
+    ach = kernels[dom]["GBps"]
     roofline = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None}
     sb = stage_bytes(inst)
@@ -252,13 +279,54 @@ def main():
                    "dct": args.dct, "grad_mode": "field", "seed": inst.meta["seed"]},
         "p50_ms": float(np.percentile(steps_ms, 50)),
         "p90_ms": float(np.percentile(steps_ms, 90)),
-        "variants": variants, "kernels": kernels, "stages": stages, "roofline": roofline,
+        "variants": variants, "kernels": kernels, "variant_kernels": variant_kernels,
+        "stages": stages, "roofline": roofline,
     }
+    ref = None
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(inst, args.cpu_evals)
+        res["cpu_baseline"], ref = cpu_baseline(inst, args.cpu_evals)
+    if not args.no_precision:
+        if ref is None:
+            import oracle
+            ref = oracle.evaluate(inst, lam=1.0, grad_mode="field")
+        res["precision"] = precision_report(fftpl, plans, plan_for, eval_fn, variants, ref,
+                                            inst, prob, gx, gy)
     for p in plans.values():
         p.close()
     print(json.dumps(res), flush=True)
+
+
+def precision_report(fftpl, plans, plan_for, eval_fn, variants, ref, inst, prob, gx, gy):
+    """Relative L2 error of psi, Ex, Ey and of the gradient against the FP64
+    oracle, per spectral variant, at the benchmark workload."""
+    import numpy as np
+    import torch
+
+    def rel(a, b):
+        a = np.asarray(a, np.float64)
+        return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+    n2 = inst.n ** 2
+    out = {}
+    g0 = np.concatenate([ref["gx"], ref["gy"]])
+    for mode, v in variants.items():
+        if "ms_per_eval" not in v or mode not in ("fft", "gemm_f32", "gemm_bf16x3"):
+            continue
+        plan = plan_for(mode)
+        eval_fn(mode)()
+        g = np.concatenate([gx.cpu().numpy(), gy.cpu().numpy()])
+        rho = plan.maps()[0].reshape(-1).clone()
+        psi = torch.empty(n2, device="cuda")
+        ex = torch.empty(n2, device="cuda")
+        ey = torch.empty(n2, device="cuda")
+        fftpl.poisson_solve(plan, prob.grid, rho, psi, ex, ey)
+        torch.cuda.synchronize()
+        shape = (inst.n, inst.n)
+        out[mode] = {"psi": rel(psi.cpu().numpy().reshape(shape), ref["psi"]),
+                     "ex": rel(ex.cpu().numpy().reshape(shape), ref["ex"]),
+                     "ey": rel(ey.cpu().numpy().reshape(shape), ref["ey"]),
+                     "grad": rel(g, g0)}
+    return out
 
 
 if __name__ == "__main__":
