@@ -34,6 +34,8 @@ def parse():
                     help="spectral variants to time besides --dct")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-evals", type=int, default=2)
+    ap.add_argument("--kernel-reps", type=int, default=0,
+                    help="evaluations timed kernel by kernel (default max(10, steps/4))")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the per-variant error report against the FP64 oracle")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -234,7 +236,7 @@ def main():
         fk = eval_fn(mode)
         plan.timing(True)
         acc = {}
-        for _ in range(max(10, args.steps // 4)):
+        for _ in range(args.kernel_reps or max(10, args.steps // 4)):
             fk()
             for name, t in plan.kernel_times():
                 acc.setdefault(name, []).append(t)
