@@ -22,6 +22,37 @@ HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
 BF16_PEAK_TFLOPS = 2500.0
 
+# HBM traffic per launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE (KiB per
+# dispatch) on the 2.1M-cell workload, scaled by what the same counters read
+# for a plain 256 MiB device copy in the same run (FETCH_SIZE x2.0, WRITE_SIZE
+# x1.0).  Each entry records the SHA-1 of the kernel's source file when the
+# counters were taken; once that source changes the figure is stale and the
+# report gives null.
+PMC_FETCH_SCALE, PMC_WRITE_SCALE = 2.0, 1.0
+PMC_TRAFFIC = {
+    # kernel: (source file, sha1, FETCH_SIZE KiB, WRITE_SIZE KiB)
+    "k_wa_slots_big": ("wirelength.hip", "922ee75d6507e0a8b2b756700c4304a5dad417d3",
+                       373752.1, 182874.7),
+    "k_wa_slots_small": ("wirelength.hip", "922ee75d6507e0a8b2b756700c4304a5dad417d3",
+                         441270.0, 206730.2),
+    "k_gather_pins": ("density.hip", "0a8d2c3c9113b790e05a6f689bfa3d07d7c16f9f",
+                      204727.2, 16406.2),
+}
+
+
+def pmc_traffic(kernel):
+    """Scaled HBM bytes per launch of `kernel`, or None if not measured or stale."""
+    import hashlib
+    rec = PMC_TRAFFIC.get(kernel)
+    if rec is None:
+        return None
+    src, sha, fetch_kib, write_kib = rec
+    path = os.path.join(ROOT, "paper_1312_4587_amd", "csrc", src)
+    with open(path, "rb") as f:
+        if hashlib.sha1(f.read()).hexdigest() != sha:
+            return None
+    return (PMC_FETCH_SCALE * fetch_kib + PMC_WRITE_SCALE * write_kib) * 1024.0
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -266,7 +297,12 @@ def main():
     dom = max(hbm, key=lambda k: hbm[k]["ms"])
     ach = kernels[dom]["GBps"]
     roofline = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None}
+                "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": pmc_traffic(dom),
+                "algorithmic_bytes": kernels[dom]["algorithmic_bytes"]}
+    for k, v in kernels.items():
+        t = pmc_traffic(k)
+        if t is not None:
+            v["pmc_hbm_bytes"] = t
     sb = stage_bytes(inst)
     stages = {"algorithmic_bytes": sb,
               "eval_GBps": sum(sb.values()) / (ms / 1e3) / 1e9}
