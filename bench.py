@@ -113,6 +113,11 @@ def kernel_bytes(inst, nent):
         "k_cols_solve": 4 * n2 + 8 * n2,                # bT in; P, Q out
         "k_rows_inverse": 8 * n2 + 4 * n2 + 8 * n2,     # P, Q, rho in; (Ex, Ey) out
         "k_gather_pins": 16 * m + 8 * n2 + 4 * (m + 1) + 8 * P + 8 * m,
+        # exchange path: u16 cell offsets and float2 pin records in A order,
+        # int32 A positions and u16 CSR offsets in B order
+        "k_xch_spread": 8 * m + 2 * P + 8 * P,
+        "k_xch_wa": 4 * P + 2 * P + 8 * P + 8 * P + 8 * P + 4 * (E + 1),
+        "k_gather_xch": 16 * m + 8 * n2 + 4 * (m + 1) + 4 * P + 8 * P + 8 * m,
         "k_eval_finalize": 0,
     }
 
@@ -243,19 +248,21 @@ def main():
             variants[mode] = {"unavailable": str(e)}
     variants[args.dct] = {"ms_per_eval": ms, "value": value}
 
-    # ---- the float-atomic evaluation path, for comparison
-    try:
-        prob_atomic = fftpl.Problem.from_instance(inst, fast=False)
-        plan_a = plan_for(args.dct)
-        fa = lambda: fftpl.eval(plan_a, prob_atomic, x, y, 1.0, inst.gamma, "field",  # noqa
-                                gx, gy, out4)
-        for _ in range(2):
-            fa()
-        msa = time_loop(fa, max(5, args.steps // 5), stream)
-        variants["fft_float_atomics"] = {"ms_per_eval": msa, "value": m / (msa / 1e3)}
-        del prob_atomic
-    except fftpl.FFTPLError as e:
-        variants["fft_float_atomics"] = {"unavailable": str(e)}
+    # ---- the other wirelength paths, for comparison: cell-major slots and
+    # float atomics
+    for path, key in (("slots", "fft_slots"), ("atomic", "fft_float_atomics")):
+        try:
+            prob_o = fftpl.Problem.from_instance(inst, path=path)
+            plan_o = plan_for(args.dct)
+            fo = lambda: fftpl.eval(plan_o, prob_o, x, y, 1.0, inst.gamma, "field",  # noqa
+                                    gx, gy, out4)
+            for _ in range(2):
+                fo()
+            mso = time_loop(fo, max(5, args.steps // 5), stream)
+            variants[key] = {"ms_per_eval": mso, "value": m / (mso / 1e3)}
+            del prob_o
+        except fftpl.FFTPLError as e:
+            variants[key] = {"unavailable": str(e)}
 
     # ---- per-kernel durations: HIP events the library records on this
     # stream after every kernel (timing on the plan; no stream overlap then)

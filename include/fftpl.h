@@ -100,13 +100,18 @@ typedef struct fftpl_plan fftpl_plan;
  * [num_pins] in [0, num_cells), pin offsets from the cell centre
  * pin_dx, pin_dy [num_pins].
  *
- * Optional, for the atomic-free evaluation path (all four set, n <= 1024):
- * cell_ptr [num_cells+1] and pin_slot [num_pins] from fftpl_netlist_index, and
- * a device workspace `work` of work_bytes >= fftpl_problem_work_bytes(...)
- * bytes, owned by the caller and used by one evaluation at a time.  When any
- * is NULL (or work_bytes is too small) fftpl_eval uses float atomics for the
- * density scatter and the wirelength gradient instead: same results up to
- * float32 rounding order, several times slower. */
+ * Optional, for the atomic-free evaluation paths (n <= 1024): a device
+ * workspace `work` of work_bytes >= fftpl_problem_work_bytes(...) bytes, owned
+ * by the caller and used by one evaluation at a time, and one pin index:
+ *   - the exchange index (fastest): xindex / xindex_bytes from
+ *     fftpl_xindex_build for this netlist and max_degree;
+ *   - or the cell-major slots: cell_ptr [num_cells+1] and pin_slot
+ *     [num_pins] from fftpl_netlist_index.
+ * When work or both indexes are missing (or work_bytes / xindex_bytes are
+ * too small) fftpl_eval uses float atomics for the density scatter and the
+ * wirelength gradient instead.  All paths give the same results up to
+ * float32 rounding order.  An index must be rebuilt when net_ptr or pin_cell
+ * change; pin offsets and positions may change freely. */
 typedef struct fftpl_problem {
   fftpl_grid grid;
   int32_t num_cells;
@@ -125,6 +130,10 @@ typedef struct fftpl_problem {
   const int32_t* pin_slot;
   void* work;
   uint64_t work_bytes;
+  const void* xindex;
+  uint64_t xindex_bytes;
+  int32_t max_degree; /* the value xindex was built for */
+  int32_t reserved2;  /* must be 0 */
 } fftpl_problem;
 
 /* Library version (FFTPL_VERSION of the build). */
@@ -236,6 +245,31 @@ int fftpl_problem_work_bytes(int32_t n, int32_t num_cells, int32_t num_nets,
  * entries.  pin_cell values must lie in [0, num_cells). */
 int fftpl_netlist_index(int32_t num_cells, int32_t num_pins, const int32_t* pin_cell,
                         int32_t* cell_ptr, int32_t* pin_slot, int32_t* work, void* stream);
+
+/* Exchange index of a netlist (Section II: the netlist as a hypergraph; the
+ * index is a blocked form of the transpose of its pin-net incidence), for the
+ * fastest fftpl_eval path.  Cells are cut into blocks of 4096 consecutive
+ * cells and nets into blocks of whole nets (at most 9728 pins per block); the
+ * index lists the pins by (cell block, net block) and, per net block, by cell
+ * block, so that positions and gradients move between cells and nets in runs
+ * through on-chip memory.
+ *
+ * fftpl_xindex_bytes: device bytes of the index and of the build's scratch
+ * for num_cells cells, num_nets nets, num_pins pins and nets of degree at most
+ * max_degree.  Host-only.  FFTPL_E_UNSUPPORTED when max_degree > 8705.
+ *
+ * fftpl_xindex_build: builds the index into `index` (index_bytes, caller
+ * owned; valid until net_ptr or pin_cell change) using `work` (work_bytes,
+ * free again on return), on `stream`, and waits for it (the call
+ * synchronises the stream).  FFTPL_E_INVAL when a net has more than
+ * max_degree pins, when net_ptr is not a CSR over num_pins pins or when a
+ * pin_cell lies outside [0, num_cells); the index is then unusable. */
+int fftpl_xindex_bytes(int32_t num_cells, int32_t num_nets, int32_t num_pins,
+                       int32_t max_degree, uint64_t* index_bytes, uint64_t* work_bytes);
+int fftpl_xindex_build(int32_t num_cells, int32_t num_nets, int32_t num_pins,
+                       const int32_t* net_ptr, const int32_t* pin_cell, int32_t max_degree,
+                       void* index, uint64_t index_bytes, void* work, uint64_t work_bytes,
+                       void* stream);
 
 /* One full evaluation (Algorithm 1, the density / FFT solve / gradient steps):
  *   rho = base + cells; Poisson solve; g = dW~/dv + lambda * g_N (grad_mode);

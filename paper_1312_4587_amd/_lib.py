@@ -28,7 +28,9 @@ class fftpl_problem(ctypes.Structure):
                 ("cap", c_void_p), ("net_ptr", c_void_p), ("pin_cell", c_void_p),
                 ("pin_dx", c_void_p), ("pin_dy", c_void_p),
                 ("cell_ptr", c_void_p), ("pin_slot", c_void_p),
-                ("work", c_void_p), ("work_bytes", ctypes.c_uint64)]
+                ("work", c_void_p), ("work_bytes", ctypes.c_uint64),
+                ("xindex", c_void_p), ("xindex_bytes", ctypes.c_uint64),
+                ("max_degree", ctypes.c_int32), ("reserved2", ctypes.c_int32)]
 
 
 _G = ctypes.POINTER(fftpl_grid)
@@ -63,6 +65,11 @@ SIGNATURES = {
                                          ctypes.POINTER(ctypes.c_uint64)]),
     "fftpl_netlist_index": (c_int, [c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p,
                                     c_void_p]),
+    "fftpl_xindex_bytes": (c_int, [c_int, c_int, c_int, c_int,
+                                   ctypes.POINTER(ctypes.c_uint64),
+                                   ctypes.POINTER(ctypes.c_uint64)]),
+    "fftpl_xindex_build": (c_int, [c_int, c_int, c_int, c_void_p, c_void_p, c_int, c_void_p,
+                                   ctypes.c_uint64, c_void_p, ctypes.c_uint64, c_void_p]),
     "fftpl_plan_timing": (c_int, [c_void_p, c_int]),
     "fftpl_plan_kernel_times": (c_int, [c_void_p, c_int, ctypes.POINTER(c_float),
                                         ctypes.POINTER(c_char_p), ctypes.POINTER(c_int)]),

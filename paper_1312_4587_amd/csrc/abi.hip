@@ -251,7 +251,7 @@ int fftpl_poisson_solve(fftpl_plan* plan, const fftpl_grid* grid, const float* r
   e = plan->p.mode == FFTPL_DCT_FFT ? spectral_fft(plan->p, a, s)
                                     : spectral_gemm(plan->p, a, s);
   if (e == hipSuccess && energy) {
-    e = launch_eval_finalize(plan->p.partials, plan->p.n_en, nullptr, 0, nullptr, 0, energy,
+    e = launch_eval_finalize(plan->p.partials, plan->p.n_en, nullptr, 0, nullptr, 0, 0, energy,
                              nullptr, nullptr, nullptr, s);
     plan_mark(plan->p, "k_eval_finalize", s);
   }
@@ -308,7 +308,7 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
                const float* y, float lambda, float gamma, int32_t grad_mode, float* gx,
                float* gy, double* out4, void* stream) {
   if (!plan || !prob || !out4 || !grid_ok(&prob->grid)) return FFTPL_E_INVAL;
-  if (prob->reserved != 0) return FFTPL_E_INVAL;
+  if (prob->reserved != 0 || prob->reserved2 != 0) return FFTPL_E_INVAL;
   if (prob->grid.n != plan->p.n) return FFTPL_E_STATE;
   const int m = prob->num_cells;
   if (m < 0 || prob->num_nets < 0 || prob->num_pins < 0) return FFTPL_E_INVAL;
@@ -327,12 +327,32 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
   const GridF g = make_gridf(prob->grid);
   hipStream_t s = as_stream(stream);
   const int64_t nn = (int64_t)p.n * p.n;
-  // Atomic-free path when the caller supplied the pin index and workspace.
+  // Atomic-free paths when the caller supplied a workspace and a pin index:
+  // the exchange index (xch) or the cell-major slots (slots).
   size_t need = 0;
   BandLayout L = band_layout(p.n, m, prob->num_nets, prob->num_pins, nullptr, &need);
-  const bool fast = prob->cell_ptr && prob->pin_slot && prob->work &&
-                    prob->work_bytes >= need && p.n <= kBandMaxN;
+  const bool ws_ok = prob->work && prob->work_bytes >= need && p.n <= kBandMaxN;
+  XchDims xd;
+  const bool xch = ws_ok && prob->xindex &&
+                   xch_dims(m, prob->num_nets, prob->num_pins, prob->max_degree, &xd) ==
+                       FFTPL_OK &&
+                   prob->xindex_bytes >= xd.index_bytes;
+  const bool slots = !xch && ws_ok && prob->cell_ptr && prob->pin_slot;
+  const bool fast = xch || slots;
   if (fast) L = band_layout(p.n, m, prob->num_nets, prob->num_pins, prob->work, nullptr);
+  XchIndex X;
+  if (xch) {
+    X = xch_index(xd, prob->xindex);
+    if (validate_env()) {
+      int32_t hdr[8];
+      if (hipDeviceSynchronize() != hipSuccess ||
+          hipMemcpy(hdr, prob->xindex, sizeof(hdr), hipMemcpyDeviceToHost) != hipSuccess)
+        return FFTPL_E_DEVICE;
+      if (hdr[1] != m || hdr[2] != prob->num_nets || hdr[3] != prob->num_pins ||
+          hdr[4] != prob->max_degree || hdr[5] != xd.npt)
+        return FFTPL_E_STATE;
+    }
+  }
   hipError_t e = hipSuccess;
   p.nev = 0;
   plan_mark(p, "start", s);
@@ -351,12 +371,22 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
       e = hipEventRecord(p.fork, s);
       if (e == hipSuccess) e = hipStreamWaitEvent(ws, p.fork, 0);
     }
-    if (e == hipSuccess) e = launch_interleave(m, x, y, L.xy, ws);
-    plan_mark(p, "k_interleave", ws);
-    if (e == hipSuccess)
-      e = launch_wa_pins(prob->num_nets, prob->net_ptr, prob->pin_cell, prob->pin_dx,
-                         prob->pin_dy, L.xy, prob->pin_slot, gamma, L.pin_grad, L.wa_part,
-                         ws, &p);
+    if (xch) {
+      // pin positions into the exchange buffer, then every net block
+      if (e == hipSuccess) e = launch_xch_spread(xd, X, x, y, L.pin_grad, ws);
+      plan_mark(p, "k_xch_spread", ws);
+      if (e == hipSuccess)
+        e = launch_xch_wa(xd, X, prob->net_ptr, prob->pin_dx, prob->pin_dy, gamma,
+                          L.pin_grad, L.wa_part, ws);
+      plan_mark(p, "k_xch_wa", ws);
+    } else {
+      if (e == hipSuccess) e = launch_interleave(m, x, y, L.xy, ws);
+      plan_mark(p, "k_interleave", ws);
+      if (e == hipSuccess)
+        e = launch_wa_pins(prob->num_nets, prob->net_ptr, prob->pin_cell, prob->pin_dx,
+                           prob->pin_dy, L.xy, prob->pin_slot, gamma, L.pin_grad, L.wa_part,
+                           ws, &p);
+    }
     if (e == hipSuccess && overlap) e = hipEventRecord(p.join, ws);
     // 2. banded density scatter
     if (e == hipSuccess)
@@ -387,10 +417,17 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
     // join the wirelength branch; 5. per cell: density gradient plus the sum
     // of its pins' slots
     if (e == hipSuccess && overlap) e = hipStreamWaitEvent(s, p.join, 0);
-    if (e == hipSuccess)
-      e = launch_gather_pins(g, m, x, y, prob->w, prob->h, p.exy, p.psi, grad_mode, lambda,
-                             prob->cell_ptr, L.pin_grad, gx, gy, s);
-    plan_mark(p, "k_gather_pins", s);
+    if (xch) {
+      if (e == hipSuccess)
+        e = launch_gather_xch(g, m, x, y, prob->w, prob->h, p.exy, p.psi, grad_mode, lambda,
+                              X.cell_ptr, X.qa, L.pin_grad, gx, gy, s);
+      plan_mark(p, "k_gather_xch", s);
+    } else {
+      if (e == hipSuccess)
+        e = launch_gather_pins(g, m, x, y, prob->w, prob->h, p.exy, p.psi, grad_mode, lambda,
+                               prob->cell_ptr, L.pin_grad, gx, gy, s);
+      plan_mark(p, "k_gather_pins", s);
+    }
   } else {
     // 4. density gradient (overwrites g), 5. WA gradient (float atomics)
     if (e == hipSuccess)
@@ -406,8 +443,10 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
   // W~ and HPWL into out4 directly)
   if (e == hipSuccess)
     e = launch_eval_finalize(p.partials, p.n_en, p.partials + p.en_max, p.n_tau,
-                             fast ? L.wa_part : nullptr, prob->num_nets, &out4[0], &out4[1], &out4[2],
-                             &out4[3], s);
+                             fast ? L.wa_part : nullptr,
+                             xch ? xd.nnb : (prob->num_nets + 255) / 256,
+                             xch ? 0 : wa_big_grid(prob->num_nets), &out4[0], &out4[1],
+                             &out4[2], &out4[3], s);
   plan_mark(p, "k_eval_finalize", s);
   return dev_status(e);
 }
@@ -464,6 +503,30 @@ int fftpl_netlist_index(int32_t num_cells, int32_t num_pins, const int32_t* pin_
   }
   return dev_status(launch_netlist_index(num_cells, num_pins, pin_cell, cell_ptr, pin_slot,
                                          work, as_stream(stream)));
+}
+
+int fftpl_xindex_bytes(int32_t num_cells, int32_t num_nets, int32_t num_pins,
+                       int32_t max_degree, uint64_t* index_bytes, uint64_t* work_bytes) {
+  if (!index_bytes || !work_bytes) return FFTPL_E_INVAL;
+  XchDims d;
+  const int st = xch_dims(num_cells, num_nets, num_pins, max_degree, &d);
+  if (st != FFTPL_OK) return st;
+  *index_bytes = d.index_bytes;
+  *work_bytes = d.work_bytes;
+  return FFTPL_OK;
+}
+
+int fftpl_xindex_build(int32_t num_cells, int32_t num_nets, int32_t num_pins,
+                       const int32_t* net_ptr, const int32_t* pin_cell, int32_t max_degree,
+                       void* index, uint64_t index_bytes, void* work, uint64_t work_bytes,
+                       void* stream) {
+  XchDims d;
+  const int st = xch_dims(num_cells, num_nets, num_pins, max_degree, &d);
+  if (st != FFTPL_OK) return st;
+  if (!net_ptr || !index || !work || (num_pins > 0 && !pin_cell)) return FFTPL_E_INVAL;
+  if (num_pins > 0 && num_cells == 0) return FFTPL_E_INVAL;
+  if (index_bytes < d.index_bytes || work_bytes < d.work_bytes) return FFTPL_E_INVAL;
+  return xch_build(d, net_ptr, pin_cell, index, work, as_stream(stream));
 }
 
 int fftpl_debug_cell_bins(const fftpl_grid* grid, int32_t num_cells, const float* x,

@@ -26,9 +26,14 @@ BandLayout band_layout(int n, int m, int num_nets, int num_pins, void* work,
   L.m = m;
   L.nblk = m > 0 ? (m + kCellsPerBlock - 1) / kCellsPerBlock : 1;
   L.nwa = (num_nets + 255) / 256;
+  // wirelength partials: 4 per 256 nets (slot path) or 2 per net block of at
+  // least kXchMinTarget pins (exchange path)
+  size_t nwp = 4 * (size_t)L.nwa;
+  const size_t nxp = 2 * ((size_t)(num_pins + kXchMinTarget - 1) / kXchMinTarget + 1);
+  if (nwp < nxp) nwp = nxp;
   size_t off = 0;
   const size_t o_wp = off;
-  off = align256(off + sizeof(double) * 4 * (size_t)L.nwa);
+  off = align256(off + sizeof(double) * nwp);
   const size_t o_xy = off;
   off = align256(off + sizeof(float2) * (size_t)m);
   const size_t o_pg = off;

@@ -144,7 +144,10 @@ hipError_t launch_init_eval(double* out4, int32_t* counters, int ncount, hipStre
 // interleaved).  EXACT: g = 2*scale/bin * sum_other-axis ov *
 // [psi at right edge - psi at left edge] for edges strictly inside (0, n).
 // ---------------------------------------------------------------------------
-template <int MODE, bool INTERLEAVED, bool PINS>
+// PINS: 0 density gradient only; 1 plus the sum of the cell's contiguous pin
+// slots (cell_ptr, pin_grad); 3 plus the sum of pin_grad[pin_idx[j]] over the
+// cell's entries j of cell_ptr (blocks in XCD order).
+template <int MODE, bool INTERLEAVED, int PINS>
 __global__ void __launch_bounds__(256) k_gather(GridF g, int m, const float* __restrict__ x,
                                                 const float* __restrict__ y,
                                                 const float* __restrict__ w,
@@ -155,56 +158,21 @@ __global__ void __launch_bounds__(256) k_gather(GridF g, int m, const float* __r
                                                 const float* __restrict__ psi, float scale,
                                                 int accumulate, const int32_t* __restrict__ cell_ptr,
                                                 const float2* __restrict__ pin_grad,
+                                                const int32_t* __restrict__ pin_idx,
                                                 float* __restrict__ gx, float* __restrict__ gy) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int blk = PINS == 3 ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
+  const int i = blk * blockDim.x + threadIdx.x;
   if (i >= m) return;
-  const int n = g.n;
-  const Span sx = cell_span(x[i], w[i], g.xl, g.inv_bw, n);
-  const Span sy = cell_span(y[i], h[i], g.yl, g.inv_bh, n);
-  float ax = 0.0f, ay = 0.0f;
-  if (MODE == FFTPL_GRAD_FIELD) {
-    for (int iy = sy.i0; iy <= sy.i1; ++iy) {
-      const float oy = span_overlap(sy, iy);
-      for (int ix = sx.i0; ix <= sx.i1; ++ix) {
-        const float ov = span_overlap(sx, ix) * oy;
-        const int64_t b = (int64_t)iy * n + ix;
-        if (INTERLEAVED) {
-          const float2 e = exy[b];
-          ax += ov * e.x;
-          ay += ov * e.y;
-        } else {
-          ax += ov * ex[b];
-          ay += ov * ey[b];
-        }
-      }
+  const float2 d = cell_density_grad<MODE, INTERLEAVED>(g, x[i], y[i], w[i], h[i], ex, ey, exy, psi);
+  float ax = scale * d.x, ay = scale * d.y;
+  if (PINS == 3) {
+    const int k1 = cell_ptr[i + 1];
+    for (int k = cell_ptr[i]; k < k1; ++k) {
+      const float2 q = pin_grad[pin_idx[k]];
+      ax += q.x;
+      ay += q.y;
     }
-    ax *= -scale * g.inv_bw;
-    ay *= -scale * g.inv_bh;
-  } else {
-    const float fn = (float)n;
-    const bool xr = sx.hi > 0.0f && sx.hi < fn, xl = sx.lo > 0.0f && sx.lo < fn;
-    const bool yr = sy.hi > 0.0f && sy.hi < fn, yl = sy.lo > 0.0f && sy.lo < fn;
-    const int cxr = xr ? (int)floorf(sx.hi) : 0, cxl = xl ? (int)floorf(sx.lo) : 0;
-    const int cyr = yr ? (int)floorf(sy.hi) : 0, cyl = yl ? (int)floorf(sy.lo) : 0;
-    for (int iy = sy.i0; iy <= sy.i1; ++iy) {
-      const float oy = span_overlap(sy, iy);
-      const float* row = psi + (int64_t)iy * n;
-      float d = 0.0f;
-      if (xr) d += row[cxr];
-      if (xl) d -= row[cxl];
-      ax += oy * d;
-    }
-    for (int ix = sx.i0; ix <= sx.i1; ++ix) {
-      const float ox = span_overlap(sx, ix);
-      float d = 0.0f;
-      if (yr) d += psi[(int64_t)cyr * n + ix];
-      if (yl) d -= psi[(int64_t)cyl * n + ix];
-      ay += ox * d;
-    }
-    ax *= 2.0f * scale * g.inv_bw;
-    ay *= 2.0f * scale * g.inv_bh;
-  }
-  if (PINS) {
+  } else if (PINS == 1) {
     // the cell's wirelength gradient: its pins' slots are contiguous
     const int k1 = cell_ptr[i + 1];
     for (int k = cell_ptr[i]; k < k1; ++k) {
@@ -231,14 +199,14 @@ hipError_t launch_gather(const GridF& g, int m, const float* x, const float* y,
   dim3 grid((m + 255) / 256), block(256);
   const float2* e2 = reinterpret_cast<const float2*>(exy);
   if (grad_mode == FFTPL_GRAD_EXACT) {
-    hipLaunchKernelGGL((k_gather<FFTPL_GRAD_EXACT, false, false>), grid, block, 0, s, g, m, x, y,
-                       w, h, ex, ey, e2, psi, scale, accumulate, nullptr, nullptr, gx, gy);
+    hipLaunchKernelGGL((k_gather<FFTPL_GRAD_EXACT, false, 0>), grid, block, 0, s, g, m, x, y,
+                       w, h, ex, ey, e2, psi, scale, accumulate, nullptr, nullptr, nullptr, gx, gy);
   } else if (exy) {
-    hipLaunchKernelGGL((k_gather<FFTPL_GRAD_FIELD, true, false>), grid, block, 0, s, g, m, x, y,
-                       w, h, ex, ey, e2, psi, scale, accumulate, nullptr, nullptr, gx, gy);
+    hipLaunchKernelGGL((k_gather<FFTPL_GRAD_FIELD, true, 0>), grid, block, 0, s, g, m, x, y,
+                       w, h, ex, ey, e2, psi, scale, accumulate, nullptr, nullptr, nullptr, gx, gy);
   } else {
-    hipLaunchKernelGGL((k_gather<FFTPL_GRAD_FIELD, false, false>), grid, block, 0, s, g, m, x, y,
-                       w, h, ex, ey, e2, psi, scale, accumulate, nullptr, nullptr, gx, gy);
+    hipLaunchKernelGGL((k_gather<FFTPL_GRAD_FIELD, false, 0>), grid, block, 0, s, g, m, x, y,
+                       w, h, ex, ey, e2, psi, scale, accumulate, nullptr, nullptr, nullptr, gx, gy);
   }
   return hipGetLastError();
 }
@@ -252,11 +220,31 @@ hipError_t launch_gather_pins(const GridF& g, int m, const float* x, const float
   dim3 grid((m + 255) / 256), block(256);
   const float2* e2 = reinterpret_cast<const float2*>(exy);
   if (grad_mode == FFTPL_GRAD_EXACT) {
-    hipLaunchKernelGGL((k_gather<FFTPL_GRAD_EXACT, false, true>), grid, block, 0, s, g, m, x,
-                       y, w, h, nullptr, nullptr, e2, psi, scale, 0, cell_ptr, pin_grad, gx, gy);
+    hipLaunchKernelGGL((k_gather<FFTPL_GRAD_EXACT, false, 1>), grid, block, 0, s, g, m, x,
+                       y, w, h, nullptr, nullptr, e2, psi, scale, 0, cell_ptr, pin_grad, nullptr, gx, gy);
   } else {
-    hipLaunchKernelGGL((k_gather<FFTPL_GRAD_FIELD, true, true>), grid, block, 0, s, g, m, x,
-                       y, w, h, nullptr, nullptr, e2, psi, scale, 0, cell_ptr, pin_grad, gx, gy);
+    hipLaunchKernelGGL((k_gather<FFTPL_GRAD_FIELD, true, 1>), grid, block, 0, s, g, m, x,
+                       y, w, h, nullptr, nullptr, e2, psi, scale, 0, cell_ptr, pin_grad, nullptr, gx, gy);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_xch(const GridF& g, int m, const float* x, const float* y,
+                             const float* w, const float* h, const float* exy,
+                             const float* psi, int grad_mode, float scale,
+                             const int32_t* cell_ptr, const int32_t* qa, const float2* T,
+                             float* gx, float* gy, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  // a multiple of 8 blocks, so that xcd_block hands each XCD a contiguous range
+  const int nb = ((m + 255) / 256 + kNumXcd - 1) / kNumXcd * kNumXcd;
+  dim3 grid(nb), block(256);
+  const float2* e2 = reinterpret_cast<const float2*>(exy);
+  if (grad_mode == FFTPL_GRAD_EXACT) {
+    hipLaunchKernelGGL((k_gather<FFTPL_GRAD_EXACT, false, 3>), grid, block, 0, s, g, m, x,
+                       y, w, h, nullptr, nullptr, e2, psi, scale, 0, cell_ptr, T, qa, gx, gy);
+  } else {
+    hipLaunchKernelGGL((k_gather<FFTPL_GRAD_FIELD, true, 3>), grid, block, 0, s, g, m, x,
+                       y, w, h, nullptr, nullptr, e2, psi, scale, 0, cell_ptr, T, qa, gx, gy);
   }
   return hipGetLastError();
 }

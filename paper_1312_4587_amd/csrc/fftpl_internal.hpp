@@ -61,6 +61,92 @@ __device__ __forceinline__ float span_overlap(const Span& s, int j) {
   return fminf(s.chi, (float)(j + 1)) - fmaxf(s.clo, (float)j);
 }
 
+// Density gradient of one cell (Section III-C), before the factor lambda.
+// FIELD: -1/bin * sum_b ov(i, b) E_b (E interleaved as (Ex, Ey) per bin, or
+// two maps).  EXACT: dN/dx = 2/bin * sum over the other axis' overlaps of
+// [psi at the right edge's bin - psi at the left edge's bin], for edges
+// strictly inside (0, n) (an edge moving inside a bin moves area from the
+// bin it leaves to the bin it enters).
+template <int MODE, bool INTERLEAVED>
+__device__ __forceinline__ float2 cell_density_grad(const GridF& g, float x, float y, float w,
+                                                    float h, const float* __restrict__ ex,
+                                                    const float* __restrict__ ey,
+                                                    const float2* __restrict__ exy,
+                                                    const float* __restrict__ psi) {
+  const int n = g.n;
+  const Span sx = cell_span(x, w, g.xl, g.inv_bw, n);
+  const Span sy = cell_span(y, h, g.yl, g.inv_bh, n);
+  float ax = 0.0f, ay = 0.0f;
+  if (MODE == FFTPL_GRAD_FIELD) {
+    for (int iy = sy.i0; iy <= sy.i1; ++iy) {
+      const float oy = span_overlap(sy, iy);
+      for (int ix = sx.i0; ix <= sx.i1; ++ix) {
+        const float ov = span_overlap(sx, ix) * oy;
+        const int64_t b = (int64_t)iy * n + ix;
+        if (INTERLEAVED) {
+          const float2 e = exy[b];
+          ax += ov * e.x;
+          ay += ov * e.y;
+        } else {
+          ax += ov * ex[b];
+          ay += ov * ey[b];
+        }
+      }
+    }
+    ax *= -g.inv_bw;
+    ay *= -g.inv_bh;
+  } else {
+    const float fn = (float)n;
+    const bool xr = sx.hi > 0.0f && sx.hi < fn, xl = sx.lo > 0.0f && sx.lo < fn;
+    const bool yr = sy.hi > 0.0f && sy.hi < fn, yl = sy.lo > 0.0f && sy.lo < fn;
+    const int cxr = xr ? (int)floorf(sx.hi) : 0, cxl = xl ? (int)floorf(sx.lo) : 0;
+    const int cyr = yr ? (int)floorf(sy.hi) : 0, cyl = yl ? (int)floorf(sy.lo) : 0;
+    for (int iy = sy.i0; iy <= sy.i1; ++iy) {
+      const float oy = span_overlap(sy, iy);
+      const float* row = psi + (int64_t)iy * n;
+      float d = 0.0f;
+      if (xr) d += row[cxr];
+      if (xl) d -= row[cxl];
+      ax += oy * d;
+    }
+    for (int ix = sx.i0; ix <= sx.i1; ++ix) {
+      const float ox = span_overlap(sx, ix);
+      float d = 0.0f;
+      if (yr) d += psi[(int64_t)cyr * n + ix];
+      if (yl) d -= psi[(int64_t)cyl * n + ix];
+      ay += ox * d;
+    }
+    ax *= 2.0f * g.inv_bw;
+    ay *= 2.0f * g.inv_bh;
+  }
+  return make_float2(ax, ay);
+}
+
+// ---- weighted-average wirelength, Eq. (3), per net and axis ----
+// Per-axis sums of one net: S+ = sum e+, T+ = sum (X-M) e+, S-, T- likewise.
+struct AxisSums {
+  float sp, tp, sm, tm;
+};
+
+__device__ __forceinline__ void axis_accum(AxisSums& a, float X, float M, float L,
+                                           float inv_gamma) {
+  float d = X - M, ee = expf(d * inv_gamma);
+  a.sp += ee;
+  a.tp += d * ee;
+  d = X - L;
+  ee = expf(-d * inv_gamma);
+  a.sm += ee;
+  a.tm += d * ee;
+}
+
+// dW~/dX for one pin, given M, L and W+ - M = wp, W- - L = wm, 1/S+, 1/S-.
+__device__ __forceinline__ float axis_grad(float X, float M, float L, float wp, float wm,
+                                           float rsp, float rsm, float inv_gamma) {
+  const float dp = X - M, dm = X - L;
+  return expf(dp * inv_gamma) * rsp * (1.0f + (dp - wp) * inv_gamma) -
+         expf(-dm * inv_gamma) * rsm * (1.0f - (dm - wm) * inv_gamma);
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
@@ -231,10 +317,10 @@ hipError_t launch_wa(int num_nets, const int32_t* net_ptr, const int32_t* pin_ce
                      const float* pin_dx, const float* pin_dy, const float* x,
                      const float* y, float gamma, float* gx, float* gy,
                      double* wa_out, double* hp_out, hipStream_t s);
-// wa: the wirelength partials of fftpl_eval's atomic-free path for num_nets
-// nets (or null: W~ and HPWL are left as they are).
+// wa: per-block wirelength partials laid out [W~ (n_s), HPWL (n_s), W~ (n_b),
+// HPWL (n_b)] (or null: W~ and HPWL are left as they are).
 hipError_t launch_eval_finalize(const double* en, int n_en, const double* tau, int n_tau,
-                                const double* wa, int num_nets, double* o_en, double* o_wa,
+                                const double* wa, int n_s, int n_b, double* o_en, double* o_wa,
                                 double* o_hp, double* o_tau, hipStream_t s);
 
 // Blocks of the persistent big-net wirelength kernel (4 waves each; 512
@@ -265,7 +351,7 @@ struct BandLayout {
   int32_t* big = nullptr;        // [m] cells spanning more than kMaxBands bands
   int32_t* blk_base = nullptr;   // [nblk*nb] block offsets inside each band
   int32_t* counters = nullptr;   // [nb + 1] band counts, then the big-cell count
-  double* wa_part = nullptr;     // [4*nwa] per-block W~ / HPWL partials
+  double* wa_part = nullptr;     // per-block W~ / HPWL partials (slot or exchange path)
   int nwa = 0;                   // blocks of each wirelength kernel
 };
 BandLayout band_layout(int n, int m, int num_nets, int num_pins, void* work,
@@ -290,6 +376,62 @@ hipError_t launch_gather_pins(const GridF& g, int m, const float* x, const float
 hipError_t launch_netlist_index(int m, int num_pins, const int32_t* pin_cell,
                                 int32_t* cell_ptr, int32_t* pin_slot, int32_t* work,
                                 hipStream_t s);
+hipError_t launch_zero_i32(int32_t* a, int64_t count, hipStream_t s);
+hipError_t launch_exclusive_scan(const int32_t* in, int count, int32_t* out, int32_t* sums,
+                                 int32_t* total, hipStream_t s);
+
+// ---- bucketed pin exchange for the wirelength gradient ---------------------
+// Cells are cut into blocks of kXchCells consecutive cells, nets into blocks
+// of whole nets holding at most kXchPinCap pins.  A pin's data moves between
+// the cell side and the net side through a buffer T[num_pins] in "A order"
+// (pins grouped by cell block, then by net block); a net block reads its pins
+// in "B order" (grouped by cell block), so both sides move runs of pins
+// instead of single random words, and every random access happens in LDS.
+constexpr int kXchCells = 4096;        // cells per cell block (32 KiB of float2)
+constexpr int kXchThreads = 512;       // threads of the cell-block kernels
+constexpr int kXchWaThreads = 1024;    // threads of the net-block kernel
+constexpr int kXchPinCap = 9728;       // pins per net block (2 x 76 KiB of float2 in LDS)
+constexpr int kXchPinTarget = 8192;    // nets are grouped by first pin / target
+constexpr int kXchMinTarget = 1024;
+
+struct XchDims {
+  int m = 0, num_nets = 0, num_pins = 0, max_degree = 0;
+  int npt = 0;         // net block k = nets whose first pin lies in [k*npt, (k+1)*npt)
+  int ncb = 0, nnb = 0;   // cell blocks, net blocks
+  size_t index_bytes = 0, work_bytes = 0;
+  // offsets inside the index buffer
+  size_t o_hdr = 0, o_cb = 0, o_nb = 0, o_ab = 0, o_lcsr = 0, o_lc = 0, o_cp = 0, o_qa = 0;
+};
+// Returns FFTPL_OK, or FFTPL_E_UNSUPPORTED when max_degree is too large for
+// a net block, or FFTPL_E_INVAL for negative sizes.
+int xch_dims(int m, int num_nets, int num_pins, int max_degree, XchDims* d);
+
+struct XchIndex {
+  const int32_t* cb_a_ptr = nullptr;    // [ncb+1] A range of each cell block
+  const int32_t* nb_net_ptr = nullptr;  // [nnb+1] first net of each net block
+  const int32_t* a_of_b = nullptr;      // [P] A position of each B-order pin
+  const uint16_t* lcsr = nullptr;       // [P] pin offset inside its net block (B order)
+  const uint16_t* lc = nullptr;         // [P] cell offset inside its cell block (A order)
+  const int32_t* cell_ptr = nullptr;    // [m+1] pins on cells < c
+  const int32_t* qa = nullptr;          // [P] A position of each pin, cell-major
+};
+XchIndex xch_index(const XchDims& d, const void* index);
+
+int xch_build(const XchDims& d, const int32_t* net_ptr, const int32_t* pin_cell, void* index,
+              void* work, hipStream_t s);   // returns fftpl_status; synchronises s
+hipError_t launch_xch_spread(const XchDims& d, const XchIndex& X, const float* x,
+                             const float* y, float2* T, hipStream_t s);
+hipError_t launch_xch_wa(const XchDims& d, const XchIndex& X, const int32_t* net_ptr,
+                         const float* pin_dx, const float* pin_dy, float gamma, float2* T,
+                         double* wa_part, hipStream_t s);
+// g = scale * density gradient + the sum over the cell's pins of T[qa[j]],
+// j in [cell_ptr[c], cell_ptr[c+1]) (one thread per cell; blocks in XCD order
+// so that the T window of a cell block is read by one L2).
+hipError_t launch_gather_xch(const GridF& g, int m, const float* x, const float* y,
+                             const float* w, const float* h, const float* exy,
+                             const float* psi, int grad_mode, float scale,
+                             const int32_t* cell_ptr, const int32_t* qa, const float2* T,
+                             float* gx, float* gy, hipStream_t s);
 
 // Spectral solve.  psi/ex/ey/exy may be null individually.  en_part, if set,
 // receives n/2 per-block partials of the energy sum rho*psi; tau_part, if

@@ -52,30 +52,6 @@ struct PinIO {
   }
 };
 
-// Per-axis sums of one net: S+ = sum e+, T+ = sum (X-M) e+, S-, T- likewise.
-struct AxisSums {
-  float sp, tp, sm, tm;
-};
-
-__device__ __forceinline__ void axis_accum(AxisSums& a, float X, float M, float L,
-                                           float inv_gamma) {
-  float d = X - M, ee = expf(d * inv_gamma);
-  a.sp += ee;
-  a.tp += d * ee;
-  d = X - L;
-  ee = expf(-d * inv_gamma);
-  a.sm += ee;
-  a.tm += d * ee;
-}
-
-// dW~/dX for one pin, given M, L and W+ - M = wp, W- - L = wm, 1/S+, 1/S-.
-__device__ __forceinline__ float axis_grad(float X, float M, float L, float wp, float wm,
-                                           float rsp, float rsm, float inv_gamma) {
-  const float dp = X - M, dm = X - L;
-  return expf(dp * inv_gamma) * rsp * (1.0f + (dp - wp) * inv_gamma) -
-         expf(-dm * inv_gamma) * rsm * (1.0f - (dm - wm) * inv_gamma);
-}
-
 template <bool SLOTS, int PART>   // PART 0: nets of degree <= kSmallDeg; 1: larger nets
 __global__ void __launch_bounds__(256)
     k_wa(int num_nets, const int32_t* __restrict__ net_ptr,
@@ -137,6 +113,8 @@ __global__ void __launch_bounds__(256)
     }
     acc_wa = (double)((mx - lx) + wpx - wmx) + (double)((my - ly) + wpy - wmy);
     acc_hp = (double)(mx - lx) + (double)(my - ly);
+  } else if (SLOTS && PART == 0 && deg == 1) {
+    io.put(p0, 0, 0.0f, 0.0f);   // a one-pin net has no wirelength: its slot holds zero
   }
 
   // Larger nets: the whole wavefront cooperates on each in turn.  This part
@@ -373,9 +351,9 @@ __global__ void __launch_bounds__(1024)
 }
 
 hipError_t launch_eval_finalize(const double* en, int n_en, const double* tau, int n_tau,
-                                const double* wa, int num_nets, double* o_en, double* o_wa,
+                                const double* wa, int n_s, int n_b, double* o_en, double* o_wa,
                                 double* o_hp, double* o_tau, hipStream_t s) {
-  const int n_s = (num_nets + 255) / 256, n_b = wa ? wa_big_grid(num_nets) : 0;
+  if (!wa) n_s = n_b = 0;
   hipLaunchKernelGGL(k_eval_finalize, dim3(1), dim3(1024), 0, s, en, n_en, tau, n_tau, wa,
                      n_s, n_b, o_en, o_wa, o_hp, o_tau);
   return hipGetLastError();
@@ -448,6 +426,31 @@ __global__ void k_pin_slots(int num_pins, const int32_t* __restrict__ pin_cell,
     const int c = pin_cell[p];
     slot[p] = cell_ptr[c] + atomicAdd(&cursor[c], 1);
   }
+}
+
+hipError_t launch_zero_i32(int32_t* a, int64_t count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_i32, dim3(256), dim3(256), 0, s, a, (int)count);
+  return hipGetLastError();
+}
+
+// out[i] = sum in[0..i) for i < count, *total = sum in[0..count); sums needs
+// ceil(count/1024) ints.  in and out may be the same array.
+hipError_t launch_exclusive_scan(const int32_t* in, int count, int32_t* out, int32_t* sums,
+                                 int32_t* total, hipStream_t s) {
+  const int nsb = (count + 1023) / 1024;
+  hipError_t e = hipSuccess;
+  if (count > 0) {
+    hipLaunchKernelGGL(k_scan_blocks, dim3(nsb), dim3(256), 0, s, in, count, out, sums);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(256), 0, s, sums, nsb, total);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (count > 0) {
+    hipLaunchKernelGGL(k_scan_add, dim3((count + 255) / 256), dim3(256), 0, s, out, count, sums);
+    e = hipGetLastError();
+  }
+  return e;
 }
 
 hipError_t launch_netlist_index(int m, int num_pins, const int32_t* pin_cell,

@@ -12,6 +12,7 @@ import ctypes
 import dataclasses
 from typing import Optional
 
+import numpy as np
 import torch
 
 from . import _lib
@@ -237,34 +238,78 @@ def netlist_index(num_cells: int, pin_cell, cell_ptr, pin_slot, stream=None):
     return work
 
 
+def xindex_bytes(num_cells: int, num_nets: int, num_pins: int, max_degree: int):
+    """(index bytes, build scratch bytes) of fftpl_xindex_build."""
+    ib, wb = ctypes.c_uint64(), ctypes.c_uint64()
+    _check(_lib.load().fftpl_xindex_bytes(int(num_cells), int(num_nets), int(num_pins),
+                                          int(max_degree), ctypes.byref(ib), ctypes.byref(wb)),
+           "fftpl_xindex_bytes")
+    return int(ib.value), int(wb.value)
+
+
+def xindex_build(num_cells: int, net_ptr, pin_cell, max_degree: int, index, stream=None):
+    """fftpl_xindex_build into the uint8 device tensor `index` (scratch
+    allocated here and released on return; the call synchronises)."""
+    m = int(num_cells)
+    E = int(net_ptr.numel()) - 1
+    P = int(pin_cell.numel())
+    ib, wb = xindex_bytes(m, E, P, max_degree)
+    if index.numel() < ib:
+        raise FFTPLError(E_INVAL, "fftpl_xindex_build (index tensor too small)")
+    work = torch.empty(max(wb, 1), dtype=torch.uint8, device="cuda")
+    _check(_lib.load().fftpl_xindex_build(
+        m, E, P, _ptr(net_ptr, torch.int32, E + 1, "net_ptr"),
+        _ptr(pin_cell, torch.int32, P, "pin_cell"), int(max_degree),
+        _ptr(index, torch.uint8, None, "index"), int(index.numel()),
+        _ptr(work, torch.uint8, None, "work"), int(work.numel()), _stream(stream)),
+        "fftpl_xindex_build")
+    del work
+
+
+PATHS = ("xch", "slots", "atomic")
+
+
 class Problem:
     """Device-resident static instance (sizes, netlist, fixed maps) and its
     fftpl_problem struct.  ``arrays`` holds the tensors the struct points to.
 
-    With ``fast=True`` (default) the cell-major pin index and the evaluation
-    workspace are built here, which selects the atomic-free evaluation path."""
+    ``path`` selects the evaluation path by what is built here:
+    "xch" (default): the exchange index and the evaluation workspace;
+    "slots": the cell-major pin slots and the workspace;
+    "atomic": nothing (float atomics for the scatter and the wirelength)."""
 
     def __init__(self, grid: Grid, w, h, net_ptr, pin_cell, pin_dx, pin_dy,
-                 base=None, cap=None, fast=True, stream=None):
+                 base=None, cap=None, path="xch", stream=None, max_degree=None):
+        if path not in PATHS:
+            raise ValueError(f"path must be one of {PATHS}")
         self.grid = grid
+        self.path = path
         m = int(w.numel())
         E = int(net_ptr.numel()) - 1
         P = int(pin_cell.numel())
         n2 = grid.n * grid.n
         self.num_cells, self.num_nets, self.num_pins = m, E, P
-        cell_ptr = pin_slot = work = None
-        work_bytes = 0
-        if fast:
+        cell_ptr = pin_slot = work = xindex = None
+        work_bytes = xbytes = 0
+        if max_degree is None:
+            max_degree = int((net_ptr[1:] - net_ptr[:-1]).max().item()) if E > 0 else 0
+        self.max_degree = int(max_degree)
+        if path != "atomic":
+            work_bytes = problem_work_bytes(grid.n, m, E, P)
+            work = torch.empty(max(work_bytes, 1), dtype=torch.uint8, device="cuda")
+        if path == "slots":
             cell_ptr = torch.empty(m + 1, dtype=torch.int32, device="cuda")
             pin_slot = torch.empty(max(P, 1), dtype=torch.int32, device="cuda")
             scratch = netlist_index(m, pin_cell, cell_ptr, pin_slot, stream=stream)
-            work_bytes = problem_work_bytes(grid.n, m, E, P)
-            work = torch.empty(max(work_bytes, 1), dtype=torch.uint8, device="cuda")
             torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
             del scratch
+        elif path == "xch":
+            xbytes, _ = xindex_bytes(m, E, P, self.max_degree)
+            xindex = torch.empty(max(xbytes, 1), dtype=torch.uint8, device="cuda")
+            xindex_build(m, net_ptr, pin_cell, self.max_degree, xindex, stream=stream)
         self.arrays = dict(w=w, h=h, net_ptr=net_ptr, pin_cell=pin_cell,
                            pin_dx=pin_dx, pin_dy=pin_dy, base=base, cap=cap,
-                           cell_ptr=cell_ptr, pin_slot=pin_slot, work=work)
+                           cell_ptr=cell_ptr, pin_slot=pin_slot, work=work, xindex=xindex)
         self.c = _lib.fftpl_problem(
             grid.c(), m, E, P, 0,
             _ptr(w, torch.float32, m, "w"), _ptr(h, torch.float32, m, "h"),
@@ -274,14 +319,15 @@ class Problem:
             _ptr(pin_dx, torch.float32, P, "pin_dx"), _ptr(pin_dy, torch.float32, P, "pin_dy"),
             _ptr(cell_ptr, torch.int32, None, "cell_ptr"),
             _ptr(pin_slot, torch.int32, None, "pin_slot"),
-            _ptr(work, torch.uint8, None, "work"), work_bytes)
+            _ptr(work, torch.uint8, None, "work"), work_bytes,
+            _ptr(xindex, torch.uint8, None, "xindex"), xbytes, self.max_degree, 0)
 
     @property
     def fast(self) -> bool:
-        return self.arrays["work"] is not None
+        return self.path != "atomic"
 
     @classmethod
-    def from_instance(cls, inst, device="cuda", stream=None, fast=True) -> "Problem":
+    def from_instance(cls, inst, device="cuda", stream=None, path="xch") -> "Problem":
         """Upload an instance's static arrays and rasterise its fixed maps."""
         def t(a, dt):
             return torch.as_tensor(a, dtype=dt).to(device).contiguous()
@@ -297,7 +343,8 @@ class Problem:
         return cls(grid, t(inst.w, torch.float32), t(inst.h, torch.float32),
                    t(inst.net_ptr, torch.int32), t(inst.pin_cell, torch.int32),
                    t(inst.pin_dx, torch.float32), t(inst.pin_dy, torch.float32),
-                   base=base, cap=cap, fast=fast, stream=stream)
+                   base=base, cap=cap, path=path, stream=stream,
+                   max_degree=int(np.diff(inst.net_ptr).max()) if inst.num_nets else 0)
 
 
 def eval(plan: Plan, prob: Problem, x, y, lam, gamma, grad_mode, gx, gy, out4,

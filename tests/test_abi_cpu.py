@@ -47,8 +47,10 @@ def test_struct_layouts_match_header():
     from paper_1312_4587_amd import _lib as L
     assert ctypes.sizeof(L.fftpl_grid) == 48
     assert L.fftpl_problem.w.offset == 64
-    assert ctypes.sizeof(L.fftpl_problem) == 64 + 8 * 8 + 4 * 8
+    assert ctypes.sizeof(L.fftpl_problem) == 64 + 8 * 8 + 4 * 8 + 24
     assert L.fftpl_problem.work_bytes.offset == 152
+    assert L.fftpl_problem.xindex.offset == 160
+    assert L.fftpl_problem.max_degree.offset == 176
 
 
 def test_argument_errors_are_reported_before_any_device_work():
@@ -96,5 +98,22 @@ def test_argument_errors_are_reported_before_any_device_work():
     assert lib.fftpl_poisson_solve(None, ctypes.byref(g), p, p, None, None, None,
                                    None) == -1
     assert lib.fftpl_debug_cell_bins(ctypes.byref(g), 4, p, p, p, p, None, None) == -1
+    u64 = ctypes.c_uint64
+    ib, wb = u64(), u64()
+    assert lib.fftpl_xindex_bytes(10, 3, 6, 2, None, ctypes.byref(wb)) == -1
+    assert lib.fftpl_xindex_bytes(-1, 3, 6, 2, ctypes.byref(ib), ctypes.byref(wb)) == -1
+    assert lib.fftpl_xindex_bytes(10, 3, 6, 8706, ctypes.byref(ib), ctypes.byref(wb)) == -4
+    assert lib.fftpl_xindex_bytes(10, 3, 6, 2, ctypes.byref(ib), ctypes.byref(wb)) == 0
+    assert ib.value > 0 and wb.value > 0
+    # too small buffers, missing arrays, pins without cells: rejected on the host
+    assert lib.fftpl_xindex_build(10, 3, 6, p, p, 2, p, ib.value - 1, p, wb.value,
+                                  None) == -1
+    assert lib.fftpl_xindex_build(10, 3, 6, p, p, 2, p, ib.value, p, wb.value - 1,
+                                  None) == -1
+    assert lib.fftpl_xindex_build(10, 3, 6, None, p, 2, p, ib.value, p, wb.value,
+                                  None) == -1
+    assert lib.fftpl_xindex_build(0, 3, 6, p, p, 2, p, ib.value, p, wb.value, None) == -1
+    assert lib.fftpl_xindex_build(10, 3, 6, p, p, 8706, p, ib.value, p, wb.value,
+                                  None) == -4
     assert lib.fftpl_plan_destroy(None) == 0
     assert lib.fftpl_plan_info(None, None, None) == -1

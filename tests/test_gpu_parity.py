@@ -281,10 +281,10 @@ def test_wa_grad(F, which):
 # full evaluation
 # ---------------------------------------------------------------------------
 
-def _run_eval(F, inst, lam, mode, dct="fft", plan=None, fast=True):
+def _run_eval(F, inst, lam, mode, dct="fft", plan=None, path="xch"):
     import torch
-    prob = F.Problem.from_instance(inst, fast=fast)
-    assert prob.fast == fast
+    prob = F.Problem.from_instance(inst, path=path)
+    assert prob.path == path
     own = plan is None
     plan = plan or F.Plan(inst.n, dct)
     c = DeviceCells(inst)
@@ -319,14 +319,14 @@ def _check_eval(inst, got, ref, lam, mode):
     assert rel_l2(got["gx"], ref["gx"]) < RTOL and rel_l2(got["gy"], ref["gy"]) < RTOL
 
 
-@pytest.mark.parametrize("fast", [True, False])
+@pytest.mark.parametrize("path", ["xch", "slots", "atomic"])
 @pytest.mark.parametrize("mode", ["field", "exact"])
-def test_eval_small(F, mode, fast):
+def test_eval_small(F, mode, path):
     inst = gen.make_config("small_2k")
     inst = with_macros(inst, [[30.0, 30.0, 10.0, 8.0], [60.0, 20.0, 5.0, 12.0]])
     lam = 3.0
-    say("eval small", mode, "fast" if fast else "atomic")
-    got = _run_eval(F, inst, lam, mode, fast=fast)
+    say("eval small", mode, path)
+    got = _run_eval(F, inst, lam, mode, path=path)
     ref = oracle.evaluate(inst, lam=lam, grad_mode=mode)
     _check_eval(inst, got, ref, lam, mode)
 
@@ -345,16 +345,16 @@ def test_eval_edge_cases(F):
     import torch
     # no cells and no nets at the smallest grid
     inst = hand_instance(np.zeros((0, 4)), n=8)
-    for fast in (True, False):
-        got = _run_eval(F, inst, 1.0, "field", fast=fast)
+    for path in ("xch", "slots", "atomic"):
+        got = _run_eval(F, inst, 1.0, "field", path=path)
         assert np.all(got["out"] == 0.0) and np.all(got["rho"] == 0.0)
     # cells partly and fully outside the region, exact mode, n = 8
     inst = hand_instance([[0.25, 2.0, 1.5, 1.0], [7.9, 7.9, 1.0, 3.0], [-5, -5, 1, 1],
                           [4, 4, 0.25, 0.25], [3.3, 5.1, 2.0, 1.0]], n=8,
                          nets=[[(0, 0, 0), (1, 0.1, 0)], [(2, 0, 0), (3, 0, 0), (4, 0, 0)]])
     for mode in ("field", "exact"):
-        for fast in (True, False):
-            got = _run_eval(F, inst, 2.0, mode, fast=fast)
+        for path in ("xch", "slots", "atomic"):
+            got = _run_eval(F, inst, 2.0, mode, path=path)
             ref = oracle.evaluate(inst, lam=2.0, grad_mode=mode)
             _check_eval(inst, got, ref, 2.0, mode)
     # a plan of another size is refused
@@ -409,7 +409,7 @@ def test_banded_scatter_with_tall_and_outside_cells(F, n):
     inst = hand_instance(cells, n=n, bin_size=side / n, nets=nets)
     inst = with_macros(inst, [[50.0, 50.0, 10.0, 30.0]])
     say("band scatter", n)
-    got = _run_eval(F, inst, 1.0, "field", fast=True)
+    got = _run_eval(F, inst, 1.0, "field")
     ref = oracle.evaluate(inst, lam=1.0, grad_mode="field")
     _check_eval(inst, got, ref, 1.0, "field")
 
