@@ -116,7 +116,7 @@ def kernel_bytes(inst, nent):
         # exchange path: u16 cell offsets and float2 pin records in A order,
         # int32 A positions and u16 CSR offsets in B order
         "k_xch_spread": 8 * m + 2 * P + 8 * P,
-        "k_xch_wa": 4 * P + 2 * P + 8 * P + 8 * P + 8 * P + 4 * (E + 1),
+        "k_xch_wa": 4 * P + 2 * P + 8 * P + 8 * P + 8 * P + 4 * (E + 1) + 2 * E,
         "k_gather_xch": 16 * m + 8 * n2 + 4 * (m + 1) + 4 * P + 8 * P + 8 * m,
         "k_eval_finalize": 0,
     }

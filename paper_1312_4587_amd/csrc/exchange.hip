@@ -42,7 +42,10 @@ constexpr int kHdrInts = 16;
 constexpr int32_t kXchMagic = 0x46584348;   // "FXCH"
 constexpr int kSmall = 8;                   // degree handled by one thread
 constexpr int NW = kXchWaThreads;
-constexpr int kStage = (kXchPinCap + NW - 1) / NW;   // B positions per thread in wa
+// B positions per thread of the net-block kernel: for blocks of up to
+// kXchPinLds2 pins, or up to kXchPinCap
+constexpr int kStageS = (kXchPinLds2 + NW - 1) / NW;
+constexpr int kStageL = (kXchPinCap + NW - 1) / NW;
 
 inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
@@ -50,8 +53,14 @@ inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 int xch_dims(int m, int num_nets, int num_pins, int max_degree, XchDims* d) {
   if (m < 0 || num_nets < 0 || num_pins < 0 || max_degree < 0) return FFTPL_E_INVAL;
+  // the largest block that still fits twice in one CU's LDS; failing that
+  // (very large nets) one block per CU
   int npt = kXchPinTarget;
-  if (npt > kXchPinCap + 1 - max_degree) npt = kXchPinCap + 1 - max_degree;
+  if (npt > kXchPinLds2 + 1 - max_degree) npt = kXchPinLds2 + 1 - max_degree;
+  if (npt < kXchMinTarget) {
+    npt = kXchPinTarget;
+    if (npt > kXchPinCap + 1 - max_degree) npt = kXchPinCap + 1 - max_degree;
+  }
   if (npt < kXchMinTarget) return FFTPL_E_UNSUPPORTED;
   XchDims r;
   r.m = m;
@@ -59,6 +68,7 @@ int xch_dims(int m, int num_nets, int num_pins, int max_degree, XchDims* d) {
   r.num_pins = num_pins;
   r.max_degree = max_degree;
   r.npt = npt;
+  r.cap = max_degree > 0 ? npt - 1 + max_degree : 1;
   r.ncb = (m + kXchCells - 1) / kXchCells;
   r.nnb = num_pins > 0 ? (num_pins + npt - 1) / npt : 1;
   size_t off = 0;
@@ -78,6 +88,8 @@ int xch_dims(int m, int num_nets, int num_pins, int max_degree, XchDims* d) {
   off = align256(off + sizeof(int32_t) * ((size_t)m + 1));
   r.o_qa = off;
   off = align256(off + sizeof(int32_t) * (size_t)num_pins);
+  r.o_ns = off;
+  off = align256(off + sizeof(uint16_t) * (size_t)num_nets);
   r.index_bytes = off;
   // build workspace: counts / cursors, A starts, transposed counts, B starts,
   // scan block sums, flag and scan totals
@@ -103,6 +115,7 @@ XchIndex xch_index(const XchDims& d, const void* index) {
   X.lc = reinterpret_cast<const uint16_t*>(b + d.o_lc);
   X.cell_ptr = reinterpret_cast<const int32_t*>(b + d.o_cp);
   X.qa = reinterpret_cast<const int32_t*>(b + d.o_qa);
+  X.nsort = reinterpret_cast<const uint16_t*>(b + d.o_ns);
   return X;
 }
 
@@ -183,6 +196,35 @@ __global__ void __launch_bounds__(256)
       lc[a] = (uint16_t)(c - cb * kXchCells);
       qa[pin_slot[p]] = a;
     }
+  }
+}
+
+// Per net block, its nets in order of degree class min(degree, 9) (0, 1, 2,
+// ..., 8, larger), as offsets from the block's first net; the order inside a
+// class is arbitrary.  A wavefront walking this order sees nets of equal
+// degree together, so its loops over pins run the length of the degree.
+__global__ void __launch_bounds__(256)
+    k_xi_netsort(const int32_t* __restrict__ net_ptr, const int32_t* __restrict__ nb_net_ptr,
+                 uint16_t* __restrict__ nsort) {
+  __shared__ int cnt[kXchBuckets], cur[kXchBuckets];
+  const int k = blockIdx.x, t = threadIdx.x;
+  const int e0 = nb_net_ptr[k], e1 = nb_net_ptr[k + 1];
+  if (t < kXchBuckets) cnt[t] = 0;
+  __syncthreads();
+  for (int e = e0 + t; e < e1; e += blockDim.x)
+    atomicAdd(&cnt[min(net_ptr[e + 1] - net_ptr[e], kXchBuckets - 1)], 1);
+  __syncthreads();
+  if (t == 0) {
+    int run = 0;
+    for (int b = 0; b < kXchBuckets; ++b) {
+      cur[b] = run;
+      run += cnt[b];
+    }
+  }
+  __syncthreads();
+  for (int e = e0 + t; e < e1; e += blockDim.x) {
+    const int b = min(net_ptr[e + 1] - net_ptr[e], kXchBuckets - 1);
+    nsort[e0 + atomicAdd(&cur[b], 1)] = (uint16_t)(e - e0);
   }
 }
 
@@ -289,6 +331,11 @@ int xch_build(const XchDims& d, const int32_t* net_ptr, const int32_t* pin_cell,
                        a_of_b, lcsr, lc, pin_slot, qa, flag);
     e = hipGetLastError();
   }
+  if (e == hipSuccess) {
+    uint16_t* nsort = reinterpret_cast<uint16_t*>(ib + d.o_ns);
+    hipLaunchKernelGGL(k_xi_netsort, dim3(d.nnb), dim3(256), 0, s, net_ptr, nb_net_ptr, nsort);
+    e = hipGetLastError();
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   return e == hipSuccess ? FFTPL_OK : FFTPL_E_DEVICE;
 }
@@ -298,13 +345,15 @@ int xch_build(const XchDims& d, const int32_t* net_ptr, const int32_t* pin_cell,
 // ---------------------------------------------------------------------------
 namespace {
 
-// T[a] = (x, y) of pin a's cell, over the block's A range.
+// T[a] = (x, y) of pin a's cell, over part blockIdx.x % kXchSpreadSplit of
+// the A range of cell block blockIdx.x / kXchSpreadSplit.
 __global__ void __launch_bounds__(NT)
     k_xch_spread(int m, const int32_t* __restrict__ cb_a_ptr, const uint16_t* __restrict__ lc,
                  const float* __restrict__ x, const float* __restrict__ y,
                  float2* __restrict__ T) {
   __shared__ float2 win[kXchCells];
-  const int cb = blockIdx.x, t = threadIdx.x;
+  const int cb = blockIdx.x / kXchSpreadSplit, part = blockIdx.x % kXchSpreadSplit;
+  const int t = threadIdx.x;
   const int c0 = cb * kXchCells;
   const int nc = min(kXchCells, m - c0);
   {
@@ -321,7 +370,9 @@ __global__ void __launch_bounds__(NT)
       if (t + k * NT < nc) win[t + k * NT] = make_float2(xv[k], yv[k]);
   }
   __syncthreads();
-  const int a0 = cb_a_ptr[cb], a1 = cb_a_ptr[cb + 1];
+  const int b0 = cb_a_ptr[cb], b1 = cb_a_ptr[cb + 1];
+  const int len = (b1 - b0 + kXchSpreadSplit - 1) / kXchSpreadSplit;
+  const int a0 = b0 + part * len, a1 = min(b1, a0 + len);
   // loads of one batch are unconditional (clamped index) so they are all in
   // flight together; only the stores are masked
   constexpr int U = 8;
@@ -335,161 +386,260 @@ __global__ void __launch_bounds__(NT)
   }
 }
 
+// Weighted-average terms of one axis with the exponentials computed once:
+// e+ = exp((X - M)/gamma), e- = exp((L - X)/gamma) (fast exp2-based exp: the
+// arguments are <= 0 and the terms that matter are near 0).
+__device__ __forceinline__ float fexp(float v) { return __expf(v); }
+
 // One net block: cell positions and pin offsets staged in LDS in CSR order,
 // nets evaluated from LDS, gradients written back over the pins' positions in
-// T.
+// T.  LDS: pos[cap], off[cap] (dynamic, 16 bytes per pin of the block).
+template <int STAGE>
 __global__ void __launch_bounds__(NW)
-    k_xch_wa(int num_pins, const int32_t* __restrict__ net_ptr,
-             const int32_t* __restrict__ nb_net_ptr, const int32_t* __restrict__ a_of_b,
-             const uint16_t* __restrict__ lcsr, const float* __restrict__ pin_dx,
-             const float* __restrict__ pin_dy, float inv_gamma, float2* __restrict__ T,
-             double* __restrict__ part) {
-  __shared__ float2 pos[kXchPinCap];
-  __shared__ float2 off[kXchPinCap];
+    k_xch_wa(int num_pins, int cap, const int32_t* __restrict__ net_ptr,
+             const int32_t* __restrict__ nb_net_ptr, const uint16_t* __restrict__ nsort,
+             const int32_t* __restrict__ a_of_b, const uint16_t* __restrict__ lcsr,
+             const float* __restrict__ pin_dx, const float* __restrict__ pin_dy,
+             float inv_gamma, float2* __restrict__ T, double* __restrict__ part) {
+  extern __shared__ float2 smem[];
+  float2* pos = smem;
+  float2* off = smem + cap;
   const int k = blockIdx.x, t = threadIdx.x, nblk = gridDim.x;
   const int lane = t & (kWave - 1), wv = t / kWave;
   const int e0 = nb_net_ptr[k], e1 = nb_net_ptr[k + 1];
   const int p0 = net_ptr[e0], p1 = net_ptr[e1];
   const int np = p1 - p0;
   double acc_wa = 0.0, acc_hp = 0.0;
-  if (np > 0 && np <= kXchPinCap) {
+  if (np > 0 && np <= cap && np <= STAGE * NW) {
     // 1. stage: off[csr offset] = pin offset (coalesced), pos[csr offset] =
-    // cell position read from T in B order (runs of consecutive A positions)
-    // loads unconditional (index clamped into the block) so that each batch
-    // is in flight at once; only the LDS stores are masked
-    int av[kStage], lv[kStage];
-    float dx[kStage], dy[kStage];
-    const int blast = p1 - 1;
+    // cell position read from T in B order (runs of consecutive A positions).
+    // Loads are unconditional (index clamped into the block) so that each
+    // batch is in flight at once; only the LDS stores are masked.
+    int av[STAGE], lv[STAGE];
+    {
+      float dx[STAGE], dy[STAGE];
+      const int blast = p1 - 1;
 #pragma unroll
-    for (int j = 0; j < kStage; ++j) {
-      const int b = max(min(p0 + t + j * NW, blast), 0);
-      av[j] = a_of_b[b];
-      lv[j] = lcsr[b];
-      dx[j] = pin_dx[b];
-      dy[j] = pin_dy[b];
-    }
+      for (int j = 0; j < STAGE; ++j) {
+        const int b = min(p0 + t + j * NW, blast);
+        av[j] = a_of_b[b];
+        lv[j] = lcsr[b];
+        dx[j] = pin_dx[b];
+        dy[j] = pin_dy[b];
+      }
 #pragma unroll
-    for (int j = 0; j < kStage; ++j) {
-      av[j] = min((unsigned)av[j], (unsigned)(num_pins - 1));
-      lv[j] = min(lv[j], kXchPinCap - 1);
-    }
-    float2 q[kStage];
+      for (int j = 0; j < STAGE; ++j) {
+        av[j] = min((unsigned)av[j], (unsigned)(num_pins - 1));
+        lv[j] = min(lv[j], cap - 1);
+      }
+      float2 q[STAGE];
 #pragma unroll
-    for (int j = 0; j < kStage; ++j) q[j] = T[av[j]];
+      for (int j = 0; j < STAGE; ++j) q[j] = T[av[j]];
 #pragma unroll
-    for (int j = 0; j < kStage; ++j) {
-      if (p0 + t + j * NW < p1) {
-        off[t + j * NW] = make_float2(dx[j], dy[j]);
-        pos[lv[j]] = q[j];
+      for (int j = 0; j < STAGE; ++j) {
+        if (p0 + t + j * NW < p1) {
+          off[t + j * NW] = make_float2(dx[j], dy[j]);
+          pos[lv[j]] = q[j];
+        }
       }
     }
     __syncthreads();
 
-    // 2. nets, walked in chunks of kWave consecutive nets per wavefront (the
-    // next chunk's pointers are loaded before the current chunk is done):
-    // larger nets by the whole wavefront, three passes over the pins in LDS
-    // (pass 1 turns positions into pin coordinates relative to the first
-    // pin's cell, pass 3 overwrites them with the gradient); nets of degree
-    // <= kSmall by one lane each.
-    int e = e0 + wv * kWave + lane;
-    int c0 = 0, c1 = 0;
-    if (e < e1) {
-      c0 = net_ptr[e];
-      c1 = net_ptr[e + 1];
-    }
-    for (int base = e0 + wv * kWave; base < e1; base += NW, e += NW) {
-      int n0 = 0, n1 = 0;
-      if (e + NW < e1) {
-        n0 = net_ptr[e + NW];
-        n1 = net_ptr[e + NW + 1];
+    // 2. nets in degree order.  Nets above kSmall sit at the tail of the
+    // order; wavefront w takes the tail's nets w, w + 8, ... (one wavefront
+    // per net, three passes over its pins in LDS: pass 1 turns positions into
+    // pin coordinates relative to the first pin's cell, pass 3 overwrites
+    // them with the gradient).  The others: one lane per net, a wavefront per
+    // chunk of kWave nets of (nearly) equal degree, loops as long as the
+    // chunk's largest degree; the next chunk's pointers are loaded before the
+    // current chunk is done.
+    const int nn = e1 - e0;
+    constexpr int NWV = NW / kWave;
+    for (int bi = nn - 1 - wv;; bi -= NWV) {
+      if (bi < 0) break;
+      const int e = e0 + nsort[e0 + bi];
+      const int q0 = net_ptr[e], q1 = net_ptr[e + 1];
+      if (q1 - q0 <= kSmall) break;   // the rest of this wavefront's tail is small
+      const int b0 = q0 - p0, b1 = q1 - p0;
+      const float2 r = pos[b0];
+      wave_lds_sync();
+      constexpr int H = 4;   // pins per lane whose LDS loads are issued together
+      float mx = -INFINITY, lx = INFINITY, my = -INFINITY, ly = INFINITY;
+      for (int l = b0 + lane; l < b1; l += H * kWave) {
+        float2 c[H], d[H];
+#pragma unroll
+        for (int u = 0; u < H; ++u) {
+          const int li = min(l + u * kWave, b1 - 1);
+          c[u] = pos[li];
+          d[u] = off[li];
+        }
+#pragma unroll
+        for (int u = 0; u < H; ++u) {
+          if (l + u * kWave < b1) {
+            const float X = (c[u].x - r.x) + d[u].x, Y = (c[u].y - r.y) + d[u].y;
+            pos[l + u * kWave] = make_float2(X, Y);
+            mx = fmaxf(mx, X);
+            lx = fminf(lx, X);
+            my = fmaxf(my, Y);
+            ly = fminf(ly, Y);
+          }
+        }
       }
-      unsigned long long big = __ballot(c1 - c0 > kSmall);
-      while (big) {
-        const int src = __ffsll((long long)big) - 1;
-        big &= big - 1;
-        const int b0 = __shfl(c0, src, kWave) - p0, b1 = __shfl(c1, src, kWave) - p0;
-        const float2 r = pos[b0];
-        wave_lds_sync();
+      mx = wave_max_dpp(mx);
+      lx = wave_min_dpp(lx);
+      my = wave_max_dpp(my);
+      ly = wave_min_dpp(ly);
+      wave_lds_sync();
+      float spx = 0.f, tpx = 0.f, smx = 0.f, tmx = 0.f;
+      float spy = 0.f, tpy = 0.f, smy = 0.f, tmy = 0.f;
+      for (int l = b0 + lane; l < b1; l += H * kWave) {
+        float2 c[H];
+#pragma unroll
+        for (int u = 0; u < H; ++u) c[u] = pos[min(l + u * kWave, b1 - 1)];
+#pragma unroll
+        for (int u = 0; u < H; ++u) {
+          if (l + u * kWave < b1) {
+            float dd = c[u].x - mx, ee = fexp(dd * inv_gamma);
+            spx += ee;
+            tpx += dd * ee;
+            dd = c[u].x - lx;
+            ee = fexp(-dd * inv_gamma);
+            smx += ee;
+            tmx += dd * ee;
+            dd = c[u].y - my;
+            ee = fexp(dd * inv_gamma);
+            spy += ee;
+            tpy += dd * ee;
+            dd = c[u].y - ly;
+            ee = fexp(-dd * inv_gamma);
+            smy += ee;
+            tmy += dd * ee;
+          }
+        }
+      }
+      spx = wave_sum_dpp(spx);
+      tpx = wave_sum_dpp(tpx);
+      smx = wave_sum_dpp(smx);
+      tmx = wave_sum_dpp(tmx);
+      spy = wave_sum_dpp(spy);
+      tpy = wave_sum_dpp(tpy);
+      smy = wave_sum_dpp(smy);
+      tmy = wave_sum_dpp(tmy);
+      const float rspx = 1.0f / spx, rsmx = 1.0f / smx;
+      const float rspy = 1.0f / spy, rsmy = 1.0f / smy;
+      const float wpx = tpx * rspx, wmx = tmx * rsmx;
+      const float wpy = tpy * rspy, wmy = tmy * rsmy;
+      for (int l = b0 + lane; l < b1; l += H * kWave) {
+        float2 c[H];
+#pragma unroll
+        for (int u = 0; u < H; ++u) c[u] = pos[min(l + u * kWave, b1 - 1)];
+#pragma unroll
+        for (int u = 0; u < H; ++u) {
+          if (l + u * kWave < b1) {
+            const float dpx = c[u].x - mx, dmx = c[u].x - lx;
+            const float dpy = c[u].y - my, dmy = c[u].y - ly;
+            pos[l + u * kWave] = make_float2(
+                fexp(dpx * inv_gamma) * rspx * (1.0f + (dpx - wpx) * inv_gamma) -
+                    fexp(-dmx * inv_gamma) * rsmx * (1.0f - (dmx - wmx) * inv_gamma),
+                fexp(dpy * inv_gamma) * rspy * (1.0f + (dpy - wpy) * inv_gamma) -
+                    fexp(-dmy * inv_gamma) * rsmy * (1.0f - (dmy - wmy) * inv_gamma));
+          }
+        }
+      }
+      if (lane == 0) {
+        acc_wa += (double)((mx - lx) + wpx - wmx) + (double)((my - ly) + wpy - wmy);
+        acc_hp += (double)(mx - lx) + (double)(my - ly);
+      }
+    }
+
+    int c0 = 0, c1 = 0;
+    {
+      const int li = wv * kWave + lane;
+      if (li < nn) {
+        const int e = e0 + nsort[e0 + li];
+        c0 = net_ptr[e];
+        c1 = net_ptr[e + 1];
+      }
+    }
+    for (int base = wv * kWave; base < nn; base += NW) {
+      int n0 = 0, n1 = 0;
+      {
+        const int li = base + NW + lane;
+        if (li < nn) {
+          const int e = e0 + nsort[e0 + li];
+          n0 = net_ptr[e];
+          n1 = net_ptr[e + 1];
+        }
+      }
+      int deg = c1 - c0;
+      if (deg > kSmall) deg = 0;   // done above
+      const int l0 = c0 - p0;
+      // the chunk's largest small degree, uniform across the wavefront
+      const int wdeg = wave_max_dpp_i(deg);
+      if (deg == 1) pos[l0] = make_float2(0.0f, 0.0f);
+      if (wdeg >= 2) {
+        float px[kSmall], py[kSmall];
+        const float2 r = pos[deg >= 1 ? l0 : 0];
         float mx = -INFINITY, lx = INFINITY, my = -INFINITY, ly = INFINITY;
-        for (int l = b0 + lane; l < b1; l += kWave) {
-          const float2 c = pos[l], d = off[l];
-          const float X = (c.x - r.x) + d.x, Y = (c.y - r.y) + d.y;
-          pos[l] = make_float2(X, Y);
-          mx = fmaxf(mx, X);
-          lx = fminf(lx, X);
-          my = fmaxf(my, Y);
-          ly = fminf(ly, Y);
+#pragma unroll
+        for (int j = 0; j < kSmall; ++j) {
+          if (j < wdeg) {
+            px[j] = 0.0f;
+            py[j] = 0.0f;
+            if (j < deg) {
+              const float2 c = pos[l0 + j], d = off[l0 + j];
+              px[j] = (c.x - r.x) + d.x;
+              py[j] = (c.y - r.y) + d.y;
+              mx = fmaxf(mx, px[j]);
+              lx = fminf(lx, px[j]);
+              my = fmaxf(my, py[j]);
+              ly = fminf(ly, py[j]);
+            }
+          }
         }
-        mx = wave_max(mx);
-        lx = wave_min(lx);
-        my = wave_max(my);
-        ly = wave_min(ly);
-        AxisSums sx = {0.f, 0.f, 0.f, 0.f}, sy = {0.f, 0.f, 0.f, 0.f};
-        for (int l = b0 + lane; l < b1; l += kWave) {
-          const float2 c = pos[l];
-          axis_accum(sx, c.x, mx, lx, inv_gamma);
-          axis_accum(sy, c.y, my, ly, inv_gamma);
+        float epx[kSmall], emx[kSmall], epy[kSmall], emy[kSmall];
+        float spx = 0.f, tpx = 0.f, smx = 0.f, tmx = 0.f;
+        float spy = 0.f, tpy = 0.f, smy = 0.f, tmy = 0.f;
+#pragma unroll
+        for (int j = 0; j < kSmall; ++j) {
+          if (j < wdeg) {
+            const bool in = j < deg;
+            const float dpx = px[j] - mx, dmx = px[j] - lx;
+            const float dpy = py[j] - my, dmy = py[j] - ly;
+            epx[j] = in ? fexp(dpx * inv_gamma) : 0.0f;
+            emx[j] = in ? fexp(-dmx * inv_gamma) : 0.0f;
+            epy[j] = in ? fexp(dpy * inv_gamma) : 0.0f;
+            emy[j] = in ? fexp(-dmy * inv_gamma) : 0.0f;
+            spx += epx[j];
+            tpx += dpx * epx[j];
+            smx += emx[j];
+            tmx += dmx * emx[j];
+            spy += epy[j];
+            tpy += dpy * epy[j];
+            smy += emy[j];
+            tmy += dmy * emy[j];
+          }
         }
-        sx.sp = wave_sum(sx.sp);
-        sx.tp = wave_sum(sx.tp);
-        sx.sm = wave_sum(sx.sm);
-        sx.tm = wave_sum(sx.tm);
-        sy.sp = wave_sum(sy.sp);
-        sy.tp = wave_sum(sy.tp);
-        sy.sm = wave_sum(sy.sm);
-        sy.tm = wave_sum(sy.tm);
-        const float wpx = sx.tp / sx.sp, wmx = sx.tm / sx.sm;
-        const float wpy = sy.tp / sy.sp, wmy = sy.tm / sy.sm;
-        const float rspx = 1.0f / sx.sp, rsmx = 1.0f / sx.sm;
-        const float rspy = 1.0f / sy.sp, rsmy = 1.0f / sy.sm;
-        for (int l = b0 + lane; l < b1; l += kWave) {
-          const float2 c = pos[l];
-          pos[l] = make_float2(axis_grad(c.x, mx, lx, wpx, wmx, rspx, rsmx, inv_gamma),
-                               axis_grad(c.y, my, ly, wpy, wmy, rspy, rsmy, inv_gamma));
-        }
-        if (lane == src) {
+        if (deg >= 2) {
+          const float rspx = 1.0f / spx, rsmx = 1.0f / smx;
+          const float rspy = 1.0f / spy, rsmy = 1.0f / smy;
+          const float wpx = tpx * rspx, wmx = tmx * rsmx;
+          const float wpy = tpy * rspy, wmy = tmy * rsmy;
+#pragma unroll
+          for (int j = 0; j < kSmall; ++j) {
+            if (j < wdeg && j < deg) {
+              const float dpx = px[j] - mx, dmx = px[j] - lx;
+              const float dpy = py[j] - my, dmy = py[j] - ly;
+              pos[l0 + j] = make_float2(
+                  epx[j] * rspx * (1.0f + (dpx - wpx) * inv_gamma) -
+                      emx[j] * rsmx * (1.0f - (dmx - wmx) * inv_gamma),
+                  epy[j] * rspy * (1.0f + (dpy - wpy) * inv_gamma) -
+                      emy[j] * rsmy * (1.0f - (dmy - wmy) * inv_gamma));
+            }
+          }
           acc_wa += (double)((mx - lx) + wpx - wmx) + (double)((my - ly) + wpy - wmy);
           acc_hp += (double)(mx - lx) + (double)(my - ly);
         }
-      }
-      const int deg = c1 - c0, l0 = c0 - p0;
-      if (deg == 1) {
-        pos[l0] = make_float2(0.0f, 0.0f);
-      } else if (deg >= 2 && deg <= kSmall) {
-        float px[kSmall], py[kSmall];
-        const float2 r = pos[l0];
-        float mx = -INFINITY, lx = INFINITY, my = -INFINITY, ly = INFINITY;
-#pragma unroll
-        for (int j = 0; j < kSmall; ++j) {
-          if (j < deg) {
-            const float2 c = pos[l0 + j], d = off[l0 + j];
-            px[j] = (c.x - r.x) + d.x;
-            py[j] = (c.y - r.y) + d.y;
-            mx = fmaxf(mx, px[j]);
-            lx = fminf(lx, px[j]);
-            my = fmaxf(my, py[j]);
-            ly = fminf(ly, py[j]);
-          }
-        }
-        AxisSums sx = {0.f, 0.f, 0.f, 0.f}, sy = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int j = 0; j < kSmall; ++j) {
-          if (j < deg) {
-            axis_accum(sx, px[j], mx, lx, inv_gamma);
-            axis_accum(sy, py[j], my, ly, inv_gamma);
-          }
-        }
-        const float wpx = sx.tp / sx.sp, wmx = sx.tm / sx.sm;
-        const float wpy = sy.tp / sy.sp, wmy = sy.tm / sy.sm;
-        const float rspx = 1.0f / sx.sp, rsmx = 1.0f / sx.sm;
-        const float rspy = 1.0f / sy.sp, rsmy = 1.0f / sy.sm;
-#pragma unroll
-        for (int j = 0; j < kSmall; ++j)
-          if (j < deg)
-            pos[l0 + j] = make_float2(axis_grad(px[j], mx, lx, wpx, wmx, rspx, rsmx, inv_gamma),
-                                      axis_grad(py[j], my, ly, wpy, wmy, rspy, rsmy, inv_gamma));
-        acc_wa += (double)((mx - lx) + wpx - wmx) + (double)((my - ly) + wpy - wmy);
-        acc_hp += (double)(mx - lx) + (double)(my - ly);
       }
       c0 = n0;
       c1 = n1;
@@ -498,7 +648,7 @@ __global__ void __launch_bounds__(NW)
 
     // 3. gradients back to the pins' A positions
 #pragma unroll
-    for (int j = 0; j < kStage; ++j)
+    for (int j = 0; j < STAGE; ++j)
       if (p0 + t + j * NW < p1) T[av[j]] = pos[lv[j]];
   }
   block_sum_to<false>(acc_wa, &part[k]);
@@ -510,16 +660,33 @@ __global__ void __launch_bounds__(NW)
 hipError_t launch_xch_spread(const XchDims& d, const XchIndex& X, const float* x,
                              const float* y, float2* T, hipStream_t s) {
   if (d.ncb <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_xch_spread, dim3(d.ncb), dim3(NT), 0, s, d.m, X.cb_a_ptr, X.lc, x, y,
-                     T);
+  hipLaunchKernelGGL(k_xch_spread, dim3(d.ncb * kXchSpreadSplit), dim3(NT), 0, s, d.m,
+                     X.cb_a_ptr, X.lc, x, y, T);
   return hipGetLastError();
 }
 
 hipError_t launch_xch_wa(const XchDims& d, const XchIndex& X, const int32_t* net_ptr,
                          const float* pin_dx, const float* pin_dy, float gamma, float2* T,
                          double* wa_part, hipStream_t s) {
-  hipLaunchKernelGGL(k_xch_wa, dim3(d.nnb), dim3(NW), 0, s, d.num_pins, net_ptr, X.nb_net_ptr,
-                     X.a_of_b, X.lcsr, pin_dx, pin_dy, 1.0f / gamma, T, wa_part);
+  const size_t lds = sizeof(float2) * 2 * (size_t)d.cap;
+  if (d.cap <= kXchPinLds2) {
+    hipLaunchKernelGGL((k_xch_wa<kStageS>), dim3(d.nnb), dim3(NW), lds, s, d.num_pins, d.cap,
+                       net_ptr, X.nb_net_ptr, X.nsort, X.a_of_b, X.lcsr, pin_dx, pin_dy,
+                       1.0f / gamma, T, wa_part);
+  } else {
+    // more than 64 KiB of dynamic LDS has to be allowed explicitly
+    static bool attr = false;
+    if (!attr) {
+      hipError_t e = hipFuncSetAttribute(
+          reinterpret_cast<const void*>(&k_xch_wa<kStageL>),
+          hipFuncAttributeMaxDynamicSharedMemorySize, (int)(sizeof(float2) * 2 * kXchPinCap));
+      if (e != hipSuccess) return e;
+      attr = true;
+    }
+    hipLaunchKernelGGL((k_xch_wa<kStageL>), dim3(d.nnb), dim3(NW), lds, s, d.num_pins, d.cap,
+                       net_ptr, X.nb_net_ptr, X.nsort, X.a_of_b, X.lcsr, pin_dx, pin_dy,
+                       1.0f / gamma, T, wa_part);
+  }
   return hipGetLastError();
 }
 

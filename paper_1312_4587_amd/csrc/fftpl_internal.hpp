@@ -166,6 +166,64 @@ __device__ __forceinline__ float wave_min(float v) {
   return v;
 }
 
+// Wave-wide reductions on the DPP path (no LDS round trips): a butterfly
+// inside each row of 16 lanes (row rotations by 8 and 4, then two quad
+// permutations) leaves every lane holding its row's result; the four row
+// results are combined in a fixed order from lanes 0, 16, 32 and 48.  The
+// result is wave-uniform.  Every lane of the wave must be active.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __builtin_bit_cast(
+      float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+constexpr int kDppRowRor8 = 0x128, kDppRowRor4 = 0x124, kDppQuad2301 = 0x4e,
+              kDppQuad1032 = 0xb1;
+
+__device__ __forceinline__ float rows4_f(float v, int op) {
+  const float a = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 0));
+  const float b = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 16));
+  const float c = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 32));
+  const float d = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 48));
+  if (op == 0) return (a + b) + (c + d);
+  if (op == 1) return fmaxf(fmaxf(a, b), fmaxf(c, d));
+  return fminf(fminf(a, b), fminf(c, d));
+}
+
+__device__ __forceinline__ float wave_sum_dpp(float v) {
+  v += dpp_f<kDppRowRor8>(v);
+  v += dpp_f<kDppRowRor4>(v);
+  v += dpp_f<kDppQuad2301>(v);
+  v += dpp_f<kDppQuad1032>(v);
+  return rows4_f(v, 0);
+}
+__device__ __forceinline__ float wave_max_dpp(float v) {
+  v = fmaxf(v, dpp_f<kDppRowRor8>(v));
+  v = fmaxf(v, dpp_f<kDppRowRor4>(v));
+  v = fmaxf(v, dpp_f<kDppQuad2301>(v));
+  v = fmaxf(v, dpp_f<kDppQuad1032>(v));
+  return rows4_f(v, 1);
+}
+__device__ __forceinline__ float wave_min_dpp(float v) {
+  v = fminf(v, dpp_f<kDppRowRor8>(v));
+  v = fminf(v, dpp_f<kDppRowRor4>(v));
+  v = fminf(v, dpp_f<kDppQuad2301>(v));
+  v = fminf(v, dpp_f<kDppQuad1032>(v));
+  return rows4_f(v, 2);
+}
+__device__ __forceinline__ int wave_max_dpp_i(int v) {
+  v = max(v, dpp_i<kDppRowRor8>(v));
+  v = max(v, dpp_i<kDppRowRor4>(v));
+  v = max(v, dpp_i<kDppQuad2301>(v));
+  v = max(v, dpp_i<kDppQuad1032>(v));
+  const int a = __builtin_amdgcn_readlane(v, 0), b = __builtin_amdgcn_readlane(v, 16);
+  const int c = __builtin_amdgcn_readlane(v, 32), d = __builtin_amdgcn_readlane(v, 48);
+  return max(max(a, b), max(c, d));
+}
+
 // Order LDS accesses of one wavefront (all lanes) without a block barrier.
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -387,20 +445,25 @@ hipError_t launch_exclusive_scan(const int32_t* in, int count, int32_t* out, int
 // (pins grouped by cell block, then by net block); a net block reads its pins
 // in "B order" (grouped by cell block), so both sides move runs of pins
 // instead of single random words, and every random access happens in LDS.
-constexpr int kXchCells = 4096;        // cells per cell block (32 KiB of float2)
+constexpr int kXchCells = 8192;        // cells per cell block (64 KiB of float2)
+constexpr int kXchSpreadSplit = 2;     // spread blocks per cell block
 constexpr int kXchThreads = 512;       // threads of the cell-block kernels
-constexpr int kXchWaThreads = 1024;    // threads of the net-block kernel
-constexpr int kXchPinCap = 9728;       // pins per net block (2 x 76 KiB of float2 in LDS)
-constexpr int kXchPinTarget = 8192;    // nets are grouped by first pin / target
+constexpr int kXchWaThreads = 512;     // threads of the net-block kernel
+constexpr int kXchPinCap = 9728;       // most pins of a net block (2 x 76 KiB of float2 in LDS)
+constexpr int kXchPinLds2 = 4864;      // pins of a net block that leave room for 2 blocks per CU
+constexpr int kXchPinTarget = 4096;    // nets are grouped by first pin / target
 constexpr int kXchMinTarget = 1024;
+constexpr int kXchBuckets = 10;        // degree classes 0..8 and > 8 of the net order
 
 struct XchDims {
   int m = 0, num_nets = 0, num_pins = 0, max_degree = 0;
   int npt = 0;         // net block k = nets whose first pin lies in [k*npt, (k+1)*npt)
+  int cap = 0;         // bound on the pins of one net block: npt - 1 + max_degree
   int ncb = 0, nnb = 0;   // cell blocks, net blocks
   size_t index_bytes = 0, work_bytes = 0;
   // offsets inside the index buffer
-  size_t o_hdr = 0, o_cb = 0, o_nb = 0, o_ab = 0, o_lcsr = 0, o_lc = 0, o_cp = 0, o_qa = 0;
+  size_t o_hdr = 0, o_cb = 0, o_nb = 0, o_ab = 0, o_lcsr = 0, o_lc = 0, o_cp = 0, o_qa = 0,
+         o_ns = 0;
 };
 // Returns FFTPL_OK, or FFTPL_E_UNSUPPORTED when max_degree is too large for
 // a net block, or FFTPL_E_INVAL for negative sizes.
@@ -414,6 +477,7 @@ struct XchIndex {
   const uint16_t* lc = nullptr;         // [P] cell offset inside its cell block (A order)
   const int32_t* cell_ptr = nullptr;    // [m+1] pins on cells < c
   const int32_t* qa = nullptr;          // [P] A position of each pin, cell-major
+  const uint16_t* nsort = nullptr;      // [E] nets of each net block by degree class
 };
 XchIndex xch_index(const XchDims& d, const void* index);
 
