@@ -157,9 +157,13 @@ int fftpl_plan_destroy(fftpl_plan* plan);
 int fftpl_plan_info(const fftpl_plan* plan, int32_t* n, int32_t* dct_mode);
 
 /* Device pointers of the maps the last fftpl_eval on this plan produced, for
- * inspection: rho [n*n], psi [n*n] (written in FFTPL_GRAD_EXACT mode and by
- * fftpl_eval_maps), exy [2*n*n] with (Ex, Ey) interleaved per bin.  Owned by
- * the plan.  Any pointer argument may be NULL. */
+ * inspection: rho [n*n], psi [n*n] (written in FFTPL_GRAD_EXACT mode), exy
+ * [2*n*n]: in FFTPL_GRAD_FIELD mode (Ex, Ey) interleaved per bin; in
+ * FFTPL_GRAD_EXACT mode the differences of psi to the next bin centre,
+ * (psi[iy][ix+1] - psi[iy][ix], psi[iy+1][ix] - psi[iy][ix]), computed in the
+ * spectral domain (Section III-C: the exact gradient sums them; taking them
+ * as differences of rounded psi values would lose their leading digits).
+ * Owned by the plan.  Any pointer argument may be NULL. */
 int fftpl_plan_maps(const fftpl_plan* plan, const float** rho, const float** psi,
                     const float** exy);
 
@@ -275,7 +279,10 @@ int fftpl_xindex_build(int32_t num_cells, int32_t num_nets, int32_t num_pins,
  *   rho = base + cells; Poisson solve; g = dW~/dv + lambda * g_N (grad_mode);
  *   out4 (device double[4]) = [N, W~, HPWL, tau] with tau the overflow ratio
  *   sum_b max(0, rho_b - base_b - cap_b) / sum_b (rho_b - base_b).
- * gx, gy [num_cells] are overwritten.  prob->grid.n must equal the plan's n. */
+ * gx, gy [num_cells] are overwritten.  prob->grid.n must equal the plan's n.
+ * With gx = gy = NULL only out4 is computed (the loss W~ + lambda N and the
+ * other scalars, without the gather); this needs a workspace and an index in
+ * prob (FFTPL_E_INVAL otherwise). */
 int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
                const float* y, float lambda, float gamma, int32_t grad_mode,
                float* gx, float* gy, double* out4, void* stream);

@@ -45,7 +45,7 @@ __all__ = [
     "dct_coefficients", "dct_coefficients_literal", "remove_dc",
     "spectral_potential", "potential_field", "poisson_solve", "energy",
     "field_gradient", "exact_gradient", "wa_wirelength", "hpwl",
-    "overflow", "evaluate",
+    "overflow", "evaluate", "local_fd_gradient", "potential_differences",
 ]
 
 
@@ -257,6 +257,20 @@ def poisson_solve(rho: np.ndarray):
     return psi, ex, ey, a
 
 
+def potential_differences(psi: np.ndarray):
+    """Differences of psi to the next bin centre, Dx[iy, ix] = psi[iy, ix+1]
+    - psi[iy, ix] and Dy[iy, ix] = psi[iy+1, ix] - psi[iy, ix] (the terms the
+    exact gradient of Section III-C sums).  The mirror of Section III-E makes
+    the potential at the next centre past the border equal to the last one,
+    so the last column of Dx and the last row of Dy are zero."""
+    psi = np.asarray(psi, np.float64)
+    dx = np.zeros_like(psi)
+    dy = np.zeros_like(psi)
+    dx[:, :-1] = psi[:, 1:] - psi[:, :-1]
+    dy[:-1, :] = psi[1:, :] - psi[:-1, :]
+    return dx, dy
+
+
 def energy(rho: np.ndarray, psi: np.ndarray) -> float:
     """Eq. (6) on the bin grid: N = sum_b rho_b psi_b (all charges,
     fixed ones included, each bin's charge times its potential)."""
@@ -435,3 +449,109 @@ def evaluate(inst, lam: float = 1.0, gamma=None, grad_mode: str = "field"
         gx=gwx + lam * gnx, gy=gwy + lam * gny,
         loss=wa + lam * N,
     )
+
+
+# ---------------------------------------------------------------------------
+# Finite differences of the objective (Eq. (7)) for a subset of cells.
+# ---------------------------------------------------------------------------
+
+def _axis_overlap(lo: float, hi: float, j0: int, j1: int, n: int) -> np.ndarray:
+    """Overlap of [lo, hi) (clipped to [0, n]) with bins j0..j1, float64."""
+    j = np.arange(j0, j1 + 1, dtype=np.float64)
+    a = min(max(lo, 0.0), float(n))
+    b = min(max(hi, 0.0), float(n))
+    return np.maximum(0.0, np.minimum(b, j + 1.0) - np.maximum(a, j))
+
+
+def local_fd_gradient(inst, cells, h: float = 1e-3, lam: float = 1.0, gamma=None,
+                      psi=None):
+    """Central differences of f = W~ + lam * N (Eq. (7)) for the given cells,
+    each moved by +-h bin widths along x and along y, in FP64.
+
+    N is evaluated locally: with d the density change of the moved cell,
+    N(rho + d) = N + 2 d.psi + d.G d (Eq. (6) is a quadratic form in rho with
+    the symmetric Green's operator G of the solve).  When no edge of the cell
+    crosses a bin line within +-h, d(-h) = -d(+h), the quadratic terms cancel
+    exactly and the central difference of N is (d(+h) - d(-h)).psi / h.
+    Cells with an edge that close to a line (or to the region border) are
+    flagged in ``kink`` and get NaN.  W~ changes only on the cell's nets.
+
+    Returns (gx, gy, kink) for the cells, gradients in physical units."""
+    n = inst.n
+    gamma = inst.gamma if gamma is None else float(gamma)
+    if psi is None:
+        base, _ = fixed_maps(inst)
+        psi = poisson_solve(density_map(inst, base))[0]
+    xlo, xhi, ylo, yhi = (np.asarray(a, np.float64) for a in _rects(inst))
+    pc = np.asarray(inst.pin_cell, np.int64)
+    net_ptr = np.asarray(inst.net_ptr, np.int64)
+    deg = np.diff(net_ptr)
+    net_of_pin = np.repeat(np.arange(len(deg)), deg)
+    order = np.argsort(pc, kind="stable")
+    first = np.searchsorted(pc[order], np.arange(len(inst.x) + 1))
+    X = np.asarray(inst.x, np.float64)
+    Y = np.asarray(inst.y, np.float64)
+    dxp = np.asarray(inst.pin_dx, np.float64)
+    dyp = np.asarray(inst.pin_dy, np.float64)
+
+    def net_wa(e, px, py):
+        tot = 0.0
+        for pos in (px, py):
+            M, L = pos.max(), pos.min()
+            ep = np.exp((pos - M) / gamma)
+            em = np.exp((L - pos) / gamma)
+            tot += (M + np.sum((pos - M) * ep) / np.sum(ep)) \
+                - (L + np.sum((pos - L) * em) / np.sum(em))
+        return tot
+
+    def wa_nets(i, sx, sy):
+        tot = 0.0
+        for e in np.unique(net_of_pin[order[first[i]:first[i + 1]]]):
+            p = np.arange(net_ptr[e], net_ptr[e + 1])
+            px = X[pc[p]] + dxp[p]
+            py = Y[pc[p]] + dyp[p]
+            px[pc[p] == i] += sx
+            py[pc[p] == i] += sy
+            tot += net_wa(e, px, py)
+        return tot
+
+    cells = np.asarray(cells, np.int64)
+    gx = np.full(cells.size, np.nan)
+    gy = np.full(cells.size, np.nan)
+    kink = np.zeros(cells.size, bool)
+    for t, i in enumerate(cells):
+        for axis in (0, 1):
+            lo, hi = (xlo[i], xhi[i]) if axis == 0 else (ylo[i], yhi[i])
+            olo, ohi = (ylo[i], yhi[i]) if axis == 0 else (xlo[i], xhi[i])
+            if any(math.floor(e - h) != math.floor(e + h) for e in (lo, hi)):
+                kink[t] = True
+                continue
+            j0 = max(int(math.floor(lo)) - 1, 0)
+            j1 = min(int(math.floor(hi)) + 1, n - 1)
+            k0 = max(int(math.floor(olo)), 0)
+            k1 = min(int(math.ceil(ohi)) - 1, n - 1)
+            if j1 < j0 or k1 < k0:
+                dn = 0.0
+            else:
+                base1 = _axis_overlap(lo, hi, j0, j1, n)
+                dp = _axis_overlap(lo + h, hi + h, j0, j1, n) - base1
+                dm = _axis_overlap(lo - h, hi - h, j0, j1, n) - base1
+                if np.max(np.abs(dp + dm)) > 1e-12:
+                    kink[t] = True
+                    continue
+                oo = _axis_overlap(olo, ohi, k0, k1, n)
+                sub = psi[k0:k1 + 1, j0:j1 + 1] if axis == 0 else psi[j0:j1 + 1, k0:k1 + 1].T
+                # 2 (d+ - d-).psi / (2h), d = outer(other-axis overlap, change)
+                dn = float(oo @ sub @ (dp - dm)) / h
+            bw = inst.bin_w if axis == 0 else inst.bin_h
+            hp = h * bw
+            sx, sy = (hp, 0.0) if axis == 0 else (0.0, hp)
+            dw = (wa_nets(i, sx, sy) - wa_nets(i, -sx, -sy)) / (2.0 * hp)
+            g = dw + lam * dn / bw
+            if axis == 0:
+                gx[t] = g
+            else:
+                gy[t] = g
+    gx[kink] = np.nan
+    gy[kink] = np.nan
+    return gx, gy, kink

@@ -314,7 +314,10 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
   if (m < 0 || prob->num_nets < 0 || prob->num_pins < 0) return FFTPL_E_INVAL;
   if (grad_mode != FFTPL_GRAD_FIELD && grad_mode != FFTPL_GRAD_EXACT) return FFTPL_E_INVAL;
   if (!isfinite(lambda) || !(gamma > 0) || !isfinite(gamma)) return FFTPL_E_INVAL;
-  if (m > 0 && (!x || !y || !prob->w || !prob->h || !gx || !gy)) return FFTPL_E_INVAL;
+  // gx, gy both NULL: the scalars only (needs an atomic-free path, below)
+  const bool grads = gx || gy;
+  if (grads && (!gx || !gy)) return FFTPL_E_INVAL;
+  if (m > 0 && (!x || !y || !prob->w || !prob->h)) return FFTPL_E_INVAL;
   if (!prob->net_ptr) return FFTPL_E_INVAL;
   if (prob->num_pins > 0 && (!prob->pin_cell || !prob->pin_dx || !prob->pin_dy || m == 0))
     return FFTPL_E_INVAL;
@@ -339,6 +342,7 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
                    prob->xindex_bytes >= xd.index_bytes;
   const bool slots = !xch && ws_ok && prob->cell_ptr && prob->pin_slot;
   const bool fast = xch || slots;
+  if (!grads && !fast && m > 0) return FFTPL_E_INVAL;
   if (fast) L = band_layout(p.n, m, prob->num_nets, prob->num_pins, prob->work, nullptr);
   XchIndex X;
   if (xch) {
@@ -404,8 +408,11 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
   if (e == hipSuccess) {
     SpectralArgs a;
     a.rho = p.rho;
-    a.psi = grad_mode == FFTPL_GRAD_EXACT ? p.psi : nullptr;
-    a.exy = grad_mode == FFTPL_GRAD_FIELD ? p.exy : nullptr;
+    // FIELD: (Ex, Ey); EXACT: psi and the difference maps (Dx, Dy) the exact
+    // gradient is summed from; scalars only: neither map
+    a.psi = grads && grad_mode == FFTPL_GRAD_EXACT ? p.psi : nullptr;
+    a.exy = grads ? p.exy : nullptr;
+    a.diff = grad_mode == FFTPL_GRAD_EXACT;
     a.en_part = p.partials;
     a.base = prob->base;
     a.cap = prob->cap;
@@ -417,7 +424,9 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
     // join the wirelength branch; 5. per cell: density gradient plus the sum
     // of its pins' slots
     if (e == hipSuccess && overlap) e = hipStreamWaitEvent(s, p.join, 0);
-    if (xch) {
+    if (!grads) {
+      // scalars only
+    } else if (xch) {
       if (e == hipSuccess)
         e = launch_gather_xch(g, m, x, y, prob->w, prob->h, p.exy, p.psi, grad_mode, lambda,
                               X.cell_ptr, X.qa, L.pin_grad, gx, gy, s);
@@ -430,7 +439,7 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
     }
   } else {
     // 4. density gradient (overwrites g), 5. WA gradient (float atomics)
-    if (e == hipSuccess)
+    if (e == hipSuccess && m > 0)
       e = launch_gather(g, m, x, y, prob->w, prob->h, nullptr, nullptr, p.exy, p.psi,
                         grad_mode, lambda, 0, gx, gy, s);
     plan_mark(p, "k_gather", s);

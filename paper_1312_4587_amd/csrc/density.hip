@@ -198,7 +198,11 @@ hipError_t launch_gather(const GridF& g, int m, const float* x, const float* y,
   if (m <= 0) return hipSuccess;
   dim3 grid((m + 255) / 256), block(256);
   const float2* e2 = reinterpret_cast<const float2*>(exy);
-  if (grad_mode == FFTPL_GRAD_EXACT) {
+  if (grad_mode == FFTPL_GRAD_EXACT && exy) {
+    // difference maps (Dx, Dy) in exy, psi for cells at the border
+    hipLaunchKernelGGL((k_gather<FFTPL_GRAD_EXACT, true, 0>), grid, block, 0, s, g, m, x, y,
+                       w, h, ex, ey, e2, psi, scale, accumulate, nullptr, nullptr, nullptr, gx, gy);
+  } else if (grad_mode == FFTPL_GRAD_EXACT) {
     hipLaunchKernelGGL((k_gather<FFTPL_GRAD_EXACT, false, 0>), grid, block, 0, s, g, m, x, y,
                        w, h, ex, ey, e2, psi, scale, accumulate, nullptr, nullptr, nullptr, gx, gy);
   } else if (exy) {
@@ -220,7 +224,7 @@ hipError_t launch_gather_pins(const GridF& g, int m, const float* x, const float
   dim3 grid((m + 255) / 256), block(256);
   const float2* e2 = reinterpret_cast<const float2*>(exy);
   if (grad_mode == FFTPL_GRAD_EXACT) {
-    hipLaunchKernelGGL((k_gather<FFTPL_GRAD_EXACT, false, 1>), grid, block, 0, s, g, m, x,
+    hipLaunchKernelGGL((k_gather<FFTPL_GRAD_EXACT, true, 1>), grid, block, 0, s, g, m, x,
                        y, w, h, nullptr, nullptr, e2, psi, scale, 0, cell_ptr, pin_grad, nullptr, gx, gy);
   } else {
     hipLaunchKernelGGL((k_gather<FFTPL_GRAD_FIELD, true, 1>), grid, block, 0, s, g, m, x,
@@ -240,7 +244,7 @@ hipError_t launch_gather_xch(const GridF& g, int m, const float* x, const float*
   dim3 grid(nb), block(256);
   const float2* e2 = reinterpret_cast<const float2*>(exy);
   if (grad_mode == FFTPL_GRAD_EXACT) {
-    hipLaunchKernelGGL((k_gather<FFTPL_GRAD_EXACT, false, 3>), grid, block, 0, s, g, m, x,
+    hipLaunchKernelGGL((k_gather<FFTPL_GRAD_EXACT, true, 3>), grid, block, 0, s, g, m, x,
                        y, w, h, nullptr, nullptr, e2, psi, scale, 0, cell_ptr, T, qa, gx, gy);
   } else {
     hipLaunchKernelGGL((k_gather<FFTPL_GRAD_FIELD, true, 3>), grid, block, 0, s, g, m, x,

@@ -66,7 +66,9 @@ __device__ __forceinline__ float span_overlap(const Span& s, int j) {
 // two maps).  EXACT: dN/dx = 2/bin * sum over the other axis' overlaps of
 // [psi at the right edge's bin - psi at the left edge's bin], for edges
 // strictly inside (0, n) (an edge moving inside a bin moves area from the
-// bin it leaves to the bin it enters).
+// bin it leaves to the bin it enters); with INTERLEAVED and exy set, exy holds
+// the difference maps (Dx, Dy) of the solve's difference mode and psi is read
+// only for cells with one edge outside the region.
 template <int MODE, bool INTERLEAVED>
 __device__ __forceinline__ float2 cell_density_grad(const GridF& g, float x, float y, float w,
                                                     float h, const float* __restrict__ ex,
@@ -95,7 +97,44 @@ __device__ __forceinline__ float2 cell_density_grad(const GridF& g, float x, flo
     }
     ax *= -g.inv_bw;
     ay *= -g.inv_bh;
+  } else if (INTERLEAVED && exy) {
+    // from the difference maps (Dx, Dy): with both edges inside, psi(right
+    // edge's bin) - psi(left edge's bin) is the sum of Dx over the bins
+    // between; with one edge inside, the single psi term
+    const float fn = (float)n;
+    const bool xr = sx.hi > 0.0f && sx.hi < fn, xl = sx.lo > 0.0f && sx.lo < fn;
+    const bool yr = sy.hi > 0.0f && sy.hi < fn, yl = sy.lo > 0.0f && sy.lo < fn;
+    const int cxr = xr ? (int)floorf(sx.hi) : 0, cxl = xl ? (int)floorf(sx.lo) : 0;
+    const int cyr = yr ? (int)floorf(sy.hi) : 0, cyl = yl ? (int)floorf(sy.lo) : 0;
+    for (int iy = sy.i0; iy <= sy.i1; ++iy) {
+      const float oy = span_overlap(sy, iy);
+      const int64_t row = (int64_t)iy * n;
+      float d = 0.0f;
+      if (xr && xl) {
+        for (int c = cxl; c < cxr; ++c) d += exy[row + c].x;
+      } else if (xr) {
+        d = psi[row + cxr];
+      } else if (xl) {
+        d = -psi[row + cxl];
+      }
+      ax += oy * d;
+    }
+    for (int ix = sx.i0; ix <= sx.i1; ++ix) {
+      const float ox = span_overlap(sx, ix);
+      float d = 0.0f;
+      if (yr && yl) {
+        for (int r = cyl; r < cyr; ++r) d += exy[(int64_t)r * n + ix].y;
+      } else if (yr) {
+        d = psi[(int64_t)cyr * n + ix];
+      } else if (yl) {
+        d = -psi[(int64_t)cyl * n + ix];
+      }
+      ay += ox * d;
+    }
+    ax *= 2.0f * g.inv_bw;
+    ay *= 2.0f * g.inv_bh;
   } else {
+    // from psi alone (differences of psi values)
     const float fn = (float)n;
     const bool xr = sx.hi > 0.0f && sx.hi < fn, xl = sx.lo > 0.0f && sx.lo < fn;
     const bool yr = sy.hi > 0.0f && sy.hi < fn, yl = sy.lo > 0.0f && sy.lo < fn;
@@ -512,6 +551,9 @@ struct SpectralArgs {
   const float* cap = nullptr;
   float rho_t = 1.0f;
   double* tau_part = nullptr;
+  // difference mode: exy receives (Dx, Dy) = (psi(ix+1) - psi(ix), psi(iy+1) - psi(iy))
+  // at every bin instead of (Ex, Ey); ex and ey must be null
+  bool diff = false;
 };
 hipError_t spectral_fft(Plan& p, const SpectralArgs& a, hipStream_t s);
 hipError_t spectral_gemm(Plan& p, const SpectralArgs& a, hipStream_t s);

@@ -10,6 +10,16 @@
 //                                               -> P[iy][u], Q[iy][u]
 //   C  rows:    DCT-III along x of P (-> psi) and of Q (-> Ey), sine
 //               transform along x of w_u P (-> Ex); energy sum rho*psi.
+// Difference mode (for the exact density gradient) replaces the fields by
+// the differences of psi between neighbouring bin centres,
+//   Dx(iy, ix) = psi(iy, ix+1) - psi(iy, ix),  Dy(iy, ix) = psi(iy+1, ix) - psi(iy, ix),
+// taken in the spectral domain: cos(w (i + 3/2)) - cos(w (i + 1/2)) =
+// (cos w - 1) cos(w (i + 1/2)) - sin w sin(w (i + 1/2)), so each difference is
+// a DCT-III with weights cos w - 1 minus a sine transform with weights sin w.
+// Both weights vanish at low frequency, so the small differences come out
+// with float32 accuracy relative to themselves instead of to psi.  Pass B
+// then outputs R = DCT-III((cos w_v - 1) G) - sine(sin w_v G) in place of Q,
+// and pass C gives Dy = DCT-III(R) and Dx from P the same way along x.
 // A length-n DCT-II is an n-point complex FFT of the even/odd reordered
 // sequence followed by a quarter-sample twiddle (Makhoul's algorithm); two
 // real sequences share one complex FFT as its real and imaginary parts.  A
@@ -166,6 +176,15 @@ __device__ __forceinline__ float2 pack2(float2 ha, float2 hb) {
   return make_float2(ha.x - hb.y, ha.y + hb.x);
 }
 
+// Difference-mode weights at the pair (k, n-k) from cs = (cos, sin)(pi k / 2n):
+// cos w_k - 1 = -2 sin^2(w_k / 2), cos w_{n-k} - 1 = -2 cos^2(w_k / 2),
+// sin w_k = sin w_{n-k} = 2 sin(w_k / 2) cos(w_k / 2).
+__device__ __forceinline__ void diff_weights(float2 cs, float& dm_k, float& dm_kp, float& sw) {
+  dm_k = -2.0f * cs.y * cs.y;
+  dm_kp = -2.0f * cs.x * cs.x;
+  sw = 2.0f * cs.y * cs.x;
+}
+
 // ---------------------------------------------------------------------------
 // Pass A: rows -> bT (transposed), row sums in double; optional overflow sums.
 // ---------------------------------------------------------------------------
@@ -247,7 +266,7 @@ __global__ void __launch_bounds__(64)
 // Pass B: columns u1 = 2q, u2 = 2q+1 (rows of bT).  Column 0 is rebuilt from
 // the double row sums minus their mean so that the DC never enters float32.
 // ---------------------------------------------------------------------------
-template <int N>
+template <int N, bool DIFF>
 __global__ void __launch_bounds__(64)
     k_cols_solve(const float* __restrict__ bT, const double* __restrict__ rowsum,
                  float* __restrict__ P, float* __restrict__ Q,
@@ -255,6 +274,7 @@ __global__ void __launch_bounds__(64)
                  const float* __restrict__ wf_g) {
   __shared__ float2 buf0[N];
   __shared__ float2 buf1[N];
+  __shared__ float2 buf2[DIFF ? N : 1];
   __shared__ float2 tw[N];
   __shared__ float2 cs[N / 2 + 1];
   __shared__ float wf[N];
@@ -306,27 +326,48 @@ __global__ void __launch_bounds__(64)
     dct3_herm(g2k, g2kp, c, k0, h2, h2p);
     buf0[k] = pack2(h1, h2);
     if (!k0 && k != N / 2) buf0[kp] = pack2(h1p, h2p);
-    dct3_herm(k0 ? 0.0f : wkp * g1kp, k0 ? 0.0f : wk * g1k, c, k0, h1, h1p);
-    dct3_herm(k0 ? 0.0f : wkp * g2kp, k0 ? 0.0f : wk * g2k, c, k0, h2, h2p);
-    buf1[k] = pack2(h1, h2);
-    if (!k0 && k != N / 2) buf1[kp] = pack2(h1p, h2p);
+    if (!DIFF) {
+      dct3_herm(k0 ? 0.0f : wkp * g1kp, k0 ? 0.0f : wk * g1k, c, k0, h1, h1p);
+      dct3_herm(k0 ? 0.0f : wkp * g2kp, k0 ? 0.0f : wk * g2k, c, k0, h2, h2p);
+      buf1[k] = pack2(h1, h2);
+      if (!k0 && k != N / 2) buf1[kp] = pack2(h1p, h2p);
+    } else {
+      // R = DCT-III((cos w - 1) G) (buf1) - sine transform of sin(w) G (buf2)
+      float dmk, dmkp, sw;
+      diff_weights(c, dmk, dmkp, sw);
+      dct3_herm(dmk * g1k, dmkp * g1kp, c, k0, h1, h1p);
+      dct3_herm(dmk * g2k, dmkp * g2kp, c, k0, h2, h2p);
+      buf1[k] = pack2(h1, h2);
+      if (!k0 && k != N / 2) buf1[kp] = pack2(h1p, h2p);
+      dct3_herm(k0 ? 0.0f : sw * g1kp, k0 ? 0.0f : sw * g1k, c, k0, h1, h1p);
+      dct3_herm(k0 ? 0.0f : sw * g2kp, k0 ? 0.0f : sw * g2k, c, k0, h2, h2p);
+      buf2[k] = pack2(h1, h2);
+      if (!k0 && k != N / 2) buf2[kp] = pack2(h1p, h2p);
+    }
   }
   wave_lds_sync();
   wave_fft<N, true>(buf0, tw, lane);
   wave_fft<N, true>(buf1, tw, lane);
+  if (DIFF) wave_fft<N, true>(buf2, tw, lane);
   for (int iy = lane; iy < N; iy += kWave) {
     const int mpos = mk_pos<N>(iy);
     const float2 zp = buf0[mpos], zq = buf1[mpos];
     const float sg = (iy & 1) ? -1.0f : 1.0f;
     *reinterpret_cast<float2*>(&P[(int64_t)iy * N + u1]) = zp;
-    *reinterpret_cast<float2*>(&Q[(int64_t)iy * N + u1]) = make_float2(sg * zq.x, sg * zq.y);
+    if (!DIFF) {
+      *reinterpret_cast<float2*>(&Q[(int64_t)iy * N + u1]) = make_float2(sg * zq.x, sg * zq.y);
+    } else {
+      const float2 zs = buf2[mpos];
+      *reinterpret_cast<float2*>(&Q[(int64_t)iy * N + u1]) =
+          make_float2(zq.x - sg * zs.x, zq.y - sg * zs.y);
+    }
   }
 }
 
 // ---------------------------------------------------------------------------
 // Pass C: rows r1 = 2p, r2 = 2p+1 of P and Q -> psi, Ex, Ey; energy.
 // ---------------------------------------------------------------------------
-template <int N>
+template <int N, bool DIFF>
 __global__ void __launch_bounds__(64)
     k_rows_inverse(const float* __restrict__ P, const float* __restrict__ Q,
                    const float* __restrict__ rho, float* __restrict__ psi,
@@ -337,6 +378,7 @@ __global__ void __launch_bounds__(64)
   __shared__ float2 bufa[N];
   __shared__ float2 bufb[N];
   __shared__ float2 bufc[N];
+  __shared__ float2 bufd[DIFF ? N : 1];
   __shared__ float2 tw[N];
   __shared__ float2 cs[N / 2 + 1];
   __shared__ float wf[N];
@@ -374,15 +416,30 @@ __global__ void __launch_bounds__(64)
     dct3_herm(Q2[k], Q2[kp], c, k0, hb, hbp);
     bufb[k] = pack2(ha, hb);
     if (!self) bufb[kp] = pack2(hap, hbp);
-    dct3_herm(k0 ? 0.0f : wkp * p1kp, k0 ? 0.0f : wk * p1k, c, k0, ha, hap);
-    dct3_herm(k0 ? 0.0f : wkp * p2kp, k0 ? 0.0f : wk * p2k, c, k0, hb, hbp);
-    bufc[k] = pack2(ha, hb);
-    if (!self) bufc[kp] = pack2(hap, hbp);
+    if (!DIFF) {
+      dct3_herm(k0 ? 0.0f : wkp * p1kp, k0 ? 0.0f : wk * p1k, c, k0, ha, hap);
+      dct3_herm(k0 ? 0.0f : wkp * p2kp, k0 ? 0.0f : wk * p2k, c, k0, hb, hbp);
+      bufc[k] = pack2(ha, hb);
+      if (!self) bufc[kp] = pack2(hap, hbp);
+    } else {
+      // Dx = DCT-III((cos w - 1) P) (bufc) - sine transform of sin(w) P (bufd)
+      float dmk, dmkp, sw;
+      diff_weights(c, dmk, dmkp, sw);
+      dct3_herm(dmk * p1k, dmkp * p1kp, c, k0, ha, hap);
+      dct3_herm(dmk * p2k, dmkp * p2kp, c, k0, hb, hbp);
+      bufc[k] = pack2(ha, hb);
+      if (!self) bufc[kp] = pack2(hap, hbp);
+      dct3_herm(k0 ? 0.0f : sw * p1kp, k0 ? 0.0f : sw * p1k, c, k0, ha, hap);
+      dct3_herm(k0 ? 0.0f : sw * p2kp, k0 ? 0.0f : sw * p2k, c, k0, hb, hbp);
+      bufd[k] = pack2(ha, hb);
+      if (!self) bufd[kp] = pack2(hap, hbp);
+    }
   }
   wave_lds_sync();
   wave_fft<N, true>(bufa, tw, lane);
   wave_fft<N, true>(bufb, tw, lane);
   wave_fft<N, true>(bufc, tw, lane);
+  if (DIFF) wave_fft<N, true>(bufd, tw, lane);
   double en = 0.0;
   constexpr int PERX = (N + kWave - 1) / kWave;
 #pragma unroll
@@ -390,8 +447,14 @@ __global__ void __launch_bounds__(64)
     const int ix = lane + kWave * t;
     if (N % kWave != 0 && ix >= N) continue;
     const int mpos = mk_pos<N>(ix);
-    const float2 za = bufa[mpos], zb = bufb[mpos], zc = bufc[mpos];
+    const float2 za = bufa[mpos], zb = bufb[mpos];
     const float sg = (ix & 1) ? -1.0f : 1.0f;
+    float2 zc = bufc[mpos];
+    if (DIFF) {
+      // (Dx, Dy) instead of (Ex, Ey): zc holds Dx after the sign below
+      const float2 zd = bufd[mpos];
+      zc = make_float2(sg * (zc.x - sg * zd.x), sg * (zc.y - sg * zd.y));
+    }
     const int64_t o1 = (int64_t)r1 * N + ix, o2 = (int64_t)r2 * N + ix;
     if (psi) {
       psi[o1] = za.x;
@@ -425,13 +488,22 @@ hipError_t run_fft(Plan& p, const SpectralArgs& a, hipStream_t s) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   plan_mark(p, "k_rows_dct2", s);
-  hipLaunchKernelGGL(k_cols_solve<N>, grid, block, 0, s, p.tmp0, p.rowsum, p.tmp1, p.tmp2,
-                     p.fft_tw, p.dct_cs, p.wfreq);
+  if (a.diff)
+    hipLaunchKernelGGL((k_cols_solve<N, true>), grid, block, 0, s, p.tmp0, p.rowsum, p.tmp1,
+                       p.tmp2, p.fft_tw, p.dct_cs, p.wfreq);
+  else
+    hipLaunchKernelGGL((k_cols_solve<N, false>), grid, block, 0, s, p.tmp0, p.rowsum, p.tmp1,
+                       p.tmp2, p.fft_tw, p.dct_cs, p.wfreq);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   plan_mark(p, "k_cols_solve", s);
-  hipLaunchKernelGGL(k_rows_inverse<N>, grid, block, 0, s, p.tmp1, p.tmp2, a.rho, a.psi,
-                     a.ex, a.ey, reinterpret_cast<float2*>(a.exy), a.en_part, p.fft_tw,
-                     p.dct_cs, p.wfreq);
+  if (a.diff)
+    hipLaunchKernelGGL((k_rows_inverse<N, true>), grid, block, 0, s, p.tmp1, p.tmp2, a.rho,
+                       a.psi, a.ex, a.ey, reinterpret_cast<float2*>(a.exy), a.en_part,
+                       p.fft_tw, p.dct_cs, p.wfreq);
+  else
+    hipLaunchKernelGGL((k_rows_inverse<N, false>), grid, block, 0, s, p.tmp1, p.tmp2, a.rho,
+                       a.psi, a.ex, a.ey, reinterpret_cast<float2*>(a.exy), a.en_part,
+                       p.fft_tw, p.dct_cs, p.wfreq);
   e = hipGetLastError();
   plan_mark(p, "k_rows_inverse", s);
   return e;

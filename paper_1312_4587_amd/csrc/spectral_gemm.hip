@@ -272,10 +272,12 @@ float bf16_to_f32(uint16_t h) {
 // Region offsets (in bytes) inside the plan's table and workspace blocks.
 struct GemmLayout {
   size_t nn;
-  // float32 tables: K [n][n], KSw [n][2n], KTSwT [2n][n]
-  size_t t_k, t_ksw, t_ktswt;
-  // bf16 tables (hi, lo): K [n][n], KSwT [2n][n], KTSwT [2n][n]
-  size_t b_kh, b_kl, b_kswth, b_kswtl, b_ktswth, b_ktswtl;
+  // float32 tables: K [n][n], KSw [n][2n], KTSwT [2n][n], and the same two
+  // with the difference matrix Kd in place of Sw
+  size_t t_k, t_ksw, t_ktswt, t_kkd, t_ktkdt;
+  // bf16 tables (hi, lo): K [n][n], KSwT [2n][n], KTSwT [2n][n], KKdT, KTKdT
+  size_t b_kh, b_kl, b_kswth, b_kswtl, b_ktswth, b_ktswtl, b_kkdth, b_kkdtl, b_ktkdth,
+      b_ktkdtl;
   size_t tables_bytes;
   // workspace float32: R [n][n], W [n][n], G [n][n], UV [n][2n]
   size_t w_r, w_w, w_g, w_uv;
@@ -291,14 +293,20 @@ GemmLayout gemm_layout(int n) {
   L.t_k = 0;
   L.t_ksw = L.t_k + 4 * nn;
   L.t_ktswt = L.t_ksw + 8 * nn;
-  const size_t f32_end = L.t_ktswt + 8 * nn;
+  L.t_kkd = L.t_ktswt + 8 * nn;
+  L.t_ktkdt = L.t_kkd + 8 * nn;
+  const size_t f32_end = L.t_ktkdt + 8 * nn;
   L.b_kh = 0;
   L.b_kl = L.b_kh + 2 * nn;
   L.b_kswth = L.b_kl + 2 * nn;
   L.b_kswtl = L.b_kswth + 4 * nn;
   L.b_ktswth = L.b_kswtl + 4 * nn;
   L.b_ktswtl = L.b_ktswth + 4 * nn;
-  const size_t bf_end = L.b_ktswtl + 4 * nn;
+  L.b_kkdth = L.b_ktswtl + 4 * nn;
+  L.b_kkdtl = L.b_kkdth + 4 * nn;
+  L.b_ktkdth = L.b_kkdtl + 4 * nn;
+  L.b_ktkdtl = L.b_ktkdth + 4 * nn;
+  const size_t bf_end = L.b_ktkdtl + 4 * nn;
   L.tables_bytes = f32_end > bf_end ? f32_end : bf_end;
   L.w_r = 0;
   L.w_w = 4 * nn;
@@ -399,14 +407,16 @@ hipError_t run_gemm_path(Plan& p, const SpectralArgs& a, hipStream_t s) {
   g.M = n; g.N = 2 * n; g.K = n;
   if (BF16) {
     g.a_hi = wb + L.v_gh; g.a_lo = wb + L.v_gl; g.lda = n;
-    g.b_hi = tb + L.b_kswth; g.b_lo = tb + L.b_kswtl; g.ldb = n;
+    g.b_hi = tb + (a.diff ? L.b_kkdth : L.b_kswth);
+    g.b_lo = tb + (a.diff ? L.b_kkdtl : L.b_kswtl);
+    g.ldb = n;
     ep.mode = EPI_SPLIT_T;
     ep.hi = reinterpret_cast<__bf16*>(wb + L.v_uvth);
     ep.lo = reinterpret_cast<__bf16*>(wb + L.v_uvtl);
     ep.ldo = n;
   } else {
     g.a_hi = wb + L.w_g; g.lda = n;
-    g.b_hi = tb + L.t_ksw; g.ldb = 2 * n;
+    g.b_hi = tb + (a.diff ? L.t_kkd : L.t_ksw); g.ldb = 2 * n;
     ep.mode = EPI_F32;
     ep.out = reinterpret_cast<float*>(wb + L.w_uv);
     ep.ldo = 2 * n;
@@ -424,10 +434,12 @@ hipError_t run_gemm_path(Plan& p, const SpectralArgs& a, hipStream_t s) {
   ep.en_part = a.en_part;
   g.M = 2 * n; g.N = n; g.K = n;
   if (BF16) {
-    g.a_hi = tb + L.b_ktswth; g.a_lo = tb + L.b_ktswtl; g.lda = n;
+    g.a_hi = tb + (a.diff ? L.b_ktkdth : L.b_ktswth);
+    g.a_lo = tb + (a.diff ? L.b_ktkdtl : L.b_ktswtl);
+    g.lda = n;
     g.b_hi = wb + L.v_uvth; g.b_lo = wb + L.v_uvtl; g.ldb = n;
   } else {
-    g.a_hi = tb + L.t_ktswt; g.lda = n;
+    g.a_hi = tb + (a.diff ? L.t_ktkdt : L.t_ktswt); g.lda = n;
     g.b_hi = wb + L.w_uv; g.ldb = 2 * n;
   }
   if ((e = launch_gemm<BF16>(g, ep, s)) != hipSuccess) return e;
@@ -466,14 +478,19 @@ int gemm_plan_init(Plan& p, hipStream_t s) {
   const double pi = 3.14159265358979323846;
   const size_t nn = L.nn;
   // K[u][i] and Sw[u][i] = w_u S[u][i], argument reduced as pi*((u(2i+1)) mod 4n)/(2n)
-  std::vector<double> K(nn), Sw(nn);
+  // Kd[u][i] = cos(w_u (i + 3/2)) - cos(w_u (i + 1/2)) = -2 sin(w_u / 2) sin(w_u (i + 1)):
+  // psi at the next bin centre minus psi at this one (the difference mode)
+  std::vector<double> K(nn), Sw(nn), Kd(nn);
   for (int u = 0; u < n; ++u) {
     const double wu = pi * u / n;
+    const double sh = sin(pi * u / (2.0 * n));
     for (int i = 0; i < n; ++i) {
       const long long r = ((long long)u * (2 * i + 1)) % (4LL * n);
       const double ang = pi * (double)r / (2.0 * n);
       K[(size_t)u * n + i] = cos(ang);
       Sw[(size_t)u * n + i] = wu * sin(ang);
+      const long long r2 = ((long long)u * (i + 1)) % (2LL * n);
+      Kd[(size_t)u * n + i] = -2.0 * sh * sin(pi * (double)r2 / n);
     }
   }
   std::vector<char> host(L.tables_bytes);
@@ -481,6 +498,8 @@ int gemm_plan_init(Plan& p, hipStream_t s) {
     float* tk = reinterpret_cast<float*>(host.data() + L.t_k);
     float* tksw = reinterpret_cast<float*>(host.data() + L.t_ksw);
     float* tkt = reinterpret_cast<float*>(host.data() + L.t_ktswt);
+    float* tkkd = reinterpret_cast<float*>(host.data() + L.t_kkd);
+    float* tktkd = reinterpret_cast<float*>(host.data() + L.t_ktkdt);
     for (int a = 0; a < n; ++a)
       for (int b = 0; b < n; ++b) {
         tk[(size_t)a * n + b] = (float)K[(size_t)a * n + b];
@@ -488,6 +507,10 @@ int gemm_plan_init(Plan& p, hipStream_t s) {
         tksw[(size_t)a * 2 * n + n + b] = (float)Sw[(size_t)a * n + b];
         tkt[(size_t)a * n + b] = (float)K[(size_t)b * n + a];               // [iy][v]
         tkt[(size_t)(n + a) * n + b] = (float)Sw[(size_t)b * n + a];
+        tkkd[(size_t)a * 2 * n + b] = (float)K[(size_t)a * n + b];
+        tkkd[(size_t)a * 2 * n + n + b] = (float)Kd[(size_t)a * n + b];
+        tktkd[(size_t)a * n + b] = (float)K[(size_t)b * n + a];
+        tktkd[(size_t)(n + a) * n + b] = (float)Kd[(size_t)b * n + a];
       }
   } else {
     uint16_t* kh = reinterpret_cast<uint16_t*>(host.data() + L.b_kh);
@@ -496,6 +519,10 @@ int gemm_plan_init(Plan& p, hipStream_t s) {
     uint16_t* sl = reinterpret_cast<uint16_t*>(host.data() + L.b_kswtl);
     uint16_t* th = reinterpret_cast<uint16_t*>(host.data() + L.b_ktswth);
     uint16_t* tl = reinterpret_cast<uint16_t*>(host.data() + L.b_ktswtl);
+    uint16_t* dh = reinterpret_cast<uint16_t*>(host.data() + L.b_kkdth);
+    uint16_t* dl = reinterpret_cast<uint16_t*>(host.data() + L.b_kkdtl);
+    uint16_t* eh = reinterpret_cast<uint16_t*>(host.data() + L.b_ktkdth);
+    uint16_t* el = reinterpret_cast<uint16_t*>(host.data() + L.b_ktkdtl);
     auto split = [](double v, uint16_t& h, uint16_t& l) {
       const float f = (float)v;
       h = f32_to_bf16_rne(f);
@@ -510,6 +537,13 @@ int gemm_plan_init(Plan& p, hipStream_t s) {
         // [K^T ; Sw^T]: row iy (n + iy), column v
         split(K[(size_t)b * n + a], th[(size_t)a * n + b], tl[(size_t)a * n + b]);
         split(Sw[(size_t)b * n + a], th[(size_t)(n + a) * n + b], tl[(size_t)(n + a) * n + b]);
+        // the same two with Kd in place of Sw
+        dh[(size_t)a * n + b] = sh[(size_t)a * n + b];
+        dl[(size_t)a * n + b] = sl[(size_t)a * n + b];
+        split(Kd[(size_t)b * n + a], dh[(size_t)(n + a) * n + b], dl[(size_t)(n + a) * n + b]);
+        eh[(size_t)a * n + b] = th[(size_t)a * n + b];
+        el[(size_t)a * n + b] = tl[(size_t)a * n + b];
+        split(Kd[(size_t)b * n + a], eh[(size_t)(n + a) * n + b], el[(size_t)(n + a) * n + b]);
       }
   }
   if (hipMemcpyAsync(p.gemm_tables, host.data(), L.tables_bytes, hipMemcpyHostToDevice, s) !=

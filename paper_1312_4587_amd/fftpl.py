@@ -353,8 +353,10 @@ def eval(plan: Plan, prob: Problem, x, y, lam, gamma, grad_mode, gx, gy, out4,
     _check(_lib.load().fftpl_eval(
         plan.handle, ctypes.byref(prob.c), _ptr(x, torch.float32, m, "x"),
         _ptr(y, torch.float32, m, "y"), float(lam), float(gamma),
-        GRAD_MODES.get(grad_mode, grad_mode), _ptr(gx, torch.float32, m, "gx"),
-        _ptr(gy, torch.float32, m, "gy"), _ptr(out4, torch.float64, 4, "out4"),
+        GRAD_MODES.get(grad_mode, grad_mode),
+        _ptr(gx, torch.float32, m, "gx") if gx is not None else None,
+        _ptr(gy, torch.float32, m, "gy") if gy is not None else None,
+        _ptr(out4, torch.float64, 4, "out4"),
         _stream(stream)), "fftpl_eval")
 
 

@@ -316,6 +316,11 @@ def _check_eval(inst, got, ref, lam, mode):
         assert rel_l2(got["exy"][..., 1], ref["ey"]) < RTOL
     else:
         assert rel_l2(got["psi"], ref["psi"]) < RTOL
+        # the exact gradient's inputs: differences of psi to the next bin centre
+        dx, dy = oracle.potential_differences(ref["psi"])
+        say("difference maps", rel_l2(got["exy"][..., 0], dx), rel_l2(got["exy"][..., 1], dy))
+        assert rel_l2(got["exy"][..., 0], dx) < RTOL
+        assert rel_l2(got["exy"][..., 1], dy) < RTOL
     assert rel_l2(got["gx"], ref["gx"]) < RTOL and rel_l2(got["gy"], ref["gy"]) < RTOL
 
 
@@ -339,6 +344,26 @@ def test_eval_large_2m_full_workload(F):
     say("oracle large_2m")
     ref = oracle.evaluate(inst, lam=1.0, grad_mode="field")
     _check_eval(inst, got, ref, 1.0, "field")
+
+
+@pytest.mark.parametrize("dct", ["fft", "gemm_f32"])
+def test_eval_exact_mode_mid_200k(F, dct):
+    # the exact gradient sums the solve's difference maps: float32 differences
+    # of psi itself would miss 1e-5 at this size (psi is ~10^3, its bin-to-bin
+    # differences ~1)
+    inst = gen.make_config("mid_200k")
+    say("eval exact mid_200k", dct)
+    got = _run_eval(F, inst, 2.0, "exact", dct=dct)
+    ref = oracle.evaluate(inst, lam=2.0, grad_mode="exact")
+    _check_eval(inst, got, ref, 2.0, "exact")
+
+
+def test_eval_exact_mode_large_2m(F):
+    inst = gen.make_config("large_2m")
+    say("eval exact large_2m")
+    got = _run_eval(F, inst, 1.0, "exact")
+    ref = oracle.evaluate(inst, lam=1.0, grad_mode="exact")
+    _check_eval(inst, got, ref, 1.0, "exact")
 
 
 def test_eval_edge_cases(F):

@@ -5,6 +5,7 @@ import math
 import numpy as np
 import pytest
 
+import gen
 import oracle
 from _helpers import hand_instance, tiny_instance, with_macros
 
@@ -201,3 +202,18 @@ def test_evaluate_composition():
     assert r["loss"] == pytest.approx(r["wa"] + 0.37 * r["energy"])
     assert np.allclose(r["gx"], r["gwx"] + 0.37 * r["gnx"])
     assert r["energy"] > 0 and 0 <= r["overflow"] <= 1
+
+
+def test_local_finite_differences_match_the_exact_gradient():
+    # the local central differences of W~ + lam N (moving one cell at a time,
+    # N updated through its quadratic form) against the closed-form exact
+    # gradient, on cells whose edges stay inside their bins
+    inst = with_macros(gen.make_config("small_2k"), [[30.0, 30.0, 10.0, 8.0]])
+    ref = oracle.evaluate(inst, lam=2.0, grad_mode="exact")
+    cells = np.random.default_rng(40).choice(inst.num_cells, 300, replace=False)
+    gx, gy, kink = oracle.local_fd_gradient(inst, cells, 1e-3, 2.0, psi=ref["psi"])
+    assert kink.sum() < 0.05 * cells.size
+    ok = ~kink
+    ex = np.concatenate([ref["gx"][cells][ok], ref["gy"][cells][ok]])
+    fd = np.concatenate([gx[ok], gy[ok]])
+    assert np.linalg.norm(ex - fd) / np.linalg.norm(ex) < 1e-6

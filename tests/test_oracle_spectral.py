@@ -59,6 +59,24 @@ def test_single_mode_closed_form(n, u, v):
     assert np.max(np.abs(ey - ey_ref)) < 1e-12 * max(1.0, 1.0 / d)
 
 
+@pytest.mark.parametrize("n,u,v", [(16, 3, 5), (16, 1, 0), (16, 0, 7), (64, 17, 40)])
+def test_single_mode_potential_differences(n, u, v):
+    # psi = mode / d; its difference to the next bin centre in closed form,
+    # cos(w (i + 3/2)) - cos(w (i + 1/2)) = -2 sin(w / 2) sin(w (i + 1)), which
+    # is zero at the last centre (the mirror of the Neumann extension)
+    x = np.arange(n) + 0.5
+    wu, wv = np.pi * u / n, np.pi * v / n
+    rho = np.outer(np.cos(wv * x), np.cos(wu * x))
+    psi = oracle.poisson_solve(rho)[0]
+    dx, dy = oracle.potential_differences(psi)
+    d = wu * wu + wv * wv
+    i1 = np.arange(n) + 1.0
+    dx_ref = -2.0 * np.sin(wu / 2) / d * np.outer(np.cos(wv * x), np.sin(wu * i1))
+    dy_ref = -2.0 * np.sin(wv / 2) / d * np.outer(np.sin(wv * i1), np.cos(wu * x))
+    tol = 1e-12 * max(1.0, 1.0 / d)
+    assert np.max(np.abs(dx - dx_ref)) < tol and np.max(np.abs(dy - dy_ref)) < tol
+
+
 def test_constant_density_gives_nothing():
     rho = np.full((16, 16), 0.9)
     psi, ex, ey, a = oracle.poisson_solve(rho)
