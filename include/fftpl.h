@@ -287,6 +287,31 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
                const float* y, float lambda, float gamma, int32_t grad_mode,
                float* gx, float* gy, double* out4, void* stream);
 
+/* Placement iteration (Algorithm 1: after each evaluation the positions move
+ * along the gradient).  The global placement here uses Nesterov's method with
+ * a look-ahead point u at which the gradient g is taken; the step length is
+ * chosen on the host from these statistics (all device, double):
+ *   out4 = [sum (u - u_prev)^2, sum (g - g_prev)^2, max |g|, sum |g|]
+ * over both axes of num_cells cells.  upx, upy, gpx, gpy may all be NULL (the
+ * first iteration: out4[0] = out4[1] = 0).  work: device double scratch of at
+ * least 1024 entries (work_doubles).  Per-block partials summed in a fixed
+ * order: repeatable. */
+int fftpl_step_stats(int32_t num_cells, const float* ux, const float* uy, const float* upx,
+                     const float* upy, const float* gx, const float* gy, const float* gpx,
+                     const float* gpy, double* out4, double* work, uint64_t work_doubles,
+                     void* stream);
+
+/* The Nesterov update of every cell centre (device arrays [num_cells]):
+ *   x_new = clamp(u - step g),  u_new = clamp(x_new + beta (x_new - x)),
+ *   then u_prev = u, g_prev = g, x = x_new, u = u_new,
+ * with clamp keeping the cell (sizes w, h) inside the region of `region`
+ * ([xl, xl + n bin_w] x [yl, yl + n bin_h]; a cell wider than the region
+ * sits at its centre).  step >= 0, 0 <= beta < 1. */
+int fftpl_nesterov_update(const fftpl_grid* region, int32_t num_cells, const float* w,
+                          const float* h, float* x, float* y, float* ux, float* uy, float* upx,
+                          float* upy, float* gpx, float* gpy, const float* gx, const float* gy,
+                          float step, float beta, void* stream);
+
 /* Test export: the integer bin range of every cell under the rectangle rule
  * above, ranges[4*i + {0,1,2,3}] = {ix0, ix1, iy0, iy1} (empty when first >
  * last).  ranges is a device int32 array [4*num_cells]. */

@@ -70,6 +70,13 @@ SIGNATURES = {
                                    ctypes.POINTER(ctypes.c_uint64)]),
     "fftpl_xindex_build": (c_int, [c_int, c_int, c_int, c_void_p, c_void_p, c_int, c_void_p,
                                    ctypes.c_uint64, c_void_p, ctypes.c_uint64, c_void_p]),
+    "fftpl_step_stats": (c_int, [c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                 c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                 ctypes.c_uint64, c_void_p]),
+    "fftpl_nesterov_update": (c_int, [_G, c_int, c_void_p, c_void_p, c_void_p, c_void_p,
+                                      c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                      c_void_p, c_void_p, c_void_p, c_float, c_float,
+                                      c_void_p]),
     "fftpl_plan_timing": (c_int, [c_void_p, c_int]),
     "fftpl_plan_kernel_times": (c_int, [c_void_p, c_int, ctypes.POINTER(c_float),
                                         ctypes.POINTER(c_char_p), ctypes.POINTER(c_int)]),

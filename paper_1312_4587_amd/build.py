@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfftpl.so")
 OBJDIR = os.path.join(HERE, "_build")
-SOURCES = ["abi.hip", "band_scatter.hip", "density.hip", "exchange.hip", "spectral_fft.hip", "spectral_gemm.hip",
+SOURCES = ["abi.hip", "band_scatter.hip", "density.hip", "driver.hip", "exchange.hip", "spectral_fft.hip", "spectral_gemm.hip",
            "wirelength.hip"]
 ARCH = os.environ.get("FFTPL_OFFLOAD_ARCH", "gfx950")
 FLAGS = [

@@ -538,6 +538,37 @@ int fftpl_xindex_build(int32_t num_cells, int32_t num_nets, int32_t num_pins,
   return xch_build(d, net_ptr, pin_cell, index, work, as_stream(stream));
 }
 
+int fftpl_step_stats(int32_t num_cells, const float* ux, const float* uy, const float* upx,
+                     const float* upy, const float* gx, const float* gy, const float* gpx,
+                     const float* gpy, double* out4, double* work, uint64_t work_doubles,
+                     void* stream) {
+  if (num_cells < 0 || !out4 || !work || work_doubles < step_stats_work_doubles())
+    return FFTPL_E_INVAL;
+  if (num_cells > 0 && (!ux || !uy || !gx || !gy)) return FFTPL_E_INVAL;
+  const bool prev = upx || upy || gpx || gpy;
+  if (prev && (!upx || !upy || !gpx || !gpy)) return FFTPL_E_INVAL;
+  return dev_status(launch_step_stats(num_cells, ux, uy, upx, upy, gx, gy, gpx, gpy, out4, work,
+                                      as_stream(stream)));
+}
+
+int fftpl_nesterov_update(const fftpl_grid* region, int32_t num_cells, const float* w,
+                          const float* h, float* x, float* y, float* ux, float* uy, float* upx,
+                          float* upy, float* gpx, float* gpy, const float* gx, const float* gy,
+                          float step, float beta, void* stream) {
+  if (!grid_ok(region) || num_cells < 0) return FFTPL_E_INVAL;
+  if (!isfinite(step) || step < 0.0f || !isfinite(beta) || beta < 0.0f || beta >= 1.0f)
+    return FFTPL_E_INVAL;
+  if (num_cells > 0 &&
+      (!w || !h || !x || !y || !ux || !uy || !upx || !upy || !gpx || !gpy || !gx || !gy))
+    return FFTPL_E_INVAL;
+  const float xl = (float)region->xl, yl = (float)region->yl;
+  const float xh = (float)(region->xl + region->n * region->bin_w);
+  const float yh = (float)(region->yl + region->n * region->bin_h);
+  return dev_status(launch_nesterov_update(num_cells, x, y, ux, uy, upx, upy, gpx, gpy, gx, gy,
+                                           w, h, step, beta, xl, yl, xh, yh,
+                                           as_stream(stream)));
+}
+
 int fftpl_debug_cell_bins(const fftpl_grid* grid, int32_t num_cells, const float* x,
                           const float* y, const float* w, const float* h,
                           int32_t* ranges, void* stream) {

@@ -1,0 +1,129 @@
+// Device side of the global placement iteration (Algorithm 1, the update of
+// the positions after each gradient evaluation): the reductions that pick the
+// step length and the Nesterov update of the cell centres.
+//
+// Step statistics, in double, from per-block partials summed in a fixed order:
+//   out[0] = sum |u - u_prev|^2    (both axes)
+//   out[1] = sum |g - g_prev|^2
+//   out[2] = max |g|               (largest gradient component)
+//   out[3] = sum |g|_1
+// Update, per cell and axis, with the look-ahead point u at which g was taken:
+//   x_new = clamp(u - step * g),  u_new = clamp(x_new + beta (x_new - x)),
+//   u_prev = u, g_prev = g, x = x_new, u = u_new,
+// where clamp keeps the cell inside the placement region.
+#include <math.h>
+
+#include "fftpl_internal.hpp"
+
+namespace fftpl {
+
+namespace {
+
+constexpr int kStatBlocks = 256;
+constexpr int kStatThreads = 256;
+
+__global__ void __launch_bounds__(kStatThreads)
+    k_step_stats(int m, const float* __restrict__ ux, const float* __restrict__ uy,
+                 const float* __restrict__ upx, const float* __restrict__ upy,
+                 const float* __restrict__ gx, const float* __restrict__ gy,
+                 const float* __restrict__ gpx, const float* __restrict__ gpy,
+                 double* __restrict__ part) {
+  double du = 0.0, dg = 0.0, gs = 0.0;
+  float gm = 0.0f;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
+    const float a = gx[i], b = gy[i];
+    if (upx) {
+      const double ex = (double)ux[i] - upx[i], ey = (double)uy[i] - upy[i];
+      const double fx = (double)a - gpx[i], fy = (double)b - gpy[i];
+      du += ex * ex + ey * ey;
+      dg += fx * fx + fy * fy;
+    }
+    gm = fmaxf(gm, fmaxf(fabsf(a), fabsf(b)));
+    gs += (double)fabsf(a) + fabsf(b);
+  }
+  block_sum_to<false>(du, &part[blockIdx.x]);
+  block_sum_to<false>(dg, &part[gridDim.x + blockIdx.x]);
+  block_sum_to<false>(gs, &part[3 * gridDim.x + blockIdx.x]);
+  // max of non-negative floats: exact in any order
+  __shared__ float wm[kStatThreads / kWave];
+  gm = wave_max(gm);
+  if ((threadIdx.x & (kWave - 1)) == 0) wm[threadIdx.x / kWave] = gm;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float v = 0.0f;
+    for (int k = 0; k < kStatThreads / kWave; ++k) v = fmaxf(v, wm[k]);
+    part[2 * gridDim.x + blockIdx.x] = v;
+  }
+}
+
+__global__ void __launch_bounds__(64)
+    k_step_stats_final(const double* __restrict__ part, int nblk, double* __restrict__ out) {
+  const int j = threadIdx.x;
+  if (j < 4) {
+    double v = 0.0;
+    for (int b = 0; b < nblk; ++b) {
+      const double p = part[j * nblk + b];
+      v = j == 2 ? fmax(v, p) : v + p;
+    }
+    out[j] = v;
+  }
+}
+
+__device__ __forceinline__ float clampc(float v, float lo, float hi) {
+  return lo <= hi ? fminf(fmaxf(v, lo), hi) : 0.5f * (lo + hi);
+}
+
+__global__ void __launch_bounds__(256)
+    k_nesterov_update(int m, float* __restrict__ x, float* __restrict__ y,
+                      float* __restrict__ ux, float* __restrict__ uy,
+                      float* __restrict__ upx, float* __restrict__ upy,
+                      float* __restrict__ gpx, float* __restrict__ gpy,
+                      const float* __restrict__ gx, const float* __restrict__ gy,
+                      const float* __restrict__ w, const float* __restrict__ h, float step,
+                      float beta, float xl, float yl, float xh, float yh) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const float hw = 0.5f * w[i], hh = 0.5f * h[i];
+  const float ax = ux[i], ay = uy[i], bx = gx[i], by = gy[i];
+  const float nx = clampc(ax - step * bx, xl + hw, xh - hw);
+  const float ny = clampc(ay - step * by, yl + hh, yh - hh);
+  const float vx = clampc(nx + beta * (nx - x[i]), xl + hw, xh - hw);
+  const float vy = clampc(ny + beta * (ny - y[i]), yl + hh, yh - hh);
+  upx[i] = ax;
+  upy[i] = ay;
+  gpx[i] = bx;
+  gpy[i] = by;
+  x[i] = nx;
+  y[i] = ny;
+  ux[i] = vx;
+  uy[i] = vy;
+}
+
+}  // namespace
+
+size_t step_stats_work_doubles() { return 4 * (size_t)kStatBlocks; }
+
+hipError_t launch_step_stats(int m, const float* ux, const float* uy, const float* upx,
+                             const float* upy, const float* gx, const float* gy,
+                             const float* gpx, const float* gpy, double* out, double* work,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_step_stats, dim3(kStatBlocks), dim3(kStatThreads), 0, s, m, ux, uy,
+                     upx, upy, gx, gy, gpx, gpy, work);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_step_stats_final, dim3(1), dim3(64), 0, s, work, kStatBlocks, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_nesterov_update(int m, float* x, float* y, float* ux, float* uy, float* upx,
+                                  float* upy, float* gpx, float* gpy, const float* gx,
+                                  const float* gy, const float* w, const float* h, float step,
+                                  float beta, float xl, float yl, float xh, float yh,
+                                  hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_nesterov_update, dim3((m + 255) / 256), dim3(256), 0, s, m, x, y, ux,
+                     uy, upx, upy, gpx, gpy, gx, gy, w, h, step, beta, xl, yl, xh, yh);
+  return hipGetLastError();
+}
+
+}  // namespace fftpl

@@ -536,6 +536,18 @@ hipError_t launch_gather_xch(const GridF& g, int m, const float* x, const float*
                              const int32_t* cell_ptr, const int32_t* qa, const float2* T,
                              float* gx, float* gy, hipStream_t s);
 
+// ---- placement iteration (driver.hip) --------------------------------------
+size_t step_stats_work_doubles();
+hipError_t launch_step_stats(int m, const float* ux, const float* uy, const float* upx,
+                             const float* upy, const float* gx, const float* gy,
+                             const float* gpx, const float* gpy, double* out, double* work,
+                             hipStream_t s);
+hipError_t launch_nesterov_update(int m, float* x, float* y, float* ux, float* uy, float* upx,
+                                  float* upy, float* gpx, float* gpy, const float* gx,
+                                  const float* gy, const float* w, const float* h, float step,
+                                  float beta, float xl, float yl, float xh, float yh,
+                                  hipStream_t s);
+
 // Spectral solve.  psi/ex/ey/exy may be null individually.  en_part, if set,
 // receives n/2 per-block partials of the energy sum rho*psi; tau_part, if
 // set, n values: per-block pairs (overflow, movable area) of the first pass,

@@ -1,0 +1,223 @@
+"""Global placement loop around the evaluation (Algorithm 1).
+
+Each iteration evaluates f = W~ + lambda N and its gradient at the look-ahead
+point (fftpl_eval), reduces the step statistics on the device
+(fftpl_step_stats) and moves every cell (fftpl_nesterov_update).  The host
+only reads eight doubles per iteration (the scalars and the statistics) to
+set the next step length, lambda and gamma.
+
+Schedules (Section IV-A):
+* step length: a Barzilai-Borwein estimate |du| / |dg| of the inverse
+  Lipschitz constant, expressed as the largest cell displacement and kept in
+  [alpha_min, alpha_max] with alpha_max_0 = 0.044 bin widths,
+  alpha_max_k = max(alpha_max_0, 2 alpha_k), alpha_min = 0.01 alpha_max;
+* gamma = 8 w_b 10^(20/9 (tau - 0.1) - 1) from the current overflow tau;
+* lambda_0 = sum |grad W~| / sum |grad N| at the start; then either doubled
+  every ``lam_every`` iterations, or the paper's mu_k = 1.1^(1 - dW / 3.5e5)
+  bounded to [0.75, 1.1] from the HPWL change;
+* optional stop when tau <= 0.1;
+* the momentum restarts (a = 1) whenever lambda doubles: the penalty term
+  then changes the landscape, and momentum built on the old one makes the
+  late, density-dominated iterations wander (overflow and wirelength grow
+  again after a few hundred iterations without the restart).
+The paper's inner solver is nonlinear CG; this loop uses Nesterov's method
+(the same gradient, no line search), so one evaluation per iteration.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import math
+from typing import Callable, Dict, Iterable, List, Optional
+
+import numpy as np
+import torch
+
+from . import _lib, fftpl
+
+
+def gamma_of_tau(tau: float, bin_w: float) -> float:
+    """Section IV-A: gamma = 8 w_b 10^(20/9 (tau - 0.1) - 1)."""
+    return 8.0 * bin_w * 10.0 ** (20.0 / 9.0 * (tau - 0.1) - 1.0)
+
+
+def mu_of_hpwl_change(dw: float, dw_ref: float = 3.5e5) -> float:
+    """Section IV-A: mu_k = 1.1^(1 - dW/dW_ref), bounded to [0.75, 1.1]."""
+    return min(1.1, max(0.75, 1.1 ** (1.0 - dw / dw_ref)))
+
+
+def nesterov_beta(a: float):
+    """a_{k+1} = (1 + sqrt(4 a_k^2 + 1)) / 2 and beta_k = (a_k - 1) / a_{k+1}."""
+    a1 = 0.5 * (1.0 + math.sqrt(4.0 * a * a + 1.0))
+    return a1, (a - 1.0) / a1
+
+
+def step_length(du2: float, dg2: float, gmax: float, alpha_min: float, alpha_max: float,
+                first: bool) -> float:
+    """Largest cell displacement of this step: alpha_max on the first step,
+    else the BB estimate sqrt(du2/dg2) * gmax kept in [alpha_min, alpha_max]."""
+    if first or dg2 <= 0.0 or du2 <= 0.0:
+        return alpha_max
+    return min(alpha_max, max(alpha_min, math.sqrt(du2 / dg2) * gmax))
+
+
+@dataclasses.dataclass
+class Schedule:
+    lam_mode: str = "double"         # "double" (every lam_every iterations) or "paper"
+    lam_every: int = 50
+    alpha_max0_bins: float = 0.044
+    stop_tau: Optional[float] = None  # stop when tau <= stop_tau (the paper: 0.1)
+    grad_mode: str = "field"
+    restart_on_lambda: bool = True   # restart the momentum when lambda changes
+
+
+class Placer:
+    """Nesterov global placement on one device.  ``inst`` gives the netlist,
+    sizes, fixed maps and starting positions."""
+
+    def __init__(self, inst, dct: str = "fft", schedule: Schedule = Schedule(),
+                 stream=None):
+        self.inst = inst
+        self.sched = schedule
+        self.prob = fftpl.Problem.from_instance(inst, stream=stream)
+        self.plan = fftpl.Plan(inst.n, dct)
+        self.region = fftpl.Grid.of(inst)
+        m = inst.num_cells
+        dev = "cuda"
+        f32 = dict(dtype=torch.float32, device=dev)
+        self.x = torch.as_tensor(inst.x, dtype=torch.float32).to(dev).contiguous()
+        self.y = torch.as_tensor(inst.y, dtype=torch.float32).to(dev).contiguous()
+        self.ux, self.uy = self.x.clone(), self.y.clone()
+        self.upx, self.upy = torch.zeros(m, **f32), torch.zeros(m, **f32)
+        self.gpx, self.gpy = torch.zeros(m, **f32), torch.zeros(m, **f32)
+        self.gx, self.gy = torch.empty(m, **f32), torch.empty(m, **f32)
+        self.scal = torch.zeros(8, dtype=torch.float64, device=dev)   # out4 | stats
+        self.work = torch.empty(1024, dtype=torch.float64, device=dev)
+        self.k = 0
+        self.a = 1.0
+        bw = float(inst.bin_w)
+        self.alpha_max0 = schedule.alpha_max0_bins * bw
+        self.alpha_max = self.alpha_max0
+        self.alpha_min = 0.01 * self.alpha_max
+        self.gamma = gamma_of_tau(1.0, bw)
+        self.lam = None
+        self.last_hpwl = None
+        self.history: List[Dict[str, float]] = []
+
+    # -- device calls ------------------------------------------------------
+    def _eval(self, lam: float, gamma: float, gx=None, gy=None):
+        fftpl.eval(self.plan, self.prob, self.ux, self.uy, lam, gamma, self.sched.grad_mode,
+                   self.gx if gx is None else gx, self.gy if gy is None else gy, self.scal[:4])
+
+    def _stats(self, first: bool):
+        lib = _lib.load()
+        p = fftpl._ptr
+        none = None
+        st = lib.fftpl_step_stats(
+            self.inst.num_cells, p(self.ux), p(self.uy),
+            none if first else p(self.upx), none if first else p(self.upy),
+            p(self.gx), p(self.gy), none if first else p(self.gpx),
+            none if first else p(self.gpy), p(self.scal) + 32, p(self.work),
+            self.work.numel(), fftpl._stream(None))
+        fftpl._check(st, "fftpl_step_stats")
+
+    def _update(self, step: float, beta: float):
+        lib = _lib.load()
+        p = fftpl._ptr
+        a = self.prob.arrays
+        st = lib.fftpl_nesterov_update(
+            ctypes.byref(self.region.c()), self.inst.num_cells, p(a["w"]), p(a["h"]),
+            p(self.x), p(self.y), p(self.ux), p(self.uy), p(self.upx), p(self.upy),
+            p(self.gpx), p(self.gpy), p(self.gx), p(self.gy), float(step), float(beta),
+            fftpl._stream(None))
+        fftpl._check(st, "fftpl_nesterov_update")
+
+    def initial_lambda(self) -> float:
+        """lambda_0 = sum |grad W~| / sum |grad N| at the current positions."""
+        m = self.inst.num_cells
+        g0x, g0y = torch.empty(m, device="cuda"), torch.empty(m, device="cuda")
+        self._eval(0.0, self.gamma, g0x, g0y)
+        self._eval(1.0, self.gamma)
+        gw = float(g0x.abs().sum() + g0y.abs().sum())
+        gn = float((self.gx - g0x).abs().sum() + (self.gy - g0y).abs().sum())
+        return gw / gn if gn > 0 else 1.0
+
+    # -- the loop ----------------------------------------------------------
+    def step(self, on_eval: Optional[Callable[["Placer"], None]] = None) -> Dict[str, float]:
+        if self.lam is None:
+            self.lam = self.initial_lambda()
+        first = self.k == 0
+        self._eval(self.lam, self.gamma)
+        self._stats(first)
+        s = self.scal.cpu().numpy()        # one 64-byte read per iteration
+        N, W, H, tau, du2, dg2, gmax, _ = (float(v) for v in s)
+        if on_eval is not None:
+            on_eval(self)
+        alpha = step_length(du2, dg2, gmax, self.alpha_min, self.alpha_max, first)
+        a1, beta = nesterov_beta(self.a)
+        self._update(alpha / gmax if gmax > 0 else 0.0, beta)
+        rec = dict(k=self.k, energy=N, wa=W, hpwl=H, tau=tau, lam=self.lam, gamma=self.gamma,
+                   alpha=alpha)
+        self.history.append(rec)
+        # next iteration's parameters
+        self.a = a1
+        self.alpha_max = max(self.alpha_max0, 2.0 * alpha)
+        self.alpha_min = 0.01 * self.alpha_max
+        self.gamma = gamma_of_tau(tau, float(self.inst.bin_w))
+        if self.sched.lam_mode == "double":
+            if (self.k + 1) % self.sched.lam_every == 0:
+                self.lam *= 2.0
+                if self.sched.restart_on_lambda:
+                    self.a = 1.0
+        else:
+            if self.last_hpwl is not None:
+                self.lam *= mu_of_hpwl_change(H - self.last_hpwl)
+        self.last_hpwl = H
+        self.k += 1
+        return rec
+
+    def run(self, iters: int, on_eval: Optional[Callable[["Placer"], None]] = None
+            ) -> List[Dict[str, float]]:
+        for _ in range(iters):
+            rec = self.step(on_eval)
+            if self.sched.stop_tau is not None and rec["tau"] <= self.sched.stop_tau:
+                break
+        return self.history
+
+    # -- checkpoint / resume -------------------------------------------------
+    def state(self) -> Dict[str, np.ndarray]:
+        torch.cuda.synchronize()
+        st = {name: getattr(self, name).cpu().numpy()
+              for name in ("x", "y", "ux", "uy", "upx", "upy", "gpx", "gpy")}
+        scal = dict(k=self.k, a=self.a, alpha_max=self.alpha_max, alpha_min=self.alpha_min,
+                    gamma=self.gamma, lam=np.nan if self.lam is None else self.lam,
+                    last_hpwl=np.nan if self.last_hpwl is None else self.last_hpwl)
+        st["scalars"] = np.array([scal[k] for k in sorted(scal)], np.float64)
+        st["scalar_names"] = np.array(sorted(scal))
+        keys = sorted(self.history[0]) if self.history else []
+        st["history"] = np.array([[h[k] for k in keys] for h in self.history], np.float64)
+        st["history_names"] = np.array(keys)
+        return st
+
+    def save(self, path: str) -> None:
+        np.savez(path, **self.state())
+
+    def load(self, path: str) -> None:
+        d = np.load(path, allow_pickle=False)
+        for name in ("x", "y", "ux", "uy", "upx", "upy", "gpx", "gpy"):
+            getattr(self, name).copy_(torch.as_tensor(d[name]))
+        sc = dict(zip([str(s) for s in d["scalar_names"]], d["scalars"].tolist()))
+        self.k = int(sc["k"])
+        self.a = sc["a"]
+        self.alpha_max, self.alpha_min = sc["alpha_max"], sc["alpha_min"]
+        self.gamma = sc["gamma"]
+        self.lam = None if math.isnan(sc["lam"]) else sc["lam"]
+        self.last_hpwl = None if math.isnan(sc["last_hpwl"]) else sc["last_hpwl"]
+        names = [str(s) for s in d["history_names"]]
+        self.history = [dict(zip(names, row.tolist())) for row in d["history"]]
+        for h in self.history:
+            h["k"] = int(h["k"])
+        torch.cuda.synchronize()
+
+    def close(self) -> None:
+        self.plan.close()

@@ -1,0 +1,141 @@
+"""Global placement loop: the device update and statistics kernels against
+numpy, per-evaluation parity with the FP64 oracle at sampled iterations of a
+1000-iteration Nesterov run on the 200k-cell workload, and checkpoint /
+resume."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+from _helpers import rel_l2
+from tests.gpu_common import RTOL, dev, host, lib_or_build, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def F():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    lib_or_build()
+    from paper_1312_4587_amd import _lib, driver, fftpl
+    return fftpl, driver, _lib
+
+
+def test_update_and_statistics_kernels(F):
+    import torch
+    fftpl, driver, L = F
+    lib = L.load()
+    rng = np.random.default_rng(9)
+    m = 50_001
+    inst = gen.make_instance(9, num_cells=m, util=0.7, n=64, num_nets=10)
+    grid = fftpl.Grid.of(inst)
+    side = grid.n * grid.bin_w
+    w = rng.integers(1, 5, m).astype(np.float32)
+    h = np.ones(m, np.float32)
+    w[0] = 2.0 * side                                   # wider than the region
+    arr = {k: rng.uniform(-5, side + 5, m).astype(np.float32) for k in ("x", "y", "ux", "uy")}
+    g = {k: rng.normal(0, 3, m).astype(np.float32) for k in ("gx", "gy", "gpx", "gpy")}
+    up = {k: rng.uniform(0, side, m).astype(np.float32) for k in ("upx", "upy")}
+    d = {k: dev(v) for k, v in {**arr, **g, **up, "w": w, "h": h}.items()}
+    out = torch.zeros(4, dtype=torch.float64, device="cuda")
+    work = torch.empty(1024, dtype=torch.float64, device="cuda")
+    p = fftpl._ptr
+    assert lib.fftpl_step_stats(m, p(d["ux"]), p(d["uy"]), p(d["upx"]), p(d["upy"]), p(d["gx"]),
+                                p(d["gy"]), p(d["gpx"]), p(d["gpy"]), p(out), p(work), 1024,
+                                None) == 0
+    o = host(out)
+    f64 = {k: v.astype(np.float64) for k, v in {**arr, **g, **up}.items()}
+    assert o[0] == pytest.approx(np.sum((f64["ux"] - f64["upx"]) ** 2 + (f64["uy"] - f64["upy"]) ** 2), rel=1e-12)
+    assert o[1] == pytest.approx(np.sum((f64["gx"] - f64["gpx"]) ** 2 + (f64["gy"] - f64["gpy"]) ** 2), rel=1e-12)
+    assert o[2] == max(np.abs(g["gx"]).max(), np.abs(g["gy"]).max())
+    assert o[3] == pytest.approx(np.sum(np.abs(f64["gx"]) + np.abs(f64["gy"])), rel=1e-12)
+    step, beta = 0.37, 0.6
+    assert lib.fftpl_nesterov_update(ctypes.byref(grid.c()), m, p(d["w"]), p(d["h"]), p(d["x"]),
+                                     p(d["y"]), p(d["ux"]), p(d["uy"]), p(d["upx"]), p(d["upy"]),
+                                     p(d["gpx"]), p(d["gpy"]), p(d["gx"]), p(d["gy"]), step, beta,
+                                     None) == 0
+    lo_x, hi_x = grid.xl + 0.5 * w, grid.xl + side - 0.5 * w
+    lo_y, hi_y = grid.yl + 0.5 * h, grid.yl + side - 0.5 * h
+
+    def clamp(v, lo, hi):
+        return np.where(lo <= hi, np.minimum(np.maximum(v, lo), hi), 0.5 * (lo + hi))
+    nx = clamp(f64["ux"] - step * f64["gx"], lo_x, hi_x)
+    ny = clamp(f64["uy"] - step * f64["gy"], lo_y, hi_y)
+    vx = clamp(nx + beta * (nx - f64["x"]), lo_x, hi_x)
+    vy = clamp(ny + beta * (ny - f64["y"]), lo_y, hi_y)
+    for name, ref in (("x", nx), ("y", ny), ("ux", vx), ("uy", vy)):
+        assert np.max(np.abs(host(d[name]) - ref)) < 1e-4, name
+    assert np.array_equal(host(d["upx"]), arr["ux"]) and np.array_equal(host(d["gpy"]), g["gy"])
+    assert host(d["x"])[0] == pytest.approx(grid.xl + 0.5 * side)
+
+
+def test_placement_run_mid_200k_parity_at_sampled_iterations(F):
+    # 1000 Nesterov iterations with lambda doubling every 50; at k = 0, 1, 10,
+    # 100, 999 the evaluation at the look-ahead point is checked against the
+    # oracle on the same positions, and the overflow must fall
+    import torch
+    fftpl, driver, _ = F
+    inst = gen.make_config("mid_200k")
+    pl = driver.Placer(inst)
+    snaps = {}
+
+    def grab(p):
+        if p.k in (0, 1, 10, 100, 999):
+            snaps[p.k] = dict(x=host(p.ux), y=host(p.uy), gx=host(p.gx), gy=host(p.gy),
+                              s=host(p.scal)[:4].copy(), lam=p.lam, gamma=p.gamma)
+    import time
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = pl.run(1000, on_eval=grab)
+    torch.cuda.synchronize()
+    say("1000 iterations", time.perf_counter() - t0, "s; tau", hist[0]["tau"], "->",
+        hist[-1]["tau"], "hpwl", hist[0]["hpwl"], "->", hist[-1]["hpwl"])
+    assert len(hist) == 1000
+    assert hist[-1]["tau"] < 0.5 * hist[0]["tau"]
+    assert hist[-1]["hpwl"] < 0.6 * hist[0]["hpwl"]
+    assert all(np.isfinite(h["hpwl"]) and h["hpwl"] > 0 for h in hist)
+    for k, sn in sorted(snaps.items()):
+        ik = inst.with_positions(sn["x"], sn["y"])
+        ref = oracle.evaluate(ik, lam=sn["lam"], gamma=sn["gamma"], grad_mode="field")
+        N, W, H, tau = sn["s"]
+        e = rel_l2(np.concatenate([sn["gx"], sn["gy"]]), np.concatenate([ref["gx"], ref["gy"]]))
+        say("k", k, "grad rel-L2", e, "tau", tau, ref["overflow"])
+        assert e < RTOL
+        assert abs(N - ref["energy"]) <= RTOL * abs(ref["energy"])
+        assert abs(W - ref["wa"]) <= RTOL * abs(ref["wa"])
+        assert abs(H - ref["hpwl"]) <= RTOL * abs(ref["hpwl"])
+        assert abs(tau - ref["overflow"]) <= RTOL
+    pl.close()
+
+
+def test_checkpoint_and_resume(F, tmp_path):
+    # a saved state reloads bit for bit, and the step taken from it matches the
+    # step the original run takes (trajectories themselves are compared one
+    # step at a time: the density scatter adds in LDS in no fixed order, and
+    # momentum amplifies such rounding differences over many steps)
+    fftpl, driver, _ = F
+    inst = gen.make_config("mid_200k")
+    b = driver.Placer(inst)
+    b.run(20)
+    path = str(tmp_path / "ckpt.npz")
+    b.save(path)
+    s20 = b.state()
+    b.step()
+    s21 = b.state()
+    b.close()
+    c = driver.Placer(inst)
+    c.load(path)
+    r20 = c.state()
+    for name in ("x", "y", "ux", "uy", "upx", "upy", "gpx", "gpy", "scalars", "history"):
+        assert np.array_equal(r20[name], s20[name]), name
+    assert c.k == 20 and len(c.history) == 20
+    c.step()
+    r21 = c.state()
+    c.close()
+    for name in ("x", "y", "ux", "uy"):
+        say("one step after resume", name, rel_l2(r21[name], s21[name]))
+        assert rel_l2(r21[name], s21[name]) < 1e-6
+    assert np.allclose(r21["history"], s21["history"], rtol=1e-6, atol=0.0)
