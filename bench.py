@@ -72,7 +72,93 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for the "
                          "FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the serving, placement-loop and differentiation runs")
+    ap.add_argument("--serve-requests", type=int, default=5000)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-pool", type=int, default=32)
+    ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--driver-iters", type=int, default=1000)
     return ap.parse_args()
+
+
+def serving_run(args, dct, count):
+    """The serving workload: Poisson arrivals at --serve-rate of designs with
+    10^4..10^6 cells (log-uniform, a pool of --serve-pool designs), each
+    request uploaded, indexed, evaluated and downloaded; latency from arrival
+    to results in host memory."""
+    import gen
+    from paper_1312_4587_amd import serving
+    pool = gen.serving_pool(args.serve_pool, seed=5)
+    arrivals, designs = gen.serving_stream(count, rate_hz=args.serve_rate,
+                                           pool_size=len(pool), seed=5)
+    ex = serving.DeviceExecutor(pool, slots=args.serve_slots, dct=dct)
+    ex.warm()
+    srv = serving.Server(ex, ex.footprint, slots=args.serve_slots, capacity_bytes=200e9)
+    st = srv.run(arrivals, designs)
+    ex.close()
+    cells = [p.num_cells for p in pool]
+    st.update(dct=dct, rate_hz=args.serve_rate, slots=args.serve_slots,
+              pool=len(pool), pool_cells_min=int(min(cells)), pool_cells_max=int(max(cells)),
+              capacity_bytes=200e9)
+    return st
+
+
+def driver_run(args):
+    """The placement loop on the 200k-cell workload: Nesterov iterations with
+    lambda doubling every 50, each one full evaluation plus the update."""
+    import gen
+    import torch
+    from paper_1312_4587_amd import driver
+    inst = gen.make_config("mid_200k")
+    pl = driver.Placer(inst)
+    pl.step()                      # lambda_0 and the first step outside the timing
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = pl.run(args.driver_iters - 1)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    pl.close()
+    pick = [h for h in hist if h["k"] in (0, 1, 10, 100, 200, 500, args.driver_iters - 1)]
+    return {"workload": "mid_200k", "cells": inst.num_cells, "grid_n": inst.n,
+            "iterations": len(hist), "ms_per_iteration": 1e3 * dt / max(1, len(hist) - 1),
+            "iterations_per_s": (len(hist) - 1) / dt,
+            "trajectory": [{k: h[k] for k in ("k", "tau", "hpwl", "lam", "gamma")}
+                           for h in pick]}
+
+
+def autograd_run():
+    """The differentiation workload: W~ + lambda N through the autograd
+    function on 500k cells, n = 512 (backward recomputes the solve)."""
+    import gen
+    import torch
+    from paper_1312_4587_amd import autograd, fftpl
+    inst = gen.make_config("diff_500k")
+    prob = fftpl.Problem.from_instance(inst)
+    plan = fftpl.Plan(inst.n, "fft")
+    x = torch.as_tensor(inst.x).cuda().requires_grad_(True)
+    y = torch.as_tensor(inst.y).cuda().requires_grad_(True)
+    for _ in range(3):
+        loss, _ = autograd.objective(x, y, plan, prob, 1.0, inst.gamma)
+        loss.backward()
+    reps = 20
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    tf = tb = 0.0
+    for _ in range(reps):
+        x.grad = None
+        y.grad = None
+        ev[0].record()
+        loss, _ = autograd.objective(x, y, plan, prob, 1.0, inst.gamma)
+        ev[1].record()
+        loss.backward()
+        ev[2].record()
+        torch.cuda.synchronize()
+        tf += ev[0].elapsed_time(ev[1])
+        tb += ev[1].elapsed_time(ev[2])
+    plan.close()
+    return {"workload": "diff_500k", "cells": inst.num_cells, "grid_n": inst.n,
+            "forward_ms": tf / reps, "backward_ms": tb / reps,
+            "saved_tensors": "positions only (backward recomputes density and solve)"}
 
 
 def band_entries(inst):
@@ -338,6 +424,18 @@ def main():
                                             inst, prob, gx, gy)
     for p in plans.values():
         p.close()
+    if not args.no_forms:
+        del prob
+        torch.cuda.empty_cache()
+        res["driver"] = driver_run(args)
+        res["differentiation"] = autograd_run()
+        torch.cuda.empty_cache()
+        sv = serving_run(args, "fft", args.serve_requests)
+        res["serving"] = {"fft": sv,
+                          "gemm_bf16x3": serving_run(args, "gemm_bf16x3",
+                                                     max(1, args.serve_requests // 5))}
+        res["served_p50_ms"] = sv["p50_ms"]
+        res["served_p99_ms"] = sv["p99_ms"]
     print(json.dumps(res), flush=True)
 
 

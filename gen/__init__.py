@@ -8,6 +8,8 @@ from .instances import (  # noqa: F401
     Instance,
     make_instance,
     make_config,
+    serving_pool,
     serving_requests,
+    serving_stream,
     CONFIGS,
 )

@@ -230,3 +230,30 @@ def serving_requests(count: int = 5000, rate_hz: float = 200.0,
             inst = make_instance((seed, r), num_cells=m, util=0.70, n=n,
                                  num_nets=int(round(1.1 * m)))
         yield r, float(arrivals[r]), inst, m, n
+
+
+def serving_pool(size: int = 64, m_range: Tuple[float, float] = (1e4, 1e6),
+                 seed: int = 5) -> list:
+    """``size`` designs for the serving stream, cell counts log-uniform over
+    ``m_range`` (design ``i`` drawn from seed ``(seed, 1, i)``), each with nets
+    1.1*m of the base degree mix, utilisation 0.7, no macros and the grid side
+    of ``serving_grid_size``."""
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 0]))
+    logm = rng.uniform(math.log(m_range[0]), math.log(m_range[1]), size=size)
+    pool = []
+    for i in range(size):
+        m = int(round(math.exp(logm[i])))
+        pool.append(make_instance((seed, 1, i), num_cells=m, util=0.70,
+                                  n=serving_grid_size(m), num_nets=int(round(1.1 * m))))
+    return pool
+
+
+def serving_stream(count: int = 5000, rate_hz: float = 200.0, pool_size: int = 64,
+                   seed: int = 5) -> Tuple[np.ndarray, np.ndarray]:
+    """Poisson arrivals (exponential gaps of mean 1/rate_hz, first at 0) and,
+    per request, the index of its design in a pool of ``pool_size``."""
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 2]))
+    gaps = rng.exponential(1.0 / rate_hz, size=count)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    design = rng.integers(0, pool_size, size=count)
+    return arrivals, design
