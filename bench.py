@@ -25,18 +25,30 @@ BF16_PEAK_TFLOPS = 2500.0
 # HBM traffic per launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE (KiB per
 # dispatch) on the 2.1M-cell workload, scaled by what the same counters read
 # for a plain 256 MiB device copy in the same run (FETCH_SIZE x2.0, WRITE_SIZE
-# x1.0).  Each entry records the SHA-1 of the kernel's source file when the
-# counters were taken; once that source changes the figure is stale and the
-# report gives null.
+# x1.0).  Each entry records the SHA-1 of the kernel's source files when the
+# counters were taken; once they change the figure is stale and the report
+# gives null.
 PMC_FETCH_SCALE, PMC_WRITE_SCALE = 2.0, 1.0
 PMC_TRAFFIC = {
-    # kernel: (source file, sha1, FETCH_SIZE KiB, WRITE_SIZE KiB)
-    "k_wa_slots_big": ("wirelength.hip", "922ee75d6507e0a8b2b756700c4304a5dad417d3",
-                       373752.1, 182874.7),
-    "k_wa_slots_small": ("wirelength.hip", "922ee75d6507e0a8b2b756700c4304a5dad417d3",
-                         441270.0, 206730.2),
-    "k_gather_pins": ("density.hip", "0a8d2c3c9113b790e05a6f689bfa3d07d7c16f9f",
-                      204727.2, 16406.2),
+    # kernel: (source files, sha1, FETCH_SIZE KiB, WRITE_SIZE KiB)
+    "k_xch_spread": (("exchange.hip", "fftpl_internal.hpp"),
+                     "b95c39bfae32e7c571cc3b51923f15b8065c0633", 28568.9, 96804.8),
+    "k_xch_wa": (("exchange.hip", "fftpl_internal.hpp"),
+                 "b95c39bfae32e7c571cc3b51923f15b8065c0633", 190057.8, 116215.7),
+    "k_gather_xch": (("density.hip", "fftpl_internal.hpp"),
+                     "c343ae05da83ba4a2d83d392b897c0e853905d47", 260405.8, 16406.2),
+    "k_band_count": (("band_scatter.hip", "fftpl_internal.hpp"),
+                     "2e45a52078ee8073d0e6ef2e6c80b2d1ce6923c9", 16462.8, 258.0),
+    "k_band_place": (("band_scatter.hip", "fftpl_internal.hpp"),
+                     "2e45a52078ee8073d0e6ef2e6c80b2d1ce6923c9", 16528.8, 36965.4),
+    "k_band_accum": (("band_scatter.hip", "fftpl_internal.hpp"),
+                     "2e45a52078ee8073d0e6ef2e6c80b2d1ce6923c9", 20115.6, 4096.0),
+    "k_rows_dct2": (("spectral_fft.hip", "fftpl_internal.hpp"),
+                    "67b3b3149ae902dd0fa74dc14dae95fb132ce129", 6287.7, 4112.0),
+    "k_cols_solve": (("spectral_fft.hip", "fftpl_internal.hpp"),
+                     "67b3b3149ae902dd0fa74dc14dae95fb132ce129", 2229.1, 8192.0),
+    "k_rows_inverse": (("spectral_fft.hip", "fftpl_internal.hpp"),
+                       "67b3b3149ae902dd0fa74dc14dae95fb132ce129", 6339.6, 8196.0),
 }
 
 
@@ -46,11 +58,13 @@ def pmc_traffic(kernel):
     rec = PMC_TRAFFIC.get(kernel)
     if rec is None:
         return None
-    src, sha, fetch_kib, write_kib = rec
-    path = os.path.join(ROOT, "paper_1312_4587_amd", "csrc", src)
-    with open(path, "rb") as f:
-        if hashlib.sha1(f.read()).hexdigest() != sha:
-            return None
+    srcs, sha, fetch_kib, write_kib = rec
+    h = hashlib.sha1()
+    for src in srcs:
+        with open(os.path.join(ROOT, "paper_1312_4587_amd", "csrc", src), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != sha:
+        return None
     return (PMC_FETCH_SCALE * fetch_kib + PMC_WRITE_SCALE * write_kib) * 1024.0
 
 
