@@ -383,6 +383,10 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
         e = launch_xch_wa(xd, X, prob->net_ptr, prob->pin_dx, prob->pin_dy, gamma,
                           L.pin_grad, L.wa_part, ws);
       plan_mark(p, "k_xch_wa", ws);
+      // per-cell sums of the pin gradients (into the xy region), still on the
+      // wirelength branch so that they overlap the scatter and the solve
+      if (e == hipSuccess && grads) e = launch_xch_pinsum(xd, X, L.pin_grad, L.xy, ws);
+      if (grads) plan_mark(p, "k_xch_pinsum", ws);
     } else {
       if (e == hipSuccess) e = launch_interleave(m, x, y, L.xy, ws);
       plan_mark(p, "k_interleave", ws);
@@ -428,9 +432,9 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
       // scalars only
     } else if (xch) {
       if (e == hipSuccess)
-        e = launch_gather_xch(g, m, x, y, prob->w, prob->h, p.exy, p.psi, grad_mode, lambda,
-                              X.cell_ptr, X.qa, L.pin_grad, gx, gy, s);
-      plan_mark(p, "k_gather_xch", s);
+        e = launch_gather_cellsum(g, m, x, y, prob->w, prob->h, p.exy, p.psi, grad_mode,
+                                  lambda, L.xy, gx, gy, s);
+      plan_mark(p, "k_gather_cellsum", s);
     } else {
       if (e == hipSuccess)
         e = launch_gather_pins(g, m, x, y, prob->w, prob->h, p.exy, p.psi, grad_mode, lambda,

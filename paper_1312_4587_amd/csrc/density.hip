@@ -145,8 +145,9 @@ hipError_t launch_init_eval(double* out4, int32_t* counters, int ncount, hipStre
 // [psi at right edge - psi at left edge] for edges strictly inside (0, n).
 // ---------------------------------------------------------------------------
 // PINS: 0 density gradient only; 1 plus the sum of the cell's contiguous pin
-// slots (cell_ptr, pin_grad); 3 plus the sum of pin_grad[pin_idx[j]] over the
-// cell's entries j of cell_ptr (blocks in XCD order).
+// slots (cell_ptr, pin_grad); 2 plus pin_grad[i] (one float2 per cell); 3
+// plus the sum of pin_grad[pin_idx[j]] over the cell's entries j of cell_ptr
+// (blocks in XCD order).
 template <int MODE, bool INTERLEAVED, int PINS>
 __global__ void __launch_bounds__(256) k_gather(GridF g, int m, const float* __restrict__ x,
                                                 const float* __restrict__ y,
@@ -172,6 +173,10 @@ __global__ void __launch_bounds__(256) k_gather(GridF g, int m, const float* __r
       ax += q.x;
       ay += q.y;
     }
+  } else if (PINS == 2) {
+    const float2 q = pin_grad[i];
+    ax += q.x;
+    ay += q.y;
   } else if (PINS == 1) {
     // the cell's wirelength gradient: its pins' slots are contiguous
     const int k1 = cell_ptr[i + 1];
@@ -229,6 +234,23 @@ hipError_t launch_gather_pins(const GridF& g, int m, const float* x, const float
   } else {
     hipLaunchKernelGGL((k_gather<FFTPL_GRAD_FIELD, true, 1>), grid, block, 0, s, g, m, x,
                        y, w, h, nullptr, nullptr, e2, psi, scale, 0, cell_ptr, pin_grad, nullptr, gx, gy);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_cellsum(const GridF& g, int m, const float* x, const float* y,
+                                 const float* w, const float* h, const float* exy,
+                                 const float* psi, int grad_mode, float scale,
+                                 const float2* gwa, float* gx, float* gy, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  dim3 grid((m + 255) / 256), block(256);
+  const float2* e2 = reinterpret_cast<const float2*>(exy);
+  if (grad_mode == FFTPL_GRAD_EXACT) {
+    hipLaunchKernelGGL((k_gather<FFTPL_GRAD_EXACT, true, 2>), grid, block, 0, s, g, m, x,
+                       y, w, h, nullptr, nullptr, e2, psi, scale, 0, nullptr, gwa, nullptr, gx, gy);
+  } else {
+    hipLaunchKernelGGL((k_gather<FFTPL_GRAD_FIELD, true, 2>), grid, block, 0, s, g, m, x,
+                       y, w, h, nullptr, nullptr, e2, psi, scale, 0, nullptr, gwa, nullptr, gx, gy);
   }
   return hipGetLastError();
 }

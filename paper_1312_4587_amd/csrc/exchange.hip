@@ -655,7 +655,44 @@ __global__ void __launch_bounds__(NW)
   block_sum_to<false>(acc_hp, &part[nblk + k]);
 }
 
+// gwa[c] = sum of the gradients in T of cell c's pins, read at the A
+// positions the index lists per cell.  Blocks in XCD order, so that the
+// window of T of one cell block is read by one L2.
+__global__ void __launch_bounds__(256)
+    k_xch_pinsum(int m, const int32_t* __restrict__ cell_ptr, const int32_t* __restrict__ qa,
+                 const float2* __restrict__ T, float2* __restrict__ gwa) {
+  const int c = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (c >= m) return;
+  const int k0 = cell_ptr[c], k1 = cell_ptr[c + 1];
+  float sx = 0.0f, sy = 0.0f;
+  constexpr int U = 8;
+  for (int k = k0; k < k1; k += U) {
+    int q[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) q[u] = qa[min(k + u, k1 - 1)];
+    float2 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = T[q[u]];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (k + u < k1) {
+        sx += v[u].x;
+        sy += v[u].y;
+      }
+    }
+  }
+  gwa[c] = make_float2(sx, sy);
+}
+
 }  // namespace
+
+hipError_t launch_xch_pinsum(const XchDims& d, const XchIndex& X, const float2* T, float2* gwa,
+                             hipStream_t s) {
+  if (d.m <= 0) return hipSuccess;
+  const int nb = ((d.m + 255) / 256 + kNumXcd - 1) / kNumXcd * kNumXcd;
+  hipLaunchKernelGGL(k_xch_pinsum, dim3(nb), dim3(256), 0, s, d.m, X.cell_ptr, X.qa, T, gwa);
+  return hipGetLastError();
+}
 
 hipError_t launch_xch_spread(const XchDims& d, const XchIndex& X, const float* x,
                              const float* y, float2* T, hipStream_t s) {

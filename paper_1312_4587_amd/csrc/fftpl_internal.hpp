@@ -527,6 +527,14 @@ hipError_t launch_xch_spread(const XchDims& d, const XchIndex& X, const float* x
 hipError_t launch_xch_wa(const XchDims& d, const XchIndex& X, const int32_t* net_ptr,
                          const float* pin_dx, const float* pin_dy, float gamma, float2* T,
                          double* wa_part, hipStream_t s);
+// gwa[c] = sum over cell c's pins of T[qa[j]] (after launch_xch_wa).
+hipError_t launch_xch_pinsum(const XchDims& d, const XchIndex& X, const float2* T, float2* gwa,
+                             hipStream_t s);
+// g = scale * density gradient + gwa[c] (one thread per cell).
+hipError_t launch_gather_cellsum(const GridF& g, int m, const float* x, const float* y,
+                                 const float* w, const float* h, const float* exy,
+                                 const float* psi, int grad_mode, float scale,
+                                 const float2* gwa, float* gx, float* gy, hipStream_t s);
 // g = scale * density gradient + the sum over the cell's pins of T[qa[j]],
 // j in [cell_ptr[c], cell_ptr[c+1]) (one thread per cell; blocks in XCD order
 // so that the T window of a cell block is read by one L2).
