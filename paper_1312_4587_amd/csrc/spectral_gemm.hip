@@ -15,8 +15,9 @@
 //   BF16X3: every float32 operand X is split into bf16 hi = bf16(X) and
 //           lo = bf16(X - hi); each product is Ah Bh + Ah Bl + Al Bh on
 //           v_mfma_f32_16x16x32_bf16 with float32 accumulation.
-// Block tile 64 x 64, four waves of 32 x 32 (2 x 2 MFMA tiles of 16 x 16),
-// K step 32 staged in LDS.  The constant matrices are built once per plan in
+// Block tile 64 x 64, eight waves: four quarters of 32 x 32 (2 x 2 MFMA
+// tiles of 16 x 16) times two halves of every K step of 64, staged in LDS,
+// double-buffered.  The constant matrices are built once per plan in
 // double and rounded (and split) once.
 #include <math.h>
 #include <string.h>
@@ -68,13 +69,19 @@ __device__ __forceinline__ void split_bf16(float v, __bf16& hi, __bf16& lo) {
   lo = (__bf16)(v - (float)hi);
 }
 
-template <bool BF16>
-__global__ void __launch_bounds__(256) k_gemm(GemmArgs g, Epi ep) {
+// KS x 4 waves: wave w works on the 32 x 32 quarter (w & 3) of the tile over
+// the K part (w >> 2) of every K step of TKB = KS * 32; with KS = 2 the two
+// parts' partial tiles are added through LDS before the epilogue (in a fixed
+// order).  KS = 2 doubles the waves per CU for grids of one block per CU.
+template <bool BF16, int KS>
+__global__ void __launch_bounds__(256 * KS) k_gemm(GemmArgs g, Epi ep) {
+  constexpr int TKB = KS * TK;
   const int tiles_n = g.N / TN;
   const int tile = xcd_block(blockIdx.x, gridDim.x);
   const int m0 = (tile / tiles_n) * TM, n0 = (tile % tiles_n) * TN;
   const int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
-  const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+  const int wq = w & 3, wk = w >> 2;
+  const int wm = (wq >> 1) * 32, wn = (wq & 1) * 32;
   const int l16 = lane & 15, lg = lane >> 4;
   f4 acc[2][2];
 #pragma unroll
@@ -82,62 +89,101 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g, Epi ep) {
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
+  // Double-buffered K loop: the next K step's operands are loaded from
+  // global memory into registers while the MFMAs run on the current LDS
+  // tile, then stored to the other LDS buffer; one barrier per step.
+  constexpr int kFloats = 2 * 2 * 2 * TK * (TM + 4);
+  __shared__ __attribute__((aligned(16))) float smem[kFloats];
   if constexpr (!BF16) {
-    __shared__ float As[TK][TM + 4];   // A^T tile: As[k][m]
-    __shared__ float Bs[TK][TN + 4];   // B tile:   Bs[k][n]
+    float(*As)[TKB][TM + 4] = reinterpret_cast<float(*)[TKB][TM + 4]>(smem);   // [buf][k][m]
+    float(*Bs)[TKB][TN + 4] =
+        reinterpret_cast<float(*)[TKB][TN + 4]>(smem + 2 * TKB * (TM + 4));   // [buf][k][n]
     const float* A = static_cast<const float*>(g.a_hi);
     const float* B = static_cast<const float*>(g.b_hi);
-    const int ar = t >> 2, ak = (t & 3) * 8;     // A: row, first k of 8
+    const int ar = t / (TKB / 8), ak = (t % (TKB / 8)) * 8;   // A: row, first k of 8
     const int bk = t >> 3, bn = (t & 7) * 8;     // B: k, first n of 8
-    for (int k0 = 0; k0 < g.K; k0 += TK) {
+    float4 a0, a1, b0, b1;
+    auto fetch = [&](int k0) {
       const float4* sa = reinterpret_cast<const float4*>(A + (size_t)(m0 + ar) * g.lda + k0 + ak);
       const float4* sb = reinterpret_cast<const float4*>(B + (size_t)(k0 + bk) * g.ldb + n0 + bn);
-      const float4 a0 = sa[0], a1 = sa[1], b0 = sb[0], b1 = sb[1];
-      As[ak + 0][ar] = a0.x;
-      As[ak + 1][ar] = a0.y;
-      As[ak + 2][ar] = a0.z;
-      As[ak + 3][ar] = a0.w;
-      As[ak + 4][ar] = a1.x;
-      As[ak + 5][ar] = a1.y;
-      As[ak + 6][ar] = a1.z;
-      As[ak + 7][ar] = a1.w;
-      *reinterpret_cast<float4*>(&Bs[bk][bn]) = b0;
-      *reinterpret_cast<float4*>(&Bs[bk][bn + 4]) = b1;
-      __syncthreads();
+      a0 = sa[0];
+      a1 = sa[1];
+      b0 = sb[0];
+      b1 = sb[1];
+    };
+    auto stash = [&](int buf) {
+      As[buf][ak + 0][ar] = a0.x;
+      As[buf][ak + 1][ar] = a0.y;
+      As[buf][ak + 2][ar] = a0.z;
+      As[buf][ak + 3][ar] = a0.w;
+      As[buf][ak + 4][ar] = a1.x;
+      As[buf][ak + 5][ar] = a1.y;
+      As[buf][ak + 6][ar] = a1.z;
+      As[buf][ak + 7][ar] = a1.w;
+      *reinterpret_cast<float4*>(&Bs[buf][bk][bn]) = b0;
+      *reinterpret_cast<float4*>(&Bs[buf][bk][bn + 4]) = b1;
+    };
+    fetch(0);
+    stash(0);
+    __syncthreads();
+    int cur = 0;
+    for (int k0 = 0; k0 < g.K; k0 += TKB) {
+      const bool more = k0 + TKB < g.K;
+      if (more) fetch(k0 + TKB);
 #pragma unroll
       for (int kk = 0; kk < TK; kk += 4) {
-        const int kq = kk + lg;
-        const float x0 = As[kq][wm + l16], x1 = As[kq][wm + 16 + l16];
-        const float y0 = Bs[kq][wn + l16], y1 = Bs[kq][wn + 16 + l16];
+        const int kq = wk * TK + kk + lg;
+        const float x0 = As[cur][kq][wm + l16], x1 = As[cur][kq][wm + 16 + l16];
+        const float y0 = Bs[cur][kq][wn + l16], y1 = Bs[cur][kq][wn + 16 + l16];
         acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(x0, y0, acc[0][0], 0, 0, 0);
         acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(x0, y1, acc[0][1], 0, 0, 0);
         acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(x1, y0, acc[1][0], 0, 0, 0);
         acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(x1, y1, acc[1][1], 0, 0, 0);
       }
+      if (more) stash(cur ^ 1);
       __syncthreads();
+      cur ^= 1;
     }
   } else {
     // tiles keep 8 consecutive k of one row (A) or one column (B^T) together,
     // which is what one lane feeds to the 16x16x32 bf16 MFMA
-    __shared__ bf8 Ah[TM][TK / 8], Al[TM][TK / 8];
-    __shared__ bf8 Bh[TN][TK / 8], Bl[TN][TK / 8];
+    constexpr int KC = TKB / 8;   // bf8 chunks per row and K step
+    bf8(*Ah)[TM][KC] = reinterpret_cast<bf8(*)[TM][KC]>(smem);
+    bf8(*Al)[TM][KC] = Ah + 2;
+    bf8(*Bh)[TN][KC] = reinterpret_cast<bf8(*)[TN][KC]>(Ah + 4);
+    bf8(*Bl)[TN][KC] = Bh + 2;
     const __bf16* gah = static_cast<const __bf16*>(g.a_hi);
     const __bf16* gal = static_cast<const __bf16*>(g.a_lo);
     const __bf16* gbh = static_cast<const __bf16*>(g.b_hi);
     const __bf16* gbl = static_cast<const __bf16*>(g.b_lo);
-    const int r = t >> 2, kc = t & 3;
-    for (int k0 = 0; k0 < g.K; k0 += TK) {
+    const int r = t / KC, kc = t % KC;
+    bf8 rah, ral, rbh, rbl;
+    auto fetch = [&](int k0) {
       const size_t oa = (size_t)(m0 + r) * g.lda + k0 + kc * 8;
       const size_t ob = (size_t)(n0 + r) * g.ldb + k0 + kc * 8;
-      Ah[r][kc] = *reinterpret_cast<const bf8*>(gah + oa);
-      Al[r][kc] = *reinterpret_cast<const bf8*>(gal + oa);
-      Bh[r][kc] = *reinterpret_cast<const bf8*>(gbh + ob);
-      Bl[r][kc] = *reinterpret_cast<const bf8*>(gbl + ob);
-      __syncthreads();
-      const bf8 xh0 = Ah[wm + l16][lg], xl0 = Al[wm + l16][lg];
-      const bf8 xh1 = Ah[wm + 16 + l16][lg], xl1 = Al[wm + 16 + l16][lg];
-      const bf8 yh0 = Bh[wn + l16][lg], yl0 = Bl[wn + l16][lg];
-      const bf8 yh1 = Bh[wn + 16 + l16][lg], yl1 = Bl[wn + 16 + l16][lg];
+      rah = *reinterpret_cast<const bf8*>(gah + oa);
+      ral = *reinterpret_cast<const bf8*>(gal + oa);
+      rbh = *reinterpret_cast<const bf8*>(gbh + ob);
+      rbl = *reinterpret_cast<const bf8*>(gbl + ob);
+    };
+    auto stash = [&](int buf) {
+      Ah[buf][r][kc] = rah;
+      Al[buf][r][kc] = ral;
+      Bh[buf][r][kc] = rbh;
+      Bl[buf][r][kc] = rbl;
+    };
+    fetch(0);
+    stash(0);
+    __syncthreads();
+    int cur = 0;
+    const int kq = wk * (TK / 8) + lg;
+    for (int k0 = 0; k0 < g.K; k0 += TKB) {
+      const bool more = k0 + TKB < g.K;
+      if (more) fetch(k0 + TKB);
+      const bf8 xh0 = Ah[cur][wm + l16][kq], xl0 = Al[cur][wm + l16][kq];
+      const bf8 xh1 = Ah[cur][wm + 16 + l16][kq], xl1 = Al[cur][wm + 16 + l16][kq];
+      const bf8 yh0 = Bh[cur][wn + l16][kq], yl0 = Bl[cur][wn + l16][kq];
+      const bf8 yh1 = Bh[cur][wn + 16 + l16][kq], yl1 = Bl[cur][wn + 16 + l16][kq];
 #define FFTPL_MFMA3(ACC, XH, XL, YH, YL)                                      \
   ACC = __builtin_amdgcn_mfma_f32_16x16x32_bf16(XH, YH, ACC, 0, 0, 0);        \
   ACC = __builtin_amdgcn_mfma_f32_16x16x32_bf16(XH, YL, ACC, 0, 0, 0);        \
@@ -147,16 +193,39 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g, Epi ep) {
       FFTPL_MFMA3(acc[1][0], xh1, xl1, yh0, yl0)
       FFTPL_MFMA3(acc[1][1], xh1, xl1, yh1, yl1)
 #undef FFTPL_MFMA3
+      if (more) stash(cur ^ 1);
       __syncthreads();
+      cur ^= 1;
     }
   }
 
-  // Epilogue.  Lane l of a 16x16 tile holds column l%16, rows 4*(l/16)+r.
+  // the second K half's partial tile joins the first one's (waves 0-3 keep
+  // going to the epilogue; the loop's last barrier has freed the buffers)
+  if (KS == 2) {
+    f4* red = reinterpret_cast<f4*>(smem);   // [quarter][i][j][lane]
+    if (wk == 1) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) red[((wq * 2 + i) * 2 + j) * kWave + lane] = acc[i][j];
+    }
+    __syncthreads();
+    if (wk == 0) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] += red[((wq * 2 + i) * 2 + j) * kWave + lane];
+    }
+  }
+
+  // Epilogue (waves 0-3).  Lane l of a 16x16 tile holds column l%16, rows
+  // 4*(l/16)+r.
   const int n = ep.n;
   const float inv_n2 = 1.0f / ((float)n * (float)n);
   double en = 0.0;
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
+    if (wk != 0) break;
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       const int col = n0 + wn + 16 * j + l16;
@@ -328,8 +397,12 @@ GemmLayout gemm_layout(int n) {
 
 template <bool BF16>
 hipError_t launch_gemm(const GemmArgs& g, const Epi& ep, hipStream_t s) {
+  // one block per CU or fewer: split K across twice the waves
   const int blocks = (g.M / TM) * (g.N / TN);
-  hipLaunchKernelGGL(k_gemm<BF16>, dim3(blocks), dim3(256), 0, s, g, ep);
+  if (blocks <= 256)
+    hipLaunchKernelGGL((k_gemm<BF16, 2>), dim3(blocks), dim3(512), 0, s, g, ep);
+  else
+    hipLaunchKernelGGL((k_gemm<BF16, 1>), dim3(blocks), dim3(256), 0, s, g, ep);
   return hipGetLastError();
 }
 
