@@ -218,7 +218,8 @@ def kernel_bytes(inst, nent):
         "k_xch_spread": 8 * m + 2 * P + 8 * P,
         "k_xch_wa": 4 * P + 2 * P + 8 * P + 8 * P + 8 * P + 4 * (E + 1) + 2 * E,
         "k_gather_xch": 16 * m + 8 * n2 + 4 * (m + 1) + 4 * P + 8 * P + 8 * m,
-        "k_xch_pinsum": 4 * (m + 1) + 4 * P + 8 * P + 8 * m,
+        # cell-block windows of T with their u16 cell-local indices; sums out
+        "k_xch_cellsum": 2 * P + 8 * P + 8 * m,
         "k_gather_cellsum": 16 * m + 8 * n2 + 8 * m + 8 * m,
         "k_eval_finalize": 0,
     }

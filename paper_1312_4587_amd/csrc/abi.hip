@@ -366,15 +366,17 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
   const bool overlap = fast && !p.timing;
   hipStream_t ws = overlap ? p.side : s;
   if (fast) {
-    // 1. zero scalars and band counters
-    e = launch_init_eval(out4, L.counters, L.nb + 1, s);
-    plan_mark(p, "k_init_eval", s);
-    // wirelength branch: interleave positions, per-pin WA gradients into
-    // cell-major slots
-    if (e == hipSuccess && overlap) {
+    // the wirelength branch reads only the inputs and writes only its own
+    // buffers, so it forks before the zeroing of the scalars and counters
+    if (overlap) {
       e = hipEventRecord(p.fork, s);
       if (e == hipSuccess) e = hipStreamWaitEvent(ws, p.fork, 0);
     }
+    // 1. zero scalars and band counters
+    if (e == hipSuccess) e = launch_init_eval(out4, L.counters, L.nb + 1, s);
+    plan_mark(p, "k_init_eval", s);
+    // wirelength branch: interleave positions, per-pin WA gradients into
+    // cell-major slots
     if (xch) {
       // pin positions into the exchange buffer, then every net block
       if (e == hipSuccess) e = launch_xch_spread(xd, X, x, y, L.pin_grad, ws);
@@ -385,8 +387,8 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
       plan_mark(p, "k_xch_wa", ws);
       // per-cell sums of the pin gradients (into the xy region), still on the
       // wirelength branch so that they overlap the scatter and the solve
-      if (e == hipSuccess && grads) e = launch_xch_pinsum(xd, X, L.pin_grad, L.xy, ws);
-      if (grads) plan_mark(p, "k_xch_pinsum", ws);
+      if (e == hipSuccess && grads) e = launch_xch_cellsum(xd, X, L.pin_grad, L.xy, ws);
+      if (grads) plan_mark(p, "k_xch_cellsum", ws);
     } else {
       if (e == hipSuccess) e = launch_interleave(m, x, y, L.xy, ws);
       plan_mark(p, "k_interleave", ws);

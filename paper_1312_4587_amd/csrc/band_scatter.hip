@@ -8,7 +8,11 @@
 //          band it touches, at LDS-atomic ranks inside the reserved slice,
 //          and the interleaved (x, y) the wirelength pass gathers;
 //   accum: one block per band adds its entries into an LDS copy of its rows
-//          (LDS float atomics) and writes rho = base + rows once.
+//          and writes rho = base + rows once.  The LDS adds are 64-bit
+//          integer adds of the overlaps in fixed point (every overlap lies in
+//          [0, 1], units of 2^-31): they retire many times faster than LDS
+//          float atomics, and the sums do not depend on the order of the
+//          entries, so rho is the same on every run.
 // Every thread issues the loads of kCellBatch cells (or entries) before it
 // uses any of them, so each block keeps many misses in flight.
 #include "fftpl_internal.hpp"
@@ -151,16 +155,23 @@ __global__ void __launch_bounds__(kBandThreads)
   }
 }
 
+// Fixed-point LDS add of an overlap v in [0, 1] (units of 2^-31; a sum of
+// up to 2^32 entries stays inside 64 bits).
+constexpr double kAccUnit = 1.0 / 2147483648.0;
+__device__ __forceinline__ void add_fixed(unsigned long long* a, float v) {
+  atomicAdd(a, (unsigned long long)__float2uint_rn(v * 2147483648.0f));
+}
+
 __global__ void __launch_bounds__(kBandThreads)
     k_band_accum(GridF g, BandLayout L, const float* __restrict__ x,
                  const float* __restrict__ y, const float* __restrict__ w,
                  const float* __restrict__ h, const float* __restrict__ base,
                  float* __restrict__ rho) {
-  __shared__ float acc[kBandMaxN * 4];   // rows * n <= 4096 floats
+  __shared__ unsigned long long acc[kBandMaxN * 4];   // rows * n <= 4096 bins
   const int t = threadIdx.x;
   const int n = g.n, R = L.rows, band = blockIdx.x, r0 = band * R;
   const int cells = min(R, n - r0) * n;
-  for (int k = t; k < cells; k += NT) acc[k] = 0.0f;
+  for (int k = t; k < cells; k += NT) acc[k] = 0ull;
   int start;
   block_exclusive_scan<NT>(t < band ? L.counters[t] : 0, &start);   // earlier bands
   const int end = start + L.counters[band];
@@ -180,8 +191,8 @@ __global__ void __launch_bounds__(kBandThreads)
       const int ya = max(sy.i0, r0), yb = min(sy.i1, r0 + R - 1);
       for (int iy = ya; iy <= yb; ++iy) {
         const float oy = span_overlap(sy, iy);
-        float* row = acc + (iy - r0) * n;
-        for (int ix = sx.i0; ix <= sx.i1; ++ix) atomicAdd(&row[ix], span_overlap(sx, ix) * oy);
+        unsigned long long* row = acc + (iy - r0) * n;
+        for (int ix = sx.i0; ix <= sx.i1; ++ix) add_fixed(&row[ix], span_overlap(sx, ix) * oy);
       }
     }
   }
@@ -197,12 +208,13 @@ __global__ void __launch_bounds__(kBandThreads)
     const int tot = nx * (yb - ya + 1);
     for (int k = t; k < tot; k += NT) {
       const int ix = sx.i0 + k % nx, iy = ya + k / nx;
-      atomicAdd(&acc[(iy - r0) * n + ix], span_overlap(sx, ix) * span_overlap(sy, iy));
+      add_fixed(&acc[(iy - r0) * n + ix], span_overlap(sx, ix) * span_overlap(sy, iy));
     }
   }
   __syncthreads();
   const size_t o = (size_t)r0 * n;
-  for (int k = t; k < cells; k += NT) rho[o + k] = (base ? base[o + k] : 0.0f) + acc[k];
+  for (int k = t; k < cells; k += NT)
+    rho[o + k] = (base ? base[o + k] : 0.0f) + (float)((double)acc[k] * kAccUnit);
 }
 
 // xy[i] = (x[i], y[i]): the wirelength pass then gathers one float2 per pin.

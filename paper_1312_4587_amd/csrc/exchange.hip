@@ -23,10 +23,10 @@
 //           evaluates every net from LDS (one thread per net of degree <= 8,
 //           one wavefront per larger net); writes each pin's gradient back to
 //           its own A position of T, again in runs;
-//   gather  (one thread per cell): the density gradient plus the sum of the
-//           cell's pin gradients, read from T at the A positions the index
-//           lists per cell (cell-major); the blocks of one cell block run on
-//           one XCD, so its window of T is read from HBM once.
+//   cellsum (one block per cell block): streams the cell block's A
+//           range of T and adds every pin's gradient into its cell's
+//           accumulator in LDS (integer fixed point: order-independent);
+//   gather  (one thread per cell): the density gradient plus that sum.
 //
 // The index (A/B layout) is built once per netlist by xch_build.
 #include <math.h>
@@ -46,6 +46,7 @@ constexpr int NW = kXchWaThreads;
 // kXchPinLds2 pins, or up to kXchPinCap
 constexpr int kStageS = (kXchPinLds2 + NW - 1) / NW;
 constexpr int kStageL = (kXchPinCap + NW - 1) / NW;
+constexpr int kSumThreads = 1024;   // cell sums: one block per cell block
 
 inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
@@ -655,42 +656,77 @@ __global__ void __launch_bounds__(NW)
   block_sum_to<false>(acc_hp, &part[nblk + k]);
 }
 
-// gwa[c] = sum of the gradients in T of cell c's pins, read at the A
-// positions the index lists per cell.  Blocks in XCD order, so that the
-// window of T of one cell block is read by one L2.
-__global__ void __launch_bounds__(256)
-    k_xch_pinsum(int m, const int32_t* __restrict__ cell_ptr, const int32_t* __restrict__ qa,
-                 const float2* __restrict__ T, float2* __restrict__ gwa) {
-  const int c = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  if (c >= m) return;
-  const int k0 = cell_ptr[c], k1 = cell_ptr[c + 1];
-  float sx = 0.0f, sy = 0.0f;
+// gwa[c] = sum of the gradients in T of cell c's pins.  One block per cell
+// block: the block streams the cell block's A range of T together with the
+// cell-local index lc (both coalesced) and adds each pin into per-cell
+// accumulators in LDS.  The adds are 64-bit integer adds of the gradients in
+// fixed point (units of 2^-S), so the sums come out the same whatever order
+// the atomics land in (LDS float atomics would not, and run several times
+// slower).  One pin's gradient component is bounded by 1.15 + ln(largest
+// degree) (its softmax weight times one plus its distance to the weighted
+// mean, and that distance is at most ln(degree) in units of gamma), so S is
+// the largest scale that keeps every pin within a 32-bit conversion; the
+// 64-bit sums then hold any number of pins.  A non-finite pin gradient makes
+// its cell's sum NaN.
+__global__ void __launch_bounds__(kSumThreads)
+    k_xch_cellsum(int m, const int32_t* __restrict__ cb_a_ptr, const uint16_t* __restrict__ lc,
+                  const float2* __restrict__ T, float scale, double inv_scale,
+                  float2* __restrict__ gwa) {
+  __shared__ unsigned long long ax[kXchCells], ay[kXchCells];
+  __shared__ unsigned char bad[kXchCells];
+  const int cb = blockIdx.x, t = threadIdx.x;
+  for (int c = t; c < kXchCells; c += kSumThreads) {
+    ax[c] = 0ull;
+    ay[c] = 0ull;
+    bad[c] = 0;
+  }
+  __syncthreads();
+  const int a0 = cb_a_ptr[cb], a1 = cb_a_ptr[cb + 1];
+  // loads of one batch are unconditional (clamped index) so they are all in
+  // flight together
   constexpr int U = 8;
-  for (int k = k0; k < k1; k += U) {
-    int q[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) q[u] = qa[min(k + u, k1 - 1)];
+  for (int a = a0 + t; a < a1; a += U * kSumThreads) {
+    int l[U];
     float2 v[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) v[u] = T[q[u]];
+    for (int k = 0; k < U; ++k) {
+      const int i = min(a + k * kSumThreads, a1 - 1);
+      l[k] = min(lc[i], kXchCells - 1);
+      v[k] = T[i];
+    }
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      if (k + u < k1) {
-        sx += v[u].x;
-        sy += v[u].y;
+    for (int k = 0; k < U; ++k) {
+      if (a + k * kSumThreads < a1) {
+        if (fabsf(v[k].x) <= 3.0e38f && fabsf(v[k].y) <= 3.0e38f) {
+          atomicAdd(&ax[l[k]], (unsigned long long)(long long)__float2int_rn(v[k].x * scale));
+          atomicAdd(&ay[l[k]], (unsigned long long)(long long)__float2int_rn(v[k].y * scale));
+        } else {
+          bad[l[k]] = 1;
+        }
       }
     }
   }
-  gwa[c] = make_float2(sx, sy);
+  __syncthreads();
+  const int c0 = cb * kXchCells;
+  for (int c = t; c < kXchCells; c += kSumThreads) {
+    if (c0 + c >= m) break;
+    gwa[c0 + c] = bad[c] ? make_float2(__builtin_nanf(""), __builtin_nanf(""))
+                         : make_float2((float)((double)(long long)ax[c] * inv_scale),
+                                       (float)((double)(long long)ay[c] * inv_scale));
+  }
 }
 
 }  // namespace
 
-hipError_t launch_xch_pinsum(const XchDims& d, const XchIndex& X, const float2* T, float2* gwa,
-                             hipStream_t s) {
+hipError_t launch_xch_cellsum(const XchDims& d, const XchIndex& X, const float2* T,
+                              float2* gwa, hipStream_t s) {
   if (d.m <= 0) return hipSuccess;
-  const int nb = ((d.m + 255) / 256 + kNumXcd - 1) / kNumXcd * kNumXcd;
-  hipLaunchKernelGGL(k_xch_pinsum, dim3(nb), dim3(256), 0, s, d.m, X.cell_ptr, X.qa, T, gwa);
+  // fixed-point scale 2^S: the largest S <= 26 with bound * 2^S <= 2^30
+  const double bound = 1.15 + log((double)(d.max_degree > 2 ? d.max_degree : 2));
+  int S = 26;
+  while (S > 0 && bound * ldexp(1.0, S) > ldexp(1.0, 30)) --S;
+  hipLaunchKernelGGL(k_xch_cellsum, dim3(d.ncb), dim3(kSumThreads), 0, s, d.m, X.cb_a_ptr, X.lc,
+                     T, (float)ldexp(1.0, S), ldexp(1.0, -S), gwa);
   return hipGetLastError();
 }
 

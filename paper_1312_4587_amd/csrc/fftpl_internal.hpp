@@ -528,8 +528,8 @@ hipError_t launch_xch_wa(const XchDims& d, const XchIndex& X, const int32_t* net
                          const float* pin_dx, const float* pin_dy, float gamma, float2* T,
                          double* wa_part, hipStream_t s);
 // gwa[c] = sum over cell c's pins of T[qa[j]] (after launch_xch_wa).
-hipError_t launch_xch_pinsum(const XchDims& d, const XchIndex& X, const float2* T, float2* gwa,
-                             hipStream_t s);
+hipError_t launch_xch_cellsum(const XchDims& d, const XchIndex& X, const float2* T,
+                              float2* gwa, hipStream_t s);
 // g = scale * density gradient + gwa[c] (one thread per cell).
 hipError_t launch_gather_cellsum(const GridF& g, int m, const float* x, const float* y,
                                  const float* w, const float* h, const float* exy,

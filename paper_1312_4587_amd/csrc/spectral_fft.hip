@@ -1,8 +1,8 @@
 // Spectral Neumann Poisson solve (Eqs. (8)-(12)) with hand-written FFTs.
 //
 // The 2-D transforms are separable; the solve is three passes over the map,
-// each one wavefront per pair of rows (or columns), the 1-D transforms done
-// in LDS:
+// each one block per pair of rows (or columns), the 1-D transforms done in
+// LDS by the whole block:
 //   A  rows:    DCT-II along x of rho           -> bT[u][iy] (written transposed)
 //   B  columns: DCT-II along y, scale by c_u c_v / n^2 / (w_u^2 + w_v^2)
 //               (zero at (0,0): the DC is removed), then DCT-III along y
@@ -27,8 +27,11 @@
 // the reversed coefficients with alternating output signs:
 //   sum_{k>=1} b_k sin(pi k (2i+1)/2n) = (-1)^i sum_{k>=1} b_{n-k} cos(pi k (2i+1)/2n).
 // The 1-D FFT is a Stockham autosort radix-4 (one radix-2 stage first when
-// log2 n is odd), in place in one LDS buffer per wave, every stage reading
-// all its inputs into registers before writing.
+// log2 n is odd), in place in LDS, every stage reading all its inputs into
+// registers before a barrier and writing after it.  The independent
+// transforms of a pass share the stages.  Each pass issues all its global
+// loads (rows and tables) before touching LDS, so a block waits on memory
+// once rather than once per loop trip.
 #include "fftpl_internal.hpp"
 
 namespace fftpl {
@@ -47,102 +50,172 @@ __device__ __forceinline__ int mk_pos(int i) {
   return (i & 1) ? N - ((i + 1) >> 1) : (i >> 1);
 }
 
-// Unnormalised in-place DFT of buf[N] by one wavefront; INV selects exp(+).
-// tw[t] = exp(-2 pi i t / N).
-template <int N, bool INV>
-__device__ __forceinline__ void wave_fft(float2* buf, const float2* __restrict__ tw,
-                                         int lane) {
+// Threads per block for a length-N transform: one radix-4 butterfly per
+// thread and stage at N = 1024 (four wavefronts), never less than one
+// wavefront.
+template <int N>
+struct FftShape {
+  static constexpr int NT = N / 4 >= 256 ? 256 : (N / 4 >= kWave ? N / 4 : kWave);
+};
+
+template <int NT>
+__device__ __forceinline__ void block_lds_sync() {
+  if constexpr (NT > kWave)
+    __syncthreads();
+  else
+    wave_lds_sync();
+}
+
+// Unnormalised in-place DFTs of NB buffers of length N (b0..b{NB-1}) by a
+// block of NT threads.  The buffers go through the stages together, so one
+// barrier per stage serves all of them and each twiddle is read once for all.
+// INV selects exp(+).  tw[t] = exp(-2 pi i t / N).
+template <int N, int NT, bool INV, int NB>
+__device__ __forceinline__ void block_fft(float2* b0, float2* b1, float2* b2, float2* b3,
+                                          const float2* __restrict__ tw, int tid) {
+  float2* const bufs[4] = {b0, b1, b2, b3};
   constexpr int LOG = ilog2c(N);
   int ns = 1;
   if constexpr (LOG & 1) {
     constexpr int B = N / 2;
-    constexpr int PER = (B + kWave - 1) / kWave;
-    float2 v0[PER], v1[PER];
+    constexpr int PER = (B + NT - 1) / NT;
+    float2 v0[NB][PER], v1[NB][PER];
 #pragma unroll
-    for (int t = 0; t < PER; ++t) {
-      const int j = lane + kWave * t;
-      if (B % kWave == 0 || j < B) {
-        v0[t] = buf[j];
-        v1[t] = buf[j + B];
-      }
-    }
-    wave_lds_sync();
+    for (int q = 0; q < NB; ++q)
 #pragma unroll
-    for (int t = 0; t < PER; ++t) {
-      const int j = lane + kWave * t;
-      if (B % kWave == 0 || j < B) {
-        buf[2 * j] = make_float2(v0[t].x + v1[t].x, v0[t].y + v1[t].y);
-        buf[2 * j + 1] = make_float2(v0[t].x - v1[t].x, v0[t].y - v1[t].y);
+      for (int t = 0; t < PER; ++t) {
+        const int j = tid + NT * t;
+        if (B % NT == 0 || j < B) {
+          v0[q][t] = bufs[q][j];
+          v1[q][t] = bufs[q][j + B];
+        }
       }
-    }
-    wave_lds_sync();
+    block_lds_sync<NT>();
+#pragma unroll
+    for (int q = 0; q < NB; ++q)
+#pragma unroll
+      for (int t = 0; t < PER; ++t) {
+        const int j = tid + NT * t;
+        if (B % NT == 0 || j < B) {
+          bufs[q][2 * j] = make_float2(v0[q][t].x + v1[q][t].x, v0[q][t].y + v1[q][t].y);
+          bufs[q][2 * j + 1] = make_float2(v0[q][t].x - v1[q][t].x, v0[q][t].y - v1[q][t].y);
+        }
+      }
+    block_lds_sync<NT>();
     ns = 2;
   }
   constexpr int B = N / 4;
-  constexpr int PER = (B + kWave - 1) / kWave;
+  constexpr int PER = (B + NT - 1) / NT;
 #pragma unroll
   for (int st = 0; st < LOG / 2; ++st) {
-    float2 v[PER][4];
+    float2 v[NB][PER][4];
 #pragma unroll
-    for (int t = 0; t < PER; ++t) {
-      const int j = lane + kWave * t;
-      if (B % kWave == 0 || j < B) {
+    for (int q = 0; q < NB; ++q)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) v[t][r] = buf[j + r * B];
+      for (int t = 0; t < PER; ++t) {
+        const int j = tid + NT * t;
+        if (B % NT == 0 || j < B) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) v[q][t][r] = bufs[q][j + r * B];
+        }
       }
-    }
-    wave_lds_sync();
+    block_lds_sync<NT>();
     const int stride = N / (4 * ns);
 #pragma unroll
     for (int t = 0; t < PER; ++t) {
-      const int j = lane + kWave * t;
-      if (B % kWave == 0 || j < B) {
+      const int j = tid + NT * t;
+      if (B % NT == 0 || j < B) {
         const int k = j & (ns - 1);
+        float2 w[4];
         if (ns > 1) {
 #pragma unroll
           for (int r = 1; r < 4; ++r) {
-            float2 w = tw[k * r * stride];
-            if (INV) w.y = -w.y;
-            v[t][r] = cmul(v[t][r], w);
+            w[r] = tw[k * r * stride];
+            if (INV) w[r].y = -w[r].y;
           }
         }
-        const float2 t0 = make_float2(v[t][0].x + v[t][2].x, v[t][0].y + v[t][2].y);
-        const float2 t1 = make_float2(v[t][0].x - v[t][2].x, v[t][0].y - v[t][2].y);
-        const float2 t2 = make_float2(v[t][1].x + v[t][3].x, v[t][1].y + v[t][3].y);
-        const float2 d = make_float2(v[t][1].x - v[t][3].x, v[t][1].y - v[t][3].y);
-        // forward: t3 = -i * d ; inverse: t3 = +i * d
-        const float2 t3 = INV ? make_float2(-d.y, d.x) : make_float2(d.y, -d.x);
         const int o = (j - k) * 4 + k;
-        buf[o] = make_float2(t0.x + t2.x, t0.y + t2.y);
-        buf[o + ns] = make_float2(t1.x + t3.x, t1.y + t3.y);
-        buf[o + 2 * ns] = make_float2(t0.x - t2.x, t0.y - t2.y);
-        buf[o + 3 * ns] = make_float2(t1.x - t3.x, t1.y - t3.y);
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+          float2* u = v[q][t];
+          if (ns > 1) {
+#pragma unroll
+            for (int r = 1; r < 4; ++r) u[r] = cmul(u[r], w[r]);
+          }
+          const float2 t0 = make_float2(u[0].x + u[2].x, u[0].y + u[2].y);
+          const float2 t1 = make_float2(u[0].x - u[2].x, u[0].y - u[2].y);
+          const float2 t2 = make_float2(u[1].x + u[3].x, u[1].y + u[3].y);
+          const float2 d = make_float2(u[1].x - u[3].x, u[1].y - u[3].y);
+          // forward: t3 = -i * d ; inverse: t3 = +i * d
+          const float2 t3 = INV ? make_float2(-d.y, d.x) : make_float2(d.y, -d.x);
+          float2* b = bufs[q];
+          b[o] = make_float2(t0.x + t2.x, t0.y + t2.y);
+          b[o + ns] = make_float2(t1.x + t3.x, t1.y + t3.y);
+          b[o + 2 * ns] = make_float2(t0.x - t2.x, t0.y - t2.y);
+          b[o + 3 * ns] = make_float2(t1.x - t3.x, t1.y - t3.y);
+        }
       }
     }
-    wave_lds_sync();
+    block_lds_sync<NT>();
     ns *= 4;
   }
 }
 
-// Copy the twiddle table into LDS (one coalesced read per block; the FFT
-// stages then never wait on global memory for a twiddle).
-template <int N>
-__device__ __forceinline__ void stage_twiddles(float2* tw, const float2* __restrict__ tw_g,
-                                               int lane) {
-  for (int t = lane; t < N; t += kWave) tw[t] = tw_g[t];
-  wave_lds_sync();
+// Copy the twiddle table, the quarter-sample table cs and (WF) the frequency
+// table wf into LDS.  All global loads are issued before the first LDS write,
+// so the block waits on memory once; the caller synchronises.
+template <int N, int NT, bool WF>
+__device__ __forceinline__ void stage_tables(float2* tw, const float2* __restrict__ tw_g,
+                                             float2* cs, const float2* __restrict__ cs_g,
+                                             float* wf, const float* __restrict__ wf_g,
+                                             int tid) {
+  constexpr int PT = (N + NT - 1) / NT, PC = (N / 2 + NT) / NT;
+  float2 a[PT], c[PC];
+  float f[PT];
+#pragma unroll
+  for (int t = 0; t < PT; ++t) {
+    const int i = min(tid + NT * t, N - 1);
+    a[t] = tw_g[i];
+    if (WF) f[t] = wf_g[i];
+  }
+#pragma unroll
+  for (int t = 0; t < PC; ++t) c[t] = cs_g[min(tid + NT * t, N / 2)];
+#pragma unroll
+  for (int t = 0; t < PT; ++t) {
+    const int i = tid + NT * t;
+    if (N % NT == 0 || i < N) {
+      tw[i] = a[t];
+      if (WF) wf[i] = f[t];
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < PC; ++t) {
+    const int i = tid + NT * t;
+    if (i <= N / 2) cs[i] = c[t];
+  }
 }
 
-// Same for the quarter-sample table cs and the frequency table wf, which the
-// pair loops read once per pair.
-template <int N>
-__device__ __forceinline__ void stage_tables(float2* cs, const float2* __restrict__ cs_g,
-                                             float* wf, const float* __restrict__ wf_g,
-                                             int lane) {
-  for (int t = lane; t <= N / 2; t += kWave) cs[t] = cs_g[t];
-  if (wf)
-    for (int t = lane; t < N; t += kWave) wf[t] = wf_g[t];
-  wave_lds_sync();
+// Sums over the block of K per-thread doubles, added in a fixed order, so
+// every thread gets the same bits.  red holds K * NT / 64 doubles of LDS.
+template <int NT, int K>
+__device__ __forceinline__ void block_sums(double (&v)[K], double* red, int tid) {
+  constexpr int NW = NT / kWave;
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+  if constexpr (NW > 1) {
+    if ((tid & (kWave - 1)) == 0) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) red[k * NW + tid / kWave] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double s = 0.0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) s += red[k * NW + w];
+      v[k] = s;
+    }
+  }
 }
 
 // Forward post-processing for the pair (k, n-k) of a two-real-sequence FFT
@@ -189,76 +262,100 @@ __device__ __forceinline__ void diff_weights(float2 cs, float& dm_k, float& dm_k
 // Pass A: rows -> bT (transposed), row sums in double; optional overflow sums.
 // ---------------------------------------------------------------------------
 template <int N>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(FftShape<N>::NT)
     k_rows_dct2(const float* __restrict__ rho, float* __restrict__ bT,
                 double* __restrict__ rowsum, const float2* __restrict__ tw_g,
                 const float2* __restrict__ cs_g, const float* __restrict__ base,
                 const float* __restrict__ cap, float rho_t, double* __restrict__ tau_part) {
+  constexpr int NT = FftShape<N>::NT;
+  constexpr int PER = (N + NT - 1) / NT, PK = (N / 2 + NT) / NT;
   __shared__ float2 buf[N];
   __shared__ float2 tw[N];
   __shared__ float2 cs[N / 2 + 1];
-  constexpr int PER = (N + kWave - 1) / kWave;
-  const int lane = threadIdx.x;
-  stage_twiddles<N>(tw, tw_g, lane);
-  stage_tables<N>(cs, cs_g, nullptr, nullptr, lane);
+  __shared__ double red[4 * (NT / kWave)];
+  const int tid = threadIdx.x;
   const int pair = xcd_block(blockIdx.x, gridDim.x);
   const int r1 = 2 * pair, r2 = r1 + 1;
-  float a1[PER], a2[PER];
-  double s1 = 0.0, s2 = 0.0, ovf = 0.0, mov = 0.0;
+  float a1[PER], a2[PER], b1[PER], b2[PER], c1[PER], c2[PER];
 #pragma unroll
   for (int t = 0; t < PER; ++t) {
-    const int i = lane + kWave * t;
-    if (N % kWave == 0 || i < N) {
-      a1[t] = rho[(int64_t)r1 * N + i];
-      a2[t] = rho[(int64_t)r2 * N + i];
-      s1 += a1[t];
-      s2 += a2[t];
-      if (tau_part) {
+    const int i = min(tid + NT * t, N - 1);
+    a1[t] = rho[(int64_t)r1 * N + i];
+    a2[t] = rho[(int64_t)r2 * N + i];
+  }
+  // (pointer tests hoisted out of the loops so that the loads issue together)
+  if (tau_part && base) {
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-          const int64_t b = (int64_t)(q ? r2 : r1) * N + i;
-          const float bb = base ? base[b] : 0.0f;
-          const float cc = cap ? cap[b] : fmaxf(0.0f, rho_t - fminf(rho_t, bb));
-          const float mv = (q ? a2[t] : a1[t]) - bb;
-          ovf += fmaxf(0.0f, mv - cc);
-          mov += mv;
-        }
+    for (int t = 0; t < PER; ++t) {
+      const int i = min(tid + NT * t, N - 1);
+      b1[t] = base[(int64_t)r1 * N + i];
+      b2[t] = base[(int64_t)r2 * N + i];
+    }
+  } else {
+#pragma unroll
+    for (int t = 0; t < PER; ++t) b1[t] = b2[t] = 0.0f;
+  }
+  if (tau_part && cap) {
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+      const int i = min(tid + NT * t, N - 1);
+      c1[t] = cap[(int64_t)r1 * N + i];
+      c2[t] = cap[(int64_t)r2 * N + i];
+    }
+  } else {
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+      c1[t] = fmaxf(0.0f, rho_t - fminf(rho_t, b1[t]));
+      c2[t] = fmaxf(0.0f, rho_t - fminf(rho_t, b2[t]));
+    }
+  }
+  stage_tables<N, NT, false>(tw, tw_g, cs, cs_g, nullptr, nullptr, tid);
+  double s[4] = {0.0, 0.0, 0.0, 0.0};   // row sums r1, r2; overflow; movable
+#pragma unroll
+  for (int t = 0; t < PER; ++t) {
+    if (N % NT == 0 || tid + NT * t < N) {
+      s[0] += a1[t];
+      s[1] += a2[t];
+      if (tau_part) {
+        const float m1 = a1[t] - b1[t], m2 = a2[t] - b2[t];
+        s[2] += fmaxf(0.0f, m1 - c1[t]);
+        s[2] += fmaxf(0.0f, m2 - c2[t]);
+        s[3] += m1;
+        s[3] += m2;
       }
     }
   }
-  s1 = wave_sum(s1);
-  s2 = wave_sum(s2);
-  if (tau_part) {
-    ovf = wave_sum(ovf);
-    mov = wave_sum(mov);
-    if (lane == 0) {
-      tau_part[2 * pair] = ovf;
-      tau_part[2 * pair + 1] = mov;
+  block_sums<NT, 4>(s, red, tid);
+  if (tid == 0) {
+    rowsum[r1] = s[0];
+    rowsum[r2] = s[1];
+    if (tau_part) {
+      tau_part[2 * pair] = s[2];
+      tau_part[2 * pair + 1] = s[3];
     }
   }
-  const float m1 = (float)(s1 / N), m2 = (float)(s2 / N);
+  const float m1 = (float)(s[0] / N), m2 = (float)(s[1] / N);
 #pragma unroll
   for (int t = 0; t < PER; ++t) {
-    const int i = lane + kWave * t;
-    if (N % kWave == 0 || i < N) buf[mk_pos<N>(i)] = make_float2(a1[t] - m1, a2[t] - m2);
+    const int i = tid + NT * t;
+    if (N % NT == 0 || i < N) buf[mk_pos<N>(i)] = make_float2(a1[t] - m1, a2[t] - m2);
   }
-  wave_lds_sync();
-  wave_fft<N, false>(buf, tw, lane);
-  for (int k = lane; k <= N / 2; k += kWave) {
+  block_lds_sync<NT>();
+  block_fft<N, NT, false, 1>(buf, nullptr, nullptr, nullptr, tw, tid);
+#pragma unroll
+  for (int t = 0; t < PK; ++t) {
+    const int k = tid + NT * t;
+    if (k > N / 2) continue;
     const int kp = (N - k) & (N - 1);
     float x1k, x2k, x1kp, x2kp;
     dct2_pair(buf[k], buf[kp], cs[k], x1k, x2k, x1kp, x2kp);
     if (k == 0) {
-      x1k = (float)s1;
-      x2k = (float)s2;
+      x1k = (float)s[0];
+      x2k = (float)s[1];
     }
     *reinterpret_cast<float2*>(&bT[(int64_t)k * N + r1]) = make_float2(x1k, x2k);
     if (k != 0 && k != N / 2)
       *reinterpret_cast<float2*>(&bT[(int64_t)kp * N + r1]) = make_float2(x1kp, x2kp);
-  }
-  if (lane == 0) {
-    rowsum[r1] = s1;
-    rowsum[r2] = s2;
   }
 }
 
@@ -267,44 +364,57 @@ __global__ void __launch_bounds__(64)
 // the double row sums minus their mean so that the DC never enters float32.
 // ---------------------------------------------------------------------------
 template <int N, bool DIFF>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(FftShape<N>::NT)
     k_cols_solve(const float* __restrict__ bT, const double* __restrict__ rowsum,
                  float* __restrict__ P, float* __restrict__ Q,
                  const float2* __restrict__ tw_g, const float2* __restrict__ cs_g,
                  const float* __restrict__ wf_g) {
+  constexpr int NT = FftShape<N>::NT;
+  constexpr int PER = (N + NT - 1) / NT, PK = (N / 2 + NT) / NT;
   __shared__ float2 buf0[N];
   __shared__ float2 buf1[N];
   __shared__ float2 buf2[DIFF ? N : 1];
   __shared__ float2 tw[N];
   __shared__ float2 cs[N / 2 + 1];
   __shared__ float wf[N];
-  constexpr int PER = (N + kWave - 1) / kWave;
-  const int lane = threadIdx.x;
-  stage_twiddles<N>(tw, tw_g, lane);
-  stage_tables<N>(cs, cs_g, wf, wf_g, lane);
+  __shared__ double red[NT / kWave];
+  const int tid = threadIdx.x;
   const int q = xcd_block(blockIdx.x, gridDim.x);
   const int u1 = 2 * q, u2 = u1 + 1;
-  double mean0 = 0.0;
+  float c1[PER], c2[PER];
   if (u1 == 0) {
-    double s = 0.0;
-    for (int i = lane; i < N; i += kWave) s += rowsum[i];
-    mean0 = wave_sum(s) / N;
+    double rs[PER];
+    double s[1] = {0.0};
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+      rs[t] = rowsum[min(tid + NT * t, N - 1)];
+      if (N % NT == 0 || tid + NT * t < N) s[0] += rs[t];
+    }
+    block_sums<NT, 1>(s, red, tid);
+    const double mean0 = s[0] / N;
+#pragma unroll
+    for (int t = 0; t < PER; ++t) c1[t] = (float)(rs[t] - mean0);
+  } else {
+#pragma unroll
+    for (int t = 0; t < PER; ++t) c1[t] = bT[(int64_t)u1 * N + min(tid + NT * t, N - 1)];
   }
 #pragma unroll
+  for (int t = 0; t < PER; ++t) c2[t] = bT[(int64_t)u2 * N + min(tid + NT * t, N - 1)];
+  stage_tables<N, NT, true>(tw, tw_g, cs, cs_g, wf, wf_g, tid);
+#pragma unroll
   for (int t = 0; t < PER; ++t) {
-    const int i = lane + kWave * t;
-    if (N % kWave == 0 || i < N) {
-      const float c1 = (u1 == 0) ? (float)(rowsum[i] - mean0) : bT[(int64_t)u1 * N + i];
-      const float c2 = bT[(int64_t)u2 * N + i];
-      buf0[mk_pos<N>(i)] = make_float2(c1, c2);
-    }
+    const int i = tid + NT * t;
+    if (N % NT == 0 || i < N) buf0[mk_pos<N>(i)] = make_float2(c1[t], c2[t]);
   }
-  wave_lds_sync();
-  wave_fft<N, false>(buf0, tw, lane);
+  block_lds_sync<NT>();
+  block_fft<N, NT, false, 1>(buf0, nullptr, nullptr, nullptr, tw, tid);
   const float inv_n2 = 1.0f / ((float)N * (float)N);
   const float wu1 = wf[u1], wu2 = wf[u2];
   const float f1 = (u1 == 0 ? 1.0f : 2.0f) * inv_n2, f2 = 2.0f * inv_n2;
-  for (int k = lane; k <= N / 2; k += kWave) {
+#pragma unroll
+  for (int t = 0; t < PK; ++t) {
+    const int k = tid + NT * t;
+    if (k > N / 2) continue;
     const int kp = (N - k) & (N - 1);
     const float2 c = cs[k];
     float x1k, x2k, x1kp, x2kp;
@@ -345,11 +455,12 @@ __global__ void __launch_bounds__(64)
       if (!k0 && k != N / 2) buf2[kp] = pack2(h1p, h2p);
     }
   }
-  wave_lds_sync();
-  wave_fft<N, true>(buf0, tw, lane);
-  wave_fft<N, true>(buf1, tw, lane);
-  if (DIFF) wave_fft<N, true>(buf2, tw, lane);
-  for (int iy = lane; iy < N; iy += kWave) {
+  block_lds_sync<NT>();
+  block_fft<N, NT, true, DIFF ? 3 : 2>(buf0, buf1, buf2, nullptr, tw, tid);
+#pragma unroll
+  for (int t = 0; t < PER; ++t) {
+    const int iy = tid + NT * t;
+    if (N % NT != 0 && iy >= N) continue;
     const int mpos = mk_pos<N>(iy);
     const float2 zp = buf0[mpos], zq = buf1[mpos];
     const float sg = (iy & 1) ? -1.0f : 1.0f;
@@ -368,13 +479,15 @@ __global__ void __launch_bounds__(64)
 // Pass C: rows r1 = 2p, r2 = 2p+1 of P and Q -> psi, Ex, Ey; energy.
 // ---------------------------------------------------------------------------
 template <int N, bool DIFF>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(FftShape<N>::NT)
     k_rows_inverse(const float* __restrict__ P, const float* __restrict__ Q,
                    const float* __restrict__ rho, float* __restrict__ psi,
                    float* __restrict__ ex, float* __restrict__ ey,
                    float2* __restrict__ exy, double* __restrict__ energy,
                    const float2* __restrict__ tw_g, const float2* __restrict__ cs_g,
                    const float* __restrict__ wf_g) {
+  constexpr int NT = FftShape<N>::NT;
+  constexpr int PER = (N + NT - 1) / NT, PK = (N / 2 + NT) / NT;
   __shared__ float2 bufa[N];
   __shared__ float2 bufb[N];
   __shared__ float2 bufc[N];
@@ -383,23 +496,46 @@ __global__ void __launch_bounds__(64)
   __shared__ float2 cs[N / 2 + 1];
   __shared__ float wf[N];
   __shared__ float rows[4 * N];
-  const int lane = threadIdx.x;
+  __shared__ double red[NT / kWave];
+  const int tid = threadIdx.x;
   const int pr = xcd_block(blockIdx.x, gridDim.x);
   const int r1 = 2 * pr, r2 = r1 + 1;
-  // rows P[r1], P[r2], Q[r1], Q[r2] staged in LDS with all loads up front
-  for (int t = lane; t < N; t += kWave) {
-    rows[t] = P[(int64_t)r1 * N + t];
-    rows[N + t] = P[(int64_t)r2 * N + t];
-    rows[2 * N + t] = Q[(int64_t)r1 * N + t];
-    rows[3 * N + t] = Q[(int64_t)r2 * N + t];
+  // rows P[r1], P[r2], Q[r1], Q[r2] (and rho for the energy): all loads first
+  float v[4][PER], e1[PER], e2[PER];
+#pragma unroll
+  for (int t = 0; t < PER; ++t) {
+    const int i = min(tid + NT * t, N - 1);
+    v[0][t] = P[(int64_t)r1 * N + i];
+    v[1][t] = P[(int64_t)r2 * N + i];
+    v[2][t] = Q[(int64_t)r1 * N + i];
+    v[3][t] = Q[(int64_t)r2 * N + i];
   }
-  stage_twiddles<N>(tw, tw_g, lane);
-  stage_tables<N>(cs, cs_g, wf, wf_g, lane);
+  if (energy) {
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+      const int i = min(tid + NT * t, N - 1);
+      e1[t] = rho[(int64_t)r1 * N + i];
+      e2[t] = rho[(int64_t)r2 * N + i];
+    }
+  }
+  stage_tables<N, NT, true>(tw, tw_g, cs, cs_g, wf, wf_g, tid);
+#pragma unroll
+  for (int t = 0; t < PER; ++t) {
+    const int i = tid + NT * t;
+    if (N % NT == 0 || i < N) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) rows[r * N + i] = v[r][t];
+    }
+  }
+  block_lds_sync<NT>();
   const float* P1 = rows;
   const float* P2 = rows + N;
   const float* Q1 = rows + 2 * N;
   const float* Q2 = rows + 3 * N;
-  for (int k = lane; k <= N / 2; k += kWave) {
+#pragma unroll
+  for (int t = 0; t < PK; ++t) {
+    const int k = tid + NT * t;
+    if (k > N / 2) continue;
     const int kp = (N - k) & (N - 1);
     const bool k0 = (k == 0), self = k0 || k == N / 2;
     const float2 c = cs[k];
@@ -435,17 +571,13 @@ __global__ void __launch_bounds__(64)
       if (!self) bufd[kp] = pack2(hap, hbp);
     }
   }
-  wave_lds_sync();
-  wave_fft<N, true>(bufa, tw, lane);
-  wave_fft<N, true>(bufb, tw, lane);
-  wave_fft<N, true>(bufc, tw, lane);
-  if (DIFF) wave_fft<N, true>(bufd, tw, lane);
-  double en = 0.0;
-  constexpr int PERX = (N + kWave - 1) / kWave;
+  block_lds_sync<NT>();
+  block_fft<N, NT, true, DIFF ? 4 : 3>(bufa, bufb, bufc, bufd, tw, tid);
+  double en[1] = {0.0};
 #pragma unroll
-  for (int t = 0; t < PERX; ++t) {
-    const int ix = lane + kWave * t;
-    if (N % kWave != 0 && ix >= N) continue;
+  for (int t = 0; t < PER; ++t) {
+    const int ix = tid + NT * t;
+    if (N % NT != 0 && ix >= N) continue;
     const int mpos = mk_pos<N>(ix);
     const float2 za = bufa[mpos], zb = bufb[mpos];
     const float sg = (ix & 1) ? -1.0f : 1.0f;
@@ -472,17 +604,17 @@ __global__ void __launch_bounds__(64)
       exy[o1] = make_float2(sg * zc.x, zb.x);
       exy[o2] = make_float2(sg * zc.y, zb.y);
     }
-    if (energy) en += (double)rho[o1] * za.x + (double)rho[o2] * za.y;
+    if (energy) en[0] += (double)e1[t] * za.x + (double)e2[t] * za.y;
   }
   if (energy) {
-    en = wave_sum(en);
-    if (lane == 0) energy[pr] = en;   // per-block partial
+    block_sums<NT, 1>(en, red, tid);
+    if (tid == 0) energy[pr] = en[0];   // per-block partial
   }
 }
 
 template <int N>
 hipError_t run_fft(Plan& p, const SpectralArgs& a, hipStream_t s) {
-  const dim3 grid(N / 2), block(kWave);
+  const dim3 grid(N / 2), block(FftShape<N>::NT);
   hipLaunchKernelGGL(k_rows_dct2<N>, grid, block, 0, s, a.rho, p.tmp0, p.rowsum, p.fft_tw,
                      p.dct_cs, a.base, a.cap, a.rho_t, a.tau_part);
   hipError_t e = hipGetLastError();
