@@ -90,7 +90,7 @@ int xch_dims(int m, int num_nets, int num_pins, int max_degree, XchDims* d) {
   r.o_qa = off;
   off = align256(off + sizeof(int32_t) * (size_t)num_pins);
   r.o_ns = off;
-  off = align256(off + sizeof(uint16_t) * (size_t)num_nets);
+  off = align256(off + sizeof(uint32_t) * (size_t)num_nets);
   r.index_bytes = off;
   // build workspace: counts / cursors, A starts, transposed counts, B starts,
   // scan block sums, flag and scan totals
@@ -116,7 +116,7 @@ XchIndex xch_index(const XchDims& d, const void* index) {
   X.lc = reinterpret_cast<const uint16_t*>(b + d.o_lc);
   X.cell_ptr = reinterpret_cast<const int32_t*>(b + d.o_cp);
   X.qa = reinterpret_cast<const int32_t*>(b + d.o_qa);
-  X.nsort = reinterpret_cast<const uint16_t*>(b + d.o_ns);
+  X.nmeta = reinterpret_cast<const uint32_t*>(b + d.o_ns);
   return X;
 }
 
@@ -200,20 +200,31 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-// Per net block, its nets in order of degree class min(degree, 9) (0, 1, 2,
-// ..., 8, larger), as offsets from the block's first net; the order inside a
-// class is arbitrary.  A wavefront walking this order sees nets of equal
-// degree together, so its loops over pins run the length of the degree.
+// Degree class of the net order: the degree itself up to kSmall, then one
+// class per power of two (9-16, 17-32, ..., the last one open-ended).
+__device__ __forceinline__ int degree_class(int deg) {
+  if (deg <= kSmall) return deg;
+  const int c = kSmall + 1 + (31 - __clz(deg - 1)) - 3;
+  return c < kXchBuckets - 1 ? c : kXchBuckets - 1;
+}
+
+// Per net block, its nets in increasing degree class, each as (first pin -
+// the block's first pin) << 16 | degree; the order inside a class is
+// arbitrary.  A wavefront walking this order from the front sees small nets
+// of equal degree together (its loops over pins run the length of the
+// degree); walking it from the back it meets the largest nets first.  The
+// kernel reads each net's extent from here with one coalesced load.
 __global__ void __launch_bounds__(256)
     k_xi_netsort(const int32_t* __restrict__ net_ptr, const int32_t* __restrict__ nb_net_ptr,
-                 uint16_t* __restrict__ nsort) {
+                 uint32_t* __restrict__ nmeta) {
   __shared__ int cnt[kXchBuckets], cur[kXchBuckets];
   const int k = blockIdx.x, t = threadIdx.x;
   const int e0 = nb_net_ptr[k], e1 = nb_net_ptr[k + 1];
+  const int p0 = net_ptr[e0];
   if (t < kXchBuckets) cnt[t] = 0;
   __syncthreads();
   for (int e = e0 + t; e < e1; e += blockDim.x)
-    atomicAdd(&cnt[min(net_ptr[e + 1] - net_ptr[e], kXchBuckets - 1)], 1);
+    atomicAdd(&cnt[degree_class(net_ptr[e + 1] - net_ptr[e])], 1);
   __syncthreads();
   if (t == 0) {
     int run = 0;
@@ -224,8 +235,9 @@ __global__ void __launch_bounds__(256)
   }
   __syncthreads();
   for (int e = e0 + t; e < e1; e += blockDim.x) {
-    const int b = min(net_ptr[e + 1] - net_ptr[e], kXchBuckets - 1);
-    nsort[e0 + atomicAdd(&cur[b], 1)] = (uint16_t)(e - e0);
+    const int q0 = net_ptr[e], deg = net_ptr[e + 1] - q0;
+    nmeta[e0 + atomicAdd(&cur[degree_class(deg)], 1)] =
+        ((uint32_t)(q0 - p0) << 16) | (uint32_t)deg;
   }
 }
 
@@ -333,8 +345,8 @@ int xch_build(const XchDims& d, const int32_t* net_ptr, const int32_t* pin_cell,
     e = hipGetLastError();
   }
   if (e == hipSuccess) {
-    uint16_t* nsort = reinterpret_cast<uint16_t*>(ib + d.o_ns);
-    hipLaunchKernelGGL(k_xi_netsort, dim3(d.nnb), dim3(256), 0, s, net_ptr, nb_net_ptr, nsort);
+    uint32_t* nmeta = reinterpret_cast<uint32_t*>(ib + d.o_ns);
+    hipLaunchKernelGGL(k_xi_netsort, dim3(d.nnb), dim3(256), 0, s, net_ptr, nb_net_ptr, nmeta);
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -398,7 +410,7 @@ __device__ __forceinline__ float fexp(float v) { return __expf(v); }
 template <int STAGE>
 __global__ void __launch_bounds__(NW)
     k_xch_wa(int num_pins, int cap, const int32_t* __restrict__ net_ptr,
-             const int32_t* __restrict__ nb_net_ptr, const uint16_t* __restrict__ nsort,
+             const int32_t* __restrict__ nb_net_ptr, const uint32_t* __restrict__ nmeta,
              const int32_t* __restrict__ a_of_b, const uint16_t* __restrict__ lcsr,
              const float* __restrict__ pin_dx, const float* __restrict__ pin_dy,
              float inv_gamma, float2* __restrict__ T, double* __restrict__ part) {
@@ -412,6 +424,17 @@ __global__ void __launch_bounds__(NW)
   const int np = p1 - p0;
   double acc_wa = 0.0, acc_hp = 0.0;
   if (np > 0 && np <= cap && np <= STAGE * NW) {
+    // 0. this wavefront's work, read before the staging loads so that the
+    // latency of both overlaps: lane j holds the j-th candidate large net
+    // from the back of the order (entries nn-1-wv, nn-1-wv-8, ...) and the
+    // lane's nets of the first two chunks of small nets.
+    const int nn = e1 - e0;
+    constexpr int NWV = NW / kWave;
+    const uint32_t* meta = nmeta + e0;
+    const int bl = nn - 1 - wv - NWV * lane;
+    const uint32_t mbig = meta[max(bl, 0)];
+    const uint32_t msm0 = meta[min(wv * kWave + lane, nn - 1)];
+    const uint32_t msm1 = meta[min(wv * kWave + NW + lane, nn - 1)];
     // 1. stage: off[csr offset] = pin offset (coalesced), pos[csr offset] =
     // cell position read from T in B order (runs of consecutive A positions).
     // Loads are unconditional (index clamped into the block) so that each
@@ -446,22 +469,22 @@ __global__ void __launch_bounds__(NW)
     }
     __syncthreads();
 
-    // 2. nets in degree order.  Nets above kSmall sit at the tail of the
-    // order; wavefront w takes the tail's nets w, w + 8, ... (one wavefront
-    // per net, three passes over its pins in LDS: pass 1 turns positions into
-    // pin coordinates relative to the first pin's cell, pass 3 overwrites
-    // them with the gradient).  The others: one lane per net, a wavefront per
-    // chunk of kWave nets of (nearly) equal degree, loops as long as the
-    // chunk's largest degree; the next chunk's pointers are loaded before the
-    // current chunk is done.
-    const int nn = e1 - e0;
-    constexpr int NWV = NW / kWave;
-    for (int bi = nn - 1 - wv;; bi -= NWV) {
-      if (bi < 0) break;
-      const int e = e0 + nsort[e0 + bi];
-      const int q0 = net_ptr[e], q1 = net_ptr[e + 1];
-      if (q1 - q0 <= kSmall) break;   // the rest of this wavefront's tail is small
-      const int b0 = q0 - p0, b1 = q1 - p0;
+    // 2. nets in degree order.  Nets above kSmall sit at the back of the
+    // order, largest class last; wavefront w takes the back's nets w, w + 8,
+    // ... (one wavefront per net, three passes over its pins in LDS: pass 1
+    // turns positions into pin coordinates relative to the first pin's
+    // cell, pass 3 overwrites them with the gradient).  The others: one lane
+    // per net, a wavefront per chunk of kWave nets of (nearly) equal degree,
+    // loops as long as the chunk's largest degree.
+    for (int j = 0;; ++j) {
+      if (nn - 1 - wv - NWV * j < 0) break;
+      // candidates beyond the first kWave: loaded here (only blocks with more
+      // than 8 * kWave large nets get this far)
+      const uint32_t mj = j < kWave ? (uint32_t)__builtin_amdgcn_readlane((int)mbig, j)
+                                    : meta[nn - 1 - wv - NWV * j];
+      const int deg = (int)(mj & 0xffffu);
+      if (deg <= kSmall) break;   // the rest of this wavefront's back part is small
+      const int b0 = (int)(mj >> 16), b1 = b0 + deg;
       const float2 r = pos[b0];
       wave_lds_sync();
       constexpr int H = 4;   // pins per lane whose LDS loads are issued together
@@ -553,28 +576,18 @@ __global__ void __launch_bounds__(NW)
       }
     }
 
-    int c0 = 0, c1 = 0;
-    {
-      const int li = wv * kWave + lane;
-      if (li < nn) {
-        const int e = e0 + nsort[e0 + li];
-        c0 = net_ptr[e];
-        c1 = net_ptr[e + 1];
-      }
-    }
-    for (int base = wv * kWave; base < nn; base += NW) {
-      int n0 = 0, n1 = 0;
-      {
-        const int li = base + NW + lane;
-        if (li < nn) {
-          const int e = e0 + nsort[e0 + li];
-          n0 = net_ptr[e];
-          n1 = net_ptr[e + 1];
-        }
-      }
-      int deg = c1 - c0;
+    // small nets: chunk q of this wavefront holds order entries
+    // wv * kWave + q * NW + lane; the first two chunks' extents were read
+    // with the large-net candidates, later ones one chunk ahead
+    uint32_t mcur = msm0, mnext = msm1;
+    for (int q = 0;; ++q) {
+      const int li = wv * kWave + q * NW + lane;
+      if (li - lane >= nn) break;
+      uint32_t mafter = 0u;
+      if (li - lane + 2 * NW < nn) mafter = meta[min(li + 2 * NW, nn - 1)];
+      int deg = li < nn ? (int)(mcur & 0xffffu) : 0;
       if (deg > kSmall) deg = 0;   // done above
-      const int l0 = c0 - p0;
+      const int l0 = (int)(mcur >> 16);
       // the chunk's largest small degree, uniform across the wavefront
       const int wdeg = wave_max_dpp_i(deg);
       if (deg == 1) pos[l0] = make_float2(0.0f, 0.0f);
@@ -642,8 +655,8 @@ __global__ void __launch_bounds__(NW)
           acc_hp += (double)(mx - lx) + (double)(my - ly);
         }
       }
-      c0 = n0;
-      c1 = n1;
+      mcur = mnext;
+      mnext = mafter;
     }
     __syncthreads();
 
@@ -744,7 +757,7 @@ hipError_t launch_xch_wa(const XchDims& d, const XchIndex& X, const int32_t* net
   const size_t lds = sizeof(float2) * 2 * (size_t)d.cap;
   if (d.cap <= kXchPinLds2) {
     hipLaunchKernelGGL((k_xch_wa<kStageS>), dim3(d.nnb), dim3(NW), lds, s, d.num_pins, d.cap,
-                       net_ptr, X.nb_net_ptr, X.nsort, X.a_of_b, X.lcsr, pin_dx, pin_dy,
+                       net_ptr, X.nb_net_ptr, X.nmeta, X.a_of_b, X.lcsr, pin_dx, pin_dy,
                        1.0f / gamma, T, wa_part);
   } else {
     // more than 64 KiB of dynamic LDS has to be allowed explicitly
@@ -757,7 +770,7 @@ hipError_t launch_xch_wa(const XchDims& d, const XchIndex& X, const int32_t* net
       attr = true;
     }
     hipLaunchKernelGGL((k_xch_wa<kStageL>), dim3(d.nnb), dim3(NW), lds, s, d.num_pins, d.cap,
-                       net_ptr, X.nb_net_ptr, X.nsort, X.a_of_b, X.lcsr, pin_dx, pin_dy,
+                       net_ptr, X.nb_net_ptr, X.nmeta, X.a_of_b, X.lcsr, pin_dx, pin_dy,
                        1.0f / gamma, T, wa_part);
   }
   return hipGetLastError();

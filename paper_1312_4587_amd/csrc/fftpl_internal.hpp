@@ -492,7 +492,8 @@ constexpr int kXchPinCap = 9728;       // most pins of a net block (2 x 76 KiB o
 constexpr int kXchPinLds2 = 4864;      // pins of a net block that leave room for 2 blocks per CU
 constexpr int kXchPinTarget = 4096;    // nets are grouped by first pin / target
 constexpr int kXchMinTarget = 1024;
-constexpr int kXchBuckets = 10;        // degree classes 0..8 and > 8 of the net order
+constexpr int kXchBuckets = 20;        // degree classes of the net order: 0..8, then
+                                       // 9-16, 17-32, ..., > 8192
 
 struct XchDims {
   int m = 0, num_nets = 0, num_pins = 0, max_degree = 0;
@@ -516,7 +517,8 @@ struct XchIndex {
   const uint16_t* lc = nullptr;         // [P] cell offset inside its cell block (A order)
   const int32_t* cell_ptr = nullptr;    // [m+1] pins on cells < c
   const int32_t* qa = nullptr;          // [P] A position of each pin, cell-major
-  const uint16_t* nsort = nullptr;      // [E] nets of each net block by degree class
+  const uint32_t* nmeta = nullptr;      // [E] per net block, its nets by degree class:
+                                       // (first pin - block's first pin) << 16 | degree
 };
 XchIndex xch_index(const XchDims& d, const void* index);
 
