@@ -417,6 +417,8 @@ __global__ void __launch_bounds__(NW)
   extern __shared__ float2 smem[];
   float2* pos = smem;
   float2* off = smem + cap;
+  __shared__ uint32_t bigmeta[NW];   // extents of the last NW nets of the order
+  __shared__ int q_big, q_small;     // work counters
   const int k = blockIdx.x, t = threadIdx.x, nblk = gridDim.x;
   const int lane = t & (kWave - 1), wv = t / kWave;
   const int e0 = nb_net_ptr[k], e1 = nb_net_ptr[k + 1];
@@ -424,17 +426,14 @@ __global__ void __launch_bounds__(NW)
   const int np = p1 - p0;
   double acc_wa = 0.0, acc_hp = 0.0;
   if (np > 0 && np <= cap && np <= STAGE * NW) {
-    // 0. this wavefront's work, read before the staging loads so that the
-    // latency of both overlaps: lane j holds the j-th candidate large net
-    // from the back of the order (entries nn-1-wv, nn-1-wv-8, ...) and the
-    // lane's nets of the first two chunks of small nets.
+    // 0. net extents, read before the staging loads so that the latency of
+    // both overlaps: the last NW entries of the order (the large nets, largest
+    // first) for LDS, and this wavefront's first chunk of small nets.
     const int nn = e1 - e0;
     constexpr int NWV = NW / kWave;
     const uint32_t* meta = nmeta + e0;
-    const int bl = nn - 1 - wv - NWV * lane;
-    const uint32_t mbig = meta[max(bl, 0)];
+    const uint32_t mbig = meta[max(nn - 1 - t, 0)];
     const uint32_t msm0 = meta[min(wv * kWave + lane, nn - 1)];
-    const uint32_t msm1 = meta[min(wv * kWave + NW + lane, nn - 1)];
     // 1. stage: off[csr offset] = pin offset (coalesced), pos[csr offset] =
     // cell position read from T in B order (runs of consecutive A positions).
     // Loads are unconditional (index clamped into the block) so that each
@@ -467,23 +466,30 @@ __global__ void __launch_bounds__(NW)
         }
       }
     }
+    bigmeta[t] = mbig;
+    if (t == 0) {
+      q_big = 0;
+      q_small = NWV;   // chunks 0..NWV-1 are the wavefronts' first ones
+    }
     __syncthreads();
 
-    // 2. nets in degree order.  Nets above kSmall sit at the back of the
-    // order, largest class last; wavefront w takes the back's nets w, w + 8,
-    // ... (one wavefront per net, three passes over its pins in LDS: pass 1
-    // turns positions into pin coordinates relative to the first pin's
-    // cell, pass 3 overwrites them with the gradient).  The others: one lane
-    // per net, a wavefront per chunk of kWave nets of (nearly) equal degree,
-    // loops as long as the chunk's largest degree.
-    for (int j = 0;; ++j) {
-      if (nn - 1 - wv - NWV * j < 0) break;
-      // candidates beyond the first kWave: loaded here (only blocks with more
-      // than 8 * kWave large nets get this far)
-      const uint32_t mj = j < kWave ? (uint32_t)__builtin_amdgcn_readlane((int)mbig, j)
-                                    : meta[nn - 1 - wv - NWV * j];
+    // 2. nets in degree order, work handed out by block-wide counters so
+    // that every wavefront stays busy until the block's nets run out.  Nets
+    // above kSmall sit at the back of the order, largest class last: each is
+    // taken by one wavefront, largest first (three passes over its pins in
+    // LDS: pass 1 turns positions into pin coordinates relative to the first
+    // pin's cell, pass 3 overwrites them with the gradient).  Then the
+    // others: one lane per net, a wavefront per chunk of kWave nets of
+    // (nearly) equal degree, loops as long as the chunk's largest degree.
+    for (;;) {
+      int j = 0;
+      if (lane == 0) j = atomicAdd(&q_big, 1);
+      j = __builtin_amdgcn_readfirstlane(j);
+      if (j >= nn) break;
+      // beyond the NW staged extents (more than NW large nets): from memory
+      const uint32_t mj = j < NW ? bigmeta[j] : meta[nn - 1 - j];
       const int deg = (int)(mj & 0xffffu);
-      if (deg <= kSmall) break;   // the rest of this wavefront's back part is small
+      if (deg <= kSmall) break;   // every net left is small
       const int b0 = (int)(mj >> 16), b1 = b0 + deg;
       const float2 r = pos[b0];
       wave_lds_sync();
@@ -576,15 +582,20 @@ __global__ void __launch_bounds__(NW)
       }
     }
 
-    // small nets: chunk q of this wavefront holds order entries
-    // wv * kWave + q * NW + lane; the first two chunks' extents were read
-    // with the large-net candidates, later ones one chunk ahead
-    uint32_t mcur = msm0, mnext = msm1;
-    for (int q = 0;; ++q) {
-      const int li = wv * kWave + q * NW + lane;
-      if (li - lane >= nn) break;
-      uint32_t mafter = 0u;
-      if (li - lane + 2 * NW < nn) mafter = meta[min(li + 2 * NW, nn - 1)];
+    // small nets: chunk c holds order entries c * kWave + lane; a
+    // wavefront's first chunk is its own (extents read before staging), the
+    // rest come from the counter, each one's extents read while the previous
+    // chunk is evaluated
+    int cc = wv;
+    uint32_t mcur = msm0;
+    for (;;) {
+      if (cc * kWave >= nn) break;
+      int cn = 0;
+      if (lane == 0) cn = atomicAdd(&q_small, 1);
+      cn = __builtin_amdgcn_readfirstlane(cn);
+      uint32_t mnext = 0u;
+      if (cn * kWave < nn) mnext = meta[min(cn * kWave + lane, nn - 1)];
+      const int li = cc * kWave + lane;
       int deg = li < nn ? (int)(mcur & 0xffffu) : 0;
       if (deg > kSmall) deg = 0;   // done above
       const int l0 = (int)(mcur >> 16);
@@ -655,8 +666,8 @@ __global__ void __launch_bounds__(NW)
           acc_hp += (double)(mx - lx) + (double)(my - ly);
         }
       }
+      cc = cn;
       mcur = mnext;
-      mnext = mafter;
     }
     __syncthreads();
 
