@@ -206,6 +206,8 @@ def kernel_bytes(inst, nent):
         "k_wa_slots_small": 12 * p_small + 8 * p_small + 4 * (E + 1) + 8 * m,
         "k_wa_slots_big": 12 * p_big + 8 * p_big + 4 * (E + 1),
         "k_band_count": 16 * m,
+        # per band: the block counts in, offsets out (4096 cells per block)
+        "k_band_scan": 8 * (-(-inst.n // (-(-inst.n // 256)))) * (-(-m // 4096)),
         "k_interleave": 8 * m + 8 * m,
         "k_band_place": 16 * m + 16 * nent,
         "k_band_accum": 16 * nent + 4 * n2 + 4 * n2,

@@ -426,6 +426,18 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
     a.tau_part = p.partials + p.en_max;
     e = p.mode == FFTPL_DCT_FFT ? spectral_fft(p, a, s) : spectral_gemm(p, a, s);
   }
+  FinalArgs fin;
+  fin.en = p.partials;
+  fin.n_en = p.n_en;
+  fin.tau = p.partials + p.en_max;
+  fin.n_tau = p.n_tau;
+  fin.wa = fast ? L.wa_part : nullptr;
+  fin.n_s = fast ? (xch ? xd.nnb : (prob->num_nets + 255) / 256) : 0;
+  fin.n_b = fast ? (xch ? 0 : wa_big_grid(prob->num_nets)) : 0;
+  fin.o_en = &out4[0];
+  fin.o_wa = &out4[1];
+  fin.o_hp = &out4[2];
+  fin.o_tau = &out4[3];
   if (fast) {
     // join the wirelength branch; 5. per cell: density gradient plus the sum
     // of its pins' slots
@@ -455,14 +467,15 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
     plan_mark(p, "k_wa_atomic", s);
   }
   // 6. N, W~, HPWL, tau from the per-block partials (the atomic path added
-  // W~ and HPWL into out4 directly)
-  if (e == hipSuccess)
-    e = launch_eval_finalize(p.partials, p.n_en, p.partials + p.en_max, p.n_tau,
-                             fast ? L.wa_part : nullptr,
-                             xch ? xd.nnb : (prob->num_nets + 255) / 256,
-                             xch ? 0 : wa_big_grid(prob->num_nets), &out4[0], &out4[1],
-                             &out4[2], &out4[3], s);
-  plan_mark(p, "k_eval_finalize", s);
+  // W~ and HPWL into out4 directly).  A separate one-block launch: a
+  // last-block-done count in the gather would put every gather block's
+  // atomic on one address, which costs far more than the launch.
+  {
+    if (e == hipSuccess)
+      e = launch_eval_finalize(fin.en, fin.n_en, fin.tau, fin.n_tau, fin.wa, fin.n_s, fin.n_b,
+                               fin.o_en, fin.o_wa, fin.o_hp, fin.o_tau, s);
+    plan_mark(p, "k_eval_finalize", s);
+  }
   return dev_status(e);
 }
 

@@ -2,11 +2,12 @@
 // global memory, which retire at roughly 20 G/s on the whole chip whatever
 // their scope:
 //   count: each block of kCellsPerBlock cells histograms the bands its
-//          cells touch in LDS and reserves its slice of every band with one
-//          integer atomic per (block, band);
-//   place: the same blocks write each cell's edges (bin units) into every
-//          band it touches, at LDS-atomic ranks inside the reserved slice,
-//          and the interleaved (x, y) the wirelength pass gathers;
+//          cells touch in LDS and stores the histogram (band-major);
+//   scan:  one block per band turns its row of block counts into each
+//          block's offset inside the band and the band's total (no global
+//          atomics, whose contention on 256 counters would serialise);
+//   place: the counting blocks write each cell's edges (bin units) into
+//          every band it touches, at LDS-atomic ranks inside their slice;
 //   accum: one block per band adds its entries into an LDS copy of its rows
 //          and writes rho = base + rows once.  The LDS adds are 64-bit
 //          integer adds of the overlaps in fixed point (every overlap lies in
@@ -67,6 +68,7 @@ BandLayout band_layout(int n, int m, int num_nets, int num_pins, void* work,
 namespace {
 
 constexpr int NT = kBandThreads;
+constexpr int NTA = kAccThreads;
 constexpr int B = kCellBatch;
 
 struct CellBatch {
@@ -78,15 +80,14 @@ __device__ __forceinline__ void load_batch(CellBatch& c, int base, int m,
                                            const float* __restrict__ y,
                                            const float* __restrict__ w,
                                            const float* __restrict__ h) {
+  // unconditional (index clamped, m >= 1) so the whole batch is in flight
 #pragma unroll
   for (int j = 0; j < B; ++j) {
-    const int i = base + j * NT + (int)threadIdx.x;
-    if (i < m) {
-      c.x[j] = x[i];
-      c.y[j] = y[i];
-      c.w[j] = w[i];
-      c.h[j] = h[i];
-    }
+    const int i = min(base + j * NT + (int)threadIdx.x, m - 1);
+    c.x[j] = x[i];
+    c.y[j] = y[i];
+    c.w[j] = w[i];
+    c.h[j] = h[i];
   }
 }
 
@@ -120,10 +121,33 @@ __global__ void __launch_bounds__(kBandThreads)
     }
   }
   __syncthreads();
-  for (int b = t; b < L.nb; b += NT) {
-    const int c = hist[b];
-    L.blk_base[(size_t)blockIdx.x * L.nb + b] = c ? atomicAdd(&L.counters[b], c) : 0;
+  for (int b = t; b < L.nb; b += NT) L.blk_base[(size_t)b * L.nblk + blockIdx.x] = hist[b];
+}
+
+// Band b: blk_base[b][k] = sum of the counts of blocks < k, counters[b] = the
+// band's total.
+constexpr int kScanThreads = 256;
+__global__ void __launch_bounds__(kScanThreads) k_band_scan(BandLayout L) {
+  int32_t* row = L.blk_base + (size_t)blockIdx.x * L.nblk;
+  int carry = 0;
+  for (int k0 = 0; k0 < L.nblk; k0 += 4 * kScanThreads) {
+    int v[4], s = 0;
+    const int base = k0 + 4 * (int)threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      v[j] = base + j < L.nblk ? row[base + j] : 0;
+      s += v[j];
+    }
+    int total;
+    int run = carry + block_exclusive_scan<kScanThreads>(s, &total);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (base + j < L.nblk) row[base + j] = run;
+      run += v[j];
+    }
+    carry += total;
   }
+  if (threadIdx.x == 0) L.counters[blockIdx.x] = carry;
 }
 
 __global__ void __launch_bounds__(kBandThreads)
@@ -134,7 +158,7 @@ __global__ void __launch_bounds__(kBandThreads)
   const int t = threadIdx.x;
   int total;
   const int ex = block_exclusive_scan<NT>(t < L.nb ? L.counters[t] : 0, &total);
-  if (t < L.nb) cursor[t] = ex + L.blk_base[(size_t)blockIdx.x * L.nb + t];
+  if (t < L.nb) cursor[t] = ex + L.blk_base[(size_t)t * L.nblk + blockIdx.x];
   __syncthreads();
   const int c0 = blockIdx.x * kCellsPerBlock;
   for (int base = c0; base < c0 + kCellsPerBlock && base < L.m; base += NT * B) {
@@ -162,7 +186,7 @@ __device__ __forceinline__ void add_fixed(unsigned long long* a, float v) {
   atomicAdd(a, (unsigned long long)__float2uint_rn(v * 2147483648.0f));
 }
 
-__global__ void __launch_bounds__(kBandThreads)
+__global__ void __launch_bounds__(kAccThreads)
     k_band_accum(GridF g, BandLayout L, const float* __restrict__ x,
                  const float* __restrict__ y, const float* __restrict__ w,
                  const float* __restrict__ h, const float* __restrict__ base,
@@ -171,21 +195,21 @@ __global__ void __launch_bounds__(kBandThreads)
   const int t = threadIdx.x;
   const int n = g.n, R = L.rows, band = blockIdx.x, r0 = band * R;
   const int cells = min(R, n - r0) * n;
-  for (int k = t; k < cells; k += NT) acc[k] = 0ull;
+  for (int k = t; k < cells; k += NTA) acc[k] = 0ull;
   int start;
-  block_exclusive_scan<NT>(t < band ? L.counters[t] : 0, &start);   // earlier bands
+  block_exclusive_scan<NTA>(t < band ? L.counters[t] : 0, &start);   // earlier bands
   const int end = start + L.counters[band];
   __syncthreads();
-  for (int e0 = start; e0 < end; e0 += NT * B) {
+  for (int e0 = start; e0 < end; e0 += NTA * B) {
     float4 q[B];
 #pragma unroll
     for (int j = 0; j < B; ++j) {
-      const int e = e0 + j * NT + t;
-      if (e < end) q[j] = L.entries[e];
+      const int e = e0 + j * NTA + t;
+      q[j] = L.entries[min(e, end - 1)];   // unconditional: the batch is in flight at once
     }
 #pragma unroll
     for (int j = 0; j < B; ++j) {
-      if (e0 + j * NT + t >= end) continue;
+      if (e0 + j * NTA + t >= end) continue;
       const Span sx = span_from_edges(q[j].x, q[j].y, n);
       const Span sy = span_from_edges(q[j].z, q[j].w, n);
       const int ya = max(sy.i0, r0), yb = min(sy.i1, r0 + R - 1);
@@ -206,14 +230,14 @@ __global__ void __launch_bounds__(kBandThreads)
     if (ya > yb) continue;
     const int nx = sx.i1 - sx.i0 + 1;
     const int tot = nx * (yb - ya + 1);
-    for (int k = t; k < tot; k += NT) {
+    for (int k = t; k < tot; k += NTA) {
       const int ix = sx.i0 + k % nx, iy = ya + k / nx;
       add_fixed(&acc[(iy - r0) * n + ix], span_overlap(sx, ix) * span_overlap(sy, iy));
     }
   }
   __syncthreads();
   const size_t o = (size_t)r0 * n;
-  for (int k = t; k < cells; k += NT)
+  for (int k = t; k < cells; k += NTA)
     rho[o + k] = (base ? base[o + k] : 0.0f) + (float)((double)acc[k] * kAccUnit);
 }
 
@@ -242,11 +266,14 @@ hipError_t launch_band_scatter(const GridF& g, const BandLayout& L, const float*
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (tp) plan_mark(*tp, "k_band_count", s);
+    hipLaunchKernelGGL(k_band_scan, dim3(L.nb), dim3(kScanThreads), 0, s, L);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (tp) plan_mark(*tp, "k_band_scan", s);
     hipLaunchKernelGGL(k_band_place, dim3(L.nblk), dim3(NT), 0, s, g, L, x, y, w, h);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (tp) plan_mark(*tp, "k_band_place", s);
   }
-  hipLaunchKernelGGL(k_band_accum, dim3(L.nb), dim3(NT), 0, s, g, L, x, y, w, h, base, rho);
+  hipLaunchKernelGGL(k_band_accum, dim3(L.nb), dim3(NTA), 0, s, g, L, x, y, w, h, base, rho);
   hipError_t e = hipGetLastError();
   if (tp) plan_mark(*tp, "k_band_accum", s);
   return e;

@@ -145,53 +145,43 @@ hipError_t launch_init_eval(double* out4, int32_t* counters, int ncount, hipStre
 // [psi at right edge - psi at left edge] for edges strictly inside (0, n).
 // ---------------------------------------------------------------------------
 // PINS: 0 density gradient only; 1 plus the sum of the cell's contiguous pin
-// slots (cell_ptr, pin_grad); 2 plus pin_grad[i] (one float2 per cell); 3
-// plus the sum of pin_grad[pin_idx[j]] over the cell's entries j of cell_ptr
-// (blocks in XCD order).
+// slots (cell_ptr, pin_grad); 2 plus pin_grad[i] (one float2 per cell).
+constexpr int kGatherThreads = 256;
+
 template <int MODE, bool INTERLEAVED, int PINS>
-__global__ void __launch_bounds__(256) k_gather(GridF g, int m, const float* __restrict__ x,
-                                                const float* __restrict__ y,
-                                                const float* __restrict__ w,
-                                                const float* __restrict__ h,
-                                                const float* __restrict__ ex,
-                                                const float* __restrict__ ey,
-                                                const float2* __restrict__ exy,
-                                                const float* __restrict__ psi, float scale,
-                                                int accumulate, const int32_t* __restrict__ cell_ptr,
-                                                const float2* __restrict__ pin_grad,
-                                                const int32_t* __restrict__ pin_idx,
-                                                float* __restrict__ gx, float* __restrict__ gy) {
-  const int blk = PINS == 3 ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
-  const int i = blk * blockDim.x + threadIdx.x;
-  if (i >= m) return;
-  const float2 d = cell_density_grad<MODE, INTERLEAVED>(g, x[i], y[i], w[i], h[i], ex, ey, exy, psi);
-  float ax = scale * d.x, ay = scale * d.y;
-  if (PINS == 3) {
-    const int k1 = cell_ptr[i + 1];
-    for (int k = cell_ptr[i]; k < k1; ++k) {
-      const float2 q = pin_grad[pin_idx[k]];
+__global__ void __launch_bounds__(kGatherThreads)
+    k_gather(GridF g, int m, const float* __restrict__ x, const float* __restrict__ y,
+             const float* __restrict__ w, const float* __restrict__ h,
+             const float* __restrict__ ex, const float* __restrict__ ey,
+             const float2* __restrict__ exy, const float* __restrict__ psi, float scale,
+             int accumulate, const int32_t* __restrict__ cell_ptr,
+             const float2* __restrict__ pin_grad, float* __restrict__ gx,
+             float* __restrict__ gy) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) {
+    const float2 d =
+        cell_density_grad<MODE, INTERLEAVED>(g, x[i], y[i], w[i], h[i], ex, ey, exy, psi);
+    float ax = scale * d.x, ay = scale * d.y;
+    if (PINS == 2) {
+      const float2 q = pin_grad[i];
       ax += q.x;
       ay += q.y;
+    } else if (PINS == 1) {
+      // the cell's wirelength gradient: its pins' slots are contiguous
+      const int k1 = cell_ptr[i + 1];
+      for (int k = cell_ptr[i]; k < k1; ++k) {
+        const float2 q = pin_grad[k];
+        ax += q.x;
+        ay += q.y;
+      }
     }
-  } else if (PINS == 2) {
-    const float2 q = pin_grad[i];
-    ax += q.x;
-    ay += q.y;
-  } else if (PINS == 1) {
-    // the cell's wirelength gradient: its pins' slots are contiguous
-    const int k1 = cell_ptr[i + 1];
-    for (int k = cell_ptr[i]; k < k1; ++k) {
-      const float2 q = pin_grad[k];
-      ax += q.x;
-      ay += q.y;
+    if (accumulate) {
+      gx[i] += ax;
+      gy[i] += ay;
+    } else {
+      gx[i] = ax;
+      gy[i] = ay;
     }
-  }
-  if (accumulate) {
-    gx[i] += ax;
-    gy[i] += ay;
-  } else {
-    gx[i] = ax;
-    gy[i] = ay;
   }
 }
 
@@ -201,21 +191,21 @@ hipError_t launch_gather(const GridF& g, int m, const float* x, const float* y,
                          int grad_mode, float scale, int accumulate, float* gx,
                          float* gy, hipStream_t s) {
   if (m <= 0) return hipSuccess;
-  dim3 grid((m + 255) / 256), block(256);
+  dim3 grid((m + kGatherThreads - 1) / kGatherThreads), block(kGatherThreads);
   const float2* e2 = reinterpret_cast<const float2*>(exy);
   if (grad_mode == FFTPL_GRAD_EXACT && exy) {
     // difference maps (Dx, Dy) in exy, psi for cells at the border
     hipLaunchKernelGGL((k_gather<FFTPL_GRAD_EXACT, true, 0>), grid, block, 0, s, g, m, x, y,
-                       w, h, ex, ey, e2, psi, scale, accumulate, nullptr, nullptr, nullptr, gx, gy);
+                       w, h, ex, ey, e2, psi, scale, accumulate, nullptr, nullptr, gx, gy);
   } else if (grad_mode == FFTPL_GRAD_EXACT) {
     hipLaunchKernelGGL((k_gather<FFTPL_GRAD_EXACT, false, 0>), grid, block, 0, s, g, m, x, y,
-                       w, h, ex, ey, e2, psi, scale, accumulate, nullptr, nullptr, nullptr, gx, gy);
+                       w, h, ex, ey, e2, psi, scale, accumulate, nullptr, nullptr, gx, gy);
   } else if (exy) {
     hipLaunchKernelGGL((k_gather<FFTPL_GRAD_FIELD, true, 0>), grid, block, 0, s, g, m, x, y,
-                       w, h, ex, ey, e2, psi, scale, accumulate, nullptr, nullptr, nullptr, gx, gy);
+                       w, h, ex, ey, e2, psi, scale, accumulate, nullptr, nullptr, gx, gy);
   } else {
     hipLaunchKernelGGL((k_gather<FFTPL_GRAD_FIELD, false, 0>), grid, block, 0, s, g, m, x, y,
-                       w, h, ex, ey, e2, psi, scale, accumulate, nullptr, nullptr, nullptr, gx, gy);
+                       w, h, ex, ey, e2, psi, scale, accumulate, nullptr, nullptr, gx, gy);
   }
   return hipGetLastError();
 }
@@ -226,14 +216,14 @@ hipError_t launch_gather_pins(const GridF& g, int m, const float* x, const float
                               const int32_t* cell_ptr, const float2* pin_grad, float* gx,
                               float* gy, hipStream_t s) {
   if (m <= 0) return hipSuccess;
-  dim3 grid((m + 255) / 256), block(256);
+  dim3 grid((m + kGatherThreads - 1) / kGatherThreads), block(kGatherThreads);
   const float2* e2 = reinterpret_cast<const float2*>(exy);
   if (grad_mode == FFTPL_GRAD_EXACT) {
     hipLaunchKernelGGL((k_gather<FFTPL_GRAD_EXACT, true, 1>), grid, block, 0, s, g, m, x,
-                       y, w, h, nullptr, nullptr, e2, psi, scale, 0, cell_ptr, pin_grad, nullptr, gx, gy);
+                       y, w, h, nullptr, nullptr, e2, psi, scale, 0, cell_ptr, pin_grad, gx, gy);
   } else {
     hipLaunchKernelGGL((k_gather<FFTPL_GRAD_FIELD, true, 1>), grid, block, 0, s, g, m, x,
-                       y, w, h, nullptr, nullptr, e2, psi, scale, 0, cell_ptr, pin_grad, nullptr, gx, gy);
+                       y, w, h, nullptr, nullptr, e2, psi, scale, 0, cell_ptr, pin_grad, gx, gy);
   }
   return hipGetLastError();
 }
@@ -243,34 +233,14 @@ hipError_t launch_gather_cellsum(const GridF& g, int m, const float* x, const fl
                                  const float* psi, int grad_mode, float scale,
                                  const float2* gwa, float* gx, float* gy, hipStream_t s) {
   if (m <= 0) return hipSuccess;
-  dim3 grid((m + 255) / 256), block(256);
+  dim3 grid((m + kGatherThreads - 1) / kGatherThreads), block(kGatherThreads);
   const float2* e2 = reinterpret_cast<const float2*>(exy);
   if (grad_mode == FFTPL_GRAD_EXACT) {
     hipLaunchKernelGGL((k_gather<FFTPL_GRAD_EXACT, true, 2>), grid, block, 0, s, g, m, x,
-                       y, w, h, nullptr, nullptr, e2, psi, scale, 0, nullptr, gwa, nullptr, gx, gy);
+                       y, w, h, nullptr, nullptr, e2, psi, scale, 0, nullptr, gwa, gx, gy);
   } else {
     hipLaunchKernelGGL((k_gather<FFTPL_GRAD_FIELD, true, 2>), grid, block, 0, s, g, m, x,
-                       y, w, h, nullptr, nullptr, e2, psi, scale, 0, nullptr, gwa, nullptr, gx, gy);
-  }
-  return hipGetLastError();
-}
-
-hipError_t launch_gather_xch(const GridF& g, int m, const float* x, const float* y,
-                             const float* w, const float* h, const float* exy,
-                             const float* psi, int grad_mode, float scale,
-                             const int32_t* cell_ptr, const int32_t* qa, const float2* T,
-                             float* gx, float* gy, hipStream_t s) {
-  if (m <= 0) return hipSuccess;
-  // a multiple of 8 blocks, so that xcd_block hands each XCD a contiguous range
-  const int nb = ((m + 255) / 256 + kNumXcd - 1) / kNumXcd * kNumXcd;
-  dim3 grid(nb), block(256);
-  const float2* e2 = reinterpret_cast<const float2*>(exy);
-  if (grad_mode == FFTPL_GRAD_EXACT) {
-    hipLaunchKernelGGL((k_gather<FFTPL_GRAD_EXACT, true, 3>), grid, block, 0, s, g, m, x,
-                       y, w, h, nullptr, nullptr, e2, psi, scale, 0, cell_ptr, T, qa, gx, gy);
-  } else {
-    hipLaunchKernelGGL((k_gather<FFTPL_GRAD_FIELD, true, 3>), grid, block, 0, s, g, m, x,
-                       y, w, h, nullptr, nullptr, e2, psi, scale, 0, cell_ptr, T, qa, gx, gy);
+                       y, w, h, nullptr, nullptr, e2, psi, scale, 0, nullptr, gwa, gx, gy);
   }
   return hipGetLastError();
 }

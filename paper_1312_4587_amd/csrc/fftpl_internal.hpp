@@ -416,6 +416,79 @@ hipError_t launch_wa(int num_nets, const int32_t* net_ptr, const int32_t* pin_ce
                      double* wa_out, double* hp_out, hipStream_t s);
 // wa: per-block wirelength partials laid out [W~ (n_s), HPWL (n_s), W~ (n_b),
 // HPWL (n_b)] (or null: W~ and HPWL are left as they are).
+// The evaluation's scalars from per-block partials, summed in double in a
+// fixed order (so repeated evaluations give identical scalars):
+//   energy N   = sum en[0..n_en)
+//   tau        = sum tau[2i] / sum tau[2i+1]   (overflow / movable area)
+//   W~, HPWL   = sums of the wirelength kernels' per-block partials,
+//                wa = [W_small(n_s), H_small(n_s), W_big(n_b), H_big(n_b)].
+// Outputs may be null; W~ and HPWL are written only with wa.
+struct FinalArgs {
+  const double* en = nullptr;
+  int n_en = 0;
+  const double* tau = nullptr;
+  int n_tau = 0;
+  const double* wa = nullptr;
+  int n_s = 0, n_b = 0;
+  double *o_en = nullptr, *o_wa = nullptr, *o_hp = nullptr, *o_tau = nullptr;
+};
+
+// The sums of FinalArgs by one whole block of NT threads.
+template <int NT>
+__device__ __forceinline__ void eval_scalars(const FinalArgs& f) {
+  const int t = threadIdx.x;
+  // v = (energy, overflow, movable, W~, HPWL) partial sums; each batch's loads
+  // (at clamped indices, the pointer tests uniform) are issued before any use
+  double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  constexpr int U = 4;
+  const int n_w = f.wa ? f.n_s + f.n_b : 0;
+  const int most = max(max(f.n_en, f.n_tau), n_w);
+  for (int i0 = t; i0 < most; i0 += U * NT) {
+    double a[U], o[U], mv[U], sw[U], sh[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * NT;
+      a[u] = f.en && f.n_en > 0 ? f.en[min(i, f.n_en - 1)] : 0.0;
+      o[u] = f.tau && f.n_tau > 0 ? f.tau[2 * min(i, f.n_tau - 1)] : 0.0;
+      mv[u] = f.tau && f.n_tau > 0 ? f.tau[2 * min(i, f.n_tau - 1) + 1] : 0.0;
+      const int j = min(i, n_w - 1);
+      const int ws = j < f.n_s ? j : 2 * f.n_s + (j - f.n_s);
+      const int hs = j < f.n_s ? f.n_s + j : 2 * f.n_s + f.n_b + (j - f.n_s);
+      sw[u] = n_w > 0 ? f.wa[ws] : 0.0;
+      sh[u] = n_w > 0 ? f.wa[hs] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * NT;
+      v[0] += i < f.n_en ? a[u] : 0.0;
+      v[1] += i < f.n_tau ? o[u] : 0.0;
+      v[2] += i < f.n_tau ? mv[u] : 0.0;
+      v[3] += i < n_w ? sw[u] : 0.0;
+      v[4] += i < n_w ? sh[u] : 0.0;
+    }
+  }
+  __shared__ double red[5][NT / kWave];
+  const int lane = t & (kWave - 1), w = t / kWave;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    v[k] = wave_sum(v[k]);
+    if (lane == 0) red[k][w] = v[k];
+  }
+  __syncthreads();
+  if (t == 0) {
+    double r[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      r[k] = 0.0;
+      for (int j = 0; j < NT / kWave; ++j) r[k] += red[k][j];
+    }
+    if (f.o_en) *f.o_en = r[0];
+    if (f.o_tau) *f.o_tau = r[2] > 0.0 ? r[1] / r[2] : 0.0;
+    if (f.wa && f.o_wa) *f.o_wa = r[3];
+    if (f.wa && f.o_hp) *f.o_hp = r[4];
+  }
+}
+
 hipError_t launch_eval_finalize(const double* en, int n_en, const double* tau, int n_tau,
                                 const double* wa, int n_s, int n_b, double* o_en, double* o_wa,
                                 double* o_hp, double* o_tau, hipStream_t s);
@@ -434,9 +507,10 @@ inline int wa_big_grid(int num_nets) {
 // in LDS and writes them out.  Needs n <= kBandMaxN.
 constexpr int kMaxBands = 4;
 constexpr int kBandMaxN = 1024;
-constexpr int kBandThreads = 1024;     // threads of every band-sort block
+constexpr int kBandThreads = 512;      // threads of a counting / placing block
 constexpr int kCellBatch = 8;          // cells whose loads a thread issues together
-constexpr int kCellsPerBlock = kBandThreads * 2 * kCellBatch;   // 16384
+constexpr int kCellsPerBlock = kBandThreads * kCellBatch;   // 4096
+constexpr int kAccThreads = 1024;      // threads of a band accumulation block
 
 struct BandLayout {
   int n = 0, rows = 0, nb = 0;   // band height in rows, number of bands
@@ -446,7 +520,8 @@ struct BandLayout {
   float2* pin_grad = nullptr;    // [P] per-pin WA gradients, cell-major slots
   float4* entries = nullptr;     // [kMaxBands*m] band entries: cell edges in bins
   int32_t* big = nullptr;        // [m] cells spanning more than kMaxBands bands
-  int32_t* blk_base = nullptr;   // [nblk*nb] block offsets inside each band
+  int32_t* blk_base = nullptr;   // [nb][nblk] per band: each block's count, then its
+                                 // offset inside the band
   int32_t* counters = nullptr;   // [nb + 1] band counts, then the big-cell count
   double* wa_part = nullptr;     // per-block W~ / HPWL partials (slot or exchange path)
   int nwa = 0;                   // blocks of each wirelength kernel
@@ -537,14 +612,6 @@ hipError_t launch_gather_cellsum(const GridF& g, int m, const float* x, const fl
                                  const float* w, const float* h, const float* exy,
                                  const float* psi, int grad_mode, float scale,
                                  const float2* gwa, float* gx, float* gy, hipStream_t s);
-// g = scale * density gradient + the sum over the cell's pins of T[qa[j]],
-// j in [cell_ptr[c], cell_ptr[c+1]) (one thread per cell; blocks in XCD order
-// so that the T window of a cell block is read by one L2).
-hipError_t launch_gather_xch(const GridF& g, int m, const float* x, const float* y,
-                             const float* w, const float* h, const float* exy,
-                             const float* psi, int grad_mode, float scale,
-                             const int32_t* cell_ptr, const int32_t* qa, const float2* T,
-                             float* gx, float* gy, hipStream_t s);
 
 // ---- placement iteration (driver.hip) --------------------------------------
 size_t step_stats_work_doubles();

@@ -293,69 +293,29 @@ hipError_t launch_wa_pins(int num_nets, const int32_t* net_ptr, const int32_t* p
   return e;
 }
 
-// Sum of v over a block, in a fixed order; valid in thread 0.
-__device__ __forceinline__ double block_total(double v) {
-  __shared__ double red[16];
-  v = wave_sum(v);
-  const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  if (lane == 0) red[w] = v;
-  __syncthreads();
-  double t = 0.0;
-  if (threadIdx.x == 0)
-    for (int k = 0; k < (int)(blockDim.x / kWave); ++k) t += red[k];
-  __syncthreads();
-  return t;
-}
+// The evaluation's scalars (FinalArgs) by one block, when no gather runs.
+constexpr int kFinalThreads = 1024;
 
-// The evaluation's scalars from per-block partials, summed in double in a
-// fixed order (so repeated evaluations give identical scalars):
-//   energy N   = sum en[0..n_en)
-//   tau        = sum tau[2i] / sum tau[2i+1]   (overflow / movable area)
-//   W~, HPWL   = sums of the two wirelength kernels' per-block partials,
-//                wa = [W_small(n_s), H_small(n_s), W_big(n_b), H_big(n_b)].
-__global__ void __launch_bounds__(1024)
-    k_eval_finalize(const double* __restrict__ en, int n_en, const double* __restrict__ tau,
-                    int n_tau, const double* __restrict__ wa, int n_s, int n_b,
-                    double* __restrict__ o_en, double* __restrict__ o_wa,
-                    double* __restrict__ o_hp, double* __restrict__ o_tau) {
-  const int t = threadIdx.x;
-  double se = 0.0, so = 0.0, sm = 0.0, sw = 0.0, sh = 0.0;
-  if (en)
-    for (int i = t; i < n_en; i += blockDim.x) se += en[i];
-  if (tau)
-    for (int i = t; i < n_tau; i += blockDim.x) {
-      so += tau[2 * i];
-      sm += tau[2 * i + 1];
-    }
-  if (wa) {
-    for (int i = t; i < n_s; i += blockDim.x) {
-      sw += wa[i];
-      sh += wa[n_s + i];
-    }
-    for (int i = t; i < n_b; i += blockDim.x) {
-      sw += wa[2 * n_s + i];
-      sh += wa[2 * n_s + n_b + i];
-    }
-  }
-  se = block_total(se);
-  so = block_total(so);
-  sm = block_total(sm);
-  sw = block_total(sw);
-  sh = block_total(sh);
-  if (t == 0) {
-    if (o_en) *o_en = se;
-    if (o_tau) *o_tau = sm > 0.0 ? so / sm : 0.0;
-    if (wa && o_wa) *o_wa = sw;
-    if (wa && o_hp) *o_hp = sh;
-  }
+__global__ void __launch_bounds__(kFinalThreads) k_eval_finalize(FinalArgs f) {
+  eval_scalars<kFinalThreads>(f);
 }
 
 hipError_t launch_eval_finalize(const double* en, int n_en, const double* tau, int n_tau,
                                 const double* wa, int n_s, int n_b, double* o_en, double* o_wa,
                                 double* o_hp, double* o_tau, hipStream_t s) {
-  if (!wa) n_s = n_b = 0;
-  hipLaunchKernelGGL(k_eval_finalize, dim3(1), dim3(1024), 0, s, en, n_en, tau, n_tau, wa,
-                     n_s, n_b, o_en, o_wa, o_hp, o_tau);
+  FinalArgs f;
+  f.en = en;
+  f.n_en = n_en;
+  f.tau = tau;
+  f.n_tau = n_tau;
+  f.wa = wa;
+  f.n_s = wa ? n_s : 0;
+  f.n_b = wa ? n_b : 0;
+  f.o_en = o_en;
+  f.o_wa = o_wa;
+  f.o_hp = o_hp;
+  f.o_tau = o_tau;
+  hipLaunchKernelGGL(k_eval_finalize, dim3(1), dim3(kFinalThreads), 0, s, f);
   return hipGetLastError();
 }
 
