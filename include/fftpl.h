@@ -102,7 +102,9 @@ typedef struct fftpl_plan fftpl_plan;
  *
  * Optional, for the atomic-free evaluation paths (n <= 1024): a device
  * workspace `work` of work_bytes >= fftpl_problem_work_bytes(...) bytes, owned
- * by the caller and used by one evaluation at a time, and one pin index:
+ * by the caller and used by one evaluation at a time, and one pin index
+ * (work and xindex 256-byte aligned, as device allocations are; otherwise
+ * fftpl_eval returns FFTPL_E_INVAL):
  *   - the exchange index (fastest): xindex / xindex_bytes from
  *     fftpl_xindex_build for this netlist and max_degree;
  *   - or the cell-major slots: cell_ptr [num_cells+1] and pin_slot
@@ -252,7 +254,7 @@ int fftpl_netlist_index(int32_t num_cells, int32_t num_pins, const int32_t* pin_
 
 /* Exchange index of a netlist (Section II: the netlist as a hypergraph; the
  * index is a blocked form of the transpose of its pin-net incidence), for the
- * fastest fftpl_eval path.  Cells are cut into blocks of 4096 consecutive
+ * fastest fftpl_eval path.  Cells are cut into blocks of 8192 consecutive
  * cells and nets into blocks of whole nets (at most 9728 pins per block); the
  * index lists the pins by (cell block, net block) and, per net block, by cell
  * block, so that positions and gradients move between cells and nets in runs
@@ -263,8 +265,9 @@ int fftpl_netlist_index(int32_t num_cells, int32_t num_pins, const int32_t* pin_
  * max_degree.  Host-only.  FFTPL_E_UNSUPPORTED when max_degree > 8705.
  *
  * fftpl_xindex_build: builds the index into `index` (index_bytes, caller
- * owned; valid until net_ptr or pin_cell change) using `work` (work_bytes,
- * free again on return), on `stream`, and waits for it (the call
+ * owned, 256-byte aligned; valid until net_ptr or pin_cell change) using
+ * `work` (work_bytes, 256-byte aligned, free again on return), on `stream`,
+ * and waits for it (the call
  * synchronises the stream).  FFTPL_E_INVAL when a net has more than
  * max_degree pins, when net_ptr is not a CSR over num_pins pins or when a
  * pin_cell lies outside [0, num_cells); the index is then unusable. */

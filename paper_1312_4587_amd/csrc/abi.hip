@@ -334,6 +334,11 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
   // the exchange index (xch) or the cell-major slots (slots).
   size_t need = 0;
   BandLayout L = band_layout(p.n, m, prob->num_nets, prob->num_pins, nullptr, &need);
+  // the workspace and the index are read in 16-byte vectors: device
+  // allocations are 256-byte aligned, and so must these be
+  if ((reinterpret_cast<uintptr_t>(prob->work) & 255) != 0 ||
+      (reinterpret_cast<uintptr_t>(prob->xindex) & 255) != 0)
+    return FFTPL_E_INVAL;
   const bool ws_ok = prob->work && prob->work_bytes >= need && p.n <= kBandMaxN;
   XchDims xd;
   const bool xch = ws_ok && prob->xindex &&
@@ -361,46 +366,45 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
   p.nev = 0;
   plan_mark(p, "start", s);
   // With per-kernel timing on, everything runs on `s` so that consecutive
-  // events bracket single kernels; otherwise the wirelength kernels overlap
-  // the density and the solve on the plan's side stream.
+  // events bracket single kernels.  Otherwise the density branch (zeroing,
+  // banded scatter, solve) runs on the plan's side stream `ds` while the
+  // wirelength branch, the longer of the two, stays on `s`: the hand-over
+  // between streams costs several microseconds each way, and this way the
+  // fork delays only the shorter branch and the join is usually complete
+  // by the time the wirelength branch reaches it.
   const bool overlap = fast && !p.timing;
-  hipStream_t ws = overlap ? p.side : s;
+  hipStream_t ds = overlap ? p.side : s;
   if (fast) {
-    // the wirelength branch reads only the inputs and writes only its own
-    // buffers, so it forks before the zeroing of the scalars and counters
     if (overlap) {
       e = hipEventRecord(p.fork, s);
-      if (e == hipSuccess) e = hipStreamWaitEvent(ws, p.fork, 0);
+      if (e == hipSuccess) e = hipStreamWaitEvent(ds, p.fork, 0);
     }
-    // 1. zero scalars and band counters
-    if (e == hipSuccess) e = launch_init_eval(out4, L.counters, L.nb + 1, s);
-    plan_mark(p, "k_init_eval", s);
-    // wirelength branch: interleave positions, per-pin WA gradients into
-    // cell-major slots
+    // density branch: 1. zero scalars and band counters, 2. banded scatter
+    if (e == hipSuccess) e = launch_init_eval(out4, L.counters, L.nb + 1, ds);
+    plan_mark(p, "k_init_eval", ds);
+    if (e == hipSuccess)
+      e = launch_band_scatter(g, L, x, y, prob->w, prob->h, prob->base, p.rho, ds, &p);
+    // wirelength branch
     if (xch) {
-      // pin positions into the exchange buffer, then every net block
-      if (e == hipSuccess) e = launch_xch_spread(xd, X, x, y, L.pin_grad, ws);
-      plan_mark(p, "k_xch_spread", ws);
+      // pin positions into the exchange buffer, then every net block, then
+      // per-cell sums of the pin gradients (into the xy region)
+      if (e == hipSuccess) e = launch_xch_spread(xd, X, x, y, L.pin_grad, s);
+      plan_mark(p, "k_xch_spread", s);
       if (e == hipSuccess)
         e = launch_xch_wa(xd, X, prob->net_ptr, prob->pin_dx, prob->pin_dy, gamma,
-                          L.pin_grad, L.wa_part, ws);
-      plan_mark(p, "k_xch_wa", ws);
-      // per-cell sums of the pin gradients (into the xy region), still on the
-      // wirelength branch so that they overlap the scatter and the solve
-      if (e == hipSuccess && grads) e = launch_xch_cellsum(xd, X, L.pin_grad, L.xy, ws);
-      if (grads) plan_mark(p, "k_xch_cellsum", ws);
+                          L.pin_grad, L.wa_part, s);
+      plan_mark(p, "k_xch_wa", s);
+      if (e == hipSuccess && grads) e = launch_xch_cellsum(xd, X, L.pin_grad, L.xy, s);
+      if (grads) plan_mark(p, "k_xch_cellsum", s);
     } else {
-      if (e == hipSuccess) e = launch_interleave(m, x, y, L.xy, ws);
-      plan_mark(p, "k_interleave", ws);
+      // interleave positions, per-pin WA gradients into cell-major slots
+      if (e == hipSuccess) e = launch_interleave(m, x, y, L.xy, s);
+      plan_mark(p, "k_interleave", s);
       if (e == hipSuccess)
         e = launch_wa_pins(prob->num_nets, prob->net_ptr, prob->pin_cell, prob->pin_dx,
                            prob->pin_dy, L.xy, prob->pin_slot, gamma, L.pin_grad, L.wa_part,
-                           ws, &p);
+                           s, &p);
     }
-    if (e == hipSuccess && overlap) e = hipEventRecord(p.join, ws);
-    // 2. banded density scatter
-    if (e == hipSuccess)
-      e = launch_band_scatter(g, L, x, y, prob->w, prob->h, prob->base, p.rho, s, &p);
   } else {
     // 1. reset: rho = base, scalar accumulators = 0; 2. atomic scatter
     e = launch_fill(p.rho, prob->base, 0.0f, nn, s);
@@ -410,7 +414,8 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
     if (e == hipSuccess) e = launch_scatter(g, m, x, y, prob->w, prob->h, p.rho, s);
     plan_mark(p, "k_scatter", s);
   }
-  // 3. spectral solve; overflow sums in the first pass, energy in the last
+  // 3. spectral solve (density branch); overflow sums in the first pass,
+  // energy in the last
   if (e == hipSuccess) {
     SpectralArgs a;
     a.rho = p.rho;
@@ -424,7 +429,12 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
     a.cap = prob->cap;
     a.rho_t = g.rho_t;
     a.tau_part = p.partials + p.en_max;
-    e = p.mode == FFTPL_DCT_FFT ? spectral_fft(p, a, s) : spectral_gemm(p, a, s);
+    e = p.mode == FFTPL_DCT_FFT ? spectral_fft(p, a, ds) : spectral_gemm(p, a, ds);
+  }
+  // join the density branch
+  if (e == hipSuccess && overlap) {
+    e = hipEventRecord(p.join, ds);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, p.join, 0);
   }
   FinalArgs fin;
   fin.en = p.partials;
@@ -439,9 +449,7 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
   fin.o_hp = &out4[2];
   fin.o_tau = &out4[3];
   if (fast) {
-    // join the wirelength branch; 5. per cell: density gradient plus the sum
-    // of its pins' slots
-    if (e == hipSuccess && overlap) e = hipStreamWaitEvent(s, p.join, 0);
+    // 5. per cell: density gradient plus the sum of its pins' gradients
     if (!grads) {
       // scalars only
     } else if (xch) {
@@ -554,6 +562,9 @@ int fftpl_xindex_build(int32_t num_cells, int32_t num_nets, int32_t num_pins,
   if (!net_ptr || !index || !work || (num_pins > 0 && !pin_cell)) return FFTPL_E_INVAL;
   if (num_pins > 0 && num_cells == 0) return FFTPL_E_INVAL;
   if (index_bytes < d.index_bytes || work_bytes < d.work_bytes) return FFTPL_E_INVAL;
+  if ((reinterpret_cast<uintptr_t>(index) & 255) != 0 ||
+      (reinterpret_cast<uintptr_t>(work) & 255) != 0)
+    return FFTPL_E_INVAL;
   return xch_build(d, net_ptr, pin_cell, index, work, as_stream(stream));
 }
 

@@ -386,16 +386,34 @@ __global__ void __launch_bounds__(NT)
   const int b0 = cb_a_ptr[cb], b1 = cb_a_ptr[cb + 1];
   const int len = (b1 - b0 + kXchSpreadSplit - 1) / kXchSpreadSplit;
   const int a0 = b0 + part * len, a1 = min(b1, a0 + len);
-  // loads of one batch are unconditional (clamped index) so they are all in
-  // flight together; only the stores are masked
+  if (a0 >= a1) return;
+  // pairs of consecutive A positions aligned to 2, consecutive pairs on
+  // consecutive lanes: one 4-byte load of their cell indices and one 16-byte
+  // store of their positions per pair, both coalesced across the wavefront;
+  // a pair straddling either end of the range is stored only inside it (its
+  // index load stays inside the index allocation)
+  const int g0 = a0 >> 1, g1 = (a1 + 1) >> 1;
+  const uint32_t* lc2 = reinterpret_cast<const uint32_t*>(lc);
+  float4* T2 = reinterpret_cast<float4*>(T);
   constexpr int U = 8;
-  for (int a = a0 + t; a < a1; a += U * NT) {
-    int l[U];
+  for (int g = g0 + t; g < g1; g += U * NT) {
+    uint32_t q[U];
 #pragma unroll
-    for (int k = 0; k < U; ++k) l[k] = lc[min(a + k * NT, a1 - 1)];
+    for (int k = 0; k < U; ++k) q[k] = lc2[min(g + k * NT, g1 - 1)];
 #pragma unroll
-    for (int k = 0; k < U; ++k)
-      if (a + k * NT < a1) T[a + k * NT] = win[min(l[k], kXchCells - 1)];
+    for (int k = 0; k < U; ++k) {
+      const int gg = g + k * NT;
+      if (gg >= g1) continue;
+      const float2 v0 = win[min((int)(q[k] & 0xffffu), kXchCells - 1)];
+      const float2 v1 = win[min((int)(q[k] >> 16), kXchCells - 1)];
+      const int a = gg * 2;
+      if (a >= a0 && a + 2 <= a1) {
+        T2[gg] = make_float4(v0.x, v0.y, v1.x, v1.y);
+      } else {
+        if (a >= a0) T[a] = v0;
+        if (a + 1 < a1) T[a + 1] = v1;
+      }
+    }
   }
 }
 
@@ -706,26 +724,38 @@ __global__ void __launch_bounds__(kSumThreads)
   }
   __syncthreads();
   const int a0 = cb_a_ptr[cb], a1 = cb_a_ptr[cb + 1];
-  // loads of one batch are unconditional (clamped index) so they are all in
-  // flight together
-  constexpr int U = 8;
-  for (int a = a0 + t; a < a1; a += U * kSumThreads) {
-    int l[U];
-    float2 v[U];
+  // pairs of consecutive A positions aligned to 2, consecutive pairs on
+  // consecutive lanes (one 4-byte load of their cell indices and one 16-byte
+  // load of their gradients, coalesced); positions outside the range are
+  // skipped (the loads of a straddling pair stay inside the allocations)
+  const int g0 = a0 >> 1, g1 = (a1 + 1) >> 1;
+  const uint32_t* lc2 = reinterpret_cast<const uint32_t*>(lc);
+  const float4* T2 = reinterpret_cast<const float4*>(T);
+  constexpr int U = 4;
+  for (int g = g0 + t; g < g1; g += U * kSumThreads) {
+    uint32_t q[U];
+    float4 v[U];
 #pragma unroll
     for (int k = 0; k < U; ++k) {
-      const int i = min(a + k * kSumThreads, a1 - 1);
-      l[k] = min(lc[i], kXchCells - 1);
-      v[k] = T[i];
+      const int gg = min(g + k * kSumThreads, g1 - 1);
+      q[k] = lc2[gg];
+      v[k] = T2[gg];
     }
 #pragma unroll
     for (int k = 0; k < U; ++k) {
-      if (a + k * kSumThreads < a1) {
-        if (fabsf(v[k].x) <= 3.0e38f && fabsf(v[k].y) <= 3.0e38f) {
-          atomicAdd(&ax[l[k]], (unsigned long long)(long long)__float2int_rn(v[k].x * scale));
-          atomicAdd(&ay[l[k]], (unsigned long long)(long long)__float2int_rn(v[k].y * scale));
+      const int gg = g + k * kSumThreads;
+      if (gg >= g1) continue;
+      const int a = gg * 2;
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        if (a + e < a0 || a + e >= a1) continue;
+        const int l = min((int)(e ? q[k] >> 16 : q[k] & 0xffffu), kXchCells - 1);
+        const float gxv = e ? v[k].z : v[k].x, gyv = e ? v[k].w : v[k].y;
+        if (fabsf(gxv) <= 3.0e38f && fabsf(gyv) <= 3.0e38f) {
+          atomicAdd(&ax[l], (unsigned long long)(long long)__float2int_rn(gxv * scale));
+          atomicAdd(&ay[l], (unsigned long long)(long long)__float2int_rn(gyv * scale));
         } else {
-          bad[l[k]] = 1;
+          bad[l] = 1;
         }
       }
     }
