@@ -159,13 +159,16 @@ __global__ void __launch_bounds__(kGatherThreads)
              float* __restrict__ gy) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < m) {
+    // the cell's own loads (and its pin sum) go out together, before the map
+    // reads that depend on them
+    const float xi = x[i], yi = y[i], wi = w[i], hi = h[i];
+    const float2 q2 = PINS == 2 ? pin_grad[i] : make_float2(0.0f, 0.0f);
     const float2 d =
-        cell_density_grad<MODE, INTERLEAVED>(g, x[i], y[i], w[i], h[i], ex, ey, exy, psi);
+        cell_density_grad<MODE, INTERLEAVED>(g, xi, yi, wi, hi, ex, ey, exy, psi);
     float ax = scale * d.x, ay = scale * d.y;
     if (PINS == 2) {
-      const float2 q = pin_grad[i];
-      ax += q.x;
-      ay += q.y;
+      ax += q2.x;
+      ay += q2.y;
     } else if (PINS == 1) {
       // the cell's wirelength gradient: its pins' slots are contiguous
       const int k1 = cell_ptr[i + 1];
