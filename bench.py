@@ -32,23 +32,27 @@ PMC_FETCH_SCALE, PMC_WRITE_SCALE = 2.0, 1.0
 PMC_TRAFFIC = {
     # kernel: (source files, sha1, FETCH_SIZE KiB, WRITE_SIZE KiB)
     "k_xch_spread": (("exchange.hip", "fftpl_internal.hpp"),
-                     "b95c39bfae32e7c571cc3b51923f15b8065c0633", 28568.9, 96804.8),
+        "5a03760b7ff584b53161d08316d12b4a1a738250", 28614.3, 96865.4),
     "k_xch_wa": (("exchange.hip", "fftpl_internal.hpp"),
-                 "b95c39bfae32e7c571cc3b51923f15b8065c0633", 190057.8, 116215.7),
-    "k_gather_xch": (("density.hip", "fftpl_internal.hpp"),
-                     "c343ae05da83ba4a2d83d392b897c0e853905d47", 260405.8, 16406.2),
+        "5a03760b7ff584b53161d08316d12b4a1a738250", 187983.6, 116210.9),
+    "k_xch_cellsum": (("exchange.hip", "fftpl_internal.hpp"),
+        "5a03760b7ff584b53161d08316d12b4a1a738250", 60559.2, 16406.2),
     "k_band_count": (("band_scatter.hip", "fftpl_internal.hpp"),
-                     "2e45a52078ee8073d0e6ef2e6c80b2d1ce6923c9", 16462.8, 258.0),
+        "7ac4d6b1345cab2fc65030a16b54d96fc0d06f06", 16465.0, 4097.0),
+    "k_band_scan": (("band_scatter.hip", "fftpl_internal.hpp"),
+        "7ac4d6b1345cab2fc65030a16b54d96fc0d06f06", 289.1, 528.0),
     "k_band_place": (("band_scatter.hip", "fftpl_internal.hpp"),
-                     "2e45a52078ee8073d0e6ef2e6c80b2d1ce6923c9", 16528.8, 36965.4),
+        "7ac4d6b1345cab2fc65030a16b54d96fc0d06f06", 18512.1, 44582.2),
     "k_band_accum": (("band_scatter.hip", "fftpl_internal.hpp"),
-                     "2e45a52078ee8073d0e6ef2e6c80b2d1ce6923c9", 20115.6, 4096.0),
+        "7ac4d6b1345cab2fc65030a16b54d96fc0d06f06", 20123.8, 4096.0),
     "k_rows_dct2": (("spectral_fft.hip", "fftpl_internal.hpp"),
-                    "67b3b3149ae902dd0fa74dc14dae95fb132ce129", 6287.7, 4112.0),
+        "902fd602d9356c5243700962d83fbbb907195c5c", 6235.2, 4112.0),
     "k_cols_solve": (("spectral_fft.hip", "fftpl_internal.hpp"),
-                     "67b3b3149ae902dd0fa74dc14dae95fb132ce129", 2229.1, 8192.0),
+        "902fd602d9356c5243700962d83fbbb907195c5c", 2171.1, 8192.0),
     "k_rows_inverse": (("spectral_fft.hip", "fftpl_internal.hpp"),
-                       "67b3b3149ae902dd0fa74dc14dae95fb132ce129", 6339.6, 8196.0),
+        "902fd602d9356c5243700962d83fbbb907195c5c", 6269.6, 8196.0),
+    "k_gather_cellsum": (("density.hip", "fftpl_internal.hpp"),
+        "748d4b8fd2027ea92219da83c0d6b07af8c8c67a", 144656.4, 16406.2),
 }
 
 
