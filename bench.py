@@ -51,8 +51,6 @@ PMC_TRAFFIC = {
         "902fd602d9356c5243700962d83fbbb907195c5c", 2171.1, 8192.0),
     "k_rows_inverse": (("spectral_fft.hip", "fftpl_internal.hpp"),
         "902fd602d9356c5243700962d83fbbb907195c5c", 6269.6, 8196.0),
-    "k_gather_cellsum": (("density.hip", "fftpl_internal.hpp"),
-        "748d4b8fd2027ea92219da83c0d6b07af8c8c67a", 144656.4, 16406.2),
 }
 
 
@@ -213,7 +211,7 @@ def kernel_bytes(inst, nent):
         # per band: the block counts in, offsets out (4096 cells per block)
         "k_band_scan": 8 * (-(-inst.n // (-(-inst.n // 256)))) * (-(-m // 4096)),
         "k_interleave": 8 * m + 8 * m,
-        "k_band_place": 16 * m + 16 * nent,
+        "k_band_place": 16 * m + 16 * nent + 4 * m,   # + each cell's first entry
         "k_band_accum": 16 * nent + 4 * n2 + 4 * n2,
         "k_rows_dct2": 4 * n2 + 4 * n2 + 8 * n2,        # rho, base+cap in; bT out
         "k_cols_solve": 4 * n2 + 8 * n2,                # bT in; P, Q out
@@ -224,9 +222,12 @@ def kernel_bytes(inst, nent):
         "k_xch_spread": 8 * m + 2 * P + 8 * P,
         "k_xch_wa": 4 * P + 2 * P + 8 * P + 8 * P + 8 * P + 4 * (E + 1) + 2 * E,
         "k_gather_xch": 16 * m + 8 * n2 + 4 * (m + 1) + 4 * P + 8 * P + 8 * m,
-        # cell-block windows of T with their u16 cell-local indices; sums out
-        "k_xch_cellsum": 2 * P + 8 * P + 8 * m,
-        "k_gather_cellsum": 16 * m + 8 * n2 + 8 * m + 8 * m,
+        # cell-block windows of T with their u16 cell-local indices; each
+        # cell's entry position and density gradient in, its gradient out
+        "k_xch_cellsum": 2 * P + 8 * P + 4 * m + 8 * m + 8 * m,
+        # band entries in, the field rows of each band once, one gradient per
+        # first-band entry out
+        "k_band_gather": 16 * nent + 8 * n2 + 8 * m,
         "k_eval_finalize": 0,
     }
 

@@ -386,16 +386,14 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
       e = launch_band_scatter(g, L, x, y, prob->w, prob->h, prob->base, p.rho, ds, &p);
     // wirelength branch
     if (xch) {
-      // pin positions into the exchange buffer, then every net block, then
-      // per-cell sums of the pin gradients (into the xy region)
+      // pin positions into the exchange buffer, then every net block (the
+      // per-cell sums follow the join)
       if (e == hipSuccess) e = launch_xch_spread(xd, X, x, y, L.pin_grad, s);
       plan_mark(p, "k_xch_spread", s);
       if (e == hipSuccess)
         e = launch_xch_wa(xd, X, prob->net_ptr, prob->pin_dx, prob->pin_dy, gamma,
                           L.pin_grad, L.wa_part, s);
       plan_mark(p, "k_xch_wa", s);
-      if (e == hipSuccess && grads) e = launch_xch_cellsum(xd, X, L.pin_grad, L.xy, s);
-      if (grads) plan_mark(p, "k_xch_cellsum", s);
     } else {
       // interleave positions, per-pin WA gradients into cell-major slots
       if (e == hipSuccess) e = launch_interleave(m, x, y, L.xy, s);
@@ -431,6 +429,13 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
     a.tau_part = p.partials + p.en_max;
     e = p.mode == FFTPL_DCT_FFT ? spectral_fft(p, a, ds) : spectral_gemm(p, a, ds);
   }
+  // exchange path: each cell's density gradient, computed band by band from
+  // the band entries (L2-local reads of the field), still on the density
+  // branch
+  if (fast && xch && grads) {
+    if (e == hipSuccess) e = launch_band_gather(g, L, p.exy, p.psi, grad_mode, ds);
+    plan_mark(p, "k_band_gather", ds);
+  }
   // join the density branch
   if (e == hipSuccess && overlap) {
     e = hipEventRecord(p.join, ds);
@@ -453,10 +458,22 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
     if (!grads) {
       // scalars only
     } else if (xch) {
-      if (e == hipSuccess)
-        e = launch_gather_cellsum(g, m, x, y, prob->w, prob->h, p.exy, p.psi, grad_mode,
-                                  lambda, L.xy, gx, gy, s);
-      plan_mark(p, "k_gather_cellsum", s);
+      // g = lambda * density gradient + each cell's sum of pin gradients
+      CellGradArgs ca;
+      ca.g = g;
+      ca.x = x;
+      ca.y = y;
+      ca.w = prob->w;
+      ca.h = prob->h;
+      ca.exy = reinterpret_cast<const float2*>(p.exy);
+      ca.psi = p.psi;
+      ca.epos = L.epos;
+      ca.egrad = L.egrad;
+      ca.scale = lambda;
+      ca.gx = gx;
+      ca.gy = gy;
+      if (e == hipSuccess) e = launch_xch_cellsum(xd, X, L.pin_grad, ca, grad_mode, s);
+      plan_mark(p, "k_xch_cellsum", s);
     } else {
       if (e == hipSuccess)
         e = launch_gather_pins(g, m, x, y, prob->w, prob->h, p.exy, p.psi, grad_mode, lambda,

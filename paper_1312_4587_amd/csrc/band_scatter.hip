@@ -47,6 +47,10 @@ BandLayout band_layout(int n, int m, int num_nets, int num_pins, void* work,
   off = align256(off + sizeof(float4) * (size_t)kMaxBands * m);
   const size_t o_big = off;
   off = align256(off + sizeof(int32_t) * (size_t)m);
+  const size_t o_ep = off;
+  off = align256(off + sizeof(int32_t) * (size_t)m);
+  const size_t o_eg = off;
+  off = align256(off + sizeof(float2) * (size_t)kMaxBands * m);
   const size_t o_bb = off;
   off = align256(off + sizeof(int32_t) * (size_t)L.nblk * L.nb);
   const size_t o_ct = off;
@@ -59,6 +63,8 @@ BandLayout band_layout(int n, int m, int num_nets, int num_pins, void* work,
     L.pin_grad = reinterpret_cast<float2*>(b + o_pg);
     L.entries = reinterpret_cast<float4*>(b + o_en);
     L.big = reinterpret_cast<int32_t*>(b + o_big);
+    L.epos = reinterpret_cast<int32_t*>(b + o_ep);
+    L.egrad = reinterpret_cast<float2*>(b + o_eg);
     L.blk_base = reinterpret_cast<int32_t*>(b + o_bb);
     L.counters = reinterpret_cast<int32_t*>(b + o_ct);
   }
@@ -170,11 +176,19 @@ __global__ void __launch_bounds__(kBandThreads)
       if (i >= L.m) continue;
       const Span sx = cell_span(c.x[j], c.w[j], g.xl, g.inv_bw, g.n);
       const Span sy = cell_span(c.y[j], c.h[j], g.yl, g.inv_bh, g.n);
-      if (sx.i0 > sx.i1 || sy.i0 > sy.i1) continue;
-      const int b0 = sy.i0 / L.rows, b1 = sy.i1 / L.rows;
-      if (b1 - b0 >= kMaxBands) continue;
-      const float4 e = make_float4(sx.lo, sx.hi, sy.lo, sy.hi);
-      for (int b = b0; b <= b1; ++b) L.entries[atomicAdd(&cursor[b], 1)] = e;
+      int first = -1;   // the cell's entry in its first band, if listed
+      if (sx.i0 <= sx.i1 && sy.i0 <= sy.i1) {
+        const int b0 = sy.i0 / L.rows, b1 = sy.i1 / L.rows;
+        if (b1 - b0 < kMaxBands) {
+          const float4 e = make_float4(sx.lo, sx.hi, sy.lo, sy.hi);
+          for (int b = b0; b <= b1; ++b) {
+            const int q = atomicAdd(&cursor[b], 1);
+            L.entries[q] = e;
+            if (b == b0) first = q;
+          }
+        }
+      }
+      L.epos[i] = first;
     }
   }
 }
@@ -239,6 +253,78 @@ __global__ void __launch_bounds__(kAccThreads)
   const size_t o = (size_t)r0 * n;
   for (int k = t; k < cells; k += NTA)
     rho[o + k] = (base ? base[o + k] : 0.0f) + (float)((double)acc[k] * kAccUnit);
+}
+
+// Density gradient of every cell listed in band b with b its first band,
+// from the cell's entry (its edges), into egrad at the entry's position.  A
+// band's cells read the field rows of that band and the next, so the map
+// reads of one block stay within a few tens of KiB (L2-resident), where a
+// per-cell gather in cell order reads the whole map at random.
+constexpr int kGatherSplit = 1;   // blocks per band
+constexpr int NTG = 1024;         // threads of a band-gather block
+template <int MODE>
+__global__ void __launch_bounds__(NTG)
+    k_band_gather(GridF g, BandLayout L, const float2* __restrict__ exy,
+                  const float* __restrict__ psi) {
+  // the band's field rows and the next one (cells of up to two rows whose
+  // first row is in the band read only these) staged in LDS
+  __shared__ float2 rows[5 * kBandMaxN];
+  const int t = threadIdx.x;
+  const int n = g.n, R = L.rows;
+  // XCD k runs a contiguous range of bands, all pieces of a band on one XCD
+  const int r = kGatherSplit > 1 ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
+  const int band = r / kGatherSplit, part = r % kGatherSplit;
+  const int r0 = band * R, nr = min(R + 1, n - r0);
+  if (MODE == FFTPL_GRAD_FIELD) {
+    for (int k = t; k < nr * n; k += NTG) rows[k] = exy[(int64_t)r0 * n + k];
+  }
+  // start of the band: the counts of the earlier bands
+  int start;
+  block_exclusive_scan<NTG>(t < band ? L.counters[t] : 0, &start);   // (synchronises)
+  const int len = L.counters[band], piece = (len + kGatherSplit - 1) / kGatherSplit;
+  const int lo = start + part * piece, end = min(start + len, lo + piece);
+  for (int e0 = lo; e0 < end; e0 += NTG * B) {
+    float4 q[B];
+#pragma unroll
+    for (int j = 0; j < B; ++j) q[j] = L.entries[min(e0 + j * NTG + t, end - 1)];
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      const int e = e0 + j * NTG + t;
+      if (e >= end) continue;
+      const Span sx = span_from_edges(q[j].x, q[j].y, n);
+      const Span sy = span_from_edges(q[j].z, q[j].w, n);
+      if (sy.i0 / R != band) continue;   // listed again below its first band
+      if (MODE == FFTPL_GRAD_FIELD && sy.i1 < r0 + nr) {
+        // the same sum as the per-cell gather, from the staged rows
+        float ax = 0.0f, ay = 0.0f;
+        for (int iy = sy.i0; iy <= sy.i1; ++iy) {
+          const float oy = span_overlap(sy, iy);
+          const float2* row = rows + (iy - r0) * n;
+          for (int ix = sx.i0; ix <= sx.i1; ++ix) {
+            const float ov = span_overlap(sx, ix) * oy;
+            const float2 f = row[ix];
+            ax += ov * f.x;
+            ay += ov * f.y;
+          }
+        }
+        L.egrad[e] = make_float2(ax * -g.inv_bw, ay * -g.inv_bh);
+      } else {
+        L.egrad[e] = density_grad_spans<MODE, true>(g, sx, sy, nullptr, nullptr, exy, psi);
+      }
+    }
+  }
+}
+
+hipError_t launch_band_gather(const GridF& g, const BandLayout& L, const float* exy,
+                              const float* psi, int grad_mode, hipStream_t s) {
+  const float2* e2 = reinterpret_cast<const float2*>(exy);
+  if (grad_mode == FFTPL_GRAD_EXACT)
+    hipLaunchKernelGGL(k_band_gather<FFTPL_GRAD_EXACT>, dim3(L.nb * kGatherSplit), dim3(NTG),
+                       0, s, g, L, e2, psi);
+  else
+    hipLaunchKernelGGL(k_band_gather<FFTPL_GRAD_FIELD>, dim3(L.nb * kGatherSplit), dim3(NTG),
+                       0, s, g, L, e2, psi);
+  return hipGetLastError();
 }
 
 // xy[i] = (x[i], y[i]): the wirelength pass then gathers one float2 per pin.

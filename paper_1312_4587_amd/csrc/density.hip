@@ -145,7 +145,7 @@ hipError_t launch_init_eval(double* out4, int32_t* counters, int ncount, hipStre
 // [psi at right edge - psi at left edge] for edges strictly inside (0, n).
 // ---------------------------------------------------------------------------
 // PINS: 0 density gradient only; 1 plus the sum of the cell's contiguous pin
-// slots (cell_ptr, pin_grad); 2 plus pin_grad[i] (one float2 per cell).
+// slots (cell_ptr, pin_grad).
 constexpr int kGatherThreads = 256;
 
 template <int MODE, bool INTERLEAVED, int PINS>
@@ -159,17 +159,13 @@ __global__ void __launch_bounds__(kGatherThreads)
              float* __restrict__ gy) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < m) {
-    // the cell's own loads (and its pin sum) go out together, before the map
-    // reads that depend on them
+    // the cell's own loads go out together, before the map reads that
+    // depend on them
     const float xi = x[i], yi = y[i], wi = w[i], hi = h[i];
-    const float2 q2 = PINS == 2 ? pin_grad[i] : make_float2(0.0f, 0.0f);
     const float2 d =
         cell_density_grad<MODE, INTERLEAVED>(g, xi, yi, wi, hi, ex, ey, exy, psi);
     float ax = scale * d.x, ay = scale * d.y;
-    if (PINS == 2) {
-      ax += q2.x;
-      ay += q2.y;
-    } else if (PINS == 1) {
+    if (PINS == 1) {
       // the cell's wirelength gradient: its pins' slots are contiguous
       const int k1 = cell_ptr[i + 1];
       for (int k = cell_ptr[i]; k < k1; ++k) {
@@ -227,23 +223,6 @@ hipError_t launch_gather_pins(const GridF& g, int m, const float* x, const float
   } else {
     hipLaunchKernelGGL((k_gather<FFTPL_GRAD_FIELD, true, 1>), grid, block, 0, s, g, m, x,
                        y, w, h, nullptr, nullptr, e2, psi, scale, 0, cell_ptr, pin_grad, gx, gy);
-  }
-  return hipGetLastError();
-}
-
-hipError_t launch_gather_cellsum(const GridF& g, int m, const float* x, const float* y,
-                                 const float* w, const float* h, const float* exy,
-                                 const float* psi, int grad_mode, float scale,
-                                 const float2* gwa, float* gx, float* gy, hipStream_t s) {
-  if (m <= 0) return hipSuccess;
-  dim3 grid((m + kGatherThreads - 1) / kGatherThreads), block(kGatherThreads);
-  const float2* e2 = reinterpret_cast<const float2*>(exy);
-  if (grad_mode == FFTPL_GRAD_EXACT) {
-    hipLaunchKernelGGL((k_gather<FFTPL_GRAD_EXACT, true, 2>), grid, block, 0, s, g, m, x,
-                       y, w, h, nullptr, nullptr, e2, psi, scale, 0, nullptr, gwa, gx, gy);
-  } else {
-    hipLaunchKernelGGL((k_gather<FFTPL_GRAD_FIELD, true, 2>), grid, block, 0, s, g, m, x,
-                       y, w, h, nullptr, nullptr, e2, psi, scale, 0, nullptr, gwa, gx, gy);
   }
   return hipGetLastError();
 }

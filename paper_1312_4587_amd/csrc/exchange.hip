@@ -25,8 +25,10 @@
 //           its own A position of T, again in runs;
 //   cellsum (one block per cell block): streams the cell block's A
 //           range of T and adds every pin's gradient into its cell's
-//           accumulator in LDS (integer fixed point: order-independent);
-//   gather  (one thread per cell): the density gradient plus that sum.
+//           accumulator in LDS (integer fixed point: order-independent),
+//           then writes each cell's gradient: lambda times its density
+//           gradient (computed per band entry on the density branch) plus
+//           that sum.
 //
 // The index (A/B layout) is built once per netlist by xch_build.
 #include <math.h>
@@ -698,7 +700,8 @@ __global__ void __launch_bounds__(NW)
   block_sum_to<false>(acc_hp, &part[nblk + k]);
 }
 
-// gwa[c] = sum of the gradients in T of cell c's pins.  One block per cell
+// The gradient of every cell (CellGradArgs): its density part plus the sum
+// of the gradients in T of its pins.  One block per cell
 // block: the block streams the cell block's A range of T together with the
 // cell-local index lc (both coalesced) and adds each pin into per-cell
 // accumulators in LDS.  The adds are 64-bit integer adds of the gradients in
@@ -710,10 +713,11 @@ __global__ void __launch_bounds__(NW)
 // the largest scale that keeps every pin within a 32-bit conversion; the
 // 64-bit sums then hold any number of pins.  A non-finite pin gradient makes
 // its cell's sum NaN.
+template <int MODE>
 __global__ void __launch_bounds__(kSumThreads)
     k_xch_cellsum(int m, const int32_t* __restrict__ cb_a_ptr, const uint16_t* __restrict__ lc,
                   const float2* __restrict__ T, float scale, double inv_scale,
-                  float2* __restrict__ gwa) {
+                  CellGradArgs a) {
   __shared__ unsigned long long ax[kXchCells], ay[kXchCells];
   __shared__ unsigned char bad[kXchCells];
   const int cb = blockIdx.x, t = threadIdx.x;
@@ -761,26 +765,46 @@ __global__ void __launch_bounds__(kSumThreads)
     }
   }
   __syncthreads();
+  // each cell's gradient: its density part from its first-band entry (one
+  // 8-byte read; all of a thread's reads issued together) or, for a cell
+  // without one, from the maps; plus its wirelength sum
+  constexpr int PC = kXchCells / kSumThreads;
   const int c0 = cb * kXchCells;
-  for (int c = t; c < kXchCells; c += kSumThreads) {
-    if (c0 + c >= m) break;
-    gwa[c0 + c] = bad[c] ? make_float2(__builtin_nanf(""), __builtin_nanf(""))
-                         : make_float2((float)((double)(long long)ax[c] * inv_scale),
-                                       (float)((double)(long long)ay[c] * inv_scale));
+  int ep[PC];
+  float2 d[PC];
+#pragma unroll
+  for (int k = 0; k < PC; ++k) ep[k] = a.epos[min(c0 + t + k * kSumThreads, m - 1)];
+#pragma unroll
+  for (int k = 0; k < PC; ++k) d[k] = a.egrad[max(ep[k], 0)];
+#pragma unroll
+  for (int k = 0; k < PC; ++k) {
+    const int c = t + k * kSumThreads, ci = c0 + c;
+    if (ci >= m) break;
+    if (ep[k] < 0)
+      d[k] = cell_density_grad<MODE, true>(a.g, a.x[ci], a.y[ci], a.w[ci], a.h[ci], nullptr,
+                                           nullptr, a.exy, a.psi);
+    const float sx = bad[c] ? __builtin_nanf("") : (float)((double)(long long)ax[c] * inv_scale);
+    const float sy = bad[c] ? __builtin_nanf("") : (float)((double)(long long)ay[c] * inv_scale);
+    a.gx[ci] = a.scale * d[k].x + sx;
+    a.gy[ci] = a.scale * d[k].y + sy;
   }
 }
 
 }  // namespace
 
 hipError_t launch_xch_cellsum(const XchDims& d, const XchIndex& X, const float2* T,
-                              float2* gwa, hipStream_t s) {
+                              const CellGradArgs& a, int grad_mode, hipStream_t s) {
   if (d.m <= 0) return hipSuccess;
   // fixed-point scale 2^S: the largest S <= 26 with bound * 2^S <= 2^30
   const double bound = 1.15 + log((double)(d.max_degree > 2 ? d.max_degree : 2));
   int S = 26;
   while (S > 0 && bound * ldexp(1.0, S) > ldexp(1.0, 30)) --S;
-  hipLaunchKernelGGL(k_xch_cellsum, dim3(d.ncb), dim3(kSumThreads), 0, s, d.m, X.cb_a_ptr, X.lc,
-                     T, (float)ldexp(1.0, S), ldexp(1.0, -S), gwa);
+  if (grad_mode == FFTPL_GRAD_EXACT)
+    hipLaunchKernelGGL(k_xch_cellsum<FFTPL_GRAD_EXACT>, dim3(d.ncb), dim3(kSumThreads), 0, s,
+                       d.m, X.cb_a_ptr, X.lc, T, (float)ldexp(1.0, S), ldexp(1.0, -S), a);
+  else
+    hipLaunchKernelGGL(k_xch_cellsum<FFTPL_GRAD_FIELD>, dim3(d.ncb), dim3(kSumThreads), 0, s,
+                       d.m, X.cb_a_ptr, X.lc, T, (float)ldexp(1.0, S), ldexp(1.0, -S), a);
   return hipGetLastError();
 }
 

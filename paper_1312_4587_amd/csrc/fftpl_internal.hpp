@@ -69,15 +69,16 @@ __device__ __forceinline__ float span_overlap(const Span& s, int j) {
 // bin it leaves to the bin it enters); with INTERLEAVED and exy set, exy holds
 // the difference maps (Dx, Dy) of the solve's difference mode and psi is read
 // only for cells with one edge outside the region.
+// density_grad_spans takes the cell's spans (from its geometry, or from the
+// edges a band entry stores: the same Span either way).
 template <int MODE, bool INTERLEAVED>
-__device__ __forceinline__ float2 cell_density_grad(const GridF& g, float x, float y, float w,
-                                                    float h, const float* __restrict__ ex,
-                                                    const float* __restrict__ ey,
-                                                    const float2* __restrict__ exy,
-                                                    const float* __restrict__ psi) {
+__device__ __forceinline__ float2 density_grad_spans(const GridF& g, const Span& sx,
+                                                     const Span& sy,
+                                                     const float* __restrict__ ex,
+                                                     const float* __restrict__ ey,
+                                                     const float2* __restrict__ exy,
+                                                     const float* __restrict__ psi) {
   const int n = g.n;
-  const Span sx = cell_span(x, w, g.xl, g.inv_bw, n);
-  const Span sy = cell_span(y, h, g.yl, g.inv_bh, n);
   float ax = 0.0f, ay = 0.0f;
   if (MODE == FFTPL_GRAD_FIELD) {
     for (int iy = sy.i0; iy <= sy.i1; ++iy) {
@@ -159,6 +160,17 @@ __device__ __forceinline__ float2 cell_density_grad(const GridF& g, float x, flo
     ay *= 2.0f * g.inv_bh;
   }
   return make_float2(ax, ay);
+}
+
+template <int MODE, bool INTERLEAVED>
+__device__ __forceinline__ float2 cell_density_grad(const GridF& g, float x, float y, float w,
+                                                    float h, const float* __restrict__ ex,
+                                                    const float* __restrict__ ey,
+                                                    const float2* __restrict__ exy,
+                                                    const float* __restrict__ psi) {
+  const Span sx = cell_span(x, w, g.xl, g.inv_bw, g.n);
+  const Span sy = cell_span(y, h, g.yl, g.inv_bh, g.n);
+  return density_grad_spans<MODE, INTERLEAVED>(g, sx, sy, ex, ey, exy, psi);
 }
 
 // ---- weighted-average wirelength, Eq. (3), per net and axis ----
@@ -519,6 +531,9 @@ struct BandLayout {
   float2* xy = nullptr;          // [m] interleaved positions
   float2* pin_grad = nullptr;    // [P] per-pin WA gradients, cell-major slots
   float4* entries = nullptr;     // [kMaxBands*m] band entries: cell edges in bins
+  int32_t* epos = nullptr;       // [m] each cell's entry in its first band, -1 if none
+  float2* egrad = nullptr;       // [kMaxBands*m] density gradient of the cell whose
+                                 // first-band entry this is (band gather)
   int32_t* big = nullptr;        // [m] cells spanning more than kMaxBands bands
   int32_t* blk_base = nullptr;   // [nb][nblk] per band: each block's count, then its
                                  // offset inside the band
@@ -529,6 +544,10 @@ struct BandLayout {
 BandLayout band_layout(int n, int m, int num_nets, int num_pins, void* work,
                        size_t* bytes_out);
 
+// egrad[entry] = density gradient (before lambda) of each cell at its
+// first-band entry (after launch_band_scatter and the solve).
+hipError_t launch_band_gather(const GridF& g, const BandLayout& L, const float* exy,
+                              const float* psi, int grad_mode, hipStream_t s);
 hipError_t launch_band_scatter(const GridF& g, const BandLayout& L, const float* x,
                                const float* y, const float* w, const float* h,
                                const float* base, float* rho, hipStream_t s,
@@ -605,14 +624,23 @@ hipError_t launch_xch_wa(const XchDims& d, const XchIndex& X, const int32_t* net
                          const float* pin_dx, const float* pin_dy, float gamma, float2* T,
                          double* wa_part, hipStream_t s);
 // gwa[c] = sum over cell c's pins of T[qa[j]] (after launch_xch_wa).
+// The per-cell part of the gradient after the wirelength: g = scale * the
+// density gradient (egrad at the cell's first-band entry, or computed from the
+// maps for a cell without one) + the cell's wirelength sum.
+struct CellGradArgs {
+  GridF g;
+  const float *x = nullptr, *y = nullptr, *w = nullptr, *h = nullptr;
+  const float2* exy = nullptr;
+  const float* psi = nullptr;
+  const int32_t* epos = nullptr;
+  const float2* egrad = nullptr;
+  float scale = 0.0f;
+  float *gx = nullptr, *gy = nullptr;
+};
+// g (CellGradArgs) for every cell, the wirelength part being the sum over
+// the cell's pins of their gradients in T (after launch_xch_wa).
 hipError_t launch_xch_cellsum(const XchDims& d, const XchIndex& X, const float2* T,
-                              float2* gwa, hipStream_t s);
-// g = scale * density gradient + gwa[c] (one thread per cell).
-hipError_t launch_gather_cellsum(const GridF& g, int m, const float* x, const float* y,
-                                 const float* w, const float* h, const float* exy,
-                                 const float* psi, int grad_mode, float scale,
-                                 const float2* gwa, float* gx, float* gy, hipStream_t s);
-
+                              const CellGradArgs& a, int grad_mode, hipStream_t s);
 // ---- placement iteration (driver.hip) --------------------------------------
 size_t step_stats_work_doubles();
 hipError_t launch_step_stats(int m, const float* ux, const float* uy, const float* upx,
