@@ -415,10 +415,12 @@ def test_netlist_index_is_a_cell_major_permutation(F):
     assert np.all(ps >= cp[c]) and np.all(ps < cp[c + 1])
 
 
+@pytest.mark.parametrize("mode", ["field", "exact"])
 @pytest.mark.parametrize("n", [16, 64, 512, 1024])
-def test_banded_scatter_with_tall_and_outside_cells(F, n):
-    # cells spanning many bands take the short list every band block walks;
-    # cells outside the region and ragged sizes mixed in
+def test_banded_scatter_with_tall_and_outside_cells(F, n, mode):
+    # cells spanning many bands take the short list every band block walks
+    # (and have no band entry, so their density gradient is taken from the
+    # maps directly); cells outside the region and ragged sizes mixed in
     rng = np.random.default_rng(n)
     m = 3000
     side = 100.0
@@ -433,10 +435,10 @@ def test_banded_scatter_with_tall_and_outside_cells(F, n):
     nets = [[(int(a), 0.0, 0.0), (int(b), 0.1, -0.1)] for a, b in rng.integers(0, m, (500, 2)) if a != b]
     inst = hand_instance(cells, n=n, bin_size=side / n, nets=nets)
     inst = with_macros(inst, [[50.0, 50.0, 10.0, 30.0]])
-    say("band scatter", n)
-    got = _run_eval(F, inst, 1.0, "field")
-    ref = oracle.evaluate(inst, lam=1.0, grad_mode="field")
-    _check_eval(inst, got, ref, 1.0, "field")
+    say("band scatter", n, mode)
+    got = _run_eval(F, inst, 1.0, mode)
+    ref = oracle.evaluate(inst, lam=1.0, grad_mode=mode)
+    _check_eval(inst, got, ref, 1.0, mode)
 
 
 # ---------------------------------------------------------------------------
