@@ -379,9 +379,8 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
       e = hipEventRecord(p.fork, s);
       if (e == hipSuccess) e = hipStreamWaitEvent(ds, p.fork, 0);
     }
-    // density branch: 1. zero scalars and band counters, 2. banded scatter
-    if (e == hipSuccess) e = launch_init_eval(out4, L.counters, L.nb + 1, ds);
-    plan_mark(p, "k_init_eval", ds);
+    // density branch: banded scatter (its counters and the scalars are all
+    // written, not accumulated, so nothing needs zeroing first)
     if (e == hipSuccess)
       e = launch_band_scatter(g, L, x, y, prob->w, prob->h, prob->base, p.rho, ds, &p);
     // wirelength branch

@@ -2,7 +2,8 @@
 // global memory, which retire at roughly 20 G/s on the whole chip whatever
 // their scope:
 //   count: each block of kCellsPerBlock cells histograms the bands its
-//          cells touch in LDS and stores the histogram (band-major);
+//          cells touch in LDS (plus one slot for cells too tall to list
+//          per band) and stores the histogram (band-major);
 //   scan:  one block per band turns its row of block counts into each
 //          block's offset inside the band and the band's total (no global
 //          atomics, whose contention on 256 counters would serialise);
@@ -52,7 +53,7 @@ BandLayout band_layout(int n, int m, int num_nets, int num_pins, void* work,
   const size_t o_eg = off;
   off = align256(off + sizeof(float2) * (size_t)kMaxBands * m);
   const size_t o_bb = off;
-  off = align256(off + sizeof(int32_t) * (size_t)L.nblk * L.nb);
+  off = align256(off + sizeof(int32_t) * (size_t)L.nblk * (L.nb + 1));
   const size_t o_ct = off;
   off = align256(off + sizeof(int32_t) * (size_t)(L.nb + 1));
   if (bytes_out) *bytes_out = off;
@@ -103,9 +104,9 @@ __global__ void __launch_bounds__(kBandThreads)
     k_band_count(GridF g, BandLayout L, const float* __restrict__ x,
                  const float* __restrict__ y, const float* __restrict__ w,
                  const float* __restrict__ h) {
-  __shared__ int hist[256];
+  __shared__ int hist[257];   // the bands, then the cells too tall to list per band
   const int t = threadIdx.x;
-  for (int b = t; b < L.nb; b += NT) hist[b] = 0;
+  for (int b = t; b <= L.nb; b += NT) hist[b] = 0;
   __syncthreads();
   const int c0 = blockIdx.x * kCellsPerBlock;
   for (int base = c0; base < c0 + kCellsPerBlock && base < L.m; base += NT * B) {
@@ -120,18 +121,18 @@ __global__ void __launch_bounds__(kBandThreads)
       if (sx.i0 > sx.i1 || sy.i0 > sy.i1) continue;
       const int b0 = sy.i0 / L.rows, b1 = sy.i1 / L.rows;
       if (b1 - b0 >= kMaxBands) {
-        L.big[atomicAdd(&L.counters[L.nb], 1)] = i;
+        atomicAdd(&hist[L.nb], 1);
         continue;
       }
       for (int b = b0; b <= b1; ++b) atomicAdd(&hist[b], 1);
     }
   }
   __syncthreads();
-  for (int b = t; b < L.nb; b += NT) L.blk_base[(size_t)b * L.nblk + blockIdx.x] = hist[b];
+  for (int b = t; b <= L.nb; b += NT) L.blk_base[(size_t)b * L.nblk + blockIdx.x] = hist[b];
 }
 
-// Band b: blk_base[b][k] = sum of the counts of blocks < k, counters[b] = the
-// band's total.
+// Band b (b = nb: the tall cells' list): blk_base[b][k] = sum of the counts
+// of blocks < k, counters[b] = the band's total.
 constexpr int kScanThreads = 256;
 __global__ void __launch_bounds__(kScanThreads) k_band_scan(BandLayout L) {
   int32_t* row = L.blk_base + (size_t)blockIdx.x * L.nblk;
@@ -160,11 +161,13 @@ __global__ void __launch_bounds__(kBandThreads)
     k_band_place(GridF g, BandLayout L, const float* __restrict__ x,
                  const float* __restrict__ y, const float* __restrict__ w,
                  const float* __restrict__ h) {
-  __shared__ int cursor[256];
+  __shared__ int cursor[257];
   const int t = threadIdx.x;
   int total;
   const int ex = block_exclusive_scan<NT>(t < L.nb ? L.counters[t] : 0, &total);
   if (t < L.nb) cursor[t] = ex + L.blk_base[(size_t)t * L.nblk + blockIdx.x];
+  // the tall cells' list has its own offsets, from 0
+  if (t == L.nb) cursor[t] = L.blk_base[(size_t)t * L.nblk + blockIdx.x];
   __syncthreads();
   const int c0 = blockIdx.x * kCellsPerBlock;
   for (int base = c0; base < c0 + kCellsPerBlock && base < L.m; base += NT * B) {
@@ -186,6 +189,8 @@ __global__ void __launch_bounds__(kBandThreads)
             L.entries[q] = e;
             if (b == b0) first = q;
           }
+        } else {
+          L.big[atomicAdd(&cursor[L.nb], 1)] = i;
         }
       }
       L.epos[i] = first;
@@ -352,12 +357,16 @@ hipError_t launch_band_scatter(const GridF& g, const BandLayout& L, const float*
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (tp) plan_mark(*tp, "k_band_count", s);
-    hipLaunchKernelGGL(k_band_scan, dim3(L.nb), dim3(kScanThreads), 0, s, L);
+    hipLaunchKernelGGL(k_band_scan, dim3(L.nb + 1), dim3(kScanThreads), 0, s, L);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (tp) plan_mark(*tp, "k_band_scan", s);
     hipLaunchKernelGGL(k_band_place, dim3(L.nblk), dim3(NT), 0, s, g, L, x, y, w, h);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (tp) plan_mark(*tp, "k_band_place", s);
+  } else {
+    // no cells: empty bands and no tall cells
+    hipError_t e = launch_zero_i32(L.counters, L.nb + 1, s);
+    if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_band_accum, dim3(L.nb), dim3(NTA), 0, s, g, L, x, y, w, h, base, rho);
   hipError_t e = hipGetLastError();
