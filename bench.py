@@ -37,10 +37,6 @@ PMC_TRAFFIC = {
         "5a03760b7ff584b53161d08316d12b4a1a738250", 187983.6, 116210.9),
     "k_xch_cellsum": (("exchange.hip", "fftpl_internal.hpp"),
         "5a03760b7ff584b53161d08316d12b4a1a738250", 60559.2, 16406.2),
-    "k_band_count": (("band_scatter.hip", "fftpl_internal.hpp"),
-        "7ac4d6b1345cab2fc65030a16b54d96fc0d06f06", 16465.0, 4097.0),
-    "k_band_scan": (("band_scatter.hip", "fftpl_internal.hpp"),
-        "7ac4d6b1345cab2fc65030a16b54d96fc0d06f06", 289.1, 528.0),
     "k_band_place": (("band_scatter.hip", "fftpl_internal.hpp"),
         "7ac4d6b1345cab2fc65030a16b54d96fc0d06f06", 18512.1, 44582.2),
     "k_band_accum": (("band_scatter.hip", "fftpl_internal.hpp"),
@@ -207,11 +203,11 @@ def kernel_bytes(inst, nent):
         # pins (cell, dx, dy) in, per-pin gradient out, net_ptr; positions once
         "k_wa_slots_small": 12 * p_small + 8 * p_small + 4 * (E + 1) + 8 * m,
         "k_wa_slots_big": 12 * p_big + 8 * p_big + 4 * (E + 1),
-        "k_band_count": 16 * m,
-        # per band: the block counts in, offsets out (4096 cells per block)
-        "k_band_scan": 8 * (-(-inst.n // (-(-inst.n // 256)))) * (-(-m // 4096)),
         "k_interleave": 8 * m + 8 * m,
-        "k_band_place": 16 * m + 16 * nent + 4 * m,   # + each cell's first entry
+        # cells in; entries, each cell's first entry and the per-(band, block)
+        # slice offsets and counts out (4096 cells per block)
+        "k_band_place": 16 * m + 16 * nent + 4 * m
+        + 8 * (-(-inst.n // (-(-inst.n // 256))) + 1) * (-(-m // 4096)),
         "k_band_accum": 16 * nent + 4 * n2 + 4 * n2,
         "k_rows_dct2": 4 * n2 + 4 * n2 + 8 * n2,        # rho, base+cap in; bT out
         "k_cols_solve": 4 * n2 + 8 * n2,                # bT in; P, Q out

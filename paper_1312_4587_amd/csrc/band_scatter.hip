@@ -1,22 +1,24 @@
 // Banded density scatter (Eq. (2), Section III-B) without float atomics in
 // global memory, which retire at roughly 20 G/s on the whole chip whatever
 // their scope:
-//   count: each block of kCellsPerBlock cells histograms the bands its
-//          cells touch in LDS (plus one slot for cells too tall to list
-//          per band) and stores the histogram (band-major);
-//   scan:  one block per band turns its row of block counts into each
-//          block's offset inside the band and the band's total (no global
-//          atomics, whose contention on 256 counters would serialise);
-//   place: the counting blocks write each cell's edges (bin units) into
-//          every band it touches, at LDS-atomic ranks inside their slice;
-//   accum: one block per band adds its entries into an LDS copy of its rows
-//          and writes rho = base + rows once.  The LDS adds are 64-bit
-//          integer adds of the overlaps in fixed point (every overlap lies in
-//          [0, 1], units of 2^-31): they retire many times faster than LDS
-//          float atomics, and the sums do not depend on the order of the
-//          entries, so rho is the same on every run.
-// Every thread issues the loads of kCellBatch cells (or entries) before it
-// uses any of them, so each block keeps many misses in flight.
+//   place: each block of kCellsPerBlock cells histograms the bands its cells
+//          touch in LDS (plus one slot for cells too tall to list per band),
+//          scans the histogram, and writes each cell's edges (bin units)
+//          into every band it touches, in a region of its own sliced by band
+//          (LDS-atomic ranks inside each slice); per band, each block's slice
+//          offset and count go out band-major;
+//   accum: one block per band walks the band's slices of every region and
+//          adds its entries into an LDS copy of its rows, then writes
+//          rho = base + rows once.  The LDS adds are 64-bit integer adds of
+//          the overlaps in fixed point (every overlap lies in [0, 1], units
+//          of 2^-31): they retire many times faster than LDS float atomics,
+//          and the sums do not depend on the order of the entries, so rho is
+//          the same on every run;
+//   gather (after the solve): one block per band walks the same slices and
+//          computes the density gradient of every cell whose first band it
+//          is, from the band's field rows staged in LDS.
+// Every thread issues the loads of its cells (or entries) before it uses any
+// of them, so each block keeps many misses in flight.
 #include "fftpl_internal.hpp"
 
 namespace fftpl {
@@ -44,18 +46,19 @@ BandLayout band_layout(int n, int m, int num_nets, int num_pins, void* work,
   off = align256(off + sizeof(float2) * (size_t)m);
   const size_t o_pg = off;
   off = align256(off + sizeof(float2) * (size_t)num_pins);
+  const size_t nreg = (size_t)L.nblk * kBandRegion;   // entries of all regions
   const size_t o_en = off;
-  off = align256(off + sizeof(float4) * (size_t)kMaxBands * m);
+  off = align256(off + sizeof(float4) * nreg);
   const size_t o_big = off;
-  off = align256(off + sizeof(int32_t) * (size_t)m);
+  off = align256(off + sizeof(int32_t) * (size_t)L.nblk * kCellsPerBlock);
   const size_t o_ep = off;
   off = align256(off + sizeof(int32_t) * (size_t)m);
   const size_t o_eg = off;
-  off = align256(off + sizeof(float2) * (size_t)kMaxBands * m);
-  const size_t o_bb = off;
+  off = align256(off + sizeof(float2) * nreg);
+  const size_t o_bo = off;
   off = align256(off + sizeof(int32_t) * (size_t)L.nblk * (L.nb + 1));
-  const size_t o_ct = off;
-  off = align256(off + sizeof(int32_t) * (size_t)(L.nb + 1));
+  const size_t o_bc = off;
+  off = align256(off + sizeof(int32_t) * (size_t)L.nblk * (L.nb + 1));
   if (bytes_out) *bytes_out = off;
   if (work) {
     char* b = static_cast<char*>(work);
@@ -66,8 +69,8 @@ BandLayout band_layout(int n, int m, int num_nets, int num_pins, void* work,
     L.big = reinterpret_cast<int32_t*>(b + o_big);
     L.epos = reinterpret_cast<int32_t*>(b + o_ep);
     L.egrad = reinterpret_cast<float2*>(b + o_eg);
-    L.blk_base = reinterpret_cast<int32_t*>(b + o_bb);
-    L.counters = reinterpret_cast<int32_t*>(b + o_ct);
+    L.blk_off = reinterpret_cast<int32_t*>(b + o_bo);
+    L.blk_cnt = reinterpret_cast<int32_t*>(b + o_bc);
   }
   return L;
 }
@@ -100,101 +103,110 @@ __device__ __forceinline__ void load_batch(CellBatch& c, int base, int m,
 
 }  // namespace
 
-__global__ void __launch_bounds__(kBandThreads)
-    k_band_count(GridF g, BandLayout L, const float* __restrict__ x,
-                 const float* __restrict__ y, const float* __restrict__ w,
-                 const float* __restrict__ h) {
-  __shared__ int hist[257];   // the bands, then the cells too tall to list per band
+// The entries of band `band` (band = nb: the tall cells) lie in one slice per
+// region: slice k holds blk_cnt[band][k] entries from index
+// k * stride + blk_off[band][k].  A block of NTB threads walks them in chunks
+// of NTB slices: the chunk's counts are scanned in LDS and each thread maps
+// its share of the chunk's entries to (slice, rank) by a binary search over
+// the scan, then calls f(index) for KB entries at a time (their indices all
+// known before any of them is used, so the caller can issue their loads
+// together).  Every thread of the block must call it.
+template <int NTB, int KB, typename F>
+__device__ __forceinline__ void walk_band(const BandLayout& L, int band, int64_t stride,
+                                          int* pre, int64_t* start, F f) {
   const int t = threadIdx.x;
-  for (int b = t; b <= L.nb; b += NT) hist[b] = 0;
-  __syncthreads();
-  const int c0 = blockIdx.x * kCellsPerBlock;
-  for (int base = c0; base < c0 + kCellsPerBlock && base < L.m; base += NT * B) {
-    CellBatch c;
-    load_batch(c, base, L.m, x, y, w, h);
+  for (int k0 = 0; k0 < L.nblk; k0 += NTB) {
+    const int k = k0 + t;
+    const int c = k < L.nblk ? L.blk_cnt[(size_t)band * L.nblk + k] : 0;
+    const int o = k < L.nblk ? L.blk_off[(size_t)band * L.nblk + k] : 0;
+    int tot;
+    const int ex = block_exclusive_scan<NTB>(c, &tot);
+    pre[t] = ex;
+    start[t] = (int64_t)k * stride + o;
+    __syncthreads();
+    for (int v0 = 0; v0 < tot; v0 += NTB * KB) {
+      int64_t idx[KB];
 #pragma unroll
-    for (int j = 0; j < B; ++j) {
-      const int i = base + j * NT + t;
-      if (i >= L.m) continue;
-      const Span sx = cell_span(c.x[j], c.w[j], g.xl, g.inv_bw, g.n);
-      const Span sy = cell_span(c.y[j], c.h[j], g.yl, g.inv_bh, g.n);
-      if (sx.i0 > sx.i1 || sy.i0 > sy.i1) continue;
-      const int b0 = sy.i0 / L.rows, b1 = sy.i1 / L.rows;
-      if (b1 - b0 >= kMaxBands) {
-        atomicAdd(&hist[L.nb], 1);
-        continue;
+      for (int j = 0; j < KB; ++j) {
+        const int v = v0 + j * NTB + t;
+        idx[j] = -1;
+        if (v < tot) {
+          int lo = 0, hi = NTB;   // largest s with pre[s] <= v: its slice holds v
+          while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (pre[mid] <= v)
+              lo = mid;
+            else
+              hi = mid;
+          }
+          idx[j] = start[lo] + (v - pre[lo]);
+        }
       }
-      for (int b = b0; b <= b1; ++b) atomicAdd(&hist[b], 1);
+      f(idx);
     }
+    __syncthreads();   // pre / start are rewritten by the next chunk
   }
-  __syncthreads();
-  for (int b = t; b <= L.nb; b += NT) L.blk_base[(size_t)b * L.nblk + blockIdx.x] = hist[b];
-}
-
-// Band b (b = nb: the tall cells' list): blk_base[b][k] = sum of the counts
-// of blocks < k, counters[b] = the band's total.
-constexpr int kScanThreads = 256;
-__global__ void __launch_bounds__(kScanThreads) k_band_scan(BandLayout L) {
-  int32_t* row = L.blk_base + (size_t)blockIdx.x * L.nblk;
-  int carry = 0;
-  for (int k0 = 0; k0 < L.nblk; k0 += 4 * kScanThreads) {
-    int v[4], s = 0;
-    const int base = k0 + 4 * (int)threadIdx.x;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      v[j] = base + j < L.nblk ? row[base + j] : 0;
-      s += v[j];
-    }
-    int total;
-    int run = carry + block_exclusive_scan<kScanThreads>(s, &total);
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      if (base + j < L.nblk) row[base + j] = run;
-      run += v[j];
-    }
-    carry += total;
-  }
-  if (threadIdx.x == 0) L.counters[blockIdx.x] = carry;
 }
 
 __global__ void __launch_bounds__(kBandThreads)
     k_band_place(GridF g, BandLayout L, const float* __restrict__ x,
                  const float* __restrict__ y, const float* __restrict__ w,
                  const float* __restrict__ h) {
-  __shared__ int cursor[257];
-  const int t = threadIdx.x;
-  int total;
-  const int ex = block_exclusive_scan<NT>(t < L.nb ? L.counters[t] : 0, &total);
-  if (t < L.nb) cursor[t] = ex + L.blk_base[(size_t)t * L.nblk + blockIdx.x];
-  // the tall cells' list has its own offsets, from 0
-  if (t == L.nb) cursor[t] = L.blk_base[(size_t)t * L.nblk + blockIdx.x];
+  __shared__ int hist[257], cur[257];   // the bands, then the tall cells
+  const int t = threadIdx.x, k = blockIdx.x;
+  for (int b = t; b <= L.nb; b += NT) hist[b] = 0;
   __syncthreads();
-  const int c0 = blockIdx.x * kCellsPerBlock;
-  for (int base = c0; base < c0 + kCellsPerBlock && base < L.m; base += NT * B) {
-    CellBatch c;
-    load_batch(c, base, L.m, x, y, w, h);
+  const int c0 = k * kCellsPerBlock;   // one batch of B cells per thread
+  CellBatch c;
+  load_batch(c, c0, L.m, x, y, w, h);
+  float4 e[B];
+  int b0[B], nbd[B];   // first band, bands listed (0: none, -1: tall)
 #pragma unroll
-    for (int j = 0; j < B; ++j) {
-      const int i = base + j * NT + t;
-      if (i >= L.m) continue;
-      const Span sx = cell_span(c.x[j], c.w[j], g.xl, g.inv_bw, g.n);
-      const Span sy = cell_span(c.y[j], c.h[j], g.yl, g.inv_bh, g.n);
-      int first = -1;   // the cell's entry in its first band, if listed
-      if (sx.i0 <= sx.i1 && sy.i0 <= sy.i1) {
-        const int b0 = sy.i0 / L.rows, b1 = sy.i1 / L.rows;
-        if (b1 - b0 < kMaxBands) {
-          const float4 e = make_float4(sx.lo, sx.hi, sy.lo, sy.hi);
-          for (int b = b0; b <= b1; ++b) {
-            const int q = atomicAdd(&cursor[b], 1);
-            L.entries[q] = e;
-            if (b == b0) first = q;
-          }
-        } else {
-          L.big[atomicAdd(&cursor[L.nb], 1)] = i;
-        }
-      }
-      L.epos[i] = first;
+  for (int j = 0; j < B; ++j) {
+    const int i = c0 + j * NT + t;
+    nbd[j] = 0;
+    b0[j] = 0;
+    if (i >= L.m) continue;
+    const Span sx = cell_span(c.x[j], c.w[j], g.xl, g.inv_bw, g.n);
+    const Span sy = cell_span(c.y[j], c.h[j], g.yl, g.inv_bh, g.n);
+    if (sx.i0 > sx.i1 || sy.i0 > sy.i1) continue;
+    b0[j] = sy.i0 / L.rows;
+    const int b1 = sy.i1 / L.rows;
+    e[j] = make_float4(sx.lo, sx.hi, sy.lo, sy.hi);
+    if (b1 - b0[j] >= kMaxBands) {
+      nbd[j] = -1;
+      atomicAdd(&hist[L.nb], 1);
+    } else {
+      nbd[j] = b1 - b0[j] + 1;
+      for (int b = b0[j]; b <= b1; ++b) atomicAdd(&hist[b], 1);
     }
+  }
+  __syncthreads();
+  int tot;
+  const int ex = block_exclusive_scan<NT>(t < L.nb ? hist[t] : 0, &tot);
+  if (t <= L.nb) {
+    const int off = t < L.nb ? ex : 0;   // the tall cells have a list of their own
+    L.blk_off[(size_t)t * L.nblk + k] = off;
+    L.blk_cnt[(size_t)t * L.nblk + k] = hist[t];
+    cur[t] = off;
+  }
+  __syncthreads();
+  const int64_t rbase = (int64_t)k * kBandRegion;
+#pragma unroll
+  for (int j = 0; j < B; ++j) {
+    const int i = c0 + j * NT + t;
+    if (i >= L.m) continue;
+    int first = -1;   // the cell's entry in its first band, if listed
+    if (nbd[j] > 0) {
+      for (int b = b0[j]; b < b0[j] + nbd[j]; ++b) {
+        const int q = atomicAdd(&cur[b], 1);
+        L.entries[rbase + q] = e[j];
+        if (b == b0[j]) first = (int)(rbase + q);
+      }
+    } else if (nbd[j] < 0) {
+      L.big[(int64_t)k * kCellsPerBlock + atomicAdd(&cur[L.nb], 1)] = i;
+    }
+    L.epos[i] = first;
   }
 }
 
@@ -211,24 +223,20 @@ __global__ void __launch_bounds__(kAccThreads)
                  const float* __restrict__ h, const float* __restrict__ base,
                  float* __restrict__ rho) {
   __shared__ unsigned long long acc[kBandMaxN * 4];   // rows * n <= 4096 bins
+  __shared__ int pre[NTA];
+  __shared__ int64_t start[NTA];
   const int t = threadIdx.x;
   const int n = g.n, R = L.rows, band = blockIdx.x, r0 = band * R;
   const int cells = min(R, n - r0) * n;
   for (int k = t; k < cells; k += NTA) acc[k] = 0ull;
-  int start;
-  block_exclusive_scan<NTA>(t < band ? L.counters[t] : 0, &start);   // earlier bands
-  const int end = start + L.counters[band];
   __syncthreads();
-  for (int e0 = start; e0 < end; e0 += NTA * B) {
+  walk_band<NTA, B>(L, band, kBandRegion, pre, start, [&](const int64_t (&idx)[B]) {
     float4 q[B];
 #pragma unroll
-    for (int j = 0; j < B; ++j) {
-      const int e = e0 + j * NTA + t;
-      q[j] = L.entries[min(e, end - 1)];   // unconditional: the batch is in flight at once
-    }
+    for (int j = 0; j < B; ++j) q[j] = L.entries[idx[j] >= 0 ? idx[j] : 0];
 #pragma unroll
     for (int j = 0; j < B; ++j) {
-      if (e0 + j * NTA + t >= end) continue;
+      if (idx[j] < 0) continue;
       const Span sx = span_from_edges(q[j].x, q[j].y, n);
       const Span sy = span_from_edges(q[j].z, q[j].w, n);
       const int ya = max(sy.i0, r0), yb = min(sy.i1, r0 + R - 1);
@@ -238,22 +246,21 @@ __global__ void __launch_bounds__(kAccThreads)
         for (int ix = sx.i0; ix <= sx.i1; ++ix) add_fixed(&row[ix], span_overlap(sx, ix) * oy);
       }
     }
-  }
-  // cells too tall to be listed per band: every band block adds its rows of them
-  const int nbig = L.counters[L.nb];
-  for (int j = 0; j < nbig; ++j) {
-    const int i = L.big[j];
+  });
+  // cells too tall to be listed per band: every band block adds its rows of
+  // them, one thread per cell
+  walk_band<NTA, 1>(L, L.nb, kCellsPerBlock, pre, start, [&](const int64_t (&idx)[1]) {
+    if (idx[0] < 0) return;
+    const int i = L.big[idx[0]];
     const Span sx = cell_span(x[i], w[i], g.xl, g.inv_bw, n);
     const Span sy = cell_span(y[i], h[i], g.yl, g.inv_bh, n);
     const int ya = max(sy.i0, r0), yb = min(sy.i1, r0 + R - 1);
-    if (ya > yb) continue;
-    const int nx = sx.i1 - sx.i0 + 1;
-    const int tot = nx * (yb - ya + 1);
-    for (int k = t; k < tot; k += NTA) {
-      const int ix = sx.i0 + k % nx, iy = ya + k / nx;
-      add_fixed(&acc[(iy - r0) * n + ix], span_overlap(sx, ix) * span_overlap(sy, iy));
+    for (int iy = ya; iy <= yb; ++iy) {
+      const float oy = span_overlap(sy, iy);
+      for (int ix = sx.i0; ix <= sx.i1; ++ix)
+        add_fixed(&acc[(iy - r0) * n + ix], span_overlap(sx, ix) * oy);
     }
-  }
+  });
   __syncthreads();
   const size_t o = (size_t)r0 * n;
   for (int k = t; k < cells; k += NTA)
@@ -263,10 +270,9 @@ __global__ void __launch_bounds__(kAccThreads)
 // Density gradient of every cell listed in band b with b its first band,
 // from the cell's entry (its edges), into egrad at the entry's position.  A
 // band's cells read the field rows of that band and the next, so the map
-// reads of one block stay within a few tens of KiB (L2-resident), where a
+// reads of one block stay within a few tens of KiB (staged in LDS), where a
 // per-cell gather in cell order reads the whole map at random.
-constexpr int kGatherSplit = 1;   // blocks per band
-constexpr int NTG = 1024;         // threads of a band-gather block
+constexpr int NTG = 1024;   // threads of a band-gather block
 template <int MODE>
 __global__ void __launch_bounds__(NTG)
     k_band_gather(GridF g, BandLayout L, const float2* __restrict__ exy,
@@ -274,28 +280,22 @@ __global__ void __launch_bounds__(NTG)
   // the band's field rows and the next one (cells of up to two rows whose
   // first row is in the band read only these) staged in LDS
   __shared__ float2 rows[5 * kBandMaxN];
+  __shared__ int pre[NTG];
+  __shared__ int64_t start[NTG];
   const int t = threadIdx.x;
-  const int n = g.n, R = L.rows;
-  // XCD k runs a contiguous range of bands, all pieces of a band on one XCD
-  const int r = kGatherSplit > 1 ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
-  const int band = r / kGatherSplit, part = r % kGatherSplit;
+  const int n = g.n, R = L.rows, band = blockIdx.x;
   const int r0 = band * R, nr = min(R + 1, n - r0);
   if (MODE == FFTPL_GRAD_FIELD) {
     for (int k = t; k < nr * n; k += NTG) rows[k] = exy[(int64_t)r0 * n + k];
   }
-  // start of the band: the counts of the earlier bands
-  int start;
-  block_exclusive_scan<NTG>(t < band ? L.counters[t] : 0, &start);   // (synchronises)
-  const int len = L.counters[band], piece = (len + kGatherSplit - 1) / kGatherSplit;
-  const int lo = start + part * piece, end = min(start + len, lo + piece);
-  for (int e0 = lo; e0 < end; e0 += NTG * B) {
+  // (the walk's first scan synchronises the block after the staging)
+  walk_band<NTG, B>(L, band, kBandRegion, pre, start, [&](const int64_t (&idx)[B]) {
     float4 q[B];
 #pragma unroll
-    for (int j = 0; j < B; ++j) q[j] = L.entries[min(e0 + j * NTG + t, end - 1)];
+    for (int j = 0; j < B; ++j) q[j] = L.entries[idx[j] >= 0 ? idx[j] : 0];
 #pragma unroll
     for (int j = 0; j < B; ++j) {
-      const int e = e0 + j * NTG + t;
-      if (e >= end) continue;
+      if (idx[j] < 0) continue;
       const Span sx = span_from_edges(q[j].x, q[j].y, n);
       const Span sy = span_from_edges(q[j].z, q[j].w, n);
       if (sy.i0 / R != band) continue;   // listed again below its first band
@@ -312,23 +312,23 @@ __global__ void __launch_bounds__(NTG)
             ay += ov * f.y;
           }
         }
-        L.egrad[e] = make_float2(ax * -g.inv_bw, ay * -g.inv_bh);
+        L.egrad[idx[j]] = make_float2(ax * -g.inv_bw, ay * -g.inv_bh);
       } else {
-        L.egrad[e] = density_grad_spans<MODE, true>(g, sx, sy, nullptr, nullptr, exy, psi);
+        L.egrad[idx[j]] = density_grad_spans<MODE, true>(g, sx, sy, nullptr, nullptr, exy, psi);
       }
     }
-  }
+  });
 }
 
 hipError_t launch_band_gather(const GridF& g, const BandLayout& L, const float* exy,
                               const float* psi, int grad_mode, hipStream_t s) {
   const float2* e2 = reinterpret_cast<const float2*>(exy);
   if (grad_mode == FFTPL_GRAD_EXACT)
-    hipLaunchKernelGGL(k_band_gather<FFTPL_GRAD_EXACT>, dim3(L.nb * kGatherSplit), dim3(NTG),
-                       0, s, g, L, e2, psi);
+    hipLaunchKernelGGL(k_band_gather<FFTPL_GRAD_EXACT>, dim3(L.nb), dim3(NTG), 0, s, g, L, e2,
+                       psi);
   else
-    hipLaunchKernelGGL(k_band_gather<FFTPL_GRAD_FIELD>, dim3(L.nb * kGatherSplit), dim3(NTG),
-                       0, s, g, L, e2, psi);
+    hipLaunchKernelGGL(k_band_gather<FFTPL_GRAD_FIELD>, dim3(L.nb), dim3(NTG), 0, s, g, L, e2,
+                       psi);
   return hipGetLastError();
 }
 
@@ -353,19 +353,13 @@ hipError_t launch_band_scatter(const GridF& g, const BandLayout& L, const float*
                                const float* y, const float* w, const float* h,
                                const float* base, float* rho, hipStream_t s, Plan* tp) {
   if (L.m > 0) {
-    hipLaunchKernelGGL(k_band_count, dim3(L.nblk), dim3(NT), 0, s, g, L, x, y, w, h);
+    hipLaunchKernelGGL(k_band_place, dim3(L.nblk), dim3(NT), 0, s, g, L, x, y, w, h);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (tp) plan_mark(*tp, "k_band_count", s);
-    hipLaunchKernelGGL(k_band_scan, dim3(L.nb + 1), dim3(kScanThreads), 0, s, L);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (tp) plan_mark(*tp, "k_band_scan", s);
-    hipLaunchKernelGGL(k_band_place, dim3(L.nblk), dim3(NT), 0, s, g, L, x, y, w, h);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
     if (tp) plan_mark(*tp, "k_band_place", s);
   } else {
-    // no cells: empty bands and no tall cells
-    hipError_t e = launch_zero_i32(L.counters, L.nb + 1, s);
+    // no cells: one empty region
+    hipError_t e = launch_zero_i32(L.blk_cnt, (int64_t)L.nblk * (L.nb + 1), s);
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_band_accum, dim3(L.nb), dim3(NTA), 0, s, g, L, x, y, w, h, base, rho);

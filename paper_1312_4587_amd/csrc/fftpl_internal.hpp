@@ -522,6 +522,7 @@ constexpr int kBandMaxN = 1024;
 constexpr int kBandThreads = 512;      // threads of a counting / placing block
 constexpr int kCellBatch = 8;          // cells whose loads a thread issues together
 constexpr int kCellsPerBlock = kBandThreads * kCellBatch;   // 4096
+constexpr int kBandRegion = kMaxBands * kCellsPerBlock;      // entries per block
 constexpr int kAccThreads = 1024;      // threads of a band accumulation block
 
 struct BandLayout {
@@ -530,14 +531,15 @@ struct BandLayout {
   // regions of the problem workspace
   float2* xy = nullptr;          // [m] interleaved positions
   float2* pin_grad = nullptr;    // [P] per-pin WA gradients, cell-major slots
-  float4* entries = nullptr;     // [kMaxBands*m] band entries: cell edges in bins
+  float4* entries = nullptr;     // [nblk*kBandRegion] band entries (cell edges in bins),
+                                 // one region per counting block, sliced by band
   int32_t* epos = nullptr;       // [m] each cell's entry in its first band, -1 if none
-  float2* egrad = nullptr;       // [kMaxBands*m] density gradient of the cell whose
+  float2* egrad = nullptr;       // [nblk*kBandRegion] density gradient of the cell whose
                                  // first-band entry this is (band gather)
-  int32_t* big = nullptr;        // [m] cells spanning more than kMaxBands bands
-  int32_t* blk_base = nullptr;   // [nb][nblk] per band: each block's count, then its
-                                 // offset inside the band
-  int32_t* counters = nullptr;   // [nb + 1] band counts, then the big-cell count
+  int32_t* big = nullptr;        // [nblk*kCellsPerBlock] per block, its cells spanning
+                                 // more than kMaxBands bands
+  int32_t* blk_off = nullptr;    // [nb + 1][nblk] per band: each block's slice offset
+  int32_t* blk_cnt = nullptr;    // [nb + 1][nblk] per band: each block's slice size
   double* wa_part = nullptr;     // per-block W~ / HPWL partials (slot or exchange path)
   int nwa = 0;                   // blocks of each wirelength kernel
 };
