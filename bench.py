@@ -31,22 +31,24 @@ BF16_PEAK_TFLOPS = 2500.0
 PMC_FETCH_SCALE, PMC_WRITE_SCALE = 2.0, 1.0
 PMC_TRAFFIC = {
     # kernel: (source files, sha1, FETCH_SIZE KiB, WRITE_SIZE KiB)
-    "k_xch_spread": (("exchange.hip", "fftpl_internal.hpp"),
-        "5a03760b7ff584b53161d08316d12b4a1a738250", 28614.3, 96865.4),
-    "k_xch_wa": (("exchange.hip", "fftpl_internal.hpp"),
-        "5a03760b7ff584b53161d08316d12b4a1a738250", 187983.6, 116210.9),
-    "k_xch_cellsum": (("exchange.hip", "fftpl_internal.hpp"),
-        "5a03760b7ff584b53161d08316d12b4a1a738250", 60559.2, 16406.2),
     "k_band_place": (("band_scatter.hip", "fftpl_internal.hpp"),
-        "7ac4d6b1345cab2fc65030a16b54d96fc0d06f06", 18512.1, 44582.2),
+        "c4ffdd89c2b745bb31cd80b9218d1fda1b3f9400", 16523.3, 64703.3),
+    "k_xch_spread": (("exchange.hip", "fftpl_internal.hpp"),
+        "7c68c14c8f6c5a24790120ebeb3b0d467bd40f3e", 28613.6, 96905.3),
     "k_band_accum": (("band_scatter.hip", "fftpl_internal.hpp"),
-        "7ac4d6b1345cab2fc65030a16b54d96fc0d06f06", 20123.8, 4096.0),
+        "c4ffdd89c2b745bb31cd80b9218d1fda1b3f9400", 27906.8, 4096.0),
+    "k_xch_wa": (("exchange.hip", "fftpl_internal.hpp"),
+        "7c68c14c8f6c5a24790120ebeb3b0d467bd40f3e", 187978.6, 116211.4),
     "k_rows_dct2": (("spectral_fft.hip", "fftpl_internal.hpp"),
-        "902fd602d9356c5243700962d83fbbb907195c5c", 6235.2, 4112.0),
+        "69709c838b0e386815b492da25bcfd12f3f7fce1", 6235.2, 4112.0),
     "k_cols_solve": (("spectral_fft.hip", "fftpl_internal.hpp"),
-        "902fd602d9356c5243700962d83fbbb907195c5c", 2171.1, 8192.0),
+        "69709c838b0e386815b492da25bcfd12f3f7fce1", 2171.1, 8192.0),
     "k_rows_inverse": (("spectral_fft.hip", "fftpl_internal.hpp"),
-        "902fd602d9356c5243700962d83fbbb907195c5c", 6269.6, 8196.0),
+        "69709c838b0e386815b492da25bcfd12f3f7fce1", 6269.6, 8196.0),
+    "k_band_gather": (("band_scatter.hip", "fftpl_internal.hpp"),
+        "c4ffdd89c2b745bb31cd80b9218d1fda1b3f9400", 30984.4, 21047.6),
+    "k_xch_cellsum": (("exchange.hip", "fftpl_internal.hpp"),
+        "7c68c14c8f6c5a24790120ebeb3b0d467bd40f3e", 73824.4, 16406.2),
 }
 
 
