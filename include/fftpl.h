@@ -16,7 +16,9 @@
  * - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Every
  *   compute call only enqueues work on `stream` and returns; no call
  *   synchronises the host, and no compute call allocates device memory
- *   (workspace lives in the plan).
+ *   (workspace lives in the plan).  fftpl_eval may also run part of its work
+ *   on the plan's own stream, forked from `stream` and joined back into it
+ *   with events, so its results are ordered on `stream` like any other.
  * - Every call returns an int status (enum fftpl_status) and never throws.
  *   Argument errors are detected on the host before anything is enqueued and
  *   return FFTPL_E_INVAL.  A failed kernel launch returns FFTPL_E_DEVICE;
@@ -285,7 +287,11 @@ int fftpl_xindex_build(int32_t num_cells, int32_t num_nets, int32_t num_pins,
  * gx, gy [num_cells] are overwritten.  prob->grid.n must equal the plan's n.
  * With gx = gy = NULL only out4 is computed (the loss W~ + lambda N and the
  * other scalars, without the gather); this needs a workspace and an index in
- * prob (FFTPL_E_INVAL otherwise). */
+ * prob (FFTPL_E_INVAL otherwise).  With a workspace and an index the density
+ * branch (scatter, solve, per-cell density gradient) runs on the plan's own
+ * stream concurrently with the wirelength on `stream`; the density map, the
+ * cell sums and the scalars do not depend on the order of any atomic adds,
+ * so repeated evaluations give identical results. */
 int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
                const float* y, float lambda, float gamma, int32_t grad_mode,
                float* gx, float* gy, double* out4, void* stream);

@@ -87,23 +87,15 @@ int xch_dims(int m, int num_nets, int num_pins, int max_degree, XchDims* d) {
   off = align256(off + sizeof(uint16_t) * (size_t)num_pins);
   r.o_lc = off;
   off = align256(off + sizeof(uint16_t) * (size_t)num_pins);
-  r.o_cp = off;
-  off = align256(off + sizeof(int32_t) * ((size_t)m + 1));
-  r.o_qa = off;
-  off = align256(off + sizeof(int32_t) * (size_t)num_pins);
   r.o_ns = off;
   off = align256(off + sizeof(uint32_t) * (size_t)num_nets);
   r.index_bytes = off;
   // build workspace: counts / cursors, A starts, transposed counts, B starts,
   // scan block sums, flag and scan totals
   const size_t seg = (size_t)r.ncb * r.nnb;
-  // ... then the cell-major index's counters and block sums, and each pin's
-  // cell-major slot
   r.work_bytes = align256(sizeof(int32_t) * seg) * 4 +
                  align256(sizeof(int32_t) * ((seg + 1023) / 1024 + 1)) +
-                 align256(sizeof(int32_t) * 4) +
-                 align256(sizeof(int32_t) * ((size_t)m + (m + 1023) / 1024 + 1)) +
-                 align256(sizeof(int32_t) * (size_t)num_pins);
+                 align256(sizeof(int32_t) * 4);
   *d = r;
   return FFTPL_OK;
 }
@@ -116,8 +108,6 @@ XchIndex xch_index(const XchDims& d, const void* index) {
   X.a_of_b = reinterpret_cast<const int32_t*>(b + d.o_ab);
   X.lcsr = reinterpret_cast<const uint16_t*>(b + d.o_lcsr);
   X.lc = reinterpret_cast<const uint16_t*>(b + d.o_lc);
-  X.cell_ptr = reinterpret_cast<const int32_t*>(b + d.o_cp);
-  X.qa = reinterpret_cast<const int32_t*>(b + d.o_qa);
   X.nmeta = reinterpret_cast<const uint32_t*>(b + d.o_ns);
   return X;
 }
@@ -159,8 +149,7 @@ __global__ void __launch_bounds__(256)
               int nnb, int32_t* __restrict__ cnt, const int32_t* __restrict__ seg_a,
               const int32_t* __restrict__ seg_bt, const int32_t* __restrict__ nb_net_ptr,
               int32_t* __restrict__ a_of_b, uint16_t* __restrict__ lcsr,
-              uint16_t* __restrict__ lc, const int32_t* __restrict__ pin_slot,
-              int32_t* __restrict__ qa, int32_t* __restrict__ flag) {
+              uint16_t* __restrict__ lc, int32_t* __restrict__ flag) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (!PLACE && e == 0 && (net_ptr[0] != 0 || net_ptr[num_nets] != num_pins))
     atomicOr(flag, 1);
@@ -197,7 +186,6 @@ __global__ void __launch_bounds__(256)
       a_of_b[b] = a;
       lcsr[b] = (uint16_t)(p - base);
       lc[a] = (uint16_t)(c - cb * kXchCells);
-      qa[pin_slot[p]] = a;
     }
   }
 }
@@ -289,10 +277,6 @@ int xch_build(const XchDims& d, const int32_t* net_ptr, const int32_t* pin_cell,
   int32_t* sums = reinterpret_cast<int32_t*>(w);
   w += align256(sizeof(int32_t) * ((seg + 1023) / 1024 + 1));
   int32_t* flag = reinterpret_cast<int32_t*>(w);   // [0] error bits, [1] [2] scan totals
-  w += align256(sizeof(int32_t) * 4);
-  int32_t* nl_work = reinterpret_cast<int32_t*>(w);
-  w += align256(sizeof(int32_t) * ((size_t)d.m + (d.m + 1023) / 1024 + 1));
-  int32_t* pin_slot = reinterpret_cast<int32_t*>(w);
 
   char* ib = static_cast<char*>(index);
   int32_t* hdr = reinterpret_cast<int32_t*>(ib + d.o_hdr);
@@ -301,8 +285,6 @@ int xch_build(const XchDims& d, const int32_t* net_ptr, const int32_t* pin_cell,
   int32_t* a_of_b = reinterpret_cast<int32_t*>(ib + d.o_ab);
   uint16_t* lcsr = reinterpret_cast<uint16_t*>(ib + d.o_lcsr);
   uint16_t* lc = reinterpret_cast<uint16_t*>(ib + d.o_lc);
-  int32_t* cell_ptr = reinterpret_cast<int32_t*>(ib + d.o_cp);
-  int32_t* qa = reinterpret_cast<int32_t*>(ib + d.o_qa);
 
   const int E = d.num_nets, P = d.num_pins;
   const dim3 net_grid((E + 255) / 256 > 0 ? (E + 255) / 256 : 1);
@@ -316,7 +298,7 @@ int xch_build(const XchDims& d, const int32_t* net_ptr, const int32_t* pin_cell,
   if (e == hipSuccess) {
     hipLaunchKernelGGL((k_xi_pins<false>), net_grid, dim3(256), 0, s, E, net_ptr, P, pin_cell,
                        d.m, d.max_degree, d.npt, d.ncb, d.nnb, cnt, nullptr, nullptr, nullptr,
-                       nullptr, nullptr, nullptr, nullptr, nullptr, flag);
+                       nullptr, nullptr, nullptr, flag);
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = launch_exclusive_scan(cnt, (int)seg, seg_a, sums, flag + 1, s);
@@ -338,12 +320,11 @@ int xch_build(const XchDims& d, const int32_t* net_ptr, const int32_t* pin_cell,
       hipStreamSynchronize(s) != hipSuccess)
     return FFTPL_E_DEVICE;
   if (hflag[0] != 0 || hflag[1] != P || hflag[2] != P) return FFTPL_E_INVAL;
-  e = launch_netlist_index(d.m, P, pin_cell, cell_ptr, pin_slot, nl_work, s);
-  if (e == hipSuccess) e = launch_zero_i32(cnt, (int64_t)seg, s);
+  e = launch_zero_i32(cnt, (int64_t)seg, s);
   if (e == hipSuccess) {
     hipLaunchKernelGGL((k_xi_pins<true>), net_grid, dim3(256), 0, s, E, net_ptr, P, pin_cell,
                        d.m, d.max_degree, d.npt, d.ncb, d.nnb, cnt, seg_a, seg_bt, nb_net_ptr,
-                       a_of_b, lcsr, lc, pin_slot, qa, flag);
+                       a_of_b, lcsr, lc, flag);
     e = hipGetLastError();
   }
   if (e == hipSuccess) {

@@ -598,7 +598,7 @@ struct XchDims {
   int ncb = 0, nnb = 0;   // cell blocks, net blocks
   size_t index_bytes = 0, work_bytes = 0;
   // offsets inside the index buffer
-  size_t o_hdr = 0, o_cb = 0, o_nb = 0, o_ab = 0, o_lcsr = 0, o_lc = 0, o_cp = 0, o_qa = 0,
+  size_t o_hdr = 0, o_cb = 0, o_nb = 0, o_ab = 0, o_lcsr = 0, o_lc = 0,
          o_ns = 0;
 };
 // Returns FFTPL_OK, or FFTPL_E_UNSUPPORTED when max_degree is too large for
@@ -611,8 +611,6 @@ struct XchIndex {
   const int32_t* a_of_b = nullptr;      // [P] A position of each B-order pin
   const uint16_t* lcsr = nullptr;       // [P] pin offset inside its net block (B order)
   const uint16_t* lc = nullptr;         // [P] cell offset inside its cell block (A order)
-  const int32_t* cell_ptr = nullptr;    // [m+1] pins on cells < c
-  const int32_t* qa = nullptr;          // [P] A position of each pin, cell-major
   const uint32_t* nmeta = nullptr;      // [E] per net block, its nets by degree class:
                                        // (first pin - block's first pin) << 16 | degree
 };
