@@ -27,6 +27,13 @@ Readings of points the paper leaves open or prints ambiguously:
   2 of a quadratic form.
 * The weighted-average wirelength of Eq. (3) is evaluated with max/min
   shifted exponentials (identical in exact arithmetic).
+* The screened (Helmholtz) equation that Section II cites as Eq. (4) is
+  taken with the sign convention of Eq. (8), -laplace(psi) + eps psi =
+  rho - mean, so each cosine mode divides by w_u^2 + w_v^2 + eps; eps = 0
+  is Eq. (8) itself.
+* The log-sum-exp wirelength that Section II names beside Eq. (3) is not
+  printed; it is taken in its usual form gamma ln sum exp(X/gamma) + gamma
+  ln sum exp(-X/gamma) per net and axis.
 * Overflow (the stopping criterion of Section IV-A, defined only by
   reference to NTUplace3): tau = sum_b max(0, rho_mov,b - cap_b) /
   sum_b rho_mov,b with cap_b = rho_t * max(0, 1 - min(1, f_b)) and f_b the
@@ -44,7 +51,8 @@ __all__ = [
     "fixed_maps", "density_map", "cos_table", "sin_table",
     "dct_coefficients", "dct_coefficients_literal", "remove_dc",
     "spectral_potential", "potential_field", "poisson_solve", "energy",
-    "field_gradient", "exact_gradient", "wa_wirelength", "hpwl",
+    "field_gradient", "exact_gradient", "wa_wirelength", "lse_wirelength",
+    "hpwl",
     "overflow", "evaluate", "local_fd_gradient", "potential_differences",
 ]
 
@@ -219,20 +227,26 @@ def remove_dc(a: np.ndarray) -> np.ndarray:
     return a
 
 
-def spectral_potential(a: np.ndarray):
-    """G = a / (w_u^2 + w_v^2) and its frequency-weighted copies
+def spectral_potential(a: np.ndarray, eps: float = 0.0):
+    """G = a / (w_u^2 + w_v^2 + eps) and its frequency-weighted copies
     Gx = w_u G, Gy = w_v G (the coefficients of Eqs. (11) and (12)), with
-    the (0, 0) entry zero."""
+    the (0, 0) entry zero.
+
+    eps = 0 is the paper's Poisson equation (8).  eps > 0 is the screened
+    (Helmholtz) form of Eq. (4), taken with the sign convention of Eq. (8):
+    -laplace(psi) + eps psi = rho - mean, whose cosine modes divide by
+    w_u^2 + w_v^2 + eps (eps in bin^-2, like w_u^2).  The DC is still
+    removed first, so the (0, 0) mode stays zero."""
     n = a.shape[0]
     wfreq = np.pi * np.arange(n) / n
-    denom = wfreq[:, None] ** 2 + wfreq[None, :] ** 2     # [v, u]
+    denom = wfreq[:, None] ** 2 + wfreq[None, :] ** 2 + float(eps)   # [v, u]
     denom[0, 0] = 1.0
     G = np.asarray(a, np.float64) / denom
     G[0, 0] = 0.0
     return G, G * wfreq[None, :], G * wfreq[:, None]
 
 
-def potential_field(a: np.ndarray):
+def potential_field(a: np.ndarray, eps: float = 0.0):
     """Eqs. (11) and (12) at the bin centres, by direct sums:
 
         psi[iy, ix] = sum_{v,u} G[v,u]   cos(w_v y) cos(w_u x)
@@ -242,18 +256,19 @@ def potential_field(a: np.ndarray):
     n = a.shape[0]
     K = cos_table(n)
     S = sin_table(n)
-    G, Gx, Gy = spectral_potential(a)
+    G, Gx, Gy = spectral_potential(a, eps)
     psi = K.T @ G @ K
     ex = K.T @ Gx @ S
     ey = S.T @ Gy @ K
     return psi, ex, ey
 
 
-def poisson_solve(rho: np.ndarray):
-    """Neumann Poisson solve of Eq. (8) through Eqs. (9)-(12):
+def poisson_solve(rho: np.ndarray, eps: float = 0.0):
+    """Neumann Poisson solve of Eq. (8) through Eqs. (9)-(12) (or, with
+    eps > 0, the screened form of Eq. (4), see ``spectral_potential``):
     returns (psi, Ex, Ey, a) with a the DC-free coefficients."""
     a = remove_dc(dct_coefficients(rho))
-    psi, ex, ey = potential_field(a)
+    psi, ex, ey = potential_field(a, eps)
     return psi, ex, ey, a
 
 
@@ -393,6 +408,46 @@ def wa_wirelength(inst, x=None, y=None, gamma=None):
     return float(np.sum(wx) + np.sum(wy)), gx, gy
 
 
+def _lse_axis(pos: np.ndarray, net_ptr, gamma: float):
+    """One axis of the log-sum-exp model (Section II) for every net:
+    LSE = gamma ln sum exp(X/gamma) + gamma ln sum exp(-X/gamma), evaluated
+    as (M - L) + gamma (ln S+ + ln S-) with S+ = sum exp((X - M)/gamma) and
+    S- = sum exp((L - X)/gamma) (the same value: the shifts cancel); the
+    gradient is the difference of the two softmax weights, e+/S+ - e-/S-.
+    Returns (LSE per net, gradient per pin) over non-empty nets."""
+    net_ptr, deg, ne = _segments(net_ptr)
+    starts = net_ptr[:-1][ne]
+    if starts.size == 0:
+        return np.zeros(0), np.zeros(pos.size)
+    M = np.maximum.reduceat(pos, starts)
+    L = np.minimum.reduceat(pos, starts)
+    seg = np.repeat(np.arange(starts.size), deg[ne])
+    ep = np.exp((pos - M[seg]) / gamma)
+    em = np.exp((L[seg] - pos) / gamma)
+    sp = np.add.reduceat(ep, starts)
+    sm = np.add.reduceat(em, starts)
+    val = (M - L) + gamma * (np.log(sp) + np.log(sm))
+    return val, ep / sp[seg] - em / sm[seg]
+
+
+def lse_wirelength(inst, x=None, y=None, gamma=None):
+    """Log-sum-exp wirelength (the smooth model Section II sets beside
+    Eq. (3)) over both axes, FP64: returns (LSE, gx, gy) like
+    ``wa_wirelength``."""
+    x = inst.x if x is None else x
+    y = inst.y if y is None else y
+    gamma = inst.gamma if gamma is None else gamma
+    pc = np.asarray(inst.pin_cell, np.int64)
+    px = np.asarray(x, np.float64)[pc] + np.asarray(inst.pin_dx, np.float64)
+    py = np.asarray(y, np.float64)[pc] + np.asarray(inst.pin_dy, np.float64)
+    m = len(x)
+    vx, gpx = _lse_axis(px, inst.net_ptr, float(gamma))
+    vy, gpy = _lse_axis(py, inst.net_ptr, float(gamma))
+    gx = np.bincount(pc, weights=gpx, minlength=m) if pc.size else np.zeros(m)
+    gy = np.bincount(pc, weights=gpy, minlength=m) if pc.size else np.zeros(m)
+    return float(np.sum(vx) + np.sum(vy)), gx, gy
+
+
 def hpwl(inst, x=None, y=None) -> float:
     """Eq. (1): sum over nets of (max - min) of pin x plus the same in y."""
     x = inst.x if x is None else x
@@ -424,18 +479,25 @@ def overflow(rho: np.ndarray, base: np.ndarray, cap: np.ndarray) -> float:
 # One evaluation (Algorithm 1, the density / solve / gradient steps).
 # ---------------------------------------------------------------------------
 
-def evaluate(inst, lam: float = 1.0, gamma=None, grad_mode: str = "field"
-             ) -> Dict[str, object]:
+def evaluate(inst, lam: float = 1.0, gamma=None, grad_mode: str = "field",
+             wl_model: str = "wa", eps: float = 0.0) -> Dict[str, object]:
     """f = W~ + lambda N (Eq. (7)) and its gradient for the movable cells.
 
     grad_mode "field": g = grad W~ + lambda * (-q E) (Section III-C);
     grad_mode "exact": g = grad W~ + lambda * dN/dx.
+    wl_model "wa" (Eq. (3)) or "lse" (Section II) for W~; eps > 0 solves
+    the screened equation (Eq. (4)) instead of Eq. (8).
     """
     base, cap = fixed_maps(inst)
     rho = density_map(inst, base)
-    psi, ex, ey, a = poisson_solve(rho)
+    psi, ex, ey, a = poisson_solve(rho, eps)
     N = energy(rho, psi)
-    wa, gwx, gwy = wa_wirelength(inst, gamma=gamma)
+    if wl_model == "wa":
+        wa, gwx, gwy = wa_wirelength(inst, gamma=gamma)
+    elif wl_model == "lse":
+        wa, gwx, gwy = lse_wirelength(inst, gamma=gamma)
+    else:
+        raise ValueError(wl_model)
     if grad_mode == "field":
         gnx, gny = field_gradient(inst, ex, ey)
     elif grad_mode == "exact":

@@ -217,3 +217,72 @@ def test_local_finite_differences_match_the_exact_gradient():
     ex = np.concatenate([ref["gx"][cells][ok], ref["gy"][cells][ok]])
     fd = np.concatenate([gx[ok], gy[ok]])
     assert np.linalg.norm(ex - fd) / np.linalg.norm(ex) < 1e-6
+
+
+# ---- log-sum-exp wirelength (the model Section II sets beside Eq. (3)) ----
+
+@pytest.mark.parametrize("d,gamma", [(0.375, 0.5), (2.0, 0.5), (7.0, 0.25), (40.0, 3.0)])
+def test_lse_two_pin_closed_form(d, gamma):
+    # per axis: gamma ln(e^{a/g} + e^{b/g}) + gamma ln(e^{-a/g} + e^{-b/g})
+    #         = d + 2 gamma ln(1 + e^{-d/gamma}); derivative tanh(d / 2 gamma)
+    inst = _net_inst([(1.0, 2.0), (1.0 + d, 2.0 + d)], gamma)
+    W, gx, gy = oracle.lse_wirelength(inst)
+    per_axis = d + 2 * gamma * math.log1p(math.exp(-d / gamma))
+    assert W == pytest.approx(2 * per_axis, rel=1e-12)
+    t = math.tanh(d / (2 * gamma))
+    assert gx[1] == pytest.approx(t, rel=1e-10) and gx[0] == pytest.approx(-t, rel=1e-10)
+    assert gy[1] == pytest.approx(t, rel=1e-10)
+
+
+def test_lse_unshifted_form_at_moderate_gamma():
+    # the textbook form with unshifted exponentials, where they do not overflow
+    inst = tiny_instance(seed=6, m=30, n=8, num_nets=20)
+    inst.gamma = 4.0
+    W, _, _ = oracle.lse_wirelength(inst)
+    pc = np.asarray(inst.pin_cell)
+    ref = 0.0
+    for pos in (inst.x.astype(np.float64)[pc] + inst.pin_dx, inst.y.astype(np.float64)[pc] + inst.pin_dy):
+        for e in range(len(inst.net_ptr) - 1):
+            q = pos[inst.net_ptr[e]:inst.net_ptr[e + 1]]
+            if q.size:
+                g = inst.gamma
+                ref += g * math.log(math.fsum(math.exp(v / g) for v in q))
+                ref += g * math.log(math.fsum(math.exp(-v / g) for v in q))
+    assert W == pytest.approx(ref, rel=1e-12)
+
+
+def test_lse_gradient_by_finite_differences():
+    inst = tiny_instance(seed=7, m=40, n=8, num_nets=30)
+    inst.gamma = 0.6
+    W, gx, gy = oracle.lse_wirelength(inst)
+    x = inst.x.astype(np.float64)
+    y = inst.y.astype(np.float64)
+    h = 1e-5
+    for i in range(0, 40, 3):
+        xp, xm = x.copy(), x.copy()
+        xp[i] += h
+        xm[i] -= h
+        fd = (oracle.lse_wirelength(inst, x=xp, y=y)[0]
+              - oracle.lse_wirelength(inst, x=xm, y=y)[0]) / (2 * h)
+        assert abs(fd - gx[i]) < 1e-6 * max(1.0, abs(gx[i]))
+        yp, ym = y.copy(), y.copy()
+        yp[i] += h
+        ym[i] -= h
+        fd = (oracle.lse_wirelength(inst, x=x, y=yp)[0]
+              - oracle.lse_wirelength(inst, x=x, y=ym)[0]) / (2 * h)
+        assert abs(fd - gy[i]) < 1e-6 * max(1.0, abs(gy[i]))
+
+
+def test_lse_bounds_translation_invariance_and_limit():
+    inst = tiny_instance(seed=8, m=80, n=8, num_nets=60)
+    W, gx, gy = oracle.lse_wirelength(inst)
+    assert abs(gx.sum()) < 1e-9 and abs(gy.sum()) < 1e-9
+    # per net and axis HPWL <= LSE <= HPWL + 2 gamma ln(degree)
+    hp = oracle.hpwl(inst)
+    deg = np.diff(inst.net_ptr)
+    slack = 2.0 * 2.0 * inst.gamma * np.sum(np.log(deg[deg > 0]))
+    assert hp <= W <= hp + slack
+    # LSE -> HPWL as gamma -> 0 (WA approaches from below, LSE from above)
+    Wa, _, _ = oracle.wa_wirelength(inst, gamma=1e-4)
+    Ws, _, _ = oracle.lse_wirelength(inst, gamma=1e-4)
+    assert Wa <= hp <= Ws and Ws - hp < 1e-2

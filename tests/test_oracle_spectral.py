@@ -187,3 +187,63 @@ def test_tables_against_direct_trig():
             ang = math.pi * uu * (2 * ii + 1) / (2 * n)
             assert abs(K[uu, ii] - math.cos(ang)) < 1e-12
             assert abs(S[uu, ii] - math.sin(ang)) < 1e-12
+
+
+# ---- the screened (Helmholtz) form of Eq. (4), Eq. (8)'s sign convention ----
+
+@pytest.mark.parametrize("n,u,v,eps", [(16, 3, 5, 0.05), (16, 0, 1, 2.0), (64, 17, 40, 0.3)])
+def test_screened_single_mode_closed_form(n, u, v, eps):
+    x = np.arange(n) + 0.5
+    wu, wv = np.pi * u / n, np.pi * v / n
+    rho = np.outer(np.cos(wv * x), np.cos(wu * x))
+    psi, ex, ey, _ = oracle.poisson_solve(rho, eps)
+    d = wu * wu + wv * wv + eps
+    assert np.max(np.abs(psi - rho / d)) < 1e-12 / d
+    assert np.max(np.abs(ex - wu / d * np.outer(np.cos(wv * x), np.sin(wu * x)))) < 1e-12 / d
+    assert np.max(np.abs(ey - wv / d * np.outer(np.sin(wv * x), np.cos(wu * x)))) < 1e-12 / d
+
+
+def test_screened_pde_and_neumann_boundary():
+    n, eps = 16, 0.4
+    rho = np.random.default_rng(12).random((n, n))
+    psi, ex, ey, a = oracle.poisson_solve(rho, eps)
+    G, Gx, Gy = oracle.spectral_potential(a, eps)
+    xc = np.arange(n) + 0.5
+    h = 1e-3
+    P = lambda xs, ys: _series(G, Gx, Gy, xs, ys)[0]
+    assert np.max(np.abs(P(xc, xc) - psi)) < 1e-12
+    lap = (P(xc + h, xc) + P(xc - h, xc) + P(xc, xc + h) + P(xc, xc - h)
+           - 4 * P(xc, xc)) / (h * h)
+    # -laplace(psi) + eps psi = rho - mean at the bin centres
+    assert np.max(np.abs(-lap + eps * psi - (rho - rho.mean()))) < 2e-5
+    dpx = (P(xc + h, xc) - P(xc - h, xc)) / (2 * h)
+    assert np.max(np.abs(ex + dpx)) < 1e-6 * np.max(np.abs(ex))
+    ys = np.linspace(0, n, 7)
+    for xb in (0.0, float(n)):
+        assert np.max(np.abs(_series(G, Gx, Gy, np.array([xb]), ys)[1])) < 1e-12
+
+
+def test_screened_parseval_monotone_and_limits():
+    n = 32
+    rho = np.random.default_rng(13).random((n, n))
+    w = np.pi * np.arange(n) / n
+    c = _cw(n)
+    last = None
+    for eps in (0.0, 1e-3, 0.1, 1.0, 10.0):
+        psi, _, _, a = oracle.poisson_solve(rho, eps)
+        d = w[:, None] ** 2 + w[None, :] ** 2 + eps
+        d[0, 0] = 1.0
+        N_spec = n * n * np.sum(a * a / (np.outer(c, c) * d))
+        N = oracle.energy(rho, psi)
+        assert abs(N - N_spec) < 1e-12 * N
+        if last is not None:
+            assert N < last          # screening only lowers every mode's weight
+        last = N
+    # eps -> 0 is Eq. (8); eps -> infinity makes the potential local: eps psi -> rho - mean
+    p0 = oracle.poisson_solve(rho)[0]
+    p1 = oracle.poisson_solve(rho, 1e-9)[0]
+    assert np.max(np.abs(p1 - p0)) < 1e-7 * np.max(np.abs(p0))
+    big = 1e6
+    pb = oracle.poisson_solve(rho, big)[0]
+    dev = rho - rho.mean()
+    assert np.max(np.abs(big * pb - dev)) < 3e-5 * np.max(np.abs(dev))
