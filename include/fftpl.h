@@ -78,6 +78,14 @@ enum fftpl_grad_mode {
                            factor 2 of the quadratic form)                   */
 };
 
+/* Wirelength model of the objective. */
+enum fftpl_wl_model {
+  FFTPL_WL_WA = 0, /* weighted average, Eq. (3): the paper's model          */
+  FFTPL_WL_LSE = 1 /* log-sum-exp, the smooth model Section II names beside
+                      Eq. (3): per net and axis
+                      gamma ln sum e^(X/gamma) + gamma ln sum e^(-X/gamma)  */
+};
+
 /* The bin grid over the placement region R (Section II): n x n bins of
  * bin_w x bin_h starting at (xl, yl).  target_density is rho_t, the scale of
  * fixed-node charge (Section III-B). */
@@ -115,13 +123,17 @@ typedef struct fftpl_plan fftpl_plan;
  * too small) fftpl_eval uses float atomics for the density scatter and the
  * wirelength gradient instead.  All paths give the same results up to
  * float32 rounding order.  An index must be rebuilt when net_ptr or pin_cell
- * change; pin offsets and positions may change freely. */
+ * change; pin offsets and positions may change freely.
+ *
+ * wl_model selects the wirelength term W~ (enum fftpl_wl_model; 0 is the
+ * paper's weighted average).  screening is eps >= 0 of the screened solve
+ * (see fftpl_helmholtz_solve; 0 is the paper's Poisson equation). */
 typedef struct fftpl_problem {
   fftpl_grid grid;
   int32_t num_cells;
   int32_t num_nets;
   int32_t num_pins;
-  int32_t reserved; /* must be 0 */
+  int32_t wl_model; /* enum fftpl_wl_model */
   const float* w;
   const float* h;
   const float* base;
@@ -137,7 +149,7 @@ typedef struct fftpl_problem {
   const void* xindex;
   uint64_t xindex_bytes;
   int32_t max_degree; /* the value xindex was built for */
-  int32_t reserved2;  /* must be 0 */
+  float screening;    /* eps >= 0, bin^-2 units; 0 = Poisson */
 } fftpl_problem;
 
 /* Library version (FFTPL_VERSION of the build). */
@@ -192,6 +204,23 @@ int fftpl_fixed_map(const fftpl_grid* grid, int32_t num_fixed, const float* fx,
                     const float* fy, const float* fw, const float* fh, float* base,
                     float* cap, void* stream);
 
+/* Dark nodes of an irregular placement region (Section III-B: each
+ * non-placeable rectangle inside the bounding box R is a dark node, charged
+ * like a fixed node at the target density).  Host-only: given R = [xl, xh] x
+ * [yl, yh] and the placeable part as the union of num_rects rectangles
+ * (HOST array rects [4*num_rects] of corners x0, y0, x1, y1 with x0 <= x1 and
+ * y0 <= y1; clipped to R, overlaps allowed), writes R minus that union as
+ * disjoint rectangles to the HOST array out [4*max_out] (same corner layout)
+ * and their count to *num_out.  The pieces are horizontal slabs between
+ * consecutive distinct y edges, merged upwards while the x intervals stay the
+ * same.  Rasterise them with fftpl_fixed_map (centre and size per
+ * rectangle) beside any fixed macros; a macro overlapping a dark node is
+ * counted twice there.  More than max_out pieces: FFTPL_E_INVAL with
+ * *num_out = the number needed (call again with a larger out).  Non-finite
+ * values, an inverted rectangle or an empty R: FFTPL_E_INVAL. */
+int fftpl_dark_nodes(double xl, double yl, double xh, double yh, int32_t num_rects,
+                     const double* rects, int32_t max_out, double* out, int32_t* num_out);
+
 /* Density map (Eq. (2), Section III-B): rho = base + sum over movable cells of
  * their overlap area with each bin.  base may be NULL (treated as 0).  rho is
  * overwritten; accumulation uses float atomics, so the rounding order (not
@@ -211,6 +240,18 @@ int fftpl_density_map(const fftpl_grid* grid, int32_t num_cells, const float* x,
 int fftpl_poisson_solve(fftpl_plan* plan, const fftpl_grid* grid, const float* rho,
                         float* psi, float* ex, float* ey, double* energy,
                         void* stream);
+
+/* The screened (Helmholtz) form of the solve, Eq. (4) as Section II cites
+ * it, taken with the sign convention of Eq. (8):
+ *   -laplace(psi) + eps psi = rho - mean(rho)   (Neumann boundary),
+ * i.e. every mode of fftpl_poisson_solve is divided by w_u^2 + w_v^2 + eps
+ * instead of w_u^2 + w_v^2 (eps in bin^-2 units, like w_u^2; the DC is still
+ * removed).  eps = 0 is fftpl_poisson_solve.  eps must be finite and >= 0
+ * (else FFTPL_E_INVAL); the other arguments are those of
+ * fftpl_poisson_solve. */
+int fftpl_helmholtz_solve(fftpl_plan* plan, const fftpl_grid* grid, float eps,
+                          const float* rho, float* psi, float* ex, float* ey,
+                          double* energy, void* stream);
 
 /* Density gradient per movable cell (Section III-C), times `scale` (lambda):
  *   FIELD: gx_i = -scale/bin_w * sum_b ov(i,b) Ex_b  (gy with Ey, bin_h); reads ex, ey.
@@ -234,6 +275,18 @@ int fftpl_wa_grad(int32_t num_nets, const int32_t* net_ptr, int32_t num_pins,
                   int32_t num_cells, const float* x, const float* y, float gamma,
                   int32_t accumulate, float* gx, float* gy, double* wa,
                   double* hpwl, void* stream);
+
+/* The log-sum-exp wirelength (FFTPL_WL_LSE) with the arguments, outputs and
+ * errors of fftpl_wa_grad: per net and axis, with M, L the largest and
+ * smallest pin coordinate, S+ = sum exp((X - M)/gamma), S- = sum exp((L -
+ * X)/gamma): value (M - L) + gamma (ln S+ + ln S-), gradient
+ * exp((X_p - M)/gamma)/S+ - exp((L - X_p)/gamma)/S-.  wa receives the LSE
+ * total. */
+int fftpl_lse_grad(int32_t num_nets, const int32_t* net_ptr, int32_t num_pins,
+                   const int32_t* pin_cell, const float* pin_dx, const float* pin_dy,
+                   int32_t num_cells, const float* x, const float* y, float gamma,
+                   int32_t accumulate, float* gx, float* gy, double* wa, double* hpwl,
+                   void* stream);
 
 /* Bytes of the optional fftpl_problem workspace for grid side n, num_cells
  * cells, num_nets nets and num_pins pins (the interleaved positions, per-pin
@@ -281,7 +334,8 @@ int fftpl_xindex_build(int32_t num_cells, int32_t num_nets, int32_t num_pins,
                        void* stream);
 
 /* One full evaluation (Algorithm 1, the density / FFT solve / gradient steps):
- *   rho = base + cells; Poisson solve; g = dW~/dv + lambda * g_N (grad_mode);
+ *   rho = base + cells; Poisson solve (screened when prob->screening > 0);
+ *   g = dW~/dv + lambda * g_N (grad_mode; W~ per prob->wl_model);
  *   out4 (device double[4]) = [N, W~, HPWL, tau] with tau the overflow ratio
  *   sum_b max(0, rho_b - base_b - cap_b) / sum_b (rho_b - base_b).
  * gx, gy [num_cells] are overwritten.  prob->grid.n must equal the plan's n.

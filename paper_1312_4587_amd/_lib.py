@@ -23,14 +23,14 @@ class fftpl_grid(ctypes.Structure):
 class fftpl_problem(ctypes.Structure):
     _fields_ = [("grid", fftpl_grid),
                 ("num_cells", ctypes.c_int32), ("num_nets", ctypes.c_int32),
-                ("num_pins", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("num_pins", ctypes.c_int32), ("wl_model", ctypes.c_int32),
                 ("w", c_void_p), ("h", c_void_p), ("base", c_void_p),
                 ("cap", c_void_p), ("net_ptr", c_void_p), ("pin_cell", c_void_p),
                 ("pin_dx", c_void_p), ("pin_dy", c_void_p),
                 ("cell_ptr", c_void_p), ("pin_slot", c_void_p),
                 ("work", c_void_p), ("work_bytes", ctypes.c_uint64),
                 ("xindex", c_void_p), ("xindex_bytes", ctypes.c_uint64),
-                ("max_degree", ctypes.c_int32), ("reserved2", ctypes.c_int32)]
+                ("max_degree", ctypes.c_int32), ("screening", ctypes.c_float)]
 
 
 _G = ctypes.POINTER(fftpl_grid)
@@ -47,16 +47,23 @@ SIGNATURES = {
                                 ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p)]),
     "fftpl_fixed_map": (c_int, [_G, c_int, c_void_p, c_void_p, c_void_p, c_void_p,
                                 c_void_p, c_void_p, c_void_p]),
+    "fftpl_dark_nodes": (c_int, [c_double, c_double, c_double, c_double, c_int, c_void_p,
+                                 c_int, c_void_p, ctypes.POINTER(c_int)]),
     "fftpl_density_map": (c_int, [_G, c_int, c_void_p, c_void_p, c_void_p, c_void_p,
                                   c_void_p, c_void_p, c_void_p]),
     "fftpl_poisson_solve": (c_int, [c_void_p, _G, c_void_p, c_void_p, c_void_p,
                                     c_void_p, c_void_p, c_void_p]),
+    "fftpl_helmholtz_solve": (c_int, [c_void_p, _G, c_float, c_void_p, c_void_p, c_void_p,
+                                      c_void_p, c_void_p, c_void_p]),
     "fftpl_field_gather": (c_int, [_G, c_int, c_void_p, c_void_p, c_void_p, c_void_p,
                                    c_void_p, c_void_p, c_void_p, c_int, c_float, c_int,
                                    c_void_p, c_void_p, c_void_p]),
     "fftpl_wa_grad": (c_int, [c_int, c_void_p, c_int, c_void_p, c_void_p, c_void_p,
                               c_int, c_void_p, c_void_p, c_float, c_int, c_void_p,
                               c_void_p, c_void_p, c_void_p, c_void_p]),
+    "fftpl_lse_grad": (c_int, [c_int, c_void_p, c_int, c_void_p, c_void_p, c_void_p,
+                               c_int, c_void_p, c_void_p, c_float, c_int, c_void_p,
+                               c_void_p, c_void_p, c_void_p, c_void_p]),
     "fftpl_eval": (c_int, [c_void_p, _P, c_void_p, c_void_p, c_float, c_float, c_int,
                            c_void_p, c_void_p, c_void_p, c_void_p]),
     "fftpl_debug_cell_bins": (c_int, [_G, c_int, c_void_p, c_void_p, c_void_p,

@@ -5,6 +5,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <vector>
 
@@ -216,6 +217,74 @@ int fftpl_fixed_map(const fftpl_grid* grid, int32_t num_fixed, const float* fx,
                                      cap, as_stream(stream)));
 }
 
+int fftpl_dark_nodes(double xl, double yl, double xh, double yh, int32_t num_rects,
+                     const double* rects, int32_t max_out, double* out, int32_t* num_out) {
+  if (!num_out || num_rects < 0 || max_out < 0) return FFTPL_E_INVAL;
+  if ((num_rects > 0 && !rects) || (max_out > 0 && !out)) return FFTPL_E_INVAL;
+  if (!isfinite(xl) || !isfinite(yl) || !isfinite(xh) || !isfinite(yh) || !(xh > xl) ||
+      !(yh > yl))
+    return FFTPL_E_INVAL;
+  struct Box {
+    double x0, y0, x1, y1;
+  };
+  std::vector<Box> place;
+  std::vector<double> ys = {yl, yh};
+  for (int32_t i = 0; i < num_rects; ++i) {
+    const double* r = rects + 4 * (size_t)i;
+    for (int k = 0; k < 4; ++k)
+      if (!isfinite(r[k])) return FFTPL_E_INVAL;
+    if (r[2] < r[0] || r[3] < r[1]) return FFTPL_E_INVAL;
+    const Box b{fmax(r[0], xl), fmax(r[1], yl), fmin(r[2], xh), fmin(r[3], yh)};
+    if (b.x1 <= b.x0 || b.y1 <= b.y0) continue;   // empty inside R
+    place.push_back(b);
+    ys.push_back(b.y0);
+    ys.push_back(b.y1);
+  }
+  std::sort(ys.begin(), ys.end());
+  ys.erase(std::unique(ys.begin(), ys.end()), ys.end());
+  // Horizontal slabs between consecutive y edges: in each, the placeable x
+  // intervals are those of the rectangles spanning the whole slab; their
+  // complement in [xl, xh] is dark.  A slab whose dark intervals equal the
+  // previous slab's extends those rectangles upwards.
+  std::vector<std::pair<double, double>> open, cur, iv;
+  double open_y = yl;
+  int64_t count = 0;
+  auto emit = [&](double y1) {
+    for (const auto& d : open) {
+      if (count < max_out) {
+        double* o = out + 4 * (size_t)count;
+        o[0] = d.first;
+        o[1] = open_y;
+        o[2] = d.second;
+        o[3] = y1;
+      }
+      ++count;
+    }
+  };
+  for (size_t k = 0; k + 1 < ys.size(); ++k) {
+    const double a = ys[k], b = ys[k + 1];
+    iv.clear();
+    for (const Box& r : place)
+      if (r.y0 <= a && r.y1 >= b) iv.emplace_back(r.x0, r.x1);
+    std::sort(iv.begin(), iv.end());
+    cur.clear();
+    double x = xl;   // left end of the part not yet known to be placeable
+    for (const auto& q : iv) {
+      if (q.first > x) cur.emplace_back(x, q.first);
+      x = fmax(x, q.second);
+    }
+    if (x < xh) cur.emplace_back(x, xh);
+    if (k > 0 && cur == open) continue;
+    emit(a);
+    open = cur;
+    open_y = a;
+  }
+  emit(yh);
+  if (count > INT32_MAX) return FFTPL_E_INVAL;
+  *num_out = (int32_t)count;
+  return count > max_out ? FFTPL_E_INVAL : FFTPL_OK;
+}
+
 int fftpl_density_map(const fftpl_grid* grid, int32_t num_cells, const float* x,
                       const float* y, const float* w, const float* h,
                       const float* base, float* rho, void* stream) {
@@ -232,10 +301,11 @@ int fftpl_density_map(const fftpl_grid* grid, int32_t num_cells, const float* x,
   return dev_status(e);
 }
 
-int fftpl_poisson_solve(fftpl_plan* plan, const fftpl_grid* grid, const float* rho,
-                        float* psi, float* ex, float* ey, double* energy,
-                        void* stream) {
+int fftpl_helmholtz_solve(fftpl_plan* plan, const fftpl_grid* grid, float eps,
+                          const float* rho, float* psi, float* ex, float* ey,
+                          double* energy, void* stream) {
   if (!plan || !grid_ok(grid) || !rho || !psi) return FFTPL_E_INVAL;
+  if (!(eps >= 0.0f) || !isfinite(eps)) return FFTPL_E_INVAL;
   if ((ex == nullptr) != (ey == nullptr)) return FFTPL_E_INVAL;
   if (grid->n != plan->p.n) return FFTPL_E_STATE;
   hipStream_t s = as_stream(stream);
@@ -244,6 +314,7 @@ int fftpl_poisson_solve(fftpl_plan* plan, const fftpl_grid* grid, const float* r
   a.psi = psi;
   a.ex = ex;
   a.ey = ey;
+  a.eps = eps;
   a.en_part = energy ? plan->p.partials : nullptr;
   hipError_t e = hipSuccess;
   plan->p.nev = 0;
@@ -256,6 +327,12 @@ int fftpl_poisson_solve(fftpl_plan* plan, const fftpl_grid* grid, const float* r
     plan_mark(plan->p, "k_eval_finalize", s);
   }
   return dev_status(e);
+}
+
+int fftpl_poisson_solve(fftpl_plan* plan, const fftpl_grid* grid, const float* rho,
+                        float* psi, float* ex, float* ey, double* energy,
+                        void* stream) {
+  return fftpl_helmholtz_solve(plan, grid, 0.0f, rho, psi, ex, ey, energy, stream);
 }
 
 int fftpl_field_gather(const fftpl_grid* grid, int32_t num_cells, const float* x,
@@ -275,11 +352,11 @@ int fftpl_field_gather(const fftpl_grid* grid, int32_t num_cells, const float* x
                                   as_stream(stream)));
 }
 
-int fftpl_wa_grad(int32_t num_nets, const int32_t* net_ptr, int32_t num_pins,
-                  const int32_t* pin_cell, const float* pin_dx, const float* pin_dy,
-                  int32_t num_cells, const float* x, const float* y, float gamma,
-                  int32_t accumulate, float* gx, float* gy, double* wa, double* hpwl,
-                  void* stream) {
+static int wl_grad(int wl_model, int32_t num_nets, const int32_t* net_ptr, int32_t num_pins,
+                   const int32_t* pin_cell, const float* pin_dx, const float* pin_dy,
+                   int32_t num_cells, const float* x, const float* y, float gamma,
+                   int32_t accumulate, float* gx, float* gy, double* wa, double* hpwl,
+                   void* stream) {
   if (num_nets < 0 || num_pins < 0 || num_cells < 0) return FFTPL_E_INVAL;
   if (!(gamma > 0) || !isfinite(gamma)) return FFTPL_E_INVAL;
   if (accumulate != 0 && accumulate != 1) return FFTPL_E_INVAL;
@@ -299,16 +376,35 @@ int fftpl_wa_grad(int32_t num_nets, const int32_t* net_ptr, int32_t num_pins,
   if (e == hipSuccess && wa) e = launch_fill_f64(wa, 0.0, 1, s);
   if (e == hipSuccess && hpwl) e = launch_fill_f64(hpwl, 0.0, 1, s);
   if (e == hipSuccess)
-    e = launch_wa(num_nets, net_ptr, pin_cell, pin_dx, pin_dy, x, y, gamma, gx, gy, wa,
-                  hpwl, s);
+    e = launch_wa(num_nets, net_ptr, pin_cell, pin_dx, pin_dy, x, y, gamma, wl_model, gx, gy,
+                  wa, hpwl, s);
   return dev_status(e);
+}
+
+int fftpl_wa_grad(int32_t num_nets, const int32_t* net_ptr, int32_t num_pins,
+                  const int32_t* pin_cell, const float* pin_dx, const float* pin_dy,
+                  int32_t num_cells, const float* x, const float* y, float gamma,
+                  int32_t accumulate, float* gx, float* gy, double* wa, double* hpwl,
+                  void* stream) {
+  return wl_grad(FFTPL_WL_WA, num_nets, net_ptr, num_pins, pin_cell, pin_dx, pin_dy, num_cells,
+                 x, y, gamma, accumulate, gx, gy, wa, hpwl, stream);
+}
+
+int fftpl_lse_grad(int32_t num_nets, const int32_t* net_ptr, int32_t num_pins,
+                   const int32_t* pin_cell, const float* pin_dx, const float* pin_dy,
+                   int32_t num_cells, const float* x, const float* y, float gamma,
+                   int32_t accumulate, float* gx, float* gy, double* wa, double* hpwl,
+                   void* stream) {
+  return wl_grad(FFTPL_WL_LSE, num_nets, net_ptr, num_pins, pin_cell, pin_dx, pin_dy,
+                 num_cells, x, y, gamma, accumulate, gx, gy, wa, hpwl, stream);
 }
 
 int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
                const float* y, float lambda, float gamma, int32_t grad_mode, float* gx,
                float* gy, double* out4, void* stream) {
   if (!plan || !prob || !out4 || !grid_ok(&prob->grid)) return FFTPL_E_INVAL;
-  if (prob->reserved != 0 || prob->reserved2 != 0) return FFTPL_E_INVAL;
+  if (prob->wl_model != FFTPL_WL_WA && prob->wl_model != FFTPL_WL_LSE) return FFTPL_E_INVAL;
+  if (!(prob->screening >= 0.0f) || !isfinite(prob->screening)) return FFTPL_E_INVAL;
   if (prob->grid.n != plan->p.n) return FFTPL_E_STATE;
   const int m = prob->num_cells;
   if (m < 0 || prob->num_nets < 0 || prob->num_pins < 0) return FFTPL_E_INVAL;
@@ -391,7 +487,7 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
       plan_mark(p, "k_xch_spread", s);
       if (e == hipSuccess)
         e = launch_xch_wa(xd, X, prob->net_ptr, prob->pin_dx, prob->pin_dy, gamma,
-                          L.pin_grad, L.wa_part, s);
+                          prob->wl_model, L.pin_grad, L.wa_part, s);
       plan_mark(p, "k_xch_wa", s);
     } else {
       // interleave positions, per-pin WA gradients into cell-major slots
@@ -399,8 +495,8 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
       plan_mark(p, "k_interleave", s);
       if (e == hipSuccess)
         e = launch_wa_pins(prob->num_nets, prob->net_ptr, prob->pin_cell, prob->pin_dx,
-                           prob->pin_dy, L.xy, prob->pin_slot, gamma, L.pin_grad, L.wa_part,
-                           s, &p);
+                           prob->pin_dy, L.xy, prob->pin_slot, gamma, prob->wl_model,
+                           L.pin_grad, L.wa_part, s, &p);
     }
   } else {
     // 1. reset: rho = base, scalar accumulators = 0; 2. atomic scatter
@@ -426,6 +522,7 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
     a.cap = prob->cap;
     a.rho_t = g.rho_t;
     a.tau_part = p.partials + p.en_max;
+    a.eps = prob->screening;
     e = p.mode == FFTPL_DCT_FFT ? spectral_fft(p, a, ds) : spectral_gemm(p, a, ds);
   }
   // exchange path: each cell's density gradient, computed band by band from
@@ -487,7 +584,8 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
     plan_mark(p, "k_gather", s);
     if (e == hipSuccess)
       e = launch_wa(prob->num_nets, prob->net_ptr, prob->pin_cell, prob->pin_dx,
-                    prob->pin_dy, x, y, gamma, gx, gy, &out4[1], &out4[2], s);
+                    prob->pin_dy, x, y, gamma, prob->wl_model, gx, gy, &out4[1], &out4[2],
+                    s);
     plan_mark(p, "k_wa_atomic", s);
   }
   // 6. N, W~, HPWL, tau from the per-block partials (the atomic path added

@@ -408,12 +408,14 @@ __device__ __forceinline__ float fexp(float v) { return __expf(v); }
 // One net block: cell positions and pin offsets staged in LDS in CSR order,
 // nets evaluated from LDS, gradients written back over the pins' positions in
 // T.  LDS: pos[cap], off[cap] (dynamic, 16 bytes per pin of the block).
-template <int STAGE>
+// LSE: the log-sum-exp model in place of the weighted average (same sums;
+// the gradient is e+/S+ - e-/S-, the value (M - L) + gamma (ln S+ + ln S-)).
+template <int STAGE, bool LSE>
 __global__ void __launch_bounds__(NW)
     k_xch_wa(int num_pins, int cap, const int32_t* __restrict__ net_ptr,
              const int32_t* __restrict__ nb_net_ptr, const uint32_t* __restrict__ nmeta,
              const int32_t* __restrict__ a_of_b, const uint16_t* __restrict__ lcsr,
-             const float* __restrict__ pin_dx, const float* __restrict__ pin_dy,
+             const float* __restrict__ pin_dx, const float* __restrict__ pin_dy, float gamma,
              float inv_gamma, float2* __restrict__ T, double* __restrict__ part) {
   extern __shared__ float2 smem[];
   float2* pos = smem;
@@ -569,16 +571,22 @@ __global__ void __launch_bounds__(NW)
           if (l + u * kWave < b1) {
             const float dpx = c[u].x - mx, dmx = c[u].x - lx;
             const float dpy = c[u].y - my, dmy = c[u].y - ly;
-            pos[l + u * kWave] = make_float2(
-                fexp(dpx * inv_gamma) * rspx * (1.0f + (dpx - wpx) * inv_gamma) -
-                    fexp(-dmx * inv_gamma) * rsmx * (1.0f - (dmx - wmx) * inv_gamma),
-                fexp(dpy * inv_gamma) * rspy * (1.0f + (dpy - wpy) * inv_gamma) -
-                    fexp(-dmy * inv_gamma) * rsmy * (1.0f - (dmy - wmy) * inv_gamma));
+            if (LSE)
+              pos[l + u * kWave] = make_float2(
+                  fexp(dpx * inv_gamma) * rspx - fexp(-dmx * inv_gamma) * rsmx,
+                  fexp(dpy * inv_gamma) * rspy - fexp(-dmy * inv_gamma) * rsmy);
+            else
+              pos[l + u * kWave] = make_float2(
+                  fexp(dpx * inv_gamma) * rspx * (1.0f + (dpx - wpx) * inv_gamma) -
+                      fexp(-dmx * inv_gamma) * rsmx * (1.0f - (dmx - wmx) * inv_gamma),
+                  fexp(dpy * inv_gamma) * rspy * (1.0f + (dpy - wpy) * inv_gamma) -
+                      fexp(-dmy * inv_gamma) * rsmy * (1.0f - (dmy - wmy) * inv_gamma));
           }
         }
       }
       if (lane == 0) {
-        acc_wa += (double)((mx - lx) + wpx - wmx) + (double)((my - ly) + wpy - wmy);
+        acc_wa += net_wl_value<LSE>(mx, lx, wpx, wmx, spx, smx, gamma) +
+                  net_wl_value<LSE>(my, ly, wpy, wmy, spy, smy, gamma);
         acc_hp += (double)(mx - lx) + (double)(my - ly);
       }
     }
@@ -656,14 +664,19 @@ __global__ void __launch_bounds__(NW)
             if (j < wdeg && j < deg) {
               const float dpx = px[j] - mx, dmx = px[j] - lx;
               const float dpy = py[j] - my, dmy = py[j] - ly;
-              pos[l0 + j] = make_float2(
-                  epx[j] * rspx * (1.0f + (dpx - wpx) * inv_gamma) -
-                      emx[j] * rsmx * (1.0f - (dmx - wmx) * inv_gamma),
-                  epy[j] * rspy * (1.0f + (dpy - wpy) * inv_gamma) -
-                      emy[j] * rsmy * (1.0f - (dmy - wmy) * inv_gamma));
+              if (LSE)
+                pos[l0 + j] = make_float2(epx[j] * rspx - emx[j] * rsmx,
+                                          epy[j] * rspy - emy[j] * rsmy);
+              else
+                pos[l0 + j] = make_float2(
+                    epx[j] * rspx * (1.0f + (dpx - wpx) * inv_gamma) -
+                        emx[j] * rsmx * (1.0f - (dmx - wmx) * inv_gamma),
+                    epy[j] * rspy * (1.0f + (dpy - wpy) * inv_gamma) -
+                        emy[j] * rsmy * (1.0f - (dmy - wmy) * inv_gamma));
             }
           }
-          acc_wa += (double)((mx - lx) + wpx - wmx) + (double)((my - ly) + wpy - wmy);
+          acc_wa += net_wl_value<LSE>(mx, lx, wpx, wmx, spx, smx, gamma) +
+                    net_wl_value<LSE>(my, ly, wpy, wmy, spy, smy, gamma);
           acc_hp += (double)(mx - lx) + (double)(my - ly);
         }
       }
@@ -797,29 +810,38 @@ hipError_t launch_xch_spread(const XchDims& d, const XchIndex& X, const float* x
   return hipGetLastError();
 }
 
-hipError_t launch_xch_wa(const XchDims& d, const XchIndex& X, const int32_t* net_ptr,
-                         const float* pin_dx, const float* pin_dy, float gamma, float2* T,
-                         double* wa_part, hipStream_t s) {
+template <bool LSE>
+hipError_t launch_xch_wa_model(const XchDims& d, const XchIndex& X, const int32_t* net_ptr,
+                               const float* pin_dx, const float* pin_dy, float gamma, float2* T,
+                               double* wa_part, hipStream_t s) {
   const size_t lds = sizeof(float2) * 2 * (size_t)d.cap;
   if (d.cap <= kXchPinLds2) {
-    hipLaunchKernelGGL((k_xch_wa<kStageS>), dim3(d.nnb), dim3(NW), lds, s, d.num_pins, d.cap,
-                       net_ptr, X.nb_net_ptr, X.nmeta, X.a_of_b, X.lcsr, pin_dx, pin_dy,
-                       1.0f / gamma, T, wa_part);
+    hipLaunchKernelGGL((k_xch_wa<kStageS, LSE>), dim3(d.nnb), dim3(NW), lds, s, d.num_pins,
+                       d.cap, net_ptr, X.nb_net_ptr, X.nmeta, X.a_of_b, X.lcsr, pin_dx, pin_dy,
+                       gamma, 1.0f / gamma, T, wa_part);
   } else {
     // more than 64 KiB of dynamic LDS has to be allowed explicitly
     static bool attr = false;
     if (!attr) {
       hipError_t e = hipFuncSetAttribute(
-          reinterpret_cast<const void*>(&k_xch_wa<kStageL>),
+          reinterpret_cast<const void*>(&k_xch_wa<kStageL, LSE>),
           hipFuncAttributeMaxDynamicSharedMemorySize, (int)(sizeof(float2) * 2 * kXchPinCap));
       if (e != hipSuccess) return e;
       attr = true;
     }
-    hipLaunchKernelGGL((k_xch_wa<kStageL>), dim3(d.nnb), dim3(NW), lds, s, d.num_pins, d.cap,
-                       net_ptr, X.nb_net_ptr, X.nmeta, X.a_of_b, X.lcsr, pin_dx, pin_dy,
-                       1.0f / gamma, T, wa_part);
+    hipLaunchKernelGGL((k_xch_wa<kStageL, LSE>), dim3(d.nnb), dim3(NW), lds, s, d.num_pins,
+                       d.cap, net_ptr, X.nb_net_ptr, X.nmeta, X.a_of_b, X.lcsr, pin_dx, pin_dy,
+                       gamma, 1.0f / gamma, T, wa_part);
   }
   return hipGetLastError();
+}
+
+hipError_t launch_xch_wa(const XchDims& d, const XchIndex& X, const int32_t* net_ptr,
+                         const float* pin_dx, const float* pin_dy, float gamma, int wl_model,
+                         float2* T, double* wa_part, hipStream_t s) {
+  return wl_model == FFTPL_WL_LSE
+             ? launch_xch_wa_model<true>(d, X, net_ptr, pin_dx, pin_dy, gamma, T, wa_part, s)
+             : launch_xch_wa_model<false>(d, X, net_ptr, pin_dx, pin_dy, gamma, T, wa_part, s);
 }
 
 }  // namespace fftpl

@@ -198,6 +198,24 @@ __device__ __forceinline__ float axis_grad(float X, float M, float L, float wp, 
          expf(-dm * inv_gamma) * rsm * (1.0f - (dm - wm) * inv_gamma);
 }
 
+// The log-sum-exp model (Section II, the usual alternative to Eq. (3)) from
+// the same shifted sums: per net and axis LSE = (M - L) + gamma (ln S+ +
+// ln S-) and dLSE/dX = e+/S+ - e-/S-.  pin_wl_grad / net_wl_value pick the
+// model: LSE = false is the weighted average of Eq. (3).
+template <bool LSE>
+__device__ __forceinline__ float pin_wl_grad(float X, float M, float L, float wp, float wm,
+                                             float rsp, float rsm, float inv_gamma) {
+  if (LSE) return expf((X - M) * inv_gamma) * rsp - expf((L - X) * inv_gamma) * rsm;
+  return axis_grad(X, M, L, wp, wm, rsp, rsm, inv_gamma);
+}
+
+template <bool LSE>
+__device__ __forceinline__ double net_wl_value(float M, float L, float wp, float wm, float sp,
+                                               float sm, float gamma) {
+  if (LSE) return (double)(M - L) + (double)gamma * (log((double)sp) + log((double)sm));
+  return (double)((M - L) + wp - wm);
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
@@ -422,9 +440,10 @@ hipError_t launch_gather(const GridF& g, int m, const float* x, const float* y,
 hipError_t launch_cell_bins(const GridF& g, int m, const float* x, const float* y,
                             const float* w, const float* h, int32_t* ranges,
                             hipStream_t s);
+// wl_model: FFTPL_WL_WA (Eq. (3)) or FFTPL_WL_LSE (log-sum-exp)
 hipError_t launch_wa(int num_nets, const int32_t* net_ptr, const int32_t* pin_cell,
                      const float* pin_dx, const float* pin_dy, const float* x,
-                     const float* y, float gamma, float* gx, float* gy,
+                     const float* y, float gamma, int wl_model, float* gx, float* gy,
                      double* wa_out, double* hp_out, hipStream_t s);
 // wa: per-block wirelength partials laid out [W~ (n_s), HPWL (n_s), W~ (n_b),
 // HPWL (n_b)] (or null: W~ and HPWL are left as they are).
@@ -559,8 +578,9 @@ hipError_t launch_interleave(int m, const float* x, const float* y, float2* xy,
                              hipStream_t s);
 hipError_t launch_wa_pins(int num_nets, const int32_t* net_ptr, const int32_t* pin_cell,
                           const float* pin_dx, const float* pin_dy, const float2* xy,
-                          const int32_t* pin_slot, float gamma, float2* pin_grad,
-                          double* wa_part, hipStream_t s, Plan* tp = nullptr);
+                          const int32_t* pin_slot, float gamma, int wl_model,
+                          float2* pin_grad, double* wa_part, hipStream_t s,
+                          Plan* tp = nullptr);
 hipError_t launch_gather_pins(const GridF& g, int m, const float* x, const float* y,
                               const float* w, const float* h, const float* exy,
                               const float* psi, int grad_mode, float scale,
@@ -621,8 +641,8 @@ int xch_build(const XchDims& d, const int32_t* net_ptr, const int32_t* pin_cell,
 hipError_t launch_xch_spread(const XchDims& d, const XchIndex& X, const float* x,
                              const float* y, float2* T, hipStream_t s);
 hipError_t launch_xch_wa(const XchDims& d, const XchIndex& X, const int32_t* net_ptr,
-                         const float* pin_dx, const float* pin_dy, float gamma, float2* T,
-                         double* wa_part, hipStream_t s);
+                         const float* pin_dx, const float* pin_dy, float gamma, int wl_model,
+                         float2* T, double* wa_part, hipStream_t s);
 // gwa[c] = sum over cell c's pins of T[qa[j]] (after launch_xch_wa).
 // The per-cell part of the gradient after the wirelength: g = scale * the
 // density gradient (egrad at the cell's first-band entry, or computed from the
@@ -668,6 +688,8 @@ struct SpectralArgs {
   const float* cap = nullptr;
   float rho_t = 1.0f;
   double* tau_part = nullptr;
+  // screening eps >= 0 (bin^-2): every mode divides by w_u^2 + w_v^2 + eps
+  float eps = 0.0f;
   // difference mode: exy receives (Dx, Dy) = (psi(ix+1) - psi(ix), psi(iy+1) - psi(iy))
   // at every bin instead of (Ex, Ey); ex and ey must be null
   bool diff = false;

@@ -4,7 +4,7 @@
 // each one block per pair of rows (or columns), the 1-D transforms done in
 // LDS by the whole block:
 //   A  rows:    DCT-II along x of rho           -> bT[u][iy] (written transposed)
-//   B  columns: DCT-II along y, scale by c_u c_v / n^2 / (w_u^2 + w_v^2)
+//   B  columns: DCT-II along y, scale by c_u c_v / n^2 / (w_u^2 + w_v^2 + eps)
 //               (zero at (0,0): the DC is removed), then DCT-III along y
 //               (-> P) and the sine transform along y weighted by w_v (-> Q)
 //                                               -> P[iy][u], Q[iy][u]
@@ -368,7 +368,7 @@ __global__ void __launch_bounds__(FftShape<N>::NT)
     k_cols_solve(const float* __restrict__ bT, const double* __restrict__ rowsum,
                  float* __restrict__ P, float* __restrict__ Q,
                  const float2* __restrict__ tw_g, const float2* __restrict__ cs_g,
-                 const float* __restrict__ wf_g) {
+                 const float* __restrict__ wf_g, float eps) {
   constexpr int NT = FftShape<N>::NT;
   constexpr int PER = (N + NT - 1) / NT, PK = (N / 2 + NT) / NT;
   __shared__ float2 buf0[N];
@@ -421,10 +421,10 @@ __global__ void __launch_bounds__(FftShape<N>::NT)
     dct2_pair(buf0[k], buf0[kp], c, x1k, x2k, x1kp, x2kp);
     const float wk = wf[k], wkp = wf[kp];
     const float ck = (k == 0 ? 1.0f : 2.0f), ckp = (kp == 0 ? 1.0f : 2.0f);
-    float g1k = x1k * (f1 * ck) / (wu1 * wu1 + wk * wk);
-    float g1kp = x1kp * (f1 * ckp) / (wu1 * wu1 + wkp * wkp);
-    const float g2k = x2k * (f2 * ck) / (wu2 * wu2 + wk * wk);
-    const float g2kp = x2kp * (f2 * ckp) / (wu2 * wu2 + wkp * wkp);
+    float g1k = x1k * (f1 * ck) / (wu1 * wu1 + wk * wk + eps);
+    float g1kp = x1kp * (f1 * ckp) / (wu1 * wu1 + wkp * wkp + eps);
+    const float g2k = x2k * (f2 * ck) / (wu2 * wu2 + wk * wk + eps);
+    const float g2kp = x2kp * (f2 * ckp) / (wu2 * wu2 + wkp * wkp + eps);
     if (u1 == 0 && k == 0) g1k = 0.0f;   // a_00 := 0
     // P: DCT-III of G.  Q: DCT-III of Yb with Yb_k = w_{n-k} G_{n-k} (k >= 1),
     // Yb_0 = 0.  The two columns' P share one complex FFT and their Q another:
@@ -622,10 +622,10 @@ hipError_t run_fft(Plan& p, const SpectralArgs& a, hipStream_t s) {
   plan_mark(p, "k_rows_dct2", s);
   if (a.diff)
     hipLaunchKernelGGL((k_cols_solve<N, true>), grid, block, 0, s, p.tmp0, p.rowsum, p.tmp1,
-                       p.tmp2, p.fft_tw, p.dct_cs, p.wfreq);
+                       p.tmp2, p.fft_tw, p.dct_cs, p.wfreq, a.eps);
   else
     hipLaunchKernelGGL((k_cols_solve<N, false>), grid, block, 0, s, p.tmp0, p.rowsum, p.tmp1,
-                       p.tmp2, p.fft_tw, p.dct_cs, p.wfreq);
+                       p.tmp2, p.fft_tw, p.dct_cs, p.wfreq, a.eps);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   plan_mark(p, "k_cols_solve", s);
   if (a.diff)

@@ -4,7 +4,7 @@
 // Sw = diag(w) S and R = rho - mean(rho) (mean in double, so the large DC
 // never enters the float32 sums):
 //   W  = R K^T                         (along x)
-//   G  = scale(K W)                    (along y; c_u c_v / n^2 / (w_u^2+w_v^2),
+//   G  = scale(K W)                    (along y; c_u c_v / n^2 / (w_u^2+w_v^2+eps),
 //                                       zero at (0,0): the DC is removed)
 //   [U | V]     = G [K | Sw]           (inverse along x: cos for psi and Ey,
 //                                       frequency-weighted sine for Ex)
@@ -49,7 +49,8 @@ struct GemmArgs {
 
 struct Epi {
   int mode = EPI_F32;
-  int spectral = 0;   // scale element (row v, col u) by c_u c_v / (n^2 (w_u^2 + w_v^2))
+  int spectral = 0;   // scale element (row v, col u) by c_u c_v / (n^2 (w_u^2 + w_v^2 + eps))
+  float eps = 0.0f;
   int n = 0;
   const float* wf = nullptr;
   float* out = nullptr;
@@ -236,7 +237,7 @@ __global__ void __launch_bounds__(256 * KS) k_gemm(GemmArgs g, Epi ep) {
         if (ep.spectral) {
           const float wu = ep.wf[col], wv = ep.wf[row];
           const float cu = col ? 2.0f : 1.0f, cv = row ? 2.0f : 1.0f;
-          v = (row == 0 && col == 0) ? 0.0f : v * (cu * cv * inv_n2) / (wu * wu + wv * wv);
+          v = (row == 0 && col == 0) ? 0.0f : v * (cu * cv * inv_n2) / (wu * wu + wv * wv + ep.eps);
         }
         if (ep.mode == EPI_F32) {
           ep.out[(size_t)row * ep.ldo + col] = v;
@@ -458,6 +459,7 @@ hipError_t run_gemm_path(Plan& p, const SpectralArgs& a, hipStream_t s) {
   ep.n = n;
   ep.wf = p.wfreq;
   ep.spectral = 1;
+  ep.eps = a.eps;
   if (BF16) {
     g.a_hi = tb + L.b_kh; g.a_lo = tb + L.b_kl; g.lda = n;
     g.b_hi = wb + L.v_wth; g.b_lo = wb + L.v_wtl; g.ldb = n;

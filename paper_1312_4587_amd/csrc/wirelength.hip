@@ -1,5 +1,5 @@
 // Weighted-average wirelength (Eq. (3)) gradient and HPWL (Eq. (1)) over the
-// pin-net CSR.
+// pin-net CSR (or, on request, the log-sum-exp model named in Section II).
 //
 // For each net and axis with pin coordinates X_p = x[cell_p] + dx_p, M = max,
 // L = min, e+_p = exp((X_p - M)/gamma), e-_p = exp((L - X_p)/gamma):
@@ -52,11 +52,13 @@ struct PinIO {
   }
 };
 
-template <bool SLOTS, int PART>   // PART 0: nets of degree <= kSmallDeg; 1: larger nets
+// PART 0: nets of degree <= kSmallDeg; 1: larger nets.  LSE: the log-sum-exp
+// model instead of the weighted average (same sums, pin_wl_grad / net_wl_value).
+template <bool SLOTS, int PART, bool LSE>
 __global__ void __launch_bounds__(256)
     k_wa(int num_nets, const int32_t* __restrict__ net_ptr,
          const int32_t* __restrict__ pin_cell, const float* __restrict__ pin_dx,
-         const float* __restrict__ pin_dy, PinIO<SLOTS> io, float inv_gamma,
+         const float* __restrict__ pin_dy, PinIO<SLOTS> io, float gamma, float inv_gamma,
          double* __restrict__ wa_out, double* __restrict__ hp_out,
          double* __restrict__ part) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -107,11 +109,12 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
     for (int k = 0; k < kSmallDeg; ++k) {
       if (k < deg) {
-        io.put(p0 + k, cell[k], axis_grad(px[k], mx, lx, wpx, wmx, rspx, rsmx, inv_gamma),
-               axis_grad(py[k], my, ly, wpy, wmy, rspy, rsmy, inv_gamma));
+        io.put(p0 + k, cell[k], pin_wl_grad<LSE>(px[k], mx, lx, wpx, wmx, rspx, rsmx, inv_gamma),
+               pin_wl_grad<LSE>(py[k], my, ly, wpy, wmy, rspy, rsmy, inv_gamma));
       }
     }
-    acc_wa = (double)((mx - lx) + wpx - wmx) + (double)((my - ly) + wpy - wmy);
+    acc_wa = net_wl_value<LSE>(mx, lx, wpx, wmx, sx.sp, sx.sm, gamma) +
+             net_wl_value<LSE>(my, ly, wpy, wmy, sy.sp, sy.sm, gamma);
     acc_hp = (double)(mx - lx) + (double)(my - ly);
   } else if (SLOTS && PART == 0 && deg == 1) {
     io.put(p0, 0, 0.0f, 0.0f);   // a one-pin net has no wirelength: its slot holds zero
@@ -191,11 +194,12 @@ __global__ void __launch_bounds__(256)
       for (int j = 0; j < kBigRegs; ++j) {
         const int p = b0 + lane + kWave * j;
         if (p < b1)
-          io.put(p, cj[j], axis_grad(q[j].x, mx, lx, wpx, wmx, rspx, rsmx, inv_gamma),
-                 axis_grad(q[j].y, my, ly, wpy, wmy, rspy, rsmy, inv_gamma));
+          io.put(p, cj[j], pin_wl_grad<LSE>(q[j].x, mx, lx, wpx, wmx, rspx, rsmx, inv_gamma),
+                 pin_wl_grad<LSE>(q[j].y, my, ly, wpy, wmy, rspy, rsmy, inv_gamma));
       }
       if (lane == src) {
-        acc_wa += (double)((mx - lx) + wpx - wmx) + (double)((my - ly) + wpy - wmy);
+        acc_wa += net_wl_value<LSE>(mx, lx, wpx, wmx, sx.sp, sx.sm, gamma) +
+                  net_wl_value<LSE>(my, ly, wpy, wmy, sy.sp, sy.sm, gamma);
         acc_hp += (double)(mx - lx) + (double)(my - ly);
       }
       continue;
@@ -237,11 +241,12 @@ __global__ void __launch_bounds__(256)
       const int c = pin_cell[p];
       const float2 q = io.pos(c);
       const float X = (q.x - r.x) + pin_dx[p], Y = (q.y - r.y) + pin_dy[p];
-      io.put(p, c, axis_grad(X, mx, lx, wpx, wmx, rspx, rsmx, inv_gamma),
-             axis_grad(Y, my, ly, wpy, wmy, rspy, rsmy, inv_gamma));
+      io.put(p, c, pin_wl_grad<LSE>(X, mx, lx, wpx, wmx, rspx, rsmx, inv_gamma),
+             pin_wl_grad<LSE>(Y, my, ly, wpy, wmy, rspy, rsmy, inv_gamma));
     }
     if (lane == src) {
-      acc_wa += (double)((mx - lx) + wpx - wmx) + (double)((my - ly) + wpy - wmy);
+      acc_wa += net_wl_value<LSE>(mx, lx, wpx, wmx, sx.sp, sx.sm, gamma) +
+                net_wl_value<LSE>(my, ly, wpy, wmy, sy.sp, sy.sm, gamma);
       acc_hp += (double)(mx - lx) + (double)(my - ly);
     }
   }
@@ -256,41 +261,49 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+template <bool SLOTS, bool LSE>
+hipError_t launch_wa_parts(int num_nets, const int32_t* net_ptr, const int32_t* pin_cell,
+                           const float* pin_dx, const float* pin_dy, PinIO<SLOTS> io,
+                           float gamma, double* wa_out, double* hp_out, double* part,
+                           hipStream_t s, Plan* tp) {
+  const int nblk = (num_nets + 255) / 256;
+  hipLaunchKernelGGL((k_wa<SLOTS, 0, LSE>), dim3(nblk), dim3(256), 0, s, num_nets, net_ptr,
+                     pin_cell, pin_dx, pin_dy, io, gamma, 1.0f / gamma, wa_out, hp_out, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (tp) plan_mark(*tp, "k_wa_slots_small", s);
+  hipLaunchKernelGGL((k_wa<SLOTS, 1, LSE>), dim3(wa_big_grid(num_nets)), dim3(256), 0, s,
+                     num_nets, net_ptr, pin_cell, pin_dx, pin_dy, io, gamma, 1.0f / gamma,
+                     wa_out, hp_out, part ? part + 2 * (size_t)nblk : nullptr);
+  e = hipGetLastError();
+  if (tp) plan_mark(*tp, "k_wa_slots_big", s);
+  return e;
+}
+
 hipError_t launch_wa(int num_nets, const int32_t* net_ptr, const int32_t* pin_cell,
                      const float* pin_dx, const float* pin_dy, const float* x,
-                     const float* y, float gamma, float* gx, float* gy,
+                     const float* y, float gamma, int wl_model, float* gx, float* gy,
                      double* wa_out, double* hp_out, hipStream_t s) {
   if (num_nets <= 0) return hipSuccess;
   PinIO<false> io{x, y, nullptr, nullptr, gx, gy, nullptr};
-  const dim3 grid((num_nets + 255) / 256);
-  hipLaunchKernelGGL((k_wa<false, 0>), grid, dim3(256), 0, s, num_nets, net_ptr, pin_cell,
-                     pin_dx, pin_dy, io, 1.0f / gamma, wa_out, hp_out, nullptr);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_wa<false, 1>), dim3(wa_big_grid(num_nets)), dim3(256), 0, s, num_nets, net_ptr, pin_cell,
-                     pin_dx, pin_dy, io, 1.0f / gamma, wa_out, hp_out, nullptr);
-  return hipGetLastError();
+  return wl_model == FFTPL_WL_LSE
+             ? launch_wa_parts<false, true>(num_nets, net_ptr, pin_cell, pin_dx, pin_dy, io,
+                                            gamma, wa_out, hp_out, nullptr, s, nullptr)
+             : launch_wa_parts<false, false>(num_nets, net_ptr, pin_cell, pin_dx, pin_dy, io,
+                                             gamma, wa_out, hp_out, nullptr, s, nullptr);
 }
 
 hipError_t launch_wa_pins(int num_nets, const int32_t* net_ptr, const int32_t* pin_cell,
                           const float* pin_dx, const float* pin_dy, const float2* xy,
-                          const int32_t* pin_slot, float gamma, float2* pin_grad,
-                          double* wa_part, hipStream_t s, Plan* tp) {
+                          const int32_t* pin_slot, float gamma, int wl_model,
+                          float2* pin_grad, double* wa_part, hipStream_t s, Plan* tp) {
   if (num_nets <= 0) return hipSuccess;
   PinIO<true> io{nullptr, nullptr, xy, pin_slot, nullptr, nullptr, pin_grad};
-  const int nblk = (num_nets + 255) / 256;
-  const dim3 grid(nblk);
-  hipLaunchKernelGGL((k_wa<true, 0>), grid, dim3(256), 0, s, num_nets, net_ptr, pin_cell,
-                     pin_dx, pin_dy, io, 1.0f / gamma, nullptr, nullptr, wa_part);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  if (tp) plan_mark(*tp, "k_wa_slots_small", s);
-  hipLaunchKernelGGL((k_wa<true, 1>), dim3(wa_big_grid(num_nets)), dim3(256), 0, s, num_nets, net_ptr, pin_cell,
-                     pin_dx, pin_dy, io, 1.0f / gamma, nullptr, nullptr,
-                     wa_part + 2 * (size_t)nblk);
-  e = hipGetLastError();
-  if (tp) plan_mark(*tp, "k_wa_slots_big", s);
-  return e;
+  return wl_model == FFTPL_WL_LSE
+             ? launch_wa_parts<true, true>(num_nets, net_ptr, pin_cell, pin_dx, pin_dy, io,
+                                           gamma, nullptr, nullptr, wa_part, s, tp)
+             : launch_wa_parts<true, false>(num_nets, net_ptr, pin_cell, pin_dx, pin_dy, io,
+                                            gamma, nullptr, nullptr, wa_part, s, tp);
 }
 
 // The evaluation's scalars (FinalArgs) by one block, when no gather runs.

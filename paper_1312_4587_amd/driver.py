@@ -22,6 +22,15 @@ Schedules (Section IV-A):
   again after a few hundred iterations without the restart).
 The paper's inner solver is nonlinear CG; this loop uses Nesterov's method
 (the same gradient, no line search), so one evaluation per iteration.
+
+Fillers (Section III-B): with ``fillers=True`` disconnected movable cells
+are appended after the real ones so that movable plus filler area equals the
+capacity the fixed and dark nodes leave (rho_t times the whitespace).  They
+take part in the density and the update like any cell and have no pins; the
+overflow tau that drives gamma and the stop is that of the real cells alone
+(a second, scalars-only evaluation of the real cells per iteration).
+Irregular regions enter through their dark nodes (``fftpl.dark_nodes``)
+added to the instance's fixed rectangles.
 """
 from __future__ import annotations
 
@@ -61,6 +70,33 @@ def step_length(du2: float, dg2: float, gmax: float, alpha_min: float, alpha_max
     return min(alpha_max, max(alpha_min, math.sqrt(du2 / dg2) * gmax))
 
 
+def filler_cells(inst, cap_area: float, seed: int = 0):
+    """Fillers of Section III-B: total filler area = cap_area - the movable
+    cells' area, with cap_area the movable capacity of the region (bin area
+    times the sum of the capacity map, i.e. rho_t times the area the fixed
+    and dark nodes leave).  The paper does not size them; here each filler
+    has the mean width and the mean height of the movable cells, and they
+    start uniformly at random inside the region.  Returns float32 arrays
+    (x, y, w, h), empty when the movable cells already fill the capacity."""
+    w = np.asarray(inst.w, np.float64)
+    h = np.asarray(inst.h, np.float64)
+    empty = tuple(np.zeros(0, np.float32) for _ in range(4))
+    if w.size == 0:
+        return empty
+    need = float(cap_area) - float(np.sum(w * h))
+    fw, fh = float(np.mean(w)), float(np.mean(h))
+    count = int(math.floor(need / (fw * fh))) if need > 0 else 0
+    if count <= 0:
+        return empty
+    rng = np.random.default_rng(seed)
+    xl, yl = float(inst.xl), float(inst.yl)
+    sx, sy = inst.n * float(inst.bin_w), inst.n * float(inst.bin_h)
+    x = xl + 0.5 * fw + rng.random(count) * max(sx - fw, 0.0)
+    y = yl + 0.5 * fh + rng.random(count) * max(sy - fh, 0.0)
+    return (x.astype(np.float32), y.astype(np.float32),
+            np.full(count, fw, np.float32), np.full(count, fh, np.float32))
+
+
 @dataclasses.dataclass
 class Schedule:
     lam_mode: str = "double"         # "double" (every lam_every iterations) or "paper"
@@ -69,17 +105,37 @@ class Schedule:
     stop_tau: Optional[float] = None  # stop when tau <= stop_tau (the paper: 0.1)
     grad_mode: str = "field"
     restart_on_lambda: bool = True   # restart the momentum when lambda changes
+    wl_model: str = "wa"             # "wa" (Eq. (3)) or "lse"
+    screening: float = 0.0           # eps of the screened solve (0: Poisson)
 
 
 class Placer:
     """Nesterov global placement on one device.  ``inst`` gives the netlist,
-    sizes, fixed maps and starting positions."""
+    sizes, fixed maps and starting positions.  With ``fillers`` the cells
+    past ``num_real`` are fillers (``positions()`` returns the real ones)."""
 
     def __init__(self, inst, dct: str = "fft", schedule: Schedule = Schedule(),
-                 stream=None):
-        self.inst = inst
+                 stream=None, fillers: bool = False, filler_seed: int = 0):
         self.sched = schedule
-        self.prob = fftpl.Problem.from_instance(inst, stream=stream)
+        obj = dict(wl_model=schedule.wl_model, screening=schedule.screening)
+        self.num_real = inst.num_cells
+        self.prob_real = None
+        if fillers:
+            # the real cells alone (no nets): their capacity map sizes the
+            # fillers, and their scalars-only evaluation gives tau
+            bare = dataclasses.replace(
+                inst, net_ptr=np.zeros(1, np.int32), pin_cell=np.zeros(0, np.int32),
+                pin_dx=np.zeros(0, np.float32), pin_dy=np.zeros(0, np.float32))
+            self.prob_real = fftpl.Problem.from_instance(bare, stream=stream, **obj)
+            cap = self.prob_real.arrays["cap"]
+            cap_area = float(cap.double().sum()) * float(inst.bin_w) * float(inst.bin_h)
+            fx, fy, fw, fh = filler_cells(inst, cap_area, filler_seed)
+            inst = dataclasses.replace(
+                inst, x=np.concatenate([inst.x, fx]), y=np.concatenate([inst.y, fy]),
+                w=np.concatenate([inst.w, fw]), h=np.concatenate([inst.h, fh]))
+        self.inst = inst
+        self.num_fillers = inst.num_cells - self.num_real
+        self.prob = fftpl.Problem.from_instance(inst, stream=stream, **obj)
         self.plan = fftpl.Plan(inst.n, dct)
         self.region = fftpl.Grid.of(inst)
         m = inst.num_cells
@@ -91,7 +147,8 @@ class Placer:
         self.upx, self.upy = torch.zeros(m, **f32), torch.zeros(m, **f32)
         self.gpx, self.gpy = torch.zeros(m, **f32), torch.zeros(m, **f32)
         self.gx, self.gy = torch.empty(m, **f32), torch.empty(m, **f32)
-        self.scal = torch.zeros(8, dtype=torch.float64, device=dev)   # out4 | stats
+        # out4 | step statistics | real cells' out4 (fillers only)
+        self.scal = torch.zeros(12, dtype=torch.float64, device=dev)
         self.work = torch.empty(1024, dtype=torch.float64, device=dev)
         self.k = 0
         self.a = 1.0
@@ -108,6 +165,16 @@ class Placer:
     def _eval(self, lam: float, gamma: float, gx=None, gy=None):
         fftpl.eval(self.plan, self.prob, self.ux, self.uy, lam, gamma, self.sched.grad_mode,
                    self.gx if gx is None else gx, self.gy if gy is None else gy, self.scal[:4])
+        if self.prob_real is not None:
+            r = self.num_real
+            fftpl.eval(self.plan, self.prob_real, self.ux[:r], self.uy[:r], lam, gamma,
+                       self.sched.grad_mode, None, None, self.scal[8:12])
+
+    def positions(self):
+        """Current centres of the real cells (fillers dropped), on the host."""
+        torch.cuda.synchronize()
+        r = self.num_real
+        return self.x[:r].cpu().numpy(), self.y[:r].cpu().numpy()
 
     def _stats(self, first: bool):
         lib = _lib.load()
@@ -149,8 +216,10 @@ class Placer:
         first = self.k == 0
         self._eval(self.lam, self.gamma)
         self._stats(first)
-        s = self.scal.cpu().numpy()        # one 64-byte read per iteration
-        N, W, H, tau, du2, dg2, gmax, _ = (float(v) for v in s)
+        s = self.scal.cpu().numpy()        # one small read per iteration
+        N, W, H, tau, du2, dg2, gmax, _ = (float(v) for v in s[:8])
+        if self.prob_real is not None:
+            tau = float(s[11])             # the real cells' overflow
         if on_eval is not None:
             on_eval(self)
         alpha = step_length(du2, dg2, gmax, self.alpha_min, self.alpha_max, first)

@@ -20,6 +20,7 @@ from . import _lib
 OK, E_INVAL, E_NOMEM, E_DEVICE, E_UNSUPPORTED, E_STATE = 0, -1, -2, -3, -4, -5
 DCT_MODES = {"fft": 0, "gemm_f32": 1, "gemm_bf16x3": 2}
 GRAD_MODES = {"field": 0, "exact": 1}
+WL_MODELS = {"wa": 0, "lse": 1}
 
 
 class FFTPLError(RuntimeError):
@@ -168,6 +169,26 @@ def fixed_map(grid: Grid, fx, fy, fw, fh, base, cap=None, stream=None):
         _ptr(cap, torch.float32, n2, "cap"), _stream(stream)), "fftpl_fixed_map")
 
 
+def dark_nodes(xl: float, yl: float, xh: float, yh: float, rects) -> np.ndarray:
+    """fftpl_dark_nodes on host arrays: the bounding box minus the union of
+    the placeable rectangles ``rects`` [k, 4] (x0, y0, x1, y1), returned as
+    disjoint rectangles [j, 4] in the same layout."""
+    r = np.ascontiguousarray(np.asarray(rects, np.float64).reshape(-1, 4))
+    lib = _lib.load()
+    cap = 2 * len(r) + 2
+    while True:
+        out = np.zeros((cap, 4), np.float64)
+        cnt = ctypes.c_int32(0)
+        st = lib.fftpl_dark_nodes(float(xl), float(yl), float(xh), float(yh), len(r),
+                                  r.ctypes.data if len(r) else None, cap, out.ctypes.data,
+                                  ctypes.byref(cnt))
+        if st == E_INVAL and cnt.value > cap:
+            cap = cnt.value
+            continue
+        _check(st, "fftpl_dark_nodes")
+        return out[:cnt.value].copy()
+
+
 def density_map(grid: Grid, x, y, w, h, base, rho, stream=None):
     m = int(x.numel())
     n2 = grid.n * grid.n
@@ -188,6 +209,16 @@ def poisson_solve(plan: Plan, grid: Grid, rho, psi, ex=None, ey=None, energy=Non
         _stream(stream)), "fftpl_poisson_solve")
 
 
+def helmholtz_solve(plan: Plan, grid: Grid, eps, rho, psi, ex=None, ey=None, energy=None,
+                    stream=None):
+    n2 = grid.n * grid.n
+    _check(_lib.load().fftpl_helmholtz_solve(
+        plan.handle, ctypes.byref(grid.c()), float(eps), _ptr(rho, torch.float32, n2, "rho"),
+        _ptr(psi, torch.float32, n2, "psi"), _ptr(ex, torch.float32, n2, "ex"),
+        _ptr(ey, torch.float32, n2, "ey"), _ptr(energy, torch.float64, 1, "energy"),
+        _stream(stream)), "fftpl_helmholtz_solve")
+
+
 def field_gather(grid: Grid, x, y, w, h, ex, ey, psi, grad_mode, scale, accumulate,
                  gx, gy, stream=None):
     m = int(x.numel())
@@ -202,19 +233,31 @@ def field_gather(grid: Grid, x, y, w, h, ex, ey, psi, grad_mode, scale, accumula
         _stream(stream)), "fftpl_field_gather")
 
 
-def wa_grad(net_ptr, pin_cell, pin_dx, pin_dy, x, y, gamma, accumulate, gx, gy,
-            wa=None, hpwl=None, stream=None):
+def _wl_grad(name, net_ptr, pin_cell, pin_dx, pin_dy, x, y, gamma, accumulate, gx, gy,
+             wa, hpwl, stream):
     E = int(net_ptr.numel()) - 1
     P = int(pin_cell.numel())
     m = int(x.numel())
-    _check(_lib.load().fftpl_wa_grad(
+    _check(getattr(_lib.load(), name)(
         E, _ptr(net_ptr, torch.int32, E + 1, "net_ptr"), P,
         _ptr(pin_cell, torch.int32, P, "pin_cell"), _ptr(pin_dx, torch.float32, P, "pin_dx"),
         _ptr(pin_dy, torch.float32, P, "pin_dy"), m, _ptr(x, torch.float32, m, "x"),
         _ptr(y, torch.float32, m, "y"), float(gamma), int(accumulate),
         _ptr(gx, torch.float32, m, "gx"), _ptr(gy, torch.float32, m, "gy"),
         _ptr(wa, torch.float64, 1, "wa"), _ptr(hpwl, torch.float64, 1, "hpwl"),
-        _stream(stream)), "fftpl_wa_grad")
+        _stream(stream)), name)
+
+
+def wa_grad(net_ptr, pin_cell, pin_dx, pin_dy, x, y, gamma, accumulate, gx, gy,
+            wa=None, hpwl=None, stream=None):
+    _wl_grad("fftpl_wa_grad", net_ptr, pin_cell, pin_dx, pin_dy, x, y, gamma, accumulate,
+             gx, gy, wa, hpwl, stream)
+
+
+def lse_grad(net_ptr, pin_cell, pin_dx, pin_dy, x, y, gamma, accumulate, gx, gy,
+             lse=None, hpwl=None, stream=None):
+    _wl_grad("fftpl_lse_grad", net_ptr, pin_cell, pin_dx, pin_dy, x, y, gamma, accumulate,
+             gx, gy, lse, hpwl, stream)
 
 
 def problem_work_bytes(n: int, num_cells: int, num_nets: int, num_pins: int) -> int:
@@ -276,10 +319,15 @@ class Problem:
     ``path`` selects the evaluation path by what is built here:
     "xch" (default): the exchange index and the evaluation workspace;
     "slots": the cell-major pin slots and the workspace;
-    "atomic": nothing (float atomics for the scatter and the wirelength)."""
+    "atomic": nothing (float atomics for the scatter and the wirelength).
+
+    ``wl_model`` ("wa" or "lse") and ``screening`` (eps >= 0 of the
+    screened solve) choose the objective; ``set_objective`` changes them
+    later without rebuilding anything."""
 
     def __init__(self, grid: Grid, w, h, net_ptr, pin_cell, pin_dx, pin_dy,
-                 base=None, cap=None, path="xch", stream=None, max_degree=None):
+                 base=None, cap=None, path="xch", stream=None, max_degree=None,
+                 wl_model="wa", screening=0.0):
         if path not in PATHS:
             raise ValueError(f"path must be one of {PATHS}")
         self.grid = grid
@@ -311,7 +359,7 @@ class Problem:
                            pin_dx=pin_dx, pin_dy=pin_dy, base=base, cap=cap,
                            cell_ptr=cell_ptr, pin_slot=pin_slot, work=work, xindex=xindex)
         self.c = _lib.fftpl_problem(
-            grid.c(), m, E, P, 0,
+            grid.c(), m, E, P, WL_MODELS.get(wl_model, wl_model),
             _ptr(w, torch.float32, m, "w"), _ptr(h, torch.float32, m, "h"),
             _ptr(base, torch.float32, n2, "base"), _ptr(cap, torch.float32, n2, "cap"),
             _ptr(net_ptr, torch.int32, E + 1, "net_ptr"),
@@ -320,14 +368,22 @@ class Problem:
             _ptr(cell_ptr, torch.int32, None, "cell_ptr"),
             _ptr(pin_slot, torch.int32, None, "pin_slot"),
             _ptr(work, torch.uint8, None, "work"), work_bytes,
-            _ptr(xindex, torch.uint8, None, "xindex"), xbytes, self.max_degree, 0)
+            _ptr(xindex, torch.uint8, None, "xindex"), xbytes, self.max_degree,
+            float(screening))
+
+    def set_objective(self, wl_model=None, screening=None) -> None:
+        if wl_model is not None:
+            self.c.wl_model = WL_MODELS.get(wl_model, wl_model)
+        if screening is not None:
+            self.c.screening = float(screening)
 
     @property
     def fast(self) -> bool:
         return self.path != "atomic"
 
     @classmethod
-    def from_instance(cls, inst, device="cuda", stream=None, path="xch") -> "Problem":
+    def from_instance(cls, inst, device="cuda", stream=None, path="xch", wl_model="wa",
+                      screening=0.0) -> "Problem":
         """Upload an instance's static arrays and rasterise its fixed maps."""
         def t(a, dt):
             return torch.as_tensor(a, dtype=dt).to(device).contiguous()
@@ -344,7 +400,8 @@ class Problem:
                    t(inst.net_ptr, torch.int32), t(inst.pin_cell, torch.int32),
                    t(inst.pin_dx, torch.float32), t(inst.pin_dy, torch.float32),
                    base=base, cap=cap, path=path, stream=stream,
-                   max_degree=int(np.diff(inst.net_ptr).max()) if inst.num_nets else 0)
+                   max_degree=int(np.diff(inst.net_ptr).max()) if inst.num_nets else 0,
+                   wl_model=wl_model, screening=screening)
 
 
 def eval(plan: Plan, prob: Problem, x, y, lam, gamma, grad_mode, gx, gy, out4,

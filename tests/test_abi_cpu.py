@@ -94,6 +94,13 @@ def test_argument_errors_are_reported_before_any_device_work():
                              None) == -1
     assert lib.fftpl_wa_grad(3, p, 6, p, p, p, 0, None, None, 1.0, 0, None, None, None,
                              None, None) == -1
+    for gam in (0.0, -1.0, float("inf"), float("nan")):
+        assert lib.fftpl_lse_grad(3, p, 6, p, p, p, 4, p, p, gam, 0, p, p, None, None,
+                                  None) == -1
+    assert lib.fftpl_lse_grad(3, p, 6, p, p, p, 4, p, p, 1.0, 3, p, p, None, None,
+                              None) == -1
+    assert lib.fftpl_helmholtz_solve(None, ctypes.byref(g), 0.5, p, p, None, None, None,
+                                     None) == -1
     assert lib.fftpl_eval(None, None, p, p, 1.0, 1.0, 0, p, p, p, None) == -1
     assert lib.fftpl_poisson_solve(None, ctypes.byref(g), p, p, None, None, None,
                                    None) == -1

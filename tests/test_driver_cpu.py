@@ -1,5 +1,8 @@
-"""Host-side schedules of the placement loop (Section IV-A formulas)."""
+"""Host-side logic of the placement loop: the Section IV-A schedule formulas
+and the filler sizing of Section III-B."""
 import math
+
+import numpy as np
 
 import pytest
 
@@ -38,3 +41,23 @@ def test_step_length_bounds():
     assert step_length(1.0, 4.0, 3.0, 0.01, 1.0, first=False) == 1.0
     assert step_length(1e-8, 4.0, 3.0, 0.01, 1.0, first=False) == 0.01
     assert step_length(1.0, 0.0, 3.0, 0.01, 1.0, first=False) == 1.0
+
+
+def test_filler_cells_fill_the_capacity():
+    import gen
+    from paper_1312_4587_amd import driver
+    inst = gen.make_instance(3, num_cells=5000, util=0.6, n=64, num_nets=10)
+    side = inst.n * inst.bin_w
+    cap_area = 0.9 * side * side
+    x, y, w, h = driver.filler_cells(inst, cap_area, seed=1)
+    mov = float(np.sum(inst.w.astype(np.float64) * inst.h))
+    fa = float(np.sum(w.astype(np.float64) * h))
+    assert len(x) > 0
+    assert np.all(w == np.float32(np.mean(inst.w))) and np.all(h == np.float32(np.mean(inst.h)))
+    # movable + filler area reaches the capacity to within one filler
+    assert 0 <= cap_area - mov - fa < w[0] * h[0] * 1.001
+    assert np.all(x - w / 2 >= inst.xl) and np.all(x + w / 2 <= inst.xl + side + 1e-3)
+    assert np.all(y - h / 2 >= inst.yl) and np.all(y + h / 2 <= inst.yl + side + 1e-3)
+    # already full: no fillers; same seed: same fillers
+    assert len(driver.filler_cells(inst, 0.5 * mov, seed=1)[0]) == 0
+    assert np.array_equal(driver.filler_cells(inst, cap_area, seed=1)[0], x)

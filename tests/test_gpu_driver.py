@@ -139,3 +139,104 @@ def test_checkpoint_and_resume(F, tmp_path):
         say("one step after resume", name, rel_l2(r21[name], s21[name]))
         assert rel_l2(r21[name], s21[name]) < 1e-6
     assert np.allclose(r21["history"], s21["history"], rtol=1e-6, atol=0.0)
+
+
+def test_fillers_and_irregular_region(F):
+    # an L-shaped region: the box's top-right quadrant is not placeable (one
+    # dark node, charged like a fixed node); fillers fill the capacity left.
+    # Cells start uniformly over the whole box.  Checked: the dark node's
+    # fixed map, per-evaluation parity of the full (real + filler) evaluation
+    # and of the real cells' overflow against the oracle, and that the density
+    # force empties the dark quadrant.
+    import dataclasses
+    fftpl, driver, _ = F
+    inst = gen.make_instance(21, num_cells=30_000, util=0.5, n=128, num_nets=32_000)
+    side = inst.n * inst.bin_w
+    xl, yl = inst.xl, inst.yl
+    half = 0.5 * side
+    d = fftpl.dark_nodes(xl, yl, xl + side, yl + side,
+                         [[xl, yl, xl + side, yl + half], [xl, yl + half, xl + half, yl + side]])
+    assert d.shape == (1, 4)
+    mac = np.stack([(d[:, 0] + d[:, 2]) / 2, (d[:, 1] + d[:, 3]) / 2, d[:, 2] - d[:, 0],
+                    d[:, 3] - d[:, 1]], axis=1).astype(np.float32)
+    inst = dataclasses.replace(inst, fx=mac[:, 0], fy=mac[:, 1], fw=mac[:, 2], fh=mac[:, 3])
+    pl = driver.Placer(inst, fillers=True, filler_seed=5)
+    m, nf = pl.num_real, pl.num_fillers
+    cap_area = float(host(pl.prob_real.arrays["cap"]).astype(np.float64).sum()) * inst.bin_w ** 2
+    filler_area = nf * float(np.mean(inst.w)) * float(np.mean(inst.h))
+    say("fillers", nf, "cap area", cap_area, "movable", float(np.sum(inst.w * inst.h)))
+    assert nf > 0
+    assert 0 <= cap_area - float(np.sum(inst.w * inst.h)) - filler_area < np.mean(inst.w)
+    # the dark quadrant carries rho_t and leaves no capacity
+    base = host(pl.prob.arrays["base"]).reshape(inst.n, inst.n)
+    h2 = inst.n // 2
+    assert np.max(np.abs(base[h2:, h2:] - 1.0)) < 1e-4
+    assert np.max(np.abs(base[:h2])) < 1e-4 and np.max(np.abs(base[:, :h2])) < 1e-4
+
+    def dark_area(x, y):
+        sel = (x > xl + half) & (y > yl + half)
+        return float(np.sum(inst.w[sel] * inst.h[sel]))
+    a0 = dark_area(inst.x, inst.y)
+    snaps = {}
+
+    def grab(p):
+        if p.k in (0, 150):
+            snaps[p.k] = dict(x=host(p.ux), y=host(p.uy), gx=host(p.gx), gy=host(p.gy),
+                              s=host(p.scal).copy(), lam=p.lam, gamma=p.gamma)
+    hist = pl.run(400, on_eval=grab)
+    x, y = pl.positions()
+    a1 = dark_area(x, y)
+    say("dark-quadrant cell area", a0, "->", a1, "tau", hist[0]["tau"], "->", hist[-1]["tau"])
+    assert a1 < 0.5 * a0
+    assert hist[-1]["tau"] < hist[0]["tau"]
+    whole = pl.inst
+    for k, sn in sorted(snaps.items()):
+        ik = whole.with_positions(sn["x"], sn["y"])
+        ref = oracle.evaluate(ik, lam=sn["lam"], gamma=sn["gamma"], grad_mode="field")
+        e = rel_l2(np.concatenate([sn["gx"], sn["gy"]]), np.concatenate([ref["gx"], ref["gy"]]))
+        real = dataclasses.replace(inst.with_positions(sn["x"][:m], sn["y"][:m]),
+                                   net_ptr=np.zeros(1, np.int32), pin_cell=np.zeros(0, np.int32),
+                                   pin_dx=np.zeros(0, np.float32), pin_dy=np.zeros(0, np.float32))
+        rref = oracle.evaluate(real, lam=sn["lam"], gamma=sn["gamma"], grad_mode="field")
+        say("k", k, "grad rel-L2", e, "tau all / real", sn["s"][3], ref["overflow"], sn["s"][11],
+            rref["overflow"])
+        assert e < RTOL
+        assert abs(sn["s"][0] - ref["energy"]) <= RTOL * abs(ref["energy"])
+        assert abs(sn["s"][3] - ref["overflow"]) <= RTOL
+        assert abs(sn["s"][8] - rref["energy"]) <= RTOL * abs(rref["energy"])
+        assert abs(sn["s"][11] - rref["overflow"]) <= RTOL
+        assert sn["s"][9] == 0.0 and sn["s"][10] == 0.0      # no nets among the real-only cells
+    pl.close()
+
+
+@pytest.mark.parametrize("wl,eps", [("lse", 0.0), ("wa", 0.1)])
+def test_placement_with_objective_variants(F, wl, eps):
+    # the loop with the log-sum-exp model or the screened solve: parity of
+    # the evaluation at a sampled iteration, and a falling wirelength (the
+    # random start is already spread out: a screened, short-range density
+    # force lets the overflow rise while the wirelength shrinks)
+    fftpl, driver, _ = F
+    inst = gen.make_instance(22, num_cells=20_000, util=0.7, n=128, num_nets=21_000)
+    pl = driver.Placer(inst, schedule=driver.Schedule(wl_model=wl, screening=eps))
+    snap = {}
+
+    def grab(p):
+        if p.k == 60:
+            snap.update(x=host(p.ux), y=host(p.uy), gx=host(p.gx), gy=host(p.gy),
+                        s=host(p.scal)[:4].copy(), lam=p.lam, gamma=p.gamma)
+    hist = pl.run(200, on_eval=grab)
+    say(wl, eps, "tau", hist[0]["tau"], "->", hist[-1]["tau"], "hpwl", hist[0]["hpwl"], "->",
+        hist[-1]["hpwl"])
+    ik = inst.with_positions(snap["x"], snap["y"])
+    ref = oracle.evaluate(ik, lam=snap["lam"], gamma=snap["gamma"], grad_mode="field",
+                          wl_model=wl, eps=eps)
+    e = rel_l2(np.concatenate([snap["gx"], snap["gy"]]), np.concatenate([ref["gx"], ref["gy"]]))
+    say("grad rel-L2", e)
+    assert e < RTOL
+    assert abs(snap["s"][0] - ref["energy"]) <= RTOL * abs(ref["energy"])
+    assert abs(snap["s"][1] - ref["wa"]) <= RTOL * abs(ref["wa"])
+    # (a screened solve spreads cells less: with eps = 0.1 bin^-2 the
+    # wirelength falls by only ~10% over these iterations)
+    assert all(np.isfinite(h["hpwl"]) for h in hist)
+    assert hist[-1]["hpwl"] < hist[0]["hpwl"] and hist[-1]["tau"] < 0.5
+    pl.close()

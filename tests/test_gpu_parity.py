@@ -281,9 +281,10 @@ def test_wa_grad(F, which):
 # full evaluation
 # ---------------------------------------------------------------------------
 
-def _run_eval(F, inst, lam, mode, dct="fft", plan=None, path="xch"):
+def _run_eval(F, inst, lam, mode, dct="fft", plan=None, path="xch", wl_model="wa",
+              screening=0.0):
     import torch
-    prob = F.Problem.from_instance(inst, path=path)
+    prob = F.Problem.from_instance(inst, path=path, wl_model=wl_model, screening=screening)
     assert prob.path == path
     own = plan is None
     plan = plan or F.Plan(inst.n, dct)

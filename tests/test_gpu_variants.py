@@ -1,0 +1,169 @@
+"""GPU parity of the objective's variants against the FP64 oracle: the
+screened (Helmholtz) solve of Eq. (4) and the log-sum-exp wirelength named
+in Section II, through their own entry points and inside fftpl_eval on
+every evaluation path.  Same bar as the paper's form: relative L2 <= 1e-5
+in float32."""
+import numpy as np
+import pytest
+
+import gen
+import oracle
+from _helpers import rel_l2, with_macros
+from gpu_common import RTOL, DeviceCells, dev, host, lib_or_build, say
+from test_gpu_parity import BF16X3_SANITY, _check_eval, _run_eval, _wa_case
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def F():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    lib_or_build()
+    from paper_1312_4587_amd import fftpl
+    return fftpl
+
+
+def _hsolve(F, n, rho, eps, mode="fft"):
+    import torch
+    grid = F.Grid(n, 0.0, 0.0, 1.0, 1.0)
+    plan = F.Plan(n, mode)
+    r = dev(rho.astype(np.float32).ravel())
+    psi, ex, ey = (torch.empty(n * n, device="cuda") for _ in range(3))
+    en = torch.empty(1, dtype=torch.float64, device="cuda")
+    F.helmholtz_solve(plan, grid, eps, r, psi, ex, ey, en)
+    out = [host(t).reshape(n, n) for t in (psi, ex, ey)] + [float(host(en)[0])]
+    plan.close()
+    return out
+
+
+@pytest.mark.parametrize("mode,n", [("fft", 16), ("fft", 256), ("fft", 1024),
+                                    ("gemm_f32", 256), ("gemm_bf16x3", 256)])
+@pytest.mark.parametrize("eps", [0.01, 1.0])
+def test_helmholtz_solve_random_density(F, mode, n, eps):
+    rng = np.random.default_rng(300 + n)
+    rho = (0.9 + 0.4 * rng.standard_normal((n, n))).astype(np.float32)
+    say("helmholtz", mode, n, eps)
+    psi, ex, ey, en = _hsolve(F, n, rho, eps, mode)
+    psi0, ex0, ey0, _ = oracle.poisson_solve(rho.astype(np.float64), eps)
+    e0 = oracle.energy(rho.astype(np.float64), psi0)
+    errs = (rel_l2(psi, psi0), rel_l2(ex, ex0), rel_l2(ey, ey0), abs(en - e0) / abs(e0))
+    say("errors psi/ex/ey/N", *errs)
+    assert max(errs) < (BF16X3_SANITY if mode == "gemm_bf16x3" else RTOL)
+
+
+def test_helmholtz_single_mode_and_zero_eps(F):
+    n, u, v, eps = 256, 17, 200, 0.3
+    x = np.arange(n) + 0.5
+    wu, wv = np.pi * u / n, np.pi * v / n
+    rho = np.outer(np.cos(wv * x), np.cos(wu * x)).astype(np.float32) + np.float32(0.75)
+    psi, ex, ey, _ = _hsolve(F, n, rho, eps)
+    d = wu * wu + wv * wv + eps
+    mode = (rho - np.float32(0.75)).astype(np.float64)
+    assert rel_l2(psi, mode / d) < RTOL
+    assert rel_l2(ex, wu / d * np.outer(np.cos(wv * x), np.sin(wu * x))) < RTOL
+    # eps = 0 through the screened entry point is the Poisson solve itself, bit for bit
+    import torch
+    grid = F.Grid(n, 0.0, 0.0, 1.0, 1.0)
+    plan = F.Plan(n)
+    r = dev(rho.ravel())
+    a = [torch.empty(n * n, device="cuda") for _ in range(3)]
+    b = [torch.empty(n * n, device="cuda") for _ in range(3)]
+    F.helmholtz_solve(plan, grid, 0.0, r, *a)
+    F.poisson_solve(plan, grid, r, *b)
+    for ta, tb in zip(a, b):
+        assert torch.equal(ta, tb)
+    with pytest.raises(F.FFTPLError):
+        F.helmholtz_solve(plan, grid, -1.0, r, *a)
+    plan.close()
+
+
+@pytest.mark.parametrize("which", ["small_2k", "hi_degree", "degenerate"])
+def test_lse_grad(F, which):
+    import torch
+    inst = _wa_case(which)
+    say("lse", which, inst.num_nets, inst.num_pins)
+    c = DeviceCells(inst)
+    m = inst.num_cells
+    gx = torch.full((m,), 11.0, device="cuda")
+    gy = torch.full((m,), 11.0, device="cuda")
+    v = torch.zeros(1, dtype=torch.float64, device="cuda")
+    hp = torch.zeros(1, dtype=torch.float64, device="cuda")
+    args = (dev(inst.net_ptr), dev(inst.pin_cell), dev(inst.pin_dx), dev(inst.pin_dy),
+            c.x, c.y, inst.gamma)
+    F.lse_grad(*args, 0, gx, gy, v, hp)
+    L0, rx, ry = oracle.lse_wirelength(inst)
+    H0 = oracle.hpwl(inst)
+    say("errors gx/gy/LSE", rel_l2(host(gx), rx), rel_l2(host(gy), ry),
+        abs(float(host(v)[0]) - L0) / L0)
+    assert rel_l2(host(gx), rx) < RTOL and rel_l2(host(gy), ry) < RTOL
+    assert abs(float(host(v)[0]) - L0) <= RTOL * L0
+    assert abs(float(host(hp)[0]) - H0) <= RTOL * H0
+    F.lse_grad(*args, 1, gx, gy, None, None)
+    assert rel_l2(host(gx), 2 * rx) < RTOL
+
+
+@pytest.mark.parametrize("path", ["xch", "slots", "atomic"])
+@pytest.mark.parametrize("mode", ["field", "exact"])
+def test_eval_lse_screened_small(F, mode, path):
+    inst = gen.make_config("small_2k")
+    inst = with_macros(inst, [[30.0, 30.0, 10.0, 8.0], [60.0, 20.0, 5.0, 12.0]])
+    lam, eps = 3.0, 0.05
+    say("eval lse screened", mode, path)
+    got = _run_eval(F, inst, lam, mode, path=path, wl_model="lse", screening=eps)
+    ref = oracle.evaluate(inst, lam=lam, grad_mode=mode, wl_model="lse", eps=eps)
+    _check_eval(inst, got, ref, lam, mode)
+
+
+@pytest.mark.parametrize("wl,eps", [("lse", 0.0), ("wa", 0.2), ("lse", 0.2)])
+def test_eval_variants_exchange_many_blocks(F, wl, eps):
+    # 15 cell blocks (the last ragged), nets up to degree 3000 (net blocks
+    # below their default size, wavefront-wide nets, more large nets than a
+    # block stages extents for)
+    inst = gen.make_instance(7, num_cells=60_000, util=0.8, n=256, num_nets=70_000,
+                             hi_frac=0.01, hi_range=(20, 3000), num_macros=5,
+                             macro_area_frac=0.1)
+    say("variants many blocks", wl, eps)
+    got = _run_eval(F, inst, 2.0, "field", wl_model=wl, screening=eps)
+    ref = oracle.evaluate(inst, lam=2.0, grad_mode="field", wl_model=wl, eps=eps)
+    _check_eval(inst, got, ref, 2.0, "field")
+
+
+def test_eval_variants_gemm_and_bad_objective(F):
+    inst = gen.make_config("small_2k")
+    got = _run_eval(F, inst, 2.0, "exact", dct="gemm_f32", wl_model="lse", screening=0.5)
+    ref = oracle.evaluate(inst, lam=2.0, grad_mode="exact", wl_model="lse", eps=0.5)
+    _check_eval(inst, got, ref, 2.0, "exact")
+    for bad in (dict(wl_model=2), dict(screening=-0.1), dict(screening=float("nan"))):
+        with pytest.raises(F.FFTPLError) as ei:
+            _run_eval(F, inst, 2.0, "field", **bad)
+        assert ei.value.status == F.E_INVAL
+
+
+@pytest.mark.parametrize("path", ["xch", "slots", "atomic"])
+def test_eval_cells_without_nets(F, path):
+    # fillers, or the real cells alone when the loop measures their overflow:
+    # cells but no nets, with the gradient and (atomic-free paths) scalars only
+    import dataclasses
+    import torch
+    inst = gen.make_config("small_2k")
+    inst = dataclasses.replace(with_macros(inst, [[30.0, 30.0, 10.0, 8.0]]),
+                               net_ptr=np.zeros(1, np.int32), pin_cell=np.zeros(0, np.int32),
+                               pin_dx=np.zeros(0, np.float32), pin_dy=np.zeros(0, np.float32))
+    say("cells without nets", path)
+    got = _run_eval(F, inst, 2.0, "field", path=path)
+    ref = oracle.evaluate(inst, lam=2.0, grad_mode="field")
+    assert got["out"][1] == 0.0 and got["out"][2] == 0.0
+    assert rel_l2(got["gx"], ref["gx"]) < RTOL and rel_l2(got["gy"], ref["gy"]) < RTOL
+    assert abs(got["out"][0] - ref["energy"]) < RTOL * ref["energy"]
+    assert abs(got["out"][3] - ref["overflow"]) < RTOL
+    if path != "atomic":
+        prob = F.Problem.from_instance(inst, path=path)
+        plan = F.Plan(inst.n)
+        c = DeviceCells(inst)
+        out4 = torch.empty(4, dtype=torch.float64, device="cuda")
+        F.eval(plan, prob, c.x, c.y, 2.0, inst.gamma, "field", None, None, out4)
+        o = host(out4)
+        assert abs(o[0] - ref["energy"]) < RTOL * ref["energy"] and o[1] == 0.0
+        assert abs(o[3] - ref["overflow"]) < RTOL
+        plan.close()
