@@ -22,6 +22,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <type_traits>
 #include <vector>
 
 #include "fftpl_internal.hpp"
@@ -77,9 +78,18 @@ __device__ __forceinline__ void split_bf16(float v, __bf16& hi, __bf16& lo) {
 template <bool BF16, int KS>
 __global__ void __launch_bounds__(256 * KS) k_gemm(GemmArgs g, Epi ep) {
   constexpr int TKB = KS * TK;
-  const int tiles_n = g.N / TN;
-  const int tile = xcd_block(blockIdx.x, gridDim.x);
-  const int m0 = (tile / tiles_n) * TM, n0 = (tile % tiles_n) * TN;
+  // Each XCD runs a contiguous range of logical tiles (xcd_block); inside
+  // it the tiles go down gsz rows of tiles before moving one column right, so
+  // the range covers a compact patch whose A row panels and B column panels
+  // share the XCD's L2.
+  const int tiles_n = g.N / TN, tiles_m = g.M / TM;
+  const int lt = xcd_block(blockIdx.x, gridDim.x);
+  const int per_xcd = gridDim.x % kNumXcd ? (int)gridDim.x : (int)gridDim.x / kNumXcd;
+  const int gsz = per_xcd >= 64 ? 8 : per_xcd >= 16 ? 4 : per_xcd >= 4 ? 2 : 1;
+  const int group = lt / (gsz * tiles_n), first = group * gsz;
+  const int gm = min(tiles_m - first, gsz);
+  const int m0 = (first + (lt % (gsz * tiles_n)) % gm) * TM;
+  const int n0 = ((lt % (gsz * tiles_n)) / gm) * TN;
   const int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
   const int wq = w & 3, wk = w >> 2;
   const int wm = (wq >> 1) * 32, wn = (wq & 1) * 32;
@@ -93,7 +103,11 @@ __global__ void __launch_bounds__(256 * KS) k_gemm(GemmArgs g, Epi ep) {
   // Double-buffered K loop: the next K step's operands are loaded from
   // global memory into registers while the MFMAs run on the current LDS
   // tile, then stored to the other LDS buffer; one barrier per step.
-  constexpr int kFloats = 2 * 2 * 2 * TK * (TM + 4);
+  // bf16: [hi, lo] x [A, B] x 2 buffers of TM rows of TKB / 8 + 1 chunks of
+  // 16 bytes (one chunk of padding per row, see below)
+  constexpr int kFloatsF32 = 2 * 2 * 2 * TK * (TM + 4);
+  constexpr int kFloatsBf16 = 2 * 2 * 2 * TM * (TKB / 8 + 1) * 4;
+  constexpr int kFloats = BF16 ? kFloatsBf16 : kFloatsF32;
   __shared__ __attribute__((aligned(16))) float smem[kFloats];
   if constexpr (!BF16) {
     float(*As)[TKB][TM + 4] = reinterpret_cast<float(*)[TKB][TM + 4]>(smem);   // [buf][k][m]
@@ -148,56 +162,78 @@ __global__ void __launch_bounds__(256 * KS) k_gemm(GemmArgs g, Epi ep) {
   } else {
     // tiles keep 8 consecutive k of one row (A) or one column (B^T) together,
     // which is what one lane feeds to the 16x16x32 bf16 MFMA
+    // Rows are KC + 1 chunks long: the eight lanes one LDS cycle serves read
+    // the same chunk of eight consecutive rows, which with unpadded rows of
+    // 128 (or 64) bytes would all fall on the same banks.
     constexpr int KC = TKB / 8;   // bf8 chunks per row and K step
-    bf8(*Ah)[TM][KC] = reinterpret_cast<bf8(*)[TM][KC]>(smem);
-    bf8(*Al)[TM][KC] = Ah + 2;
-    bf8(*Bh)[TN][KC] = reinterpret_cast<bf8(*)[TN][KC]>(Ah + 4);
-    bf8(*Bl)[TN][KC] = Bh + 2;
+    constexpr int KCP = KC + 1;
+    static_assert(TM == TN, "A and B tiles share the padded row layout");
+    bf8(*Ah)[TM][KCP] = reinterpret_cast<bf8(*)[TM][KCP]>(smem);
+    bf8(*Al)[TM][KCP] = Ah + 2;
+    bf8(*Bh)[TN][KCP] = reinterpret_cast<bf8(*)[TN][KCP]>(Ah + 4);
+    bf8(*Bl)[TN][KCP] = Bh + 2;
     const __bf16* gah = static_cast<const __bf16*>(g.a_hi);
     const __bf16* gal = static_cast<const __bf16*>(g.a_lo);
     const __bf16* gbh = static_cast<const __bf16*>(g.b_hi);
     const __bf16* gbl = static_cast<const __bf16*>(g.b_lo);
     const int r = t / KC, kc = t % KC;
-    bf8 rah, ral, rbh, rbl;
-    auto fetch = [&](int k0) {
-      const size_t oa = (size_t)(m0 + r) * g.lda + k0 + kc * 8;
-      const size_t ob = (size_t)(n0 + r) * g.ldb + k0 + kc * 8;
-      rah = *reinterpret_cast<const bf8*>(gah + oa);
-      ral = *reinterpret_cast<const bf8*>(gal + oa);
-      rbh = *reinterpret_cast<const bf8*>(gbh + ob);
-      rbl = *reinterpret_cast<const bf8*>(gbl + ob);
-    };
-    auto stash = [&](int buf) {
-      Ah[buf][r][kc] = rah;
-      Al[buf][r][kc] = ral;
-      Bh[buf][r][kc] = rbh;
-      Bl[buf][r][kc] = rbl;
-    };
-    fetch(0);
-    stash(0);
-    __syncthreads();
-    int cur = 0;
+    // Operands of the next PRE K steps are in flight in registers while the
+    // MFMAs of the current step run from LDS.  Register set j holds step
+    // s0 + j and is refilled right after being stored to LDS.  The body has
+    // no data-dependent branches (loads past the last step re-read the last
+    // step, the store after the last step fills the idle buffer) so that
+    // every wait is for the oldest loads only.
+    const int steps = g.K / TKB;
     const int kq = wk * (TK / 8) + lg;
-    for (int k0 = 0; k0 < g.K; k0 += TKB) {
-      const bool more = k0 + TKB < g.K;
-      if (more) fetch(k0 + TKB);
-      const bf8 xh0 = Ah[cur][wm + l16][kq], xl0 = Al[cur][wm + l16][kq];
-      const bf8 xh1 = Ah[cur][wm + 16 + l16][kq], xl1 = Al[cur][wm + 16 + l16][kq];
-      const bf8 yh0 = Bh[cur][wn + l16][kq], yl0 = Bl[cur][wn + l16][kq];
-      const bf8 yh1 = Bh[cur][wn + 16 + l16][kq], yl1 = Bl[cur][wn + 16 + l16][kq];
+    auto run = [&](auto pre) {
+      constexpr int PRE = decltype(pre)::value;
+      bf8 rah[PRE], ral[PRE], rbh[PRE], rbl[PRE];
+      auto fetch = [&](int q, int step) {
+        const int k0 = min(step, steps - 1) * TKB;
+        const size_t oa = (size_t)(m0 + r) * g.lda + k0 + kc * 8;
+        const size_t ob = (size_t)(n0 + r) * g.ldb + k0 + kc * 8;
+        rah[q] = *reinterpret_cast<const bf8*>(gah + oa);
+        ral[q] = *reinterpret_cast<const bf8*>(gal + oa);
+        rbh[q] = *reinterpret_cast<const bf8*>(gbh + ob);
+        rbl[q] = *reinterpret_cast<const bf8*>(gbl + ob);
+      };
+      auto stash = [&](int q, int buf) {
+        Ah[buf][r][kc] = rah[q];
+        Al[buf][r][kc] = ral[q];
+        Bh[buf][r][kc] = rbh[q];
+        Bl[buf][r][kc] = rbl[q];
+      };
+#pragma unroll
+      for (int q = 0; q < PRE; ++q) fetch(q, q);
+      stash(0, 0);
+      __syncthreads();
+      for (int s0 = 0; s0 < steps; s0 += PRE) {
+#pragma unroll
+        for (int j = 0; j < PRE; ++j) {
+          const int cur = (s0 + j) & 1;
+          fetch(j, s0 + j + PRE);
+          const bf8 xh0 = Ah[cur][wm + l16][kq], xl0 = Al[cur][wm + l16][kq];
+          const bf8 xh1 = Ah[cur][wm + 16 + l16][kq], xl1 = Al[cur][wm + 16 + l16][kq];
+          const bf8 yh0 = Bh[cur][wn + l16][kq], yl0 = Bl[cur][wn + l16][kq];
+          const bf8 yh1 = Bh[cur][wn + 16 + l16][kq], yl1 = Bl[cur][wn + 16 + l16][kq];
 #define FFTPL_MFMA3(ACC, XH, XL, YH, YL)                                      \
   ACC = __builtin_amdgcn_mfma_f32_16x16x32_bf16(XH, YH, ACC, 0, 0, 0);        \
   ACC = __builtin_amdgcn_mfma_f32_16x16x32_bf16(XH, YL, ACC, 0, 0, 0);        \
   ACC = __builtin_amdgcn_mfma_f32_16x16x32_bf16(XL, YH, ACC, 0, 0, 0);
-      FFTPL_MFMA3(acc[0][0], xh0, xl0, yh0, yl0)
-      FFTPL_MFMA3(acc[0][1], xh0, xl0, yh1, yl1)
-      FFTPL_MFMA3(acc[1][0], xh1, xl1, yh0, yl0)
-      FFTPL_MFMA3(acc[1][1], xh1, xl1, yh1, yl1)
+          FFTPL_MFMA3(acc[0][0], xh0, xl0, yh0, yl0)
+          FFTPL_MFMA3(acc[0][1], xh0, xl0, yh1, yl1)
+          FFTPL_MFMA3(acc[1][0], xh1, xl1, yh0, yl0)
+          FFTPL_MFMA3(acc[1][1], xh1, xl1, yh1, yl1)
 #undef FFTPL_MFMA3
-      if (more) stash(cur ^ 1);
-      __syncthreads();
-      cur ^= 1;
-    }
+          stash((j + 1) % PRE, cur ^ 1);
+          __syncthreads();
+        }
+      }
+    };
+    if (steps % 4 == 0)
+      run(std::integral_constant<int, 4>{});
+    else
+      run(std::integral_constant<int, 1>{});
   }
 
   // the second K half's partial tile joins the first one's (waves 0-3 keep
@@ -266,7 +302,7 @@ __global__ void __launch_bounds__(256 * KS) k_gemm(GemmArgs g, Epi ep) {
       }
     }
   }
-  if (ep.mode == EPI_PSI_EY && ep.en_part) block_sum_to<false>(en, &ep.en_part[tile]);
+  if (ep.mode == EPI_PSI_EY && ep.en_part) block_sum_to<false>(en, &ep.en_part[lt]);
 }
 
 // Row sums of rho in double, and the per-row overflow pairs (overflow,
