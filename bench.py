@@ -32,23 +32,23 @@ PMC_FETCH_SCALE, PMC_WRITE_SCALE = 2.0, 1.0
 PMC_TRAFFIC = {
     # kernel: (source files, sha1, FETCH_SIZE KiB, WRITE_SIZE KiB)
     "k_band_place": (("band_scatter.hip", "fftpl_internal.hpp"),
-        "c4ffdd89c2b745bb31cd80b9218d1fda1b3f9400", 16523.3, 64703.3),
+        "f236aa9d9dff01c5fb40b411ba6250ba24ce0fdb", 16523.2, 64800.8),
     "k_xch_spread": (("exchange.hip", "fftpl_internal.hpp"),
-        "7c68c14c8f6c5a24790120ebeb3b0d467bd40f3e", 28613.6, 96905.3),
+        "93cefbdb74f288e03a1f8587c96aab4e611000a2", 28615.8, 96900.5),
     "k_band_accum": (("band_scatter.hip", "fftpl_internal.hpp"),
-        "c4ffdd89c2b745bb31cd80b9218d1fda1b3f9400", 27906.8, 4096.0),
+        "f236aa9d9dff01c5fb40b411ba6250ba24ce0fdb", 27906.4, 4096.0),
     "k_xch_wa": (("exchange.hip", "fftpl_internal.hpp"),
-        "7c68c14c8f6c5a24790120ebeb3b0d467bd40f3e", 187978.6, 116211.4),
+        "93cefbdb74f288e03a1f8587c96aab4e611000a2", 187969.7, 116211.0),
     "k_rows_dct2": (("spectral_fft.hip", "fftpl_internal.hpp"),
-        "69709c838b0e386815b492da25bcfd12f3f7fce1", 6235.2, 4112.0),
+        "9d2baff3bd487d073e3971e4f1bd594dd0161bbc", 6235.3, 4112.0),
     "k_cols_solve": (("spectral_fft.hip", "fftpl_internal.hpp"),
-        "69709c838b0e386815b492da25bcfd12f3f7fce1", 2171.1, 8192.0),
+        "9d2baff3bd487d073e3971e4f1bd594dd0161bbc", 2180.1, 8192.0),
     "k_rows_inverse": (("spectral_fft.hip", "fftpl_internal.hpp"),
-        "69709c838b0e386815b492da25bcfd12f3f7fce1", 6269.6, 8196.0),
+        "9d2baff3bd487d073e3971e4f1bd594dd0161bbc", 6265.6, 8196.0),
     "k_band_gather": (("band_scatter.hip", "fftpl_internal.hpp"),
-        "c4ffdd89c2b745bb31cd80b9218d1fda1b3f9400", 30984.4, 21047.6),
+        "f236aa9d9dff01c5fb40b411ba6250ba24ce0fdb", 30984.2, 21049.7),
     "k_xch_cellsum": (("exchange.hip", "fftpl_internal.hpp"),
-        "7c68c14c8f6c5a24790120ebeb3b0d467bd40f3e", 73824.4, 16406.2),
+        "93cefbdb74f288e03a1f8587c96aab4e611000a2", 73836.9, 16406.2),
 }
 
 
