@@ -537,6 +537,7 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
     e = hipEventRecord(p.join, ds);
     if (e == hipSuccess) e = hipStreamWaitEvent(s, p.join, 0);
   }
+  bool fin_in_cellsum = false;
   FinalArgs fin;
   fin.en = p.partials;
   fin.n_en = p.n_en;
@@ -568,6 +569,11 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
       ca.scale = lambda;
       ca.gx = gx;
       ca.gy = gy;
+      // the last cell block (the last one dispatched, and at most as large as
+      // the others) reduces the scalars too
+      ca.fin = fin;
+      ca.fin_block = xd.ncb - 1;
+      fin_in_cellsum = xd.ncb > 0;
       if (e == hipSuccess) e = launch_xch_cellsum(xd, X, L.pin_grad, ca, grad_mode, s);
       plan_mark(p, "k_xch_cellsum", s);
     } else {
@@ -589,10 +595,11 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
     plan_mark(p, "k_wa_atomic", s);
   }
   // 6. N, W~, HPWL, tau from the per-block partials (the atomic path added
-  // W~ and HPWL into out4 directly).  A separate one-block launch: a
-  // last-block-done count in the gather would put every gather block's
-  // atomic on one address, which costs far more than the launch.
-  {
+  // W~ and HPWL into out4 directly): by the exchange path's cell sums, or a
+  // separate one-block launch (a last-block-done count in the gather would
+  // put every gather block's atomic on one address, which costs far more
+  // than the launch).
+  if (!fin_in_cellsum) {
     if (e == hipSuccess)
       e = launch_eval_finalize(fin.en, fin.n_en, fin.tau, fin.n_tau, fin.wa, fin.n_s, fin.n_b,
                                fin.o_en, fin.o_wa, fin.o_hp, fin.o_tau, s);

@@ -782,6 +782,10 @@ __global__ void __launch_bounds__(kSumThreads)
     a.gx[ci] = a.scale * d[k].x + sx;
     a.gy[ci] = a.scale * d[k].y + sy;
   }
+  if ((int)blockIdx.x == a.fin_block) {
+    __syncthreads();
+    eval_scalars<kSumThreads>(a.fin);
+  }
 }
 
 }  // namespace

@@ -656,6 +656,11 @@ struct CellGradArgs {
   const float2* egrad = nullptr;
   float scale = 0.0f;
   float *gx = nullptr, *gy = nullptr;
+  // block fin_block (if >= 0) also reduces the evaluation's scalars (every
+  // partial they need is complete before the cell sums start), in place of a
+  // separate finalize launch
+  FinalArgs fin;
+  int fin_block = -1;
 };
 // g (CellGradArgs) for every cell, the wirelength part being the sum over
 // the cell's pins of their gradients in T (after launch_xch_wa).
