@@ -600,7 +600,11 @@ hipError_t launch_exclusive_scan(const int32_t* in, int count, int32_t* out, int
 // (pins grouped by cell block, then by net block); a net block reads its pins
 // in "B order" (grouped by cell block), so both sides move runs of pins
 // instead of single random words, and every random access happens in LDS.
-constexpr int kXchCells = 8192;        // cells per cell block (64 KiB of float2)
+// cells per cell block: 9 x 1024, so that designs up to 2.36M cells have at
+// most 256 cell blocks (one per CU: the cell sums then run in a single round
+// instead of leaving one block for a second); the cell-sum accumulators
+// (17 bytes per cell) fill 153 KiB of LDS
+constexpr int kXchCells = 9216;
 constexpr int kXchSpreadSplit = 2;     // spread blocks per cell block
 constexpr int kXchThreads = 512;       // threads of the cell-block kernels
 constexpr int kXchWaThreads = 512;     // threads of the net-block kernel
