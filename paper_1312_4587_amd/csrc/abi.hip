@@ -449,12 +449,12 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
   if (xch) {
     X = xch_index(xd, prob->xindex);
     if (validate_env()) {
-      int32_t hdr[8];
+      int32_t hdr[9];
       if (hipDeviceSynchronize() != hipSuccess ||
           hipMemcpy(hdr, prob->xindex, sizeof(hdr), hipMemcpyDeviceToHost) != hipSuccess)
         return FFTPL_E_DEVICE;
       if (hdr[1] != m || hdr[2] != prob->num_nets || hdr[3] != prob->num_pins ||
-          hdr[4] != prob->max_degree || hdr[5] != xd.npt)
+          hdr[4] != prob->max_degree || hdr[5] != xd.npt || hdr[8] != xd.cpb)
         return FFTPL_E_STATE;
     }
   }

@@ -7,7 +7,8 @@
 // write, each of which moves a whole cache line.  Here the permutation is
 // split in two halves that both run through LDS:
 //
-//   cell blocks: kXchCells consecutive cells;
+//   cell blocks: cpb consecutive cells (a multiple of 1024, at most kXchCells,
+//                about one block per CU);
 //   net blocks:  the nets whose first pin lies in [k*npt, (k+1)*npt), so a
 //                block holds at most npt - 1 + max_degree <= kXchPinCap pins;
 //   A order:     pins sorted by (cell block, net block);
@@ -32,6 +33,8 @@
 //
 // The index (A/B layout) is built once per netlist by xch_build.
 #include <math.h>
+
+#include <algorithm>
 
 #include "fftpl_internal.hpp"
 
@@ -72,7 +75,12 @@ int xch_dims(int m, int num_nets, int num_pins, int max_degree, XchDims* d) {
   r.max_degree = max_degree;
   r.npt = npt;
   r.cap = max_degree > 0 ? npt - 1 + max_degree : 1;
-  r.ncb = (m + kXchCells - 1) / kXchCells;
+  {
+    const int64_t per_cu = ((int64_t)m + kNumCus - 1) / kNumCus;
+    const int64_t step = (per_cu + kXchCellStep - 1) / kXchCellStep * kXchCellStep;
+    r.cpb = (int)std::min<int64_t>(kXchCells, std::max<int64_t>(kXchCellStep, step));
+  }
+  r.ncb = (m + r.cpb - 1) / r.cpb;
   r.nnb = num_pins > 0 ? (num_pins + npt - 1) / npt : 1;
   size_t off = 0;
   r.o_hdr = off;
@@ -145,7 +153,8 @@ __global__ void k_xi_netblocks(int num_nets, const int32_t* __restrict__ net_ptr
 template <bool PLACE>
 __global__ void __launch_bounds__(256)
     k_xi_pins(int num_nets, const int32_t* __restrict__ net_ptr, int num_pins,
-              const int32_t* __restrict__ pin_cell, int m, int max_degree, int npt, int ncb,
+              const int32_t* __restrict__ pin_cell, int m, int cpb, int max_degree, int npt,
+              int ncb,
               int nnb, int32_t* __restrict__ cnt, const int32_t* __restrict__ seg_a,
               const int32_t* __restrict__ seg_bt, const int32_t* __restrict__ nb_net_ptr,
               int32_t* __restrict__ a_of_b, uint16_t* __restrict__ lcsr,
@@ -175,7 +184,7 @@ __global__ void __launch_bounds__(256)
       if (!PLACE) atomicOr(flag, 8);
       continue;
     }
-    const int cb = c / kXchCells;
+    const int cb = c / cpb;
     const size_t idx = (size_t)cb * nnb + k;
     if (!PLACE) {
       atomicAdd(&cnt[idx], 1);
@@ -185,7 +194,7 @@ __global__ void __launch_bounds__(256)
       const int b = seg_bt[(size_t)k * ncb + cb] + r;
       a_of_b[b] = a;
       lcsr[b] = (uint16_t)(p - base);
-      lc[a] = (uint16_t)(c - cb * kXchCells);
+      lc[a] = (uint16_t)(c - cb * cpb);
     }
   }
 }
@@ -243,7 +252,7 @@ __global__ void k_xi_transpose(int ncb, int nnb, const int32_t* __restrict__ cnt
 
 __global__ void k_xi_finish(int ncb, int nnb, int num_pins, const int32_t* __restrict__ seg_a,
                             int32_t* __restrict__ cb_a_ptr, int32_t* __restrict__ hdr,
-                            int m, int num_nets, int max_degree, int npt) {
+                            int m, int num_nets, int max_degree, int npt, int cpb) {
   const int cb = blockIdx.x * blockDim.x + threadIdx.x;
   if (cb < ncb) cb_a_ptr[cb] = seg_a[(size_t)cb * nnb];
   if (cb == ncb) cb_a_ptr[cb] = num_pins;
@@ -256,6 +265,7 @@ __global__ void k_xi_finish(int ncb, int nnb, int num_pins, const int32_t* __res
     hdr[5] = npt;
     hdr[6] = ncb;
     hdr[7] = nnb;
+    hdr[8] = cpb;
   }
 }
 
@@ -297,7 +307,7 @@ int xch_build(const XchDims& d, const int32_t* net_ptr, const int32_t* pin_cell,
   }
   if (e == hipSuccess) {
     hipLaunchKernelGGL((k_xi_pins<false>), net_grid, dim3(256), 0, s, E, net_ptr, P, pin_cell,
-                       d.m, d.max_degree, d.npt, d.ncb, d.nnb, cnt, nullptr, nullptr, nullptr,
+                       d.m, d.cpb, d.max_degree, d.npt, d.ncb, d.nnb, cnt, nullptr, nullptr, nullptr,
                        nullptr, nullptr, nullptr, flag);
     e = hipGetLastError();
   }
@@ -309,7 +319,7 @@ int xch_build(const XchDims& d, const int32_t* net_ptr, const int32_t* pin_cell,
   if (e == hipSuccess) e = launch_exclusive_scan(cnt_t, (int)seg, seg_bt, sums, flag + 2, s);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_xi_finish, dim3((d.ncb + 256) / 256), dim3(256), 0, s, d.ncb, d.nnb,
-                       P, seg_a, cb_a_ptr, hdr, d.m, E, d.max_degree, d.npt);
+                       P, seg_a, cb_a_ptr, hdr, d.m, E, d.max_degree, d.npt, d.cpb);
     e = hipGetLastError();
   }
   if (e != hipSuccess) return FFTPL_E_DEVICE;
@@ -323,7 +333,7 @@ int xch_build(const XchDims& d, const int32_t* net_ptr, const int32_t* pin_cell,
   e = launch_zero_i32(cnt, (int64_t)seg, s);
   if (e == hipSuccess) {
     hipLaunchKernelGGL((k_xi_pins<true>), net_grid, dim3(256), 0, s, E, net_ptr, P, pin_cell,
-                       d.m, d.max_degree, d.npt, d.ncb, d.nnb, cnt, seg_a, seg_bt, nb_net_ptr,
+                       d.m, d.cpb, d.max_degree, d.npt, d.ncb, d.nnb, cnt, seg_a, seg_bt, nb_net_ptr,
                        a_of_b, lcsr, lc, flag);
     e = hipGetLastError();
   }
@@ -344,14 +354,14 @@ namespace {
 // T[a] = (x, y) of pin a's cell, over part blockIdx.x % kXchSpreadSplit of
 // the A range of cell block blockIdx.x / kXchSpreadSplit.
 __global__ void __launch_bounds__(NT)
-    k_xch_spread(int m, const int32_t* __restrict__ cb_a_ptr, const uint16_t* __restrict__ lc,
-                 const float* __restrict__ x, const float* __restrict__ y,
-                 float2* __restrict__ T) {
+    k_xch_spread(int m, int cpb, const int32_t* __restrict__ cb_a_ptr,
+                 const uint16_t* __restrict__ lc, const float* __restrict__ x,
+                 const float* __restrict__ y, float2* __restrict__ T) {
   __shared__ float2 win[kXchCells];
   const int cb = blockIdx.x / kXchSpreadSplit, part = blockIdx.x % kXchSpreadSplit;
   const int t = threadIdx.x;
-  const int c0 = cb * kXchCells;
-  const int nc = min(kXchCells, m - c0);
+  const int c0 = cb * cpb;
+  const int nc = min(cpb, m - c0);
   {
     constexpr int W = kXchCells / NT;
     float xv[W], yv[W];
@@ -709,9 +719,9 @@ __global__ void __launch_bounds__(NW)
 // its cell's sum NaN.
 template <int MODE>
 __global__ void __launch_bounds__(kSumThreads)
-    k_xch_cellsum(int m, const int32_t* __restrict__ cb_a_ptr, const uint16_t* __restrict__ lc,
-                  const float2* __restrict__ T, float scale, double inv_scale,
-                  CellGradArgs a) {
+    k_xch_cellsum(int m, int cpb, const int32_t* __restrict__ cb_a_ptr,
+                  const uint16_t* __restrict__ lc, const float2* __restrict__ T, float scale,
+                  double inv_scale, CellGradArgs a) {
   __shared__ unsigned long long ax[kXchCells], ay[kXchCells];
   __shared__ unsigned char bad[kXchCells];
   const int cb = blockIdx.x, t = threadIdx.x;
@@ -763,7 +773,7 @@ __global__ void __launch_bounds__(kSumThreads)
   // 8-byte read; all of a thread's reads issued together) or, for a cell
   // without one, from the maps; plus its wirelength sum
   constexpr int PC = kXchCells / kSumThreads;
-  const int c0 = cb * kXchCells;
+  const int c0 = cb * cpb;
   int ep[PC];
   float2 d[PC];
 #pragma unroll
@@ -773,7 +783,7 @@ __global__ void __launch_bounds__(kSumThreads)
 #pragma unroll
   for (int k = 0; k < PC; ++k) {
     const int c = t + k * kSumThreads, ci = c0 + c;
-    if (ci >= m) break;
+    if (c >= cpb || ci >= m) break;
     if (ep[k] < 0)
       d[k] = cell_density_grad<MODE, true>(a.g, a.x[ci], a.y[ci], a.w[ci], a.h[ci], nullptr,
                                            nullptr, a.exy, a.psi);
@@ -799,17 +809,19 @@ hipError_t launch_xch_cellsum(const XchDims& d, const XchIndex& X, const float2*
   while (S > 0 && bound * ldexp(1.0, S) > ldexp(1.0, 30)) --S;
   if (grad_mode == FFTPL_GRAD_EXACT)
     hipLaunchKernelGGL(k_xch_cellsum<FFTPL_GRAD_EXACT>, dim3(d.ncb), dim3(kSumThreads), 0, s,
-                       d.m, X.cb_a_ptr, X.lc, T, (float)ldexp(1.0, S), ldexp(1.0, -S), a);
+                       d.m, d.cpb, X.cb_a_ptr, X.lc, T, (float)ldexp(1.0, S), ldexp(1.0, -S),
+                       a);
   else
     hipLaunchKernelGGL(k_xch_cellsum<FFTPL_GRAD_FIELD>, dim3(d.ncb), dim3(kSumThreads), 0, s,
-                       d.m, X.cb_a_ptr, X.lc, T, (float)ldexp(1.0, S), ldexp(1.0, -S), a);
+                       d.m, d.cpb, X.cb_a_ptr, X.lc, T, (float)ldexp(1.0, S), ldexp(1.0, -S),
+                       a);
   return hipGetLastError();
 }
 
 hipError_t launch_xch_spread(const XchDims& d, const XchIndex& X, const float* x,
                              const float* y, float2* T, hipStream_t s) {
   if (d.ncb <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_xch_spread, dim3(d.ncb * kXchSpreadSplit), dim3(NT), 0, s, d.m,
+  hipLaunchKernelGGL(k_xch_spread, dim3(d.ncb * kXchSpreadSplit), dim3(NT), 0, s, d.m, d.cpb,
                      X.cb_a_ptr, X.lc, x, y, T);
   return hipGetLastError();
 }

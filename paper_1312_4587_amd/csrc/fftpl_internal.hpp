@@ -600,11 +600,15 @@ hipError_t launch_exclusive_scan(const int32_t* in, int count, int32_t* out, int
 // (pins grouped by cell block, then by net block); a net block reads its pins
 // in "B order" (grouped by cell block), so both sides move runs of pins
 // instead of single random words, and every random access happens in LDS.
-// cells per cell block: 9 x 1024, so that designs up to 2.36M cells have at
-// most 256 cell blocks (one per CU: the cell sums then run in a single round
-// instead of leaving one block for a second); the cell-sum accumulators
-// (17 bytes per cell) fill 153 KiB of LDS
+// Most cells of a cell block, 9 x 1024: the cell-sum accumulators (17 bytes
+// per cell) then fill 153 KiB of LDS.  A design's cell blocks hold
+// XchDims::cpb cells, a multiple of kXchCellStep chosen so that there are
+// about as many blocks as CUs (kNumCus): the cell sums, one block per CU,
+// then run in a single round at any size up to 2.36M cells, and small designs
+// still spread over the chip.
 constexpr int kXchCells = 9216;
+constexpr int kXchCellStep = 1024;
+constexpr int kNumCus = 256;           // compute units of an MI355X (gfx950)
 constexpr int kXchSpreadSplit = 2;     // spread blocks per cell block
 constexpr int kXchThreads = 512;       // threads of the cell-block kernels
 constexpr int kXchWaThreads = 512;     // threads of the net-block kernel
@@ -619,6 +623,7 @@ struct XchDims {
   int m = 0, num_nets = 0, num_pins = 0, max_degree = 0;
   int npt = 0;         // net block k = nets whose first pin lies in [k*npt, (k+1)*npt)
   int cap = 0;         // bound on the pins of one net block: npt - 1 + max_degree
+  int cpb = kXchCells;     // cells per cell block
   int ncb = 0, nnb = 0;   // cell blocks, net blocks
   size_t index_bytes = 0, work_bytes = 0;
   // offsets inside the index buffer

@@ -40,7 +40,7 @@ def _with_nets(inst, degs, seed):
 
 @pytest.mark.parametrize("mode", ["field", "exact"])
 def test_exchange_many_blocks_and_new_positions(F, mode):
-    # 60k cells = 7 cell blocks (the last one ragged), nets up to degree 3000
+    # 60k cells = 59 cell blocks (the last one ragged), nets up to degree 3000
     # so the net blocks shrink below their default target
     inst = gen.make_instance(7, num_cells=60_000, util=0.8, n=256, num_nets=70_000,
                              hi_frac=0.01, hi_range=(20, 3000), num_macros=5,
@@ -59,7 +59,7 @@ def test_exchange_many_blocks_and_new_positions(F, mode):
 
 def test_exchange_odd_nets(F):
     # empty nets, one-pin nets (zero gradient), a net at the largest degree the
-    # index takes (8705), a net of 5000, and ordinary nets, over 3 cell blocks
+    # index takes (8705), a net of 5000, and ordinary nets, over 20 cell blocks
     base = gen.make_instance(8, num_cells=20000, util=0.7, n=64, num_nets=10)
     rng = np.random.default_rng(80)
     degs = np.concatenate([rng.integers(2, 9, 3000), [8705, 5000, 1, 1, 0, 0],

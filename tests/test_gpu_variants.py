@@ -117,7 +117,7 @@ def test_eval_lse_screened_small(F, mode, path):
 
 @pytest.mark.parametrize("wl,eps", [("lse", 0.0), ("wa", 0.2), ("lse", 0.2)])
 def test_eval_variants_exchange_many_blocks(F, wl, eps):
-    # 7 cell blocks (the last ragged), nets up to degree 3000 (net blocks
+    # 59 cell blocks (the last ragged), nets up to degree 3000 (net blocks
     # below their default size, wavefront-wide nets, more large nets than a
     # block stages extents for)
     inst = gen.make_instance(7, num_cells=60_000, util=0.8, n=256, num_nets=70_000,
