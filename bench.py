@@ -32,23 +32,23 @@ PMC_FETCH_SCALE, PMC_WRITE_SCALE = 2.0, 1.0
 PMC_TRAFFIC = {
     # kernel: (source files, sha1, FETCH_SIZE KiB, WRITE_SIZE KiB)
     "k_band_place": (("band_scatter.hip", "fftpl_internal.hpp"),
-        "f236aa9d9dff01c5fb40b411ba6250ba24ce0fdb", 16523.2, 64800.8),
+        "22db1457c9769cbe94d184114e565c21817873b3", 16524.1, 64883.5),
     "k_xch_spread": (("exchange.hip", "fftpl_internal.hpp"),
-        "93cefbdb74f288e03a1f8587c96aab4e611000a2", 28615.8, 96900.5),
+        "121a99bdb798bd62cd84f29224daf48658f27c3a", 28605.0, 96881.7),
     "k_band_accum": (("band_scatter.hip", "fftpl_internal.hpp"),
-        "f236aa9d9dff01c5fb40b411ba6250ba24ce0fdb", 27906.4, 4096.0),
+        "22db1457c9769cbe94d184114e565c21817873b3", 27906.1, 4096.0),
     "k_xch_wa": (("exchange.hip", "fftpl_internal.hpp"),
-        "93cefbdb74f288e03a1f8587c96aab4e611000a2", 187969.7, 116211.0),
+        "121a99bdb798bd62cd84f29224daf48658f27c3a", 182381.0, 114043.4),
     "k_rows_dct2": (("spectral_fft.hip", "fftpl_internal.hpp"),
-        "9d2baff3bd487d073e3971e4f1bd594dd0161bbc", 6235.3, 4112.0),
+        "542792a9c01261660e23c00b485f16c68c1ecd08", 6235.4, 4112.0),
     "k_cols_solve": (("spectral_fft.hip", "fftpl_internal.hpp"),
-        "9d2baff3bd487d073e3971e4f1bd594dd0161bbc", 2180.1, 8192.0),
+        "542792a9c01261660e23c00b485f16c68c1ecd08", 2180.2, 8192.0),
     "k_rows_inverse": (("spectral_fft.hip", "fftpl_internal.hpp"),
-        "9d2baff3bd487d073e3971e4f1bd594dd0161bbc", 6265.6, 8196.0),
+        "542792a9c01261660e23c00b485f16c68c1ecd08", 6265.6, 8196.0),
     "k_band_gather": (("band_scatter.hip", "fftpl_internal.hpp"),
-        "f236aa9d9dff01c5fb40b411ba6250ba24ce0fdb", 30984.2, 21049.7),
+        "22db1457c9769cbe94d184114e565c21817873b3", 30983.1, 21047.4),
     "k_xch_cellsum": (("exchange.hip", "fftpl_internal.hpp"),
-        "93cefbdb74f288e03a1f8587c96aab4e611000a2", 73836.9, 16406.2),
+        "121a99bdb798bd62cd84f29224daf48658f27c3a", 77611.4, 16406.5),
 }
 
 
