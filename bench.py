@@ -32,23 +32,23 @@ PMC_FETCH_SCALE, PMC_WRITE_SCALE = 2.0, 1.0
 PMC_TRAFFIC = {
     # kernel: (source files, sha1, FETCH_SIZE KiB, WRITE_SIZE KiB)
     "k_band_place": (("band_scatter.hip", "fftpl_internal.hpp"),
-        "22db1457c9769cbe94d184114e565c21817873b3", 16524.1, 64883.5),
+        "9e3d254663c7326949940ac3680dc4c645584d0c", 16523.2, 64771.8),
     "k_xch_spread": (("exchange.hip", "fftpl_internal.hpp"),
-        "121a99bdb798bd62cd84f29224daf48658f27c3a", 28605.0, 96881.7),
+        "84a9d600b5ed34571b20bf4564b365f643193a66", 28605.8, 96883.0),
     "k_band_accum": (("band_scatter.hip", "fftpl_internal.hpp"),
-        "22db1457c9769cbe94d184114e565c21817873b3", 27906.1, 4096.0),
+        "9e3d254663c7326949940ac3680dc4c645584d0c", 27906.5, 4096.0),
     "k_xch_wa": (("exchange.hip", "fftpl_internal.hpp"),
-        "121a99bdb798bd62cd84f29224daf48658f27c3a", 182381.0, 114043.4),
+        "84a9d600b5ed34571b20bf4564b365f643193a66", 182399.8, 114043.6),
     "k_rows_dct2": (("spectral_fft.hip", "fftpl_internal.hpp"),
-        "542792a9c01261660e23c00b485f16c68c1ecd08", 6235.4, 4112.0),
+        "7ffed285bca2410f8e722a78803c0e5b31aceb14", 6235.3, 4112.0),
     "k_cols_solve": (("spectral_fft.hip", "fftpl_internal.hpp"),
-        "542792a9c01261660e23c00b485f16c68c1ecd08", 2180.2, 8192.0),
+        "7ffed285bca2410f8e722a78803c0e5b31aceb14", 2180.1, 8192.0),
     "k_rows_inverse": (("spectral_fft.hip", "fftpl_internal.hpp"),
-        "542792a9c01261660e23c00b485f16c68c1ecd08", 6265.6, 8196.0),
+        "7ffed285bca2410f8e722a78803c0e5b31aceb14", 6265.6, 8196.0),
     "k_band_gather": (("band_scatter.hip", "fftpl_internal.hpp"),
-        "22db1457c9769cbe94d184114e565c21817873b3", 30983.1, 21047.4),
+        "9e3d254663c7326949940ac3680dc4c645584d0c", 30984.5, 21047.6),
     "k_xch_cellsum": (("exchange.hip", "fftpl_internal.hpp"),
-        "121a99bdb798bd62cd84f29224daf48658f27c3a", 77611.4, 16406.5),
+        "84a9d600b5ed34571b20bf4564b365f643193a66", 77684.9, 16406.5),
 }
 
 
