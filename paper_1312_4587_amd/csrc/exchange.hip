@@ -9,8 +9,10 @@
 //
 //   cell blocks: cpb consecutive cells (a multiple of 1024, at most kXchCells,
 //                about one block per CU);
-//   net blocks:  the nets whose first pin lies in [k*npt, (k+1)*npt), so a
-//                block holds at most npt - 1 + max_degree <= kXchPinCap pins;
+//   net blocks:  whole nets packed in CSR order, as many as fit in cap =
+//                npt - 1 + max_degree <= kXchPinCap pins, so every block but
+//                the last holds at least npt pins and there are at most
+//                ceil(P / npt) blocks (the trailing ones may be empty);
 //   A order:     pins sorted by (cell block, net block);
 //   B order:     inside each net block's CSR range, pins sorted by cell block,
 //                in the same order as A within each (cell block, net block)
@@ -35,6 +37,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <vector>
 
 #include "fftpl_internal.hpp"
 
@@ -125,27 +128,6 @@ XchIndex xch_index(const XchDims& d, const void* index) {
 // ---------------------------------------------------------------------------
 namespace {
 
-// nb_net_ptr[k] = first net whose first pin is >= k*npt (k < nnb); [nnb] = E.
-__global__ void k_xi_netblocks(int num_nets, const int32_t* __restrict__ net_ptr, int npt,
-                               int nnb, int32_t* __restrict__ nb_net_ptr) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k > nnb) return;
-  if (k == nnb) {
-    nb_net_ptr[k] = num_nets;
-    return;
-  }
-  const int64_t target = (int64_t)k * npt;
-  int lo = 0, hi = num_nets + 1;   // lower bound over net_ptr[0..E]
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if ((int64_t)net_ptr[mid] < target)
-      lo = mid + 1;
-    else
-      hi = mid;
-  }
-  nb_net_ptr[k] = lo < num_nets ? lo : num_nets;
-}
-
 // Checks the CSR (net_ptr[0] = 0, net_ptr[E] = P, monotone, degrees <=
 // max_degree, pin cells in range) and, with PLACE = false, counts the pins of
 // every (cell block, net block) segment; with PLACE = true, hands each pin its
@@ -172,8 +154,17 @@ __global__ void __launch_bounds__(256)
     return;
   }
   if (p1 == p0) return;
-  const int k = p0 / npt;
-  if (k >= nnb) {
+  // the net block holding net e: the last k with nb_net_ptr[k] <= e
+  int lo = 0, hi = nnb - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (nb_net_ptr[mid] <= e)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const int k = lo;
+  if (e >= nb_net_ptr[k + 1]) {
     if (!PLACE) atomicOr(flag, 4);
     return;
   }
@@ -298,16 +289,41 @@ int xch_build(const XchDims& d, const int32_t* net_ptr, const int32_t* pin_cell,
 
   const int E = d.num_nets, P = d.num_pins;
   const dim3 net_grid((E + 255) / 256 > 0 ? (E + 255) / 256 : 1);
+  // Net blocks, packed greedily on the host from the CSR (a sequential scan
+  // of the net sizes, once per netlist): a block is closed when the next net
+  // does not fit in cap pins.  Packing instead of cutting at fixed pin counts
+  // fills the blocks (the LDS is sized for cap) rather than reserving room
+  // for a largest net at every block end.
+  {
+    std::vector<int32_t> hptr((size_t)E + 1), hnb((size_t)d.nnb + 1, E);
+    if (hipMemcpyAsync(hptr.data(), net_ptr, sizeof(int32_t) * ((size_t)E + 1),
+                       hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return FFTPL_E_DEVICE;
+    if (hptr[0] != 0 || hptr[E] != P) return FFTPL_E_INVAL;
+    int k = 0;
+    int64_t cur = 0;
+    hnb[0] = 0;
+    for (int en = 0; en < E; ++en) {
+      const int64_t deg = (int64_t)hptr[(size_t)en + 1] - hptr[en];
+      if (deg < 0 || deg > d.max_degree) return FFTPL_E_INVAL;
+      if (cur + deg > d.cap) {
+        if (++k >= d.nnb) return FFTPL_E_INVAL;   // cannot happen for a valid CSR
+        hnb[k] = en;
+        cur = 0;
+      }
+      cur += deg;
+    }
+    if (hipMemcpyAsync(nb_net_ptr, hnb.data(), sizeof(int32_t) * hnb.size(),
+                       hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return FFTPL_E_DEVICE;
+  }
   hipError_t e = launch_zero_i32(cnt, (int64_t)seg, s);
   if (e == hipSuccess) e = launch_zero_i32(flag, 4, s);
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_xi_netblocks, dim3((d.nnb + 256) / 256), dim3(256), 0, s, E, net_ptr,
-                       d.npt, d.nnb, nb_net_ptr);
-    e = hipGetLastError();
-  }
-  if (e == hipSuccess) {
     hipLaunchKernelGGL((k_xi_pins<false>), net_grid, dim3(256), 0, s, E, net_ptr, P, pin_cell,
-                       d.m, d.cpb, d.max_degree, d.npt, d.ncb, d.nnb, cnt, nullptr, nullptr, nullptr,
+                       d.m, d.cpb, d.max_degree, d.npt, d.ncb, d.nnb, cnt, nullptr, nullptr, nb_net_ptr,
                        nullptr, nullptr, nullptr, flag);
     e = hipGetLastError();
   }
