@@ -32,13 +32,13 @@ PMC_FETCH_SCALE, PMC_WRITE_SCALE = 2.0, 1.0
 PMC_TRAFFIC = {
     # kernel: (source files, sha1, FETCH_SIZE KiB, WRITE_SIZE KiB)
     "k_band_place": (("band_scatter.hip", "fftpl_internal.hpp"),
-        "9e3d254663c7326949940ac3680dc4c645584d0c", 16523.2, 64771.8),
+        "9e3d254663c7326949940ac3680dc4c645584d0c", 16523.3, 64704.5),
     "k_xch_spread": (("exchange.hip", "fftpl_internal.hpp"),
-        "84a9d600b5ed34571b20bf4564b365f643193a66", 28605.8, 96883.0),
+        "abb1379852b53e5c5de598d5cb46a437f9720fb0", 28602.2, 96872.2),
     "k_band_accum": (("band_scatter.hip", "fftpl_internal.hpp"),
-        "9e3d254663c7326949940ac3680dc4c645584d0c", 27906.5, 4096.0),
+        "9e3d254663c7326949940ac3680dc4c645584d0c", 27906.6, 4096.0),
     "k_xch_wa": (("exchange.hip", "fftpl_internal.hpp"),
-        "84a9d600b5ed34571b20bf4564b365f643193a66", 182399.8, 114043.6),
+        "abb1379852b53e5c5de598d5cb46a437f9720fb0", 175446.6, 111000.7),
     "k_rows_dct2": (("spectral_fft.hip", "fftpl_internal.hpp"),
         "7ffed285bca2410f8e722a78803c0e5b31aceb14", 6235.3, 4112.0),
     "k_cols_solve": (("spectral_fft.hip", "fftpl_internal.hpp"),
@@ -46,9 +46,9 @@ PMC_TRAFFIC = {
     "k_rows_inverse": (("spectral_fft.hip", "fftpl_internal.hpp"),
         "7ffed285bca2410f8e722a78803c0e5b31aceb14", 6265.6, 8196.0),
     "k_band_gather": (("band_scatter.hip", "fftpl_internal.hpp"),
-        "9e3d254663c7326949940ac3680dc4c645584d0c", 30984.5, 21047.6),
+        "9e3d254663c7326949940ac3680dc4c645584d0c", 30983.1, 21050.8),
     "k_xch_cellsum": (("exchange.hip", "fftpl_internal.hpp"),
-        "84a9d600b5ed34571b20bf4564b365f643193a66", 77684.9, 16406.5),
+        "abb1379852b53e5c5de598d5cb46a437f9720fb0", 77649.9, 16406.5),
 }
 
 
