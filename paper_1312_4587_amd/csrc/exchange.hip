@@ -135,8 +135,7 @@ namespace {
 template <bool PLACE>
 __global__ void __launch_bounds__(256)
     k_xi_pins(int num_nets, const int32_t* __restrict__ net_ptr, int num_pins,
-              const int32_t* __restrict__ pin_cell, int m, int cpb, int max_degree, int npt,
-              int ncb,
+              const int32_t* __restrict__ pin_cell, int m, int cpb, int max_degree, int ncb,
               int nnb, int32_t* __restrict__ cnt, const int32_t* __restrict__ seg_a,
               const int32_t* __restrict__ seg_bt, const int32_t* __restrict__ nb_net_ptr,
               int32_t* __restrict__ a_of_b, uint16_t* __restrict__ lcsr,
@@ -323,7 +322,7 @@ int xch_build(const XchDims& d, const int32_t* net_ptr, const int32_t* pin_cell,
   if (e == hipSuccess) e = launch_zero_i32(flag, 4, s);
   if (e == hipSuccess) {
     hipLaunchKernelGGL((k_xi_pins<false>), net_grid, dim3(256), 0, s, E, net_ptr, P, pin_cell,
-                       d.m, d.cpb, d.max_degree, d.npt, d.ncb, d.nnb, cnt, nullptr, nullptr, nb_net_ptr,
+                       d.m, d.cpb, d.max_degree, d.ncb, d.nnb, cnt, nullptr, nullptr, nb_net_ptr,
                        nullptr, nullptr, nullptr, flag);
     e = hipGetLastError();
   }
@@ -349,7 +348,7 @@ int xch_build(const XchDims& d, const int32_t* net_ptr, const int32_t* pin_cell,
   e = launch_zero_i32(cnt, (int64_t)seg, s);
   if (e == hipSuccess) {
     hipLaunchKernelGGL((k_xi_pins<true>), net_grid, dim3(256), 0, s, E, net_ptr, P, pin_cell,
-                       d.m, d.cpb, d.max_degree, d.npt, d.ncb, d.nnb, cnt, seg_a, seg_bt, nb_net_ptr,
+                       d.m, d.cpb, d.max_degree, d.ncb, d.nnb, cnt, seg_a, seg_bt, nb_net_ptr,
                        a_of_b, lcsr, lc, flag);
     e = hipGetLastError();
   }

@@ -614,14 +614,14 @@ constexpr int kXchThreads = 512;       // threads of the cell-block kernels
 constexpr int kXchWaThreads = 512;     // threads of the net-block kernel
 constexpr int kXchPinCap = 9728;       // most pins of a net block (2 x 76 KiB of float2 in LDS)
 constexpr int kXchPinLds2 = 4864;      // pins of a net block that leave room for 2 blocks per CU
-constexpr int kXchPinTarget = 4096;    // nets are grouped by first pin / target
+constexpr int kXchPinTarget = 4096;    // most of npt, the least pins of a full net block
 constexpr int kXchMinTarget = 1024;
 constexpr int kXchBuckets = 20;        // degree classes of the net order: 0..8, then
                                        // 9-16, 17-32, ..., > 8192
 
 struct XchDims {
   int m = 0, num_nets = 0, num_pins = 0, max_degree = 0;
-  int npt = 0;         // net block k = nets whose first pin lies in [k*npt, (k+1)*npt)
+  int npt = 0;         // every net block but the last holds at least npt pins
   int cap = 0;         // bound on the pins of one net block: npt - 1 + max_degree
   int cpb = kXchCells;     // cells per cell block
   int ncb = 0, nnb = 0;   // cell blocks, net blocks
