@@ -32,23 +32,23 @@ PMC_FETCH_SCALE, PMC_WRITE_SCALE = 2.0, 1.0
 PMC_TRAFFIC = {
     # kernel: (source files, sha1, FETCH_SIZE KiB, WRITE_SIZE KiB)
     "k_band_place": (("band_scatter.hip", "fftpl_internal.hpp"),
-        "9e3d254663c7326949940ac3680dc4c645584d0c", 16523.3, 64704.5),
+        "368865b5341cce28660798bb391b9e7b48049851", 16523.2, 64892.8),
     "k_xch_spread": (("exchange.hip", "fftpl_internal.hpp"),
-        "abb1379852b53e5c5de598d5cb46a437f9720fb0", 28602.2, 96872.2),
+        "da6bdc1258df44286116bda9072aa280bf821339", 28602.0, 96871.9),
     "k_band_accum": (("band_scatter.hip", "fftpl_internal.hpp"),
-        "9e3d254663c7326949940ac3680dc4c645584d0c", 27906.6, 4096.0),
+        "368865b5341cce28660798bb391b9e7b48049851", 27906.2, 4096.0),
     "k_xch_wa": (("exchange.hip", "fftpl_internal.hpp"),
-        "abb1379852b53e5c5de598d5cb46a437f9720fb0", 175446.6, 111000.7),
+        "da6bdc1258df44286116bda9072aa280bf821339", 175482.1, 111001.1),
     "k_rows_dct2": (("spectral_fft.hip", "fftpl_internal.hpp"),
-        "7ffed285bca2410f8e722a78803c0e5b31aceb14", 6235.3, 4112.0),
+        "d52da1318ece596a0f48c11873097abcd4129ba4", 6235.3, 4112.0),
     "k_cols_solve": (("spectral_fft.hip", "fftpl_internal.hpp"),
-        "7ffed285bca2410f8e722a78803c0e5b31aceb14", 2180.1, 8192.0),
+        "d52da1318ece596a0f48c11873097abcd4129ba4", 2180.1, 8192.0),
     "k_rows_inverse": (("spectral_fft.hip", "fftpl_internal.hpp"),
-        "7ffed285bca2410f8e722a78803c0e5b31aceb14", 6265.6, 8196.0),
+        "d52da1318ece596a0f48c11873097abcd4129ba4", 6265.6, 8196.0),
     "k_band_gather": (("band_scatter.hip", "fftpl_internal.hpp"),
-        "9e3d254663c7326949940ac3680dc4c645584d0c", 30983.1, 21050.8),
+        "368865b5341cce28660798bb391b9e7b48049851", 30982.8, 21053.2),
     "k_xch_cellsum": (("exchange.hip", "fftpl_internal.hpp"),
-        "abb1379852b53e5c5de598d5cb46a437f9720fb0", 77649.9, 16406.5),
+        "da6bdc1258df44286116bda9072aa280bf821339", 77687.6, 16406.5),
 }
 
 
