@@ -462,18 +462,20 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
   p.nev = 0;
   plan_mark(p, "start", s);
   // With per-kernel timing on, everything runs on `s` so that consecutive
-  // events bracket single kernels.  Otherwise the density branch (zeroing,
-  // banded scatter, solve) runs on the plan's side stream `ds` while the
-  // wirelength branch, the longer of the two, stays on `s`: the hand-over
-  // between streams costs several microseconds each way, and this way the
-  // fork delays only the shorter branch and the join is usually complete
-  // by the time the wirelength branch reaches it.
+  // events bracket single kernels.  Otherwise the wirelength branch (spread,
+  // net blocks) runs on the plan's side stream `ws` while the density branch
+  // (banded scatter, solve, band gather), the longer of the two when they
+  // share the chip, stays on `s`: the hand-over between streams costs
+  // several microseconds each way, and this way the fork delays only the
+  // shorter branch and the join is usually complete by the time the density
+  // branch reaches it.
   const bool overlap = fast && !p.timing;
-  hipStream_t ds = overlap ? p.side : s;
+  hipStream_t ds = s;
+  hipStream_t ws = overlap ? p.side : s;
   if (fast) {
     if (overlap) {
       e = hipEventRecord(p.fork, s);
-      if (e == hipSuccess) e = hipStreamWaitEvent(ds, p.fork, 0);
+      if (e == hipSuccess) e = hipStreamWaitEvent(ws, p.fork, 0);
     }
     // density branch: banded scatter (its counters and the scalars are all
     // written, not accumulated, so nothing needs zeroing first)
@@ -483,20 +485,20 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
     if (xch) {
       // pin positions into the exchange buffer, then every net block (the
       // per-cell sums follow the join)
-      if (e == hipSuccess) e = launch_xch_spread(xd, X, x, y, L.pin_grad, s);
-      plan_mark(p, "k_xch_spread", s);
+      if (e == hipSuccess) e = launch_xch_spread(xd, X, x, y, L.pin_grad, ws);
+      plan_mark(p, "k_xch_spread", ws);
       if (e == hipSuccess)
         e = launch_xch_wa(xd, X, prob->net_ptr, prob->pin_dx, prob->pin_dy, gamma,
-                          prob->wl_model, L.pin_grad, L.wa_part, s);
-      plan_mark(p, "k_xch_wa", s);
+                          prob->wl_model, L.pin_grad, L.wa_part, ws);
+      plan_mark(p, "k_xch_wa", ws);
     } else {
       // interleave positions, per-pin WA gradients into cell-major slots
-      if (e == hipSuccess) e = launch_interleave(m, x, y, L.xy, s);
-      plan_mark(p, "k_interleave", s);
+      if (e == hipSuccess) e = launch_interleave(m, x, y, L.xy, ws);
+      plan_mark(p, "k_interleave", ws);
       if (e == hipSuccess)
         e = launch_wa_pins(prob->num_nets, prob->net_ptr, prob->pin_cell, prob->pin_dx,
                            prob->pin_dy, L.xy, prob->pin_slot, gamma, prob->wl_model,
-                           L.pin_grad, L.wa_part, s, &p);
+                           L.pin_grad, L.wa_part, ws, &p);
     }
   } else {
     // 1. reset: rho = base, scalar accumulators = 0; 2. atomic scatter
@@ -532,9 +534,9 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
     if (e == hipSuccess) e = launch_band_gather(g, L, p.exy, p.psi, grad_mode, ds);
     plan_mark(p, "k_band_gather", ds);
   }
-  // join the density branch
+  // join the wirelength branch
   if (e == hipSuccess && overlap) {
-    e = hipEventRecord(p.join, ds);
+    e = hipEventRecord(p.join, ws);
     if (e == hipSuccess) e = hipStreamWaitEvent(s, p.join, 0);
   }
   bool fin_in_cellsum = false;
