@@ -342,9 +342,11 @@ int fftpl_xindex_build(int32_t num_cells, int32_t num_nets, int32_t num_pins,
  * gx, gy [num_cells] are overwritten.  prob->grid.n must equal the plan's n.
  * With gx = gy = NULL only out4 is computed (the loss W~ + lambda N and the
  * other scalars, without the gather); this needs a workspace and an index in
- * prob (FFTPL_E_INVAL otherwise).  With a workspace and an index the density
- * branch (scatter, solve, per-cell density gradient) runs on the plan's own
- * stream concurrently with the wirelength on `stream`; the density map, the
+ * prob (FFTPL_E_INVAL otherwise).  With a workspace and an index the
+ * wirelength branch (pin positions, net blocks) runs on the plan's own stream
+ * concurrently with the density branch (scatter, solve, per-cell density
+ * gradient) on `stream`, and is joined back before the per-cell sums; the
+ * density map, the
  * cell sums and the scalars do not depend on the order of any atomic adds,
  * so repeated evaluations give identical results. */
 int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
