@@ -353,6 +353,22 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
                const float* y, float lambda, float gamma, int32_t grad_mode,
                float* gx, float* gy, double* out4, void* stream);
 
+/* Serving extension: count evaluations of designs that share the plan's grid
+ * side, in order on `stream`, request i exactly as
+ *   fftpl_eval(plan, probs[i], xs[i], ys[i], lambdas[i], gammas[i], grad_mode,
+ *              gxs ? gxs[i] : NULL, gys ? gys[i] : NULL, out4s + 4*i, stream).
+ * probs, xs, ys, lambdas, gammas, gxs and gys are HOST arrays of count entries
+ * (gxs and gys both NULL: the scalars only, for every request); the pointers
+ * they hold and out4s (double [4*count]) are device memory.  Every request is
+ * checked on the host before anything is enqueued: on an argument error
+ * nothing runs and the status of the first failing request is returned.
+ * Requests may share a workspace (they run one after another).  count = 0 is
+ * a no-op. */
+int fftpl_eval_batch(fftpl_plan* plan, int32_t count, const fftpl_problem* const* probs,
+                     const float* const* xs, const float* const* ys, const float* lambdas,
+                     const float* gammas, int32_t grad_mode, float* const* gxs,
+                     float* const* gys, double* out4s, void* stream);
+
 /* Placement iteration (Algorithm 1: after each evaluation the positions move
  * along the gradient).  The global placement here uses Nesterov's method with
  * a look-ahead point u at which the gradient g is taken; the step length is

@@ -66,6 +66,11 @@ SIGNATURES = {
                                c_void_p, c_void_p, c_void_p, c_void_p]),
     "fftpl_eval": (c_int, [c_void_p, _P, c_void_p, c_void_p, c_float, c_float, c_int,
                            c_void_p, c_void_p, c_void_p, c_void_p]),
+    "fftpl_eval_batch": (c_int, [c_void_p, c_int, ctypes.POINTER(_P),
+                                 ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p),
+                                 ctypes.POINTER(c_float), ctypes.POINTER(c_float), c_int,
+                                 ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p),
+                                 c_void_p, c_void_p]),
     "fftpl_debug_cell_bins": (c_int, [_G, c_int, c_void_p, c_void_p, c_void_p,
                                       c_void_p, c_void_p, c_void_p]),
     "fftpl_problem_work_bytes": (c_int, [c_int, c_int, c_int, c_int,

@@ -399,9 +399,11 @@ int fftpl_lse_grad(int32_t num_nets, const int32_t* net_ptr, int32_t num_pins,
                  num_cells, x, y, gamma, accumulate, gx, gy, wa, hpwl, stream);
 }
 
-int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
-               const float* y, float lambda, float gamma, int32_t grad_mode, float* gx,
-               float* gy, double* out4, void* stream) {
+// One evaluation; with check_only, the host-side checks alone (nothing is
+// enqueued).
+static int eval_impl(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
+                     const float* y, float lambda, float gamma, int32_t grad_mode, float* gx,
+                     float* gy, double* out4, void* stream, bool check_only) {
   if (!plan || !prob || !out4 || !grid_ok(&prob->grid)) return FFTPL_E_INVAL;
   if (prob->wl_model != FFTPL_WL_WA && prob->wl_model != FFTPL_WL_LSE) return FFTPL_E_INVAL;
   if (!(prob->screening >= 0.0f) || !isfinite(prob->screening)) return FFTPL_E_INVAL;
@@ -458,6 +460,7 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
         return FFTPL_E_STATE;
     }
   }
+  if (check_only) return FFTPL_OK;
   hipError_t e = hipSuccess;
   p.nev = 0;
   plan_mark(p, "start", s);
@@ -608,6 +611,36 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
     plan_mark(p, "k_eval_finalize", s);
   }
   return dev_status(e);
+}
+
+int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
+               const float* y, float lambda, float gamma, int32_t grad_mode, float* gx,
+               float* gy, double* out4, void* stream) {
+  return eval_impl(plan, prob, x, y, lambda, gamma, grad_mode, gx, gy, out4, stream, false);
+}
+
+int fftpl_eval_batch(fftpl_plan* plan, int32_t count, const fftpl_problem* const* probs,
+                     const float* const* xs, const float* const* ys, const float* lambdas,
+                     const float* gammas, int32_t grad_mode, float* const* gxs,
+                     float* const* gys, double* out4s, void* stream) {
+  if (count < 0) return FFTPL_E_INVAL;
+  if (count == 0) return FFTPL_OK;
+  if (!plan || !probs || !xs || !ys || !lambdas || !gammas || !out4s) return FFTPL_E_INVAL;
+  if ((gxs == nullptr) != (gys == nullptr)) return FFTPL_E_INVAL;
+  // every request is checked before any is enqueued
+  for (int32_t i = 0; i < count; ++i) {
+    const int st = eval_impl(plan, probs[i], xs[i], ys[i], lambdas[i], gammas[i], grad_mode,
+                             gxs ? gxs[i] : nullptr, gys ? gys[i] : nullptr,
+                             out4s + 4 * (size_t)i, stream, true);
+    if (st != FFTPL_OK) return st;
+  }
+  for (int32_t i = 0; i < count; ++i) {
+    const int st = eval_impl(plan, probs[i], xs[i], ys[i], lambdas[i], gammas[i], grad_mode,
+                             gxs ? gxs[i] : nullptr, gys ? gys[i] : nullptr,
+                             out4s + 4 * (size_t)i, stream, false);
+    if (st != FFTPL_OK) return st;
+  }
+  return FFTPL_OK;
 }
 
 int fftpl_plan_timing(fftpl_plan* plan, int32_t enable) {

@@ -417,6 +417,36 @@ def eval(plan: Plan, prob: Problem, x, y, lam, gamma, grad_mode, gx, gy, out4,
         _stream(stream)), "fftpl_eval")
 
 
+def eval_batch(plan: Plan, probs, xs, ys, lams, gammas, grad_mode, gxs, gys, out4s,
+               stream=None):
+    """fftpl_eval_batch: requests i = 0..len(probs)-1 in order on one stream.
+    gxs and gys are lists of tensors, or None for the scalars only; out4s is
+    a float64 device tensor [len(probs), 4]."""
+    k = len(probs)
+    if not (len(xs) == len(ys) == len(lams) == len(gammas) == k):
+        raise ValueError("one x, y, lambda and gamma per problem")
+    P = _lib.fftpl_problem
+    pa = (P * max(k, 1))(*[pr.c for pr in probs])
+    pp = (ctypes.POINTER(P) * max(k, 1))(*[ctypes.pointer(pa[i]) for i in range(k)])
+    vp = lambda ts, name: (ctypes.c_void_p * max(k, 1))(
+        *[_ptr(t, torch.float32, probs[i].num_cells, name) for i, t in enumerate(ts)])
+    xa, ya = vp(xs, "x"), vp(ys, "y")
+    la = (ctypes.c_float * max(k, 1))(*[float(v) for v in lams])
+    ga = (ctypes.c_float * max(k, 1))(*[float(v) for v in gammas])
+    gxa = vp(gxs, "gx") if gxs is not None else None
+    gya = vp(gys, "gy") if gys is not None else None
+    _check(_lib.load().fftpl_eval_batch(
+        plan.handle, k, ctypes.cast(pp, ctypes.POINTER(ctypes.POINTER(P))),
+        ctypes.cast(xa, ctypes.POINTER(ctypes.c_void_p)),
+        ctypes.cast(ya, ctypes.POINTER(ctypes.c_void_p)),
+        ctypes.cast(la, ctypes.POINTER(ctypes.c_float)),
+        ctypes.cast(ga, ctypes.POINTER(ctypes.c_float)),
+        GRAD_MODES.get(grad_mode, grad_mode),
+        ctypes.cast(gxa, ctypes.POINTER(ctypes.c_void_p)) if gxa is not None else None,
+        ctypes.cast(gya, ctypes.POINTER(ctypes.c_void_p)) if gya is not None else None,
+        _ptr(out4s, torch.float64, 4 * k, "out4s"), _stream(stream)), "fftpl_eval_batch")
+
+
 def debug_cell_bins(grid: Grid, x, y, w, h, ranges, stream=None):
     m = int(x.numel())
     _check(_lib.load().fftpl_debug_cell_bins(

@@ -102,6 +102,12 @@ def test_argument_errors_are_reported_before_any_device_work():
     assert lib.fftpl_helmholtz_solve(None, ctypes.byref(g), 0.5, p, p, None, None, None,
                                      None) == -1
     assert lib.fftpl_eval(None, None, p, p, 1.0, 1.0, 0, p, p, p, None) == -1
+    assert lib.fftpl_eval_batch(None, 0, None, None, None, None, None, 0, None, None, None,
+                                None) == 0
+    assert lib.fftpl_eval_batch(None, -1, None, None, None, None, None, 0, None, None, None,
+                                None) == -1
+    assert lib.fftpl_eval_batch(None, 2, None, None, None, None, None, 0, None, None, p,
+                                None) == -1
     assert lib.fftpl_poisson_solve(None, ctypes.byref(g), p, p, None, None, None,
                                    None) == -1
     assert lib.fftpl_debug_cell_bins(ctypes.byref(g), 4, p, p, p, p, None, None) == -1

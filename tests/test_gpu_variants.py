@@ -167,3 +167,57 @@ def test_eval_cells_without_nets(F, path):
         assert abs(o[0] - ref["energy"]) < RTOL * ref["energy"] and o[1] == 0.0
         assert abs(o[3] - ref["overflow"]) < RTOL
         plan.close()
+
+
+def test_eval_batch_matches_single_evaluations(F):
+    # the serving extension: requests sharing the grid side in one call, in
+    # order on one stream, equal to one fftpl_eval each; two requests share a
+    # problem (and so a workspace) with different positions
+    import torch
+    a = gen.make_config("small_2k")
+    b = gen.make_instance(41, num_cells=3000, util=0.6, n=64, num_nets=3300, hi_frac=0.02,
+                          hi_range=(9, 80))
+    rng = np.random.default_rng(42)
+    a2 = a.with_positions(np.clip(a.x + rng.normal(0, 2.0, a.num_cells), 0, a.side),
+                          np.clip(a.y + rng.normal(0, 2.0, a.num_cells), 0, a.side))
+    insts = [a, b, a2]
+    pa, pb = F.Problem.from_instance(a), F.Problem.from_instance(b)
+    probs = [pa, pb, pa]
+    plan = F.Plan(64)
+    cells = [DeviceCells(i) for i in insts]
+    lams, gammas = [1.5, 2.0, 0.5], [i.gamma for i in insts]
+    for mode in ("field", "exact"):
+        gxs = [torch.empty(i.num_cells, device="cuda") for i in insts]
+        gys = [torch.empty(i.num_cells, device="cuda") for i in insts]
+        out = torch.empty((3, 4), dtype=torch.float64, device="cuda")
+        F.eval_batch(plan, probs, [c.x for c in cells], [c.y for c in cells], lams, gammas,
+                     mode, gxs, gys, out)
+        torch.cuda.synchronize()
+        for i, inst in enumerate(insts):
+            gx = torch.empty(inst.num_cells, device="cuda")
+            gy = torch.empty(inst.num_cells, device="cuda")
+            o4 = torch.empty(4, dtype=torch.float64, device="cuda")
+            F.eval(plan, probs[i], cells[i].x, cells[i].y, lams[i], gammas[i], mode, gx, gy, o4)
+            torch.cuda.synchronize()
+            assert rel_l2(host(gxs[i]), host(gx)) < 1e-7 and rel_l2(host(gys[i]), host(gy)) < 1e-7
+            assert np.allclose(host(out[i]), host(o4), rtol=1e-12, atol=0.0)
+        ref = oracle.evaluate(b, lam=2.0, grad_mode=mode)
+        assert rel_l2(host(gxs[1]), ref["gx"]) < RTOL and rel_l2(host(gys[1]), ref["gy"]) < RTOL
+    # scalars only
+    out = torch.empty((3, 4), dtype=torch.float64, device="cuda")
+    F.eval_batch(plan, probs, [c.x for c in cells], [c.y for c in cells], lams, gammas,
+                 "field", None, None, out)
+    ref = oracle.evaluate(a2, lam=0.5, grad_mode="field")
+    assert abs(float(host(out[2])[0]) - ref["energy"]) < RTOL * abs(ref["energy"])
+    # a request of another grid side: refused before anything runs
+    other = F.Problem.from_instance(gen.make_instance(43, num_cells=500, util=0.5, n=32,
+                                                      num_nets=400))
+    oc = DeviceCells(gen.make_instance(43, num_cells=500, util=0.5, n=32, num_nets=400))
+    out.fill_(-7.0)
+    with pytest.raises(F.FFTPLError) as ei:
+        F.eval_batch(plan, [pa, other], [cells[0].x, oc.x], [cells[0].y, oc.y], [1.0, 1.0],
+                     [1.0, 1.0], "field", None, None, out[:2])
+    assert ei.value.status == F.E_STATE
+    torch.cuda.synchronize()
+    assert np.all(host(out) == -7.0)
+    plan.close()
