@@ -78,7 +78,7 @@ def parse():
     ap.add_argument("--variants", default="fft,gemm_f32,gemm_bf16x3",
                     help="spectral variants to time besides --dct")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-evals", type=int, default=2)
+    ap.add_argument("--cpu-evals", type=int, default=5)
     ap.add_argument("--kernel-reps", type=int, default=0,
                     help="evaluations timed kernel by kernel (default max(10, steps/4))")
     ap.add_argument("--no-precision", action="store_true",
