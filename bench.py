@@ -294,8 +294,8 @@ def cpu_baseline(inst, evals):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): this build has "
-              "no multi-GPU path; see the sharding notes in DESIGN.md", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the library "
+              "evaluates one design on one GPU and has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
