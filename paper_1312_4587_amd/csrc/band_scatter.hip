@@ -262,9 +262,17 @@ __global__ void __launch_bounds__(kAccThreads)
     }
   });
   __syncthreads();
+  // rho = base + rows: all of a thread's base loads issued before any store
+  constexpr int PA = kBandMaxN * 4 / NTA;
   const size_t o = (size_t)r0 * n;
-  for (int k = t; k < cells; k += NTA)
-    rho[o + k] = (base ? base[o + k] : 0.0f) + (float)((double)acc[k] * kAccUnit);
+  float bv[PA];
+#pragma unroll
+  for (int j = 0; j < PA; ++j) bv[j] = base ? base[o + min(t + j * NTA, cells - 1)] : 0.0f;
+#pragma unroll
+  for (int j = 0; j < PA; ++j) {
+    const int k = t + j * NTA;
+    if (k < cells) rho[o + k] = bv[j] + (float)((double)acc[k] * kAccUnit);
+  }
 }
 
 // Density gradient of every cell listed in band b with b its first band,
@@ -286,7 +294,15 @@ __global__ void __launch_bounds__(NTG)
   const int n = g.n, R = L.rows, band = blockIdx.x;
   const int r0 = band * R, nr = min(R + 1, n - r0);
   if (MODE == FFTPL_GRAD_FIELD) {
-    for (int k = t; k < nr * n; k += NTG) rows[k] = exy[(int64_t)r0 * n + k];
+    // all of a thread's loads issued before its LDS stores
+    constexpr int PS = (5 * kBandMaxN + NTG - 1) / NTG;
+    const int cnt = nr * n;
+    float2 v[PS];
+#pragma unroll
+    for (int j = 0; j < PS; ++j) v[j] = exy[(int64_t)r0 * n + min(t + j * NTG, cnt - 1)];
+#pragma unroll
+    for (int j = 0; j < PS; ++j)
+      if (t + j * NTG < cnt) rows[t + j * NTG] = v[j];
   }
   // (the walk's first scan synchronises the block after the staging)
   walk_band<NTG, B>(L, band, kBandRegion, pre, start, [&](const int64_t (&idx)[B]) {
