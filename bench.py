@@ -32,23 +32,23 @@ PMC_FETCH_SCALE, PMC_WRITE_SCALE = 2.0, 1.0
 PMC_TRAFFIC = {
     # kernel: (source files, sha1, FETCH_SIZE KiB, WRITE_SIZE KiB)
     "k_band_place": (("band_scatter.hip", "fftpl_internal.hpp"),
-        "368865b5341cce28660798bb391b9e7b48049851", 16523.2, 64892.8),
+        "ce6342ab6d88b496996a0edec09e0708a1d9faf4", 16523.2, 64755.6),
     "k_xch_spread": (("exchange.hip", "fftpl_internal.hpp"),
-        "da6bdc1258df44286116bda9072aa280bf821339", 28602.0, 96871.9),
+        "da6bdc1258df44286116bda9072aa280bf821339", 28601.9, 96877.0),
     "k_band_accum": (("band_scatter.hip", "fftpl_internal.hpp"),
-        "368865b5341cce28660798bb391b9e7b48049851", 27906.2, 4096.0),
+        "ce6342ab6d88b496996a0edec09e0708a1d9faf4", 27909.4, 4096.0),
     "k_xch_wa": (("exchange.hip", "fftpl_internal.hpp"),
-        "da6bdc1258df44286116bda9072aa280bf821339", 175482.1, 111001.1),
+        "da6bdc1258df44286116bda9072aa280bf821339", 175494.3, 111000.2),
     "k_rows_dct2": (("spectral_fft.hip", "fftpl_internal.hpp"),
-        "d52da1318ece596a0f48c11873097abcd4129ba4", 6235.3, 4112.0),
+        "d52da1318ece596a0f48c11873097abcd4129ba4", 6235.2, 4112.0),
     "k_cols_solve": (("spectral_fft.hip", "fftpl_internal.hpp"),
         "d52da1318ece596a0f48c11873097abcd4129ba4", 2180.1, 8192.0),
     "k_rows_inverse": (("spectral_fft.hip", "fftpl_internal.hpp"),
         "d52da1318ece596a0f48c11873097abcd4129ba4", 6265.6, 8196.0),
     "k_band_gather": (("band_scatter.hip", "fftpl_internal.hpp"),
-        "368865b5341cce28660798bb391b9e7b48049851", 30982.8, 21053.2),
+        "ce6342ab6d88b496996a0edec09e0708a1d9faf4", 30981.6, 21041.8),
     "k_xch_cellsum": (("exchange.hip", "fftpl_internal.hpp"),
-        "da6bdc1258df44286116bda9072aa280bf821339", 77687.6, 16406.5),
+        "da6bdc1258df44286116bda9072aa280bf821339", 77638.5, 16406.5),
 }
 
 
