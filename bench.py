@@ -32,13 +32,13 @@ PMC_FETCH_SCALE, PMC_WRITE_SCALE = 2.0, 1.0
 PMC_TRAFFIC = {
     # kernel: (source files, sha1, FETCH_SIZE KiB, WRITE_SIZE KiB)
     "k_band_place": (("band_scatter.hip", "fftpl_internal.hpp"),
-        "ce6342ab6d88b496996a0edec09e0708a1d9faf4", 16523.2, 64755.6),
+        "ce6342ab6d88b496996a0edec09e0708a1d9faf4", 16523.2, 64976.0),
     "k_xch_spread": (("exchange.hip", "fftpl_internal.hpp"),
-        "da6bdc1258df44286116bda9072aa280bf821339", 28601.9, 96877.0),
+        "54250ba9f3403f84a79dc41d2fda149099fcbb61", 28602.6, 96875.7),
     "k_band_accum": (("band_scatter.hip", "fftpl_internal.hpp"),
-        "ce6342ab6d88b496996a0edec09e0708a1d9faf4", 27909.4, 4096.0),
+        "ce6342ab6d88b496996a0edec09e0708a1d9faf4", 27909.0, 4096.0),
     "k_xch_wa": (("exchange.hip", "fftpl_internal.hpp"),
-        "da6bdc1258df44286116bda9072aa280bf821339", 175494.3, 111000.2),
+        "54250ba9f3403f84a79dc41d2fda149099fcbb61", 175549.3, 111001.4),
     "k_rows_dct2": (("spectral_fft.hip", "fftpl_internal.hpp"),
         "d52da1318ece596a0f48c11873097abcd4129ba4", 6235.2, 4112.0),
     "k_cols_solve": (("spectral_fft.hip", "fftpl_internal.hpp"),
@@ -46,9 +46,9 @@ PMC_TRAFFIC = {
     "k_rows_inverse": (("spectral_fft.hip", "fftpl_internal.hpp"),
         "d52da1318ece596a0f48c11873097abcd4129ba4", 6265.6, 8196.0),
     "k_band_gather": (("band_scatter.hip", "fftpl_internal.hpp"),
-        "ce6342ab6d88b496996a0edec09e0708a1d9faf4", 30981.6, 21041.8),
+        "ce6342ab6d88b496996a0edec09e0708a1d9faf4", 30981.9, 21042.8),
     "k_xch_cellsum": (("exchange.hip", "fftpl_internal.hpp"),
-        "da6bdc1258df44286116bda9072aa280bf821339", 77638.5, 16406.5),
+        "54250ba9f3403f84a79dc41d2fda149099fcbb61", 77617.1, 16406.5),
 }
 
 

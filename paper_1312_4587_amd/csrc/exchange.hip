@@ -37,6 +37,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <atomic>
 #include <vector>
 
 #include "fftpl_internal.hpp"
@@ -54,6 +55,7 @@ constexpr int NW = kXchWaThreads;
 // kXchPinLds2 pins, or up to kXchPinCap
 constexpr int kStageS = (kXchPinLds2 + NW - 1) / NW;
 constexpr int kStageL = (kXchPinCap + NW - 1) / NW;
+constexpr int kMaxDevices = 64;     // device ordinals with a per-device flag
 constexpr int kSumThreads = 1024;   // cell sums: one block per cell block
 
 inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -851,14 +853,20 @@ hipError_t launch_xch_wa_model(const XchDims& d, const XchIndex& X, const int32_
                        d.cap, net_ptr, X.nb_net_ptr, X.nmeta, X.a_of_b, X.lcsr, pin_dx, pin_dy,
                        gamma, 1.0f / gamma, T, wa_part);
   } else {
-    // more than 64 KiB of dynamic LDS has to be allowed explicitly
-    static bool attr = false;
-    if (!attr) {
-      hipError_t e = hipFuncSetAttribute(
-          reinterpret_cast<const void*>(&k_xch_wa<kStageL, LSE>),
-          hipFuncAttributeMaxDynamicSharedMemorySize, (int)(sizeof(float2) * 2 * kXchPinCap));
+    // more than 64 KiB of dynamic LDS has to be allowed explicitly, once per
+    // device (the flags are per kernel instantiation; setting the attribute
+    // twice from racing threads is harmless)
+    static std::atomic<bool> attr[kMaxDevices];
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    if (!attr[dev].load(std::memory_order_acquire)) {
+      e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_xch_wa<kStageL, LSE>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)(sizeof(float2) * 2 * kXchPinCap));
       if (e != hipSuccess) return e;
-      attr = true;
+      attr[dev].store(true, std::memory_order_release);
     }
     hipLaunchKernelGGL((k_xch_wa<kStageL, LSE>), dim3(d.nnb), dim3(NW), lds, s, d.num_pins,
                        d.cap, net_ptr, X.nb_net_ptr, X.nmeta, X.a_of_b, X.lcsr, pin_dx, pin_dy,
