@@ -1,7 +1,8 @@
 """Exchange-index wirelength path of fftpl_eval against the FP64 oracle:
 many cell and net blocks, ragged last blocks, empty / one-pin / very large
-nets, repeated evaluations with new positions on one index, and the index
-build's refusal of malformed netlists."""
+nets, repeated evaluations with new positions on one index, the index
+build's refusal of malformed netlists, and the two-stream schedule against
+the one-stream one (bit-identical)."""
 import dataclasses
 
 import numpy as np
@@ -9,6 +10,7 @@ import pytest
 
 import gen
 import oracle
+from _helpers import rel_l2
 from tests.gpu_common import RTOL, dev, host, lib_or_build, say
 from tests.test_gpu_parity import _check_eval, _run_eval
 
@@ -108,3 +110,49 @@ def test_exchange_build_rejects_malformed_netlists(F):
         with pytest.raises(F.FFTPLError) as ei:
             _build(F, m, ptr, pc, md)
         assert ei.value.status == F.E_INVAL, name
+
+
+@pytest.mark.parametrize("path", ["xch", "slots"])
+def test_two_stream_schedule_matches_one_stream(F, path):
+    # The evaluation normally forks its wirelength branch to the plan's side
+    # stream and joins it before the cell sums; with per-kernel timing on,
+    # everything runs in order on the caller's stream.  Every sum in the
+    # evaluation is order-independent (fixed-point LDS adds, fixed-order
+    # block partials), so both schedules must give the same bits, also for
+    # evaluations enqueued back to back with new positions and no host wait
+    # between them (the next fork must wait for the previous cell sums).
+    import torch
+    from tests.gpu_common import DeviceCells
+    inst = gen.make_instance(31, num_cells=120_000, util=0.8, n=512, num_nets=130_000,
+                             hi_frac=0.01, hi_range=(20, 500))
+    m = inst.num_cells
+    rng = np.random.default_rng(31)
+    insts = [inst]
+    for _ in range(2):
+        x = np.clip(insts[-1].x + rng.normal(0, 2.0, m), 0, inst.side)
+        y = np.clip(insts[-1].y + rng.normal(0, 2.0, m), 0, inst.side)
+        insts.append(insts[-1].with_positions(x, y))
+    say("two-stream schedule", path, m, inst.num_pins)
+    prob = F.Problem.from_instance(inst, path=path)
+    assert prob.path == path
+    plan = F.Plan(inst.n, "fft")
+    cells = [DeviceCells(i) for i in insts]
+    outs = {}
+    for timing in (True, False):
+        plan.timing(timing)
+        bufs = [(torch.empty(m, device="cuda"), torch.empty(m, device="cuda"),
+                 torch.empty(4, dtype=torch.float64, device="cuda")) for _ in insts]
+        for c, (gx, gy, o4) in zip(cells, bufs):
+            F.eval(plan, prob, c.x, c.y, 1.5, inst.gamma, "field", gx, gy, o4)
+        torch.cuda.synchronize()
+        outs[timing] = [[host(t) for t in b] for b in bufs]
+    plan.timing(False)
+    plan.close()
+    for one, two in zip(outs[True], outs[False]):
+        for a, b in zip(one, two):
+            assert np.array_equal(a, b)
+    # and the last of them against the oracle
+    gx, gy, out = outs[False][-1]
+    ref = oracle.evaluate(insts[-1], lam=1.5, grad_mode="field")
+    assert rel_l2(gx, ref["gx"]) < RTOL and rel_l2(gy, ref["gy"]) < RTOL
+    assert abs(out[1] - ref["wa"]) < RTOL * abs(ref["wa"])
