@@ -32,23 +32,23 @@ PMC_FETCH_SCALE, PMC_WRITE_SCALE = 2.0, 1.0
 PMC_TRAFFIC = {
     # kernel: (source files, sha1, FETCH_SIZE KiB, WRITE_SIZE KiB)
     "k_band_place": (("band_scatter.hip", "fftpl_internal.hpp"),
-        "ce6342ab6d88b496996a0edec09e0708a1d9faf4", 16523.2, 64976.0),
+        "69d7a4c591392f2afd52c70f6eb0a576917e8a08", 16523.3, 64900.7),
     "k_xch_spread": (("exchange.hip", "fftpl_internal.hpp"),
-        "54250ba9f3403f84a79dc41d2fda149099fcbb61", 28602.6, 96875.7),
+        "cc51d2a3fd685c7c4fcf4a3e6952cd82e70a3008", 28614.9, 96897.2),
     "k_band_accum": (("band_scatter.hip", "fftpl_internal.hpp"),
-        "ce6342ab6d88b496996a0edec09e0708a1d9faf4", 27909.0, 4096.0),
+        "69d7a4c591392f2afd52c70f6eb0a576917e8a08", 27909.0, 4096.0),
     "k_xch_wa": (("exchange.hip", "fftpl_internal.hpp"),
-        "54250ba9f3403f84a79dc41d2fda149099fcbb61", 175549.3, 111001.4),
+        "cc51d2a3fd685c7c4fcf4a3e6952cd82e70a3008", 178810.8, 112288.7),
     "k_rows_dct2": (("spectral_fft.hip", "fftpl_internal.hpp"),
-        "d52da1318ece596a0f48c11873097abcd4129ba4", 6235.2, 4112.0),
+        "fe3cf6061cae301ed67348ad9ef5d0c35619f22a", 6235.3, 4112.0),
     "k_cols_solve": (("spectral_fft.hip", "fftpl_internal.hpp"),
-        "d52da1318ece596a0f48c11873097abcd4129ba4", 2180.1, 8192.0),
+        "fe3cf6061cae301ed67348ad9ef5d0c35619f22a", 2180.1, 8192.0),
     "k_rows_inverse": (("spectral_fft.hip", "fftpl_internal.hpp"),
-        "d52da1318ece596a0f48c11873097abcd4129ba4", 6265.6, 8196.0),
+        "fe3cf6061cae301ed67348ad9ef5d0c35619f22a", 6265.6, 8196.0),
     "k_band_gather": (("band_scatter.hip", "fftpl_internal.hpp"),
-        "ce6342ab6d88b496996a0edec09e0708a1d9faf4", 30981.9, 21042.8),
+        "69d7a4c591392f2afd52c70f6eb0a576917e8a08", 30982.0, 21043.8),
     "k_xch_cellsum": (("exchange.hip", "fftpl_internal.hpp"),
-        "54250ba9f3403f84a79dc41d2fda149099fcbb61", 77617.1, 16406.5),
+        "cc51d2a3fd685c7c4fcf4a3e6952cd82e70a3008", 80991.5, 16406.5),
 }
 
 

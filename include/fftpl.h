@@ -310,7 +310,7 @@ int fftpl_netlist_index(int32_t num_cells, int32_t num_pins, const int32_t* pin_
 /* Exchange index of a netlist (Section II: the netlist as a hypergraph; the
  * index is a blocked form of the transpose of its pin-net incidence), for the
  * fastest fftpl_eval path.  Cells are cut into blocks of consecutive cells
- * (a multiple of 1024 cells, at most 9216, about one block per compute unit)
+ * (a multiple of 256 cells, at most 9216, about one block per compute unit)
  * and nets into blocks of whole nets (at most 9728 pins per block); the
  * index lists the pins by (cell block, net block) and, per net block, by cell
  * block, so that positions and gradients move between cells and nets in runs

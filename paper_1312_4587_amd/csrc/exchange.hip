@@ -7,7 +7,7 @@
 // write, each of which moves a whole cache line.  Here the permutation is
 // split in two halves that both run through LDS:
 //
-//   cell blocks: cpb consecutive cells (a multiple of 1024, at most kXchCells,
+//   cell blocks: cpb consecutive cells (a multiple of 256, at most kXchCells,
 //                about one block per CU);
 //   net blocks:  whole nets packed in CSR order, as many as fit in cap =
 //                npt - 1 + max_degree <= kXchPinCap pins, so every block but

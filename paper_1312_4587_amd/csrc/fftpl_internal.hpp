@@ -607,7 +607,7 @@ hipError_t launch_exclusive_scan(const int32_t* in, int count, int32_t* out, int
 // then run in a single round at any size up to 2.36M cells, and small designs
 // still spread over the chip.
 constexpr int kXchCells = 9216;
-constexpr int kXchCellStep = 1024;
+constexpr int kXchCellStep = 256;
 constexpr int kNumCus = 256;           // compute units of an MI355X (gfx950)
 constexpr int kXchSpreadSplit = 2;     // spread blocks per cell block
 constexpr int kXchThreads = 512;       // threads of the cell-block kernels
