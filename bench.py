@@ -78,7 +78,7 @@ def parse():
     ap.add_argument("--variants", default="fft,gemm_f32,gemm_bf16x3",
                     help="spectral variants to time besides --dct")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-evals", type=int, default=5)
+    ap.add_argument("--cpu-evals", type=int, default=3)
     ap.add_argument("--kernel-reps", type=int, default=0,
                     help="evaluations timed kernel by kernel (default max(10, steps/4))")
     ap.add_argument("--no-precision", action="store_true",
@@ -192,9 +192,10 @@ def band_entries(inst):
 
 
 def kernel_bytes(inst, nent):
-    """Algorithmic bytes per launch of every kernel of the atomic-free
-    evaluation: compulsory reads and writes of its inputs and outputs in the
-    float32 structure-of-arrays layout (entries are 16-byte band records)."""
+    """Design bytes per launch of every kernel of the atomic-free evaluation:
+    each array the kernel's own layout reads or writes, once (index arrays,
+    the exchange buffer and the 16-byte band records included).  These are
+    not the compulsory bytes of stage_bytes."""
     import numpy as np
     m, E, P, n2 = inst.num_cells, inst.num_nets, inst.num_pins, inst.n ** 2
     deg = np.diff(inst.net_ptr.astype(np.int64))
@@ -237,14 +238,60 @@ def gemm_flops(n):
 
 
 def stage_bytes(inst):
-    """Compulsory bytes per stage of one evaluation, implementation-free."""
+    """Compulsory (algorithmic) bytes per step of one evaluation, whatever the
+    implementation: each input read once and each output written once in the
+    float32 structure-of-arrays layout (cells x, y, w, h; maps n*n; pins
+    (cell, dx, dy); net_ptr)."""
     m, E, P, n2 = inst.num_cells, inst.num_nets, inst.num_pins, inst.n ** 2
     return {
-        "density": 16 * m + 4 * n2 + 4 * n2,          # cells in; base in; rho out
-        "spectral": 4 * n2 * 4,                       # rho in; psi, Ex, Ey out
-        "gather": 16 * m + 8 * n2 + 8 * m,            # cells, E in; g out
-        "wirelength": 12 * P + 4 * (E + 1) + 8 * m + 8 * m,   # pins, nets, x, y in; g out
+        # a2: cells in; base in; rho out
+        "a2_scatter": 16 * m + 4 * n2 + 4 * n2,
+        # a3-a5: rho in; psi, Ex, Ey out
+        "a3_a5_spectral": 4 * n2 * 4,
+        # a6: cells and the field maps in; g out
+        "a6_gather": 16 * m + 8 * n2 + 8 * m,
+        # a8: pins and net_ptr in; x, y in; g read-modify-write counted once
+        "a8_wirelength": 12 * P + 4 * E + 8 * m + 8 * m,
     }
+
+
+# The kernels that carry each step (whichever path or spectral variant ran).
+# k_xch_cellsum sums each cell's pin gradients (a8) and adds lambda times the
+# density gradient (a9); its time is booked to a8.
+STAGE_KERNELS = {
+    "a2_scatter": ("k_band_place", "k_band_accum", "k_fill", "k_scatter"),
+    "a3_a5_spectral": ("k_rows_dct2", "k_cols_solve", "k_rows_inverse", "k_gemm_rowsum",
+                       "k_gemm_prep", "k_gemm_w", "k_gemm_g", "k_gemm_uv",
+                       "k_gemm_psi_ey", "k_gemm_ex"),
+    "a6_gather": ("k_band_gather", "k_gather", "k_gather_pins"),
+    "a8_wirelength": ("k_xch_spread", "k_xch_wa", "k_xch_cellsum", "k_interleave",
+                      "k_wa_slots_small", "k_wa_slots_big", "k_wa_atomic"),
+}
+
+
+def stage_table(kernels, sb, eval_ms):
+    """Per step: its kernels' summed event time (kernels timed one at a time),
+    the compulsory bytes over that time against the HBM peak, and the counter
+    traffic of its kernels over the compulsory bytes."""
+    out = {}
+    for st, names in STAGE_KERNELS.items():
+        ks = [k for k in names if k in kernels]
+        if not ks:
+            continue
+        t = sum(kernels[k]["ms"] for k in ks)
+        row = {"kernels": ks, "ms": t, "algorithmic_bytes": sb[st],
+               "GBps": sb[st] / (t / 1e3) / 1e9}
+        row["frac"] = row["GBps"] / HBM_PEAK_GBS
+        pmc = [kernels[k].get("pmc_hbm_bytes") for k in ks]
+        if all(v is not None for v in pmc):
+            row["pmc_hbm_bytes"] = sum(pmc)
+            row["traffic_over_algorithmic"] = sum(pmc) / sb[st]
+        out[st] = row
+    tot = sum(sb.values())
+    out["evaluation"] = {"ms": eval_ms, "algorithmic_bytes": tot,
+                         "GBps": tot / (eval_ms / 1e3) / 1e9,
+                         "frac": tot / (eval_ms / 1e3) / 1e9 / HBM_PEAK_GBS}
+    return out
 
 
 def time_loop(fn, steps, stream):
@@ -272,23 +319,62 @@ def per_step_times(fn, steps, stream):
     return [evs[i].elapsed_time(evs[i + 1]) for i in range(steps)]
 
 
-def cpu_baseline(inst, evals):
-    import oracle
+def cpu_model():
     try:
-        from threadpoolctl import threadpool_info
-        cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
-    except Exception:  # pragma: no cover
-        cores = 1
-    t0 = time.perf_counter()
-    for _ in range(evals):
-        ref = oracle.evaluate(inst, lam=1.0, grad_mode="field")
-    dt = (time.perf_counter() - t0) / evals
-    return {"value": inst.num_cells / dt, "unit": "cell-gradient evals/s",
-            "cores": int(cores), "kind": "oracle",
-            "sample": (f"{evals} full FP64 oracle evaluation(s) of the same "
-                       f"{inst.num_cells}-cell n={inst.n} workload, {dt:.2f} s each; "
-                       "numpy, BLAS threads for the dense cosine sums, the rest "
-                       "single-threaded")}, ref
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(inst, name, evals, other_configs=("small_2k", "mid_200k")):
+    """The FP64 oracle as it stands, timed on this machine's host cores: one
+    leg with a single BLAS thread and one with every core, on the benchmark
+    workload and on the smaller workloads.  The headline figure is the
+    benchmark workload on every core.  Returns (record, oracle result of the
+    benchmark workload)."""
+    import gen
+    import oracle
+    from threadpoolctl import threadpool_info, threadpool_limits
+    nproc = os.cpu_count() or 1
+    legs = []
+    ref = None
+
+    def leg(name, ins, threads, reps):
+        nonlocal ref
+        with threadpool_limits(threads):
+            used = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                r = oracle.evaluate(ins, lam=1.0, grad_mode="field")
+            dt = (time.perf_counter() - t0) / reps
+        if ins is inst:
+            ref = r
+        legs.append({"workload": name, "cells": ins.num_cells, "grid_n": ins.n,
+                     "threads": int(used), "evals": reps, "s_per_eval": dt,
+                     "value": ins.num_cells / dt})
+
+    leg(name, inst, nproc, evals)
+    leg(name, inst, 1, 1)
+    for name in other_configs:
+        ins = gen.make_config(name)
+        reps = 20 if ins.num_cells <= 10_000 else 2
+        leg(name, ins, nproc, reps)
+        leg(name, ins, 1, reps)
+    head = legs[0]
+    rec = {"value": head["value"], "unit": "cell-gradient evals/s",
+           "cores": head["threads"], "kind": "oracle",
+           "sample": (f"{evals} full FP64 oracle evaluation(s) of the same "
+                      f"{inst.num_cells}-cell n={inst.n} workload, "
+                      f"{head['s_per_eval']:.2f} s each, numpy with "
+                      f"{head['threads']} BLAS threads (the dense cosine sums; the "
+                      "rest is single-threaded); further legs: one thread, and the "
+                      "2k- and 200k-cell workloads"),
+           "nproc": nproc, "cpu_model": cpu_model(), "legs": legs}
+    return rec, ref
 
 
 def main():
@@ -408,19 +494,34 @@ def main():
         if mode != args.dct and "ms_per_eval" in variants[mode] and mode in ("gemm_f32",
                                                                             "gemm_bf16x3"):
             variant_kernels[mode] = kernel_table(mode)
-    hbm = {k: v for k, v in kernels.items() if v.get("GBps")}
-    dom = max(hbm, key=lambda k: hbm[k]["ms"])
-    ach = kernels[dom]["GBps"]
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": pmc_traffic(dom),
-                "algorithmic_bytes": kernels[dom]["algorithmic_bytes"]}
     for k, v in kernels.items():
         t = pmc_traffic(k)
         if t is not None:
             v["pmc_hbm_bytes"] = t
     sb = stage_bytes(inst)
-    stages = {"algorithmic_bytes": sb,
-              "eval_GBps": sum(sb.values()) / (ms / 1e3) / 1e9}
+    stages = stage_table(kernels, sb, ms)
+    # The dominant kernel: the longest one of the HBM-bound steps.  `achieved`
+    # books its whole step's compulsory bytes to it (the other kernels of the
+    # step get none); the step's own fraction over all its kernels is the
+    # stages entry.  `design_bytes` are what the kernel's own layout reads and
+    # writes once (index arrays, the exchange buffer).
+    hbm_steps = ("a2_scatter", "a6_gather", "a8_wirelength")
+    cands = [(kernels[k]["ms"], k, st) for st in hbm_steps if st in stages
+             for k in stages[st]["kernels"]]
+    _, dom, dom_st = max(cands)
+    ach = sb[dom_st] / (kernels[dom]["ms"] / 1e3) / 1e9
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": pmc_traffic(dom),
+                "algorithmic_bytes": sb[dom_st], "step": dom_st,
+                "kernel_ms": kernels[dom]["ms"],
+                "design_bytes": kernels[dom].get("algorithmic_bytes"),
+                "step_frac": stages[dom_st]["frac"],
+                "evaluation_frac": stages["evaluation"]["frac"]}
+    for k, v in kernels.items():
+        if "algorithmic_bytes" in v:
+            # per kernel: bytes of its own layout (not the step's compulsory bytes)
+            v["design_bytes"] = v.pop("algorithmic_bytes")
+            v["design_GBps"] = v.pop("GBps")
 
     res = {
         "metric": METRIC, "value": value, "unit": "cell-gradient evals/s",
@@ -437,7 +538,7 @@ def main():
     }
     ref = None
     if not args.no_cpu_baseline:
-        res["cpu_baseline"], ref = cpu_baseline(inst, args.cpu_evals)
+        res["cpu_baseline"], ref = cpu_baseline(inst, args.workload, args.cpu_evals)
     if not args.no_precision:
         if ref is None:
             import oracle
