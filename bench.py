@@ -389,9 +389,8 @@ def main():
     import gen
     from paper_1312_4587_amd import _lib, fftpl
 
-    if not os.path.exists(_lib.LIB_PATH):
-        from paper_1312_4587_amd import build
-        build.build()
+    from paper_1312_4587_amd import build
+    build.ensure_built()   # rebuilt when the sources differ from the built ones
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     if args.calibrate_copy:

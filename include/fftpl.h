@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define FFTPL_VERSION 10000 /* major*10000 + minor*100 + patch */
+#define FFTPL_VERSION 20000 /* major*10000 + minor*100 + patch */
 
 enum fftpl_status {
   FFTPL_OK = 0,
@@ -97,8 +97,9 @@ typedef struct fftpl_grid {
   double target_density;
 } fftpl_grid;
 
-/* Opaque: twiddle/trigonometric tables and map workspace for one n and one
- * dct_mode.  About 36*n*n bytes of device memory at n = 1024. */
+/* Opaque: twiddle/trigonometric tables and map workspace for one n, one
+ * dct_mode and up to max_batch designs evaluated together (fftpl_eval_batch).
+ * About 36*n*n bytes of device memory per batch slot at n = 1024. */
 typedef struct fftpl_plan fftpl_plan;
 
 /* A static netlist and fixed charge; references caller-owned device arrays,
@@ -116,14 +117,20 @@ typedef struct fftpl_plan fftpl_plan;
  * (work and xindex 256-byte aligned, as device allocations are; otherwise
  * fftpl_eval returns FFTPL_E_INVAL):
  *   - the exchange index (fastest): xindex / xindex_bytes from
- *     fftpl_xindex_build for this netlist and max_degree;
+ *     fftpl_xindex_build for this netlist and max_degree, and xindex_key, the
+ *     key that build returned;
  *   - or the cell-major slots: cell_ptr [num_cells+1] and pin_slot
  *     [num_pins] from fftpl_netlist_index.
- * When work or both indexes are missing (or work_bytes / xindex_bytes are
- * too small) fftpl_eval uses float atomics for the density scatter and the
- * wirelength gradient instead.  All paths give the same results up to
- * float32 rounding order.  An index must be rebuilt when net_ptr or pin_cell
- * change; pin offsets and positions may change freely.
+ * With neither work nor an index fftpl_eval uses float atomics for the density
+ * scatter and the wirelength gradient (fftpl_problem_path reports which path
+ * a problem takes).  A workspace or an index that is given but cannot be
+ * used is an error, never a silent change of path: FFTPL_E_UNSUPPORTED for
+ * n > 1024, FFTPL_E_INVAL for a missing or too small workspace or index,
+ * FFTPL_E_STATE when xindex_key does not match the sizes, max_degree,
+ * net_ptr, pin_cell and xindex of the problem (an index built for another
+ * netlist).  All paths give the same results up to float32 rounding order.
+ * An index must be rebuilt when net_ptr or pin_cell change; pin offsets and
+ * positions may change freely.
  *
  * wl_model selects the wirelength term W~ (enum fftpl_wl_model; 0 is the
  * paper's weighted average).  screening is eps >= 0 of the screened solve
@@ -150,7 +157,17 @@ typedef struct fftpl_problem {
   uint64_t xindex_bytes;
   int32_t max_degree; /* the value xindex was built for */
   float screening;    /* eps >= 0, bin^-2 units; 0 = Poisson */
+  uint64_t xindex_key; /* returned by fftpl_xindex_build for xindex */
 } fftpl_problem;
+
+/* Which implementation of the density scatter and the wirelength gradient an
+ * evaluation of a problem takes (fftpl_problem_path). */
+enum fftpl_path {
+  FFTPL_PATH_EXCHANGE = 0, /* banded LDS scatter, bucketed pin exchange:
+                              no float atomics, bit-repeatable              */
+  FFTPL_PATH_SLOTS = 1,    /* banded LDS scatter, cell-major pin slots      */
+  FFTPL_PATH_ATOMIC = 2    /* float atomics for both (no workspace, no index) */
+};
 
 /* Library version (FFTPL_VERSION of the build). */
 int fftpl_version(void);
@@ -158,19 +175,24 @@ int fftpl_version(void);
 /* Static, NUL-terminated description of a status code. */
 const char* fftpl_status_string(int status);
 
-/* Create a plan for grid side n and a dct_mode.  FFTPL_DCT_FFT needs n a
- * power of two with 8 <= n <= 1024 (the paper's grids are powers of two up to
- * 1024, Section IV-A); the GEMM modes need n a multiple of 64 with
- * 64 <= n <= 4096.  Tables are uploaded on `stream`.  On success *out owns
- * device memory until fftpl_plan_destroy.  Errors: FFTPL_E_INVAL (NULL out,
- * bad mode), FFTPL_E_UNSUPPORTED (n), FFTPL_E_NOMEM, FFTPL_E_DEVICE. */
-int fftpl_plan_create(fftpl_plan** out, int32_t n, int32_t dct_mode, void* stream);
+/* Create a plan for grid side n, a dct_mode and batches of up to max_batch
+ * designs (1 <= max_batch <= FFTPL_MAX_BATCH; fftpl_eval_batch evaluates that
+ * many designs in one launch per stage).  FFTPL_DCT_FFT needs n a power of two
+ * with 8 <= n <= 1024 (the paper's grids are powers of two up to 1024, Section
+ * IV-A); the GEMM modes need n a multiple of 64 with 64 <= n <= 4096.  Tables
+ * are uploaded on `stream`.  On success *out owns device memory until
+ * fftpl_plan_destroy.  Errors: FFTPL_E_INVAL (NULL out, bad mode or
+ * max_batch), FFTPL_E_UNSUPPORTED (n), FFTPL_E_NOMEM, FFTPL_E_DEVICE. */
+#define FFTPL_MAX_BATCH 8
+int fftpl_plan_create(fftpl_plan** out, int32_t n, int32_t dct_mode, int32_t max_batch,
+                      void* stream);
 
 /* Destroy a plan (synchronises the device first).  NULL is accepted. */
 int fftpl_plan_destroy(fftpl_plan* plan);
 
-/* Side n and dct_mode of a plan. */
-int fftpl_plan_info(const fftpl_plan* plan, int32_t* n, int32_t* dct_mode);
+/* Side n, dct_mode and max_batch of a plan (any output may be NULL). */
+int fftpl_plan_info(const fftpl_plan* plan, int32_t* n, int32_t* dct_mode,
+                    int32_t* max_batch);
 
 /* Device pointers of the maps the last fftpl_eval on this plan produced, for
  * inspection: rho [n*n], psi [n*n] (written in FFTPL_GRAD_EXACT mode), exy
@@ -179,7 +201,11 @@ int fftpl_plan_info(const fftpl_plan* plan, int32_t* n, int32_t* dct_mode);
  * (psi[iy][ix+1] - psi[iy][ix], psi[iy+1][ix] - psi[iy][ix]), computed in the
  * spectral domain (Section III-C: the exact gradient sums them; taking them
  * as differences of rounded psi values would lose their leading digits).
- * Owned by the plan.  Any pointer argument may be NULL. */
+ * Owned by the plan.  Any pointer argument may be NULL.  After
+ * fftpl_eval_batch the maps of the batch's request i follow at offsets
+ * i*n*n (rho, psi) and i*2*n*n (exy) floats from these pointers, for the
+ * requests evaluated together in the call's last group (see
+ * fftpl_eval_batch). */
 int fftpl_plan_maps(const fftpl_plan* plan, const float** rho, const float** psi,
                     const float** exy);
 
@@ -223,11 +249,27 @@ int fftpl_dark_nodes(double xl, double yl, double xh, double yh, int32_t num_rec
 
 /* Density map (Eq. (2), Section III-B): rho = base + sum over movable cells of
  * their overlap area with each bin.  base may be NULL (treated as 0).  rho is
- * overwritten; accumulation uses float atomics, so the rounding order (not
- * the value beyond float32 rounding) varies between runs. */
+ * overwritten.  This stateless form has no workspace and accumulates with
+ * float atomics, so the rounding order (not the value beyond float32
+ * rounding) varies between runs and it runs several times slower than
+ * fftpl_problem_density, the workspace-backed form. */
 int fftpl_density_map(const fftpl_grid* grid, int32_t num_cells, const float* x,
                       const float* y, const float* w, const float* h,
                       const float* base, float* rho, void* stream);
+
+/* The density map of a problem's cells at positions x, y [num_cells], the
+ * same quantity as fftpl_density_map with grid, w, h and base from prob,
+ * computed without float atomics in prob->work (banded counting sort of the
+ * cells, fixed-point sums in LDS): rho [n*n] is the same on every run.  Needs
+ * prob->work (FFTPL_E_INVAL otherwise) and n <= 1024
+ * (FFTPL_E_UNSUPPORTED).  The netlist fields of prob are not read. */
+int fftpl_problem_density(const fftpl_problem* prob, const float* x, const float* y,
+                          float* rho, void* stream);
+
+/* Path an evaluation of prob takes (enum fftpl_path) into *path, or the
+ * status fftpl_eval would return for the problem's workspace and index
+ * fields.  Host-only; reads no device memory. */
+int fftpl_problem_path(const fftpl_problem* prob, int32_t* path);
 
 /* Spectral Neumann Poisson solve (Eqs. (8)-(12)) on the plan's grid:
  *   a_uv = (c_u c_v / n^2) sum rho cos(w_u (ix+1/2)) cos(w_v (iy+1/2)),
@@ -288,6 +330,19 @@ int fftpl_lse_grad(int32_t num_nets, const int32_t* net_ptr, int32_t num_pins,
                    int32_t accumulate, float* gx, float* gy, double* wa, double* hpwl,
                    void* stream);
 
+/* The wirelength term of a problem (prob->wl_model: Eq. (3) or log-sum-exp)
+ * at positions x, y [num_cells]: adds (accumulate = 1) or writes
+ * (accumulate = 0) each cell's summed pin gradient into gx, gy [num_cells];
+ * wl and hpwl, if not NULL, are device doubles set to the totals.  The same
+ * quantities as fftpl_wa_grad / fftpl_lse_grad, through the bucketed pin
+ * exchange of prob->xindex (its key in prob->xindex_key) in prob->work,
+ * without float atomics: the result is the same on every run.  Errors as for
+ * an evaluation of prob (FFTPL_E_INVAL without work or xindex,
+ * FFTPL_E_STATE for an index of another netlist); gamma > 0. */
+int fftpl_problem_wl_grad(const fftpl_problem* prob, const float* x, const float* y,
+                          float gamma, int32_t accumulate, float* gx, float* gy, double* wl,
+                          double* hpwl, void* stream);
+
 /* Bytes of the optional fftpl_problem workspace for grid side n, num_cells
  * cells, num_nets nets and num_pins pins (the interleaved positions, per-pin
  * gradients, band lists of the density scatter, their counters, and per-block
@@ -323,8 +378,11 @@ int fftpl_netlist_index(int32_t num_cells, int32_t num_pins, const int32_t* pin_
  * fftpl_xindex_build: builds the index into `index` (index_bytes, caller
  * owned, 256-byte aligned; valid until net_ptr or pin_cell change) using
  * `work` (work_bytes, 256-byte aligned, free again on return), on `stream`,
- * and waits for it (the call
- * synchronises the stream).  FFTPL_E_INVAL when a net has more than
+ * and waits for it (the call synchronises the stream).  *key (if key is not
+ * NULL) receives a host-side fingerprint of the sizes, max_degree and the
+ * net_ptr, pin_cell and index pointers; a problem using the index carries it
+ * in xindex_key, so that an index built for another netlist is refused on the
+ * host without reading device memory.  FFTPL_E_INVAL when a net has more than
  * max_degree pins, when net_ptr is not a CSR over num_pins pins or when a
  * pin_cell lies outside [0, num_cells); the index is then unusable. */
 int fftpl_xindex_bytes(int32_t num_cells, int32_t num_nets, int32_t num_pins,
@@ -332,7 +390,7 @@ int fftpl_xindex_bytes(int32_t num_cells, int32_t num_nets, int32_t num_pins,
 int fftpl_xindex_build(int32_t num_cells, int32_t num_nets, int32_t num_pins,
                        const int32_t* net_ptr, const int32_t* pin_cell, int32_t max_degree,
                        void* index, uint64_t index_bytes, void* work, uint64_t work_bytes,
-                       void* stream);
+                       uint64_t* key, void* stream);
 
 /* One full evaluation (Algorithm 1, the density / FFT solve / gradient steps):
  *   rho = base + cells; Poisson solve (screened when prob->screening > 0);
@@ -342,7 +400,9 @@ int fftpl_xindex_build(int32_t num_cells, int32_t num_nets, int32_t num_pins,
  * gx, gy [num_cells] are overwritten.  prob->grid.n must equal the plan's n.
  * With gx = gy = NULL only out4 is computed (the loss W~ + lambda N and the
  * other scalars, without the gather); this needs a workspace and an index in
- * prob (FFTPL_E_INVAL otherwise).  With a workspace and an index the
+ * prob (FFTPL_E_INVAL otherwise).  A workspace or index that prob gives but
+ * that cannot be used is an error (see fftpl_problem), not a silent change
+ * of path.  With a workspace and an index the
  * wirelength branch (pin positions, net blocks) runs on the plan's own stream
  * concurrently with the density branch (scatter, solve, per-cell density
  * gradient) on `stream`, and is joined back before the per-cell sums; the
@@ -354,16 +414,21 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
                float* gx, float* gy, double* out4, void* stream);
 
 /* Serving extension: count evaluations of designs that share the plan's grid
- * side, in order on `stream`, request i exactly as
+ * side, with the results of
  *   fftpl_eval(plan, probs[i], xs[i], ys[i], lambdas[i], gammas[i], grad_mode,
- *              gxs ? gxs[i] : NULL, gys ? gys[i] : NULL, out4s + 4*i, stream).
- * probs, xs, ys, lambdas, gammas, gxs and gys are HOST arrays of count entries
- * (gxs and gys both NULL: the scalars only, for every request); the pointers
- * they hold and out4s (double [4*count]) are device memory.  Every request is
- * checked on the host before anything is enqueued: on an argument error
- * nothing runs and the status of the first failing request is returned.
- * Requests may share a workspace (they run one after another).  count = 0 is
- * a no-op. */
+ *              gxs ? gxs[i] : NULL, gys ? gys[i] : NULL, out4s + 4*i, stream)
+ * for every i.  probs, xs, ys, lambdas, gammas, gxs and gys are HOST arrays of
+ * count entries (gxs and gys both NULL: the scalars only, for every request);
+ * the pointers they hold and out4s (double [4*count]) are device memory.
+ * Requests are taken in order in groups of up to the plan's max_batch that
+ * take the exchange path, have workspaces that do not overlap and share the
+ * wirelength model and net-block size class; each group runs every stage
+ * (scatter, the three FFT passes, field gather, pin exchange, per-cell sums)
+ * as one launch over all of its designs (GEMM plans run the solve of each
+ * design in turn inside the group).  Requests that cannot join a group run
+ * alone.  Every request is checked on the host before anything is enqueued:
+ * on an argument error nothing runs and the status of the first failing
+ * request is returned.  count = 0 is a no-op. */
 int fftpl_eval_batch(fftpl_plan* plan, int32_t count, const fftpl_problem* const* probs,
                      const float* const* xs, const float* const* ys, const float* lambdas,
                      const float* gammas, int32_t grad_mode, float* const* gxs,
@@ -400,6 +465,16 @@ int fftpl_nesterov_update(const fftpl_grid* region, int32_t num_cells, const flo
 int fftpl_debug_cell_bins(const fftpl_grid* grid, int32_t num_cells, const float* x,
                           const float* y, const float* w, const float* h,
                           int32_t* ranges, void* stream);
+
+/* Test export: per-net values as the exchange path computes them (Eqs. (1),
+ * (3), or the log-sum-exp model per prob->wl_model), for a problem with an
+ * exchange index and workspace: for every net e with at least one pin,
+ * wl_first[net_ptr[e]] = its wirelength term over both axes and
+ * hpwl_first[net_ptr[e]] = its half-perimeter; device double arrays
+ * [num_pins] whose other entries are left as they are.  Errors as for
+ * fftpl_problem_wl_grad. */
+int fftpl_debug_net_values(const fftpl_problem* prob, const float* x, const float* y,
+                           float gamma, double* wl_first, double* hpwl_first, void* stream);
 
 #ifdef __cplusplus
 }

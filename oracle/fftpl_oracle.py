@@ -52,7 +52,7 @@ __all__ = [
     "dct_coefficients", "dct_coefficients_literal", "remove_dc",
     "spectral_potential", "potential_field", "poisson_solve", "energy",
     "field_gradient", "exact_gradient", "wa_wirelength", "lse_wirelength",
-    "hpwl",
+    "hpwl", "net_values",
     "overflow", "evaluate", "local_fd_gradient", "potential_differences",
 ]
 
@@ -463,6 +463,32 @@ def hpwl(inst, x=None, y=None) -> float:
         tot += float(np.sum(np.maximum.reduceat(pos, starts)
                             - np.minimum.reduceat(pos, starts)))
     return tot
+
+
+def net_values(inst, x=None, y=None, gamma=None, model: str = "wa"):
+    """Per net, over both axes: its wirelength term (Eq. (3), or the
+    log-sum-exp model with model="lse") and its half-perimeter (Eq. (1)).
+    Returns two float64 arrays [num_nets], zero for nets without pins."""
+    x = inst.x if x is None else x
+    y = inst.y if y is None else y
+    gamma = inst.gamma if gamma is None else gamma
+    pc = np.asarray(inst.pin_cell, np.int64)
+    net_ptr, deg, ne = _segments(inst.net_ptr)
+    E = net_ptr.size - 1
+    wl = np.zeros(E)
+    hp = np.zeros(E)
+    starts = net_ptr[:-1][ne]
+    if starts.size == 0:
+        return wl, hp
+    for pos in (np.asarray(x, np.float64)[pc] + np.asarray(inst.pin_dx, np.float64),
+                np.asarray(y, np.float64)[pc] + np.asarray(inst.pin_dy, np.float64)):
+        if model == "lse":
+            v = _lse_axis(pos, inst.net_ptr, float(gamma))[0]
+        else:
+            v = _wa_axis(pos, inst.net_ptr, float(gamma))[0]
+        wl[ne] += v
+        hp[ne] += np.maximum.reduceat(pos, starts) - np.minimum.reduceat(pos, starts)
+    return wl, hp
 
 
 def overflow(rho: np.ndarray, base: np.ndarray, cap: np.ndarray) -> float:

@@ -30,7 +30,8 @@ class fftpl_problem(ctypes.Structure):
                 ("cell_ptr", c_void_p), ("pin_slot", c_void_p),
                 ("work", c_void_p), ("work_bytes", ctypes.c_uint64),
                 ("xindex", c_void_p), ("xindex_bytes", ctypes.c_uint64),
-                ("max_degree", ctypes.c_int32), ("screening", ctypes.c_float)]
+                ("max_degree", ctypes.c_int32), ("screening", ctypes.c_float),
+                ("xindex_key", ctypes.c_uint64)]
 
 
 _G = ctypes.POINTER(fftpl_grid)
@@ -40,9 +41,10 @@ _P = ctypes.POINTER(fftpl_problem)
 SIGNATURES = {
     "fftpl_version": (c_int, []),
     "fftpl_status_string": (c_char_p, [c_int]),
-    "fftpl_plan_create": (c_int, [ctypes.POINTER(c_void_p), c_int, c_int, c_void_p]),
+    "fftpl_plan_create": (c_int, [ctypes.POINTER(c_void_p), c_int, c_int, c_int, c_void_p]),
     "fftpl_plan_destroy": (c_int, [c_void_p]),
-    "fftpl_plan_info": (c_int, [c_void_p, ctypes.POINTER(c_int), ctypes.POINTER(c_int)]),
+    "fftpl_plan_info": (c_int, [c_void_p, ctypes.POINTER(c_int), ctypes.POINTER(c_int),
+                                ctypes.POINTER(c_int)]),
     "fftpl_plan_maps": (c_int, [c_void_p, ctypes.POINTER(c_void_p),
                                 ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p)]),
     "fftpl_fixed_map": (c_int, [_G, c_int, c_void_p, c_void_p, c_void_p, c_void_p,
@@ -81,7 +83,14 @@ SIGNATURES = {
                                    ctypes.POINTER(ctypes.c_uint64),
                                    ctypes.POINTER(ctypes.c_uint64)]),
     "fftpl_xindex_build": (c_int, [c_int, c_int, c_int, c_void_p, c_void_p, c_int, c_void_p,
-                                   ctypes.c_uint64, c_void_p, ctypes.c_uint64, c_void_p]),
+                                   ctypes.c_uint64, c_void_p, ctypes.c_uint64,
+                                   ctypes.POINTER(ctypes.c_uint64), c_void_p]),
+    "fftpl_problem_path": (c_int, [_P, ctypes.POINTER(c_int)]),
+    "fftpl_problem_density": (c_int, [_P, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "fftpl_problem_wl_grad": (c_int, [_P, c_void_p, c_void_p, c_float, c_int, c_void_p,
+                                      c_void_p, c_void_p, c_void_p, c_void_p]),
+    "fftpl_debug_net_values": (c_int, [_P, c_void_p, c_void_p, c_float, c_void_p, c_void_p,
+                                       c_void_p]),
     "fftpl_step_stats": (c_int, [c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                  c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                  ctypes.c_uint64, c_void_p]),

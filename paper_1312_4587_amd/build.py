@@ -39,6 +39,38 @@ def _compile(src):
     return obj
 
 
+STAMP = LIB + ".sources"
+
+
+def sources_digest():
+    """SHA-1 over the library's sources and its public header."""
+    import hashlib
+    h = hashlib.sha1()
+    paths = [os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC))
+             if f.endswith((".hip", ".hpp"))]
+    paths.append(os.path.join(os.path.dirname(HERE), "include", "fftpl.h"))
+    for p in paths:
+        h.update(os.path.basename(p).encode())
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def is_current():
+    """True when libfftpl.so exists and was built from the sources as they are."""
+    if not os.path.exists(LIB) or not os.path.exists(STAMP):
+        return False
+    with open(STAMP) as f:
+        return f.read().strip() == sources_digest()
+
+
+def ensure_built(verbose=False):
+    """Build libfftpl.so unless it was built from the current sources."""
+    if not is_current():
+        build(verbose=verbose)
+    return LIB
+
+
 def build(verbose=False):
     os.makedirs(OBJDIR, exist_ok=True)
     with concurrent.futures.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
@@ -49,6 +81,8 @@ def build(verbose=False):
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
     os.replace(tmp, LIB)
+    with open(STAMP, "w") as f:
+        f.write(sources_digest() + "\n")
     if verbose:
         print("built", LIB)
     return LIB

@@ -68,7 +68,7 @@ int validate_cells(int m, const float* x, const float* y, const float* w, const 
 }
 
 // Sizes the per-block partial sums of the solve (see Plan::partials) and
-// returns the number of doubles to allocate.
+// returns the number of doubles to allocate for one batch slot.
 size_t plan_partials(Plan& p, int n, int mode) {
   if (mode == FFTPL_DCT_FFT) {
     p.n_en = n / 2;
@@ -79,6 +79,27 @@ size_t plan_partials(Plan& p, int n, int mode) {
   }
   p.en_max = p.n_en;
   return (size_t)p.en_max + 2 * (size_t)p.n_tau + 2;
+}
+
+// Host-side fingerprint of an exchange index: the sizes and arrays it was
+// built from and the buffer it lives in (FNV-1a over their bytes; never 0).
+uint64_t xindex_fingerprint(int m, int E, int P, int max_degree, const void* net_ptr,
+                            const void* pin_cell, const void* index) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&h](uint64_t v) {
+    for (int i = 0; i < 8; ++i) {
+      h ^= (v >> (8 * i)) & 0xffu;
+      h *= 1099511628211ull;
+    }
+  };
+  mix((uint64_t)(uint32_t)m);
+  mix((uint64_t)(uint32_t)E);
+  mix((uint64_t)(uint32_t)P);
+  mix((uint64_t)(uint32_t)max_degree);
+  mix((uint64_t)(uintptr_t)net_ptr);
+  mix((uint64_t)(uintptr_t)pin_cell);
+  mix((uint64_t)(uintptr_t)index);
+  return h ? h : 1;
 }
 
 void free_plan(Plan& p) {
@@ -119,10 +140,12 @@ const char* fftpl_status_string(int status) {
   }
 }
 
-int fftpl_plan_create(fftpl_plan** out, int32_t n, int32_t dct_mode, void* stream) {
+int fftpl_plan_create(fftpl_plan** out, int32_t n, int32_t dct_mode, int32_t max_batch,
+                      void* stream) {
   if (!out) return FFTPL_E_INVAL;
   *out = nullptr;
   if (dct_mode < FFTPL_DCT_FFT || dct_mode > FFTPL_DCT_GEMM_BF16X3) return FFTPL_E_INVAL;
+  if (max_batch < 1 || max_batch > FFTPL_MAX_BATCH) return FFTPL_E_INVAL;
   if (dct_mode == FFTPL_DCT_FFT) {
     if (!is_pow2(n) || n < 8 || n > 1024) return FFTPL_E_UNSUPPORTED;
   } else {
@@ -133,19 +156,21 @@ int fftpl_plan_create(fftpl_plan** out, int32_t n, int32_t dct_mode, void* strea
   Plan& p = pl->p;
   p.n = n;
   p.mode = dct_mode;
+  p.max_batch = max_batch;
   hipGetDevice(&p.device);
-  const size_t nn = (size_t)n * n;
+  const size_t nn = (size_t)n * n, B = (size_t)max_batch;
+  p.part_stride = plan_partials(p, n, dct_mode);
   bool ok = hipMalloc(&p.fft_tw, sizeof(float2) * n) == hipSuccess &&
             hipMalloc(&p.dct_cs, sizeof(float2) * (n / 2 + 1)) == hipSuccess &&
             hipMalloc(&p.wfreq, sizeof(float) * n) == hipSuccess &&
-            hipMalloc(&p.rho, sizeof(float) * nn) == hipSuccess &&
-            hipMalloc(&p.tmp0, sizeof(float) * nn) == hipSuccess &&
-            hipMalloc(&p.tmp1, sizeof(float) * nn) == hipSuccess &&
-            hipMalloc(&p.tmp2, sizeof(float) * nn) == hipSuccess &&
-            hipMalloc(&p.psi, sizeof(float) * nn) == hipSuccess &&
-            hipMalloc(&p.exy, sizeof(float) * 2 * nn) == hipSuccess &&
-            hipMalloc(&p.rowsum, sizeof(double) * n) == hipSuccess &&
-            hipMalloc(&p.partials, sizeof(double) * plan_partials(p, n, dct_mode)) == hipSuccess;
+            hipMalloc(&p.rho, sizeof(float) * nn * B) == hipSuccess &&
+            hipMalloc(&p.tmp0, sizeof(float) * nn * B) == hipSuccess &&
+            hipMalloc(&p.tmp1, sizeof(float) * nn * B) == hipSuccess &&
+            hipMalloc(&p.tmp2, sizeof(float) * nn * B) == hipSuccess &&
+            hipMalloc(&p.psi, sizeof(float) * nn * B) == hipSuccess &&
+            hipMalloc(&p.exy, sizeof(float) * 2 * nn * B) == hipSuccess &&
+            hipMalloc(&p.rowsum, sizeof(double) * n * B) == hipSuccess &&
+            hipMalloc(&p.partials, sizeof(double) * p.part_stride * B) == hipSuccess;
   ok = ok && hipStreamCreateWithFlags(&p.side, hipStreamNonBlocking) == hipSuccess &&
        hipEventCreateWithFlags(&p.fork, hipEventDisableTiming) == hipSuccess &&
        hipEventCreateWithFlags(&p.join, hipEventDisableTiming) == hipSuccess;
@@ -192,10 +217,12 @@ int fftpl_plan_destroy(fftpl_plan* plan) {
   return dev_status(e);
 }
 
-int fftpl_plan_info(const fftpl_plan* plan, int32_t* n, int32_t* dct_mode) {
+int fftpl_plan_info(const fftpl_plan* plan, int32_t* n, int32_t* dct_mode,
+                    int32_t* max_batch) {
   if (!plan) return FFTPL_E_INVAL;
   if (n) *n = plan->p.n;
   if (dct_mode) *dct_mode = plan->p.mode;
+  if (max_batch) *max_batch = plan->p.max_batch;
   return FFTPL_OK;
 }
 
@@ -399,15 +426,86 @@ int fftpl_lse_grad(int32_t num_nets, const int32_t* net_ptr, int32_t num_pins,
                  num_cells, x, y, gamma, accumulate, gx, gy, wa, hpwl, stream);
 }
 
-// One evaluation; with check_only, the host-side checks alone (nothing is
-// enqueued).
-static int eval_impl(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
-                     const float* y, float lambda, float gamma, int32_t grad_mode, float* gx,
-                     float* gy, double* out4, void* stream, bool check_only) {
-  if (!plan || !prob || !out4 || !grid_ok(&prob->grid)) return FFTPL_E_INVAL;
+}  // extern "C"
+
+namespace {
+
+// The path an evaluation of prob takes, after the host checks of its
+// workspace and index fields (enum fftpl_path in *path), or their status.
+int problem_path(const fftpl_problem* prob, int* path, XchDims* xd, size_t* need_out) {
+  if (!prob || !grid_ok(&prob->grid)) return FFTPL_E_INVAL;
+  const int m = prob->num_cells;
+  if (m < 0 || prob->num_nets < 0 || prob->num_pins < 0) return FFTPL_E_INVAL;
+  // the workspace and the index are read in 16-byte vectors: device
+  // allocations are 256-byte aligned, and so must these be
+  if ((reinterpret_cast<uintptr_t>(prob->work) & 255) != 0 ||
+      (reinterpret_cast<uintptr_t>(prob->xindex) & 255) != 0)
+    return FFTPL_E_INVAL;
+  const bool any = prob->work || prob->xindex || prob->cell_ptr || prob->pin_slot;
+  if (!any) {
+    *path = FFTPL_PATH_ATOMIC;
+    return FFTPL_OK;
+  }
+  // a workspace or an index was given: it is used, or the call fails
+  if (prob->grid.n > kBandMaxN) return FFTPL_E_UNSUPPORTED;
+  size_t need = 0;
+  band_layout(prob->grid.n, m, prob->num_nets, prob->num_pins, nullptr, &need);
+  if (need_out) *need_out = need;
+  if (!prob->work || prob->work_bytes < need) return FFTPL_E_INVAL;
+  if (prob->xindex) {
+    XchDims d;
+    const int st = xch_dims(m, prob->num_nets, prob->num_pins, prob->max_degree, &d);
+    if (st != FFTPL_OK) return st;
+    if (prob->xindex_bytes < d.index_bytes) return FFTPL_E_INVAL;
+    if (prob->xindex_key != xindex_fingerprint(m, prob->num_nets, prob->num_pins,
+                                               prob->max_degree, prob->net_ptr,
+                                               prob->pin_cell, prob->xindex))
+      return FFTPL_E_STATE;
+    if (xd) *xd = d;
+    *path = FFTPL_PATH_EXCHANGE;
+    return FFTPL_OK;
+  }
+  if (prob->cell_ptr && prob->pin_slot) {
+    *path = FFTPL_PATH_SLOTS;
+    return FFTPL_OK;
+  }
+  return FFTPL_E_INVAL;   // a workspace without a pin index, or half an index
+}
+
+// Under FFTPL_VALIDATE=1: the index header read back against the problem.
+int validate_index(const fftpl_problem* prob, const XchDims& xd) {
+  int32_t hdr[9];
+  if (hipDeviceSynchronize() != hipSuccess ||
+      hipMemcpy(hdr, prob->xindex, sizeof(hdr), hipMemcpyDeviceToHost) != hipSuccess)
+    return FFTPL_E_DEVICE;
+  if (hdr[1] != prob->num_cells || hdr[2] != prob->num_nets || hdr[3] != prob->num_pins ||
+      hdr[4] != prob->max_degree || hdr[5] != xd.npt || hdr[8] != xd.cpb)
+    return FFTPL_E_STATE;
+  return FFTPL_OK;
+}
+
+// One checked evaluation request.
+struct EvalReq {
+  const fftpl_problem* prob = nullptr;
+  const float *x = nullptr, *y = nullptr;
+  float lambda = 0.0f, gamma = 1.0f;
+  float *gx = nullptr, *gy = nullptr;
+  double* out4 = nullptr;
+  int path = FFTPL_PATH_ATOMIC;
+  GridF g;
+  BandLayout L;
+  XchDims xd;
+  XchIndex X;
+};
+
+// Host-side checks of one evaluation (nothing is enqueued); fills r.
+int check_eval(const Plan& p, const fftpl_problem* prob, const float* x, const float* y,
+               float lambda, float gamma, int32_t grad_mode, float* gx, float* gy,
+               double* out4, EvalReq* r) {
+  if (!prob || !out4 || !grid_ok(&prob->grid)) return FFTPL_E_INVAL;
   if (prob->wl_model != FFTPL_WL_WA && prob->wl_model != FFTPL_WL_LSE) return FFTPL_E_INVAL;
   if (!(prob->screening >= 0.0f) || !isfinite(prob->screening)) return FFTPL_E_INVAL;
-  if (prob->grid.n != plan->p.n) return FFTPL_E_STATE;
+  if (prob->grid.n != p.n) return FFTPL_E_STATE;
   const int m = prob->num_cells;
   if (m < 0 || prob->num_nets < 0 || prob->num_pins < 0) return FFTPL_E_INVAL;
   if (grad_mode != FFTPL_GRAD_FIELD && grad_mode != FFTPL_GRAD_EXACT) return FFTPL_E_INVAL;
@@ -419,204 +517,280 @@ static int eval_impl(fftpl_plan* plan, const fftpl_problem* prob, const float* x
   if (!prob->net_ptr) return FFTPL_E_INVAL;
   if (prob->num_pins > 0 && (!prob->pin_cell || !prob->pin_dx || !prob->pin_dy || m == 0))
     return FFTPL_E_INVAL;
+  int path = FFTPL_PATH_ATOMIC;
+  XchDims xd;
+  const int st = problem_path(prob, &path, &xd, nullptr);
+  if (st != FFTPL_OK) return st;
+  if (!grads && path == FFTPL_PATH_ATOMIC && m > 0) return FFTPL_E_INVAL;
   if (validate_env()) {
     int v = validate_netlist(prob->num_nets, prob->net_ptr, prob->num_pins, prob->pin_cell, m);
     if (v == FFTPL_OK && m > 0) v = validate_cells(m, x, y, prob->w, prob->h);
+    if (v == FFTPL_OK && path == FFTPL_PATH_EXCHANGE) v = validate_index(prob, xd);
     if (v != FFTPL_OK) return v;
   }
-  Plan& p = plan->p;
-  const GridF g = make_gridf(prob->grid);
-  hipStream_t s = as_stream(stream);
-  const int64_t nn = (int64_t)p.n * p.n;
-  // Atomic-free paths when the caller supplied a workspace and a pin index:
-  // the exchange index (xch) or the cell-major slots (slots).
-  size_t need = 0;
-  BandLayout L = band_layout(p.n, m, prob->num_nets, prob->num_pins, nullptr, &need);
-  // the workspace and the index are read in 16-byte vectors: device
-  // allocations are 256-byte aligned, and so must these be
-  if ((reinterpret_cast<uintptr_t>(prob->work) & 255) != 0 ||
-      (reinterpret_cast<uintptr_t>(prob->xindex) & 255) != 0)
-    return FFTPL_E_INVAL;
-  const bool ws_ok = prob->work && prob->work_bytes >= need && p.n <= kBandMaxN;
-  XchDims xd;
-  const bool xch = ws_ok && prob->xindex &&
-                   xch_dims(m, prob->num_nets, prob->num_pins, prob->max_degree, &xd) ==
-                       FFTPL_OK &&
-                   prob->xindex_bytes >= xd.index_bytes;
-  const bool slots = !xch && ws_ok && prob->cell_ptr && prob->pin_slot;
-  const bool fast = xch || slots;
-  if (!grads && !fast && m > 0) return FFTPL_E_INVAL;
-  if (fast) L = band_layout(p.n, m, prob->num_nets, prob->num_pins, prob->work, nullptr);
-  XchIndex X;
-  if (xch) {
-    X = xch_index(xd, prob->xindex);
-    if (validate_env()) {
-      int32_t hdr[9];
-      if (hipDeviceSynchronize() != hipSuccess ||
-          hipMemcpy(hdr, prob->xindex, sizeof(hdr), hipMemcpyDeviceToHost) != hipSuccess)
-        return FFTPL_E_DEVICE;
-      if (hdr[1] != m || hdr[2] != prob->num_nets || hdr[3] != prob->num_pins ||
-          hdr[4] != prob->max_degree || hdr[5] != xd.npt || hdr[8] != xd.cpb)
-        return FFTPL_E_STATE;
-    }
+  r->prob = prob;
+  r->x = x;
+  r->y = y;
+  r->lambda = lambda;
+  r->gamma = gamma;
+  r->gx = gx;
+  r->gy = gy;
+  r->out4 = out4;
+  r->path = path;
+  r->g = make_gridf(prob->grid);
+  r->L = band_layout(p.n, m, prob->num_nets, prob->num_pins,
+                     path == FFTPL_PATH_ATOMIC ? nullptr : prob->work, nullptr);
+  if (path == FFTPL_PATH_EXCHANGE) {
+    r->xd = xd;
+    r->X = xch_index(xd, prob->xindex);
   }
-  if (check_only) return FFTPL_OK;
+  return FFTPL_OK;
+}
+
+// The solve's arguments for a request in batch slot `slot` of the plan.
+SpectralArgs spectral_args(Plan& p, const EvalReq& r, int slot, int grad_mode, bool grads) {
+  const size_t nn = (size_t)p.n * p.n;
+  SpectralArgs a;
+  a.rho = p.rho + slot * nn;
+  // FIELD: (Ex, Ey); EXACT: psi and the difference maps (Dx, Dy) the exact
+  // gradient is summed from; scalars only: neither map
+  a.psi = grads && grad_mode == FFTPL_GRAD_EXACT ? p.psi + slot * nn : nullptr;
+  a.exy = grads ? p.exy + 2 * slot * nn : nullptr;
+  a.diff = grad_mode == FFTPL_GRAD_EXACT;
+  a.en_part = p.partials + slot * p.part_stride;
+  a.base = r.prob->base;
+  a.cap = r.prob->cap;
+  a.rho_t = r.g.rho_t;
+  a.tau_part = a.en_part + p.en_max;
+  a.eps = r.prob->screening;
+  return a;
+}
+
+// The exchange path for count requests (count <= the plan's max_batch, one
+// wirelength model, workspaces that do not overlap): every stage is one
+// launch over all of them, request i in batch slot i of the plan.  The
+// wirelength branch (spread, net blocks) runs on the plan's side stream
+// while the density branch (banded scatter, solve, band gather), the longer
+// of the two when they share the chip, stays on `s`: the hand-over between
+// streams costs several microseconds each way, and this way the fork delays
+// only the shorter branch and the join is usually complete by the time the
+// density branch reaches it.  With per-kernel timing on, everything runs on
+// `s` so that consecutive events bracket single kernels.
+int run_exchange_group(Plan& p, EvalReq* rs, int count, int grad_mode, hipStream_t s) {
+  const bool grads = rs[0].gx != nullptr;
+  const size_t nn = (size_t)p.n * p.n;
+  const bool overlap = !p.timing;
+  hipStream_t ds = s, ws = overlap ? p.side : s;
   hipError_t e = hipSuccess;
   p.nev = 0;
   plan_mark(p, "start", s);
-  // With per-kernel timing on, everything runs on `s` so that consecutive
-  // events bracket single kernels.  Otherwise the wirelength branch (spread,
-  // net blocks) runs on the plan's side stream `ws` while the density branch
-  // (banded scatter, solve, band gather), the longer of the two when they
-  // share the chip, stays on `s`: the hand-over between streams costs
-  // several microseconds each way, and this way the fork delays only the
-  // shorter branch and the join is usually complete by the time the density
-  // branch reaches it.
-  const bool overlap = fast && !p.timing;
-  hipStream_t ds = s;
-  hipStream_t ws = overlap ? p.side : s;
-  if (fast) {
-    if (overlap) {
-      e = hipEventRecord(p.fork, s);
-      if (e == hipSuccess) e = hipStreamWaitEvent(ws, p.fork, 0);
-    }
-    // density branch: banded scatter (its counters and the scalars are all
-    // written, not accumulated, so nothing needs zeroing first)
-    if (e == hipSuccess)
-      e = launch_band_scatter(g, L, x, y, prob->w, prob->h, prob->base, p.rho, ds, &p);
-    // wirelength branch
-    if (xch) {
-      // pin positions into the exchange buffer, then every net block (the
-      // per-cell sums follow the join)
-      if (e == hipSuccess) e = launch_xch_spread(xd, X, x, y, L.pin_grad, ws);
-      plan_mark(p, "k_xch_spread", ws);
-      if (e == hipSuccess)
-        e = launch_xch_wa(xd, X, prob->net_ptr, prob->pin_dx, prob->pin_dy, gamma,
-                          prob->wl_model, L.pin_grad, L.wa_part, ws);
-      plan_mark(p, "k_xch_wa", ws);
-    } else {
-      // interleave positions, per-pin WA gradients into cell-major slots
-      if (e == hipSuccess) e = launch_interleave(m, x, y, L.xy, ws);
-      plan_mark(p, "k_interleave", ws);
-      if (e == hipSuccess)
-        e = launch_wa_pins(prob->num_nets, prob->net_ptr, prob->pin_cell, prob->pin_dx,
-                           prob->pin_dy, L.xy, prob->pin_slot, gamma, prob->wl_model,
-                           L.pin_grad, L.wa_part, ws, &p);
-    }
-  } else {
-    // 1. reset: rho = base, scalar accumulators = 0; 2. atomic scatter
-    e = launch_fill(p.rho, prob->base, 0.0f, nn, s);
-    plan_mark(p, "k_fill", s);
-    if (e == hipSuccess) e = launch_init_eval(out4, nullptr, 0, s);
-    plan_mark(p, "k_init_eval", s);
-    if (e == hipSuccess) e = launch_scatter(g, m, x, y, prob->w, prob->h, p.rho, s);
-    plan_mark(p, "k_scatter", s);
+  if (overlap) {
+    e = hipEventRecord(p.fork, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(ws, p.fork, 0);
   }
-  // 3. spectral solve (density branch); overflow sums in the first pass,
-  // energy in the last
+  BandReq br[kMaxBatch];
+  XchReq xr[kMaxBatch];
+  SpectralArgs sa[kMaxBatch];
+  for (int i = 0; i < count; ++i) {
+    const EvalReq& r = rs[i];
+    br[i].g = r.g;
+    br[i].L = r.L;
+    br[i].x = r.x;
+    br[i].y = r.y;
+    br[i].w = r.prob->w;
+    br[i].h = r.prob->h;
+    br[i].base = r.prob->base;
+    br[i].rho = p.rho + i * nn;
+    br[i].exy = reinterpret_cast<const float2*>(p.exy + 2 * i * nn);
+    br[i].psi = p.psi + i * nn;
+    xr[i] = xch_req(r.xd, r.X, r.x, r.y, r.L.pin_grad, r.prob->net_ptr, r.prob->pin_dx,
+                    r.prob->pin_dy, r.gamma, r.L.wa_part);
+    sa[i] = spectral_args(p, r, i, grad_mode, grads);
+  }
+  // density branch: banded scatter (its counters and the scalars are all
+  // written, not accumulated, so nothing needs zeroing first)
+  if (e == hipSuccess) e = launch_band_scatter_batch(br, count, ds, &p);
+  // wirelength branch: pin positions into the exchange buffer, then every
+  // net block (the per-cell sums follow the join)
+  if (e == hipSuccess) e = launch_xch_spread_batch(xr, count, ws);
+  plan_mark(p, "k_xch_spread", ws);
+  if (e == hipSuccess) e = launch_xch_wa_batch(xr, count, rs[0].prob->wl_model, ws);
+  plan_mark(p, "k_xch_wa", ws);
+  // spectral solve (density branch); overflow sums in the first pass, energy
+  // in the last
   if (e == hipSuccess) {
-    SpectralArgs a;
-    a.rho = p.rho;
-    // FIELD: (Ex, Ey); EXACT: psi and the difference maps (Dx, Dy) the exact
-    // gradient is summed from; scalars only: neither map
-    a.psi = grads && grad_mode == FFTPL_GRAD_EXACT ? p.psi : nullptr;
-    a.exy = grads ? p.exy : nullptr;
-    a.diff = grad_mode == FFTPL_GRAD_EXACT;
-    a.en_part = p.partials;
-    a.base = prob->base;
-    a.cap = prob->cap;
-    a.rho_t = g.rho_t;
-    a.tau_part = p.partials + p.en_max;
-    a.eps = prob->screening;
-    e = p.mode == FFTPL_DCT_FFT ? spectral_fft(p, a, ds) : spectral_gemm(p, a, ds);
+    if (p.mode == FFTPL_DCT_FFT) {
+      e = spectral_fft_batch(p, sa, count, ds);
+    } else {
+      for (int i = 0; i < count && e == hipSuccess; ++i) e = spectral_gemm(p, sa[i], ds);
+    }
   }
-  // exchange path: each cell's density gradient, computed band by band from
-  // the band entries (L2-local reads of the field), still on the density
-  // branch
-  if (fast && xch && grads) {
-    if (e == hipSuccess) e = launch_band_gather(g, L, p.exy, p.psi, grad_mode, ds);
+  // each cell's density gradient, computed band by band from the band
+  // entries (L2-local reads of the field), still on the density branch
+  if (grads) {
+    if (e == hipSuccess) e = launch_band_gather_batch(br, count, grad_mode, ds);
     plan_mark(p, "k_band_gather", ds);
   }
-  // join the wirelength branch
   if (e == hipSuccess && overlap) {
     e = hipEventRecord(p.join, ws);
     if (e == hipSuccess) e = hipStreamWaitEvent(s, p.join, 0);
   }
-  bool fin_in_cellsum = false;
-  FinalArgs fin;
-  fin.en = p.partials;
-  fin.n_en = p.n_en;
-  fin.tau = p.partials + p.en_max;
-  fin.n_tau = p.n_tau;
-  fin.wa = fast ? L.wa_part : nullptr;
-  fin.n_s = fast ? (xch ? xd.nnb : (prob->num_nets + 255) / 256) : 0;
-  fin.n_b = fast ? (xch ? 0 : wa_big_grid(prob->num_nets)) : 0;
-  fin.o_en = &out4[0];
-  fin.o_wa = &out4[1];
-  fin.o_hp = &out4[2];
-  fin.o_tau = &out4[3];
-  if (fast) {
-    // 5. per cell: density gradient plus the sum of its pins' gradients
-    if (!grads) {
-      // scalars only
-    } else if (xch) {
-      // g = lambda * density gradient + each cell's sum of pin gradients
-      CellGradArgs ca;
-      ca.g = g;
-      ca.x = x;
-      ca.y = y;
-      ca.w = prob->w;
-      ca.h = prob->h;
-      ca.exy = reinterpret_cast<const float2*>(p.exy);
-      ca.psi = p.psi;
-      ca.epos = L.epos;
-      ca.egrad = L.egrad;
-      ca.scale = lambda;
-      ca.gx = gx;
-      ca.gy = gy;
-      // the last cell block (the last one dispatched, and at most as large as
-      // the others) reduces the scalars too
-      ca.fin = fin;
-      ca.fin_block = xd.ncb - 1;
-      fin_in_cellsum = xd.ncb > 0;
-      if (e == hipSuccess) e = launch_xch_cellsum(xd, X, L.pin_grad, ca, grad_mode, s);
-      plan_mark(p, "k_xch_cellsum", s);
-    } else {
-      if (e == hipSuccess)
-        e = launch_gather_pins(g, m, x, y, prob->w, prob->h, p.exy, p.psi, grad_mode, lambda,
-                               prob->cell_ptr, L.pin_grad, gx, gy, s);
-      plan_mark(p, "k_gather_pins", s);
-    }
-  } else {
-    // 4. density gradient (overwrites g), 5. WA gradient (float atomics)
-    if (e == hipSuccess && m > 0)
-      e = launch_gather(g, m, x, y, prob->w, prob->h, nullptr, nullptr, p.exy, p.psi,
-                        grad_mode, lambda, 0, gx, gy, s);
-    plan_mark(p, "k_gather", s);
-    if (e == hipSuccess)
-      e = launch_wa(prob->num_nets, prob->net_ptr, prob->pin_cell, prob->pin_dx,
-                    prob->pin_dy, x, y, gamma, prob->wl_model, gx, gy, &out4[1], &out4[2],
-                    s);
-    plan_mark(p, "k_wa_atomic", s);
+  // per cell: lambda times the density gradient plus the sum of its pins'
+  // gradients; the last cell block of each design also reduces its scalars
+  // (N, W~, HPWL, tau from the per-block partials, complete by then)
+  SumReq sr[kMaxBatch];
+  bool fin_separate[kMaxBatch];
+  for (int i = 0; i < count; ++i) {
+    const EvalReq& r = rs[i];
+    FinalArgs fin;
+    fin.en = sa[i].en_part;
+    fin.n_en = p.n_en;
+    fin.tau = sa[i].tau_part;
+    fin.n_tau = p.n_tau;
+    fin.wa = r.L.wa_part;
+    fin.n_s = r.xd.nnb;
+    fin.n_b = 0;
+    fin.o_en = &r.out4[0];
+    fin.o_wa = &r.out4[1];
+    fin.o_hp = &r.out4[2];
+    fin.o_tau = &r.out4[3];
+    CellGradArgs ca;
+    ca.g = r.g;
+    ca.x = r.x;
+    ca.y = r.y;
+    ca.w = r.prob->w;
+    ca.h = r.prob->h;
+    ca.exy = reinterpret_cast<const float2*>(p.exy + 2 * i * nn);
+    ca.psi = p.psi + i * nn;
+    ca.epos = r.L.epos;
+    ca.egrad = r.L.egrad;
+    ca.scale = r.lambda;
+    ca.gx = r.gx;
+    ca.gy = r.gy;
+    ca.fin = fin;
+    ca.fin_block = r.xd.ncb - 1;
+    sr[i] = sum_req(r.xd, r.X, r.L.pin_grad, ca);
+    // designs without cells (or the scalars alone) reduce in a separate launch
+    fin_separate[i] = !grads || r.xd.ncb <= 0 || r.xd.m <= 0;
   }
-  // 6. N, W~, HPWL, tau from the per-block partials (the atomic path added
-  // W~ and HPWL into out4 directly): by the exchange path's cell sums, or a
-  // separate one-block launch (a last-block-done count in the gather would
-  // put every gather block's atomic on one address, which costs far more
-  // than the launch).
-  if (!fin_in_cellsum) {
+  if (grads) {
+    if (e == hipSuccess) e = launch_xch_cellsum_batch(sr, count, grad_mode, true, s);
+    plan_mark(p, "k_xch_cellsum", s);
+  }
+  for (int i = 0; i < count; ++i) {
+    if (!fin_separate[i]) continue;
+    const FinalArgs& f = sr[i].a.fin;
     if (e == hipSuccess)
-      e = launch_eval_finalize(fin.en, fin.n_en, fin.tau, fin.n_tau, fin.wa, fin.n_s, fin.n_b,
-                               fin.o_en, fin.o_wa, fin.o_hp, fin.o_tau, s);
+      e = launch_eval_finalize(f.en, f.n_en, f.tau, f.n_tau, f.wa, f.n_s, f.n_b, f.o_en,
+                               f.o_wa, f.o_hp, f.o_tau, s);
     plan_mark(p, "k_eval_finalize", s);
   }
   return dev_status(e);
 }
 
+// One evaluation on the cell-major slot path or the float-atomic path.
+int run_other(Plan& p, const EvalReq& r, int grad_mode, hipStream_t s) {
+  const fftpl_problem* prob = r.prob;
+  const bool grads = r.gx != nullptr;
+  const bool slots = r.path == FFTPL_PATH_SLOTS;
+  const int m = prob->num_cells;
+  const BandLayout& L = r.L;
+  const int64_t nn = (int64_t)p.n * p.n;
+  hipError_t e = hipSuccess;
+  p.nev = 0;
+  plan_mark(p, "start", s);
+  const bool overlap = slots && !p.timing;
+  hipStream_t ws = overlap ? p.side : s;
+  if (slots) {
+    if (overlap) {
+      e = hipEventRecord(p.fork, s);
+      if (e == hipSuccess) e = hipStreamWaitEvent(ws, p.fork, 0);
+    }
+    if (e == hipSuccess)
+      e = launch_band_scatter(r.g, L, r.x, r.y, prob->w, prob->h, prob->base, p.rho, s, &p);
+    // interleave positions, per-pin gradients into cell-major slots
+    if (e == hipSuccess) e = launch_interleave(m, r.x, r.y, L.xy, ws);
+    plan_mark(p, "k_interleave", ws);
+    if (e == hipSuccess)
+      e = launch_wa_pins(prob->num_nets, prob->net_ptr, prob->pin_cell, prob->pin_dx,
+                         prob->pin_dy, L.xy, prob->pin_slot, r.gamma, prob->wl_model,
+                         L.pin_grad, L.wa_part, ws, &p);
+  } else {
+    // 1. reset: rho = base, scalar accumulators = 0; 2. atomic scatter
+    e = launch_fill(p.rho, prob->base, 0.0f, nn, s);
+    plan_mark(p, "k_fill", s);
+    if (e == hipSuccess) e = launch_init_eval(r.out4, nullptr, 0, s);
+    plan_mark(p, "k_init_eval", s);
+    if (e == hipSuccess) e = launch_scatter(r.g, m, r.x, r.y, prob->w, prob->h, p.rho, s);
+    plan_mark(p, "k_scatter", s);
+  }
+  SpectralArgs a = spectral_args(p, r, 0, grad_mode, grads);
+  if (e == hipSuccess) e = p.mode == FFTPL_DCT_FFT ? spectral_fft(p, a, s) : spectral_gemm(p, a, s);
+  if (e == hipSuccess && overlap) {
+    e = hipEventRecord(p.join, ws);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, p.join, 0);
+  }
+  if (slots) {
+    if (grads) {
+      if (e == hipSuccess)
+        e = launch_gather_pins(r.g, m, r.x, r.y, prob->w, prob->h, p.exy, p.psi, grad_mode,
+                               r.lambda, prob->cell_ptr, L.pin_grad, r.gx, r.gy, s);
+      plan_mark(p, "k_gather_pins", s);
+    }
+  } else {
+    // 4. density gradient (overwrites g), 5. wirelength gradient (float atomics)
+    if (e == hipSuccess && m > 0)
+      e = launch_gather(r.g, m, r.x, r.y, prob->w, prob->h, nullptr, nullptr, p.exy, p.psi,
+                        grad_mode, r.lambda, 0, r.gx, r.gy, s);
+    plan_mark(p, "k_gather", s);
+    if (e == hipSuccess)
+      e = launch_wa(prob->num_nets, prob->net_ptr, prob->pin_cell, prob->pin_dx, prob->pin_dy,
+                    r.x, r.y, r.gamma, prob->wl_model, r.gx, r.gy, &r.out4[1], &r.out4[2], s);
+    plan_mark(p, "k_wa_atomic", s);
+  }
+  // 6. N, W~, HPWL, tau from the per-block partials (the atomic path added
+  // W~ and HPWL into out4 directly)
+  if (e == hipSuccess)
+    e = launch_eval_finalize(a.en_part, p.n_en, a.tau_part, p.n_tau, slots ? L.wa_part : nullptr,
+                             slots ? (prob->num_nets + 255) / 256 : 0,
+                             slots ? wa_big_grid(prob->num_nets) : 0, &r.out4[0], &r.out4[1],
+                             &r.out4[2], &r.out4[3], s);
+  plan_mark(p, "k_eval_finalize", s);
+  return dev_status(e);
+}
+
+bool ranges_overlap(const void* a, uint64_t na, const void* b, uint64_t nb) {
+  const uintptr_t a0 = reinterpret_cast<uintptr_t>(a), b0 = reinterpret_cast<uintptr_t>(b);
+  return a0 < b0 + nb && b0 < a0 + na;
+}
+
+// Whether request r can join a group of exchange-path requests.
+bool joins_group(const EvalReq* g, int count, const EvalReq& r, int max_batch) {
+  if (count >= max_batch || r.path != FFTPL_PATH_EXCHANGE) return false;
+  if (count == 0) return true;
+  const bool big = g[0].xd.cap > kXchPinLds2;
+  if (r.prob->wl_model != g[0].prob->wl_model || (r.xd.cap > kXchPinLds2) != big) return false;
+  for (int i = 0; i < count; ++i)
+    if (ranges_overlap(g[i].prob->work, g[i].prob->work_bytes, r.prob->work,
+                       r.prob->work_bytes))
+      return false;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
 int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
                const float* y, float lambda, float gamma, int32_t grad_mode, float* gx,
                float* gy, double* out4, void* stream) {
-  return eval_impl(plan, prob, x, y, lambda, gamma, grad_mode, gx, gy, out4, stream, false);
+  if (!plan) return FFTPL_E_INVAL;
+  EvalReq r;
+  const int st = check_eval(plan->p, prob, x, y, lambda, gamma, grad_mode, gx, gy, out4, &r);
+  if (st != FFTPL_OK) return st;
+  hipStream_t s = as_stream(stream);
+  if (r.path == FFTPL_PATH_EXCHANGE) return run_exchange_group(plan->p, &r, 1, grad_mode, s);
+  return run_other(plan->p, r, grad_mode, s);
 }
 
 int fftpl_eval_batch(fftpl_plan* plan, int32_t count, const fftpl_problem* const* probs,
@@ -628,19 +802,134 @@ int fftpl_eval_batch(fftpl_plan* plan, int32_t count, const fftpl_problem* const
   if (!plan || !probs || !xs || !ys || !lambdas || !gammas || !out4s) return FFTPL_E_INVAL;
   if ((gxs == nullptr) != (gys == nullptr)) return FFTPL_E_INVAL;
   // every request is checked before any is enqueued
+  std::vector<EvalReq> rs((size_t)count);
   for (int32_t i = 0; i < count; ++i) {
-    const int st = eval_impl(plan, probs[i], xs[i], ys[i], lambdas[i], gammas[i], grad_mode,
-                             gxs ? gxs[i] : nullptr, gys ? gys[i] : nullptr,
-                             out4s + 4 * (size_t)i, stream, true);
+    const int st = check_eval(plan->p, probs[i], xs[i], ys[i], lambdas[i], gammas[i],
+                              grad_mode, gxs ? gxs[i] : nullptr, gys ? gys[i] : nullptr,
+                              out4s + 4 * (size_t)i, &rs[(size_t)i]);
     if (st != FFTPL_OK) return st;
   }
+  hipStream_t s = as_stream(stream);
+  EvalReq group[kMaxBatch];
+  int ng = 0;
   for (int32_t i = 0; i < count; ++i) {
-    const int st = eval_impl(plan, probs[i], xs[i], ys[i], lambdas[i], gammas[i], grad_mode,
-                             gxs ? gxs[i] : nullptr, gys ? gys[i] : nullptr,
-                             out4s + 4 * (size_t)i, stream, false);
-    if (st != FFTPL_OK) return st;
+    const EvalReq& r = rs[(size_t)i];
+    if (!joins_group(group, ng, r, plan->p.max_batch) && ng > 0) {
+      const int st = run_exchange_group(plan->p, group, ng, grad_mode, s);
+      if (st != FFTPL_OK) return st;
+      ng = 0;
+    }
+    if (joins_group(group, ng, r, plan->p.max_batch)) {
+      group[ng++] = r;
+    } else {
+      const int st = run_other(plan->p, r, grad_mode, s);
+      if (st != FFTPL_OK) return st;
+    }
   }
+  if (ng > 0) return run_exchange_group(plan->p, group, ng, grad_mode, s);
   return FFTPL_OK;
+}
+
+int fftpl_problem_path(const fftpl_problem* prob, int32_t* path) {
+  if (!path) return FFTPL_E_INVAL;
+  int pth = FFTPL_PATH_ATOMIC;
+  const int st = problem_path(prob, &pth, nullptr, nullptr);
+  if (st == FFTPL_OK) *path = pth;
+  return st;
+}
+
+int fftpl_problem_density(const fftpl_problem* prob, const float* x, const float* y,
+                          float* rho, void* stream) {
+  if (!prob || !rho || !grid_ok(&prob->grid)) return FFTPL_E_INVAL;
+  const int m = prob->num_cells;
+  if (m < 0) return FFTPL_E_INVAL;
+  if (m > 0 && (!x || !y || !prob->w || !prob->h)) return FFTPL_E_INVAL;
+  if (prob->grid.n > kBandMaxN) return FFTPL_E_UNSUPPORTED;
+  if ((reinterpret_cast<uintptr_t>(prob->work) & 255) != 0) return FFTPL_E_INVAL;
+  size_t need = 0;
+  band_layout(prob->grid.n, m, prob->num_nets, prob->num_pins, nullptr, &need);
+  if (!prob->work || prob->work_bytes < need) return FFTPL_E_INVAL;
+  if (validate_env() && m > 0) {
+    const int v = validate_cells(m, x, y, prob->w, prob->h);
+    if (v != FFTPL_OK) return v;
+  }
+  const BandLayout L =
+      band_layout(prob->grid.n, m, prob->num_nets, prob->num_pins, prob->work, nullptr);
+  return dev_status(launch_band_scatter(make_gridf(prob->grid), L, x, y, prob->w, prob->h,
+                                        prob->base, rho, as_stream(stream)));
+}
+
+// The wirelength through the exchange path alone (wl_grad), or its per-net
+// values (net_wl, net_hp: the test export).
+static int problem_wl(const fftpl_problem* prob, const float* x, const float* y, float gamma,
+                      int32_t accumulate, float* gx, float* gy, double* wl, double* hpwl,
+                      double* net_wl, double* net_hp, void* stream) {
+  if (!prob || !grid_ok(&prob->grid)) return FFTPL_E_INVAL;
+  if (!(gamma > 0) || !isfinite(gamma)) return FFTPL_E_INVAL;
+  if (accumulate != 0 && accumulate != 1) return FFTPL_E_INVAL;
+  if (prob->wl_model != FFTPL_WL_WA && prob->wl_model != FFTPL_WL_LSE) return FFTPL_E_INVAL;
+  const int m = prob->num_cells;
+  if (m < 0 || prob->num_nets < 0 || prob->num_pins < 0) return FFTPL_E_INVAL;
+  if (m > 0 && (!x || !y)) return FFTPL_E_INVAL;
+  if (!net_wl && m > 0 && (!gx || !gy)) return FFTPL_E_INVAL;
+  if (!prob->net_ptr) return FFTPL_E_INVAL;
+  if (prob->num_pins > 0 && (!prob->pin_cell || !prob->pin_dx || !prob->pin_dy || m == 0))
+    return FFTPL_E_INVAL;
+  int path = FFTPL_PATH_ATOMIC;
+  XchDims xd;
+  const int st = problem_path(prob, &path, &xd, nullptr);
+  if (st != FFTPL_OK) return st;
+  if (path != FFTPL_PATH_EXCHANGE) return FFTPL_E_INVAL;
+  if (validate_env()) {
+    int v = validate_netlist(prob->num_nets, prob->net_ptr, prob->num_pins, prob->pin_cell, m);
+    if (v == FFTPL_OK) v = validate_index(prob, xd);
+    if (v != FFTPL_OK) return v;
+  }
+  hipStream_t s = as_stream(stream);
+  const BandLayout L =
+      band_layout(prob->grid.n, m, prob->num_nets, prob->num_pins, prob->work, nullptr);
+  const XchIndex X = xch_index(xd, prob->xindex);
+  XchReq xr = xch_req(xd, X, x, y, L.pin_grad, prob->net_ptr, prob->pin_dx, prob->pin_dy,
+                      gamma, L.wa_part);
+  xr.net_wl = net_wl;
+  xr.net_hp = net_hp;
+  hipError_t e = launch_xch_spread_batch(&xr, 1, s);
+  if (e == hipSuccess) e = launch_xch_wa_batch(&xr, 1, prob->wl_model, s);
+  if (net_wl) return dev_status(e);
+  FinalArgs fin;
+  fin.wa = L.wa_part;
+  fin.n_s = xd.nnb;
+  fin.o_wa = wl;
+  fin.o_hp = hpwl;
+  const bool want = wl || hpwl;
+  if (m > 0 && xd.ncb > 0) {
+    CellGradArgs ca;
+    ca.g = make_gridf(prob->grid);
+    ca.gx = gx;
+    ca.gy = gy;
+    ca.accumulate = accumulate;
+    ca.fin = fin;
+    ca.fin_block = want ? xd.ncb - 1 : -1;
+    const SumReq sr = sum_req(xd, X, L.pin_grad, ca);
+    if (e == hipSuccess) e = launch_xch_cellsum_batch(&sr, 1, FFTPL_GRAD_FIELD, false, s);
+  } else if (want && e == hipSuccess) {
+    e = launch_eval_finalize(nullptr, 0, nullptr, 0, fin.wa, fin.n_s, 0, nullptr, wl, hpwl,
+                             nullptr, s);
+  }
+  return dev_status(e);
+}
+
+int fftpl_problem_wl_grad(const fftpl_problem* prob, const float* x, const float* y,
+                          float gamma, int32_t accumulate, float* gx, float* gy, double* wl,
+                          double* hpwl, void* stream) {
+  return problem_wl(prob, x, y, gamma, accumulate, gx, gy, wl, hpwl, nullptr, nullptr, stream);
+}
+
+int fftpl_debug_net_values(const fftpl_problem* prob, const float* x, const float* y,
+                           float gamma, double* wl_first, double* hpwl_first, void* stream) {
+  if (!wl_first || !hpwl_first) return FFTPL_E_INVAL;
+  return problem_wl(prob, x, y, gamma, 0, nullptr, nullptr, nullptr, nullptr, wl_first,
+                    hpwl_first, stream);
 }
 
 int fftpl_plan_timing(fftpl_plan* plan, int32_t enable) {
@@ -711,7 +1000,7 @@ int fftpl_xindex_bytes(int32_t num_cells, int32_t num_nets, int32_t num_pins,
 int fftpl_xindex_build(int32_t num_cells, int32_t num_nets, int32_t num_pins,
                        const int32_t* net_ptr, const int32_t* pin_cell, int32_t max_degree,
                        void* index, uint64_t index_bytes, void* work, uint64_t work_bytes,
-                       void* stream) {
+                       uint64_t* key, void* stream) {
   XchDims d;
   const int st = xch_dims(num_cells, num_nets, num_pins, max_degree, &d);
   if (st != FFTPL_OK) return st;
@@ -721,7 +1010,11 @@ int fftpl_xindex_build(int32_t num_cells, int32_t num_nets, int32_t num_pins,
   if ((reinterpret_cast<uintptr_t>(index) & 255) != 0 ||
       (reinterpret_cast<uintptr_t>(work) & 255) != 0)
     return FFTPL_E_INVAL;
-  return xch_build(d, net_ptr, pin_cell, index, work, as_stream(stream));
+  const int st2 = xch_build(d, net_ptr, pin_cell, index, work, as_stream(stream));
+  if (st2 == FFTPL_OK && key)
+    *key = xindex_fingerprint(num_cells, num_nets, num_pins, max_degree, net_ptr, pin_cell,
+                              index);
+  return st2;
 }
 
 int fftpl_step_stats(int32_t num_cells, const float* ux, const float* uy, const float* upx,

@@ -19,6 +19,8 @@
 //          is, from the band's field rows staged in LDS.
 // Every thread issues the loads of its cells (or entries) before it uses any
 // of them, so each block keeps many misses in flight.
+#include <algorithm>
+
 #include "fftpl_internal.hpp"
 
 namespace fftpl {
@@ -148,12 +150,19 @@ __device__ __forceinline__ void walk_band(const BandLayout& L, int band, int64_t
   }
 }
 
-__global__ void __launch_bounds__(kBandThreads)
-    k_band_place(GridF g, BandLayout L, const float* __restrict__ x,
-                 const float* __restrict__ y, const float* __restrict__ w,
-                 const float* __restrict__ h) {
-  __shared__ int hist[257], cur[257];   // the bands, then the tall cells
+template <int NB>
+__global__ void __launch_bounds__(kBandThreads) k_band_place(BandBatch<NB> bb) {
+  // design blockIdx.y of the batch; blocks past its count of cell blocks idle
+  const BandReq& q = bb.r[blockIdx.y];
+  const GridF g = q.g;
+  const BandLayout L = q.L;
   const int t = threadIdx.x, k = blockIdx.x;
+  if (L.m <= 0 || k >= L.nblk) return;
+  const float* __restrict__ x = q.x;
+  const float* __restrict__ y = q.y;
+  const float* __restrict__ w = q.w;
+  const float* __restrict__ h = q.h;
+  __shared__ int hist[257], cur[257];   // the bands, then the tall cells
   for (int b = t; b <= L.nb; b += NT) hist[b] = 0;
   __syncthreads();
   const int c0 = k * kCellsPerBlock;   // one batch of B cells per thread
@@ -217,11 +226,17 @@ __device__ __forceinline__ void add_fixed(unsigned long long* a, float v) {
   atomicAdd(a, (unsigned long long)__float2uint_rn(v * 2147483648.0f));
 }
 
-__global__ void __launch_bounds__(kAccThreads)
-    k_band_accum(GridF g, BandLayout L, const float* __restrict__ x,
-                 const float* __restrict__ y, const float* __restrict__ w,
-                 const float* __restrict__ h, const float* __restrict__ base,
-                 float* __restrict__ rho) {
+template <int NB>
+__global__ void __launch_bounds__(kAccThreads) k_band_accum(BandBatch<NB> bb) {
+  const BandReq& q = bb.r[blockIdx.y];
+  const GridF g = q.g;
+  const BandLayout L = q.L;
+  const float* __restrict__ x = q.x;
+  const float* __restrict__ y = q.y;
+  const float* __restrict__ w = q.w;
+  const float* __restrict__ h = q.h;
+  const float* __restrict__ base = q.base;
+  float* __restrict__ rho = q.rho;
   __shared__ unsigned long long acc[kBandMaxN * 4];   // rows * n <= 4096 bins
   __shared__ int pre[NTA];
   __shared__ int64_t start[NTA];
@@ -281,10 +296,13 @@ __global__ void __launch_bounds__(kAccThreads)
 // reads of one block stay within a few tens of KiB (staged in LDS), where a
 // per-cell gather in cell order reads the whole map at random.
 constexpr int NTG = 1024;   // threads of a band-gather block
-template <int MODE>
-__global__ void __launch_bounds__(NTG)
-    k_band_gather(GridF g, BandLayout L, const float2* __restrict__ exy,
-                  const float* __restrict__ psi) {
+template <int MODE, int NB>
+__global__ void __launch_bounds__(NTG) k_band_gather(BandBatch<NB> bb) {
+  const BandReq& q = bb.r[blockIdx.y];
+  const GridF g = q.g;
+  const BandLayout L = q.L;
+  const float2* __restrict__ exy = q.exy;
+  const float* __restrict__ psi = q.psi;
   // the band's field rows and the next one (cells of up to two rows whose
   // first row is in the band read only these) staged in LDS
   __shared__ float2 rows[5 * kBandMaxN];
@@ -336,16 +354,42 @@ __global__ void __launch_bounds__(NTG)
   });
 }
 
+template <int NB>
+static hipError_t band_gather_nb(const BandBatch<NB>& bb, int nb, int grad_mode,
+                                 hipStream_t s) {
+  const dim3 grid(nb, bb.count);
+  if (grad_mode == FFTPL_GRAD_EXACT)
+    hipLaunchKernelGGL((k_band_gather<FFTPL_GRAD_EXACT, NB>), grid, dim3(NTG), 0, s, bb);
+  else
+    hipLaunchKernelGGL((k_band_gather<FFTPL_GRAD_FIELD, NB>), grid, dim3(NTG), 0, s, bb);
+  return hipGetLastError();
+}
+
+hipError_t launch_band_gather_batch(const BandReq* reqs, int count, int grad_mode,
+                                    hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  if (count > kMaxBatch) return hipErrorInvalidValue;
+  const int nb = reqs[0].L.nb;
+  if (count == 1) {
+    BandBatch<1> bb;
+    bb.count = 1;
+    bb.r[0] = reqs[0];
+    return band_gather_nb(bb, nb, grad_mode, s);
+  }
+  BandBatch<kMaxBatch> bb;
+  bb.count = count;
+  for (int i = 0; i < count; ++i) bb.r[i] = reqs[i];
+  return band_gather_nb(bb, nb, grad_mode, s);
+}
+
 hipError_t launch_band_gather(const GridF& g, const BandLayout& L, const float* exy,
                               const float* psi, int grad_mode, hipStream_t s) {
-  const float2* e2 = reinterpret_cast<const float2*>(exy);
-  if (grad_mode == FFTPL_GRAD_EXACT)
-    hipLaunchKernelGGL(k_band_gather<FFTPL_GRAD_EXACT>, dim3(L.nb), dim3(NTG), 0, s, g, L, e2,
-                       psi);
-  else
-    hipLaunchKernelGGL(k_band_gather<FFTPL_GRAD_FIELD>, dim3(L.nb), dim3(NTG), 0, s, g, L, e2,
-                       psi);
-  return hipGetLastError();
+  BandReq q;
+  q.g = g;
+  q.L = L;
+  q.exy = reinterpret_cast<const float2*>(exy);
+  q.psi = psi;
+  return launch_band_gather_batch(&q, 1, grad_mode, s);
 }
 
 // xy[i] = (x[i], y[i]): the wirelength pass then gathers one float2 per pin.
@@ -365,23 +409,64 @@ hipError_t launch_interleave(int m, const float* x, const float* y, float2* xy,
   return hipGetLastError();
 }
 
+template <int NB>
+static hipError_t band_scatter_nb(const BandBatch<NB>& bb, int max_nblk, int nb,
+                                  bool any_cells, hipStream_t s, Plan* tp) {
+  hipError_t e = hipSuccess;
+  if (any_cells) {
+    hipLaunchKernelGGL((k_band_place<NB>), dim3(max_nblk, bb.count), dim3(NT), 0, s, bb);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (tp) plan_mark(*tp, "k_band_place", s);
+  }
+  hipLaunchKernelGGL((k_band_accum<NB>), dim3(nb, bb.count), dim3(NTA), 0, s, bb);
+  e = hipGetLastError();
+  if (tp) plan_mark(*tp, "k_band_accum", s);
+  return e;
+}
+
+hipError_t launch_band_scatter_batch(const BandReq* reqs, int count, hipStream_t s,
+                                     Plan* tp) {
+  if (count <= 0) return hipSuccess;
+  if (count > kMaxBatch) return hipErrorInvalidValue;
+  int max_nblk = 1;
+  bool any = false;
+  for (int i = 0; i < count; ++i) {
+    if (reqs[i].L.m > 0) {
+      any = true;
+      max_nblk = std::max(max_nblk, reqs[i].L.nblk);
+    } else {
+      // no cells: one empty region
+      hipError_t e = launch_zero_i32(reqs[i].L.blk_cnt,
+                                     (int64_t)reqs[i].L.nblk * (reqs[i].L.nb + 1), s);
+      if (e != hipSuccess) return e;
+    }
+  }
+  const int nb = reqs[0].L.nb;
+  if (count == 1) {
+    BandBatch<1> bb;
+    bb.count = 1;
+    bb.r[0] = reqs[0];
+    return band_scatter_nb(bb, max_nblk, nb, any, s, tp);
+  }
+  BandBatch<kMaxBatch> bb;
+  bb.count = count;
+  for (int i = 0; i < count; ++i) bb.r[i] = reqs[i];
+  return band_scatter_nb(bb, max_nblk, nb, any, s, tp);
+}
+
 hipError_t launch_band_scatter(const GridF& g, const BandLayout& L, const float* x,
                                const float* y, const float* w, const float* h,
                                const float* base, float* rho, hipStream_t s, Plan* tp) {
-  if (L.m > 0) {
-    hipLaunchKernelGGL(k_band_place, dim3(L.nblk), dim3(NT), 0, s, g, L, x, y, w, h);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    if (tp) plan_mark(*tp, "k_band_place", s);
-  } else {
-    // no cells: one empty region
-    hipError_t e = launch_zero_i32(L.blk_cnt, (int64_t)L.nblk * (L.nb + 1), s);
-    if (e != hipSuccess) return e;
-  }
-  hipLaunchKernelGGL(k_band_accum, dim3(L.nb), dim3(NTA), 0, s, g, L, x, y, w, h, base, rho);
-  hipError_t e = hipGetLastError();
-  if (tp) plan_mark(*tp, "k_band_accum", s);
-  return e;
+  BandReq q;
+  q.g = g;
+  q.L = L;
+  q.x = x;
+  q.y = y;
+  q.w = w;
+  q.h = h;
+  q.base = base;
+  q.rho = rho;
+  return launch_band_scatter_batch(&q, 1, s, tp);
 }
 
 }  // namespace fftpl

@@ -370,10 +370,17 @@ namespace {
 
 // T[a] = (x, y) of pin a's cell, over part blockIdx.x % kXchSpreadSplit of
 // the A range of cell block blockIdx.x / kXchSpreadSplit.
-__global__ void __launch_bounds__(NT)
-    k_xch_spread(int m, int cpb, const int32_t* __restrict__ cb_a_ptr,
-                 const uint16_t* __restrict__ lc, const float* __restrict__ x,
-                 const float* __restrict__ y, float2* __restrict__ T) {
+template <int NB>
+__global__ void __launch_bounds__(NT) k_xch_spread(XchBatch<NB> xb) {
+  // design blockIdx.y of the batch; blocks past its cell blocks idle
+  const XchReq& rq = xb.r[blockIdx.y];
+  const int m = rq.m, cpb = rq.cpb;
+  if ((int)blockIdx.x >= rq.ncb * kXchSpreadSplit) return;
+  const int32_t* __restrict__ cb_a_ptr = rq.cb_a_ptr;
+  const uint16_t* __restrict__ lc = rq.lc;
+  const float* __restrict__ x = rq.x;
+  const float* __restrict__ y = rq.y;
+  float2* __restrict__ T = rq.T;
   __shared__ float2 win[kXchCells];
   const int cb = blockIdx.x / kXchSpreadSplit, part = blockIdx.x % kXchSpreadSplit;
   const int t = threadIdx.x;
@@ -437,19 +444,29 @@ __device__ __forceinline__ float fexp(float v) { return __expf(v); }
 // T.  LDS: pos[cap], off[cap] (dynamic, 16 bytes per pin of the block).
 // LSE: the log-sum-exp model in place of the weighted average (same sums;
 // the gradient is e+/S+ - e-/S-, the value (M - L) + gamma (ln S+ + ln S-)).
-template <int STAGE, bool LSE>
-__global__ void __launch_bounds__(NW)
-    k_xch_wa(int num_pins, int cap, const int32_t* __restrict__ net_ptr,
-             const int32_t* __restrict__ nb_net_ptr, const uint32_t* __restrict__ nmeta,
-             const int32_t* __restrict__ a_of_b, const uint16_t* __restrict__ lcsr,
-             const float* __restrict__ pin_dx, const float* __restrict__ pin_dy, float gamma,
-             float inv_gamma, float2* __restrict__ T, double* __restrict__ part) {
+template <int STAGE, bool LSE, int NB>
+__global__ void __launch_bounds__(NW) k_xch_wa(XchBatch<NB> xb) {
+  const XchReq& rq = xb.r[blockIdx.y];
+  const int k = blockIdx.x, t = threadIdx.x, nblk = rq.nnb;
+  if (k >= nblk) return;
+  const int num_pins = rq.num_pins, cap = rq.cap;
+  const int32_t* __restrict__ net_ptr = rq.net_ptr;
+  const int32_t* __restrict__ nb_net_ptr = rq.nb_net_ptr;
+  const uint32_t* __restrict__ nmeta = rq.nmeta;
+  const int32_t* __restrict__ a_of_b = rq.a_of_b;
+  const uint16_t* __restrict__ lcsr = rq.lcsr;
+  const float* __restrict__ pin_dx = rq.pin_dx;
+  const float* __restrict__ pin_dy = rq.pin_dy;
+  const float gamma = rq.gamma, inv_gamma = rq.inv_gamma;
+  float2* __restrict__ T = rq.T;
+  double* __restrict__ part = rq.part;
+  double* __restrict__ net_wl = rq.net_wl;
+  double* __restrict__ net_hp = rq.net_hp;
   extern __shared__ float2 smem[];
   float2* pos = smem;
   float2* off = smem + cap;
   __shared__ uint32_t bigmeta[NW];   // extents of the last NW nets of the order
   __shared__ int q_big, q_small;     // work counters
-  const int k = blockIdx.x, t = threadIdx.x, nblk = gridDim.x;
   const int lane = t & (kWave - 1), wv = t / kWave;
   const int e0 = nb_net_ptr[k], e1 = nb_net_ptr[k + 1];
   const int p0 = net_ptr[e0], p1 = net_ptr[e1];
@@ -520,7 +537,9 @@ __global__ void __launch_bounds__(NW)
       const uint32_t mj = j < NW ? bigmeta[j] : meta[nn - 1 - j];
       const int deg = (int)(mj & 0xffffu);
       if (deg <= kSmall) break;   // every net left is small
-      const int b0 = (int)(mj >> 16), b1 = b0 + deg;
+      // extents come from the index; kept inside the staged pins whatever it
+      // holds, so a block never leaves its LDS
+      const int b0 = min((int)(mj >> 16), np - 1), b1 = min(b0 + deg, np);
       const float2 r = pos[b0];
       wave_lds_sync();
       constexpr int H = 4;   // pins per lane whose LDS loads are issued together
@@ -612,9 +631,15 @@ __global__ void __launch_bounds__(NW)
         }
       }
       if (lane == 0) {
-        acc_wa += net_wl_value<LSE>(mx, lx, wpx, wmx, spx, smx, gamma) +
-                  net_wl_value<LSE>(my, ly, wpy, wmy, spy, smy, gamma);
-        acc_hp += (double)(mx - lx) + (double)(my - ly);
+        const double vw = net_wl_value<LSE>(mx, lx, wpx, wmx, spx, smx, gamma) +
+                          net_wl_value<LSE>(my, ly, wpy, wmy, spy, smy, gamma);
+        const double vh = (double)(mx - lx) + (double)(my - ly);
+        acc_wa += vw;
+        acc_hp += vh;
+        if (net_wl) {
+          net_wl[p0 + b0] = vw;
+          net_hp[p0 + b0] = vh;
+        }
       }
     }
 
@@ -634,7 +659,9 @@ __global__ void __launch_bounds__(NW)
       const int li = cc * kWave + lane;
       int deg = li < nn ? (int)(mcur & 0xffffu) : 0;
       if (deg > kSmall) deg = 0;   // done above
-      const int l0 = (int)(mcur >> 16);
+      // kept inside the staged pins whatever the index holds
+      const int l0 = min((int)(mcur >> 16), np - 1);
+      deg = min(deg, np - l0);
       // the chunk's largest small degree, uniform across the wavefront
       const int wdeg = wave_max_dpp_i(deg);
       if (deg == 1) pos[l0] = make_float2(0.0f, 0.0f);
@@ -702,9 +729,15 @@ __global__ void __launch_bounds__(NW)
                         emy[j] * rsmy * (1.0f - (dmy - wmy) * inv_gamma));
             }
           }
-          acc_wa += net_wl_value<LSE>(mx, lx, wpx, wmx, spx, smx, gamma) +
-                    net_wl_value<LSE>(my, ly, wpy, wmy, spy, smy, gamma);
-          acc_hp += (double)(mx - lx) + (double)(my - ly);
+          const double vw = net_wl_value<LSE>(mx, lx, wpx, wmx, spx, smx, gamma) +
+                            net_wl_value<LSE>(my, ly, wpy, wmy, spy, smy, gamma);
+          const double vh = (double)(mx - lx) + (double)(my - ly);
+          acc_wa += vw;
+          acc_hp += vh;
+          if (net_wl) {
+            net_wl[p0 + l0] = vw;
+            net_hp[p0 + l0] = vh;
+          }
         }
       }
       cc = cn;
@@ -734,14 +767,20 @@ __global__ void __launch_bounds__(NW)
 // the largest scale that keeps every pin within a 32-bit conversion; the
 // 64-bit sums then hold any number of pins.  A non-finite pin gradient makes
 // its cell's sum NaN.
-template <int MODE>
-__global__ void __launch_bounds__(kSumThreads)
-    k_xch_cellsum(int m, int cpb, const int32_t* __restrict__ cb_a_ptr,
-                  const uint16_t* __restrict__ lc, const float2* __restrict__ T, float scale,
-                  double inv_scale, CellGradArgs a) {
+template <int MODE, bool DENS, int NB>
+__global__ void __launch_bounds__(kSumThreads) k_xch_cellsum(SumBatch<NB> sb) {
+  const SumReq& rq = sb.r[blockIdx.y];
+  const int cb = blockIdx.x, t = threadIdx.x;
+  if (cb >= rq.ncb) return;
+  const int m = rq.m, cpb = rq.cpb;
+  const int32_t* __restrict__ cb_a_ptr = rq.cb_a_ptr;
+  const uint16_t* __restrict__ lc = rq.lc;
+  const float2* __restrict__ T = rq.T;
+  const float scale = rq.fx_scale;
+  const double inv_scale = rq.inv_scale;
+  const CellGradArgs& a = rq.a;
   __shared__ unsigned long long ax[kXchCells], ay[kXchCells];
   __shared__ unsigned char bad[kXchCells];
-  const int cb = blockIdx.x, t = threadIdx.x;
   for (int c = t; c < kXchCells; c += kSumThreads) {
     ax[c] = 0ull;
     ay[c] = 0ull;
@@ -788,28 +827,45 @@ __global__ void __launch_bounds__(kSumThreads)
   __syncthreads();
   // each cell's gradient: its density part from its first-band entry (one
   // 8-byte read; all of a thread's reads issued together) or, for a cell
-  // without one, from the maps; plus its wirelength sum
+  // without one, from the maps; plus its wirelength sum (DENS = false: the
+  // wirelength sum alone, written or added to the gradient)
   constexpr int PC = kXchCells / kSumThreads;
   const int c0 = cb * cpb;
   int ep[PC];
   float2 d[PC];
+  if (DENS) {
 #pragma unroll
-  for (int k = 0; k < PC; ++k) ep[k] = a.epos[min(c0 + t + k * kSumThreads, m - 1)];
+    for (int k = 0; k < PC; ++k) ep[k] = a.epos[min(c0 + t + k * kSumThreads, m - 1)];
 #pragma unroll
-  for (int k = 0; k < PC; ++k) d[k] = a.egrad[max(ep[k], 0)];
+    for (int k = 0; k < PC; ++k) d[k] = a.egrad[max(ep[k], 0)];
+  } else if (a.accumulate) {
+#pragma unroll
+    for (int k = 0; k < PC; ++k) {
+      const int ci = min(c0 + t + k * kSumThreads, m - 1);
+      d[k] = make_float2(a.gx[ci], a.gy[ci]);
+    }
+  }
 #pragma unroll
   for (int k = 0; k < PC; ++k) {
     const int c = t + k * kSumThreads, ci = c0 + c;
     if (c >= cpb || ci >= m) break;
-    if (ep[k] < 0)
+    if (DENS && ep[k] < 0)
       d[k] = cell_density_grad<MODE, true>(a.g, a.x[ci], a.y[ci], a.w[ci], a.h[ci], nullptr,
                                            nullptr, a.exy, a.psi);
     const float sx = bad[c] ? __builtin_nanf("") : (float)((double)(long long)ax[c] * inv_scale);
     const float sy = bad[c] ? __builtin_nanf("") : (float)((double)(long long)ay[c] * inv_scale);
-    a.gx[ci] = a.scale * d[k].x + sx;
-    a.gy[ci] = a.scale * d[k].y + sy;
+    if (DENS) {
+      a.gx[ci] = a.scale * d[k].x + sx;
+      a.gy[ci] = a.scale * d[k].y + sy;
+    } else if (a.accumulate) {
+      a.gx[ci] = d[k].x + sx;
+      a.gy[ci] = d[k].y + sy;
+    } else {
+      a.gx[ci] = sx;
+      a.gy[ci] = sy;
+    }
   }
-  if ((int)blockIdx.x == a.fin_block) {
+  if (cb == a.fin_block) {
     __syncthreads();
     eval_scalars<kSumThreads>(a.fin);
   }
@@ -817,70 +873,196 @@ __global__ void __launch_bounds__(kSumThreads)
 
 }  // namespace
 
+// Fixed-point scale 2^S of the cell sums: the largest S <= 26 with
+// bound * 2^S <= 2^30 for the largest pin gradient component bound.
+static int cellsum_shift(int max_degree) {
+  const double bound = 1.15 + log((double)(max_degree > 2 ? max_degree : 2));
+  int S = 26;
+  while (S > 0 && bound * ldexp(1.0, S) > ldexp(1.0, 30)) --S;
+  return S;
+}
+
+SumReq sum_req(const XchDims& d, const XchIndex& X, const float2* T, const CellGradArgs& a) {
+  SumReq q;
+  q.m = d.m;
+  q.cpb = d.cpb;
+  q.ncb = d.ncb;
+  q.cb_a_ptr = X.cb_a_ptr;
+  q.lc = X.lc;
+  q.T = T;
+  const int S = cellsum_shift(d.max_degree);
+  q.fx_scale = (float)ldexp(1.0, S);
+  q.inv_scale = ldexp(1.0, -S);
+  q.a = a;
+  return q;
+}
+
+template <int NB>
+static hipError_t cellsum_nb(const SumBatch<NB>& sb, int max_ncb, int grad_mode, bool dens,
+                             hipStream_t s) {
+  const dim3 grid(max_ncb, sb.count), block(kSumThreads);
+  if (!dens)
+    hipLaunchKernelGGL((k_xch_cellsum<FFTPL_GRAD_FIELD, false, NB>), grid, block, 0, s, sb);
+  else if (grad_mode == FFTPL_GRAD_EXACT)
+    hipLaunchKernelGGL((k_xch_cellsum<FFTPL_GRAD_EXACT, true, NB>), grid, block, 0, s, sb);
+  else
+    hipLaunchKernelGGL((k_xch_cellsum<FFTPL_GRAD_FIELD, true, NB>), grid, block, 0, s, sb);
+  return hipGetLastError();
+}
+
+hipError_t launch_xch_cellsum_batch(const SumReq* reqs, int count, int grad_mode, bool dens,
+                                    hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  if (count > kMaxBatch) return hipErrorInvalidValue;
+  int max_ncb = 0;
+  for (int i = 0; i < count; ++i)
+    if (reqs[i].m > 0) max_ncb = std::max(max_ncb, reqs[i].ncb);
+  if (max_ncb == 0) return hipSuccess;
+  if (count == 1) {
+    SumBatch<1> sb;
+    sb.count = 1;
+    sb.r[0] = reqs[0];
+    return cellsum_nb(sb, max_ncb, grad_mode, dens, s);
+  }
+  SumBatch<kMaxBatch> sb;
+  sb.count = count;
+  for (int i = 0; i < count; ++i) sb.r[i] = reqs[i];
+  return cellsum_nb(sb, max_ncb, grad_mode, dens, s);
+}
+
 hipError_t launch_xch_cellsum(const XchDims& d, const XchIndex& X, const float2* T,
                               const CellGradArgs& a, int grad_mode, hipStream_t s) {
   if (d.m <= 0) return hipSuccess;
-  // fixed-point scale 2^S: the largest S <= 26 with bound * 2^S <= 2^30
-  const double bound = 1.15 + log((double)(d.max_degree > 2 ? d.max_degree : 2));
-  int S = 26;
-  while (S > 0 && bound * ldexp(1.0, S) > ldexp(1.0, 30)) --S;
-  if (grad_mode == FFTPL_GRAD_EXACT)
-    hipLaunchKernelGGL(k_xch_cellsum<FFTPL_GRAD_EXACT>, dim3(d.ncb), dim3(kSumThreads), 0, s,
-                       d.m, d.cpb, X.cb_a_ptr, X.lc, T, (float)ldexp(1.0, S), ldexp(1.0, -S),
-                       a);
-  else
-    hipLaunchKernelGGL(k_xch_cellsum<FFTPL_GRAD_FIELD>, dim3(d.ncb), dim3(kSumThreads), 0, s,
-                       d.m, d.cpb, X.cb_a_ptr, X.lc, T, (float)ldexp(1.0, S), ldexp(1.0, -S),
-                       a);
+  const SumReq q = sum_req(d, X, T, a);
+  return launch_xch_cellsum_batch(&q, 1, grad_mode, true, s);
+}
+
+XchReq xch_req(const XchDims& d, const XchIndex& X, const float* x, const float* y, float2* T,
+               const int32_t* net_ptr, const float* pin_dx, const float* pin_dy, float gamma,
+               double* part) {
+  XchReq q;
+  q.m = d.m;
+  q.cpb = d.cpb;
+  q.ncb = d.ncb;
+  q.cb_a_ptr = X.cb_a_ptr;
+  q.lc = X.lc;
+  q.x = x;
+  q.y = y;
+  q.T = T;
+  q.num_pins = d.num_pins;
+  q.cap = d.cap;
+  q.nnb = d.nnb;
+  q.net_ptr = net_ptr;
+  q.nb_net_ptr = X.nb_net_ptr;
+  q.nmeta = X.nmeta;
+  q.a_of_b = X.a_of_b;
+  q.lcsr = X.lcsr;
+  q.pin_dx = pin_dx;
+  q.pin_dy = pin_dy;
+  q.gamma = gamma;
+  q.inv_gamma = 1.0f / gamma;
+  q.part = part;
+  return q;
+}
+
+template <int NB>
+static hipError_t spread_nb(const XchBatch<NB>& xb, int max_ncb, hipStream_t s) {
+  hipLaunchKernelGGL((k_xch_spread<NB>), dim3(max_ncb * kXchSpreadSplit, xb.count), dim3(NT),
+                     0, s, xb);
   return hipGetLastError();
+}
+
+hipError_t launch_xch_spread_batch(const XchReq* reqs, int count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  if (count > kMaxBatch) return hipErrorInvalidValue;
+  int max_ncb = 0;
+  for (int i = 0; i < count; ++i) max_ncb = std::max(max_ncb, reqs[i].ncb);
+  if (max_ncb == 0) return hipSuccess;
+  if (count == 1) {
+    XchBatch<1> xb;
+    xb.count = 1;
+    xb.r[0] = reqs[0];
+    return spread_nb(xb, max_ncb, s);
+  }
+  XchBatch<kMaxBatch> xb;
+  xb.count = count;
+  for (int i = 0; i < count; ++i) xb.r[i] = reqs[i];
+  return spread_nb(xb, max_ncb, s);
 }
 
 hipError_t launch_xch_spread(const XchDims& d, const XchIndex& X, const float* x,
                              const float* y, float2* T, hipStream_t s) {
   if (d.ncb <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_xch_spread, dim3(d.ncb * kXchSpreadSplit), dim3(NT), 0, s, d.m, d.cpb,
-                     X.cb_a_ptr, X.lc, x, y, T);
+  const XchReq q = xch_req(d, X, x, y, T, nullptr, nullptr, nullptr, 1.0f, nullptr);
+  return launch_xch_spread_batch(&q, 1, s);
+}
+
+// more than 64 KiB of dynamic LDS has to be allowed explicitly, once per
+// device and kernel instantiation (setting it twice from racing threads is
+// harmless)
+template <typename K>
+static hipError_t allow_big_lds(K* kernel, std::atomic<bool>* flags) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  if (!flags[dev].load(std::memory_order_acquire)) {
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(sizeof(float2) * 2 * kXchPinCap));
+    if (e != hipSuccess) return e;
+    flags[dev].store(true, std::memory_order_release);
+  }
+  return hipSuccess;
+}
+
+template <bool LSE, int NB>
+static hipError_t wa_nb(const XchBatch<NB>& xb, int max_nnb, int max_cap, hipStream_t s) {
+  const size_t lds = sizeof(float2) * 2 * (size_t)max_cap;
+  const dim3 grid(max_nnb, xb.count);
+  if (max_cap <= kXchPinLds2) {
+    hipLaunchKernelGGL((k_xch_wa<kStageS, LSE, NB>), grid, dim3(NW), lds, s, xb);
+  } else {
+    static std::atomic<bool> attr[kMaxDevices];
+    const hipError_t e = allow_big_lds(&k_xch_wa<kStageL, LSE, NB>, attr);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_xch_wa<kStageL, LSE, NB>), grid, dim3(NW), lds, s, xb);
+  }
   return hipGetLastError();
 }
 
 template <bool LSE>
-hipError_t launch_xch_wa_model(const XchDims& d, const XchIndex& X, const int32_t* net_ptr,
-                               const float* pin_dx, const float* pin_dy, float gamma, float2* T,
-                               double* wa_part, hipStream_t s) {
-  const size_t lds = sizeof(float2) * 2 * (size_t)d.cap;
-  if (d.cap <= kXchPinLds2) {
-    hipLaunchKernelGGL((k_xch_wa<kStageS, LSE>), dim3(d.nnb), dim3(NW), lds, s, d.num_pins,
-                       d.cap, net_ptr, X.nb_net_ptr, X.nmeta, X.a_of_b, X.lcsr, pin_dx, pin_dy,
-                       gamma, 1.0f / gamma, T, wa_part);
-  } else {
-    // more than 64 KiB of dynamic LDS has to be allowed explicitly, once per
-    // device (the flags are per kernel instantiation; setting the attribute
-    // twice from racing threads is harmless)
-    static std::atomic<bool> attr[kMaxDevices];
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return e;
-    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
-    if (!attr[dev].load(std::memory_order_acquire)) {
-      e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_xch_wa<kStageL, LSE>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)(sizeof(float2) * 2 * kXchPinCap));
-      if (e != hipSuccess) return e;
-      attr[dev].store(true, std::memory_order_release);
-    }
-    hipLaunchKernelGGL((k_xch_wa<kStageL, LSE>), dim3(d.nnb), dim3(NW), lds, s, d.num_pins,
-                       d.cap, net_ptr, X.nb_net_ptr, X.nmeta, X.a_of_b, X.lcsr, pin_dx, pin_dy,
-                       gamma, 1.0f / gamma, T, wa_part);
+static hipError_t wa_model(const XchReq* reqs, int count, hipStream_t s) {
+  int max_nnb = 0, max_cap = 1;
+  for (int i = 0; i < count; ++i) {
+    max_nnb = std::max(max_nnb, reqs[i].nnb);
+    max_cap = std::max(max_cap, reqs[i].cap);
   }
-  return hipGetLastError();
+  if (max_nnb == 0) return hipSuccess;
+  if (count == 1) {
+    XchBatch<1> xb;
+    xb.count = 1;
+    xb.r[0] = reqs[0];
+    return wa_nb<LSE, 1>(xb, max_nnb, max_cap, s);
+  }
+  XchBatch<kMaxBatch> xb;
+  xb.count = count;
+  for (int i = 0; i < count; ++i) xb.r[i] = reqs[i];
+  return wa_nb<LSE, kMaxBatch>(xb, max_nnb, max_cap, s);
+}
+
+hipError_t launch_xch_wa_batch(const XchReq* reqs, int count, int wl_model, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  if (count > kMaxBatch) return hipErrorInvalidValue;
+  return wl_model == FFTPL_WL_LSE ? wa_model<true>(reqs, count, s)
+                                  : wa_model<false>(reqs, count, s);
 }
 
 hipError_t launch_xch_wa(const XchDims& d, const XchIndex& X, const int32_t* net_ptr,
                          const float* pin_dx, const float* pin_dy, float gamma, int wl_model,
                          float2* T, double* wa_part, hipStream_t s) {
-  return wl_model == FFTPL_WL_LSE
-             ? launch_xch_wa_model<true>(d, X, net_ptr, pin_dx, pin_dy, gamma, T, wa_part, s)
-             : launch_xch_wa_model<false>(d, X, net_ptr, pin_dx, pin_dy, gamma, T, wa_part, s);
+  const XchReq q = xch_req(d, X, nullptr, nullptr, T, net_ptr, pin_dx, pin_dy, gamma, wa_part);
+  return launch_xch_wa_batch(&q, 1, wl_model, s);
 }
 
 }  // namespace fftpl

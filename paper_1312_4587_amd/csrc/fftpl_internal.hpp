@@ -376,6 +376,10 @@ struct Plan {
   int n = 0;
   int mode = 0;
   int device = 0;
+  // batch slots: every map below (and rowsum, partials) holds max_batch
+  // consecutive copies, one per design of a batched evaluation
+  int max_batch = 1;
+  size_t part_stride = 0;   // doubles of partials per slot
   // FFT-mode tables (float2): fft twiddles exp(-2 pi i t / n), t < n, and
   // (cos, sin)(pi k / (2n)), k <= n/2; frequency table w_u = pi u / n.
   float2* fft_tw = nullptr;
@@ -565,6 +569,33 @@ struct BandLayout {
 BandLayout band_layout(int n, int m, int num_nets, int num_pins, void* work,
                        size_t* bytes_out);
 
+// ---- batches: several designs of one grid side in one launch per stage ----
+// Kernels take a batch of per-design descriptors by value (the kernel
+// argument block, so nothing is staged through memory) and run design
+// blockIdx.y; a design with fewer blocks than the launch's x extent leaves
+// the rest idle.  NB = 1 for single designs keeps their argument blocks small.
+constexpr int kMaxBatch = FFTPL_MAX_BATCH;
+
+// One design's banded scatter and band gather.
+struct BandReq {
+  GridF g;
+  BandLayout L;
+  const float *x = nullptr, *y = nullptr, *w = nullptr, *h = nullptr;
+  const float* base = nullptr;   // scatter: fixed charge (or null)
+  float* rho = nullptr;          // scatter: the density map written
+  const float2* exy = nullptr;   // gather: (Ex, Ey), or (Dx, Dy) in exact mode
+  const float* psi = nullptr;    // gather: exact mode
+};
+template <int NB>
+struct BandBatch {
+  int count = 0;
+  BandReq r[NB];
+};
+hipError_t launch_band_scatter_batch(const BandReq* reqs, int count, hipStream_t s,
+                                     Plan* tp = nullptr);
+hipError_t launch_band_gather_batch(const BandReq* reqs, int count, int grad_mode,
+                                    hipStream_t s);
+
 // egrad[entry] = density gradient (before lambda) of each cell at its
 // first-band entry (after launch_band_scatter and the solve).
 hipError_t launch_band_gather(const GridF& g, const BandLayout& L, const float* exy,
@@ -670,11 +701,64 @@ struct CellGradArgs {
   // separate finalize launch
   FinalArgs fin;
   int fin_block = -1;
+  // without a density part (the wirelength alone): add to gx, gy instead of
+  // overwriting them
+  int accumulate = 0;
 };
 // g (CellGradArgs) for every cell, the wirelength part being the sum over
 // the cell's pins of their gradients in T (after launch_xch_wa).
 hipError_t launch_xch_cellsum(const XchDims& d, const XchIndex& X, const float2* T,
                               const CellGradArgs& a, int grad_mode, hipStream_t s);
+
+// One design's pin exchange: the spread (cells -> pins) and the net blocks.
+struct XchReq {
+  int m = 0, cpb = 0, ncb = 0;
+  const int32_t* cb_a_ptr = nullptr;
+  const uint16_t* lc = nullptr;
+  const float *x = nullptr, *y = nullptr;
+  float2* T = nullptr;
+  int num_pins = 0, cap = 1, nnb = 0;
+  const int32_t* net_ptr = nullptr;
+  const int32_t* nb_net_ptr = nullptr;
+  const uint32_t* nmeta = nullptr;
+  const int32_t* a_of_b = nullptr;
+  const uint16_t* lcsr = nullptr;
+  const float *pin_dx = nullptr, *pin_dy = nullptr;
+  float gamma = 1.0f, inv_gamma = 1.0f;
+  double* part = nullptr;
+  // per-net values at each net's first pin (a test export), or null
+  double *net_wl = nullptr, *net_hp = nullptr;
+};
+template <int NB>
+struct XchBatch {
+  int count = 0;
+  XchReq r[NB];
+};
+// One design's per-cell sums (and density part).
+struct SumReq {
+  int m = 0, cpb = 0, ncb = 0;
+  const int32_t* cb_a_ptr = nullptr;
+  const uint16_t* lc = nullptr;
+  const float2* T = nullptr;
+  float fx_scale = 1.0f;   // fixed-point scale of the pin gradients
+  double inv_scale = 1.0;
+  CellGradArgs a;
+};
+template <int NB>
+struct SumBatch {
+  int count = 0;
+  SumReq r[NB];
+};
+XchReq xch_req(const XchDims& d, const XchIndex& X, const float* x, const float* y, float2* T,
+               const int32_t* net_ptr, const float* pin_dx, const float* pin_dy, float gamma,
+               double* part);
+SumReq sum_req(const XchDims& d, const XchIndex& X, const float2* T, const CellGradArgs& a);
+// count <= kMaxBatch designs per launch; the net blocks of one launch share
+// the wirelength model.  dens = false: the cell sums without density part.
+hipError_t launch_xch_spread_batch(const XchReq* reqs, int count, hipStream_t s);
+hipError_t launch_xch_wa_batch(const XchReq* reqs, int count, int wl_model, hipStream_t s);
+hipError_t launch_xch_cellsum_batch(const SumReq* reqs, int count, int grad_mode, bool dens,
+                                    hipStream_t s);
 // ---- placement iteration (driver.hip) --------------------------------------
 size_t step_stats_work_doubles();
 hipError_t launch_step_stats(int m, const float* ux, const float* uy, const float* upx,
@@ -709,6 +793,27 @@ struct SpectralArgs {
   bool diff = false;
 };
 hipError_t spectral_fft(Plan& p, const SpectralArgs& a, hipStream_t s);
+// count designs (count <= the plan's max_batch, one difference mode): design
+// i uses batch slot i of the plan's intermediate maps; one launch per pass.
+hipError_t spectral_fft_batch(Plan& p, const SpectralArgs* a, int count, hipStream_t s);
+
+// One design of a batched FFT solve: its maps and the plan slot it uses.
+struct SpecReq {
+  const float* rho = nullptr;
+  float *psi = nullptr, *ex = nullptr, *ey = nullptr;
+  float2* exy = nullptr;
+  float* bT = nullptr;        // plan slot: transposed row transforms
+  double* rowsum = nullptr;   // plan slot: double row sums
+  float *P = nullptr, *Q = nullptr;   // plan slot: column pass outputs
+  const float *base = nullptr, *cap = nullptr;
+  float rho_t = 1.0f, eps = 0.0f;
+  double *en_part = nullptr, *tau_part = nullptr;
+};
+template <int NB>
+struct SpecBatch {
+  int count = 0;
+  SpecReq r[NB];
+};
 hipError_t spectral_gemm(Plan& p, const SpectralArgs& a, hipStream_t s);
 int gemm_plan_init(Plan& p, hipStream_t s);   // returns fftpl_status
 void gemm_plan_free(Plan& p);

@@ -261,12 +261,19 @@ __device__ __forceinline__ void diff_weights(float2 cs, float& dm_k, float& dm_k
 // ---------------------------------------------------------------------------
 // Pass A: rows -> bT (transposed), row sums in double; optional overflow sums.
 // ---------------------------------------------------------------------------
-template <int N>
+template <int N, int NB>
 __global__ void __launch_bounds__(FftShape<N>::NT)
-    k_rows_dct2(const float* __restrict__ rho, float* __restrict__ bT,
-                double* __restrict__ rowsum, const float2* __restrict__ tw_g,
-                const float2* __restrict__ cs_g, const float* __restrict__ base,
-                const float* __restrict__ cap, float rho_t, double* __restrict__ tau_part) {
+    k_rows_dct2(SpecBatch<NB> sb, const float2* __restrict__ tw_g,
+                const float2* __restrict__ cs_g) {
+  // design blockIdx.y of the batch
+  const SpecReq& rq = sb.r[blockIdx.y];
+  const float* __restrict__ rho = rq.rho;
+  float* __restrict__ bT = rq.bT;
+  double* __restrict__ rowsum = rq.rowsum;
+  const float* __restrict__ base = rq.base;
+  const float* __restrict__ cap = rq.cap;
+  const float rho_t = rq.rho_t;
+  double* __restrict__ tau_part = rq.tau_part;
   constexpr int NT = FftShape<N>::NT;
   constexpr int PER = (N + NT - 1) / NT, PK = (N / 2 + NT) / NT;
   __shared__ float2 buf[N];
@@ -363,12 +370,16 @@ __global__ void __launch_bounds__(FftShape<N>::NT)
 // Pass B: columns u1 = 2q, u2 = 2q+1 (rows of bT).  Column 0 is rebuilt from
 // the double row sums minus their mean so that the DC never enters float32.
 // ---------------------------------------------------------------------------
-template <int N, bool DIFF>
+template <int N, bool DIFF, int NB>
 __global__ void __launch_bounds__(FftShape<N>::NT)
-    k_cols_solve(const float* __restrict__ bT, const double* __restrict__ rowsum,
-                 float* __restrict__ P, float* __restrict__ Q,
-                 const float2* __restrict__ tw_g, const float2* __restrict__ cs_g,
-                 const float* __restrict__ wf_g, float eps) {
+    k_cols_solve(SpecBatch<NB> sb, const float2* __restrict__ tw_g,
+                 const float2* __restrict__ cs_g, const float* __restrict__ wf_g) {
+  const SpecReq& rq = sb.r[blockIdx.y];
+  const float* __restrict__ bT = rq.bT;
+  const double* __restrict__ rowsum = rq.rowsum;
+  float* __restrict__ P = rq.P;
+  float* __restrict__ Q = rq.Q;
+  const float eps = rq.eps;
   constexpr int NT = FftShape<N>::NT;
   constexpr int PER = (N + NT - 1) / NT, PK = (N / 2 + NT) / NT;
   __shared__ float2 buf0[N];
@@ -478,14 +489,19 @@ __global__ void __launch_bounds__(FftShape<N>::NT)
 // ---------------------------------------------------------------------------
 // Pass C: rows r1 = 2p, r2 = 2p+1 of P and Q -> psi, Ex, Ey; energy.
 // ---------------------------------------------------------------------------
-template <int N, bool DIFF>
+template <int N, bool DIFF, int NB>
 __global__ void __launch_bounds__(FftShape<N>::NT)
-    k_rows_inverse(const float* __restrict__ P, const float* __restrict__ Q,
-                   const float* __restrict__ rho, float* __restrict__ psi,
-                   float* __restrict__ ex, float* __restrict__ ey,
-                   float2* __restrict__ exy, double* __restrict__ energy,
-                   const float2* __restrict__ tw_g, const float2* __restrict__ cs_g,
-                   const float* __restrict__ wf_g) {
+    k_rows_inverse(SpecBatch<NB> sb, const float2* __restrict__ tw_g,
+                   const float2* __restrict__ cs_g, const float* __restrict__ wf_g) {
+  const SpecReq& rq = sb.r[blockIdx.y];
+  const float* __restrict__ P = rq.P;
+  const float* __restrict__ Q = rq.Q;
+  const float* __restrict__ rho = rq.rho;
+  float* __restrict__ psi = rq.psi;
+  float* __restrict__ ex = rq.ex;
+  float* __restrict__ ey = rq.ey;
+  float2* __restrict__ exy = rq.exy;
+  double* __restrict__ energy = rq.en_part;
   constexpr int NT = FftShape<N>::NT;
   constexpr int PER = (N + NT - 1) / NT, PK = (N / 2 + NT) / NT;
   __shared__ float2 bufa[N];
@@ -612,49 +628,90 @@ __global__ void __launch_bounds__(FftShape<N>::NT)
   }
 }
 
-template <int N>
-hipError_t run_fft(Plan& p, const SpectralArgs& a, hipStream_t s) {
-  const dim3 grid(N / 2), block(FftShape<N>::NT);
-  hipLaunchKernelGGL(k_rows_dct2<N>, grid, block, 0, s, a.rho, p.tmp0, p.rowsum, p.fft_tw,
-                     p.dct_cs, a.base, a.cap, a.rho_t, a.tau_part);
+template <int N, int NB>
+hipError_t run_fft_nb(Plan& p, const SpecBatch<NB>& sb, bool diff, hipStream_t s) {
+  const dim3 grid(N / 2, sb.count), block(FftShape<N>::NT);
+  hipLaunchKernelGGL((k_rows_dct2<N, NB>), grid, block, 0, s, sb, p.fft_tw, p.dct_cs);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   plan_mark(p, "k_rows_dct2", s);
-  if (a.diff)
-    hipLaunchKernelGGL((k_cols_solve<N, true>), grid, block, 0, s, p.tmp0, p.rowsum, p.tmp1,
-                       p.tmp2, p.fft_tw, p.dct_cs, p.wfreq, a.eps);
+  if (diff)
+    hipLaunchKernelGGL((k_cols_solve<N, true, NB>), grid, block, 0, s, sb, p.fft_tw, p.dct_cs,
+                       p.wfreq);
   else
-    hipLaunchKernelGGL((k_cols_solve<N, false>), grid, block, 0, s, p.tmp0, p.rowsum, p.tmp1,
-                       p.tmp2, p.fft_tw, p.dct_cs, p.wfreq, a.eps);
+    hipLaunchKernelGGL((k_cols_solve<N, false, NB>), grid, block, 0, s, sb, p.fft_tw,
+                       p.dct_cs, p.wfreq);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   plan_mark(p, "k_cols_solve", s);
-  if (a.diff)
-    hipLaunchKernelGGL((k_rows_inverse<N, true>), grid, block, 0, s, p.tmp1, p.tmp2, a.rho,
-                       a.psi, a.ex, a.ey, reinterpret_cast<float2*>(a.exy), a.en_part,
-                       p.fft_tw, p.dct_cs, p.wfreq);
+  if (diff)
+    hipLaunchKernelGGL((k_rows_inverse<N, true, NB>), grid, block, 0, s, sb, p.fft_tw,
+                       p.dct_cs, p.wfreq);
   else
-    hipLaunchKernelGGL((k_rows_inverse<N, false>), grid, block, 0, s, p.tmp1, p.tmp2, a.rho,
-                       a.psi, a.ex, a.ey, reinterpret_cast<float2*>(a.exy), a.en_part,
-                       p.fft_tw, p.dct_cs, p.wfreq);
+    hipLaunchKernelGGL((k_rows_inverse<N, false, NB>), grid, block, 0, s, sb, p.fft_tw,
+                       p.dct_cs, p.wfreq);
   e = hipGetLastError();
   plan_mark(p, "k_rows_inverse", s);
   return e;
 }
 
+// The descriptor of request a for the plan's batch slot `slot`.
+SpecReq spec_req(Plan& p, const SpectralArgs& a, int slot) {
+  const size_t nn = (size_t)p.n * p.n;
+  SpecReq q;
+  q.rho = a.rho;
+  q.psi = a.psi;
+  q.ex = a.ex;
+  q.ey = a.ey;
+  q.exy = reinterpret_cast<float2*>(a.exy);
+  q.bT = p.tmp0 + slot * nn;
+  q.rowsum = p.rowsum + (size_t)slot * p.n;
+  q.P = p.tmp1 + slot * nn;
+  q.Q = p.tmp2 + slot * nn;
+  q.base = a.base;
+  q.cap = a.cap;
+  q.rho_t = a.rho_t;
+  q.eps = a.eps;
+  q.en_part = a.en_part;
+  q.tau_part = a.tau_part;
+  return q;
+}
+
+template <int N>
+hipError_t run_fft(Plan& p, const SpectralArgs* a, int count, hipStream_t s) {
+  if (count == 1) {
+    SpecBatch<1> sb;
+    sb.count = 1;
+    sb.r[0] = spec_req(p, a[0], 0);
+    return run_fft_nb<N, 1>(p, sb, a[0].diff, s);
+  }
+  SpecBatch<kMaxBatch> sb;
+  sb.count = count;
+  for (int i = 0; i < count; ++i) sb.r[i] = spec_req(p, a[i], i);
+  return run_fft_nb<N, kMaxBatch>(p, sb, a[0].diff, s);
+}
+
 }  // namespace
 
-hipError_t spectral_fft(Plan& p, const SpectralArgs& a, hipStream_t s) {
+hipError_t spectral_fft_batch(Plan& p, const SpectralArgs* a, int count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  if (count > p.max_batch) return hipErrorInvalidValue;
+  for (int i = 1; i < count; ++i)
+    if (a[i].diff != a[0].diff) return hipErrorInvalidValue;
   switch (p.n) {
-    case 8: return run_fft<8>(p, a, s);
-    case 16: return run_fft<16>(p, a, s);
-    case 32: return run_fft<32>(p, a, s);
-    case 64: return run_fft<64>(p, a, s);
-    case 128: return run_fft<128>(p, a, s);
-    case 256: return run_fft<256>(p, a, s);
-    case 512: return run_fft<512>(p, a, s);
-    case 1024: return run_fft<1024>(p, a, s);
+    case 8: return run_fft<8>(p, a, count, s);
+    case 16: return run_fft<16>(p, a, count, s);
+    case 32: return run_fft<32>(p, a, count, s);
+    case 64: return run_fft<64>(p, a, count, s);
+    case 128: return run_fft<128>(p, a, count, s);
+    case 256: return run_fft<256>(p, a, count, s);
+    case 512: return run_fft<512>(p, a, count, s);
+    case 1024: return run_fft<1024>(p, a, count, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t spectral_fft(Plan& p, const SpectralArgs& a, hipStream_t s) {
+  return spectral_fft_batch(p, &a, 1, s);
 }
 
 }  // namespace fftpl

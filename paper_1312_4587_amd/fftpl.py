@@ -89,14 +89,15 @@ def status_string(status: int) -> str:
 class Plan:
     """fftpl_plan_create / fftpl_plan_destroy."""
 
-    def __init__(self, n: int, dct_mode: str = "fft", stream=None):
+    def __init__(self, n: int, dct_mode: str = "fft", stream=None, max_batch: int = 1):
         lib = _lib.load()
         h = ctypes.c_void_p()
         _check(lib.fftpl_plan_create(ctypes.byref(h), int(n), DCT_MODES[dct_mode],
-                                     _stream(stream)), "fftpl_plan_create")
+                                     int(max_batch), _stream(stream)), "fftpl_plan_create")
         self._h = h
         self.n = int(n)
         self.dct_mode = dct_mode
+        self.max_batch = int(max_batch)
 
     @property
     def handle(self):
@@ -105,18 +106,23 @@ class Plan:
         return self._h
 
     def info(self):
-        n, mode = ctypes.c_int32(), ctypes.c_int32()
-        _check(_lib.load().fftpl_plan_info(self.handle, ctypes.byref(n), ctypes.byref(mode)),
-               "fftpl_plan_info")
-        return n.value, mode.value
+        n, mode, mb = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(_lib.load().fftpl_plan_info(self.handle, ctypes.byref(n), ctypes.byref(mode),
+                                           ctypes.byref(mb)), "fftpl_plan_info")
+        return n.value, mode.value, mb.value
 
-    def maps(self):
-        """Views (no copy) of the plan's rho [n,n], psi [n,n] and exy [n,n,2]."""
+    def maps(self, slot: int = 0):
+        """Views (no copy) of the plan's rho [n,n], psi [n,n] and exy [n,n,2]
+        (batch slot ``slot``: request ``slot`` of the last batched group)."""
+        if not 0 <= slot < self.max_batch:
+            raise ValueError("slot outside the plan's batch")
         r, p, e = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
         _check(_lib.load().fftpl_plan_maps(self.handle, ctypes.byref(r), ctypes.byref(p),
                                            ctypes.byref(e)), "fftpl_plan_maps")
         n = self.n
-        return (_wrap(r.value, (n, n)), _wrap(p.value, (n, n)), _wrap(e.value, (n, n, 2)))
+        o = 4 * n * n * slot
+        return (_wrap(r.value + o, (n, n)), _wrap(p.value + o, (n, n)),
+                _wrap(e.value + 2 * o, (n, n, 2)))
 
     def timing(self, enable: bool = True):
         """fftpl_plan_timing: per-kernel HIP events on later calls."""
@@ -292,7 +298,8 @@ def xindex_bytes(num_cells: int, num_nets: int, num_pins: int, max_degree: int):
 
 def xindex_build(num_cells: int, net_ptr, pin_cell, max_degree: int, index, stream=None):
     """fftpl_xindex_build into the uint8 device tensor `index` (scratch
-    allocated here and released on return; the call synchronises)."""
+    allocated here and released on return; the call synchronises).  Returns
+    the index's key for fftpl_problem.xindex_key."""
     m = int(num_cells)
     E = int(net_ptr.numel()) - 1
     P = int(pin_cell.numel())
@@ -300,13 +307,15 @@ def xindex_build(num_cells: int, net_ptr, pin_cell, max_degree: int, index, stre
     if index.numel() < ib:
         raise FFTPLError(E_INVAL, "fftpl_xindex_build (index tensor too small)")
     work = torch.empty(max(wb, 1), dtype=torch.uint8, device="cuda")
+    key = ctypes.c_uint64(0)
     _check(_lib.load().fftpl_xindex_build(
         m, E, P, _ptr(net_ptr, torch.int32, E + 1, "net_ptr"),
         _ptr(pin_cell, torch.int32, P, "pin_cell"), int(max_degree),
         _ptr(index, torch.uint8, None, "index"), int(index.numel()),
-        _ptr(work, torch.uint8, None, "work"), int(work.numel()), _stream(stream)),
-        "fftpl_xindex_build")
+        _ptr(work, torch.uint8, None, "work"), int(work.numel()), ctypes.byref(key),
+        _stream(stream)), "fftpl_xindex_build")
     del work
+    return int(key.value)
 
 
 PATHS = ("xch", "slots", "atomic")
@@ -330,6 +339,8 @@ class Problem:
                  wl_model="wa", screening=0.0):
         if path not in PATHS:
             raise ValueError(f"path must be one of {PATHS}")
+        if path != "atomic" and grid.n > 1024:
+            raise ValueError("the atomic-free paths need n <= 1024; use path='atomic'")
         self.grid = grid
         self.path = path
         m = int(w.numel())
@@ -338,7 +349,7 @@ class Problem:
         n2 = grid.n * grid.n
         self.num_cells, self.num_nets, self.num_pins = m, E, P
         cell_ptr = pin_slot = work = xindex = None
-        work_bytes = xbytes = 0
+        work_bytes = xbytes = xkey = 0
         if max_degree is None:
             max_degree = int((net_ptr[1:] - net_ptr[:-1]).max().item()) if E > 0 else 0
         self.max_degree = int(max_degree)
@@ -354,7 +365,7 @@ class Problem:
         elif path == "xch":
             xbytes, _ = xindex_bytes(m, E, P, self.max_degree)
             xindex = torch.empty(max(xbytes, 1), dtype=torch.uint8, device="cuda")
-            xindex_build(m, net_ptr, pin_cell, self.max_degree, xindex, stream=stream)
+            xkey = xindex_build(m, net_ptr, pin_cell, self.max_degree, xindex, stream=stream)
         self.arrays = dict(w=w, h=h, net_ptr=net_ptr, pin_cell=pin_cell,
                            pin_dx=pin_dx, pin_dy=pin_dy, base=base, cap=cap,
                            cell_ptr=cell_ptr, pin_slot=pin_slot, work=work, xindex=xindex)
@@ -369,7 +380,7 @@ class Problem:
             _ptr(pin_slot, torch.int32, None, "pin_slot"),
             _ptr(work, torch.uint8, None, "work"), work_bytes,
             _ptr(xindex, torch.uint8, None, "xindex"), xbytes, self.max_degree,
-            float(screening))
+            float(screening), xkey)
 
     def set_objective(self, wl_model=None, screening=None) -> None:
         if wl_model is not None:
@@ -402,6 +413,45 @@ class Problem:
                    base=base, cap=cap, path=path, stream=stream,
                    max_degree=int(np.diff(inst.net_ptr).max()) if inst.num_nets else 0,
                    wl_model=wl_model, screening=screening)
+
+
+def problem_path(prob: Problem) -> str:
+    """fftpl_problem_path: the path an evaluation of prob takes."""
+    v = ctypes.c_int32()
+    _check(_lib.load().fftpl_problem_path(ctypes.byref(prob.c), ctypes.byref(v)),
+           "fftpl_problem_path")
+    return PATHS[v.value]
+
+
+def problem_density(prob: Problem, x, y, rho, stream=None):
+    """fftpl_problem_density: rho = base + cells through the problem's workspace."""
+    m = prob.num_cells
+    n2 = prob.grid.n ** 2
+    _check(_lib.load().fftpl_problem_density(
+        ctypes.byref(prob.c), _ptr(x, torch.float32, m, "x"), _ptr(y, torch.float32, m, "y"),
+        _ptr(rho, torch.float32, n2, "rho"), _stream(stream)), "fftpl_problem_density")
+
+
+def problem_wl_grad(prob: Problem, x, y, gamma, accumulate, gx, gy, wl=None, hpwl=None,
+                    stream=None):
+    """fftpl_problem_wl_grad: the problem's wirelength model through its
+    exchange index."""
+    m = prob.num_cells
+    _check(_lib.load().fftpl_problem_wl_grad(
+        ctypes.byref(prob.c), _ptr(x, torch.float32, m, "x"), _ptr(y, torch.float32, m, "y"),
+        float(gamma), int(accumulate), _ptr(gx, torch.float32, m, "gx"),
+        _ptr(gy, torch.float32, m, "gy"), _ptr(wl, torch.float64, 1, "wl"),
+        _ptr(hpwl, torch.float64, 1, "hpwl"), _stream(stream)), "fftpl_problem_wl_grad")
+
+
+def debug_net_values(prob: Problem, x, y, gamma, wl_first, hpwl_first, stream=None):
+    """fftpl_debug_net_values: per-net wirelength and HPWL at each net's first pin."""
+    m, P = prob.num_cells, prob.num_pins
+    _check(_lib.load().fftpl_debug_net_values(
+        ctypes.byref(prob.c), _ptr(x, torch.float32, m, "x"), _ptr(y, torch.float32, m, "y"),
+        float(gamma), _ptr(wl_first, torch.float64, P, "wl_first"),
+        _ptr(hpwl_first, torch.float64, P, "hpwl_first"), _stream(stream)),
+        "fftpl_debug_net_values")
 
 
 def eval(plan: Plan, prob: Problem, x, y, lam, gamma, grad_mode, gx, gy, out4,

@@ -9,10 +9,10 @@ RTOL = 1e-5          # relative L2 bound for float32 GPU vs float64 oracle
 
 
 def lib_or_build():
-    from paper_1312_4587_amd import _lib
-    if not os.path.exists(_lib.LIB_PATH):
-        from paper_1312_4587_amd import build
-        build.build()
+    """Load libfftpl.so, building it first when it is missing or was built
+    from other sources than the ones in the tree."""
+    from paper_1312_4587_amd import _lib, build
+    build.ensure_built()
     _lib.load()
 
 

@@ -37,7 +37,7 @@ def test_every_declared_symbol_is_exported_and_bound():
 
 def test_version_and_status_strings():
     lib = _lib()
-    assert lib.fftpl_version() == 10000
+    assert lib.fftpl_version() == 20000
     for st in (0, -1, -2, -3, -4, -5):
         assert lib.fftpl_status_string(st).startswith(b"FFTPL_")
     assert b"unknown" in lib.fftpl_status_string(17)
@@ -47,22 +47,25 @@ def test_struct_layouts_match_header():
     from paper_1312_4587_amd import _lib as L
     assert ctypes.sizeof(L.fftpl_grid) == 48
     assert L.fftpl_problem.w.offset == 64
-    assert ctypes.sizeof(L.fftpl_problem) == 64 + 8 * 8 + 4 * 8 + 24
+    assert ctypes.sizeof(L.fftpl_problem) == 64 + 8 * 8 + 4 * 8 + 24 + 8
     assert L.fftpl_problem.work_bytes.offset == 152
     assert L.fftpl_problem.xindex.offset == 160
     assert L.fftpl_problem.max_degree.offset == 176
+    assert L.fftpl_problem.xindex_key.offset == 184
 
 
 def test_argument_errors_are_reported_before_any_device_work():
     lib = _lib()
     from paper_1312_4587_amd import _lib as L
     h = ctypes.c_void_p()
-    assert lib.fftpl_plan_create(None, 64, 0, None) == -1
-    assert lib.fftpl_plan_create(ctypes.byref(h), 64, 7, None) == -1
+    assert lib.fftpl_plan_create(None, 64, 0, 1, None) == -1
+    assert lib.fftpl_plan_create(ctypes.byref(h), 64, 7, 1, None) == -1
+    for mb in (0, -1, 9):
+        assert lib.fftpl_plan_create(ctypes.byref(h), 64, 0, mb, None) == -1
     for n in (0, 4, 100, 2048):
-        assert lib.fftpl_plan_create(ctypes.byref(h), n, 0, None) == -4
+        assert lib.fftpl_plan_create(ctypes.byref(h), n, 0, 1, None) == -4
     for n in (32, 100, 8192):
-        assert lib.fftpl_plan_create(ctypes.byref(h), n, 1, None) == -4
+        assert lib.fftpl_plan_create(ctypes.byref(h), n, 1, 1, None) == -4
     g = L.fftpl_grid(64, 0, 0.0, 0.0, 1.0, 1.0, 1.0)
     bad = [L.fftpl_grid(0, 0, 0.0, 0.0, 1.0, 1.0, 1.0),
            L.fftpl_grid(64, 1, 0.0, 0.0, 1.0, 1.0, 1.0),
@@ -120,13 +123,76 @@ def test_argument_errors_are_reported_before_any_device_work():
     assert ib.value > 0 and wb.value > 0
     # too small buffers, missing arrays, pins without cells: rejected on the host
     assert lib.fftpl_xindex_build(10, 3, 6, p, p, 2, p, ib.value - 1, p, wb.value,
-                                  None) == -1
+                                  None, None) == -1
     assert lib.fftpl_xindex_build(10, 3, 6, p, p, 2, p, ib.value, p, wb.value - 1,
-                                  None) == -1
+                                  None, None) == -1
     assert lib.fftpl_xindex_build(10, 3, 6, None, p, 2, p, ib.value, p, wb.value,
+                                  None, None) == -1
+    assert lib.fftpl_xindex_build(0, 3, 6, p, p, 2, p, ib.value, p, wb.value, None,
                                   None) == -1
-    assert lib.fftpl_xindex_build(0, 3, 6, p, p, 2, p, ib.value, p, wb.value, None) == -1
     assert lib.fftpl_xindex_build(10, 3, 6, p, p, 8706, p, ib.value, p, wb.value,
-                                  None) == -4
+                                  None, None) == -4
     assert lib.fftpl_plan_destroy(None) == 0
-    assert lib.fftpl_plan_info(None, None, None) == -1
+    assert lib.fftpl_plan_info(None, None, None, None) == -1
+
+
+def _problem(L, n=64, m=10, E=3, P=6, **kw):
+    """An fftpl_problem over fake (never dereferenced) device addresses."""
+    p = ctypes.c_void_p(1 << 20)
+    pr = L.fftpl_problem(L.fftpl_grid(n, 0, 0.0, 0.0, 1.0, 1.0, 1.0), m, E, P, 0,
+                         p, p, None, None, p, p, p, p, None, None, None, 0, None, 0, 8, 0.0, 0)
+    for k, v in kw.items():
+        setattr(pr, k, v)
+    return pr
+
+
+def test_problem_paths_are_decided_on_the_host():
+    # which evaluation path a problem takes, and the errors for a workspace or
+    # an index that is given but cannot be used (never a silent fallback)
+    lib = _lib()
+    from paper_1312_4587_amd import _lib as L
+    path = ctypes.c_int32(-7)
+    pr = _problem(L)
+    assert lib.fftpl_problem_path(ctypes.byref(pr), ctypes.byref(path)) == 0
+    assert path.value == 2   # nothing given: float atomics
+    need = ctypes.c_uint64()
+    assert lib.fftpl_problem_work_bytes(64, 10, 3, 6, ctypes.byref(need)) == 0
+    work = 1 << 30
+    # a workspace without a pin index
+    pr = _problem(L, work=work, work_bytes=need.value)
+    assert lib.fftpl_problem_path(ctypes.byref(pr), ctypes.byref(path)) == -1
+    # the cell-major slots
+    pr = _problem(L, work=work, work_bytes=need.value, cell_ptr=work * 2, pin_slot=work * 3)
+    assert lib.fftpl_problem_path(ctypes.byref(pr), ctypes.byref(path)) == 0
+    assert path.value == 1
+    # too small a workspace, an unaligned one, n above the banded limit
+    pr = _problem(L, work=work, work_bytes=need.value - 1, cell_ptr=work * 2,
+                  pin_slot=work * 3)
+    assert lib.fftpl_problem_path(ctypes.byref(pr), ctypes.byref(path)) == -1
+    pr = _problem(L, work=work + 16, work_bytes=need.value, cell_ptr=work * 2,
+                  pin_slot=work * 3)
+    assert lib.fftpl_problem_path(ctypes.byref(pr), ctypes.byref(path)) == -1
+    pr = _problem(L, n=2048, work=work, work_bytes=1 << 40, cell_ptr=work * 2,
+                  pin_slot=work * 3)
+    assert lib.fftpl_problem_path(ctypes.byref(pr), ctypes.byref(path)) == -4
+    # the exchange index: needs its size and the key of its build; an index of
+    # another netlist (another key) is refused with FFTPL_E_STATE
+    ib, wb = ctypes.c_uint64(), ctypes.c_uint64()
+    assert lib.fftpl_xindex_bytes(10, 3, 6, 8, ctypes.byref(ib), ctypes.byref(wb)) == 0
+    pr = _problem(L, work=work, work_bytes=need.value, xindex=work * 4, xindex_bytes=ib.value,
+                  xindex_key=12345)
+    assert lib.fftpl_problem_path(ctypes.byref(pr), ctypes.byref(path)) == -5
+    pr.xindex_bytes = ib.value - 1
+    assert lib.fftpl_problem_path(ctypes.byref(pr), ctypes.byref(path)) == -1
+    # the same checks guard the evaluation and the standalone problem calls
+    # (the key mismatch is found before anything is enqueued)
+    pr.xindex_bytes = ib.value
+    h = ctypes.c_void_p(1 << 20)
+    assert lib.fftpl_problem_wl_grad(ctypes.byref(pr), h, h, 1.0, 0, h, h, None, None,
+                                     None) == -5
+    assert lib.fftpl_debug_net_values(ctypes.byref(pr), h, h, 1.0, h, h, None) == -5
+    assert lib.fftpl_problem_wl_grad(ctypes.byref(pr), h, h, 0.0, 0, h, h, None, None,
+                                     None) == -1
+    assert lib.fftpl_problem_density(ctypes.byref(_problem(L)), h, h, h, None) == -1
+    assert lib.fftpl_problem_density(ctypes.byref(_problem(L, n=2048)), h, h, h, None) == -4
+    assert lib.fftpl_problem_path(None, ctypes.byref(path)) == -1

@@ -286,3 +286,42 @@ def test_lse_bounds_translation_invariance_and_limit():
     Wa, _, _ = oracle.wa_wirelength(inst, gamma=1e-4)
     Ws, _, _ = oracle.lse_wirelength(inst, gamma=1e-4)
     assert Wa <= hp <= Ws and Ws - hp < 1e-2
+
+
+@pytest.mark.parametrize("model", ["wa", "lse"])
+def test_net_values_by_brute_force_per_net(model):
+    # per-net values against each net's definition written out pin by pin
+    # (unshifted exponentials at a moderate gamma; max - min by pairwise
+    # distances), including empty and one-pin nets
+    base = tiny_instance(seed=8, m=40, n=8, num_nets=30)
+    rng = np.random.default_rng(8)
+    nets = [[], [(3, 0.1, -0.2)]]
+    for d in (2, 3, 5, 9, 17):
+        nets.append([(int(c), float(rng.random() - 0.5), float(rng.random() - 0.5))
+                     for c in rng.choice(40, d, replace=False)])
+    nets.append([])
+    cells = np.stack([base.x, base.y, base.w, base.h], axis=1)
+    inst = hand_instance(cells, n=8, bin_size=base.bin_w, nets=nets)
+    g = 2.5
+    wl, hp = oracle.net_values(inst, gamma=g, model=model)
+    assert wl.shape == hp.shape == (inst.num_nets,)
+    for e in range(inst.num_nets):
+        a, b = inst.net_ptr[e], inst.net_ptr[e + 1]
+        if b - a == 0:
+            assert wl[e] == 0.0 and hp[e] == 0.0
+            continue
+        w_ref = h_ref = 0.0
+        for pos, off in ((inst.x, inst.pin_dx), (inst.y, inst.pin_dy)):
+            s = [float(pos[inst.pin_cell[p]]) + float(off[p]) for p in range(a, b)]
+            h_ref += max(abs(u - v) for u in s for v in s)
+            ep = [math.exp(v / g) for v in s]
+            em = [math.exp(-v / g) for v in s]
+            if model == "lse":
+                w_ref += g * math.log(sum(ep)) + g * math.log(sum(em))
+            else:
+                w_ref += (sum(v * q for v, q in zip(s, ep)) / sum(ep)
+                          - sum(v * q for v, q in zip(s, em)) / sum(em))
+        assert wl[e] == pytest.approx(w_ref, rel=1e-11, abs=1e-12)
+        assert hp[e] == pytest.approx(h_ref, rel=1e-12, abs=1e-12)
+    # a one-pin net: zero spread; its LSE value is 2 gamma ln 1 = 0 too
+    assert hp[1] == 0.0 and abs(wl[1]) < 1e-12
