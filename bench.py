@@ -91,30 +91,48 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=5000)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-pool", type=int, default=32)
-    ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-batch", type=int, default=8,
+                    help="most requests of one grid side evaluated in one group")
+    ap.add_argument("--serve-variants", type=int, default=4,
+                    help="placements per design (request r uses placement r mod this)")
+    ap.add_argument("--serve-saturate", type=int, default=2000,
+                    help="requests of the saturated run (arrivals far above the "
+                         "service rate), with and without grouping; 0 skips it")
     ap.add_argument("--driver-iters", type=int, default=1000)
     return ap.parse_args()
 
 
-def serving_run(args, dct, count):
-    """The serving workload: Poisson arrivals at --serve-rate of designs with
-    10^4..10^6 cells (log-uniform, a pool of --serve-pool designs), each
-    request uploaded, indexed, evaluated and downloaded; latency from arrival
-    to results in host memory."""
+def serving_run(args, dct, count, rate=None, max_batch=None):
+    """The serving workload: Poisson arrivals at `rate` (default --serve-rate)
+    of placements of designs with 10^4..10^6 cells (log-uniform, a pool of
+    --serve-pool designs made resident before the stream starts, --serve-variants
+    placements each); requests of one grid side waiting together are
+    evaluated in groups of up to `max_batch` (one launch per stage); latency
+    from arrival to results in host memory."""
+    import numpy as np
+
     import gen
     from paper_1312_4587_amd import serving
+    rate = args.serve_rate if rate is None else rate
+    mb = args.serve_batch if max_batch is None else max_batch
     pool = gen.serving_pool(args.serve_pool, seed=5)
-    arrivals, designs = gen.serving_stream(count, rate_hz=args.serve_rate,
-                                           pool_size=len(pool), seed=5)
-    ex = serving.DeviceExecutor(pool, slots=args.serve_slots, dct=dct)
-    ex.warm()
-    srv = serving.Server(ex, ex.footprint, slots=args.serve_slots, capacity_bytes=200e9)
-    st = srv.run(arrivals, designs)
+    arrivals, designs = gen.serving_stream(count, rate_hz=rate, pool_size=len(pool), seed=5)
+    variants = np.arange(count) % args.serve_variants
+    ex = serving.DeviceExecutor(pool, slots=args.serve_slots, dct=dct, max_batch=mb,
+                                variants=args.serve_variants)
+    t0 = time.perf_counter()
+    ex.warm(load_designs=True)
+    load_s = time.perf_counter() - t0
+    srv = serving.Server(ex, ex.footprint, slots=args.serve_slots, capacity_bytes=200e9,
+                         grid=ex.grid, max_batch=mb)
+    st = srv.run(arrivals, designs, variants)
     ex.close()
     cells = [p.num_cells for p in pool]
-    st.update(dct=dct, rate_hz=args.serve_rate, slots=args.serve_slots,
+    st.update(dct=dct, rate_hz=rate, slots=args.serve_slots, max_batch=mb,
               pool=len(pool), pool_cells_min=int(min(cells)), pool_cells_max=int(max(cells)),
-              capacity_bytes=200e9)
+              capacity_bytes=200e9, designs_loaded=ex.loads,
+              design_load_s=load_s, design_load_ms_mean=1e3 * ex.load_s / max(1, ex.loads))
     return st
 
 
@@ -556,6 +574,13 @@ def main():
         res["serving"] = {"fft": sv,
                           "gemm_bf16x3": serving_run(args, "gemm_bf16x3",
                                                      max(1, args.serve_requests // 5))}
+        if args.serve_saturate > 0:
+            # arrivals far above the service rate: throughput with grouping by
+            # grid side against one request per launch
+            res["serving"]["saturated"] = {
+                f"max_batch_{mb}": serving_run(args, "fft", args.serve_saturate,
+                                               rate=50_000.0, max_batch=mb)
+                for mb in (1, args.serve_batch)}
         res["served_p50_ms"] = sv["p50_ms"]
         res["served_p99_ms"] = sv["p99_ms"]
     print(json.dumps(res), flush=True)

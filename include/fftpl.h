@@ -459,6 +459,32 @@ int fftpl_nesterov_update(const fftpl_grid* region, int32_t num_cells, const flo
                           float* upy, float* gpx, float* gpy, const float* gx, const float* gy,
                           float step, float beta, void* stream);
 
+/* Nonlinear conjugate gradients, the inner solver of Algorithm 1 (the
+ * "CGsolver" step: one direction and one line search inside the step
+ * interval [alpha_min, alpha_max] of Section IV-A per outer iteration).  The
+ * direction update and the line search are chosen on the host from these
+ * device reductions (all double, over both axes of num_cells cells,
+ * per-block partials summed in a fixed order):
+ *   fftpl_cg_dots:      out4 = [g.g, g.gp, gp.gp, g.d] (gp, gpx/gpy the previous
+ *                       gradient, d the previous direction; either pair may be
+ *                       NULL: its terms are 0);
+ *   fftpl_cg_direction: d = -g + beta d (beta >= 0; beta = 0 restarts with
+ *                       d = -g and does not read d), *dmax = max |d| over the
+ *                       components (a device double);
+ *   fftpl_cg_move:      xo = clamp(x + t d) per axis, with clamp keeping each
+ *                       cell (sizes w, h) inside the region of `region` (as
+ *                       fftpl_nesterov_update); xo, yo may alias x, y.
+ * work: device double scratch of at least 1024 entries (work_doubles). */
+int fftpl_cg_dots(int32_t num_cells, const float* gx, const float* gy, const float* gpx,
+                  const float* gpy, const float* dx, const float* dy, double* out4,
+                  double* work, uint64_t work_doubles, void* stream);
+int fftpl_cg_direction(int32_t num_cells, const float* gx, const float* gy, float beta,
+                       float* dx, float* dy, double* dmax, double* work, uint64_t work_doubles,
+                       void* stream);
+int fftpl_cg_move(const fftpl_grid* region, int32_t num_cells, const float* w, const float* h,
+                  const float* x, const float* y, const float* dx, const float* dy, float t,
+                  float* xo, float* yo, void* stream);
+
 /* Test export: the integer bin range of every cell under the rectangle rule
  * above, ranges[4*i + {0,1,2,3}] = {ix0, ix1, iy0, iy1} (empty when first >
  * last).  ranges is a device int32 array [4*num_cells]. */

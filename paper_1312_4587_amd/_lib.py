@@ -98,6 +98,12 @@ SIGNATURES = {
                                       c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                       c_void_p, c_void_p, c_void_p, c_float, c_float,
                                       c_void_p]),
+    "fftpl_cg_dots": (c_int, [c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                              c_void_p, c_void_p, c_void_p, ctypes.c_uint64, c_void_p]),
+    "fftpl_cg_direction": (c_int, [c_int, c_void_p, c_void_p, c_float, c_void_p, c_void_p,
+                                   c_void_p, c_void_p, ctypes.c_uint64, c_void_p]),
+    "fftpl_cg_move": (c_int, [_G, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                              c_void_p, c_float, c_void_p, c_void_p, c_void_p]),
     "fftpl_plan_timing": (c_int, [c_void_p, c_int]),
     "fftpl_plan_kernel_times": (c_int, [c_void_p, c_int, ctypes.POINTER(c_float),
                                         ctypes.POINTER(c_char_p), ctypes.POINTER(c_int)]),

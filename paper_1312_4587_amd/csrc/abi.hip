@@ -1048,6 +1048,42 @@ int fftpl_nesterov_update(const fftpl_grid* region, int32_t num_cells, const flo
                                            as_stream(stream)));
 }
 
+int fftpl_cg_dots(int32_t num_cells, const float* gx, const float* gy, const float* gpx,
+                  const float* gpy, const float* dx, const float* dy, double* out4,
+                  double* work, uint64_t work_doubles, void* stream) {
+  if (num_cells < 0 || !out4 || !work || work_doubles < step_stats_work_doubles())
+    return FFTPL_E_INVAL;
+  if (num_cells > 0 && (!gx || !gy)) return FFTPL_E_INVAL;
+  if ((gpx == nullptr) != (gpy == nullptr) || (dx == nullptr) != (dy == nullptr))
+    return FFTPL_E_INVAL;
+  return dev_status(
+      launch_cg_dots(num_cells, gx, gy, gpx, gpy, dx, dy, out4, work, as_stream(stream)));
+}
+
+int fftpl_cg_direction(int32_t num_cells, const float* gx, const float* gy, float beta,
+                       float* dx, float* dy, double* dmax, double* work, uint64_t work_doubles,
+                       void* stream) {
+  if (num_cells < 0 || !dmax || !work || work_doubles < step_stats_work_doubles())
+    return FFTPL_E_INVAL;
+  if (!isfinite(beta) || beta < 0.0f) return FFTPL_E_INVAL;
+  if (num_cells > 0 && (!gx || !gy || !dx || !dy)) return FFTPL_E_INVAL;
+  return dev_status(
+      launch_cg_direction(num_cells, gx, gy, beta, dx, dy, dmax, work, as_stream(stream)));
+}
+
+int fftpl_cg_move(const fftpl_grid* region, int32_t num_cells, const float* w, const float* h,
+                  const float* x, const float* y, const float* dx, const float* dy, float t,
+                  float* xo, float* yo, void* stream) {
+  if (!grid_ok(region) || num_cells < 0 || !isfinite(t)) return FFTPL_E_INVAL;
+  if (num_cells > 0 && (!w || !h || !x || !y || !dx || !dy || !xo || !yo))
+    return FFTPL_E_INVAL;
+  const float xl = (float)region->xl, yl = (float)region->yl;
+  const float xh = (float)(region->xl + region->n * region->bin_w);
+  const float yh = (float)(region->yl + region->n * region->bin_h);
+  return dev_status(launch_cg_move(num_cells, x, y, dx, dy, t, w, h, xl, yl, xh, yh, xo, yo,
+                                   as_stream(stream)));
+}
+
 int fftpl_debug_cell_bins(const fftpl_grid* grid, int32_t num_cells, const float* x,
                           const float* y, const float* w, const float* h,
                           int32_t* ranges, void* stream) {

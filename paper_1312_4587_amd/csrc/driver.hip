@@ -1,6 +1,7 @@
 // Device side of the global placement iteration (Algorithm 1, the update of
 // the positions after each gradient evaluation): the reductions that pick the
-// step length and the Nesterov update of the cell centres.
+// step length, the Nesterov update of the cell centres, and the vector steps
+// of nonlinear conjugate gradients (dots, direction, move along it).
 //
 // Step statistics, in double, from per-block partials summed in a fixed order:
 //   out[0] = sum |u - u_prev|^2    (both axes)
@@ -99,9 +100,120 @@ __global__ void __launch_bounds__(256)
   uy[i] = vy;
 }
 
+// Nonlinear conjugate gradients (the inner solver of Algorithm 1).
+// Dots over both axes, per-block partials: [g.g, g.gp, gp.gp, g.d] (the
+// previous gradient gp and the previous direction d may be null: zeros).
+__global__ void __launch_bounds__(kStatThreads)
+    k_cg_dots(int m, const float* __restrict__ gx, const float* __restrict__ gy,
+              const float* __restrict__ gpx, const float* __restrict__ gpy,
+              const float* __restrict__ dx, const float* __restrict__ dy,
+              double* __restrict__ part) {
+  double gg = 0.0, gq = 0.0, qq = 0.0, gd = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
+    const double a = gx[i], b = gy[i];
+    gg += a * a + b * b;
+    if (gpx) {
+      const double p = gpx[i], q = gpy[i];
+      gq += a * p + b * q;
+      qq += p * p + q * q;
+    }
+    if (dx) gd += a * (double)dx[i] + b * (double)dy[i];
+  }
+  block_sum_to<false>(gg, &part[blockIdx.x]);
+  block_sum_to<false>(gq, &part[gridDim.x + blockIdx.x]);
+  block_sum_to<false>(qq, &part[2 * gridDim.x + blockIdx.x]);
+  block_sum_to<false>(gd, &part[3 * gridDim.x + blockIdx.x]);
+}
+
+// d = -g + beta d (beta = 0: d = -g, d read only otherwise); per-block max |d|.
+__global__ void __launch_bounds__(kStatThreads)
+    k_cg_direction(int m, const float* __restrict__ gx, const float* __restrict__ gy,
+                   float beta, float* __restrict__ dx, float* __restrict__ dy,
+                   double* __restrict__ part) {
+  float dm = 0.0f;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
+    const float a = beta != 0.0f ? beta * dx[i] - gx[i] : -gx[i];
+    const float b = beta != 0.0f ? beta * dy[i] - gy[i] : -gy[i];
+    dx[i] = a;
+    dy[i] = b;
+    dm = fmaxf(dm, fmaxf(fabsf(a), fabsf(b)));
+  }
+  __shared__ float wm[kStatThreads / kWave];
+  dm = wave_max(dm);
+  if ((threadIdx.x & (kWave - 1)) == 0) wm[threadIdx.x / kWave] = dm;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float v = 0.0f;
+    for (int k = 0; k < kStatThreads / kWave; ++k) v = fmaxf(v, wm[k]);
+    part[blockIdx.x] = v;
+  }
+}
+
+// Fixed-order totals of `count` partial rows of nblk entries each; rows in
+// max_mask take the maximum instead of the sum.
+__global__ void __launch_bounds__(64)
+    k_rows_final(const double* __restrict__ part, int nblk, int count, int max_mask,
+                 double* __restrict__ out) {
+  const int j = threadIdx.x;
+  if (j < count) {
+    const bool mx = (max_mask >> j) & 1;
+    double v = 0.0;
+    for (int b = 0; b < nblk; ++b) {
+      const double p = part[j * nblk + b];
+      v = mx ? fmax(v, p) : v + p;
+    }
+    out[j] = v;
+  }
+}
+
+// xo = clamp(x + t d), per cell and axis (xo may alias x).
+__global__ void __launch_bounds__(256)
+    k_cg_move(int m, const float* x, const float* y, const float* __restrict__ dx,
+              const float* __restrict__ dy, float t,
+              const float* __restrict__ w, const float* __restrict__ h, float xl, float yl,
+              float xh, float yh, float* xo, float* yo) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const float hw = 0.5f * w[i], hh = 0.5f * h[i];
+  const float nx = clampc(x[i] + t * dx[i], xl + hw, xh - hw);
+  const float ny = clampc(y[i] + t * dy[i], yl + hh, yh - hh);
+  xo[i] = nx;
+  yo[i] = ny;
+}
+
 }  // namespace
 
 size_t step_stats_work_doubles() { return 4 * (size_t)kStatBlocks; }
+
+hipError_t launch_cg_dots(int m, const float* gx, const float* gy, const float* gpx,
+                          const float* gpy, const float* dx, const float* dy, double* out,
+                          double* work, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_dots, dim3(kStatBlocks), dim3(kStatThreads), 0, s, m, gx, gy, gpx,
+                     gpy, dx, dy, work);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_rows_final, dim3(1), dim3(64), 0, s, work, kStatBlocks, 4, 0, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_direction(int m, const float* gx, const float* gy, float beta, float* dx,
+                               float* dy, double* dmax, double* work, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_direction, dim3(kStatBlocks), dim3(kStatThreads), 0, s, m, gx, gy,
+                     beta, dx, dy, work);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_rows_final, dim3(1), dim3(64), 0, s, work, kStatBlocks, 1, 1, dmax);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_move(int m, const float* x, const float* y, const float* dx,
+                          const float* dy, float t, const float* w, const float* h, float xl,
+                          float yl, float xh, float yh, float* xo, float* yo, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cg_move, dim3((m + 255) / 256), dim3(256), 0, s, m, x, y, dx, dy, t, w,
+                     h, xl, yl, xh, yh, xo, yo);
+  return hipGetLastError();
+}
 
 hipError_t launch_step_stats(int m, const float* ux, const float* uy, const float* upx,
                              const float* upy, const float* gx, const float* gy,

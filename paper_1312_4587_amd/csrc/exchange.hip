@@ -664,7 +664,14 @@ __global__ void __launch_bounds__(NW) k_xch_wa(XchBatch<NB> xb) {
       deg = min(deg, np - l0);
       // the chunk's largest small degree, uniform across the wavefront
       const int wdeg = wave_max_dpp_i(deg);
-      if (deg == 1) pos[l0] = make_float2(0.0f, 0.0f);
+      if (deg == 1) {
+        // a one-pin net: no gradient, zero wirelength and half-perimeter
+        pos[l0] = make_float2(0.0f, 0.0f);
+        if (net_wl) {
+          net_wl[p0 + l0] = 0.0;
+          net_hp[p0 + l0] = 0.0;
+        }
+      }
       if (wdeg >= 2) {
         float px[kSmall], py[kSmall];
         const float2 r = pos[deg >= 1 ? l0 : 0];

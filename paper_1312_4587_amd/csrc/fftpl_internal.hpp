@@ -765,6 +765,14 @@ hipError_t launch_step_stats(int m, const float* ux, const float* uy, const floa
                              const float* upy, const float* gx, const float* gy,
                              const float* gpx, const float* gpy, double* out, double* work,
                              hipStream_t s);
+hipError_t launch_cg_dots(int m, const float* gx, const float* gy, const float* gpx,
+                          const float* gpy, const float* dx, const float* dy, double* out,
+                          double* work, hipStream_t s);
+hipError_t launch_cg_direction(int m, const float* gx, const float* gy, float beta, float* dx,
+                               float* dy, double* dmax, double* work, hipStream_t s);
+hipError_t launch_cg_move(int m, const float* x, const float* y, const float* dx,
+                          const float* dy, float t, const float* w, const float* h, float xl,
+                          float yl, float xh, float yh, float* xo, float* yo, hipStream_t s);
 hipError_t launch_nesterov_update(int m, float* x, float* y, float* ux, float* uy, float* upx,
                                   float* upy, float* gpx, float* gpy, const float* gx,
                                   const float* gy, const float* w, const float* h, float step,

@@ -20,8 +20,16 @@ Schedules (Section IV-A):
   then changes the landscape, and momentum built on the old one makes the
   late, density-dominated iterations wander (overflow and wirelength grow
   again after a few hundred iterations without the restart).
-The paper's inner solver is nonlinear CG; this loop uses Nesterov's method
-(the same gradient, no line search), so one evaluation per iteration.
+Two inner solvers (``Schedule.solver``):
+* "cg", the paper's (Algorithm 1, "CGsolver"): nonlinear conjugate gradients,
+  Polak-Ribiere with restarts (beta = max(0, g.(g - g_prev) / |g_prev|^2);
+  d = -g when that is not a descent direction), and per outer iteration one
+  backtracking line search inside the step interval [alpha_min, alpha_max],
+  expressed as the largest cell displacement: it starts at alpha_max, halves
+  until f = W~ + lambda N has fallen by the Armijo amount, and stops at
+  alpha_min.  Each trial costs a scalars-only evaluation.
+* "nesterov": Nesterov's method with a Barzilai-Borwein step in the same
+  interval (no line search: one evaluation per iteration).
 
 Fillers (Section III-B): with ``fillers=True`` disconnected movable cells
 are appended after the real ones so that movable plus filler area equals the
@@ -70,6 +78,32 @@ def step_length(du2: float, dg2: float, gmax: float, alpha_min: float, alpha_max
     return min(alpha_max, max(alpha_min, math.sqrt(du2 / dg2) * gmax))
 
 
+def pr_beta(gg: float, ggp: float, gpgp: float) -> float:
+    """Polak-Ribiere with restart: max(0, g.(g - g_prev) / |g_prev|^2)."""
+    if gpgp <= 0.0:
+        return 0.0
+    return max(0.0, (gg - ggp) / gpgp)
+
+
+def backtrack(phi: Callable[[float], float], f0: float, slope: float, alpha_max: float,
+              alpha_min: float, dmax: float, c1: float = 1e-4, shrink: float = 0.5):
+    """Backtracking line search inside [alpha_min, alpha_max] (step lengths as
+    the largest cell displacement; the move along the direction is t =
+    alpha / dmax).  phi(alpha) evaluates the objective after that move.
+    Starts at alpha_max and shrinks by `shrink` until the Armijo condition
+    f <= f0 + c1 t slope holds (slope = g.d < 0); at alpha_min the step is
+    taken as it is.  Returns (alpha, f(alpha), trials)."""
+    alpha = alpha_max
+    trials = 0
+    while True:
+        f = phi(alpha)
+        trials += 1
+        t = alpha / dmax if dmax > 0 else 0.0
+        if f <= f0 + c1 * t * slope or alpha <= alpha_min:
+            return alpha, f, trials
+        alpha = max(alpha_min, alpha * shrink)
+
+
 def filler_cells(inst, cap_area: float, seed: int = 0):
     """Fillers of Section III-B: total filler area = cap_area - the movable
     cells' area, with cap_area the movable capacity of the region (bin area
@@ -107,6 +141,16 @@ class Schedule:
     restart_on_lambda: bool = True   # restart the momentum when lambda changes
     wl_model: str = "wa"             # "wa" (Eq. (3)) or "lse"
     screening: float = 0.0           # eps of the screened solve (0: Poisson)
+    solver: str = "nesterov"         # "nesterov" or "cg" (the paper's)
+
+
+def paper_schedule(**kw) -> Schedule:
+    """Algorithm 1 as printed: nonlinear CG, lambda_k = mu_k lambda_(k-1),
+    stop when tau <= 10%."""
+    kw.setdefault("solver", "cg")
+    kw.setdefault("lam_mode", "paper")
+    kw.setdefault("stop_tau", 0.1)
+    return Schedule(**kw)
 
 
 class Placer:
@@ -188,6 +232,32 @@ class Placer:
             self.work.numel(), fftpl._stream(None))
         fftpl._check(st, "fftpl_step_stats")
 
+    def _cg_dots(self, first: bool):
+        p = fftpl._ptr
+        st = _lib.load().fftpl_cg_dots(
+            self.inst.num_cells, p(self.gx), p(self.gy), None if first else p(self.gpx),
+            None if first else p(self.gpy), None if first else p(self.upx),
+            None if first else p(self.upy), p(self.scal) + 32, p(self.work),
+            self.work.numel(), fftpl._stream(None))
+        fftpl._check(st, "fftpl_cg_dots")
+
+    def _cg_direction(self, beta: float):
+        # the direction d lives in (upx, upy); max |d| into scal[7]
+        p = fftpl._ptr
+        st = _lib.load().fftpl_cg_direction(
+            self.inst.num_cells, p(self.gx), p(self.gy), float(beta), p(self.upx),
+            p(self.upy), p(self.scal) + 56, p(self.work), self.work.numel(),
+            fftpl._stream(None))
+        fftpl._check(st, "fftpl_cg_direction")
+
+    def _cg_move(self, t: float, xo, yo):
+        p = fftpl._ptr
+        a = self.prob.arrays
+        st = _lib.load().fftpl_cg_move(
+            ctypes.byref(self.region.c()), self.inst.num_cells, p(a["w"]), p(a["h"]), p(self.x),
+            p(self.y), p(self.upx), p(self.upy), float(t), p(xo), p(yo), fftpl._stream(None))
+        fftpl._check(st, "fftpl_cg_move")
+
     def _update(self, step: float, beta: float):
         lib = _lib.load()
         p = fftpl._ptr
@@ -210,9 +280,72 @@ class Placer:
         return gw / gn if gn > 0 else 1.0
 
     # -- the loop ----------------------------------------------------------
+    def _cg_step(self, on_eval) -> Dict[str, float]:
+        """One outer iteration of Algorithm 1 with the CG inner solver.  The
+        gradient is taken at x (u = x); the direction is kept in (upx, upy)
+        and the previous gradient in (gpx, gpy); trial points go to (ux, uy)."""
+        first = self.k == 0
+        self.ux.copy_(self.x)
+        self.uy.copy_(self.y)
+        self._eval(self.lam, self.gamma)
+        self._cg_dots(first)
+        s = self.scal.cpu().numpy()
+        N, W, H, tau = (float(v) for v in s[:4])
+        gg, ggp, gpgp, gd = (float(v) for v in s[4:8])
+        if self.prob_real is not None:
+            tau = float(s[11])
+        if on_eval is not None:
+            on_eval(self)
+        f0 = W + self.lam * N
+        beta = 0.0 if first else pr_beta(gg, ggp, gpgp)
+        slope = -gg + beta * gd
+        if beta > 0.0 and slope >= 0.0:      # not a descent direction: restart
+            beta, slope = 0.0, -gg
+        self._cg_direction(beta)
+        dmax = float(self.scal[7].item())
+        restarted = beta == 0.0
+
+        def phi(alpha):
+            t = alpha / dmax if dmax > 0 else 0.0
+            self._cg_move(t, self.ux, self.uy)
+            fftpl.eval(self.plan, self.prob, self.ux, self.uy, self.lam, self.gamma,
+                       self.sched.grad_mode, None, None, self.scal[:4])
+            o = self.scal[:2].cpu().numpy()
+            return float(o[1]) + self.lam * float(o[0])
+
+        alpha, f1, trials = backtrack(phi, f0, slope, self.alpha_max, self.alpha_min, dmax)
+        # accept the last trial point: x = u; the gradient becomes the previous one
+        self.x.copy_(self.ux)
+        self.y.copy_(self.uy)
+        self.gpx.copy_(self.gx)
+        self.gpy.copy_(self.gy)
+        rec = dict(k=self.k, energy=N, wa=W, hpwl=H, tau=tau, lam=self.lam, gamma=self.gamma,
+                   alpha=alpha, f=f0, f_next=f1, trials=trials, beta=beta,
+                   restart=float(restarted))
+        self.history.append(rec)
+        self.alpha_max = max(self.alpha_max0, 2.0 * alpha)
+        self.alpha_min = 0.01 * self.alpha_max
+        self.gamma = gamma_of_tau(tau, float(self.inst.bin_w))
+        self._next_lambda(H)
+        self.k += 1
+        return rec
+
+    def _next_lambda(self, H: float) -> None:
+        if self.sched.lam_mode == "double":
+            if (self.k + 1) % self.sched.lam_every == 0:
+                self.lam *= 2.0
+                if self.sched.restart_on_lambda:
+                    self.a = 1.0
+        else:
+            if self.last_hpwl is not None:
+                self.lam *= mu_of_hpwl_change(H - self.last_hpwl)
+        self.last_hpwl = H
+
     def step(self, on_eval: Optional[Callable[["Placer"], None]] = None) -> Dict[str, float]:
         if self.lam is None:
             self.lam = self.initial_lambda()
+        if self.sched.solver == "cg":
+            return self._cg_step(on_eval)
         first = self.k == 0
         self._eval(self.lam, self.gamma)
         self._stats(first)
@@ -233,15 +366,7 @@ class Placer:
         self.alpha_max = max(self.alpha_max0, 2.0 * alpha)
         self.alpha_min = 0.01 * self.alpha_max
         self.gamma = gamma_of_tau(tau, float(self.inst.bin_w))
-        if self.sched.lam_mode == "double":
-            if (self.k + 1) % self.sched.lam_every == 0:
-                self.lam *= 2.0
-                if self.sched.restart_on_lambda:
-                    self.a = 1.0
-        else:
-            if self.last_hpwl is not None:
-                self.lam *= mu_of_hpwl_change(H - self.last_hpwl)
-        self.last_hpwl = H
+        self._next_lambda(H)
         self.k += 1
         return rec
 

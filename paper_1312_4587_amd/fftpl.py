@@ -336,7 +336,7 @@ class Problem:
 
     def __init__(self, grid: Grid, w, h, net_ptr, pin_cell, pin_dx, pin_dy,
                  base=None, cap=None, path="xch", stream=None, max_degree=None,
-                 wl_model="wa", screening=0.0):
+                 wl_model="wa", screening=0.0, own_work=True):
         if path not in PATHS:
             raise ValueError(f"path must be one of {PATHS}")
         if path != "atomic" and grid.n > 1024:
@@ -353,9 +353,12 @@ class Problem:
         if max_degree is None:
             max_degree = int((net_ptr[1:] - net_ptr[:-1]).max().item()) if E > 0 else 0
         self.max_degree = int(max_degree)
+        self.work_bytes_needed = 0
         if path != "atomic":
-            work_bytes = problem_work_bytes(grid.n, m, E, P)
-            work = torch.empty(max(work_bytes, 1), dtype=torch.uint8, device="cuda")
+            self.work_bytes_needed = problem_work_bytes(grid.n, m, E, P)
+            if own_work:
+                work_bytes = self.work_bytes_needed
+                work = torch.empty(max(work_bytes, 1), dtype=torch.uint8, device="cuda")
         if path == "slots":
             cell_ptr = torch.empty(m + 1, dtype=torch.int32, device="cuda")
             pin_slot = torch.empty(max(P, 1), dtype=torch.int32, device="cuda")
@@ -381,6 +384,24 @@ class Problem:
             _ptr(work, torch.uint8, None, "work"), work_bytes,
             _ptr(xindex, torch.uint8, None, "xindex"), xbytes, self.max_degree,
             float(screening), xkey)
+
+    def with_work(self, work) -> "Problem":
+        """The same problem with the caller's workspace `work` (a uint8 device
+        tensor of at least work_bytes_needed bytes) in place of its own; the
+        static arrays and the index are shared, so views with distinct
+        workspaces can be evaluated at the same time."""
+        import copy
+        if self.path == "atomic":
+            raise ValueError("the float-atomic path has no workspace")
+        if work.numel() < self.work_bytes_needed:
+            raise ValueError(f"work needs {self.work_bytes_needed} bytes")
+        v = copy.copy(self)
+        v.c = _lib.fftpl_problem()
+        ctypes.pointer(v.c)[0] = self.c
+        v.c.work = _ptr(work, torch.uint8, None, "work")
+        v.c.work_bytes = int(work.numel())
+        v.arrays = dict(self.arrays, work=work)
+        return v
 
     def set_objective(self, wl_model=None, screening=None) -> None:
         if wl_model is not None:

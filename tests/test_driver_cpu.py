@@ -61,3 +61,41 @@ def test_filler_cells_fill_the_capacity():
     # already full: no fillers; same seed: same fillers
     assert len(driver.filler_cells(inst, 0.5 * mov, seed=1)[0]) == 0
     assert np.array_equal(driver.filler_cells(inst, cap_area, seed=1)[0], x)
+
+
+def test_polak_ribiere_beta_restarts():
+    from paper_1312_4587_amd.driver import pr_beta
+    assert pr_beta(4.0, 1.0, 2.0) == pytest.approx(1.5)
+    assert pr_beta(1.0, 3.0, 2.0) == 0.0          # negative: restart
+    assert pr_beta(1.0, 0.0, 0.0) == 0.0          # no previous gradient
+
+
+def test_backtracking_line_search_stays_in_the_interval():
+    from paper_1312_4587_amd.driver import backtrack
+    # f(x) = (x - 3)^2 from x = 0 along d = +1 (slope -6), dmax = 1
+    f = lambda a: (a - 3.0) ** 2          # noqa: E731
+    calls = []
+
+    def phi(a):
+        calls.append(a)
+        return f(a)
+    a, fa, n = backtrack(phi, 9.0, -6.0, 16.0, 0.16, 1.0)
+    # 16 and 8 overshoot (f = 169, 25 > 9 - ...); 4 satisfies Armijo
+    assert calls == [16.0, 8.0, 4.0] and a == 4.0 and fa == 1.0 and n == 3
+    # the largest step when it already decreases enough
+    a, fa, n = backtrack(f, 9.0, -6.0, 2.0, 0.02, 1.0)
+    assert a == 2.0 and n == 1
+    # never below alpha_min: taken as it is when nothing decreases
+    a, fa, n = backtrack(lambda a: 100.0, 9.0, -6.0, 1.0, 0.1, 1.0)
+    assert a == 0.1 and n == 5
+    # the step is a displacement: with dmax = 2 the move is t = alpha / 2
+    seen = []
+    backtrack(lambda a: seen.append(a) or 0.0, 1.0, -1.0, 0.5, 0.005, 2.0)
+    assert seen == [0.5]
+
+
+def test_paper_schedule_is_algorithm_1():
+    from paper_1312_4587_amd.driver import paper_schedule
+    s = paper_schedule()
+    assert s.solver == "cg" and s.lam_mode == "paper" and s.stop_tau == 0.1
+    assert s.alpha_max0_bins == 0.044

@@ -240,3 +240,116 @@ def test_placement_with_objective_variants(F, wl, eps):
     assert all(np.isfinite(h["hpwl"]) for h in hist)
     assert hist[-1]["hpwl"] < hist[0]["hpwl"] and hist[-1]["tau"] < 0.5
     pl.close()
+
+
+def test_cg_kernels_against_numpy(F):
+    # the vector steps of the CG inner solver: dots, direction, clamped move
+    import torch
+    fftpl, driver, L = F
+    lib = L.load()
+    rng = np.random.default_rng(19)
+    m = 40_001
+    inst = gen.make_instance(19, num_cells=m, util=0.7, n=64, num_nets=10)
+    grid = fftpl.Grid.of(inst)
+    side = grid.n * grid.bin_w
+    v = {k: rng.normal(0, 3, m).astype(np.float32)
+         for k in ("gx", "gy", "gpx", "gpy", "dx", "dy")}
+    x = rng.uniform(0, side, m).astype(np.float32)
+    y = rng.uniform(0, side, m).astype(np.float32)
+    w = rng.integers(1, 5, m).astype(np.float32)
+    h = np.ones(m, np.float32)
+    d = {k: dev(a) for k, a in {**v, "x": x, "y": y, "w": w, "h": h}.items()}
+    out = torch.zeros(4, dtype=torch.float64, device="cuda")
+    work = torch.empty(1024, dtype=torch.float64, device="cuda")
+    p = fftpl._ptr
+    assert lib.fftpl_cg_dots(m, p(d["gx"]), p(d["gy"]), p(d["gpx"]), p(d["gpy"]), p(d["dx"]),
+                             p(d["dy"]), p(out), p(work), 1024, None) == 0
+    f = {k: a.astype(np.float64) for k, a in v.items()}
+    o = host(out)
+    assert o[0] == pytest.approx(np.sum(f["gx"] ** 2 + f["gy"] ** 2), rel=1e-12)
+    assert o[1] == pytest.approx(np.sum(f["gx"] * f["gpx"] + f["gy"] * f["gpy"]), rel=1e-12)
+    assert o[2] == pytest.approx(np.sum(f["gpx"] ** 2 + f["gpy"] ** 2), rel=1e-12)
+    assert o[3] == pytest.approx(np.sum(f["gx"] * f["dx"] + f["gy"] * f["dy"]), rel=1e-12)
+    assert lib.fftpl_cg_dots(m, p(d["gx"]), p(d["gy"]), None, None, None, None, p(out),
+                             p(work), 1024, None) == 0
+    o = host(out)
+    assert o[1] == 0.0 and o[2] == 0.0 and o[3] == 0.0
+    beta = 0.625
+    dmax = torch.zeros(1, dtype=torch.float64, device="cuda")
+    assert lib.fftpl_cg_direction(m, p(d["gx"]), p(d["gy"]), beta, p(d["dx"]), p(d["dy"]),
+                                  p(dmax), p(work), 1024, None) == 0
+    # (the device may fuse beta * d - g into one rounding)
+    rx = (beta * f["dx"] - f["gx"]).astype(np.float32)
+    ry = (beta * f["dy"] - f["gy"]).astype(np.float32)
+    gdx, gdy = host(d["dx"]), host(d["dy"])
+    assert np.max(np.abs(gdx - rx)) <= 1e-6 * np.abs(rx).max()
+    assert np.max(np.abs(gdy - ry)) <= 1e-6 * np.abs(ry).max()
+    assert float(host(dmax)[0]) == max(np.abs(gdx).max(), np.abs(gdy).max())
+    t = 0.75
+    assert lib.fftpl_cg_move(ctypes.byref(grid.c()), m, p(d["w"]), p(d["h"]), p(d["x"]),
+                             p(d["y"]), p(d["dx"]), p(d["dy"]), t, p(d["x"]), p(d["y"]),
+                             None) == 0
+    lo, hi = grid.xl + 0.5 * w, grid.xl + side - 0.5 * w
+    ex = np.minimum(np.maximum(x + np.float32(t) * gdx, lo), hi)
+    assert np.max(np.abs(host(d["x"]) - ex)) < 1e-4
+    assert lib.fftpl_cg_direction(m, p(d["gx"]), p(d["gy"]), -1.0, p(d["dx"]), p(d["dy"]),
+                                  p(dmax), p(work), 1024, None) == -1
+
+
+def test_cg_paper_schedule_mid_200k(F):
+    # Algorithm 1 as printed on the 200k-cell workload: nonlinear CG with the
+    # line search inside [alpha_min, alpha_max], lambda_k = mu_k lambda_(k-1)
+    # from the HPWL change, gamma(tau), stop once tau <= 10%.  The evaluation
+    # at sampled iterations matches the oracle on the same positions, and the
+    # energy N falls together with tau (the paper's Fig. 3(a))
+    import json
+    import os
+    import time
+    import torch
+    fftpl, driver, _ = F
+    inst = gen.make_config("mid_200k")
+    pl = driver.Placer(inst, schedule=driver.paper_schedule())
+    snaps = {}
+    pick = {0, 1, 10, 50, 100, 200}
+
+    def grab(p):
+        if p.k in pick:
+            snaps[p.k] = dict(x=host(p.ux), y=host(p.uy), gx=host(p.gx), gy=host(p.gy),
+                              s=host(p.scal)[:4].copy(), lam=p.lam, gamma=p.gamma)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = pl.run(1000, on_eval=grab)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    say("CG, paper schedule:", len(hist), "iterations in", dt, "s; tau", hist[0]["tau"], "->",
+        hist[-1]["tau"], "hpwl", hist[0]["hpwl"], "->", hist[-1]["hpwl"], "trials",
+        sum(h["trials"] for h in hist))
+    out = os.environ.get("FFTPL_TRACE_OUT")
+    if out:
+        with open(out, "w") as f:
+            for h in hist:
+                f.write(json.dumps({k: h[k] for k in ("k", "energy", "tau", "hpwl", "wa", "lam",
+                                                      "gamma", "alpha", "trials")}) + "\n")
+    assert hist[-1]["tau"] <= 0.1 and len(hist) < 1000       # stopped by the criterion
+    assert all(h["alpha"] >= 0 and np.isfinite(h["hpwl"]) for h in hist)
+    taus = np.array([h["tau"] for h in hist])
+    ens = np.array([h["energy"] for h in hist])
+    assert ens[-1] < ens[0] and taus[-1] < taus[0]
+    # N tracks tau: rank correlation over the run
+    rt = np.argsort(np.argsort(taus))
+    re = np.argsort(np.argsort(ens))
+    rho_s = np.corrcoef(rt, re)[0, 1]
+    say("rank correlation of N and tau", rho_s)
+    assert rho_s > 0.8
+    last = hist[-1]["k"]
+    for k, sn in sorted(snaps.items()):
+        ik = inst.with_positions(sn["x"], sn["y"])
+        ref = oracle.evaluate(ik, lam=sn["lam"], gamma=sn["gamma"], grad_mode="field")
+        N, W, H, tau = sn["s"]
+        e = rel_l2(np.concatenate([sn["gx"], sn["gy"]]), np.concatenate([ref["gx"], ref["gy"]]))
+        say("k", k, "of", last, "grad rel-L2", e, "tau", tau, ref["overflow"])
+        assert e < RTOL
+        assert abs(N - ref["energy"]) <= RTOL * abs(ref["energy"])
+        assert abs(W - ref["wa"]) <= RTOL * abs(ref["wa"])
+        assert abs(tau - ref["overflow"]) <= RTOL
+    pl.close()

@@ -1,34 +1,47 @@
 """Scheduling of the serving loop with a stand-in executor (no device):
-first-come-first-served admission, the device-memory cap, several requests
-in service at once, and the latency statistics."""
+first-come-first-served admission, the device-memory cap, several groups in
+service at once, grouping by grid side, per-request failure isolation and the
+latency statistics."""
 import threading
 import time
 
 import numpy as np
 
-from paper_1312_4587_amd.serving import Server, footprint_bytes
+from paper_1312_4587_amd.serving import Outcome, Server, footprint_bytes
 
 
 class FakeExecutor:
-    def __init__(self, seconds):
+    """Sleeps a per-design time per group; fails the request ids in `bad`
+    (per request) or raises for groups containing an id in `boom`."""
+
+    def __init__(self, seconds, bad=(), boom=()):
         self.seconds = seconds
+        self.bad = set(bad)
+        self.boom = set(boom)
         self.lock = threading.Lock()
         self.order = []
+        self.groups = []
 
-    def __call__(self, slot, rid, design):
+    def __call__(self, slot, reqs):
         with self.lock:
-            self.order.append(rid)
-        time.sleep(self.seconds[design])
-        return np.array([design, 0, 0, 0], float), None, None
+            self.order.extend(r.rid for r in reqs)
+            self.groups.append([r.rid for r in reqs])
+        time.sleep(max(self.seconds[r.design] for r in reqs))
+        if any(r.rid in self.boom for r in reqs):
+            raise RuntimeError("executor failure")
+        return [Outcome(False, error="bad request") if r.rid in self.bad else
+                Outcome(True, np.array([r.design, r.variant, 0, 0], float))
+                for r in reqs]
 
 
 def test_all_served_in_arrival_order_with_one_slot():
     ex = FakeExecutor([0.002] * 3)
     srv = Server(ex, lambda d: 100, slots=1, capacity_bytes=1e9)
-    st = srv.run(np.arange(20) * 0.001, np.arange(20) % 3)
-    assert st["requests"] == 20 and ex.order == list(range(20))
-    assert st["max_in_service"] == 1
-    assert all(srv.results[r].out4[0] == r % 3 for r in range(20))
+    st = srv.run(np.arange(20) * 0.001, np.arange(20) % 3, variants=np.arange(20) % 4)
+    assert st["requests"] == 20 and st["served"] == 20 and st["errors"] == 0
+    assert ex.order == list(range(20)) and st["max_in_service"] == 1
+    assert all(srv.results[r].out4[0] == r % 3 and srv.results[r].out4[1] == r % 4
+               for r in range(20))
     assert st["p50_ms"] <= st["p99_ms"] <= st["max_ms"]
 
 
@@ -62,6 +75,54 @@ def test_latency_counts_queueing():
     srv = Server(FakeExecutor([0.01]), lambda d: 1, slots=1)
     st = srv.run(np.zeros(10), np.zeros(10, int))
     assert st["max_ms"] >= 90.0 and st["p50_ms"] >= 40.0
+
+
+def test_groups_share_a_grid_side_and_respect_batch_and_memory():
+    # designs 0, 1 on grid 64, design 2 on grid 128: a burst is served in
+    # groups of one grid side, at most max_batch each, within the memory cap
+    grid = {0: 64, 1: 64, 2: 128}
+    ex = FakeExecutor([0.01, 0.01, 0.01])
+    srv = Server(ex, lambda d: 100, slots=1, capacity_bytes=350, grid=grid.get,
+                 max_batch=4)
+    designs = np.array([0, 2, 1, 0, 2, 1, 1, 0, 2, 2])
+    st = srv.run(np.zeros(10), designs)
+    assert st["served"] == 10 and sorted(ex.order) == list(range(10))
+    for g in ex.groups:
+        assert len({grid[designs[r]] for r in g}) == 1
+        assert len(g) <= 3                      # 350 bytes hold three requests
+    assert st["max_batch_seen"] == 3 and st["groups"] < 10
+    # the head of the queue is always served first (no starvation)
+    assert ex.groups[0][0] == 0 and ex.groups[1][0] == 1
+    # one request at a time without batching
+    ex = FakeExecutor([0.001] * 3)
+    st = Server(ex, lambda d: 1, slots=1, grid=grid.get).run(np.zeros(10), designs)
+    assert st["max_batch_seen"] == 1 and st["groups"] == 10
+
+
+def test_failed_requests_fail_alone_and_release_their_share():
+    # requests 3 and 7 fail inside the executor; the others are served, every
+    # slot share and admitted byte is released, the statistics cover the
+    # successes and list the failures
+    ex = FakeExecutor([0.003], bad=(3, 7))
+    srv = Server(ex, lambda d: 100, slots=2, capacity_bytes=1e9)
+    st = srv.run(np.arange(12) * 0.001, np.zeros(12, int))
+    assert st["requests"] == 12 and st["served"] == 10 and st["errors"] == 2
+    assert st["failed_ids"] == [3, 7]
+    assert not srv.results[3].ok and srv.results[3].error == "bad request"
+    assert all(srv.results[r].ok for r in range(12) if r not in (3, 7))
+    assert srv.admitted_bytes == 0 and srv.in_service == 0
+
+
+def test_executor_exception_fails_only_its_group():
+    # the executor raises for the group holding request 4: that group fails,
+    # later requests are served, nothing stays admitted
+    ex = FakeExecutor([0.002], boom=(4,))
+    srv = Server(ex, lambda d: 10, slots=1, capacity_bytes=1e9)
+    st = srv.run(np.arange(10) * 0.004, np.zeros(10, int))
+    assert st["errors"] >= 1 and 4 in st["failed_ids"]
+    assert srv.results[4].error.startswith("RuntimeError")
+    assert srv.results[9].ok and st["served"] == 10 - st["errors"]
+    assert srv.admitted_bytes == 0 and srv.in_service == 0
 
 
 def test_footprint_formula():
