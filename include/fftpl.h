@@ -257,6 +257,23 @@ int fftpl_density_map(const fftpl_grid* grid, int32_t num_cells, const float* x,
                       const float* y, const float* w, const float* h,
                       const float* base, float* rho, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * density map of fftpl_density_map with the same arguments, computed like
+ * fftpl_problem_density (banded counting sort, fixed-point LDS sums: rho is
+ * the same on every run) with the band lists in a static device array of
+ * FFTPL_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs on
+ * until the process ends.  The call allocates nothing.  At most
+ * FFTPL_NOALLOC_MAX_CELLS cells and n <= 1024 (FFTPL_E_UNSUPPORTED
+ * otherwise).  Every call on one GPU uses that GPU's one array: calls that
+ * overlap on a GPU (other streams, other threads) race and must be ordered
+ * by the caller. */
+#define FFTPL_NOALLOC_SCRATCH_BYTES (64 << 20)
+#define FFTPL_NOALLOC_MAX_CELLS 921600
+int fftpl_density_map_noalloc(const fftpl_grid* grid, int32_t num_cells, const float* x,
+                              const float* y, const float* w, const float* h,
+                              const float* base, float* rho, void* stream);
+
 /* The density map of a problem's cells at positions x, y [num_cells], the
  * same quantity as fftpl_density_map with grid, w, h and base from prob,
  * computed without float atomics in prob->work (banded counting sort of the

@@ -53,6 +53,8 @@ SIGNATURES = {
                                  c_int, c_void_p, ctypes.POINTER(c_int)]),
     "fftpl_density_map": (c_int, [_G, c_int, c_void_p, c_void_p, c_void_p, c_void_p,
                                   c_void_p, c_void_p, c_void_p]),
+    "fftpl_density_map_noalloc": (c_int, [_G, c_int, c_void_p, c_void_p, c_void_p, c_void_p,
+                                          c_void_p, c_void_p, c_void_p]),
     "fftpl_poisson_solve": (c_int, [c_void_p, _G, c_void_p, c_void_p, c_void_p,
                                     c_void_p, c_void_p, c_void_p]),
     "fftpl_helmholtz_solve": (c_int, [c_void_p, _G, c_float, c_void_p, c_void_p, c_void_p,

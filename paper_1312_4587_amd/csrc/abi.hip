@@ -328,6 +328,27 @@ int fftpl_density_map(const fftpl_grid* grid, int32_t num_cells, const float* x,
   return dev_status(e);
 }
 
+int fftpl_density_map_noalloc(const fftpl_grid* grid, int32_t num_cells, const float* x,
+                              const float* y, const float* w, const float* h,
+                              const float* base, float* rho, void* stream) {
+  if (!grid_ok(grid) || num_cells < 0 || !rho) return FFTPL_E_INVAL;
+  if (num_cells > 0 && (!x || !y || !w || !h)) return FFTPL_E_INVAL;
+  if (grid->n > kBandMaxN || num_cells > FFTPL_NOALLOC_MAX_CELLS) return FFTPL_E_UNSUPPORTED;
+  size_t need = 0;
+  band_layout_density(grid->n, num_cells, nullptr, &need);
+  if (need > kNoallocScratchBytes) return FFTPL_E_UNSUPPORTED;
+  if (validate_env() && num_cells > 0) {
+    const int v = validate_cells(num_cells, x, y, w, h);
+    if (v != FFTPL_OK) return v;
+  }
+  void* scr = nullptr;
+  hipError_t e = noalloc_scratch(&scr);
+  if (e != hipSuccess) return FFTPL_E_DEVICE;
+  const BandLayout L = band_layout_density(grid->n, num_cells, scr, nullptr);
+  return dev_status(launch_band_scatter(make_gridf(*grid), L, x, y, w, h, base, rho,
+                                        as_stream(stream)));
+}
+
 int fftpl_helmholtz_solve(fftpl_plan* plan, const fftpl_grid* grid, float eps,
                           const float* rho, float* psi, float* ex, float* ey,
                           double* energy, void* stream) {

@@ -20,6 +20,7 @@
 // Every thread issues the loads of its cells (or entries) before it uses any
 // of them, so each block keeps many misses in flight.
 #include <algorithm>
+#include <mutex>
 
 #include "fftpl_internal.hpp"
 
@@ -452,6 +453,65 @@ hipError_t launch_band_scatter_batch(const BandReq* reqs, int count, hipStream_t
   bb.count = count;
   for (int i = 0; i < count; ++i) bb.r[i] = reqs[i];
   return band_scatter_nb(bb, max_nblk, nb, any, s, tp);
+}
+
+// ---- the density map without allocation -----------------------------------
+// A file-scope device array holds the band lists for callers that cannot
+// allocate (see fftpl_density_map_noalloc).  Host code never passes the
+// array's name to a kernel: its device address, looked up once per device,
+// is what the launches get.
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevicesNoalloc] = {};
+}  // namespace
+
+// Band lists of the density scatter alone (no wirelength or gather arrays).
+BandLayout band_layout_density(int n, int m, void* work, size_t* bytes_out) {
+  BandLayout L;
+  L.n = n;
+  L.rows = (n + 255) / 256;
+  L.nb = (n + L.rows - 1) / L.rows;
+  L.m = m;
+  L.nblk = m > 0 ? (m + kCellsPerBlock - 1) / kCellsPerBlock : 1;
+  size_t off = 0;
+  const size_t o_en = off;
+  off = align256(off + sizeof(float4) * (size_t)L.nblk * kBandRegion);
+  const size_t o_big = off;
+  off = align256(off + sizeof(int32_t) * (size_t)L.nblk * kCellsPerBlock);
+  const size_t o_ep = off;
+  off = align256(off + sizeof(int32_t) * (size_t)m);
+  const size_t o_bo = off;
+  off = align256(off + sizeof(int32_t) * (size_t)L.nblk * (L.nb + 1));
+  const size_t o_bc = off;
+  off = align256(off + sizeof(int32_t) * (size_t)L.nblk * (L.nb + 1));
+  if (bytes_out) *bytes_out = off;
+  if (work) {
+    char* b = static_cast<char*>(work);
+    L.entries = reinterpret_cast<float4*>(b + o_en);
+    L.big = reinterpret_cast<int32_t*>(b + o_big);
+    L.epos = reinterpret_cast<int32_t*>(b + o_ep);
+    L.blk_off = reinterpret_cast<int32_t*>(b + o_bo);
+    L.blk_cnt = reinterpret_cast<int32_t*>(b + o_bc);
+  }
+  return L;
+}
+
+hipError_t noalloc_scratch(void** ptr) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevicesNoalloc) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *ptr = g_scratch_ptr[dev];
+  return hipSuccess;
 }
 
 hipError_t launch_band_scatter(const GridF& g, const BandLayout& L, const float* x,

@@ -593,6 +593,13 @@ struct BandBatch {
 };
 hipError_t launch_band_scatter_batch(const BandReq* reqs, int count, hipStream_t s,
                                      Plan* tp = nullptr);
+// The density scatter's band lists alone (for the allocation-free density
+// map), and the device address of the library's static scratch array on the
+// current device (looked up once per device).
+constexpr size_t kNoallocScratchBytes = (size_t)64 << 20;
+constexpr int kMaxDevicesNoalloc = 64;
+BandLayout band_layout_density(int n, int m, void* work, size_t* bytes_out);
+hipError_t noalloc_scratch(void** ptr);
 hipError_t launch_band_gather_batch(const BandReq* reqs, int count, int grad_mode,
                                     hipStream_t s);
 
