@@ -263,6 +263,27 @@ __global__ void k_xi_finish(int ncb, int nnb, int num_pins, const int32_t* __res
 
 }  // namespace
 
+int pack_net_blocks(const int32_t* ptr, int E, int P, int max_degree, int cap, int nnb,
+                    int32_t* first) {
+  if (E < 0 || nnb < 1 || cap < 1) return FFTPL_E_INVAL;
+  if (ptr[0] != 0 || ptr[E] != P) return FFTPL_E_INVAL;
+  for (int k = 0; k <= nnb; ++k) first[k] = E;
+  int k = 0;
+  int64_t cur = 0;
+  first[0] = 0;
+  for (int en = 0; en < E; ++en) {
+    const int64_t deg = (int64_t)ptr[(size_t)en + 1] - ptr[en];
+    if (deg < 0 || deg > max_degree) return FFTPL_E_INVAL;
+    if (cur + deg > cap) {
+      if (++k >= nnb) return FFTPL_E_INVAL;   // cannot happen for a valid CSR
+      first[k] = en;
+      cur = 0;
+    }
+    cur += deg;
+  }
+  return FFTPL_OK;
+}
+
 int xch_build(const XchDims& d, const int32_t* net_ptr, const int32_t* pin_cell, void* index,
               void* work, hipStream_t s) {
   const size_t seg = (size_t)d.ncb * d.nnb;
@@ -301,20 +322,8 @@ int xch_build(const XchDims& d, const int32_t* net_ptr, const int32_t* pin_cell,
                        hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
       return FFTPL_E_DEVICE;
-    if (hptr[0] != 0 || hptr[E] != P) return FFTPL_E_INVAL;
-    int k = 0;
-    int64_t cur = 0;
-    hnb[0] = 0;
-    for (int en = 0; en < E; ++en) {
-      const int64_t deg = (int64_t)hptr[(size_t)en + 1] - hptr[en];
-      if (deg < 0 || deg > d.max_degree) return FFTPL_E_INVAL;
-      if (cur + deg > d.cap) {
-        if (++k >= d.nnb) return FFTPL_E_INVAL;   // cannot happen for a valid CSR
-        hnb[k] = en;
-        cur = 0;
-      }
-      cur += deg;
-    }
+    const int st = pack_net_blocks(hptr.data(), E, P, d.max_degree, d.cap, d.nnb, hnb.data());
+    if (st != FFTPL_OK) return st;
     if (hipMemcpyAsync(nb_net_ptr, hnb.data(), sizeof(int32_t) * hnb.size(),
                        hipMemcpyHostToDevice, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)

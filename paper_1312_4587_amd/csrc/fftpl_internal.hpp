@@ -685,6 +685,13 @@ XchIndex xch_index(const XchDims& d, const void* index);
 
 int xch_build(const XchDims& d, const int32_t* net_ptr, const int32_t* pin_cell, void* index,
               void* work, hipStream_t s);   // returns fftpl_status; synchronises s
+// Host side of the build: net blocks packed greedily from a host copy of the
+// CSR (whole nets in order, a block closed when the next net does not fit in
+// cap pins): first[k] = first net of block k, first[k] = E past the last
+// block, k <= nnb.  FFTPL_E_INVAL for a CSR that is not one over P pins,
+// a net above max_degree, or more than nnb blocks.
+int pack_net_blocks(const int32_t* ptr, int E, int P, int max_degree, int cap, int nnb,
+                    int32_t* first);
 hipError_t launch_xch_spread(const XchDims& d, const XchIndex& X, const float* x,
                              const float* y, float2* T, hipStream_t s);
 hipError_t launch_xch_wa(const XchDims& d, const XchIndex& X, const int32_t* net_ptr,
