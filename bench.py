@@ -86,6 +86,8 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for the "
                          "FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--no-standalone", action="store_true",
+                    help="skip timing the standalone entry points")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the serving, placement-loop and differentiation runs")
     ap.add_argument("--serve-requests", type=int, default=5000)
@@ -337,6 +339,74 @@ def per_step_times(fn, steps, stream):
     return [evs[i].elapsed_time(evs[i + 1]) for i in range(steps)]
 
 
+def standalone_calls(fftpl, inst, prob, x, y, gx, gy, plan, stream, reps):
+    """Milliseconds per call of each standalone entry point at the benchmark
+    workload (inputs resident), and whether repeated calls give the same
+    bits."""
+    import ctypes
+
+    import torch
+    from paper_1312_4587_amd import _lib
+    n2 = inst.n ** 2
+    rho = torch.empty(n2, device="cuda")
+    rho2 = torch.empty(n2, device="cuda")
+    a = prob.arrays
+    out = {}
+
+    def run(name, f, check=None):
+        f()
+        ms = time_loop(f, reps, stream)
+        out[name] = {"ms": ms}
+        if check is not None:
+            out[name]["repeatable"] = bool(check())
+
+    def same_rho(f):
+        def chk():
+            f()
+            torch.cuda.synchronize()
+            r1 = rho.clone()
+            f()
+            torch.cuda.synchronize()
+            return torch.equal(r1, rho)
+        return chk
+    fd = lambda: fftpl.density_map(prob.grid, x, y, a["w"], a["h"], a["base"], rho)  # noqa
+    run("fftpl_density_map (float atomics)", fd, same_rho(fd))
+    fp = lambda: fftpl.problem_density(prob, x, y, rho)  # noqa
+    run("fftpl_problem_density", fp, same_rho(fp))
+    # the allocation-free form holds at most 921,600 cells: its first ones
+    mm = min(inst.num_cells, 921_600)
+    lib = _lib.load()
+    P = fftpl._ptr
+
+    def fna():
+        st = lib.fftpl_density_map_noalloc(ctypes.byref(prob.grid.c()), mm, P(x), P(y),
+                                           P(a["w"]), P(a["h"]), P(a["base"]), P(rho),
+                                           fftpl._stream(None))
+        fftpl._check(st, "fftpl_density_map_noalloc")
+    run(f"fftpl_density_map_noalloc ({mm} cells)", fna, same_rho(fna))
+    exy = plan.maps()[2].reshape(-1, 2)
+    ex, ey = exy[:, 0].contiguous(), exy[:, 1].contiguous()
+    psi = plan.maps()[1].reshape(-1)
+    fg = lambda: fftpl.field_gather(prob.grid, x, y, a["w"], a["h"], ex, ey, psi,  # noqa
+                                    "field", 1.0, 0, gx, gy)
+    run("fftpl_field_gather", fg)
+    fw = lambda: fftpl.wa_grad(a["net_ptr"], a["pin_cell"], a["pin_dx"], a["pin_dy"],  # noqa
+                               x, y, inst.gamma, 0, gx, gy)
+    run("fftpl_wa_grad (float atomics)", fw)
+    fx = lambda: fftpl.problem_wl_grad(prob, x, y, inst.gamma, 0, gx, gy)  # noqa
+
+    def same_g():
+        fx()
+        torch.cuda.synchronize()
+        g1 = gx.clone()
+        fx()
+        torch.cuda.synchronize()
+        return torch.equal(g1, gx)
+    run("fftpl_problem_wl_grad", fx, same_g)
+    del rho2
+    return out
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -475,6 +545,13 @@ def main():
         except fftpl.FFTPLError as e:
             variants[key] = {"unavailable": str(e)}
 
+    # ---- the standalone calls of the boundary, one at a time on this stream:
+    # the stateless ones (float atomics) beside their workspace-backed forms
+    standalone = None
+    if not args.no_standalone:
+        standalone = standalone_calls(fftpl, inst, prob, x, y, gx, gy, plan_for(args.dct),
+                                      stream, max(10, args.steps // 4))
+
     # ---- per-kernel durations: HIP events the library records on this
     # stream after every kernel (timing on the plan; no stream overlap then)
     nbytes = kernel_bytes(inst, band_entries(inst))
@@ -551,7 +628,7 @@ def main():
         "p50_ms": float(np.percentile(steps_ms, 50)),
         "p90_ms": float(np.percentile(steps_ms, 90)),
         "variants": variants, "kernels": kernels, "variant_kernels": variant_kernels,
-        "stages": stages, "roofline": roofline,
+        "stages": stages, "roofline": roofline, "standalone": standalone,
     }
     ref = None
     if not args.no_cpu_baseline:
