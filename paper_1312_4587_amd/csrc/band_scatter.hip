@@ -109,14 +109,22 @@ __device__ __forceinline__ void load_batch(CellBatch& c, int base, int m,
 // The entries of band `band` (band = nb: the tall cells) lie in one slice per
 // region: slice k holds blk_cnt[band][k] entries from index
 // k * stride + blk_off[band][k].  A block of NTB threads walks them in chunks
-// of NTB slices: the chunk's counts are scanned in LDS and each thread maps
-// its share of the chunk's entries to (slice, rank) by a binary search over
-// the scan, then calls f(index) for KB entries at a time (their indices all
-// known before any of them is used, so the caller can issue their loads
-// together).  Every thread of the block must call it.
+// of NTB slices: the chunk's counts are scanned, and the chunk's entries are
+// taken in windows of NTB * KB.  For each window every slice writes its own
+// number into an LDS owner map at the window positions it covers (slices
+// longer than a wavefront are written by the whole wavefront), so a
+// thread finds the slice of its entry with one LDS read (a binary search over
+// the scan, ten dependent LDS reads per entry, cost the walk more than its
+// loads).  Thread t takes window entries t, t + NTB, ...: KB of them, whose
+// indices are all known before f(index) uses any, so the caller can issue
+// their loads together.  Every thread of the block must call it; `owner`
+// holds NTB * KB entries.
 template <int NTB, int KB, typename F>
 __device__ __forceinline__ void walk_band(const BandLayout& L, int band, int64_t stride,
-                                          int* pre, int64_t* start, F f) {
+                                          int* pre, int64_t* start, unsigned short* owner,
+                                          F f) {
+  static_assert(NTB <= 65536, "slice numbers are u16");
+  constexpr int W = NTB * KB;
   const int t = threadIdx.x;
   for (int k0 = 0; k0 < L.nblk; k0 += NTB) {
     const int k = k0 + t;
@@ -126,28 +134,34 @@ __device__ __forceinline__ void walk_band(const BandLayout& L, int band, int64_t
     const int ex = block_exclusive_scan<NTB>(c, &tot);
     pre[t] = ex;
     start[t] = (int64_t)k * stride + o;
-    __syncthreads();
-    for (int v0 = 0; v0 < tot; v0 += NTB * KB) {
+    for (int w0 = 0; w0 < tot; w0 += W) {
+      // a slice of up to 64 window entries is written by its own thread,
+      // a longer one by its whole wavefront
+      const int a = max(ex, w0), e = min(ex + c, w0 + W);
+      const bool big = e - a > kWave;
+      if (!big)
+        for (int v = a; v < e; ++v) owner[v - w0] = (unsigned short)t;
+      unsigned long long bm = __ballot(big);
+      while (bm) {
+        const int l = __ffsll((long long)bm) - 1;
+        bm &= bm - 1;
+        const int ba = __shfl(a, l), be = __shfl(e, l), bt = __shfl(t, l);
+        for (int v = ba + (t & (kWave - 1)); v < be; v += kWave) owner[v - w0] = (unsigned short)bt;
+      }
+      __syncthreads();
       int64_t idx[KB];
 #pragma unroll
       for (int j = 0; j < KB; ++j) {
-        const int v = v0 + j * NTB + t;
+        const int v = w0 + j * NTB + t;
         idx[j] = -1;
         if (v < tot) {
-          int lo = 0, hi = NTB;   // largest s with pre[s] <= v: its slice holds v
-          while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (pre[mid] <= v)
-              lo = mid;
-            else
-              hi = mid;
-          }
-          idx[j] = start[lo] + (v - pre[lo]);
+          const int sl = owner[v - w0];
+          idx[j] = start[sl] + (v - pre[sl]);
         }
       }
       f(idx);
+      __syncthreads();   // owner, pre and start are rewritten next
     }
-    __syncthreads();   // pre / start are rewritten by the next chunk
   }
 }
 
@@ -241,12 +255,13 @@ __global__ void __launch_bounds__(kAccThreads) k_band_accum(BandBatch<NB> bb) {
   __shared__ unsigned long long acc[kBandMaxN * 4];   // rows * n <= 4096 bins
   __shared__ int pre[NTA];
   __shared__ int64_t start[NTA];
+  __shared__ unsigned short owner[NTA * B];
   const int t = threadIdx.x;
   const int n = g.n, R = L.rows, band = blockIdx.x, r0 = band * R;
   const int cells = min(R, n - r0) * n;
   for (int k = t; k < cells; k += NTA) acc[k] = 0ull;
   __syncthreads();
-  walk_band<NTA, B>(L, band, kBandRegion, pre, start, [&](const int64_t (&idx)[B]) {
+  walk_band<NTA, B>(L, band, kBandRegion, pre, start, owner, [&](const int64_t (&idx)[B]) {
     float4 q[B];
 #pragma unroll
     for (int j = 0; j < B; ++j) q[j] = L.entries[idx[j] >= 0 ? idx[j] : 0];
@@ -265,7 +280,7 @@ __global__ void __launch_bounds__(kAccThreads) k_band_accum(BandBatch<NB> bb) {
   });
   // cells too tall to be listed per band: every band block adds its rows of
   // them, one thread per cell
-  walk_band<NTA, 1>(L, L.nb, kCellsPerBlock, pre, start, [&](const int64_t (&idx)[1]) {
+  walk_band<NTA, 1>(L, L.nb, kCellsPerBlock, pre, start, owner, [&](const int64_t (&idx)[1]) {
     if (idx[0] < 0) return;
     const int i = L.big[idx[0]];
     const Span sx = cell_span(x[i], w[i], g.xl, g.inv_bw, n);
@@ -309,6 +324,7 @@ __global__ void __launch_bounds__(NTG) k_band_gather(BandBatch<NB> bb) {
   __shared__ float2 rows[5 * kBandMaxN];
   __shared__ int pre[NTG];
   __shared__ int64_t start[NTG];
+  __shared__ unsigned short owner[NTG * B];
   const int t = threadIdx.x;
   const int n = g.n, R = L.rows, band = blockIdx.x;
   const int r0 = band * R, nr = min(R + 1, n - r0);
@@ -324,7 +340,7 @@ __global__ void __launch_bounds__(NTG) k_band_gather(BandBatch<NB> bb) {
       if (t + j * NTG < cnt) rows[t + j * NTG] = v[j];
   }
   // (the walk's first scan synchronises the block after the staging)
-  walk_band<NTG, B>(L, band, kBandRegion, pre, start, [&](const int64_t (&idx)[B]) {
+  walk_band<NTG, B>(L, band, kBandRegion, pre, start, owner, [&](const int64_t (&idx)[B]) {
     float4 q[B];
 #pragma unroll
     for (int j = 0; j < B; ++j) q[j] = L.entries[idx[j] >= 0 ? idx[j] : 0];

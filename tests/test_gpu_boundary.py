@@ -41,7 +41,18 @@ def _tall_outside(n, seed):
                        [[50.0, 50.0, 10.0, 30.0]])
 
 
-@pytest.mark.parametrize("case", ["small_2k", "tall_outside_64", "n1024_300k", "empty"])
+def clustered(inst, sigma_bins, seed):
+    """The instance with every cell drawn around the region's centre (normal,
+    sigma in bins): most bands hold long slices from every cell block."""
+    rng = np.random.default_rng(seed)
+    c = 0.5 * inst.n * inst.bin_w
+    x = (c + rng.normal(0.0, sigma_bins * inst.bin_w, inst.num_cells)).astype(np.float32)
+    y = (c + rng.normal(0.0, sigma_bins * inst.bin_h, inst.num_cells)).astype(np.float32)
+    return inst.with_positions(x, y)
+
+
+@pytest.mark.parametrize("case", ["small_2k", "tall_outside_64", "n1024_300k", "empty",
+                                  "clustered_256", "n1024_4_3m"])
 def test_problem_density_matches_oracle_and_repeats_bit_for_bit(F, case):
     import torch
     if case == "small_2k":
@@ -51,6 +62,15 @@ def test_problem_density_matches_oracle_and_repeats_bit_for_bit(F, case):
     elif case == "n1024_300k":
         inst = gen.make_instance(23, num_cells=300_000, util=0.9, n=1024, num_nets=10,
                                  num_macros=30, macro_area_frac=0.15)
+    elif case == "clustered_256":
+        # slices of hundreds of entries per cell block and band, several
+        # windows per band
+        inst = clustered(gen.make_instance(24, num_cells=200_000, util=0.8, n=256,
+                                           num_nets=10), 6.0, 24)
+    elif case == "n1024_4_3m":
+        # more than 1024 cell blocks: the band walks take their slices in
+        # two chunks
+        inst = gen.make_instance(25, num_cells=4_300_000, util=0.9, n=1024, num_nets=10)
     else:
         inst = hand_instance(np.zeros((0, 4)), n=16)
     say("problem_density", case, inst.num_cells, inst.n)

@@ -476,6 +476,22 @@ def test_banded_scatter_with_tall_and_outside_cells(F, n, mode):
     _check_eval(inst, got, ref, 1.0, mode)
 
 
+@pytest.mark.parametrize("mode", ["field", "exact"])
+def test_eval_clustered_cells(F, mode):
+    # every cell near the centre: long slices per band and cell block, filled
+    # into the walks' owner maps by whole wavefronts, several windows per band
+    rng = np.random.default_rng(31)
+    inst = gen.make_instance(31, num_cells=120_000, util=0.8, n=256, num_nets=100_000)
+    c = 0.5 * inst.n * inst.bin_w
+    x = (c + rng.normal(0.0, 5.0 * inst.bin_w, inst.num_cells)).astype(np.float32)
+    y = (c + rng.normal(0.0, 5.0 * inst.bin_h, inst.num_cells)).astype(np.float32)
+    inst = inst.with_positions(x, y)
+    say("clustered", inst.num_cells, inst.n, mode)
+    got = _run_eval(F, inst, 1.0, mode)
+    ref = oracle.evaluate(inst, lam=1.0, grad_mode=mode)
+    _check_eval(inst, got, ref, 1.0, mode)
+
+
 # ---------------------------------------------------------------------------
 # GEMM (matrix-core) variants of the spectral solve
 # ---------------------------------------------------------------------------
