@@ -797,13 +797,16 @@ __global__ void __launch_bounds__(kSumThreads) k_xch_cellsum(SumBatch<NB> sb) {
   const CellGradArgs& a = rq.a;
   __shared__ unsigned long long ax[kXchCells], ay[kXchCells];
   __shared__ unsigned char bad[kXchCells];
-  for (int c = t; c < kXchCells; c += kSumThreads) {
-    ax[c] = 0ull;
-    ay[c] = 0ull;
-    bad[c] = 0;
-  }
-  __syncthreads();
+  // the block's A range, then the first-band entry of each of the thread's
+  // cells and its first group of pins: all in flight while LDS is cleared
   const int a0 = cb_a_ptr[cb], a1 = cb_a_ptr[cb + 1];
+  constexpr int PC = kXchCells / kSumThreads;
+  const int c0 = cb * cpb;
+  int ep[PC];
+  if (DENS) {
+#pragma unroll
+    for (int k = 0; k < PC; ++k) ep[k] = a.epos[min(c0 + t + k * kSumThreads, m - 1)];
+  }
   // pairs of consecutive A positions aligned to 2, consecutive pairs on
   // consecutive lanes (one 4-byte load of their cell indices and one 16-byte
   // load of their gradients, coalesced); positions outside the range are
@@ -811,16 +814,29 @@ __global__ void __launch_bounds__(kSumThreads) k_xch_cellsum(SumBatch<NB> sb) {
   const int g0 = a0 >> 1, g1 = (a1 + 1) >> 1;
   const uint32_t* lc2 = reinterpret_cast<const uint32_t*>(lc);
   const float4* T2 = reinterpret_cast<const float4*>(T);
-  constexpr int U = 4;
-  for (int g = g0 + t; g < g1; g += U * kSumThreads) {
-    uint32_t q[U];
-    float4 v[U];
+  constexpr int U = 4, STEP = U * kSumThreads;
+  // two groups of U pairs per thread in flight: the next group's loads are
+  // issued before the current group's adds
+  uint32_t q[U], qn[U];
+  float4 v[U], vn[U];
+  auto fetch = [&](uint32_t (&qq)[U], float4 (&vv)[U], int g) {
 #pragma unroll
     for (int k = 0; k < U; ++k) {
       const int gg = min(g + k * kSumThreads, g1 - 1);
-      q[k] = lc2[gg];
-      v[k] = T2[gg];
+      qq[k] = lc2[gg];
+      vv[k] = T2[gg];
     }
+  };
+  int g = g0 + t;
+  if (g < g1) fetch(q, v, g);
+  for (int c = t; c < kXchCells; c += kSumThreads) {
+    ax[c] = 0ull;
+    ay[c] = 0ull;
+    bad[c] = 0;
+  }
+  __syncthreads();
+  for (; g < g1; g += STEP) {
+    if (g + STEP < g1) fetch(qn, vn, g + STEP);
 #pragma unroll
     for (int k = 0; k < U; ++k) {
       const int gg = g + k * kSumThreads;
@@ -839,19 +855,19 @@ __global__ void __launch_bounds__(kSumThreads) k_xch_cellsum(SumBatch<NB> sb) {
         }
       }
     }
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      q[k] = qn[k];
+      v[k] = vn[k];
+    }
   }
   __syncthreads();
   // each cell's gradient: its density part from its first-band entry (one
   // 8-byte read; all of a thread's reads issued together) or, for a cell
   // without one, from the maps; plus its wirelength sum (DENS = false: the
   // wirelength sum alone, written or added to the gradient)
-  constexpr int PC = kXchCells / kSumThreads;
-  const int c0 = cb * cpb;
-  int ep[PC];
   float2 d[PC];
   if (DENS) {
-#pragma unroll
-    for (int k = 0; k < PC; ++k) ep[k] = a.epos[min(c0 + t + k * kSumThreads, m - 1)];
 #pragma unroll
     for (int k = 0; k < PC; ++k) d[k] = a.egrad[max(ep[k], 0)];
   } else if (a.accumulate) {
