@@ -32,23 +32,23 @@ PMC_FETCH_SCALE, PMC_WRITE_SCALE = 2.0, 1.0
 PMC_TRAFFIC = {
     # kernel: (source files, sha1, FETCH_SIZE KiB, WRITE_SIZE KiB)
     "k_band_place": (("band_scatter.hip", "fftpl_internal.hpp"),
-        "69d7a4c591392f2afd52c70f6eb0a576917e8a08", 16523.3, 64900.7),
+        "5940b9949d8ad08e700d6c8487884e19ab10f0f7", 16523.0, 64744.2),
     "k_xch_spread": (("exchange.hip", "fftpl_internal.hpp"),
-        "cc51d2a3fd685c7c4fcf4a3e6952cd82e70a3008", 28614.9, 96897.2),
+        "7b3e17fc6e6937f0f373726fe4ec8763bae3a53e", 28608.4, 96893.4),
     "k_band_accum": (("band_scatter.hip", "fftpl_internal.hpp"),
-        "69d7a4c591392f2afd52c70f6eb0a576917e8a08", 27909.0, 4096.0),
+        "5940b9949d8ad08e700d6c8487884e19ab10f0f7", 27911.4, 4096.0),
     "k_xch_wa": (("exchange.hip", "fftpl_internal.hpp"),
-        "cc51d2a3fd685c7c4fcf4a3e6952cd82e70a3008", 178810.8, 112288.7),
+        "7b3e17fc6e6937f0f373726fe4ec8763bae3a53e", 179001.6, 112289.1),
     "k_rows_dct2": (("spectral_fft.hip", "fftpl_internal.hpp"),
-        "fe3cf6061cae301ed67348ad9ef5d0c35619f22a", 6235.3, 4112.0),
+        "bbe015b47a027e441e6f8bdb56bde4c8ace387d2", 6235.7, 4117.9),
     "k_cols_solve": (("spectral_fft.hip", "fftpl_internal.hpp"),
-        "fe3cf6061cae301ed67348ad9ef5d0c35619f22a", 2180.1, 8192.0),
+        "bbe015b47a027e441e6f8bdb56bde4c8ace387d2", 2180.6, 8192.0),
     "k_rows_inverse": (("spectral_fft.hip", "fftpl_internal.hpp"),
-        "fe3cf6061cae301ed67348ad9ef5d0c35619f22a", 6265.6, 8196.0),
+        "bbe015b47a027e441e6f8bdb56bde4c8ace387d2", 6264.1, 8196.0),
     "k_band_gather": (("band_scatter.hip", "fftpl_internal.hpp"),
-        "69d7a4c591392f2afd52c70f6eb0a576917e8a08", 30982.0, 21043.8),
+        "5940b9949d8ad08e700d6c8487884e19ab10f0f7", 30993.3, 21001.5),
     "k_xch_cellsum": (("exchange.hip", "fftpl_internal.hpp"),
-        "cc51d2a3fd685c7c4fcf4a3e6952cd82e70a3008", 80991.5, 16406.5),
+        "7b3e17fc6e6937f0f373726fe4ec8763bae3a53e", 80819.4, 16406.5),
 }
 
 
