@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define FFTPL_VERSION 20000 /* major*10000 + minor*100 + patch */
+#define FFTPL_VERSION 20100 /* major*10000 + minor*100 + patch */
 
 enum fftpl_status {
   FFTPL_OK = 0,
@@ -430,6 +430,21 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
                const float* y, float lambda, float gamma, int32_t grad_mode,
                float* gx, float* gy, double* out4, void* stream);
 
+/* fftpl_eval with lambda and gamma read on the device, when the kernels run,
+ * from params[0] and params[1] (a device float[2]) instead of host arguments,
+ * so that a loop whose lambda and gamma are set on the device
+ * (fftpl_nesterov_schedule) can be enqueued, or captured in a graph, with no
+ * host read per iteration.  The results are those of fftpl_eval(..., params[0],
+ * params[1], ...): the same kernels and arithmetic (1/gamma formed in float as
+ * on the host).  Exchange path only (a problem with a workspace and an
+ * index; FFTPL_E_UNSUPPORTED otherwise); gx and gy must not be NULL.  params
+ * is read on the device and not checked: it must hold a finite lambda and a
+ * finite gamma > 0 when the evaluation runs (otherwise the results are not
+ * finite). */
+int fftpl_eval_params(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
+                      const float* y, const float* params, int32_t grad_mode, float* gx,
+                      float* gy, double* out4, void* stream);
+
 /* Serving extension: count evaluations of designs that share the plan's grid
  * side, with the results of
  *   fftpl_eval(plan, probs[i], xs[i], ys[i], lambdas[i], gammas[i], grad_mode,
@@ -475,6 +490,45 @@ int fftpl_nesterov_update(const fftpl_grid* region, int32_t num_cells, const flo
                           const float* h, float* x, float* y, float* ux, float* uy, float* upx,
                           float* upy, float* gpx, float* gpy, const float* gx, const float* gy,
                           float step, float beta, void* stream);
+
+/* fftpl_nesterov_update with step and beta read on the device from
+ * step_beta[0] and step_beta[1] (device doubles, rounded to float like the
+ * host call's arguments; e.g. state + 12 of fftpl_nesterov_schedule).  Not
+ * checked on the host: step >= 0 and 0 <= beta < 1 are the schedule's to
+ * keep. */
+int fftpl_nesterov_update_dev(const fftpl_grid* region, int32_t num_cells, const float* w,
+                              const float* h, float* x, float* y, float* ux, float* uy,
+                              float* upx, float* upy, float* gpx, float* gpy, const float* gx,
+                              const float* gy, const double* step_beta, void* stream);
+
+/* The schedule of one Nesterov iteration on the device (Section IV-A: the
+ * step interval, the gamma rule and the lambda update), so that a loop of
+ * fftpl_eval_params, fftpl_step_stats, fftpl_nesterov_schedule and
+ * fftpl_nesterov_update_dev needs no host read per iteration.  One thread
+ * reads stats (device double[4], fftpl_step_stats' out4) and out4 (device
+ * double[4], the evaluation's [N, W~, HPWL, tau]) and updates state (device
+ * double[FFTPL_LOOP_STATE]):
+ *   [0] a (Nesterov sequence), [1] alpha_max, [2] alpha_min (physical units),
+ *   [3] lambda, [4] gamma, [5] k (iterations done), [6] the previous
+ *   iteration's HPWL (NaN: none), [7] alpha_max_0, [8] bin width,
+ *   [9] lambda rule (0: doubled every [10] iterations, and a restarts at 1
+ *   when [11] != 0; 1: the paper's mu_k = 1.1^(1 - dHPWL / 3.5e5) bounded to
+ *   [0.75, 1.1]), [12], [13] (out) step and beta of this iteration's update,
+ *   [14] the first logged k.
+ * This iteration: alpha = the Barzilai-Borwein estimate sqrt(stats[0] /
+ * stats[1]) * stats[2] kept in [alpha_min, alpha_max] (alpha_max at k = 0 or
+ * when either sum is 0), step = alpha / stats[2] (0 when stats[2] = 0),
+ * a' = (1 + sqrt(4 a^2 + 1)) / 2, beta = (a - 1) / a'.  Next iteration:
+ * alpha_max = max(alpha_max_0, 2 alpha), alpha_min = 0.01 alpha_max,
+ * gamma = 8 bin 10^(20/9 (tau - 0.1) - 1), lambda by the rule, and params
+ * (device float[2]) = (lambda, gamma) for fftpl_eval_params.  If
+ * 0 <= k - state[14] < log_cap, log[8 (k - state[14]) + 0..7] = [k, N, W~,
+ * HPWL, tau, lambda, gamma, alpha] with this iteration's values (log: device
+ * double[8 log_cap], may be NULL when log_cap = 0).  Double arithmetic in the
+ * host rule's order. */
+#define FFTPL_LOOP_STATE 16
+int fftpl_nesterov_schedule(const double* stats, const double* out4, double* state,
+                            float* params, double* log, int32_t log_cap, void* stream);
 
 /* Nonlinear conjugate gradients, the inner solver of Algorithm 1 (the
  * "CGsolver" step: one direction and one line search inside the step

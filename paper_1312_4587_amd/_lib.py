@@ -70,6 +70,8 @@ SIGNATURES = {
                                c_void_p, c_void_p, c_void_p, c_void_p]),
     "fftpl_eval": (c_int, [c_void_p, _P, c_void_p, c_void_p, c_float, c_float, c_int,
                            c_void_p, c_void_p, c_void_p, c_void_p]),
+    "fftpl_eval_params": (c_int, [c_void_p, _P, c_void_p, c_void_p, c_void_p, c_int,
+                                  c_void_p, c_void_p, c_void_p, c_void_p]),
     "fftpl_eval_batch": (c_int, [c_void_p, c_int, ctypes.POINTER(_P),
                                  ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p),
                                  ctypes.POINTER(c_float), ctypes.POINTER(c_float), c_int,
@@ -100,6 +102,11 @@ SIGNATURES = {
                                       c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                       c_void_p, c_void_p, c_void_p, c_float, c_float,
                                       c_void_p]),
+    "fftpl_nesterov_update_dev": (c_int, [_G, c_int, c_void_p, c_void_p, c_void_p, c_void_p,
+                                          c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                          c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "fftpl_nesterov_schedule": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                        c_int, c_void_p]),
     "fftpl_cg_dots": (c_int, [c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                               c_void_p, c_void_p, c_void_p, ctypes.c_uint64, c_void_p]),
     "fftpl_cg_direction": (c_int, [c_int, c_void_p, c_void_p, c_float, c_void_p, c_void_p,

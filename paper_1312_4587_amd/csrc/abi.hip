@@ -510,6 +510,8 @@ struct EvalReq {
   const fftpl_problem* prob = nullptr;
   const float *x = nullptr, *y = nullptr;
   float lambda = 0.0f, gamma = 1.0f;
+  // if set, lambda and gamma are read on the device from params[0], params[1]
+  const float* params = nullptr;
   float *gx = nullptr, *gy = nullptr;
   double* out4 = nullptr;
   int path = FFTPL_PATH_ATOMIC;
@@ -626,6 +628,7 @@ int run_exchange_group(Plan& p, EvalReq* rs, int count, int grad_mode, hipStream
     br[i].psi = p.psi + i * nn;
     xr[i] = xch_req(r.xd, r.X, r.x, r.y, r.L.pin_grad, r.prob->net_ptr, r.prob->pin_dx,
                     r.prob->pin_dy, r.gamma, r.L.wa_part);
+    if (r.params) xr[i].dgamma = r.params + 1;
     sa[i] = spectral_args(p, r, i, grad_mode, grads);
   }
   // density branch: banded scatter (its counters and the scalars are all
@@ -686,6 +689,7 @@ int run_exchange_group(Plan& p, EvalReq* rs, int count, int grad_mode, hipStream
     ca.epos = r.L.epos;
     ca.egrad = r.L.egrad;
     ca.scale = r.lambda;
+    if (r.params) ca.dscale = r.params;
     ca.gx = r.gx;
     ca.gy = r.gy;
     ca.fin = fin;
@@ -812,6 +816,19 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
   hipStream_t s = as_stream(stream);
   if (r.path == FFTPL_PATH_EXCHANGE) return run_exchange_group(plan->p, &r, 1, grad_mode, s);
   return run_other(plan->p, r, grad_mode, s);
+}
+
+int fftpl_eval_params(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
+                      const float* y, const float* params, int32_t grad_mode, float* gx,
+                      float* gy, double* out4, void* stream) {
+  if (!plan || !params || !gx || !gy) return FFTPL_E_INVAL;
+  EvalReq r;
+  // lambda and gamma are not known on the host: the checks take placeholders
+  const int st = check_eval(plan->p, prob, x, y, 0.0f, 1.0f, grad_mode, gx, gy, out4, &r);
+  if (st != FFTPL_OK) return st;
+  if (r.path != FFTPL_PATH_EXCHANGE) return FFTPL_E_UNSUPPORTED;
+  r.params = params;
+  return run_exchange_group(plan->p, &r, 1, grad_mode, as_stream(stream));
 }
 
 int fftpl_eval_batch(fftpl_plan* plan, int32_t count, const fftpl_problem* const* probs,
@@ -1065,8 +1082,32 @@ int fftpl_nesterov_update(const fftpl_grid* region, int32_t num_cells, const flo
   const float xh = (float)(region->xl + region->n * region->bin_w);
   const float yh = (float)(region->yl + region->n * region->bin_h);
   return dev_status(launch_nesterov_update(num_cells, x, y, ux, uy, upx, upy, gpx, gpy, gx, gy,
-                                           w, h, step, beta, xl, yl, xh, yh,
+                                           w, h, step, beta, nullptr, xl, yl, xh, yh,
                                            as_stream(stream)));
+}
+
+int fftpl_nesterov_update_dev(const fftpl_grid* region, int32_t num_cells, const float* w,
+                              const float* h, float* x, float* y, float* ux, float* uy,
+                              float* upx, float* upy, float* gpx, float* gpy, const float* gx,
+                              const float* gy, const double* step_beta, void* stream) {
+  if (!grid_ok(region) || num_cells < 0 || !step_beta) return FFTPL_E_INVAL;
+  if (num_cells > 0 &&
+      (!w || !h || !x || !y || !ux || !uy || !upx || !upy || !gpx || !gpy || !gx || !gy))
+    return FFTPL_E_INVAL;
+  const float xl = (float)region->xl, yl = (float)region->yl;
+  const float xh = (float)(region->xl + region->n * region->bin_w);
+  const float yh = (float)(region->yl + region->n * region->bin_h);
+  return dev_status(launch_nesterov_update(num_cells, x, y, ux, uy, upx, upy, gpx, gpy, gx, gy,
+                                           w, h, 0.0f, 0.0f, step_beta, xl, yl, xh, yh,
+                                           as_stream(stream)));
+}
+
+int fftpl_nesterov_schedule(const double* stats, const double* out4, double* state,
+                            float* params, double* log, int32_t log_cap, void* stream) {
+  if (!stats || !out4 || !state || !params || log_cap < 0 || (log_cap > 0 && !log))
+    return FFTPL_E_INVAL;
+  return dev_status(launch_nesterov_schedule(stats, out4, state, params, log, log_cap,
+                                             as_stream(stream)));
 }
 
 int fftpl_cg_dots(int32_t num_cells, const float* gx, const float* gy, const float* gpx,

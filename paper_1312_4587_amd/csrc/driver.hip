@@ -81,9 +81,14 @@ __global__ void __launch_bounds__(256)
                       float* __restrict__ gpx, float* __restrict__ gpy,
                       const float* __restrict__ gx, const float* __restrict__ gy,
                       const float* __restrict__ w, const float* __restrict__ h, float step,
-                      float beta, float xl, float yl, float xh, float yh) {
+                      float beta, const double* __restrict__ step_beta, float xl, float yl,
+                      float xh, float yh) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= m) return;
+  if (step_beta) {   // set on the device by the schedule
+    step = (float)step_beta[0];
+    beta = (float)step_beta[1];
+  }
   const float hw = 0.5f * w[i], hh = 0.5f * h[i];
   const float ax = ux[i], ay = uy[i], bx = gx[i], by = gy[i];
   const float nx = clampc(ax - step * bx, xl + hw, xh - hw);
@@ -98,6 +103,63 @@ __global__ void __launch_bounds__(256)
   y[i] = ny;
   ux[i] = vx;
   uy[i] = vy;
+}
+
+// The host schedule of one Nesterov iteration, on the device (Section IV-A),
+// in double with the host's operation order (no contraction), so that a loop
+// of evaluations can run without a host read per iteration.  State layout:
+// see fftpl_nesterov_schedule.
+__global__ void __launch_bounds__(64)
+    k_nesterov_schedule(const double* __restrict__ stats, const double* __restrict__ out4,
+                        double* __restrict__ st, float* __restrict__ params,
+                        double* __restrict__ log, int log_cap) {
+#pragma clang fp contract(off)
+  if (threadIdx.x != 0) return;
+  const double du2 = stats[0], dg2 = stats[1], gmax = stats[2];
+  const double N = out4[0], W = out4[1], H = out4[2], tau = out4[3];
+  const double a = st[0], amax = st[1], amin = st[2], lam = st[3], gamma = st[4];
+  const double k = st[5], last_h = st[6], amax0 = st[7], bw = st[8];
+  // step length: the Barzilai-Borwein estimate as the largest displacement
+  double alpha = amax;
+  if (!(k == 0.0 || dg2 <= 0.0 || du2 <= 0.0)) alpha = fmin(amax, fmax(amin, sqrt(du2 / dg2) * gmax));
+  const double a1 = 0.5 * (1.0 + sqrt(4.0 * a * a + 1.0));
+  st[12] = gmax > 0.0 ? alpha / gmax : 0.0;
+  st[13] = (a - 1.0) / a1;
+  const double rel = k - st[14];
+  if (log && rel >= 0.0 && rel < (double)log_cap) {
+    double* r = log + 8 * (long long)rel;
+    r[0] = k;
+    r[1] = N;
+    r[2] = W;
+    r[3] = H;
+    r[4] = tau;
+    r[5] = lam;
+    r[6] = gamma;
+    r[7] = alpha;
+  }
+  // the next iteration's parameters
+  double na = a1, nlam = lam;
+  const double namax = fmax(amax0, 2.0 * alpha);
+  const double ngamma = 8.0 * bw * pow(10.0, 20.0 / 9.0 * (tau - 0.1) - 1.0);
+  if (st[9] == 0.0) {
+    const double every = st[10];
+    if (every >= 1.0 && fmod(k + 1.0, every) == 0.0) {
+      nlam = lam * 2.0;
+      if (st[11] != 0.0) na = 1.0;
+    }
+  } else if (last_h == last_h) {   // not NaN: a previous HPWL exists
+    const double mu = pow(1.1, 1.0 - (H - last_h) / 3.5e5);
+    nlam = lam * fmin(1.1, fmax(0.75, mu));
+  }
+  st[0] = na;
+  st[1] = namax;
+  st[2] = 0.01 * namax;
+  st[3] = nlam;
+  st[4] = ngamma;
+  st[5] = k + 1.0;
+  st[6] = H;
+  params[0] = (float)nlam;
+  params[1] = (float)ngamma;
 }
 
 // Nonlinear conjugate gradients (the inner solver of Algorithm 1).
@@ -230,11 +292,19 @@ hipError_t launch_step_stats(int m, const float* ux, const float* uy, const floa
 hipError_t launch_nesterov_update(int m, float* x, float* y, float* ux, float* uy, float* upx,
                                   float* upy, float* gpx, float* gpy, const float* gx,
                                   const float* gy, const float* w, const float* h, float step,
-                                  float beta, float xl, float yl, float xh, float yh,
-                                  hipStream_t s) {
+                                  float beta, const double* step_beta, float xl, float yl,
+                                  float xh, float yh, hipStream_t s) {
   if (m <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_nesterov_update, dim3((m + 255) / 256), dim3(256), 0, s, m, x, y, ux,
-                     uy, upx, upy, gpx, gpy, gx, gy, w, h, step, beta, xl, yl, xh, yh);
+                     uy, upx, upy, gpx, gpy, gx, gy, w, h, step, beta, step_beta, xl, yl, xh,
+                     yh);
+  return hipGetLastError();
+}
+
+hipError_t launch_nesterov_schedule(const double* stats, const double* out4, double* state,
+                                    float* params, double* log, int log_cap, hipStream_t s) {
+  hipLaunchKernelGGL(k_nesterov_schedule, dim3(1), dim3(64), 0, s, stats, out4, state, params,
+                     log, log_cap);
   return hipGetLastError();
 }
 

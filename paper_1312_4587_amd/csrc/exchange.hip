@@ -466,7 +466,8 @@ __global__ void __launch_bounds__(NW) k_xch_wa(XchBatch<NB> xb) {
   const uint16_t* __restrict__ lcsr = rq.lcsr;
   const float* __restrict__ pin_dx = rq.pin_dx;
   const float* __restrict__ pin_dy = rq.pin_dy;
-  const float gamma = rq.gamma, inv_gamma = rq.inv_gamma;
+  const float gamma = rq.dgamma ? rq.dgamma[0] : rq.gamma;
+  const float inv_gamma = rq.dgamma ? 1.0f / gamma : rq.inv_gamma;
   float2* __restrict__ T = rq.T;
   double* __restrict__ part = rq.part;
   double* __restrict__ net_wl = rq.net_wl;
@@ -867,6 +868,7 @@ __global__ void __launch_bounds__(kSumThreads) k_xch_cellsum(SumBatch<NB> sb) {
   // without one, from the maps; plus its wirelength sum (DENS = false: the
   // wirelength sum alone, written or added to the gradient)
   float2 d[PC];
+  const float lam = DENS && a.dscale ? a.dscale[0] : a.scale;
   if (DENS) {
 #pragma unroll
     for (int k = 0; k < PC; ++k) d[k] = a.egrad[max(ep[k], 0)];
@@ -887,8 +889,8 @@ __global__ void __launch_bounds__(kSumThreads) k_xch_cellsum(SumBatch<NB> sb) {
     const float sx = bad[c] ? __builtin_nanf("") : (float)((double)(long long)ax[c] * inv_scale);
     const float sy = bad[c] ? __builtin_nanf("") : (float)((double)(long long)ay[c] * inv_scale);
     if (DENS) {
-      a.gx[ci] = a.scale * d[k].x + sx;
-      a.gy[ci] = a.scale * d[k].y + sy;
+      a.gx[ci] = lam * d[k].x + sx;
+      a.gy[ci] = lam * d[k].y + sy;
     } else if (a.accumulate) {
       a.gx[ci] = d[k].x + sx;
       a.gy[ci] = d[k].y + sy;

@@ -709,6 +709,8 @@ struct CellGradArgs {
   const int32_t* epos = nullptr;
   const float2* egrad = nullptr;
   float scale = 0.0f;
+  // if set, the scale is read on the device from dscale[0] when the kernel runs
+  const float* dscale = nullptr;
   float *gx = nullptr, *gy = nullptr;
   // block fin_block (if >= 0) also reduces the evaluation's scalars (every
   // partial they need is complete before the cell sums start), in place of a
@@ -739,6 +741,9 @@ struct XchReq {
   const uint16_t* lcsr = nullptr;
   const float *pin_dx = nullptr, *pin_dy = nullptr;
   float gamma = 1.0f, inv_gamma = 1.0f;
+  // if set, gamma is read on the device from dgamma[0] when the kernel runs
+  // (and 1/gamma formed there in float, as on the host)
+  const float* dgamma = nullptr;
   double* part = nullptr;
   // per-net values at each net's first pin (a test export), or null
   double *net_wl = nullptr, *net_hp = nullptr;
@@ -787,11 +792,14 @@ hipError_t launch_cg_direction(int m, const float* gx, const float* gy, float be
 hipError_t launch_cg_move(int m, const float* x, const float* y, const float* dx,
                           const float* dy, float t, const float* w, const float* h, float xl,
                           float yl, float xh, float yh, float* xo, float* yo, hipStream_t s);
+// step_beta (if not null): step and beta read on the device instead
 hipError_t launch_nesterov_update(int m, float* x, float* y, float* ux, float* uy, float* upx,
                                   float* upy, float* gpx, float* gpy, const float* gx,
                                   const float* gy, const float* w, const float* h, float step,
-                                  float beta, float xl, float yl, float xh, float yh,
-                                  hipStream_t s);
+                                  float beta, const double* step_beta, float xl, float yl,
+                                  float xh, float yh, hipStream_t s);
+hipError_t launch_nesterov_schedule(const double* stats, const double* out4, double* state,
+                                    float* params, double* log, int log_cap, hipStream_t s);
 
 // Spectral solve.  psi/ex/ey/exy may be null individually.  en_part, if set,
 // receives n/2 per-block partials of the energy sum rho*psi; tau_part, if

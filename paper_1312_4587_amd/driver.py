@@ -4,7 +4,9 @@ Each iteration evaluates f = W~ + lambda N and its gradient at the look-ahead
 point (fftpl_eval), reduces the step statistics on the device
 (fftpl_step_stats) and moves every cell (fftpl_nesterov_update).  The host
 only reads eight doubles per iteration (the scalars and the statistics) to
-set the next step length, lambda and gamma.
+set the next step length, lambda and gamma; ``Placer.run_device`` runs the
+same rule on the device (fftpl_nesterov_schedule), so that iterations are
+enqueued, or replayed from a HIP graph, without that read.
 
 Schedules (Section IV-A):
 * step length: a Barzilai-Borwein estimate |du| / |dg| of the inverse
@@ -376,6 +378,76 @@ class Placer:
             rec = self.step(on_eval)
             if self.sched.stop_tau is not None and rec["tau"] <= self.sched.stop_tau:
                 break
+        return self.history
+
+    def run_device(self, iters: int, graph: bool = True) -> List[Dict[str, float]]:
+        """``iters`` Nesterov iterations with the schedule on the device: each
+        is fftpl_eval_params, fftpl_step_stats, fftpl_nesterov_schedule and
+        fftpl_nesterov_update_dev, with no host read until the end (with
+        ``graph``, one iteration is captured in a HIP graph and replayed).
+        The rule is step()'s (the first iteration, which has no previous point,
+        runs through step()).  The exchange path and the Nesterov solver only,
+        without fillers, stop_tau or a per-evaluation callback."""
+        if self.sched.solver != "nesterov":
+            raise ValueError("run_device runs the Nesterov solver")
+        if self.prob_real is not None or self.sched.stop_tau is not None:
+            raise ValueError("run_device has no fillers and no stop test")
+        if self.prob.path != "xch":
+            raise ValueError("run_device needs the exchange path")
+        if iters <= 0:
+            return self.history
+        if self.k == 0:
+            self.step()
+            iters -= 1
+            if iters == 0:
+                return self.history
+        dev = "cuda"
+        last = float("nan") if self.last_hpwl is None else float(self.last_hpwl)
+        st = torch.tensor([self.a, self.alpha_max, self.alpha_min, self.lam, self.gamma,
+                           float(self.k), last, self.alpha_max0, float(self.inst.bin_w),
+                           0.0 if self.sched.lam_mode == "double" else 1.0,
+                           float(self.sched.lam_every),
+                           1.0 if self.sched.restart_on_lambda else 0.0, 0.0, 0.0,
+                           float(self.k), 0.0], dtype=torch.float64, device=dev)
+        params = torch.tensor([self.lam, self.gamma], dtype=torch.float32, device=dev)
+        log = torch.zeros(8 * iters, dtype=torch.float64, device=dev)
+        lib = _lib.load()
+        p = fftpl._ptr
+        a = self.prob.arrays
+        m = self.inst.num_cells
+
+        def one():
+            fftpl.eval_params(self.plan, self.prob, self.ux, self.uy, params,
+                              self.sched.grad_mode, self.gx, self.gy, self.scal[:4])
+            self._stats(False)
+            s = fftpl._stream(None)
+            fftpl._check(lib.fftpl_nesterov_schedule(
+                p(self.scal) + 32, p(self.scal), p(st), p(params), p(log), iters, s),
+                "fftpl_nesterov_schedule")
+            fftpl._check(lib.fftpl_nesterov_update_dev(
+                ctypes.byref(self.region.c()), m, p(a["w"]), p(a["h"]), p(self.x), p(self.y),
+                p(self.ux), p(self.uy), p(self.upx), p(self.upy), p(self.gpx), p(self.gpy),
+                p(self.gx), p(self.gy), p(st) + 12 * 8, s), "fftpl_nesterov_update_dev")
+
+        if graph:
+            torch.cuda.synchronize()
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                one()
+            for _ in range(iters):
+                g.replay()
+        else:
+            for _ in range(iters):
+                one()
+        torch.cuda.synchronize()
+        sv = st.cpu().numpy()
+        for r in log.cpu().numpy().reshape(iters, 8):
+            self.history.append(dict(k=int(r[0]), energy=float(r[1]), wa=float(r[2]),
+                                     hpwl=float(r[3]), tau=float(r[4]), lam=float(r[5]),
+                                     gamma=float(r[6]), alpha=float(r[7])))
+        self.a, self.alpha_max, self.alpha_min = float(sv[0]), float(sv[1]), float(sv[2])
+        self.lam, self.gamma, self.k = float(sv[3]), float(sv[4]), int(sv[5])
+        self.last_hpwl = None if math.isnan(sv[6]) else float(sv[6])
         return self.history
 
     # -- checkpoint / resume -------------------------------------------------

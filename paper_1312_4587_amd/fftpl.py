@@ -488,6 +488,19 @@ def eval(plan: Plan, prob: Problem, x, y, lam, gamma, grad_mode, gx, gy, out4,
         _stream(stream)), "fftpl_eval")
 
 
+def eval_params(plan: Plan, prob: Problem, x, y, params, grad_mode, gx, gy, out4,
+                stream=None):
+    """fftpl_eval_params: fftpl_eval with (lambda, gamma) read on the device
+    from params (a float32 device tensor of 2 entries)."""
+    m = prob.num_cells
+    _check(_lib.load().fftpl_eval_params(
+        plan.handle, ctypes.byref(prob.c), _ptr(x, torch.float32, m, "x"),
+        _ptr(y, torch.float32, m, "y"), _ptr(params, torch.float32, 2, "params"),
+        GRAD_MODES.get(grad_mode, grad_mode), _ptr(gx, torch.float32, m, "gx"),
+        _ptr(gy, torch.float32, m, "gy"), _ptr(out4, torch.float64, 4, "out4"),
+        _stream(stream)), "fftpl_eval_params")
+
+
 def eval_batch(plan: Plan, probs, xs, ys, lams, gammas, grad_mode, gxs, gys, out4s,
                stream=None):
     """fftpl_eval_batch: requests i = 0..len(probs)-1 in order on one stream.

@@ -37,7 +37,7 @@ def test_every_declared_symbol_is_exported_and_bound():
 
 def test_version_and_status_strings():
     lib = _lib()
-    assert lib.fftpl_version() == 20000
+    assert lib.fftpl_version() == 20100
     for st in (0, -1, -2, -3, -4, -5):
         assert lib.fftpl_status_string(st).startswith(b"FFTPL_")
     assert b"unknown" in lib.fftpl_status_string(17)
@@ -105,6 +105,16 @@ def test_argument_errors_are_reported_before_any_device_work():
     assert lib.fftpl_helmholtz_solve(None, ctypes.byref(g), 0.5, p, p, None, None, None,
                                      None) == -1
     assert lib.fftpl_eval(None, None, p, p, 1.0, 1.0, 0, p, p, p, None) == -1
+    assert lib.fftpl_eval_params(None, None, p, p, p, 0, p, p, p, None) == -1
+    # the device loop's schedule and update: missing device arrays
+    assert lib.fftpl_nesterov_schedule(None, p, p, p, None, 0, None) == -1
+    assert lib.fftpl_nesterov_schedule(p, p, p, None, None, 0, None) == -1
+    assert lib.fftpl_nesterov_schedule(p, p, p, p, None, 4, None) == -1
+    assert lib.fftpl_nesterov_schedule(p, p, p, p, p, -1, None) == -1
+    assert lib.fftpl_nesterov_update_dev(ctypes.byref(g), 5, p, p, p, p, p, p, p, p, p, p,
+                                         p, p, None, None) == -1
+    assert lib.fftpl_nesterov_update_dev(ctypes.byref(g), 5, None, p, p, p, p, p, p, p, p,
+                                         p, p, p, p, None) == -1
     assert lib.fftpl_eval_batch(None, 0, None, None, None, None, None, 0, None, None, None,
                                 None) == 0
     assert lib.fftpl_eval_batch(None, -1, None, None, None, None, None, 0, None, None, None,

@@ -353,3 +353,85 @@ def test_cg_paper_schedule_mid_200k(F):
         assert abs(W - ref["wa"]) <= RTOL * abs(ref["wa"])
         assert abs(tau - ref["overflow"]) <= RTOL
     pl.close()
+
+
+@pytest.mark.parametrize("lam_mode", ["double", "paper"])
+def test_device_loop_matches_host_loop(F, lam_mode):
+    # The schedule on the device (fftpl_nesterov_schedule, eval with lambda
+    # and gamma read on the device, update with step and beta read there)
+    # follows the host loop: same histories and positions.  Enqueued and
+    # graph-replayed device loops run the same kernels on the same inputs:
+    # the same bits.  The lambda rule crosses a doubling (with the momentum
+    # restart) or applies mu_k every iteration.
+    import torch
+    fftpl, driver, _ = F
+    inst = gen.make_instance(61, num_cells=40_000, util=0.8, n=256, num_nets=42_000,
+                             hi_frac=0.01, hi_range=(20, 200), num_macros=5,
+                             macro_area_frac=0.1)
+    iters = 16
+    sched = driver.Schedule(lam_mode=lam_mode, lam_every=6)
+    runs = {}
+    for how in ("host", "device", "graph"):
+        pl = driver.Placer(inst, schedule=sched)
+        if how == "host":
+            pl.run(iters)
+        else:
+            pl.run_device(iters, graph=(how == "graph"))
+        torch.cuda.synchronize()
+        runs[how] = (pl.history, host(pl.x), host(pl.y), pl.k, pl.lam, pl.gamma, pl.a)
+        say(how, pl.k, pl.lam, pl.gamma, pl.history[-1])
+        pl.close()
+    hh, dh, gh = runs["host"][0], runs["device"][0], runs["graph"][0]
+    assert len(hh) == len(dh) == len(gh) == iters
+    assert [r["k"] for r in dh] == list(range(iters))
+    for a, b in zip(dh, gh):
+        assert a == b
+    assert np.array_equal(runs["device"][1], runs["graph"][1])
+    assert np.array_equal(runs["device"][2], runs["graph"][2])
+    # host vs device: the same rule in double; pow may round differently in
+    # the last bit, which float32 gamma almost always absorbs
+    for a, b in zip(hh, dh):
+        for key in ("energy", "wa", "hpwl", "tau", "lam", "gamma", "alpha"):
+            assert b[key] == pytest.approx(a[key], rel=1e-5, abs=1e-12), (a["k"], key)
+    if lam_mode == "double":
+        lams = [r["lam"] for r in dh]
+        assert lams[6] == 2.0 * lams[5] and lams[12] == 2.0 * lams[11]
+    assert runs["device"][3] == runs["host"][3] == iters
+    side = inst.n * inst.bin_w
+    for i in (1, 2):
+        assert np.max(np.abs(runs["device"][i] - runs["host"][i])) < 1e-4 * side
+    # the loop state handed back to the host continues like a host-only run
+    assert runs["device"][4] == pytest.approx(runs["host"][4], rel=1e-6)
+    assert runs["device"][5] == pytest.approx(runs["host"][5], rel=1e-5)
+    assert runs["device"][6] == pytest.approx(runs["host"][6], rel=1e-12)
+
+
+def test_eval_params_matches_eval(F):
+    # lambda and gamma read on the device give the bits of the host-argument
+    # evaluation; paths other than the exchange are refused
+    import torch
+    fftpl, driver, _ = F
+    inst = gen.make_instance(62, num_cells=30_000, util=0.8, n=128, num_nets=33_000,
+                             hi_frac=0.01, hi_range=(20, 200))
+    prob = fftpl.Problem.from_instance(inst)
+    plan = fftpl.Plan(inst.n)
+    x, y = dev(inst.x), dev(inst.y)
+    m = inst.num_cells
+    lam, gamma = 0.731, float(inst.gamma) * 1.37
+    for wl in ("wa", "lse"):
+        prob.set_objective(wl_model=wl)
+        g1 = [torch.empty(m, device="cuda") for _ in range(2)]
+        g2 = [torch.empty(m, device="cuda") for _ in range(2)]
+        o1 = torch.zeros(4, dtype=torch.float64, device="cuda")
+        o2 = torch.zeros(4, dtype=torch.float64, device="cuda")
+        fftpl.eval(plan, prob, x, y, lam, gamma, "field", g1[0], g1[1], o1)
+        params = torch.tensor([lam, gamma], dtype=torch.float32, device="cuda")
+        fftpl.eval_params(plan, prob, x, y, params, "field", g2[0], g2[1], o2)
+        torch.cuda.synchronize()
+        assert torch.equal(g1[0], g2[0]) and torch.equal(g1[1], g2[1]), wl
+        assert torch.equal(o1, o2), wl
+    slots = fftpl.Problem.from_instance(inst, path="slots")
+    with pytest.raises(fftpl.FFTPLError) as ei:
+        fftpl.eval_params(plan, slots, x, y, params, "field", g2[0], g2[1], o2)
+    assert ei.value.status == fftpl.E_UNSUPPORTED
+    plan.close()
