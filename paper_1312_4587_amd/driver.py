@@ -380,14 +380,17 @@ class Placer:
                 break
         return self.history
 
-    def run_device(self, iters: int, graph: bool = True) -> List[Dict[str, float]]:
+    def run_device(self, iters: int, graph: bool = True,
+                   between: Optional[Callable[[int], None]] = None) -> List[Dict[str, float]]:
         """``iters`` Nesterov iterations with the schedule on the device: each
         is fftpl_eval_params, fftpl_step_stats, fftpl_nesterov_schedule and
         fftpl_nesterov_update_dev, with no host read until the end (with
         ``graph``, one iteration is captured in a HIP graph and replayed).
         The rule is step()'s (the first iteration, which has no previous point,
         runs through step()).  The exchange path and the Nesterov solver only,
-        without fillers, stop_tau or a per-evaluation callback."""
+        without fillers, stop_tau or a per-evaluation callback.  ``between(i)``,
+        if given, runs on the host after the i-th device iteration is enqueued
+        (a test hook: it may synchronise and read state)."""
         if self.sched.solver != "nesterov":
             raise ValueError("run_device runs the Nesterov solver")
         if self.prob_real is not None or self.sched.stop_tau is not None:
@@ -434,11 +437,15 @@ class Placer:
             g = torch.cuda.CUDAGraph()
             with torch.cuda.graph(g):
                 one()
-            for _ in range(iters):
+            for i in range(iters):
                 g.replay()
+                if between is not None:
+                    between(i)
         else:
-            for _ in range(iters):
+            for i in range(iters):
                 one()
+                if between is not None:
+                    between(i)
         torch.cuda.synchronize()
         sv = st.cpu().numpy()
         for r in log.cpu().numpy().reshape(iters, 8):

@@ -435,3 +435,30 @@ def test_eval_params_matches_eval(F):
         fftpl.eval_params(plan, slots, x, y, params, "field", g2[0], g2[1], o2)
     assert ei.value.status == fftpl.E_UNSUPPORTED
     plan.close()
+
+
+def test_device_loop_graph_replays_match_eager_each_time(F):
+    # every replay of the captured iteration, with the program's own eager
+    # work and synchronisations between replays, gives the bits of the same
+    # iteration enqueued directly
+    import torch
+    fftpl, driver, _ = F
+    inst = gen.make_instance(63, num_cells=25_000, util=0.8, n=128, num_nets=27_000,
+                             hi_frac=0.01, hi_range=(20, 200))
+    snaps = {}
+    for graph in (False, True):
+        pl = driver.Placer(inst, schedule=driver.Schedule(lam_every=3))
+        seen = []
+
+        def between(i):
+            torch.cuda.synchronize()
+            junk = torch.randn(4096, device="cuda")
+            junk.mul_(2.0).sum().item()          # eager device work between replays
+            seen.append((host(pl.x), host(pl.y), host(pl.gx), host(pl.scal)))
+        pl.run_device(8, graph=graph, between=between)
+        snaps[graph] = seen
+        pl.close()
+    assert len(snaps[False]) == len(snaps[True]) == 7
+    for i, (a, b) in enumerate(zip(snaps[False], snaps[True])):
+        for u, v in zip(a, b):
+            assert np.array_equal(u, v), i
