@@ -32,23 +32,23 @@ PMC_FETCH_SCALE, PMC_WRITE_SCALE = 2.0, 1.0
 PMC_TRAFFIC = {
     # kernel: (source files, sha1, FETCH_SIZE KiB, WRITE_SIZE KiB)
     "k_band_place": (("band_scatter.hip", "fftpl_internal.hpp"),
-        "5940b9949d8ad08e700d6c8487884e19ab10f0f7", 16523.0, 64744.2),
+        "329608cc56474b6c23ba3bde17ae6854273be028", 16523.1, 64737.1),
     "k_xch_spread": (("exchange.hip", "fftpl_internal.hpp"),
-        "7b3e17fc6e6937f0f373726fe4ec8763bae3a53e", 28608.4, 96893.4),
+        "cea68045c6f9232b0afa2bc18d426f226fdd52f8", 28609.5, 96892.5),
     "k_band_accum": (("band_scatter.hip", "fftpl_internal.hpp"),
-        "5940b9949d8ad08e700d6c8487884e19ab10f0f7", 27911.4, 4096.0),
+        "329608cc56474b6c23ba3bde17ae6854273be028", 27911.0, 4096.0),
     "k_xch_wa": (("exchange.hip", "fftpl_internal.hpp"),
-        "7b3e17fc6e6937f0f373726fe4ec8763bae3a53e", 179001.6, 112289.1),
+        "cea68045c6f9232b0afa2bc18d426f226fdd52f8", 178947.9, 112289.3),
     "k_rows_dct2": (("spectral_fft.hip", "fftpl_internal.hpp"),
-        "bbe015b47a027e441e6f8bdb56bde4c8ace387d2", 6235.7, 4117.9),
+        "23eae4c941a6d65eb46b253566152ecf748c8596", 6235.7, 4112.0),
     "k_cols_solve": (("spectral_fft.hip", "fftpl_internal.hpp"),
-        "bbe015b47a027e441e6f8bdb56bde4c8ace387d2", 2180.6, 8192.0),
+        "23eae4c941a6d65eb46b253566152ecf748c8596", 2180.5, 8192.0),
     "k_rows_inverse": (("spectral_fft.hip", "fftpl_internal.hpp"),
-        "bbe015b47a027e441e6f8bdb56bde4c8ace387d2", 6264.1, 8196.0),
+        "23eae4c941a6d65eb46b253566152ecf748c8596", 6264.1, 8196.0),
     "k_band_gather": (("band_scatter.hip", "fftpl_internal.hpp"),
-        "5940b9949d8ad08e700d6c8487884e19ab10f0f7", 30993.3, 21001.5),
+        "329608cc56474b6c23ba3bde17ae6854273be028", 30993.6, 20998.0),
     "k_xch_cellsum": (("exchange.hip", "fftpl_internal.hpp"),
-        "7b3e17fc6e6937f0f373726fe4ec8763bae3a53e", 80819.4, 16406.5),
+        "cea68045c6f9232b0afa2bc18d426f226fdd52f8", 80800.3, 16406.5),
 }
 
 
