@@ -372,16 +372,39 @@ class Placer:
         self.k += 1
         return rec
 
-    def run(self, iters: int, on_eval: Optional[Callable[["Placer"], None]] = None
-            ) -> List[Dict[str, float]]:
+    def run(self, iters: int, on_eval: Optional[Callable[["Placer"], None]] = None,
+            trace: Optional[str] = None, checkpoint: Optional[str] = None,
+            checkpoint_every: int = 50) -> List[Dict[str, float]]:
+        """``iters`` iterations (fewer if the schedule's stop test fires).
+        ``trace``: a JSON-lines file that gets one record per iteration (k,
+        energy N, wa W~, hpwl, tau, lam, gamma, alpha, ...), appended as the
+        iterations complete.  ``checkpoint``: an .npz path saved every
+        ``checkpoint_every`` iterations and after the last one (load() resumes
+        from it)."""
         for _ in range(iters):
             rec = self.step(on_eval)
-            if self.sched.stop_tau is not None and rec["tau"] <= self.sched.stop_tau:
+            if trace is not None:
+                self._trace(trace, [rec])
+            stop = self.sched.stop_tau is not None and rec["tau"] <= self.sched.stop_tau
+            if checkpoint is not None and (self.k % checkpoint_every == 0 or stop):
+                self.save(checkpoint)
+            if stop:
                 break
+        if checkpoint is not None and self.k % checkpoint_every != 0:
+            self.save(checkpoint)
         return self.history
 
+    @staticmethod
+    def _trace(path: str, recs) -> None:
+        import json
+        with open(path, "a") as f:
+            for r in recs:
+                f.write(json.dumps({k: (int(v) if k == "k" else float(v)) for k, v in r.items()})
+                        + "\n")
+
     def run_device(self, iters: int, graph: bool = True,
-                   between: Optional[Callable[[int], None]] = None) -> List[Dict[str, float]]:
+                   between: Optional[Callable[[int], None]] = None,
+                   trace: Optional[str] = None) -> List[Dict[str, float]]:
         """``iters`` Nesterov iterations with the schedule on the device: each
         is fftpl_eval_params, fftpl_step_stats, fftpl_nesterov_schedule and
         fftpl_nesterov_update_dev, with no host read until the end (with
@@ -390,7 +413,8 @@ class Placer:
         runs through step()).  The exchange path and the Nesterov solver only,
         without fillers, stop_tau or a per-evaluation callback.  ``between(i)``,
         if given, runs on the host after the i-th device iteration is enqueued
-        (a test hook: it may synchronise and read state)."""
+        (a test hook: it may synchronise and read state).  ``trace``: as in
+        run(), written when the device log is read back at the end."""
         if self.sched.solver != "nesterov":
             raise ValueError("run_device runs the Nesterov solver")
         if self.prob_real is not None or self.sched.stop_tau is not None:
@@ -401,6 +425,8 @@ class Placer:
             return self.history
         if self.k == 0:
             self.step()
+            if trace is not None:
+                self._trace(trace, self.history[-1:])
             iters -= 1
             if iters == 0:
                 return self.history
@@ -448,10 +474,13 @@ class Placer:
                     between(i)
         torch.cuda.synchronize()
         sv = st.cpu().numpy()
+        first = len(self.history)
         for r in log.cpu().numpy().reshape(iters, 8):
             self.history.append(dict(k=int(r[0]), energy=float(r[1]), wa=float(r[2]),
                                      hpwl=float(r[3]), tau=float(r[4]), lam=float(r[5]),
                                      gamma=float(r[6]), alpha=float(r[7])))
+        if trace is not None:
+            self._trace(trace, self.history[first:])
         self.a, self.alpha_max, self.alpha_min = float(sv[0]), float(sv[1]), float(sv[2])
         self.lam, self.gamma, self.k = float(sv[3]), float(sv[4]), int(sv[5])
         self.last_hpwl = None if math.isnan(sv[6]) else float(sv[6])

@@ -22,7 +22,10 @@ host memory.
 Failures stay with their request: an executor reports a status per request,
 a request that fails releases its slot share and its admitted bytes like any
 other, and the statistics cover the requests that succeeded, with the failed
-ones counted and listed.
+ones counted and listed.  A request still waiting ``timeout_s`` after its
+arrival is failed with "timeout" without running, and ``cancel(rid)``
+withdraws a waiting request ("cancelled"); neither touches a request already
+in service.
 
 The executor is the part that touches the device; ``Server`` only schedules,
 so the scheduling logic can be exercised with any callable of the same
@@ -98,7 +101,8 @@ class Server:
 
     def __init__(self, executor: Callable, footprint: Callable[[int], int], slots: int = 8,
                  capacity_bytes: float = 200e9, keep: Sequence[int] = (),
-                 grid: Optional[Callable[[int], int]] = None, max_batch: int = 1):
+                 grid: Optional[Callable[[int], int]] = None, max_batch: int = 1,
+                 timeout_s: Optional[float] = None):
         self.executor = executor
         self.footprint = footprint
         self.grid = grid or (lambda d: 0)
@@ -116,6 +120,42 @@ class Server:
         self.results: Dict[int, Result] = {}
         self.busy_intervals: List[tuple] = []
         self.batch_sizes: List[int] = []
+        self.timeout_s = timeout_s
+        self.queue_seen: List[int] = []   # queue length each arrival found
+        self.max_queue = 0
+
+    def _fail_waiting(self, res: Result, why: str) -> None:
+        """Under the lock: a request that leaves the queue without running."""
+        res.done = time.perf_counter() - self.t0
+        res.start = res.done
+        res.ok = False
+        res.error = why
+        self.results[res.rid] = res
+
+    def _expire(self) -> None:
+        """Under the lock: fail the waiting requests past their deadline."""
+        if self.timeout_s is None or not self.waiting:
+            return
+        now = time.perf_counter() - self.t0
+        keep = collections.deque()
+        for item in self.waiting:
+            if now - item[0].arrival > self.timeout_s:
+                self._fail_waiting(item[0], "timeout")
+            else:
+                keep.append(item)
+        self.waiting = keep
+
+    def cancel(self, rid: int) -> bool:
+        """Withdraw request rid if it is still waiting (it fails with
+        "cancelled"); False if it is in service, done or unknown."""
+        with self.cv:
+            for i, item in enumerate(self.waiting):
+                if item[0].rid == rid:
+                    del self.waiting[i]
+                    self._fail_waiting(item[0], "cancelled")
+                    self.cv.notify_all()
+                    return True
+        return False
 
     def _take(self) -> Optional[List[Tuple[Result, int]]]:
         """Under the lock: the head request and the other waiting requests of
@@ -143,12 +183,14 @@ class Server:
         while True:
             with self.cv:
                 while True:
+                    self._expire()
                     group = self._take() if self.waiting else None
                     if group is not None:
                         break
                     if self.closed and not self.waiting:
                         return
-                    self.cv.wait()
+                    # with a deadline, wake up to expire waiting requests
+                    self.cv.wait(self.timeout_s if self.timeout_s else None)
                 need = sum(g[1] for g in group)
                 self.admitted_bytes += need
                 self.peak_bytes = max(self.peak_bytes, self.admitted_bytes)
@@ -200,7 +242,9 @@ class Server:
             v = int(variants[rid]) if variants is not None else 0
             res = Result(rid=rid, design=int(d), arrival=float(t), variant=v)
             with self.cv:
+                self.queue_seen.append(len(self.waiting))
                 self.waiting.append((res, self.footprint(int(d))))
+                self.max_queue = max(self.max_queue, len(self.waiting))
                 self.cv.notify_all()
         with self.cv:
             self.closed = True
@@ -226,8 +270,12 @@ class Server:
         if cur_e is not None:
             busy += cur_e - cur_s
         bs = np.array(self.batch_sizes) if self.batch_sizes else np.zeros(1)
+        why = collections.Counter(r.error for r in self.results.values() if not r.ok)
         return dict(requests=len(self.results), served=len(good), errors=len(failed),
-                    failed_ids=failed[:20], wall_s=wall,
+                    failed_ids=failed[:20], timeouts=why.get("timeout", 0),
+                    cancelled=why.get("cancelled", 0), wall_s=wall,
+                    max_queue_depth=self.max_queue,
+                    mean_queue_depth=float(np.mean(self.queue_seen)) if self.queue_seen else 0.0,
                     evals_per_s=len(good) / wall if wall > 0 else 0.0,
                     p50_ms=float(np.percentile(lat, 50) * 1e3),
                     p99_ms=float(np.percentile(lat, 99) * 1e3),

@@ -462,3 +462,36 @@ def test_device_loop_graph_replays_match_eager_each_time(F):
     for i, (a, b) in enumerate(zip(snaps[False], snaps[True])):
         for u, v in zip(a, b):
             assert np.array_equal(u, v), i
+
+
+def test_periodic_checkpoint_and_trace(F, tmp_path):
+    # run() with a JSON-lines trace and a checkpoint every 5 iterations: the
+    # trace holds every iteration's record as the history does; the last
+    # checkpoint (after iteration 12) resumes into the same next step; the
+    # device loop appends its records to a trace the same way
+    import json
+    fftpl, driver, _ = F
+    inst = gen.make_instance(64, num_cells=20_000, util=0.8, n=128, num_nets=22_000)
+    trace = str(tmp_path / "trace.jsonl")
+    ckpt = str(tmp_path / "ckpt.npz")
+    a = driver.Placer(inst)
+    a.run(12, trace=trace, checkpoint=ckpt, checkpoint_every=5)
+    recs = [json.loads(line) for line in open(trace)]
+    assert [r["k"] for r in recs] == list(range(12))
+    for r, h in zip(recs, a.history):
+        for key in ("energy", "wa", "hpwl", "tau", "lam", "gamma", "alpha"):
+            assert r[key] == h[key], key
+    a.step()
+    nxt = a.history[-1]
+    a.close()
+    b = driver.Placer(inst)
+    b.load(ckpt)
+    assert b.k == 12
+    b.step()
+    for key in ("energy", "wa", "hpwl", "tau", "alpha"):
+        assert b.history[-1][key] == pytest.approx(nxt[key], rel=1e-6), key
+    dtrace = str(tmp_path / "device.jsonl")
+    b.run_device(4, trace=dtrace)
+    drecs = [json.loads(line) for line in open(dtrace)]
+    assert [r["k"] for r in drecs] == [13, 14, 15, 16]
+    b.close()

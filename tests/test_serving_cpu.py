@@ -128,3 +128,42 @@ def test_executor_exception_fails_only_its_group():
 def test_footprint_formula():
     assert footprint_bytes(10, 5, 20, 8) == 16 * 10 + 8 * 10 + 12 * 20 + 4 * 6 + 8 * 64
     assert footprint_bytes(10, 5, 20, 8, 7, 3) == footprint_bytes(10, 5, 20, 8) + 10
+
+
+def test_waiting_requests_time_out_without_running():
+    # one slot, 20 ms per request, 10 at once, 50 ms deadline: the requests
+    # that would start after it fail with "timeout" and never reach the
+    # executor; everything admitted is released
+    ex = FakeExecutor([0.02])
+    srv = Server(ex, lambda d: 100, slots=1, capacity_bytes=1e9, timeout_s=0.05)
+    st = srv.run(np.zeros(10), np.zeros(10, int))
+    late = [r for r in range(10) if srv.results[r].error == "timeout"]
+    assert st["requests"] == 10 and st["timeouts"] == len(late) >= 5
+    assert st["served"] + st["timeouts"] == 10
+    assert not set(late) & set(ex.order)
+    assert all(srv.results[r].ok for r in ex.order)
+    assert srv.admitted_bytes == 0 and srv.in_service == 0
+    assert st["max_queue_depth"] >= 8 and st["mean_queue_depth"] > 0
+
+
+def test_cancel_withdraws_a_waiting_request_only():
+    # the executor, while running request 0 on the only slot, cancels
+    # request 5 (waiting: withdrawn) and request 0 (in service: refused)
+    answers = {}
+
+    class Canceller(FakeExecutor):
+        def __call__(self, slot, reqs):
+            if reqs[0].rid == 0:
+                time.sleep(0.01)               # let the burst queue up
+                answers[5] = srv.cancel(5)
+                answers[0] = srv.cancel(0)
+                answers[99] = srv.cancel(99)
+            return super().__call__(slot, reqs)
+
+    ex = Canceller([0.002])
+    srv = Server(ex, lambda d: 10, slots=1, capacity_bytes=1e9)
+    st = srv.run(np.zeros(8), np.zeros(8, int))
+    assert answers == {5: True, 0: False, 99: False}
+    assert srv.results[5].error == "cancelled" and 5 not in ex.order
+    assert st["cancelled"] == 1 and st["served"] == 7 and srv.results[0].ok
+    assert srv.admitted_bytes == 0 and srv.in_service == 0
