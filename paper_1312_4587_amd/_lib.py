@@ -4,7 +4,9 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libfftpl.so")
+# FFTPL_ROCTX=1: the build with roctx ranges around the entry points
+LIB_PATH = os.path.join(_HERE, "libfftpl_roctx.so" if os.environ.get("FFTPL_ROCTX") == "1"
+                        else "libfftpl.so")
 
 c_int = ctypes.c_int32
 c_float = ctypes.c_float

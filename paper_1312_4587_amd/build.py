@@ -1,6 +1,10 @@
 """Build libfftpl.so in-tree with hipcc for gfx950.
 
 Usage: python -m paper_1312_4587_amd.build   (or build() from Python).
+With FFTPL_ROCTX=1 in the environment the build (and the loader) use
+libfftpl_roctx.so instead: the same library with a roctx range around every
+entry point (rocprofv3 --marker-trace shows them), linked against the roctx
+library; the default build has none.
 """
 import concurrent.futures
 import os
@@ -10,8 +14,9 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
-LIB = os.path.join(HERE, "libfftpl.so")
-OBJDIR = os.path.join(HERE, "_build")
+ROCTX = os.environ.get("FFTPL_ROCTX") == "1"
+LIB = os.path.join(HERE, "libfftpl_roctx.so" if ROCTX else "libfftpl.so")
+OBJDIR = os.path.join(HERE, "_build_roctx" if ROCTX else "_build")
 SOURCES = ["abi.hip", "band_scatter.hip", "density.hip", "driver.hip", "exchange.hip", "spectral_fft.hip", "spectral_gemm.hip",
            "wirelength.hip"]
 ARCH = os.environ.get("FFTPL_OFFLOAD_ARCH", "gfx950")
@@ -20,7 +25,10 @@ FLAGS = [
     # packed FP32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
-]
+] + (["-DFFTPL_ROCTX"] if ROCTX else [])
+ROCM_LIB = "/opt/rocm/lib"
+LINK_EXTRA = ([f"-L{ROCM_LIB}", f"-Wl,-rpath,{ROCM_LIB}", "-lrocprofiler-sdk-roctx"]
+              if ROCTX else [])
 
 
 def _hipcc():
@@ -76,7 +84,7 @@ def build(verbose=False):
     with concurrent.futures.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, *LINK_EXTRA, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")

@@ -17,6 +17,23 @@ struct fftpl_plan {
   Plan p;
 };
 
+
+// A profiler range around each entry point that enqueues device work: built
+// with FFTPL_ROCTX (and linked against the roctx library) every call appears
+// by name in a rocprofv3 --marker-trace; otherwise this compiles to nothing.
+#ifdef FFTPL_ROCTX
+#include <rocprofiler-sdk-roctx/roctx.h>
+namespace {
+struct RoctxRange {
+  explicit RoctxRange(const char* name) { roctxRangePush(name); }
+  ~RoctxRange() { roctxRangePop(); }
+};
+}  // namespace
+#define FFTPL_RANGE() RoctxRange fftpl_roctx_range_(__func__)
+#else
+#define FFTPL_RANGE() ((void)0)
+#endif
+
 namespace {
 
 inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
@@ -238,6 +255,7 @@ int fftpl_plan_maps(const fftpl_plan* plan, const float** rho, const float** psi
 int fftpl_fixed_map(const fftpl_grid* grid, int32_t num_fixed, const float* fx,
                     const float* fy, const float* fw, const float* fh, float* base,
                     float* cap, void* stream) {
+  FFTPL_RANGE();
   if (!grid_ok(grid) || num_fixed < 0 || !base) return FFTPL_E_INVAL;
   if (num_fixed > 0 && (!fx || !fy || !fw || !fh)) return FFTPL_E_INVAL;
   return dev_status(launch_fixed_map(make_gridf(*grid), num_fixed, fx, fy, fw, fh, base,
@@ -315,6 +333,7 @@ int fftpl_dark_nodes(double xl, double yl, double xh, double yh, int32_t num_rec
 int fftpl_density_map(const fftpl_grid* grid, int32_t num_cells, const float* x,
                       const float* y, const float* w, const float* h,
                       const float* base, float* rho, void* stream) {
+  FFTPL_RANGE();
   if (!grid_ok(grid) || num_cells < 0 || !rho) return FFTPL_E_INVAL;
   if (num_cells > 0 && (!x || !y || !w || !h)) return FFTPL_E_INVAL;
   if (validate_env() && num_cells > 0) {
@@ -331,6 +350,7 @@ int fftpl_density_map(const fftpl_grid* grid, int32_t num_cells, const float* x,
 int fftpl_density_map_noalloc(const fftpl_grid* grid, int32_t num_cells, const float* x,
                               const float* y, const float* w, const float* h,
                               const float* base, float* rho, void* stream) {
+  FFTPL_RANGE();
   if (!grid_ok(grid) || num_cells < 0 || !rho) return FFTPL_E_INVAL;
   if (num_cells > 0 && (!x || !y || !w || !h)) return FFTPL_E_INVAL;
   if (grid->n > kBandMaxN || num_cells > FFTPL_NOALLOC_MAX_CELLS) return FFTPL_E_UNSUPPORTED;
@@ -352,6 +372,7 @@ int fftpl_density_map_noalloc(const fftpl_grid* grid, int32_t num_cells, const f
 int fftpl_helmholtz_solve(fftpl_plan* plan, const fftpl_grid* grid, float eps,
                           const float* rho, float* psi, float* ex, float* ey,
                           double* energy, void* stream) {
+  FFTPL_RANGE();
   if (!plan || !grid_ok(grid) || !rho || !psi) return FFTPL_E_INVAL;
   if (!(eps >= 0.0f) || !isfinite(eps)) return FFTPL_E_INVAL;
   if ((ex == nullptr) != (ey == nullptr)) return FFTPL_E_INVAL;
@@ -380,6 +401,7 @@ int fftpl_helmholtz_solve(fftpl_plan* plan, const fftpl_grid* grid, float eps,
 int fftpl_poisson_solve(fftpl_plan* plan, const fftpl_grid* grid, const float* rho,
                         float* psi, float* ex, float* ey, double* energy,
                         void* stream) {
+  FFTPL_RANGE();
   return fftpl_helmholtz_solve(plan, grid, 0.0f, rho, psi, ex, ey, energy, stream);
 }
 
@@ -388,6 +410,7 @@ int fftpl_field_gather(const fftpl_grid* grid, int32_t num_cells, const float* x
                        const float* ex, const float* ey, const float* psi,
                        int32_t grad_mode, float scale, int32_t accumulate,
                        float* gx, float* gy, void* stream) {
+  FFTPL_RANGE();
   if (!grid_ok(grid) || num_cells < 0 || !isfinite(scale)) return FFTPL_E_INVAL;
   if (grad_mode != FFTPL_GRAD_FIELD && grad_mode != FFTPL_GRAD_EXACT) return FFTPL_E_INVAL;
   if (accumulate != 0 && accumulate != 1) return FFTPL_E_INVAL;
@@ -434,6 +457,7 @@ int fftpl_wa_grad(int32_t num_nets, const int32_t* net_ptr, int32_t num_pins,
                   int32_t num_cells, const float* x, const float* y, float gamma,
                   int32_t accumulate, float* gx, float* gy, double* wa, double* hpwl,
                   void* stream) {
+  FFTPL_RANGE();
   return wl_grad(FFTPL_WL_WA, num_nets, net_ptr, num_pins, pin_cell, pin_dx, pin_dy, num_cells,
                  x, y, gamma, accumulate, gx, gy, wa, hpwl, stream);
 }
@@ -443,6 +467,7 @@ int fftpl_lse_grad(int32_t num_nets, const int32_t* net_ptr, int32_t num_pins,
                    int32_t num_cells, const float* x, const float* y, float gamma,
                    int32_t accumulate, float* gx, float* gy, double* wa, double* hpwl,
                    void* stream) {
+  FFTPL_RANGE();
   return wl_grad(FFTPL_WL_LSE, num_nets, net_ptr, num_pins, pin_cell, pin_dx, pin_dy,
                  num_cells, x, y, gamma, accumulate, gx, gy, wa, hpwl, stream);
 }
@@ -809,6 +834,7 @@ extern "C" {
 int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
                const float* y, float lambda, float gamma, int32_t grad_mode, float* gx,
                float* gy, double* out4, void* stream) {
+  FFTPL_RANGE();
   if (!plan) return FFTPL_E_INVAL;
   EvalReq r;
   const int st = check_eval(plan->p, prob, x, y, lambda, gamma, grad_mode, gx, gy, out4, &r);
@@ -821,6 +847,7 @@ int fftpl_eval(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
 int fftpl_eval_params(fftpl_plan* plan, const fftpl_problem* prob, const float* x,
                       const float* y, const float* params, int32_t grad_mode, float* gx,
                       float* gy, double* out4, void* stream) {
+  FFTPL_RANGE();
   if (!plan || !params || !gx || !gy) return FFTPL_E_INVAL;
   EvalReq r;
   // lambda and gamma are not known on the host: the checks take placeholders
@@ -835,6 +862,7 @@ int fftpl_eval_batch(fftpl_plan* plan, int32_t count, const fftpl_problem* const
                      const float* const* xs, const float* const* ys, const float* lambdas,
                      const float* gammas, int32_t grad_mode, float* const* gxs,
                      float* const* gys, double* out4s, void* stream) {
+  FFTPL_RANGE();
   if (count < 0) return FFTPL_E_INVAL;
   if (count == 0) return FFTPL_OK;
   if (!plan || !probs || !xs || !ys || !lambdas || !gammas || !out4s) return FFTPL_E_INVAL;
@@ -878,6 +906,7 @@ int fftpl_problem_path(const fftpl_problem* prob, int32_t* path) {
 
 int fftpl_problem_density(const fftpl_problem* prob, const float* x, const float* y,
                           float* rho, void* stream) {
+  FFTPL_RANGE();
   if (!prob || !rho || !grid_ok(&prob->grid)) return FFTPL_E_INVAL;
   const int m = prob->num_cells;
   if (m < 0) return FFTPL_E_INVAL;
@@ -960,11 +989,13 @@ static int problem_wl(const fftpl_problem* prob, const float* x, const float* y,
 int fftpl_problem_wl_grad(const fftpl_problem* prob, const float* x, const float* y,
                           float gamma, int32_t accumulate, float* gx, float* gy, double* wl,
                           double* hpwl, void* stream) {
+  FFTPL_RANGE();
   return problem_wl(prob, x, y, gamma, accumulate, gx, gy, wl, hpwl, nullptr, nullptr, stream);
 }
 
 int fftpl_debug_net_values(const fftpl_problem* prob, const float* x, const float* y,
                            float gamma, double* wl_first, double* hpwl_first, void* stream) {
+  FFTPL_RANGE();
   if (!wl_first || !hpwl_first) return FFTPL_E_INVAL;
   return problem_wl(prob, x, y, gamma, 0, nullptr, nullptr, nullptr, nullptr, wl_first,
                     hpwl_first, stream);
@@ -1012,6 +1043,7 @@ int fftpl_problem_work_bytes(int32_t n, int32_t num_cells, int32_t num_nets,
 
 int fftpl_netlist_index(int32_t num_cells, int32_t num_pins, const int32_t* pin_cell,
                         int32_t* cell_ptr, int32_t* pin_slot, int32_t* work, void* stream) {
+  FFTPL_RANGE();
   if (num_cells < 0 || num_pins < 0 || !cell_ptr || !work) return FFTPL_E_INVAL;
   if (num_pins > 0 && (!pin_cell || !pin_slot || num_cells == 0)) return FFTPL_E_INVAL;
   if (validate_env() && num_pins > 0) {
@@ -1039,6 +1071,7 @@ int fftpl_xindex_build(int32_t num_cells, int32_t num_nets, int32_t num_pins,
                        const int32_t* net_ptr, const int32_t* pin_cell, int32_t max_degree,
                        void* index, uint64_t index_bytes, void* work, uint64_t work_bytes,
                        uint64_t* key, void* stream) {
+  FFTPL_RANGE();
   XchDims d;
   const int st = xch_dims(num_cells, num_nets, num_pins, max_degree, &d);
   if (st != FFTPL_OK) return st;
@@ -1059,6 +1092,7 @@ int fftpl_step_stats(int32_t num_cells, const float* ux, const float* uy, const 
                      const float* upy, const float* gx, const float* gy, const float* gpx,
                      const float* gpy, double* out4, double* work, uint64_t work_doubles,
                      void* stream) {
+  FFTPL_RANGE();
   if (num_cells < 0 || !out4 || !work || work_doubles < step_stats_work_doubles())
     return FFTPL_E_INVAL;
   if (num_cells > 0 && (!ux || !uy || !gx || !gy)) return FFTPL_E_INVAL;
@@ -1072,6 +1106,7 @@ int fftpl_nesterov_update(const fftpl_grid* region, int32_t num_cells, const flo
                           const float* h, float* x, float* y, float* ux, float* uy, float* upx,
                           float* upy, float* gpx, float* gpy, const float* gx, const float* gy,
                           float step, float beta, void* stream) {
+  FFTPL_RANGE();
   if (!grid_ok(region) || num_cells < 0) return FFTPL_E_INVAL;
   if (!isfinite(step) || step < 0.0f || !isfinite(beta) || beta < 0.0f || beta >= 1.0f)
     return FFTPL_E_INVAL;
@@ -1090,6 +1125,7 @@ int fftpl_nesterov_update_dev(const fftpl_grid* region, int32_t num_cells, const
                               const float* h, float* x, float* y, float* ux, float* uy,
                               float* upx, float* upy, float* gpx, float* gpy, const float* gx,
                               const float* gy, const double* step_beta, void* stream) {
+  FFTPL_RANGE();
   if (!grid_ok(region) || num_cells < 0 || !step_beta) return FFTPL_E_INVAL;
   if (num_cells > 0 &&
       (!w || !h || !x || !y || !ux || !uy || !upx || !upy || !gpx || !gpy || !gx || !gy))
@@ -1104,6 +1140,7 @@ int fftpl_nesterov_update_dev(const fftpl_grid* region, int32_t num_cells, const
 
 int fftpl_nesterov_schedule(const double* stats, const double* out4, double* state,
                             float* params, double* log, int32_t log_cap, void* stream) {
+  FFTPL_RANGE();
   if (!stats || !out4 || !state || !params || log_cap < 0 || (log_cap > 0 && !log))
     return FFTPL_E_INVAL;
   return dev_status(launch_nesterov_schedule(stats, out4, state, params, log, log_cap,
@@ -1113,6 +1150,7 @@ int fftpl_nesterov_schedule(const double* stats, const double* out4, double* sta
 int fftpl_cg_dots(int32_t num_cells, const float* gx, const float* gy, const float* gpx,
                   const float* gpy, const float* dx, const float* dy, double* out4,
                   double* work, uint64_t work_doubles, void* stream) {
+  FFTPL_RANGE();
   if (num_cells < 0 || !out4 || !work || work_doubles < step_stats_work_doubles())
     return FFTPL_E_INVAL;
   if (num_cells > 0 && (!gx || !gy)) return FFTPL_E_INVAL;
@@ -1125,6 +1163,7 @@ int fftpl_cg_dots(int32_t num_cells, const float* gx, const float* gy, const flo
 int fftpl_cg_direction(int32_t num_cells, const float* gx, const float* gy, float beta,
                        float* dx, float* dy, double* dmax, double* work, uint64_t work_doubles,
                        void* stream) {
+  FFTPL_RANGE();
   if (num_cells < 0 || !dmax || !work || work_doubles < step_stats_work_doubles())
     return FFTPL_E_INVAL;
   if (!isfinite(beta) || beta < 0.0f) return FFTPL_E_INVAL;
@@ -1136,6 +1175,7 @@ int fftpl_cg_direction(int32_t num_cells, const float* gx, const float* gy, floa
 int fftpl_cg_move(const fftpl_grid* region, int32_t num_cells, const float* w, const float* h,
                   const float* x, const float* y, const float* dx, const float* dy, float t,
                   float* xo, float* yo, void* stream) {
+  FFTPL_RANGE();
   if (!grid_ok(region) || num_cells < 0 || !isfinite(t)) return FFTPL_E_INVAL;
   if (num_cells > 0 && (!w || !h || !x || !y || !dx || !dy || !xo || !yo))
     return FFTPL_E_INVAL;
@@ -1149,6 +1189,7 @@ int fftpl_cg_move(const fftpl_grid* region, int32_t num_cells, const float* w, c
 int fftpl_debug_cell_bins(const fftpl_grid* grid, int32_t num_cells, const float* x,
                           const float* y, const float* w, const float* h,
                           int32_t* ranges, void* stream) {
+  FFTPL_RANGE();
   if (!grid_ok(grid) || num_cells < 0) return FFTPL_E_INVAL;
   if (num_cells > 0 && (!x || !y || !w || !h || !ranges)) return FFTPL_E_INVAL;
   return dev_status(

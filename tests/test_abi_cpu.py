@@ -206,3 +206,22 @@ def test_problem_paths_are_decided_on_the_host():
     assert lib.fftpl_problem_density(ctypes.byref(_problem(L)), h, h, h, None) == -1
     assert lib.fftpl_problem_density(ctypes.byref(_problem(L, n=2048)), h, h, h, None) == -4
     assert lib.fftpl_problem_path(None, ctypes.byref(path)) == -1
+
+
+def test_roctx_ranges_only_in_the_flagged_build(tmp_path):
+    # the entry points' profiler ranges compile in with FFTPL_ROCTX and out
+    # without it (compiled here, host and gfx950 device code)
+    import shutil
+    import subprocess
+    from paper_1312_4587_amd import build
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    src = os.path.join(build.CSRC, "abi.hip")
+    refs = {}
+    for flag in ([], ["-DFFTPL_ROCTX"]):
+        obj = str(tmp_path / ("abi%s.o" % ("_roctx" if flag else "")))
+        r = subprocess.run([hipcc, "-O1", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
+                            "-w", *flag, "-c", src, "-o", obj], capture_output=True, text=True)
+        assert r.returncode == 0, r.stderr[-2000:]
+        nm = subprocess.run(["nm", obj], capture_output=True, text=True).stdout
+        refs[bool(flag)] = ("roctxRangePush" in nm, "roctxRangePop" in nm)
+    assert refs[False] == (False, False) and refs[True] == (True, True)
