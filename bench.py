@@ -383,7 +383,7 @@ def standalone_calls(fftpl, inst, prob, x, y, gx, gy, plan, stream, reps):
             return torch.equal(r1, rho)
         return chk
     fd = lambda: fftpl.density_map(prob.grid, x, y, a["w"], a["h"], a["base"], rho)  # noqa
-    run("fftpl_density_map (float atomics)", fd, same_rho(fd))
+    run("fftpl_density_map (temporary stream-ordered workspace)", fd, same_rho(fd))
     fp = lambda: fftpl.problem_density(prob, x, y, rho)  # noqa
     run("fftpl_problem_density", fp, same_rho(fp))
     # the allocation-free form holds at most 921,600 cells: its first ones

@@ -249,10 +249,14 @@ int fftpl_dark_nodes(double xl, double yl, double xh, double yh, int32_t num_rec
 
 /* Density map (Eq. (2), Section III-B): rho = base + sum over movable cells of
  * their overlap area with each bin.  base may be NULL (treated as 0).  rho is
- * overwritten.  This stateless form has no workspace and accumulates with
- * float atomics, so the rounding order (not the value beyond float32
- * rounding) varies between runs and it runs several times slower than
- * fftpl_problem_density, the workspace-backed form. */
+ * overwritten.  For n <= 1024 it runs the evaluation's banded scatter
+ * (counting sort by band, fixed-point LDS sums: the same bits on every run)
+ * with its band lists in a temporary allocation made and released on
+ * `stream` (hipMallocAsync / hipFreeAsync; FFTPL_E_NOMEM if it fails); the
+ * caller that keeps a workspace uses fftpl_problem_density, the caller that
+ * cannot allocate fftpl_density_map_noalloc.  For n > 1024 it accumulates
+ * with float atomics: the rounding order (not the value beyond float32
+ * rounding) then varies between runs. */
 int fftpl_density_map(const fftpl_grid* grid, int32_t num_cells, const float* x,
                       const float* y, const float* w, const float* h,
                       const float* base, float* rho, void* stream);

@@ -342,6 +342,23 @@ int fftpl_density_map(const fftpl_grid* grid, int32_t num_cells, const float* x,
   }
   const GridF g = make_gridf(*grid);
   hipStream_t s = as_stream(stream);
+  if (grid->n <= kBandMaxN) {
+    // the banded scatter of the evaluation, its band lists in a temporary
+    // stream-ordered allocation released on the stream after the scatter
+    size_t need = 0;
+    band_layout_density(grid->n, num_cells, nullptr, &need);
+    void* work = nullptr;
+    if (hipMallocAsync(&work, need, s) != hipSuccess || !work) {
+      (void)hipGetLastError();
+      return FFTPL_E_NOMEM;
+    }
+    const BandLayout L = band_layout_density(grid->n, num_cells, work, nullptr);
+    hipError_t e = launch_band_scatter(g, L, x, y, w, h, base, rho, s);
+    const hipError_t f = hipFreeAsync(work, s);
+    if (e == hipSuccess) e = f;
+    return dev_status(e);
+  }
+  // grids past the band kernels' LDS rows: float atomics
   hipError_t e = launch_fill(rho, base, 0.0f, (int64_t)grid->n * grid->n, s);
   if (e == hipSuccess) e = launch_scatter(g, num_cells, x, y, w, h, rho, s);
   return dev_status(e);

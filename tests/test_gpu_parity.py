@@ -98,7 +98,8 @@ def test_fixed_map(F):
     assert float(base.abs().max()) == 0.0 and np.allclose(host(cap), 0.9)
 
 
-@pytest.mark.parametrize("which", ["tiny_outside", "small_2k", "mid_macros", "n1024"])
+@pytest.mark.parametrize("which", ["tiny_outside", "small_2k", "mid_macros", "n1024",
+                                   "n2048_atomic"])
 def test_density_map(F, which):
     import torch
     if which == "tiny_outside":
@@ -109,8 +110,11 @@ def test_density_map(F, which):
     elif which == "mid_macros":
         inst = gen.make_instance(22, num_cells=100_000, util=0.8, n=512, num_nets=10,
                                  num_macros=20, macro_area_frac=0.15)
-    else:
+    elif which == "n1024":
         inst = gen.make_instance(23, num_cells=300_000, util=0.9, n=1024, num_nets=10)
+    else:
+        # past the band kernels' rows: float atomics
+        inst = gen.make_instance(26, num_cells=400_000, util=0.9, n=2048, num_nets=10)
     say("density", which, inst.num_cells, inst.n)
     n2 = inst.n ** 2
     base = torch.empty(n2, device="cuda")
@@ -122,6 +126,13 @@ def test_density_map(F, which):
     rho = torch.empty(n2, device="cuda")
     c = DeviceCells(inst)
     F.density_map(grid, c.x, c.y, c.w, c.h, base, rho)
+    rho2 = torch.full((n2,), -1.0, device="cuda")
+    F.density_map(grid, c.x, c.y, c.w, c.h, base, rho2)
+    torch.cuda.synchronize()
+    if inst.n <= 1024:
+        assert torch.equal(rho, rho2)      # banded scatter: the same bits every run
+    else:
+        assert rel_l2(host(rho2), host(rho)) < 1e-6
     b0, _ = oracle.fixed_maps(inst)
     r0 = oracle.density_map(inst, b0)
     assert rel_l2(host(rho).reshape(inst.n, inst.n), r0) < RTOL
