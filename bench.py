@@ -405,17 +405,19 @@ def standalone_calls(fftpl, inst, prob, x, y, gx, gy, plan, stream, reps):
     run("fftpl_field_gather", fg)
     fw = lambda: fftpl.wa_grad(a["net_ptr"], a["pin_cell"], a["pin_dx"], a["pin_dy"],  # noqa
                                x, y, inst.gamma, 0, gx, gy)
-    run("fftpl_wa_grad (float atomics)", fw)
-    fx = lambda: fftpl.problem_wl_grad(prob, x, y, inst.gamma, 0, gx, gy)  # noqa
 
-    def same_g():
-        fx()
-        torch.cuda.synchronize()
-        g1 = gx.clone()
-        fx()
-        torch.cuda.synchronize()
-        return torch.equal(g1, gx)
-    run("fftpl_problem_wl_grad", fx, same_g)
+    def same_g(f):
+        def chk():
+            f()
+            torch.cuda.synchronize()
+            a1, b1 = gx.clone(), gy.clone()
+            f()
+            torch.cuda.synchronize()
+            return torch.equal(a1, gx) and torch.equal(b1, gy)
+        return chk
+    run("fftpl_wa_grad (fixed-point global atomics, temporary workspace)", fw, same_g(fw))
+    fx = lambda: fftpl.problem_wl_grad(prob, x, y, inst.gamma, 0, gx, gy)  # noqa
+    run("fftpl_problem_wl_grad", fx, same_g(fx))
     del rho2
     return out
 

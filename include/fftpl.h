@@ -331,8 +331,15 @@ int fftpl_field_gather(const fftpl_grid* grid, int32_t num_cells, const float* x
 /* Weighted-average wirelength (Eq. (3)) and HPWL (Eq. (1)) over the pin-net
  * CSR, pins at cell centre + offset.  Adds (accumulate = 1) or writes
  * (accumulate = 0) dW~/dx, dW~/dy summed over each cell's pins into gx, gy
- * [num_cells] (float atomics).  wa and hpwl, if not NULL, are device doubles
- * set to the totals over all nets and both axes.  gamma > 0, physical units. */
+ * [num_cells].  wa and hpwl, if not NULL, are device doubles set to the
+ * totals over all nets and both axes.  gamma > 0, physical units.  Each pin's
+ * gradient is added to its cell in 64-bit fixed point (units of 2^-32; a
+ * non-finite pin gradient makes its cell NaN) and the totals are per-block
+ * partials summed in a fixed order, so the results are the same on every
+ * run; the accumulators live in a temporary allocation made and released on
+ * `stream` (hipMallocAsync / hipFreeAsync; FFTPL_E_NOMEM if it fails).  The
+ * per-cell adds are global atomics (one per pin and axis); the problem form
+ * fftpl_problem_wl_grad moves the pins through its exchange index instead. */
 int fftpl_wa_grad(int32_t num_nets, const int32_t* net_ptr, int32_t num_pins,
                   const int32_t* pin_cell, const float* pin_dx, const float* pin_dy,
                   int32_t num_cells, const float* x, const float* y, float gamma,

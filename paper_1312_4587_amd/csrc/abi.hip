@@ -457,15 +457,28 @@ static int wl_grad(int wl_model, int32_t num_nets, const int32_t* net_ptr, int32
   }
   hipStream_t s = as_stream(stream);
   hipError_t e = hipSuccess;
+  if (num_nets > 0 && num_pins > 0) {
+    // fixed-point per-cell sums in a temporary stream-ordered workspace:
+    // the same bits on every run
+    void* work = nullptr;
+    if (hipMallocAsync(&work, wa_fixed_work_bytes(num_cells, num_nets), s) != hipSuccess ||
+        !work) {
+      (void)hipGetLastError();
+      return FFTPL_E_NOMEM;
+    }
+    e = launch_wa_fixed(num_nets, net_ptr, pin_cell, pin_dx, pin_dy, num_cells, x, y, gamma,
+                        wl_model, accumulate, gx, gy, wa, hpwl, work, s);
+    const hipError_t f = hipFreeAsync(work, s);
+    if (e == hipSuccess) e = f;
+    return dev_status(e);
+  }
+  // no pins: zero gradients (unless accumulating) and zero totals
   if (!accumulate && num_cells > 0) {
     e = launch_fill(gx, nullptr, 0.0f, num_cells, s);
     if (e == hipSuccess) e = launch_fill(gy, nullptr, 0.0f, num_cells, s);
   }
   if (e == hipSuccess && wa) e = launch_fill_f64(wa, 0.0, 1, s);
   if (e == hipSuccess && hpwl) e = launch_fill_f64(hpwl, 0.0, 1, s);
-  if (e == hipSuccess)
-    e = launch_wa(num_nets, net_ptr, pin_cell, pin_dx, pin_dy, x, y, gamma, wl_model, gx, gy,
-                  wa, hpwl, s);
   return dev_status(e);
 }
 

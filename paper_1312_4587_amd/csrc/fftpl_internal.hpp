@@ -449,6 +449,17 @@ hipError_t launch_wa(int num_nets, const int32_t* net_ptr, const int32_t* pin_ce
                      const float* pin_dx, const float* pin_dy, const float* x,
                      const float* y, float gamma, int wl_model, float* gx, float* gy,
                      double* wa_out, double* hp_out, hipStream_t s);
+// The stateless wirelength gradient with order-independent sums: per-pin
+// gradients added to per-cell 64-bit fixed-point accumulators, then written
+// (accumulate = 0) or added to gx, gy; wa_out / hp_out (if set) get the
+// totals from per-block partials summed in a fixed order.  work: at least
+// wa_fixed_work_bytes(num_cells, num_nets) bytes, 8-byte aligned.
+size_t wa_fixed_work_bytes(int num_cells, int num_nets);
+hipError_t launch_wa_fixed(int num_nets, const int32_t* net_ptr, const int32_t* pin_cell,
+                           const float* pin_dx, const float* pin_dy, int num_cells,
+                           const float* x, const float* y, float gamma, int wl_model,
+                           int accumulate, float* gx, float* gy, double* wa_out,
+                           double* hp_out, void* work, hipStream_t s);
 // wa: per-block wirelength partials laid out [W~ (n_s), HPWL (n_s), W~ (n_b),
 // HPWL (n_b)] (or null: W~ and HPWL are left as they are).
 // The evaluation's scalars from per-block partials, summed in double in a

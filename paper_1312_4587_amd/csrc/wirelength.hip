@@ -13,9 +13,14 @@
 // One thread per net for degree <= kSmallDeg (the bulk of every netlist);
 // larger nets found in a wavefront are processed by the whole wavefront
 // cooperatively, one after another.  The W~ and HPWL totals are reduced in
-// double.  Two ways to hand the per-pin gradients to the cells:
-//   ATOMIC: float atomics into gx, gy (stateless; each atomic costs about as
-//           much as a random cache-line transfer, two per pin);
+// double.  Three ways to hand the per-pin gradients to the cells:
+//   ATOMIC: float atomics into gx, gy (the float-atomic evaluation path; each
+//           atomic costs about as much as a random cache-line transfer, two
+//           per pin);
+//   FIXED:  64-bit integer atomics of the gradients in fixed point (units of
+//           2^-32, exact for every component of magnitude >= 2^-9) into
+//           per-cell accumulators, converted once per cell: the sums do not
+//           depend on the order of the adds (the stateless calls);
 //   SLOTS:  each pin's (gx, gy) is stored at its slot in a cell-major copy of
 //           the pins (one random 8-byte write per pin); the cell pass then sums
 //           contiguous slots.  Positions come interleaved as float2 so the
@@ -29,7 +34,11 @@ namespace fftpl {
 constexpr int kSmallDeg = 8;
 constexpr int kBigRegs = 16;   // pins per lane kept in registers for one wave's net
 
-template <bool SLOTS>
+constexpr int kIoAtomic = 0, kIoSlots = 1, kIoFixed = 2;
+constexpr float kFixScale = 4294967296.0f;   // 2^32
+constexpr float kFixLimit = 1073741824.0f;   // 2^30: far above any pin gradient
+
+template <int IO>
 struct PinIO {
   const float* x;
   const float* y;
@@ -38,13 +47,23 @@ struct PinIO {
   float* gx;
   float* gy;
   float2* pin_grad;
+  unsigned long long* fx = nullptr;   // FIXED: per-cell sums (2^-32 units)
+  unsigned long long* fy = nullptr;
+  unsigned int* bad = nullptr;        // FIXED: a non-finite (or absurd) pin gradient
   __device__ __forceinline__ float2 pos(int c) const {
-    if (SLOTS) return xy[c];
+    if (IO == kIoSlots) return xy[c];
     return make_float2(x[c], y[c]);
   }
   __device__ __forceinline__ void put(int p, int c, float vx, float vy) const {
-    if (SLOTS) {
+    if (IO == kIoSlots) {
       pin_grad[slot[p]] = make_float2(vx, vy);
+    } else if (IO == kIoFixed) {
+      if (fabsf(vx) <= kFixLimit && fabsf(vy) <= kFixLimit) {
+        atomicAdd(&fx[c], (unsigned long long)__float2ll_rn(vx * kFixScale));
+        atomicAdd(&fy[c], (unsigned long long)__float2ll_rn(vy * kFixScale));
+      } else {
+        atomicOr(&bad[c], 1u);
+      }
     } else {
       unsafeAtomicAdd(&gx[c], vx);
       unsafeAtomicAdd(&gy[c], vy);
@@ -54,11 +73,11 @@ struct PinIO {
 
 // PART 0: nets of degree <= kSmallDeg; 1: larger nets.  LSE: the log-sum-exp
 // model instead of the weighted average (same sums, pin_wl_grad / net_wl_value).
-template <bool SLOTS, int PART, bool LSE>
+template <int IO, int PART, bool LSE>
 __global__ void __launch_bounds__(256)
     k_wa(int num_nets, const int32_t* __restrict__ net_ptr,
          const int32_t* __restrict__ pin_cell, const float* __restrict__ pin_dx,
-         const float* __restrict__ pin_dy, PinIO<SLOTS> io, float gamma, float inv_gamma,
+         const float* __restrict__ pin_dy, PinIO<IO> io, float gamma, float inv_gamma,
          double* __restrict__ wa_out, double* __restrict__ hp_out,
          double* __restrict__ part) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -116,7 +135,7 @@ __global__ void __launch_bounds__(256)
     acc_wa = net_wl_value<LSE>(mx, lx, wpx, wmx, sx.sp, sx.sm, gamma) +
              net_wl_value<LSE>(my, ly, wpy, wmy, sy.sp, sy.sm, gamma);
     acc_hp = (double)(mx - lx) + (double)(my - ly);
-  } else if (SLOTS && PART == 0 && deg == 1) {
+  } else if (IO == kIoSlots && PART == 0 && deg == 1) {
     io.put(p0, 0, 0.0f, 0.0f);   // a one-pin net has no wirelength: its slot holds zero
   }
 
@@ -261,18 +280,18 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-template <bool SLOTS, bool LSE>
+template <int IO, bool LSE>
 hipError_t launch_wa_parts(int num_nets, const int32_t* net_ptr, const int32_t* pin_cell,
-                           const float* pin_dx, const float* pin_dy, PinIO<SLOTS> io,
+                           const float* pin_dx, const float* pin_dy, PinIO<IO> io,
                            float gamma, double* wa_out, double* hp_out, double* part,
                            hipStream_t s, Plan* tp) {
   const int nblk = (num_nets + 255) / 256;
-  hipLaunchKernelGGL((k_wa<SLOTS, 0, LSE>), dim3(nblk), dim3(256), 0, s, num_nets, net_ptr,
+  hipLaunchKernelGGL((k_wa<IO, 0, LSE>), dim3(nblk), dim3(256), 0, s, num_nets, net_ptr,
                      pin_cell, pin_dx, pin_dy, io, gamma, 1.0f / gamma, wa_out, hp_out, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (tp) plan_mark(*tp, "k_wa_slots_small", s);
-  hipLaunchKernelGGL((k_wa<SLOTS, 1, LSE>), dim3(wa_big_grid(num_nets)), dim3(256), 0, s,
+  hipLaunchKernelGGL((k_wa<IO, 1, LSE>), dim3(wa_big_grid(num_nets)), dim3(256), 0, s,
                      num_nets, net_ptr, pin_cell, pin_dx, pin_dy, io, gamma, 1.0f / gamma,
                      wa_out, hp_out, part ? part + 2 * (size_t)nblk : nullptr);
   e = hipGetLastError();
@@ -285,12 +304,70 @@ hipError_t launch_wa(int num_nets, const int32_t* net_ptr, const int32_t* pin_ce
                      const float* y, float gamma, int wl_model, float* gx, float* gy,
                      double* wa_out, double* hp_out, hipStream_t s) {
   if (num_nets <= 0) return hipSuccess;
-  PinIO<false> io{x, y, nullptr, nullptr, gx, gy, nullptr};
+  PinIO<kIoAtomic> io{x, y, nullptr, nullptr, gx, gy, nullptr};
   return wl_model == FFTPL_WL_LSE
-             ? launch_wa_parts<false, true>(num_nets, net_ptr, pin_cell, pin_dx, pin_dy, io,
-                                            gamma, wa_out, hp_out, nullptr, s, nullptr)
-             : launch_wa_parts<false, false>(num_nets, net_ptr, pin_cell, pin_dx, pin_dy, io,
-                                             gamma, wa_out, hp_out, nullptr, s, nullptr);
+             ? launch_wa_parts<kIoAtomic, true>(num_nets, net_ptr, pin_cell, pin_dx, pin_dy,
+                                                io, gamma, wa_out, hp_out, nullptr, s, nullptr)
+             : launch_wa_parts<kIoAtomic, false>(num_nets, net_ptr, pin_cell, pin_dx, pin_dy,
+                                                 io, gamma, wa_out, hp_out, nullptr, s, nullptr);
+}
+
+// Per cell: the fixed-point sums back to float (NaN for a cell that had a
+// non-finite pin gradient), written or added to gx, gy.
+__global__ void __launch_bounds__(256)
+    k_fix_cells(int m, const unsigned long long* __restrict__ fx,
+                const unsigned long long* __restrict__ fy, const unsigned int* __restrict__ bad,
+                int accumulate, float* __restrict__ gx, float* __restrict__ gy) {
+  constexpr double unit = 1.0 / 4294967296.0;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < m; c += gridDim.x * blockDim.x) {
+    const bool b = bad[c] != 0u;
+    const float vx = b ? __builtin_nanf("") : (float)((double)(long long)fx[c] * unit);
+    const float vy = b ? __builtin_nanf("") : (float)((double)(long long)fy[c] * unit);
+    gx[c] = accumulate ? gx[c] + vx : vx;
+    gy[c] = accumulate ? gy[c] + vy : vy;
+  }
+}
+
+size_t wa_fixed_work_bytes(int num_cells, int num_nets) {
+  const size_t parts = 2 * ((size_t)(num_nets + 255) / 256 + (size_t)wa_big_grid(num_nets));
+  return 16 * (size_t)num_cells + 4 * (size_t)num_cells + 8 * parts + 256;
+}
+
+hipError_t launch_wa_fixed(int num_nets, const int32_t* net_ptr, const int32_t* pin_cell,
+                           const float* pin_dx, const float* pin_dy, int num_cells,
+                           const float* x, const float* y, float gamma, int wl_model,
+                           int accumulate, float* gx, float* gy, double* wa_out,
+                           double* hp_out, void* work, hipStream_t s) {
+  // work: fx, fy [m] (u64), W~/HPWL partials, bad [m] (u32), cleared first
+  char* w = static_cast<char*>(work);
+  unsigned long long* fx = reinterpret_cast<unsigned long long*>(w);
+  unsigned long long* fy = fx + num_cells;
+  double* part = reinterpret_cast<double*>(fy + num_cells);
+  const int nblk = (num_nets + 255) / 256, nbig = wa_big_grid(num_nets);
+  unsigned int* bad = reinterpret_cast<unsigned int*>(part + 2 * ((size_t)nblk + nbig));
+  const int64_t words = (16 * (int64_t)num_cells + 4 * (int64_t)num_cells) / 4 +
+                        4 * ((int64_t)nblk + nbig);
+  hipError_t e = launch_zero_i32(reinterpret_cast<int32_t*>(work), words, s);
+  if (e != hipSuccess) return e;
+  PinIO<kIoFixed> io{x, y, nullptr, nullptr, nullptr, nullptr, nullptr, fx, fy, bad};
+  e = wl_model == FFTPL_WL_LSE
+          ? launch_wa_parts<kIoFixed, true>(num_nets, net_ptr, pin_cell, pin_dx, pin_dy, io,
+                                            gamma, nullptr, nullptr, part, s, nullptr)
+          : launch_wa_parts<kIoFixed, false>(num_nets, net_ptr, pin_cell, pin_dx, pin_dy, io,
+                                             gamma, nullptr, nullptr, part, s, nullptr);
+  if (e != hipSuccess) return e;
+  if (num_cells > 0) {
+    int blocks = (num_cells + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_fix_cells, dim3(blocks), dim3(256), 0, s, num_cells, fx, fy, bad,
+                       accumulate, gx, gy);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  // the totals from the per-block partials in a fixed order
+  if (wa_out || hp_out)
+    e = launch_eval_finalize(nullptr, 0, nullptr, 0, part, nblk, nbig, nullptr, wa_out, hp_out,
+                             nullptr, s);
+  return e;
 }
 
 hipError_t launch_wa_pins(int num_nets, const int32_t* net_ptr, const int32_t* pin_cell,
@@ -298,12 +375,12 @@ hipError_t launch_wa_pins(int num_nets, const int32_t* net_ptr, const int32_t* p
                           const int32_t* pin_slot, float gamma, int wl_model,
                           float2* pin_grad, double* wa_part, hipStream_t s, Plan* tp) {
   if (num_nets <= 0) return hipSuccess;
-  PinIO<true> io{nullptr, nullptr, xy, pin_slot, nullptr, nullptr, pin_grad};
+  PinIO<kIoSlots> io{nullptr, nullptr, xy, pin_slot, nullptr, nullptr, pin_grad};
   return wl_model == FFTPL_WL_LSE
-             ? launch_wa_parts<true, true>(num_nets, net_ptr, pin_cell, pin_dx, pin_dy, io,
-                                           gamma, nullptr, nullptr, wa_part, s, tp)
-             : launch_wa_parts<true, false>(num_nets, net_ptr, pin_cell, pin_dx, pin_dy, io,
-                                            gamma, nullptr, nullptr, wa_part, s, tp);
+             ? launch_wa_parts<kIoSlots, true>(num_nets, net_ptr, pin_cell, pin_dx, pin_dy, io,
+                                               gamma, nullptr, nullptr, wa_part, s, tp)
+             : launch_wa_parts<kIoSlots, false>(num_nets, net_ptr, pin_cell, pin_dx, pin_dy,
+                                                io, gamma, nullptr, nullptr, wa_part, s, tp);
 }
 
 // The evaluation's scalars (FinalArgs) by one block, when no gather runs.

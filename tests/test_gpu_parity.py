@@ -283,6 +283,15 @@ def test_wa_grad(F, which):
     assert rel_l2(host(gx), rx) < RTOL and rel_l2(host(gy), ry) < RTOL
     assert abs(float(host(wa)[0]) - W0) <= RTOL * W0
     assert abs(float(host(hp)[0]) - H0) <= RTOL * H0
+    # fixed-point per-cell sums and fixed-order totals: the same bits again
+    gx2, gy2 = torch.empty_like(gx), torch.empty_like(gy)
+    wa2 = torch.zeros(1, dtype=torch.float64, device="cuda")
+    hp2 = torch.zeros(1, dtype=torch.float64, device="cuda")
+    F.wa_grad(dev(inst.net_ptr), dev(inst.pin_cell), dev(inst.pin_dx), dev(inst.pin_dy),
+              c.x, c.y, gamma, 0, gx2, gy2, wa2, hp2)
+    torch.cuda.synchronize()
+    assert torch.equal(gx, gx2) and torch.equal(gy, gy2)
+    assert torch.equal(wa, wa2) and torch.equal(hp, hp2)
     F.wa_grad(dev(inst.net_ptr), dev(inst.pin_cell), dev(inst.pin_dx), dev(inst.pin_dy),
               c.x, c.y, gamma, 1, gx, gy, None, None)
     assert rel_l2(host(gx), 2 * rx) < RTOL
