@@ -32,23 +32,23 @@ PMC_FETCH_SCALE, PMC_WRITE_SCALE = 2.0, 1.0
 PMC_TRAFFIC = {
     # kernel: (source files, sha1, FETCH_SIZE KiB, WRITE_SIZE KiB)
     "k_band_place": (("band_scatter.hip", "fftpl_internal.hpp"),
-        "329608cc56474b6c23ba3bde17ae6854273be028", 16523.1, 64737.1),
+        "363d6c18c810a50f8ba1358a41d225290199574c", 16523.6, 64791.1),
     "k_xch_spread": (("exchange.hip", "fftpl_internal.hpp"),
-        "cea68045c6f9232b0afa2bc18d426f226fdd52f8", 28609.5, 96892.5),
+        "aa1810760312d0fe8d4d95a86c95e7764cd01c4a", 28609.1, 96907.1),
     "k_band_accum": (("band_scatter.hip", "fftpl_internal.hpp"),
-        "329608cc56474b6c23ba3bde17ae6854273be028", 27911.0, 4096.0),
+        "363d6c18c810a50f8ba1358a41d225290199574c", 27911.0, 4096.0),
     "k_xch_wa": (("exchange.hip", "fftpl_internal.hpp"),
-        "cea68045c6f9232b0afa2bc18d426f226fdd52f8", 178947.9, 112289.3),
+        "aa1810760312d0fe8d4d95a86c95e7764cd01c4a", 178984.5, 112289.7),
     "k_rows_dct2": (("spectral_fft.hip", "fftpl_internal.hpp"),
-        "23eae4c941a6d65eb46b253566152ecf748c8596", 6235.7, 4112.0),
+        "63506664793af2e33294635574c5e783f13c917a", 6235.8, 4112.0),
     "k_cols_solve": (("spectral_fft.hip", "fftpl_internal.hpp"),
-        "23eae4c941a6d65eb46b253566152ecf748c8596", 2180.5, 8192.0),
+        "63506664793af2e33294635574c5e783f13c917a", 2180.6, 8192.0),
     "k_rows_inverse": (("spectral_fft.hip", "fftpl_internal.hpp"),
-        "23eae4c941a6d65eb46b253566152ecf748c8596", 6264.1, 8196.0),
+        "63506664793af2e33294635574c5e783f13c917a", 6264.1, 8196.0),
     "k_band_gather": (("band_scatter.hip", "fftpl_internal.hpp"),
-        "329608cc56474b6c23ba3bde17ae6854273be028", 30993.6, 20998.0),
+        "363d6c18c810a50f8ba1358a41d225290199574c", 30994.6, 21000.0),
     "k_xch_cellsum": (("exchange.hip", "fftpl_internal.hpp"),
-        "cea68045c6f9232b0afa2bc18d426f226fdd52f8", 80800.3, 16406.5),
+        "aa1810760312d0fe8d4d95a86c95e7764cd01c4a", 80868.2, 16406.5),
 }
 
 
