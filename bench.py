@@ -265,7 +265,14 @@ def kernel_bytes(inst, nent):
 
 
 def gemm_flops(n):
-    """Multiply-add flops (2 per MAC) of each GEMM of the matrix-core solve."""
+    """Multiply-add flops (2 per MAC) each step of the matrix-core solve
+    executes (field mode).  With n a multiple of 128 the products are split
+    into even and odd frequencies: [Sx Ke^T | Dx Ko^T] and [Ke Sy ; Ko Dy]
+    (2 x n (n/2)^2 MACs each), U and V (4 x n (n/2)^2), psi, Ey and Ex (6 x n
+    (n/2)^2), 3.5 n^3 MACs in all; otherwise the five dense products, 7 n^3."""
+    if n % 128 == 0:
+        return {"k_gemm_w": n ** 3, "k_gemm_g": n ** 3, "k_gemm_uv": 2 * n ** 3,
+                "k_gemm_psi_ey": 3 * n ** 3}
     return {"k_gemm_w": 2 * n ** 3, "k_gemm_g": 2 * n ** 3, "k_gemm_uv": 4 * n ** 3,
             "k_gemm_psi_ey": 4 * n ** 3, "k_gemm_ex": 2 * n ** 3}
 
@@ -294,7 +301,7 @@ def stage_bytes(inst):
 STAGE_KERNELS = {
     "a2_scatter": ("k_band_place", "k_band_accum", "k_fill", "k_scatter"),
     "a3_a5_spectral": ("k_rows_dct2", "k_cols_solve", "k_rows_inverse", "k_gemm_rowsum",
-                       "k_gemm_prep", "k_gemm_w", "k_gemm_g", "k_gemm_uv",
+                       "k_gemm_prep", "k_gemm_w", "k_gemm_bfly", "k_gemm_g", "k_gemm_uv",
                        "k_gemm_psi_ey", "k_gemm_ex"),
     "a6_gather": ("k_band_gather", "k_gather", "k_gather_pins"),
     "a8_wirelength": ("k_xch_spread", "k_xch_wa", "k_xch_cellsum", "k_interleave",

@@ -10,7 +10,9 @@
 //                                       frequency-weighted sine for Ex)
 //   [psi ; Ey]  = [K^T ; Sw^T] U       (inverse along y)
 //   Ex          = K^T V
-// 7 n^3 multiply-adds in all.  Two precisions:
+// 7 n^3 multiply-adds in all as written; with n a multiple of 128 and the
+// fields (not the differences) wanted, the even/odd symmetry of K and Sw
+// halves that (the split products, below run_gemm_split).  Two precisions:
 //   FP32:   v_mfma_f32_16x16x4_f32 on float32 operands;
 //   BF16X3: every float32 operand X is split into bf16 hi = bf16(X) and
 //           lo = bf16(X - hi); each product is Ah Bh + Ah Bl + Al Bh on
@@ -36,21 +38,39 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 constexpr int TM = 64, TN = 64, TK = 32;
 
-enum EpiMode { EPI_F32 = 0, EPI_SPLIT = 1, EPI_SPLIT_T = 2, EPI_PSI_EY = 3, EPI_EX = 4 };
+// EPI_F32_T: float32 stored transposed.  EPI_DUAL_X / EPI_DUAL_Y (dual
+// products, see GemmArgs): P1 + P2 at (row, col) and dsign (P1 - P2) at the
+// mirrored column n - 1 - col (X) or row n - 1 - row (Y).
+enum EpiMode {
+  EPI_F32 = 0, EPI_SPLIT = 1, EPI_SPLIT_T = 2, EPI_PSI_EY = 3, EPI_EX = 4, EPI_F32_T = 5,
+  EPI_DUAL_X = 6, EPI_DUAL_Y = 7
+};
 
 struct GemmArgs {
-  const void* a_hi;   // A [M][K] row-major (float32, or bf16 hi)
-  const void* a_lo;   // bf16 lo of A
-  int lda;
-  const void* b_hi;   // float32: B [K][N] row-major; bf16: B^T [N][K] row-major
-  const void* b_lo;
-  int ldb;
-  int M, N, K;
+  const void* a_hi = nullptr;   // A [M][K] row-major (float32, or bf16 hi)
+  const void* a_lo = nullptr;   // bf16 lo of A
+  int lda = 0;
+  const void* b_hi = nullptr;   // float32: B [K][N] row-major; bf16: B^T [N][K] row-major
+  const void* b_lo = nullptr;
+  int ldb = 0;
+  int M = 0, N = 0, K = 0;
+  // dual: a second product P2 = A2 B2 of the same shape (same leading
+  // dimensions) beside P1 = A B; the block's two K halves run one each and
+  // the epilogue receives P1 + P2 and P1 - P2 (the even/odd butterfly)
+  int dual = 0;
+  const void* a2_hi = nullptr;
+  const void* a2_lo = nullptr;
+  const void* b2_hi = nullptr;
+  const void* b2_lo = nullptr;
 };
 
 struct Epi {
   int mode = EPI_F32;
-  int spectral = 0;   // scale element (row v, col u) by c_u c_v / (n^2 (w_u^2 + w_v^2 + eps))
+  // 1: scale element (row v, col u) by c_u c_v / (n^2 (w_u^2 + w_v^2 + eps));
+  // 2: the same for an even/odd split product, row b being v = 2 b + vpar
+  // and column u' being u = 2 u' (u' < n/2) or 2 (u' - n/2) + 1
+  int spectral = 0;
+  int vpar = 0;
   float eps = 0.0f;
   int n = 0;
   const float* wf = nullptr;
@@ -64,6 +84,18 @@ struct Epi {
   float* exy = nullptr;
   const float* rho = nullptr;
   double* en_part = nullptr;
+  int en_slots = 1;       // energy partials per block: the sum, then zeros
+  float dsign = 1.0f;     // dual: the mirrored output is dsign (P1 - P2)
+  float* f = nullptr;     // EPI_DUAL_Y: the map written (psi, Ex or Ey)
+  int exy_off = -1;       // EPI_DUAL_Y: also exy[2 o + exy_off] (0: Ex, 1: Ey)
+};
+
+constexpr int kGemmMaxProb = 3;
+// Up to kGemmMaxProb products of one shape in one launch (blockIdx.y).
+struct GemmBatch {
+  int count = 1;
+  GemmArgs g[kGemmMaxProb];
+  Epi ep[kGemmMaxProb];
 };
 
 __device__ __forceinline__ void split_bf16(float v, __bf16& hi, __bf16& lo) {
@@ -71,13 +103,99 @@ __device__ __forceinline__ void split_bf16(float v, __bf16& hi, __bf16& lo) {
   lo = (__bf16)(v - (float)hi);
 }
 
+// One element of a product's result: optional spectral scaling, then the
+// store the step needs (see EpiMode); en gathers rho * psi for the energy.
+__device__ __forceinline__ void epi_store(const Epi& ep, int row, int col, float v, double& en) {
+  const int n = ep.n;
+  if (ep.spectral) {
+    const float inv_n2 = 1.0f / ((float)n * (float)n);
+    int u = col, w = row;
+    if (ep.spectral == 2) {
+      const int h = n / 2;
+      w = 2 * row + ep.vpar;
+      u = col < h ? 2 * col : 2 * (col - h) + 1;
+    }
+    const float wu = ep.wf[u], wv = ep.wf[w];
+    const float cu = u ? 2.0f : 1.0f, cv = w ? 2.0f : 1.0f;
+    v = (w == 0 && u == 0) ? 0.0f : v * (cu * cv * inv_n2) / (wu * wu + wv * wv + ep.eps);
+  }
+  if (ep.mode == EPI_F32) {
+    ep.out[(size_t)row * ep.ldo + col] = v;
+  } else if (ep.mode == EPI_F32_T) {
+    ep.out[(size_t)col * ep.ldo + row] = v;
+  } else if (ep.mode == EPI_SPLIT || ep.mode == EPI_SPLIT_T) {
+    __bf16 h, l;
+    split_bf16(v, h, l);
+    const size_t o =
+        ep.mode == EPI_SPLIT ? (size_t)row * ep.ldo + col : (size_t)col * ep.ldo + row;
+    ep.hi[o] = h;
+    ep.lo[o] = l;
+  } else if (ep.mode == EPI_PSI_EY) {
+    if (row < n) {
+      const size_t o = (size_t)row * n + col;
+      if (ep.psi) ep.psi[o] = v;
+      if (ep.rho) en += (double)ep.rho[o] * v;
+    } else {
+      const size_t o = (size_t)(row - n) * n + col;
+      if (ep.ey) ep.ey[o] = v;
+      if (ep.exy) ep.exy[2 * o + 1] = v;
+    }
+  } else {   // EPI_EX
+    const size_t o = (size_t)row * n + col;
+    if (ep.ex) ep.ex[o] = v;
+    if (ep.exy) ep.exy[2 * o] = v;
+  }
+}
+
+// The two outputs of a dual product's element (row, col): vs = P1 + P2 there,
+// dsign vd = dsign (P1 - P2) at the mirrored column (EPI_DUAL_X: bf16 hi/lo
+// stored transposed, or float32 row-major) or row (EPI_DUAL_Y: n x n maps).
+__device__ __forceinline__ void epi_store_dual(const Epi& ep, int row, int col, float vs,
+                                               float vd, double& en) {
+  const int n = ep.n;
+  const float v2 = ep.dsign * vd;
+  if (ep.mode == EPI_DUAL_X) {
+    const int c2 = n - 1 - col;
+    if (ep.hi) {
+      __bf16 h, l;
+      split_bf16(vs, h, l);
+      ep.hi[(size_t)col * ep.ldo + row] = h;
+      ep.lo[(size_t)col * ep.ldo + row] = l;
+      split_bf16(v2, h, l);
+      ep.hi[(size_t)c2 * ep.ldo + row] = h;
+      ep.lo[(size_t)c2 * ep.ldo + row] = l;
+    } else {
+      ep.out[(size_t)row * ep.ldo + col] = vs;
+      ep.out[(size_t)row * ep.ldo + c2] = v2;
+    }
+  } else {   // EPI_DUAL_Y
+    const size_t o1 = (size_t)row * n + col, o2 = (size_t)(n - 1 - row) * n + col;
+    if (ep.f) {
+      ep.f[o1] = vs;
+      ep.f[o2] = v2;
+    }
+    if (ep.exy) {
+      ep.exy[2 * o1 + ep.exy_off] = vs;
+      ep.exy[2 * o2 + ep.exy_off] = v2;
+    }
+    if (ep.rho) en += (double)ep.rho[o1] * vs + (double)ep.rho[o2] * v2;
+  }
+}
+
 // KS x 4 waves: wave w works on the 32 x 32 quarter (w & 3) of the tile over
 // the K part (w >> 2) of every K step of TKB = KS * 32; with KS = 2 the two
 // parts' partial tiles are added through LDS before the epilogue (in a fixed
 // order).  KS = 2 doubles the waves per CU for grids of one block per CU.
 template <bool BF16, int KS>
-__global__ void __launch_bounds__(256 * KS) k_gemm(GemmArgs g, Epi ep) {
+__global__ void __launch_bounds__(256 * KS) k_gemm(GemmBatch gb) {
+  const GemmArgs& g = gb.g[blockIdx.y];
+  const Epi& ep = gb.ep[blockIdx.y];
   constexpr int TKB = KS * TK;
+  // dual (KS = 2 only): each K step holds TK of the first product, then TK of
+  // the second, so the wavefronts of K half 0 run P1 and those of half 1 P2
+  const bool dual = KS == 2 && g.dual;
+  const int kstep = dual ? TK : TKB;   // K of each product per step
+  const int steps = g.K / kstep;
   // Each XCD runs a contiguous range of logical tiles (xcd_block); inside
   // it the tiles go down gsz rows of tiles before moving one column right, so
   // the range covers a compact patch whose A row panels and B column panels
@@ -113,14 +231,17 @@ __global__ void __launch_bounds__(256 * KS) k_gemm(GemmArgs g, Epi ep) {
     float(*As)[TKB][TM + 4] = reinterpret_cast<float(*)[TKB][TM + 4]>(smem);   // [buf][k][m]
     float(*Bs)[TKB][TN + 4] =
         reinterpret_cast<float(*)[TKB][TN + 4]>(smem + 2 * TKB * (TM + 4));   // [buf][k][n]
-    const float* A = static_cast<const float*>(g.a_hi);
-    const float* B = static_cast<const float*>(g.b_hi);
     const int ar = t / (TKB / 8), ak = (t % (TKB / 8)) * 8;   // A: row, first k of 8
     const int bk = t >> 3, bn = (t & 7) * 8;     // B: k, first n of 8
+    const bool a2 = dual && ak >= TK, b2 = dual && bk >= TK;
+    const float* A = static_cast<const float*>(a2 ? g.a2_hi : g.a_hi);
+    const float* B = static_cast<const float*>(b2 ? g.b2_hi : g.b_hi);
+    const int akc = a2 ? ak - TK : ak, bkr = b2 ? bk - TK : bk;
     float4 a0, a1, b0, b1;
-    auto fetch = [&](int k0) {
-      const float4* sa = reinterpret_cast<const float4*>(A + (size_t)(m0 + ar) * g.lda + k0 + ak);
-      const float4* sb = reinterpret_cast<const float4*>(B + (size_t)(k0 + bk) * g.ldb + n0 + bn);
+    auto fetch = [&](int s) {
+      const int k0 = s * kstep;
+      const float4* sa = reinterpret_cast<const float4*>(A + (size_t)(m0 + ar) * g.lda + k0 + akc);
+      const float4* sb = reinterpret_cast<const float4*>(B + (size_t)(k0 + bkr) * g.ldb + n0 + bn);
       a0 = sa[0];
       a1 = sa[1];
       b0 = sb[0];
@@ -142,9 +263,9 @@ __global__ void __launch_bounds__(256 * KS) k_gemm(GemmArgs g, Epi ep) {
     stash(0);
     __syncthreads();
     int cur = 0;
-    for (int k0 = 0; k0 < g.K; k0 += TKB) {
-      const bool more = k0 + TKB < g.K;
-      if (more) fetch(k0 + TKB);
+    for (int s = 0; s < steps; ++s) {
+      const bool more = s + 1 < steps;
+      if (more) fetch(s + 1);
 #pragma unroll
       for (int kk = 0; kk < TK; kk += 4) {
         const int kq = wk * TK + kk + lg;
@@ -172,26 +293,27 @@ __global__ void __launch_bounds__(256 * KS) k_gemm(GemmArgs g, Epi ep) {
     bf8(*Al)[TM][KCP] = Ah + 2;
     bf8(*Bh)[TN][KCP] = reinterpret_cast<bf8(*)[TN][KCP]>(Ah + 4);
     bf8(*Bl)[TN][KCP] = Bh + 2;
-    const __bf16* gah = static_cast<const __bf16*>(g.a_hi);
-    const __bf16* gal = static_cast<const __bf16*>(g.a_lo);
-    const __bf16* gbh = static_cast<const __bf16*>(g.b_hi);
-    const __bf16* gbl = static_cast<const __bf16*>(g.b_lo);
     const int r = t / KC, kc = t % KC;
+    const bool two = dual && kc >= KC / 2;   // this thread loads the second product
+    const __bf16* gah = static_cast<const __bf16*>(two ? g.a2_hi : g.a_hi);
+    const __bf16* gal = static_cast<const __bf16*>(two ? g.a2_lo : g.a_lo);
+    const __bf16* gbh = static_cast<const __bf16*>(two ? g.b2_hi : g.b_hi);
+    const __bf16* gbl = static_cast<const __bf16*>(two ? g.b2_lo : g.b_lo);
+    const int kcol = (two ? kc - KC / 2 : kc) * 8;
     // Operands of the next PRE K steps are in flight in registers while the
     // MFMAs of the current step run from LDS.  Register set j holds step
     // s0 + j and is refilled right after being stored to LDS.  The body has
     // no data-dependent branches (loads past the last step re-read the last
     // step, the store after the last step fills the idle buffer) so that
     // every wait is for the oldest loads only.
-    const int steps = g.K / TKB;
     const int kq = wk * (TK / 8) + lg;
     auto run = [&](auto pre) {
       constexpr int PRE = decltype(pre)::value;
       bf8 rah[PRE], ral[PRE], rbh[PRE], rbl[PRE];
       auto fetch = [&](int q, int step) {
-        const int k0 = min(step, steps - 1) * TKB;
-        const size_t oa = (size_t)(m0 + r) * g.lda + k0 + kc * 8;
-        const size_t ob = (size_t)(n0 + r) * g.ldb + k0 + kc * 8;
+        const int k0 = min(step, steps - 1) * kstep + kcol;
+        const size_t oa = (size_t)(m0 + r) * g.lda + k0;
+        const size_t ob = (size_t)(n0 + r) * g.ldb + k0;
         rah[q] = *reinterpret_cast<const bf8*>(gah + oa);
         ral[q] = *reinterpret_cast<const bf8*>(gal + oa);
         rbh[q] = *reinterpret_cast<const bf8*>(gbh + ob);
@@ -237,7 +359,9 @@ __global__ void __launch_bounds__(256 * KS) k_gemm(GemmArgs g, Epi ep) {
   }
 
   // the second K half's partial tile joins the first one's (waves 0-3 keep
-  // going to the epilogue; the loop's last barrier has freed the buffers)
+  // going to the epilogue; the loop's last barrier has freed the buffers);
+  // dual: acc = P1 + P2 and dif = P1 - P2
+  f4 dif[2][2];
   if (KS == 2) {
     f4* red = reinterpret_cast<f4*>(smem);   // [quarter][i][j][lane]
     if (wk == 1) {
@@ -251,14 +375,16 @@ __global__ void __launch_bounds__(256 * KS) k_gemm(GemmArgs g, Epi ep) {
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] += red[((wq * 2 + i) * 2 + j) * kWave + lane];
+        for (int j = 0; j < 2; ++j) {
+          const f4 o = red[((wq * 2 + i) * 2 + j) * kWave + lane];
+          dif[i][j] = acc[i][j] - o;
+          acc[i][j] += o;
+        }
     }
   }
 
   // Epilogue (waves 0-3).  Lane l of a 16x16 tile holds column l%16, rows
   // 4*(l/16)+r.
-  const int n = ep.n;
-  const float inv_n2 = 1.0f / ((float)n * (float)n);
   double en = 0.0;
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
@@ -269,40 +395,18 @@ __global__ void __launch_bounds__(256 * KS) k_gemm(GemmArgs g, Epi ep) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = m0 + wm + 16 * i + 4 * lg + r;
-        float v = acc[i][j][r];
-        if (ep.spectral) {
-          const float wu = ep.wf[col], wv = ep.wf[row];
-          const float cu = col ? 2.0f : 1.0f, cv = row ? 2.0f : 1.0f;
-          v = (row == 0 && col == 0) ? 0.0f : v * (cu * cv * inv_n2) / (wu * wu + wv * wv + ep.eps);
-        }
-        if (ep.mode == EPI_F32) {
-          ep.out[(size_t)row * ep.ldo + col] = v;
-        } else if (ep.mode == EPI_SPLIT || ep.mode == EPI_SPLIT_T) {
-          __bf16 h, l;
-          split_bf16(v, h, l);
-          const size_t o = ep.mode == EPI_SPLIT ? (size_t)row * ep.ldo + col
-                                                : (size_t)col * ep.ldo + row;
-          ep.hi[o] = h;
-          ep.lo[o] = l;
-        } else if (ep.mode == EPI_PSI_EY) {
-          if (row < n) {
-            const size_t o = (size_t)row * n + col;
-            if (ep.psi) ep.psi[o] = v;
-            if (ep.rho) en += (double)ep.rho[o] * v;
-          } else {
-            const size_t o = (size_t)(row - n) * n + col;
-            if (ep.ey) ep.ey[o] = v;
-            if (ep.exy) ep.exy[2 * o + 1] = v;
-          }
-        } else {   // EPI_EX
-          const size_t o = (size_t)row * n + col;
-          if (ep.ex) ep.ex[o] = v;
-          if (ep.exy) ep.exy[2 * o] = v;
-        }
+        if (dual)
+          epi_store_dual(ep, row, col, acc[i][j][r], dif[i][j][r], en);
+        else
+          epi_store(ep, row, col, acc[i][j][r], en);
       }
     }
   }
-  if (ep.mode == EPI_PSI_EY && ep.en_part) block_sum_to<false>(en, &ep.en_part[lt]);
+  if ((ep.mode == EPI_PSI_EY || ep.mode == EPI_DUAL_Y) && ep.en_part) {
+    double* slot = ep.en_part + (size_t)lt * ep.en_slots;
+    block_sum_to<false>(en, slot);
+    if (t > 0 && t < ep.en_slots) slot[t] = 0.0;
+  }
 }
 
 // Row sums of rho in double, and the per-row overflow pairs (overflow,
@@ -355,6 +459,59 @@ __global__ void __launch_bounds__(256)
       lo[i] = l;
     } else {
       out[i] = v;
+    }
+  }
+}
+
+// Even/odd butterfly for the split products.  Columns (ROWS = false): for
+// every row r and i < n/2, S[r][i] = v(r, i) + v(r, n-1-i) and D[r][i] =
+// v(r, i) - v(r, n-1-i), [n][n/2]; rows (ROWS = true): S[r][c] = v(r, c) +
+// v(n-1-r, c), D likewise, r < n/2, [n/2][n].  v = in - mean, the mean taken
+// from the double row sums when rowsum is given (else 0).  float32 (s32,
+// d32) or bf16 hi/lo (sh, sl, dh, dl).
+template <bool BF16, bool ROWS>
+__global__ void __launch_bounds__(256)
+    k_gemm_bfly(const float* __restrict__ in, int n, const double* __restrict__ rowsum,
+                float* __restrict__ s32, float* __restrict__ d32, __bf16* __restrict__ sh,
+                __bf16* __restrict__ sl, __bf16* __restrict__ dh, __bf16* __restrict__ dl) {
+  float mean = 0.0f;
+  if (rowsum) {
+    __shared__ double red[4];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) s += rowsum[i];
+    s = wave_sum(s);
+    if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = s;
+    __syncthreads();
+    mean = (float)((red[0] + red[1] + red[2] + red[3]) / ((double)n * n));
+  }
+  const int h = n / 2;
+  const size_t total = (size_t)n * h;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    float v1, v2;
+    if (ROWS) {
+      const size_t r = e / n, c = e % n;
+      v1 = in[r * n + c];
+      v2 = in[(n - 1 - r) * n + c];
+    } else {
+      const size_t r = e / h, i = e % h;
+      v1 = in[r * n + i];
+      v2 = in[r * n + (n - 1 - i)];
+    }
+    v1 -= mean;
+    v2 -= mean;
+    const float sv = v1 + v2, dv = v1 - v2;
+    if (BF16) {
+      __bf16 a, b;
+      split_bf16(sv, a, b);
+      sh[e] = a;
+      sl[e] = b;
+      split_bf16(dv, a, b);
+      dh[e] = a;
+      dl[e] = b;
+    } else {
+      s32[e] = sv;
+      d32[e] = dv;
     }
   }
 }
@@ -432,15 +589,273 @@ GemmLayout gemm_layout(int n) {
   return L;
 }
 
+// The even/odd split of the products (n a multiple of 128, fields rather
+// than differences).  With h = n/2, the cosine rows of even and odd
+// frequency restricted to the first h samples, Ke[a][i] = K[2a][i] and
+// Ko[a][i] = K[2a+1][i] (K[u][n-1-i] = (-1)^u K[u][i]), and the same for Sw
+// (Sw[u][n-1-i] = (-1)^(u+1) Sw[u][i]), turn every n-point transform into two
+// h-point products and a butterfly: half the multiply-adds and operand bytes.
+// Frequencies are kept in the order (even | odd) between the steps.
+//   W'  = [Sx Ke^T | Dx Ko^T]       Sx, Dx = R left half +/- mirrored right half
+//   G'  = scale([Ke Sy ; Ko Dy])    Sy, Dy = W' top half +/- mirrored bottom half
+//   U'  = G'_e Ke + G'_o Ko | mirror(G'_e Ke - G'_o Ko)      (columns)
+//   V'  = G'_e Swe + G'_o Swo | mirror(G'_o Swo - G'_e Swe)
+//   psi = Ke^T U'_e + Ko^T U'_o ; mirror(Ke^T U'_e - Ko^T U'_o)   (rows)
+//   Ey  = Swe^T U'_e + Swo^T U'_o ; mirror(Swo^T U'_o - Swe^T U'_e)
+//   Ex  = Ke^T V'_e + Ko^T V'_o ; mirror(Ke^T V'_e - Ko^T V'_o)
+// (_e, _o: the first and second h frequency rows or columns).  Each pair of
+// half products sharing an output runs as one dual product (GemmArgs).
+bool gemm_split(int n) { return n % 128 == 0; }
+
+struct SplitLayout {
+  size_t hh, nh;
+  // tables after the dense ones, h x h each; float32: Ke, Ko, Swe, Swo and
+  // their transposes; bf16 (hi, then lo at + 2 hh bytes): Ke, Ko, KeT, KoT,
+  // SweT, SwoT
+  size_t t_ke, t_ko, t_ket, t_kot, t_swe, t_swo, t_swet, t_swot;
+  size_t b_ke, b_ko, b_ket, b_kot, b_swet, b_swot;
+  size_t tables_bytes;
+  // workspace; float32: Sx, Dx [n][h], W' [n][n], Sy, Dy [h][n], G', U', V'
+  // [n][n]; bf16 (hi, then lo at + half the region): Sx, Dx [n][h], W'^T
+  // float32 [n][n], Sy^T, Dy^T [n][h], G' [n][n], [U' | V']^T [2n][n]
+  size_t w_sx, w_dx, w_w, w_sy, w_dy, w_g, w_u, w_v;
+  size_t v_sx, v_dx, v_wt, v_syt, v_dyt, v_g, v_uvt;
+  size_t ws_bytes;
+};
+
+SplitLayout split_layout(int n) {
+  SplitLayout S;
+  const size_t h = (size_t)n / 2, nn = (size_t)n * n;
+  S.hh = h * h;
+  S.nh = (size_t)n * h;
+  const size_t t4 = 4 * S.hh;   // one float32 table, or one bf16 hi/lo pair
+  S.t_ke = 0;
+  S.t_ko = t4;
+  S.t_ket = 2 * t4;
+  S.t_kot = 3 * t4;
+  S.t_swe = 4 * t4;
+  S.t_swo = 5 * t4;
+  S.t_swet = 6 * t4;
+  S.t_swot = 7 * t4;
+  S.b_ke = 0;
+  S.b_ko = t4;
+  S.b_ket = 2 * t4;
+  S.b_kot = 3 * t4;
+  S.b_swet = 4 * t4;
+  S.b_swot = 5 * t4;
+  S.tables_bytes = 8 * t4;
+  S.w_sx = 0;
+  S.w_dx = 2 * nn;
+  S.w_w = 4 * nn;
+  S.w_sy = 8 * nn;
+  S.w_dy = 10 * nn;
+  S.w_g = 12 * nn;
+  S.w_u = 16 * nn;
+  S.w_v = 20 * nn;
+  S.v_sx = 0;
+  S.v_dx = 2 * nn;
+  S.v_wt = 4 * nn;
+  S.v_syt = 8 * nn;
+  S.v_dyt = 10 * nn;
+  S.v_g = 12 * nn;
+  S.v_uvt = 16 * nn;
+  S.ws_bytes = 24 * nn;
+  return S;
+}
+
+// One launch over gb.count products of one shape (grid.y = product).  Dual
+// products take the 512-thread form (two K halves); otherwise it is used
+// when the launch has one block per CU or fewer, so that each CU runs twice
+// the waves.
+template <bool BF16>
+hipError_t launch_gemm(const GemmBatch& gb, hipStream_t s) {
+  const GemmArgs& g = gb.g[0];
+  const int tiles = (g.M / TM) * (g.N / TN);
+  const dim3 grid(tiles, gb.count);
+  if (g.dual || tiles * gb.count <= 256)
+    hipLaunchKernelGGL((k_gemm<BF16, 2>), grid, dim3(512), 0, s, gb);
+  else
+    hipLaunchKernelGGL((k_gemm<BF16, 1>), grid, dim3(256), 0, s, gb);
+  return hipGetLastError();
+}
+
 template <bool BF16>
 hipError_t launch_gemm(const GemmArgs& g, const Epi& ep, hipStream_t s) {
-  // one block per CU or fewer: split K across twice the waves
-  const int blocks = (g.M / TM) * (g.N / TN);
-  if (blocks <= 256)
-    hipLaunchKernelGGL((k_gemm<BF16, 2>), dim3(blocks), dim3(512), 0, s, g, ep);
+  GemmBatch gb;
+  gb.count = 1;
+  gb.g[0] = g;
+  gb.ep[0] = ep;
+  return launch_gemm<BF16>(gb, s);
+}
+
+// The solve through the split products (after k_gemm_rowsum).
+template <bool BF16>
+hipError_t run_gemm_split(Plan& p, const SpectralArgs& a, hipStream_t s) {
+  const int n = p.n, h = n / 2;
+  const GemmLayout L = gemm_layout(n);
+  const SplitLayout S = split_layout(n);
+  const size_t nn = (size_t)n * n, nh = S.nh;
+  char* tb = static_cast<char*>(p.gemm_tables) + L.tables_bytes;
+  char* wb = static_cast<char*>(p.gemm_ws);
+  auto f32 = [&](size_t off) { return reinterpret_cast<float*>(wb + off); };
+  auto bfw = [&](size_t off) { return reinterpret_cast<__bf16*>(wb + off); };
+  auto bft = [&](size_t off) { return reinterpret_cast<const __bf16*>(tb + off); };
+  auto ft = [&](size_t off) { return reinterpret_cast<const float*>(tb + off); };
+  int pblocks = (int)((nh + 1023) / 1024);
+  if (pblocks > 4096) pblocks = 4096;
+  // Sx, Dx from R = rho - mean
+  if (BF16)
+    hipLaunchKernelGGL((k_gemm_bfly<true, false>), dim3(pblocks), dim3(256), 0, s, a.rho, n,
+                       p.rowsum, nullptr, nullptr, bfw(S.v_sx), bfw(S.v_sx) + nh, bfw(S.v_dx),
+                       bfw(S.v_dx) + nh);
   else
-    hipLaunchKernelGGL((k_gemm<BF16, 1>), dim3(blocks), dim3(256), 0, s, g, ep);
-  return hipGetLastError();
+    hipLaunchKernelGGL((k_gemm_bfly<false, false>), dim3(pblocks), dim3(256), 0, s, a.rho, n,
+                       p.rowsum, f32(S.w_sx), f32(S.w_dx), nullptr, nullptr, nullptr, nullptr);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  plan_mark(p, "k_gemm_prep", s);
+
+  // 1. W' = [Sx Ke^T | Dx Ko^T]   (bf16: stored transposed in float32)
+  GemmBatch gb;
+  gb.count = 2;
+  for (int q = 0; q < 2; ++q) {
+    GemmArgs& g = gb.g[q];
+    Epi& ep = gb.ep[q];
+    ep.n = n;
+    g.M = n; g.N = h; g.K = h;
+    g.lda = h;
+    g.ldb = h;
+    if (BF16) {
+      const size_t ax = q ? S.v_dx : S.v_sx, bx = q ? S.b_ko : S.b_ke;
+      g.a_hi = bfw(ax); g.a_lo = bfw(ax) + nh;
+      g.b_hi = bft(bx); g.b_lo = bft(bx) + S.hh;
+      ep.mode = EPI_F32_T;
+      ep.out = f32(S.v_wt) + (size_t)q * h * n;
+    } else {
+      g.a_hi = f32(q ? S.w_dx : S.w_sx);
+      g.b_hi = ft(q ? S.t_kot : S.t_ket);
+      ep.mode = EPI_F32;
+      ep.out = f32(S.w_w) + (size_t)q * h;
+    }
+    ep.ldo = n;
+  }
+  if ((e = launch_gemm<BF16>(gb, s)) != hipSuccess) return e;
+  plan_mark(p, "k_gemm_w", s);
+  // Sy, Dy: the butterfly along y of W'
+  if (BF16)
+    hipLaunchKernelGGL((k_gemm_bfly<true, false>), dim3(pblocks), dim3(256), 0, s,
+                       f32(S.v_wt), n, nullptr, nullptr, nullptr, bfw(S.v_syt),
+                       bfw(S.v_syt) + nh, bfw(S.v_dyt), bfw(S.v_dyt) + nh);
+  else
+    hipLaunchKernelGGL((k_gemm_bfly<false, true>), dim3(pblocks), dim3(256), 0, s,
+                       f32(S.w_w), n, nullptr, f32(S.w_sy), f32(S.w_dy), nullptr, nullptr,
+                       nullptr, nullptr);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  plan_mark(p, "k_gemm_bfly", s);
+  // 2. G' = scale([Ke Sy ; Ko Dy])
+  gb = GemmBatch();
+  gb.count = 2;
+  for (int q = 0; q < 2; ++q) {
+    GemmArgs& g = gb.g[q];
+    Epi& ep = gb.ep[q];
+    ep.n = n;
+    ep.wf = p.wfreq;
+    ep.spectral = 2;
+    ep.vpar = q;
+    ep.eps = a.eps;
+    g.M = h; g.N = n; g.K = h;
+    g.lda = h;
+    if (BF16) {
+      const size_t ax = q ? S.b_ko : S.b_ke, bx = q ? S.v_dyt : S.v_syt;
+      g.a_hi = bft(ax); g.a_lo = bft(ax) + S.hh;
+      g.b_hi = bfw(bx); g.b_lo = bfw(bx) + nh; g.ldb = h;
+      ep.mode = EPI_SPLIT;
+      ep.hi = bfw(S.v_g) + (size_t)q * h * n;
+      ep.lo = bfw(S.v_g) + nn + (size_t)q * h * n;
+    } else {
+      g.a_hi = ft(q ? S.t_ko : S.t_ke);
+      g.b_hi = f32(q ? S.w_dy : S.w_sy); g.ldb = n;
+      ep.mode = EPI_F32;
+      ep.out = f32(S.w_g) + (size_t)q * h * n;
+    }
+    ep.ldo = n;
+  }
+  if ((e = launch_gemm<BF16>(gb, s)) != hipSuccess) return e;
+  plan_mark(p, "k_gemm_g", s);
+  // 3. U' (q = 0) and V' (q = 1) along x, dual: even frequencies times the
+  // even rows of the table, odd times odd
+  gb = GemmBatch();
+  gb.count = 2;
+  for (int q = 0; q < 2; ++q) {
+    GemmArgs& g = gb.g[q];
+    Epi& ep = gb.ep[q];
+    ep.n = n;
+    ep.mode = EPI_DUAL_X;
+    ep.dsign = q ? -1.0f : 1.0f;
+    g.M = n; g.N = h; g.K = h;
+    g.dual = 1;
+    g.lda = n;
+    g.ldb = h;
+    if (BF16) {
+      const size_t b1 = q ? S.b_swet : S.b_ket, b2 = q ? S.b_swot : S.b_kot;
+      g.a_hi = bfw(S.v_g); g.a_lo = bfw(S.v_g) + nn;
+      g.a2_hi = bfw(S.v_g) + h; g.a2_lo = bfw(S.v_g) + nn + h;
+      g.b_hi = bft(b1); g.b_lo = bft(b1) + S.hh;
+      g.b2_hi = bft(b2); g.b2_lo = bft(b2) + S.hh;
+      ep.hi = bfw(S.v_uvt) + (size_t)q * nn;
+      ep.lo = bfw(S.v_uvt) + 2 * nn + (size_t)q * nn;
+    } else {
+      g.a_hi = f32(S.w_g);
+      g.a2_hi = f32(S.w_g) + h;
+      g.b_hi = ft(q ? S.t_swe : S.t_ke);
+      g.b2_hi = ft(q ? S.t_swo : S.t_ko);
+      ep.out = f32(q ? S.w_v : S.w_u);
+    }
+    ep.ldo = n;
+  }
+  if ((e = launch_gemm<BF16>(gb, s)) != hipSuccess) return e;
+  plan_mark(p, "k_gemm_uv", s);
+  // 4. psi (q = 0), Ey (q = 1), Ex (q = 2) along y, dual; energy partials
+  // from the psi blocks
+  gb = GemmBatch();
+  gb.count = 3;
+  for (int q = 0; q < 3; ++q) {
+    GemmArgs& g = gb.g[q];
+    Epi& ep = gb.ep[q];
+    ep.n = n;
+    ep.mode = EPI_DUAL_Y;
+    ep.dsign = q == 1 ? -1.0f : 1.0f;
+    ep.f = q == 0 ? a.psi : q == 1 ? a.ey : a.ex;
+    ep.exy = q ? a.exy : nullptr;
+    ep.exy_off = q == 1 ? 1 : 0;
+    if (q == 0) {
+      ep.rho = a.en_part ? a.rho : nullptr;
+      ep.en_part = a.en_part;
+      ep.en_slots = 4;   // (h/64)(n/64) blocks fill the 2 (n/64)^2 partials
+    }
+    g.M = h; g.N = n; g.K = h;
+    g.dual = 1;
+    g.lda = h;
+    g.ldb = n;
+    if (BF16) {
+      const size_t a1 = q == 1 ? S.b_swet : S.b_ket, a2 = q == 1 ? S.b_swot : S.b_kot;
+      const __bf16* bh = bfw(S.v_uvt) + (q == 2 ? nn : 0);
+      const __bf16* bl = bfw(S.v_uvt) + 2 * nn + (q == 2 ? nn : 0);
+      g.a_hi = bft(a1); g.a_lo = bft(a1) + S.hh;
+      g.a2_hi = bft(a2); g.a2_lo = bft(a2) + S.hh;
+      g.b_hi = bh; g.b_lo = bl;
+      g.b2_hi = bh + h; g.b2_lo = bl + h;
+    } else {
+      const float* b = f32(q == 2 ? S.w_v : S.w_u);
+      g.a_hi = ft(q == 1 ? S.t_swet : S.t_ket);
+      g.a2_hi = ft(q == 1 ? S.t_swot : S.t_kot);
+      g.b_hi = b;
+      g.b2_hi = b + (size_t)h * n;
+    }
+  }
+  if ((e = launch_gemm<BF16>(gb, s)) != hipSuccess) return e;
+  plan_mark(p, "k_gemm_psi_ey", s);
+  return hipSuccess;
 }
 
 template <bool BF16>
@@ -455,6 +870,7 @@ hipError_t run_gemm_path(Plan& p, const SpectralArgs& a, hipStream_t s) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   plan_mark(p, "k_gemm_rowsum", s);
+  if (gemm_split(n) && !a.diff) return run_gemm_split<BF16>(p, a, s);
   int pblocks = (int)((L.nn + 1023) / 1024);
   if (pblocks > 4096) pblocks = 4096;
   if (BF16) {
@@ -579,13 +995,17 @@ hipError_t run_gemm_path(Plan& p, const SpectralArgs& a, hipStream_t s) {
 int gemm_plan_init(Plan& p, hipStream_t s) {
   const int n = p.n;
   const GemmLayout L = gemm_layout(n);
-  if (hipMalloc(&p.gemm_tables, L.tables_bytes) != hipSuccess ||
-      hipMalloc(&p.gemm_ws, L.ws_bytes) != hipSuccess) {
+  const bool split = gemm_split(n);
+  const SplitLayout S = split_layout(n);
+  const size_t tables_bytes = L.tables_bytes + (split ? S.tables_bytes : 0);
+  const size_t ws_bytes = split && S.ws_bytes > L.ws_bytes ? S.ws_bytes : L.ws_bytes;
+  if (hipMalloc(&p.gemm_tables, tables_bytes) != hipSuccess ||
+      hipMalloc(&p.gemm_ws, ws_bytes) != hipSuccess) {
     hipGetLastError();
     return FFTPL_E_NOMEM;
   }
-  p.gemm_tables_bytes = L.tables_bytes;
-  p.gemm_ws_bytes = L.ws_bytes;
+  p.gemm_tables_bytes = tables_bytes;
+  p.gemm_ws_bytes = ws_bytes;
   const double pi = 3.14159265358979323846;
   const size_t nn = L.nn;
   // K[u][i] and Sw[u][i] = w_u S[u][i], argument reduced as pi*((u(2i+1)) mod 4n)/(2n)
@@ -604,7 +1024,7 @@ int gemm_plan_init(Plan& p, hipStream_t s) {
       Kd[(size_t)u * n + i] = -2.0 * sh * sin(pi * (double)r2 / n);
     }
   }
-  std::vector<char> host(L.tables_bytes);
+  std::vector<char> host(tables_bytes);
   if (p.mode == FFTPL_DCT_GEMM_F32) {
     float* tk = reinterpret_cast<float*>(host.data() + L.t_k);
     float* tksw = reinterpret_cast<float*>(host.data() + L.t_ksw);
@@ -657,7 +1077,46 @@ int gemm_plan_init(Plan& p, hipStream_t s) {
         split(Kd[(size_t)b * n + a], eh[(size_t)(n + a) * n + b], el[(size_t)(n + a) * n + b]);
       }
   }
-  if (hipMemcpyAsync(p.gemm_tables, host.data(), L.tables_bytes, hipMemcpyHostToDevice, s) !=
+  if (split) {
+    // the split tables: rows 2a (even) and 2a + 1 (odd) of K and Sw over the
+    // first h samples, and their transposes
+    const int h = n / 2;
+    char* st = host.data() + L.tables_bytes;
+    auto kv = [&](int u, int i) { return K[(size_t)u * n + i]; };
+    auto sv = [&](int u, int i) { return Sw[(size_t)u * n + i]; };
+    for (int a = 0; a < h; ++a)
+      for (int i = 0; i < h; ++i) {
+        const size_t ai = (size_t)a * h + i, ia = (size_t)i * h + a;
+        const double ke = kv(2 * a, i), ko = kv(2 * a + 1, i);
+        const double se = sv(2 * a, i), so = sv(2 * a + 1, i);
+        if (p.mode == FFTPL_DCT_GEMM_F32) {
+          float* t = reinterpret_cast<float*>(st);
+          t[S.t_ke / 4 + ai] = (float)ke;
+          t[S.t_ko / 4 + ai] = (float)ko;
+          t[S.t_ket / 4 + ia] = (float)ke;
+          t[S.t_kot / 4 + ia] = (float)ko;
+          t[S.t_swe / 4 + ai] = (float)se;
+          t[S.t_swo / 4 + ai] = (float)so;
+          t[S.t_swet / 4 + ia] = (float)se;
+          t[S.t_swot / 4 + ia] = (float)so;
+        } else {
+          uint16_t* t = reinterpret_cast<uint16_t*>(st);
+          auto put = [&](size_t off, size_t idx, double v) {
+            const float f = (float)v;
+            const uint16_t hv = f32_to_bf16_rne(f);
+            t[off / 2 + idx] = hv;
+            t[off / 2 + S.hh + idx] = f32_to_bf16_rne(f - bf16_to_f32(hv));
+          };
+          put(S.b_ke, ai, ke);
+          put(S.b_ko, ai, ko);
+          put(S.b_ket, ia, ke);
+          put(S.b_kot, ia, ko);
+          put(S.b_swet, ia, se);
+          put(S.b_swot, ia, so);
+        }
+      }
+  }
+  if (hipMemcpyAsync(p.gemm_tables, host.data(), tables_bytes, hipMemcpyHostToDevice, s) !=
           hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return FFTPL_E_DEVICE;
