@@ -549,6 +549,26 @@ def test_poisson_single_mode_gemm(F, mode):
 
 
 @pytest.mark.parametrize("mode", ["gemm_f32", "gemm_bf16x3"])
+def test_eval_gemm_field_and_exact_share_a_plan(F, mode):
+    # n = 128: the field mode takes the even/odd split products and the exact
+    # mode the dense ones; the two alternate on one plan (one GEMM workspace)
+    inst = gen.make_config("small_2k", n=128)
+    refs = {g: oracle.evaluate(inst, lam=2.0, grad_mode=g) for g in ("field", "exact")}
+    plan = F.Plan(inst.n, mode)
+    try:
+        for grad in ("field", "exact", "field"):
+            got = _run_eval(F, inst, 2.0, grad, dct=mode, plan=plan)
+            if mode == "gemm_f32":
+                _check_eval(inst, got, refs[grad], 2.0, grad)
+            else:
+                e = rel_l2(got["gx"], refs[grad]["gx"])
+                say("bf16x3 n=128", grad, "grad err", e)
+                assert e < BF16X3_SANITY
+    finally:
+        plan.close()
+
+
+@pytest.mark.parametrize("mode", ["gemm_f32", "gemm_bf16x3"])
 @pytest.mark.parametrize("grad", ["field", "exact"])
 def test_eval_small_gemm(F, mode, grad):
     inst = gen.make_config("small_2k")
