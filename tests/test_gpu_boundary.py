@@ -232,7 +232,8 @@ def _designs(n, count, seed):
 
 
 @pytest.mark.parametrize("dct,grad", [("fft", "field"), ("fft", "exact"),
-                                      ("gemm_f32", "field")])
+                                      ("gemm_f32", "field"), ("gemm_f32", "exact"),
+                                      ("gemm_bf16x3", "field")])
 def test_batched_groups_equal_single_evaluations_bit_for_bit(F, dct, grad):
     # designs of one grid side evaluated in groups of up to max_batch per
     # launch give the same bits as one evaluation each (every sum is
@@ -274,8 +275,9 @@ def test_batched_groups_equal_single_evaluations_bit_for_bit(F, dct, grad):
         assert abs(float(o4[1]) - float(out[k][1])) <= 1e-12 * abs(float(o4[1]))
     # and one of the grouped designs against the oracle
     ref = oracle.evaluate(insts[1], lam=lams[1], grad_mode=grad)
-    assert rel_l2(host(gxs[1]), ref["gx"]) < RTOL and rel_l2(host(gys[1]), ref["gy"]) < RTOL
-    assert abs(float(host(out[1])[0]) - ref["energy"]) < RTOL * abs(ref["energy"])
+    tol = 1e-4 if dct == "gemm_bf16x3" else RTOL   # split-bf16: reported, not gated at 1e-5
+    assert rel_l2(host(gxs[1]), ref["gx"]) < tol and rel_l2(host(gys[1]), ref["gy"]) < tol
+    assert abs(float(host(out[1])[0]) - ref["energy"]) < tol * abs(ref["energy"])
     single.close()
     plan.close()
 
