@@ -383,6 +383,61 @@ __global__ void __launch_bounds__(256 * KS) k_gemm(GemmBatch gb) {
     }
   }
 
+  // Transposed outputs (EPI_F32_T, EPI_SPLIT_T, EPI_DUAL_X into bf16): the
+  // tile goes through LDS so that each thread writes a contiguous run of one
+  // output row instead of single elements one row apart (these steps have no
+  // spectral scaling and no energy).
+  if (ep.mode == EPI_F32_T || ep.mode == EPI_SPLIT_T || (ep.mode == EPI_DUAL_X && ep.hi)) {
+    constexpr int TP = TM + 1;                       // padded row of a transposed tile
+    constexpr int SEG = TM * TN / (256 * KS);        // elements per thread: 16 or 8
+    static_assert(2 * TN * TP <= kFloats, "two transposed tiles fit the LDS buffers");
+    float* T1 = smem;             // [col][row]: the output at (row, col)
+    float* T2 = smem + TN * TP;   // dual: the mirrored output
+    __syncthreads();              // every read of the K-half reduction is done
+    if (wk == 0) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int c = wn + 16 * j + l16, rr = wm + 16 * i + 4 * lg + r;
+            T1[c * TP + rr] = acc[i][j][r];
+            if (dual) T2[c * TP + rr] = ep.dsign * dif[i][j][r];
+          }
+    }
+    __syncthreads();
+    const int c = t / (TM / SEG), r0 = (t % (TM / SEG)) * SEG;
+    auto put = [&](const float* T, int ocol) {
+      float v[SEG];
+#pragma unroll
+      for (int q = 0; q < SEG; ++q) v[q] = T[c * TP + r0 + q];
+      const size_t o = (size_t)ocol * ep.ldo + m0 + r0;
+      if (ep.mode == EPI_F32_T) {
+#pragma unroll
+        for (int q = 0; q < SEG; q += 4)
+          *reinterpret_cast<float4*>(ep.out + o + q) = make_float4(v[q], v[q + 1], v[q + 2], v[q + 3]);
+      } else {
+#pragma unroll
+        for (int q = 0; q < SEG; q += 8) {
+          bf8 h, l;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            __bf16 a, b;
+            split_bf16(v[q + e], a, b);
+            h[e] = a;
+            l[e] = b;
+          }
+          *reinterpret_cast<bf8*>(ep.hi + o + q) = h;
+          *reinterpret_cast<bf8*>(ep.lo + o + q) = l;
+        }
+      }
+    };
+    put(T1, n0 + c);
+    if (dual) put(T2, ep.n - 1 - (n0 + c));
+    return;
+  }
+
   // Epilogue (waves 0-3).  Lane l of a 16x16 tile holds column l%16, rows
   // 4*(l/16)+r.
   double en = 0.0;
