@@ -105,20 +105,23 @@ __device__ __forceinline__ void split_bf16(float v, __bf16& hi, __bf16& lo) {
 
 // One element of a product's result: optional spectral scaling, then the
 // store the step needs (see EpiMode); en gathers rho * psi for the energy.
+__device__ __forceinline__ float spectral_scale(const Epi& ep, int row, int col, float v) {
+  const int n = ep.n;
+  const float inv_n2 = 1.0f / ((float)n * (float)n);
+  int u = col, w = row;
+  if (ep.spectral == 2) {
+    const int h = n / 2;
+    w = 2 * row + ep.vpar;
+    u = col < h ? 2 * col : 2 * (col - h) + 1;
+  }
+  const float wu = ep.wf[u], wv = ep.wf[w];
+  const float cu = u ? 2.0f : 1.0f, cv = w ? 2.0f : 1.0f;
+  return (w == 0 && u == 0) ? 0.0f : v * (cu * cv * inv_n2) / (wu * wu + wv * wv + ep.eps);
+}
+
 __device__ __forceinline__ void epi_store(const Epi& ep, int row, int col, float v, double& en) {
   const int n = ep.n;
-  if (ep.spectral) {
-    const float inv_n2 = 1.0f / ((float)n * (float)n);
-    int u = col, w = row;
-    if (ep.spectral == 2) {
-      const int h = n / 2;
-      w = 2 * row + ep.vpar;
-      u = col < h ? 2 * col : 2 * (col - h) + 1;
-    }
-    const float wu = ep.wf[u], wv = ep.wf[w];
-    const float cu = u ? 2.0f : 1.0f, cv = w ? 2.0f : 1.0f;
-    v = (w == 0 && u == 0) ? 0.0f : v * (cu * cv * inv_n2) / (wu * wu + wv * wv + ep.eps);
-  }
+  if (ep.spectral) v = spectral_scale(ep, row, col, v);
   if (ep.mode == EPI_F32) {
     ep.out[(size_t)row * ep.ldo + col] = v;
   } else if (ep.mode == EPI_F32_T) {
@@ -383,15 +386,18 @@ __global__ void __launch_bounds__(256 * KS) k_gemm(GemmBatch gb) {
     }
   }
 
-  // Transposed outputs (EPI_F32_T, EPI_SPLIT_T, EPI_DUAL_X into bf16): the
-  // tile goes through LDS so that each thread writes a contiguous run of one
-  // output row instead of single elements one row apart (these steps have no
-  // spectral scaling and no energy).
-  if (ep.mode == EPI_F32_T || ep.mode == EPI_SPLIT_T || (ep.mode == EPI_DUAL_X && ep.hi)) {
+  // Single-map outputs (EPI_F32, EPI_SPLIT, their transposed forms and
+  // EPI_DUAL_X): the tile goes through LDS so that each thread writes a
+  // contiguous run of one output row (for the transposed forms, instead of
+  // single elements one row apart; for the mirrored half of a float32
+  // EPI_DUAL_X, a run in reverse order).
+  const bool trans = ep.mode == EPI_F32_T || ep.mode == EPI_SPLIT_T ||
+                     (ep.mode == EPI_DUAL_X && ep.hi);
+  if (trans || ep.mode == EPI_F32 || ep.mode == EPI_SPLIT || ep.mode == EPI_DUAL_X) {
     constexpr int TP = TM + 1;                       // padded row of a transposed tile
     constexpr int SEG = TM * TN / (256 * KS);        // elements per thread: 16 or 8
     static_assert(2 * TN * TP <= kFloats, "two transposed tiles fit the LDS buffers");
-    float* T1 = smem;             // [col][row]: the output at (row, col)
+    float* T1 = smem;             // [col][row] (transposed) or [row][col]
     float* T2 = smem + TN * TP;   // dual: the mirrored output
     __syncthreads();              // every read of the K-half reduction is done
     if (wk == 0) {
@@ -402,18 +408,39 @@ __global__ void __launch_bounds__(256 * KS) k_gemm(GemmBatch gb) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int c = wn + 16 * j + l16, rr = wm + 16 * i + 4 * lg + r;
-            T1[c * TP + rr] = acc[i][j][r];
-            if (dual) T2[c * TP + rr] = ep.dsign * dif[i][j][r];
+            const int x = trans ? c * TP + rr : rr * TP + c;
+            T1[x] = acc[i][j][r];
+            if (dual) T2[x] = ep.dsign * dif[i][j][r];
           }
     }
     __syncthreads();
+    // thread t: line c of the staged tile (an output row), elements r0..
     const int c = t / (TM / SEG), r0 = (t % (TM / SEG)) * SEG;
-    auto put = [&](const float* T, int ocol) {
+    auto put = [&](const float* T, int oline) {
       float v[SEG];
 #pragma unroll
       for (int q = 0; q < SEG; ++q) v[q] = T[c * TP + r0 + q];
-      const size_t o = (size_t)ocol * ep.ldo + m0 + r0;
-      if (ep.mode == EPI_F32_T) {
+      if (!trans && ep.spectral) {
+#pragma unroll
+        for (int q = 0; q < SEG; ++q) v[q] = spectral_scale(ep, m0 + c, n0 + r0 + q, v[q]);
+      }
+      const size_t o = trans ? (size_t)oline * ep.ldo + m0 + r0
+                             : (size_t)(m0 + c) * ep.ldo + n0 + r0;
+      if (!trans && ep.mode == EPI_DUAL_X) {
+        // float32 row-major: the first output at (row, n0 + r0 ..), the
+        // mirrored one at (row, n - 1 - (n0 + r0 + SEG - 1) ..) reversed
+        if (T == T1) {
+#pragma unroll
+          for (int q = 0; q < SEG; q += 4)
+            *reinterpret_cast<float4*>(ep.out + o + q) = make_float4(v[q], v[q + 1], v[q + 2], v[q + 3]);
+        } else {
+          const size_t o2 = (size_t)(m0 + c) * ep.ldo + (ep.n - n0 - r0 - SEG);
+#pragma unroll
+          for (int q = 0; q < SEG; q += 4)
+            *reinterpret_cast<float4*>(ep.out + o2 + q) =
+                make_float4(v[SEG - 1 - q], v[SEG - 2 - q], v[SEG - 3 - q], v[SEG - 4 - q]);
+        }
+      } else if (ep.mode == EPI_F32_T || ep.mode == EPI_F32) {
 #pragma unroll
         for (int q = 0; q < SEG; q += 4)
           *reinterpret_cast<float4*>(ep.out + o + q) = make_float4(v[q], v[q + 1], v[q + 2], v[q + 3]);
